@@ -1,0 +1,235 @@
+"""Seeded synthetic workloads: the tip-over-cathode tetrahedral mesh and the
+run parameters of the benchmark configurations.
+
+This module produces *inputs only*: node coordinates, tetrahedron
+connectivity with periodic vertex shifts, and plain parameter records.  It
+holds none of the method's arithmetic (no orientation, adjacency, assembly,
+field, emission or particle update); both the HIP library and the CPU oracle
+derive everything else from these arrays on their own.
+
+Mesh recipe (stands in for the FEMOCS mesh of the paper's Sec. II, which is
+built around MD atoms and is out of scope here):
+
+* a structured nx x ny x nz grid of cubes of edge h over the box
+  [0, nx h] x [0, ny h] x [0, nz h], periodic in x and y (the lateral
+  periodicity of Sec. II B 1);
+* every cube (i, j, k) is Kuhn-split into 6 tetrahedra, one per axis
+  permutation pi in lexicographic order (012, 021, 102, 120, 201, 210):
+  [c, c + e_pi0, c + e_pi0 + e_pi1, c + (1,1,1)];
+* the metal tip is a hemisphere-capped cylinder of radius R and total height
+  H standing on z = 0 with its axis at (Lx/2, Ly/2); every tetrahedron with a
+  vertex strictly inside the tip solid is removed, orphan nodes are dropped
+  and the survivors are renumbered in their original order.
+
+Node ids before compaction are ((i mod nx) ny + (j mod ny)) (nz + 1) + k, so
+nodes on x = Lx / y = Ly are the same nodes as on x = 0 / y = 0; each
+tetrahedron vertex carries a shift (sx, sy) in {0, 1}^2 such that its
+unwrapped position is xyz[node] + (sx Lx, sy Ly, 0).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+# Axis permutations of the Kuhn split, lexicographic order.
+_PERMS = ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0))
+
+
+@dataclasses.dataclass
+class TipMesh:
+    """Arrays describing one vacuum mesh (host, numpy)."""
+    xyz: np.ndarray      # float64 [n_nodes, 3], wrapped into [0, Lx) x [0, Ly)
+    tet: np.ndarray      # int32 [n_tets, 4]
+    shift: np.ndarray    # int8 [n_tets, 4, 2]
+    Lx: float
+    Ly: float
+    z_top: float
+    h: float
+    nx: int
+    ny: int
+    nz: int
+    tip_R: float
+    tip_H: float
+
+    @property
+    def n_nodes(self) -> int:
+        return int(self.xyz.shape[0])
+
+    @property
+    def n_tets(self) -> int:
+        return int(self.tet.shape[0])
+
+
+def _inside_tip(x, y, z, cx, cy, R, H):
+    """Strict interior of the capped cylinder (squared distances, exact for
+    binary-exact grid coordinates)."""
+    r2 = (x - cx) ** 2 + (y - cy) ** 2
+    zc = H - R
+    cyl = (z > 0) & (z <= zc) & (r2 < R * R)
+    cap = (z > zc) & (r2 + (z - zc) ** 2 < R * R)
+    return cyl | cap
+
+
+def kuhn_tip_mesh(nx: int, ny: int, nz: int, h: float = 0.5,
+                  tip_R: float = 0.0, tip_H: float = 0.0) -> TipMesh:
+    """Structured Kuhn mesh of the periodic box with the tip removed.
+
+    tip_R <= 0 gives the plain parallel-plate box (no tip)."""
+    Lx, Ly, Lz = nx * h, ny * h, nz * h
+    ii, jj, kk = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz),
+                             indexing="ij")
+    ii = ii.reshape(-1)
+    jj = jj.reshape(-1)
+    kk = kk.reshape(-1)
+    ncube = ii.size
+    # local corner offsets of the 4 vertices for each permutation
+    offs = np.zeros((6, 4, 3), dtype=np.int64)
+    for p, perm in enumerate(_PERMS):
+        e0 = np.eye(3, dtype=np.int64)[perm[0]]
+        e1 = np.eye(3, dtype=np.int64)[perm[1]]
+        offs[p, 1] = e0
+        offs[p, 2] = e0 + e1
+        offs[p, 3] = (1, 1, 1)
+    # unwrapped integer vertex coordinates [ncube, 6, 4, 3]
+    base = np.stack([ii, jj, kk], axis=1)[:, None, None, :]
+    vint = base + offs[None, :, :, :]
+    vint = vint.reshape(ncube * 6, 4, 3)
+    vi, vj, vk = vint[..., 0], vint[..., 1], vint[..., 2]
+    node = ((vi % nx) * ny + (vj % ny)) * (nz + 1) + vk
+    sx = (vi >= nx).astype(np.int8)
+    sy = (vj >= ny).astype(np.int8)
+    keep = np.ones(ncube * 6, dtype=bool)
+    if tip_R > 0.0:
+        cx, cy = 0.5 * Lx, 0.5 * Ly
+        inside = _inside_tip(vi * h, vj * h, vk * h, cx, cy, tip_R, tip_H)
+        keep = ~inside.any(axis=1)
+    node = node[keep]
+    sx = sx[keep]
+    sy = sy[keep]
+    n_all = nx * ny * (nz + 1)
+    used = np.zeros(n_all, dtype=bool)
+    used[node.reshape(-1)] = True
+    newid = np.full(n_all, -1, dtype=np.int64)
+    newid[used] = np.arange(int(used.sum()))
+    tet = newid[node].astype(np.int32)
+    old = np.nonzero(used)[0]
+    k = old % (nz + 1)
+    j = (old // (nz + 1)) % ny
+    i = old // ((nz + 1) * ny)
+    xyz = np.stack([i * h, j * h, k * h], axis=1).astype(np.float64)
+    shift = np.stack([sx, sy], axis=2).astype(np.int8)
+    return TipMesh(xyz=np.ascontiguousarray(xyz), tet=np.ascontiguousarray(tet),
+                   shift=np.ascontiguousarray(shift), Lx=float(Lx), Ly=float(Ly),
+                   z_top=float(Lz), h=float(h), nx=nx, ny=ny, nz=nz,
+                   tip_R=float(tip_R), tip_H=float(tip_H))
+
+
+# --------------------------------------------------------------------------
+# Run configurations.  The five workloads: a tiny tip, a production-shaped
+# tip (about 3.1M tetrahedra), its mixed-precision form, a batch of 32 uneven
+# tips, and an adjoint window over the production mesh.
+# --------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class RunConfig:
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    h: float
+    tip_R: float
+    tip_H: float
+    E0: float              # applied field, V/nm
+    phi_w: float           # work function, eV
+    dt: float              # fs
+    n_steps: int
+    tol: float
+    n_target: int          # live superparticles wanted in steady state
+    emit_zmin: float       # emitting metal faces: centroid z >= emit_zmin
+    seed: int
+    resort_every: int
+    transit_steps: int     # T of the superparticle-weight rule
+
+    def mesh(self) -> TipMesh:
+        return kuhn_tip_mesh(self.nx, self.ny, self.nz, self.h,
+                             self.tip_R, self.tip_H)
+
+
+def transit_steps(Lz: float, H: float, E0: float, dt: float) -> int:
+    """Steps an electron needs to cross the gap above the apex in the
+    uniform applied field: ceil(sqrt(2 (Lz - H) / (|q/m| E0)) / dt), with
+    |q/m| = 0.17588 nm fs^-2 per V/nm (this only sizes the weight)."""
+    qm = 0.1758820
+    return int(math.ceil(math.sqrt(2.0 * (Lz - H) / (qm * E0)) / dt))
+
+
+def config_tiny() -> RunConfig:
+    """Box 8x8x16 nm, 16x16x32 grid, tip R = 2, H = 8, E0 = 0.4 V/nm,
+    tip faces emit, 10 steps at 0.5 fs, tol 1e-12, ~1e4 live."""
+    return RunConfig("tiny_tip_16x16x32", 16, 16, 32, 0.5, 2.0, 8.0, 0.4, 4.5,
+                     0.5, 10, 1e-12, 10_000, 0.01, 1, 10, 10)
+
+
+def config_production() -> RunConfig:
+    """Box 32x32x64 nm, 64x64x128 grid (3,100,504 tets), tip R = 3, H = 30,
+    E0 = 0.5 V/nm, apex faces emit, 100 steps, tol 1e-10, ~1e6 live,
+    re-sort every 10 steps."""
+    T = transit_steps(64.0, 30.0, 0.5, 0.5)
+    return RunConfig("production_tip_64x64x128", 64, 64, 128, 0.5, 3.0, 30.0,
+                     0.5, 4.5, 0.5, 100, 1e-10, 1_000_000, 27.0, 2, 10, T)
+
+
+def philox_uniform_stream(seed: int, n: int) -> np.ndarray:
+    """Plain seeded uniforms for *input* generation (instance draws, test
+    points).  Not used by the method itself."""
+    return np.random.Generator(np.random.Philox(seed)).random(n)
+
+
+def batch_configs(n_inst: int = 32, seed: int = 4) -> list[RunConfig]:
+    """Uneven tip instances: grid n x n x 2n with n in U{32..64} at h = 0.5,
+    R in U[1.5, 4], H in U[10, 30] (redrawn while H > 0.75 Lz),
+    E0 in U[0.3, 0.7], N_target log-uniform in [1e4, 1e6]."""
+    out = []
+    for i in range(n_inst):
+        g = np.random.Generator(np.random.Philox(key=[seed, i]))
+        n = int(g.integers(32, 65))
+        R = float(g.uniform(1.5, 4.0))
+        Lz = 2 * n * 0.5
+        H = float(g.uniform(10.0, 30.0))
+        while H > 0.75 * Lz:
+            H = float(g.uniform(10.0, 30.0))
+        E0 = float(g.uniform(0.3, 0.7))
+        nt = int(round(10 ** g.uniform(4.0, 6.0)))
+        # snap H and R to the grid resolution so node tests stay exact
+        H = round(H * 2) / 2
+        R = round(R * 4) / 4
+        T = transit_steps(Lz, H, E0, 0.5)
+        out.append(RunConfig(f"batch_{i}", n, n, 2 * n, 0.5, R, H, E0, 4.5,
+                             0.5, 50, 1e-10, nt, H - R, seed, 10, T))
+    return out
+
+
+def random_points_in_box(mesh: TipMesh, n: int, seed: int) -> np.ndarray:
+    """Uniform points over the (unwrapped) box; some fall in the metal."""
+    g = np.random.Generator(np.random.Philox(seed))
+    p = g.random((n, 3))
+    p[:, 0] *= mesh.Lx
+    p[:, 1] *= mesh.Ly
+    p[:, 2] *= mesh.z_top
+    return p
+
+
+def lattice_points(mesh: TipMesh, n: int, seed: int) -> np.ndarray:
+    """Points on vertices, edge midpoints and face centroids of the grid
+    (all binary-exact): degenerate cases for point location."""
+    g = np.random.Generator(np.random.Philox(seed))
+    q = g.integers(0, 4, size=(n, 3)) * 0.25  # quarter-cell offsets
+    c = np.stack([g.integers(0, mesh.nx, n), g.integers(0, mesh.ny, n),
+                  g.integers(0, mesh.nz, n)], axis=1) * mesh.h
+    p = c + q * mesh.h * 2.0
+    p[:, 0] = np.minimum(p[:, 0], mesh.Lx)
+    p[:, 1] = np.minimum(p[:, 1], mesh.Ly)
+    p[:, 2] = np.minimum(p[:, 2], mesh.z_top)
+    return p

@@ -1,0 +1,34 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line(
+        "markers", "gpu: needs an MI355X (gfx950) and the built HIP library")
+    config.addinivalue_line("markers", "slow: minutes-scale CPU test")
+
+
+@pytest.fixture(scope="session")
+def tiny_mesh():
+    from paper_1906_08125_amd import workloads as w
+    return w.config_tiny().mesh()
+
+
+@pytest.fixture(scope="session")
+def plates_mesh():
+    """Periodic parallel plates, no tip: 4 x 4 x 8 cubes of 0.5 nm."""
+    from paper_1906_08125_amd import workloads as w
+    return w.kuhn_tip_mesh(4, 4, 8, 0.5)
+
+
+@pytest.fixture(scope="session")
+def small_tip_mesh():
+    """3 x 3 x 4 cubes (216 tets before removal) with a one-cell tip."""
+    from paper_1906_08125_amd import workloads as w
+    return w.kuhn_tip_mesh(3, 3, 4, 0.5, 0.5, 1.0)
