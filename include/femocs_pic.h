@@ -1,0 +1,230 @@
+/*
+ * femocs_pic.h -- C ABI of the MI355X (gfx950) electron particle-in-cell
+ * library: the PIC cycle in the vacuum above a field-emitting tip, after
+ * Veske et al., "Dynamic coupling between particle-in-cell and atomistic
+ * simulations", Phys. Rev. E 101, 053307 (2020), Sec. II A-B and
+ * Appendices B and E.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  Units: nm, fs, V, V/nm, eV, elementary charge e.
+ *  Memory: "host" pointers are read during the call only; "device" pointers
+ *    are HIP device memory owned by the caller.  The library never frees
+ *    caller memory.  mesh_create allocates the mesh's own device arrays
+ *    (freed by mesh_destroy); pic_step grows a per-handle particle scratch
+ *    on the first call with a larger capacity and allocates nothing after.
+ *  Streams: `stream` is a hipStream_t passed as void*; NULL is the null
+ *    stream.  Every call only enqueues work on that stream (mesh_create and
+ *    mesh_destroy synchronize it); results land in device memory.  One mesh
+ *    handle must not be used on two streams at once.
+ *  Errors: every call returns a pic_status (0 = success) and never throws.
+ *    PIC_E_ARG: a host-checked argument is invalid; nothing was enqueued.
+ *    PIC_E_DEVICE: a HIP runtime call failed.  Device-side conditions
+ *    (non-convergence, capacity overflow) are reported in the stats structs
+ *    the caller passes.  pic_last_error() returns the last message of the
+ *    calling thread.
+ *  Geometry: tetrahedra are oriented by the library so that
+ *    D = (v1-v0).((v2-v0)x(v3-v0)) > 0 (local vertices 2 and 3 swapped when
+ *    needed); face i of a tetrahedron is the one opposite local vertex i.
+ *  Charge: deposited in int64 fixed point, 2^40 units per unit relative
+ *    weight; the rounding rule makes deposition order-independent.
+ */
+#ifndef FEMOCS_PIC_H
+#define FEMOCS_PIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define PIC_API __attribute__((visibility("default")))
+#else
+#define PIC_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pic_status;
+enum {
+  PIC_OK = 0,
+  PIC_E_ARG = -1,
+  PIC_E_DEVICE = -2,
+  PIC_E_MESH = -3,
+  PIC_E_NOCONV = -4,
+  PIC_E_CAPACITY = -5,
+  PIC_E_NUMERIC = -6
+};
+
+enum { PIC_FP64 = 0, PIC_MIXED = 1 };
+
+/* Fixed-point scale of deposited charge: units per unit relative weight. */
+#define PIC_CHARGE_SCALE 1099511627776.0 /* 2^40 */
+
+/* Where a located point ended up. */
+enum { PIC_WHERE_INSIDE = 0, PIC_WHERE_ANODE = 1, PIC_WHERE_OUTSIDE = 2 };
+
+/* ------------------------------------------------------------------------ */
+/* Mesh (Sec. II A: linear tetrahedral elements over the vacuum domain;     */
+/* Eq. poisson_bc: Neumann E0 on the top plane, Dirichlet 0 on the metal,   */
+/* lateral periodicity of Sec. II B 1).                                      */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  int64_t n_nodes;
+  const double* xyz;    /* host [3*n_nodes]: node coordinates, wrapped      */
+  int64_t n_tets;
+  const int32_t* tet;   /* host [4*n_tets]: node ids                         */
+  const int8_t* shift;  /* host [8*n_tets] or NULL: per vertex (sx, sy);   */
+                        /* unwrapped vertex = xyz + (sx Lx, sy Ly, 0)        */
+  double Lx, Ly;        /* lateral periods (> 0)                            */
+  double z_top;         /* top plane: Neumann boundary and particle anode   */
+  double emit_zmin;     /* metal faces with centroid z >= emit_zmin emit    */
+} pic_mesh_desc;
+
+typedef struct pic_mesh pic_mesh;
+
+typedef struct {
+  int64_t n_nodes, n_tets, n_free, nnz, nnz_field, n_emit, n_top, n_metal;
+  int64_t device_bytes;
+} pic_mesh_info;
+
+/* Build a mesh handle: orientation, adjacency with periodic shifts,
+ * boundary tags (a boundary face is top when its three vertices lie on
+ * z = z_top, metal otherwise; metal vertices are Dirichlet), the P1
+ * stiffness matrix on free nodes (App. B), the Neumann load per unit E0,
+ * the nodal-field operator, the emitting faces and a bucket grid; uploads
+ * everything to the current device.  PIC_E_MESH for out-of-range node ids,
+ * zero-volume or non-manifold elements.  *out receives the handle. */
+PIC_API pic_status mesh_create(const pic_mesh_desc* desc, void* stream, pic_mesh** out);
+PIC_API pic_status mesh_destroy(pic_mesh* mesh);
+PIC_API pic_status mesh_query(const pic_mesh* mesh, pic_mesh_info* info);
+/* Host copies of the emitting faces: owner tet, node ids (3 per face),
+ * area (nm^2); each pointer may be NULL. */
+PIC_API pic_status mesh_emit_faces(const pic_mesh* mesh, int32_t* tet, int32_t* nodes3,
+                           double* area);
+
+/* ------------------------------------------------------------------------ */
+/* Point location (Sec. II B 2): the containing element of each point.      */
+/* The answer is canonical: the lowest-index tetrahedron whose closed        */
+/* region holds the point, decided with exact orientation predicates; the   */
+/* neighbour walk from the hint only finds it faster.                       */
+/* x, y, z: device [n] f64, already wrapped into [0, Lx] x [0, Ly].          */
+/* tet_inout: device [n] i32, in: hint tet or -1, out: tet or -1.           */
+/* where_out: device [n] u8 (PIC_WHERE_*); z >= z_top is ANODE.             */
+/* ------------------------------------------------------------------------ */
+PIC_API pic_status locate(const pic_mesh* mesh, int64_t n, const double* x,
+                  const double* y, const double* z, int32_t* tet_inout,
+                  uint8_t* where_out, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Charge deposition (Eq. q_delta, Eq. poisson_rhs; same shape functions    */
+/* as the field gather).  For each point with tet >= 0: lambda_i of the     */
+/* point in its tet, q_i = rint(lambda_i w 2^40) (i = 1..3),                */
+/* q_0 = rint(w 2^40) - (q_1 + q_2 + q_3), added atomically to the four     */
+/* vertices of charge (device [n_nodes] i64, accumulated, not cleared).      */
+/* ------------------------------------------------------------------------ */
+PIC_API pic_status deposit(const pic_mesh* mesh, int64_t n, const double* x,
+                   const double* y, const double* z, const int32_t* tet,
+                   const double* w, int64_t* charge, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Poisson solve (Eq. poisson with Eq. poisson_bc, Galerkin form of App. B) */
+/* K phi_f = b_f on free nodes, b_i = (-e/eps0) w_sp c_i 2^-40 + E0 g_i,    */
+/* Jacobi-preconditioned CG (the paper only says "iteratively"), warm       */
+/* started from phi, stopped when ||b - K phi||_2 <= tol ||b||_2 (checked   */
+/* on the true residual).  phi: device [n_nodes] f64 (in: guess, out:       */
+/* solution, 0 on Dirichlet nodes).  charge: device [n_nodes] or NULL.      */
+/* E_out: device [4*n_nodes] f64 or NULL: nodal field (x, y, z, 0), the      */
+/* volume-weighted mean of -grad(phi) over the tets holding each node.       */
+/* stats: device pic_solve_stats or NULL.                                   */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  double tol;        /* relative residual target                         */
+  double inner_tol;  /* mixed precision: FP32 inner solve target          */
+  int32_t max_iter;  /* iteration cap (PIC_E_NOCONV in stats beyond it)   */
+  int32_t precision; /* PIC_FP64 or PIC_MIXED (FP32 inner CG + FP64 IR)   */
+} pic_solve_params;
+
+typedef struct {
+  int64_t iters;     /* CG iterations (inner ones in mixed mode)          */
+  int64_t status;    /* PIC_OK or PIC_E_NOCONV                            */
+  int64_t restarts;  /* true-residual restarts / refinement sweeps        */
+  int64_t pad;
+  double relres;     /* final true relative residual                      */
+  double bnorm;
+} pic_solve_stats;
+
+PIC_API pic_status poisson_solve(const pic_mesh* mesh, const int64_t* charge,
+                         double w_sp, double E0, double* phi, double* E_out,
+                         const pic_solve_params* params,
+                         pic_solve_stats* stats, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* The PIC cycle (Sec. II B 1-3).                                            */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  int64_t capacity;  /* slots in every array below                        */
+  int32_t precision; /* PIC_FP64: x..vz are double; PIC_MIXED: float       */
+  int32_t pad;
+  void *x, *y, *z;    /* device [capacity] positions (wrapped)            */
+  void *vx, *vy, *vz; /* device [capacity] velocities v_{k-1/2}           */
+  double* w;          /* device [capacity] relative weight               */
+  int32_t* tet;       /* device [capacity] containing tet; -1 = free slot */
+  int32_t* birth;     /* device [capacity] emitting face index            */
+  int64_t* id;        /* device [capacity] step<<42 | face<<21 | ordinal  */
+  int32_t* n_slots;   /* device scalar: slots in use (live + free slots)   */
+} pic_particles;
+
+typedef struct {
+  double* phi;      /* device [n_nodes] potential                         */
+  double* E;        /* device [4*n_nodes] nodal field of phi              */
+  int64_t* charge;  /* device [n_nodes] fixed-point charge of last step   */
+} pic_fields;
+
+typedef struct {
+  double dt;        /* time step (fs)                                     */
+  double E0;        /* applied field (V/nm)                               */
+  double w_sp;      /* superparticle weight (electrons per unit w)        */
+  double phi_w;     /* work function (eV)                                 */
+  double j_scale;   /* multiplier on the emission current (1 = physical)  */
+  uint64_t seed;    /* Philox key word 0                                  */
+  int64_t step0;    /* index of the first step                            */
+  int64_t instance; /* Philox key word 1                                  */
+  const double* s_face; /* device [n_emit] weight per emitting face or NULL */
+  int32_t resort_every; /* sort by tet + compact every k steps (0: never) */
+  int32_t pad;
+  pic_solve_params solve;
+} pic_step_params;
+
+typedef struct {
+  int64_t n_before, n_inj, n_anode, n_cathode, n_after;
+  int64_t q_before, q_inj, q_anode, q_cathode, q_after; /* fixed point */
+  int64_t cg_iters, n_clamp, status, n_trunc;
+  int64_t walk_steps, walk_max, n_fallback, n_slots;
+  double cg_relres, emit_current, mean_face_E, max_face_E;
+} pic_step_stats;
+
+/* Advance n_steps steps k = step0 .. step0+n_steps-1.  Per step: gather the
+ * nodal field at each particle and kick (Eq. leapfrog3 then Eq. leapfrog1),
+ * inject from the emitting faces with the same field (Eq. nsp,
+ * Eq. rnd_nsp, App. E, Eq. sp_velocity, Eq. sp_displacement), drift
+ * (Eq. leapfrog2), wrap laterally, absorb at z >= z_top (anode) or outside
+ * the vacuum (cathode), locate, deposit, solve for phi_{k+1} and recover the
+ * nodal field.  fields->E must hold the field of phi on entry.
+ * stats: device [n_steps] pic_step_stats (overwritten). */
+PIC_API pic_status pic_step(pic_mesh* mesh, const pic_particles* particles,
+                    const pic_fields* fields, const pic_step_params* params,
+                    int32_t n_steps, pic_step_stats* stats, void* stream);
+
+/* Sum over emitting faces of J_f A_f (e/fs) for the nodal field E (device
+ * [4*n_nodes]); result written to device *rate (f64) and, when face_F is
+ * not NULL, |E| at each face centroid to device face_F [n_emit]. */
+PIC_API pic_status emission_rate(const pic_mesh* mesh, const double* E, double phi_w,
+                         double* rate, double* face_F, void* stream);
+
+PIC_API const char* pic_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FEMOCS_PIC_H */

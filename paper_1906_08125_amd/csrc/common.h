@@ -1,0 +1,273 @@
+// Internal definitions shared by the HIP sources of the PIC library.
+// Everything here is compiled for gfx950 with -ffp-contract=off: the
+// barycentric and deposition arithmetic is specified operation by operation
+// and must not be re-associated or fused.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/femocs_pic.h"
+
+namespace fp {
+
+// ---------------------------------------------------------------------------
+// Physical constants (CODATA 2018 base values; derived values computed).
+// ---------------------------------------------------------------------------
+struct Phys {
+  double qm;     // q/m of an electron, nm fs^-2 per V/nm
+  double e_eps;  // e/eps0, V nm per elementary charge
+  double a_fn;   // A eV V^-2
+  double b_fn;   // eV^-3/2 V nm^-1
+  double c_s;    // eV^2 V^-1 nm
+  double j_unit; // A/m^2 -> e nm^-2 fs^-1
+};
+Phys phys_constants();  // host
+
+constexpr double kFx = 1099511627776.0;       // 2^40
+constexpr double kFxInv = 1.0 / 1099511627776.0;
+
+// ---------------------------------------------------------------------------
+// Device mesh records (one 128-byte line each).
+// ---------------------------------------------------------------------------
+struct alignas(128) TetWalk {   // vertices (unwrapped) + adjacency
+  double v[12];
+  int32_t nbr[4];   // neighbour tet, -1 top, -2 metal
+  int8_t nsh[8];    // (dx, dy) frame shift when crossing face i
+  int32_t pad[2];
+};
+static_assert(sizeof(TetWalk) == 128, "TetWalk is one line");
+
+struct alignas(128) TetGeom {   // barycentric map + vertex ids
+  double v0[3];
+  double m[9];      // rows m1, m2, m3
+  int32_t node[4];
+  int32_t pad[4];
+};
+static_assert(sizeof(TetGeom) == 128, "TetGeom is one line");
+
+struct DevMesh {
+  int64_t n_nodes, n_tets, n_free, nnz, nnz_field, n_emit;
+  double Lx, Ly, z_top;
+  const TetWalk* tw;
+  const TetGeom* tg;
+  // stiffness on free nodes (CSR, int32 rowptr), Jacobi inverse diagonal
+  const int32_t* rowptr;
+  const int32_t* col;
+  const double* val;
+  const float* val32;
+  const double* invdiag;
+  const float* invdiag32;
+  const double* g_unit;      // Neumann load per unit E0 [n_free]
+  const int32_t* free2node;  // [n_free]
+  const int32_t* node2free;  // [n_nodes], -1 for Dirichlet
+  // nodal field operator: rows all nodes, columns free indices
+  const int32_t* frow;
+  const int32_t* fcol;
+  const double* fval;        // [3][nnz_field]
+  // emitting faces
+  const int32_t* e_tet;
+  const int32_t* e_nodes;    // [3*n_emit]
+  const double* e_abc;       // [9*n_emit]
+  const double* e_area;
+  const double* e_nrm;       // [3*n_emit], into the vacuum
+  // bucket grid
+  int32_t nb[3];
+  double b0[3], b1[3], binv[3];
+  const int32_t* bstart;     // [nbx*nby*nbz + 1]
+  const int32_t* bitem;
+};
+
+// ---------------------------------------------------------------------------
+// Error-free transformations and orientation predicates.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline void ef_sum(double a, double b, double& s,
+                                       double& e) {
+  s = a + b;
+  double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+__host__ __device__ inline void ef_prod(double a, double b, double& p,
+                                        double& e) {
+  p = a * b;
+  e = fma(a, b, -p);
+}
+
+// Floating-point vol6(a,b,c,d) = det[b-a; c-a; d-a] and the static error
+// bound (7 + 56 u) u * permanent of Shewchuk's orient3d filter: when
+// |det| > bound the sign of det is the sign of the exact determinant.
+__host__ __device__ inline double vol6_filtered(const double* a,
+                                                const double* b,
+                                                const double* c,
+                                                const double* d,
+                                                double& bound) {
+  const double ux = b[0] - a[0], uy = b[1] - a[1], uz = b[2] - a[2];
+  const double vx = c[0] - a[0], vy = c[1] - a[1], vz = c[2] - a[2];
+  const double wx = d[0] - a[0], wy = d[1] - a[1], wz = d[2] - a[2];
+  const double m1 = vy * wz, m2 = vz * wy;
+  const double m3 = vz * wx, m4 = vx * wz;
+  const double m5 = vx * wy, m6 = vy * wx;
+  const double det = ux * (m1 - m2) + uy * (m3 - m4) + uz * (m5 - m6);
+  const double perm = (fabs(m1) + fabs(m2)) * fabs(ux) +
+                      (fabs(m3) + fabs(m4)) * fabs(uy) +
+                      (fabs(m5) + fabs(m6)) * fabs(uz);
+  const double u = 1.1102230246251565e-16;  // 2^-53
+  bound = (7.0 + 56.0 * u) * u * perm;
+  return det;
+}
+
+// Exact sign of det[b-a; c-a; d-a]: the three difference vectors are split
+// into exact two-term sums (x = hi + lo), the determinant is expanded
+// multilinearly into 6 x 8 triple products, each turned into four doubles
+// that sum to it exactly, and all of them are accumulated into one
+// nonoverlapping expansion (Shewchuk 1997, Grow-Expansion with zero
+// elimination).  The sign of the largest component is the answer.
+__host__ __device__ inline int vol6_sign_exact(const double* a,
+                                               const double* b,
+                                               const double* c,
+                                               const double* d) {
+  double U[3][2], V[3][2], W[3][2];
+  for (int k = 0; k < 3; ++k) {
+    ef_sum(b[k], -a[k], U[k][0], U[k][1]);
+    ef_sum(c[k], -a[k], V[k][0], V[k][1]);
+    ef_sum(d[k], -a[k], W[k][0], W[k][1]);
+  }
+  // permutations of (x, y, z) for rows (U, V, W) and their signs
+  const int P[6][3] = {{0, 1, 2}, {1, 2, 0}, {2, 0, 1},
+                       {0, 2, 1}, {2, 1, 0}, {1, 0, 2}};
+  double ex[200];
+  int len = 0;
+  for (int s = 0; s < 6; ++s) {
+    const double sg = s < 3 ? 1.0 : -1.0;
+    for (int h = 0; h < 8; ++h) {
+      const double f0 = U[P[s][0]][h & 1];
+      const double f1 = V[P[s][1]][(h >> 1) & 1];
+      const double f2 = W[P[s][2]][(h >> 2) & 1];
+      double p, e, p1, e1, p2, e2;
+      ef_prod(f0, f1, p, e);
+      ef_prod(p, f2, p1, e1);
+      ef_prod(e, f2, p2, e2);
+      const double t[4] = {p1, e1, p2, e2};
+      for (int q = 0; q < 4; ++q) {
+        double acc = sg * t[q];
+        if (acc == 0.0) continue;
+        // in-place grow: output index never passes the input index
+        int out = 0;
+        for (int i = 0; i < len; ++i) {
+          double sum, err;
+          ef_sum(acc, ex[i], sum, err);
+          acc = sum;
+          if (err != 0.0) ex[out++] = err;
+        }
+        if (acc != 0.0 || out == 0) ex[out++] = acc;
+        len = out;
+      }
+    }
+  }
+  for (int i = len - 1; i >= 0; --i) {
+    if (ex[i] > 0.0) return 1;
+    if (ex[i] < 0.0) return -1;
+  }
+  return 0;
+}
+
+__host__ __device__ inline int vol6_sign(const double* a, const double* b,
+                                         const double* c, const double* d) {
+  double bound;
+  const double det = vol6_filtered(a, b, c, d, bound);
+  if (det > bound) return 1;
+  if (-det > bound) return -1;
+  return vol6_sign_exact(a, b, c, d);
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 counter-based generator (Salmon et al., SC'11).
+// ---------------------------------------------------------------------------
+__host__ __device__ inline void philox4x64_10(uint64_t k0, uint64_t k1,
+                                              uint64_t c0, uint64_t c1,
+                                              uint64_t c2, uint64_t c3,
+                                              uint64_t out[4]) {
+  for (int r = 0; r < 10; ++r) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const uint64_t h0 = __umul64hi(0xD2E7470EE14C6C93ull, c0);
+    const uint64_t h1 = __umul64hi(0xCA5A826395121157ull, c2);
+#else
+    const uint64_t h0 = (uint64_t)(((unsigned __int128)0xD2E7470EE14C6C93ull * c0) >> 64);
+    const uint64_t h1 = (uint64_t)(((unsigned __int128)0xCA5A826395121157ull * c2) >> 64);
+#endif
+    const uint64_t l0 = 0xD2E7470EE14C6C93ull * c0;
+    const uint64_t l1 = 0xCA5A826395121157ull * c2;
+    const uint64_t n0 = h1 ^ c1 ^ k0;
+    const uint64_t n2 = h0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = l1;
+    c2 = n2;
+    c3 = l0;
+    k0 += 0x9E3779B97F4A7C15ull;
+    k1 += 0xBB67AE8584CAA73Bull;
+  }
+  out[0] = c0;
+  out[1] = c1;
+  out[2] = c2;
+  out[3] = c3;
+}
+
+__host__ __device__ inline double unit_double(uint64_t w) {
+  return (double)(w >> 11) * 1.1102230246251565e-16;
+}
+
+// ---------------------------------------------------------------------------
+// Barycentric coordinates in a tet (the fixed arithmetic shared with the
+// deposition rule): d = p - v0, l_k = (m_k.x d.x + m_k.y d.y) + m_k.z d.z,
+// l_0 = ((1 - l_1) - l_2) - l_3.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline void barycentric(const TetGeom& g, double px,
+                                            double py, double pz,
+                                            double lam[4]) {
+  const double dx = px - g.v0[0], dy = py - g.v0[1], dz = pz - g.v0[2];
+  const double l1 = (g.m[0] * dx + g.m[1] * dy) + g.m[2] * dz;
+  const double l2 = (g.m[3] * dx + g.m[4] * dy) + g.m[5] * dz;
+  const double l3 = (g.m[6] * dx + g.m[7] * dy) + g.m[8] * dz;
+  lam[0] = ((1.0 - l1) - l2) - l3;
+  lam[1] = l1;
+  lam[2] = l2;
+  lam[3] = l3;
+}
+
+__host__ __device__ inline int64_t fx_round(double x) {
+  return (int64_t)rint(x);
+}
+
+// Fixed-point split of one particle's charge over its four vertices.
+__host__ __device__ inline void charge_split(const double lam[4], double w,
+                                             int64_t q[4]) {
+  q[1] = fx_round((lam[1] * w) * kFx);
+  q[2] = fx_round((lam[2] * w) * kFx);
+  q[3] = fx_round((lam[3] * w) * kFx);
+  q[0] = fx_round(w * kFx) - ((q[1] + q[2]) + q[3]);
+}
+
+// Bucket index along one axis: a monotone map, shared by registration and
+// query, so a tet registered from its closed bounding box is found by every
+// point it holds.
+__host__ __device__ inline int bucket_axis(double x, double x0, double inv,
+                                           int n) {
+  const double f = floor((x - x0) * inv);
+  if (f < 0.0) return 0;
+  if (f > (double)(n - 1)) return n - 1;
+  return (int)f;
+}
+
+// Internal per-handle device scratch layout (counters and scalars).
+struct StepScratch {
+  // counters used by the particle kernels of one step
+  int32_t n_fallback;
+  int32_t inj_base;
+  int32_t inj_total;
+  int32_t inj_fit;
+  int32_t n_live;
+  int32_t pad[3];
+};
+
+}  // namespace fp

@@ -1,0 +1,490 @@
+// mesh_create / mesh_destroy: host preprocessing of the tetrahedral vacuum
+// mesh (Sec. II A) and upload of the device records.
+//
+//  * orientation: exact sign of D, local vertices 2 and 3 swapped when
+//    negative; the barycentric map m_k = c_k / D with c_1 = e2 x e3,
+//    c_2 = e3 x e1, c_3 = e1 x e2, D = e1 . c_1 (fixed arithmetic);
+//  * adjacency: faces matched by node triple plus relative lattice shift,
+//    with the frame shift to apply when crossing a periodic face;
+//  * boundary: unmatched faces on z = z_top are the Neumann top (Gamma_1),
+//    all others metal (Gamma_3, Dirichlet) -- Eq. poisson_bc;
+//  * P1 stiffness on free nodes (App. B), Jacobi inverse diagonal, Neumann
+//    load per unit E0 (area/3 per top-face vertex), nodal-field operator R
+//    (volume-weighted mean of -grad phi over the tets holding a node);
+//  * emitting faces (metal faces with centroid z >= emit_zmin) in
+//    (owner tet, local face) order, with vertices in ascending local order;
+//  * a bucket grid listing every tet in each bucket its closed bounding box
+//    touches under the monotone bucket map used by queries.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mesh.h"
+#include "solver.h"
+
+namespace fp {
+
+Phys phys_constants() {
+  const double e = 1.602176634e-19;
+  const double h = 6.62607015e-34;
+  const double me = 9.1093837015e-31;
+  const double eps0 = 8.8541878128e-12;
+  const double pi = 3.14159265358979323846;
+  Phys p;
+  p.qm = -(e / me) * 1e9 * 1e-21;
+  p.e_eps = (e / eps0) * 1e9;
+  p.a_fn = e * e / (8.0 * pi * h);
+  p.b_fn = (8.0 * pi / 3.0) * std::sqrt(2.0 * me) / (e * h) * std::pow(e, 1.5) / 1e9;
+  p.c_s = e / (4.0 * pi * eps0) * 1e9;
+  p.j_unit = 1.0 / e * 1e-33;
+  return p;
+}
+
+namespace {
+
+const int kFace[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
+
+struct V3 {
+  double x, y, z;
+};
+inline V3 sub(const double* a, const double* b) {
+  return {a[0] - b[0], a[1] - b[1], a[2] - b[2]};
+}
+inline V3 cross(V3 a, V3 b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+inline double dot(V3 a, V3 b) { return (a.x * b.x + a.y * b.y) + a.z * b.z; }
+
+struct FaceKey {
+  uint64_t hi, lo;
+  int32_t tet;
+  int8_t face, s0x, s0y, pad;
+  bool operator<(const FaceKey& o) const {
+    if (hi != o.hi) return hi < o.hi;
+    if (lo != o.lo) return lo < o.lo;
+    return tet < o.tet;
+  }
+  bool same(const FaceKey& o) const { return hi == o.hi && lo == o.lo; }
+};
+
+template <typename T>
+T* upload(pic_mesh* h, const std::vector<T>& v, hipError_t& err) {
+  if (err != hipSuccess) return nullptr;
+  void* p = nullptr;
+  const size_t bytes = std::max<size_t>(v.size() * sizeof(T), 16);
+  err = hipMalloc(&p, bytes);
+  if (err != hipSuccess) return nullptr;
+  h->allocs.push_back(p);
+  h->info.device_bytes += (int64_t)bytes;
+  if (!v.empty()) err = hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+  return (T*)p;
+}
+
+}  // namespace
+
+void* dev_alloc(pic_mesh* h, size_t bytes, hipError_t& err) {
+  if (err != hipSuccess) return nullptr;
+  void* p = nullptr;
+  err = hipMalloc(&p, std::max<size_t>(bytes, 16));
+  if (err != hipSuccess) return nullptr;
+  h->allocs.push_back(p);
+  h->info.device_bytes += (int64_t)bytes;
+  return p;
+}
+
+pic_status build_mesh(const pic_mesh_desc* d, pic_mesh* h, std::string& msg) {
+  const int64_t N = d->n_nodes, T = d->n_tets;
+  if (N <= 0 || T <= 0 || !d->xyz || !d->tet) {
+    msg = "mesh_create: empty mesh or null arrays";
+    return PIC_E_ARG;
+  }
+  if (!(d->Lx > 0) || !(d->Ly > 0) || !std::isfinite(d->z_top)) {
+    msg = "mesh_create: lateral periods must be positive and z_top finite";
+    return PIC_E_ARG;
+  }
+  if (N >= (1ll << 31) || T >= (1ll << 31)) {
+    msg = "mesh_create: more than 2^31 nodes or tets";
+    return PIC_E_ARG;
+  }
+  const double Lx = d->Lx, Ly = d->Ly;
+  std::vector<int32_t> tv(d->tet, d->tet + 4 * T);
+  std::vector<int8_t> ts(8 * T, 0);
+  if (d->shift) std::copy(d->shift, d->shift + 8 * T, ts.begin());
+  std::vector<TetWalk> tw(T);
+  std::vector<TetGeom> tg(T);
+  std::vector<double> D(T);
+  // 1. orientation, unwrapped vertices, barycentric maps
+  for (int64_t t = 0; t < T; ++t) {
+    double v[4][3];
+    for (int k = 0; k < 4; ++k) {
+      const int32_t nd = tv[4 * t + k];
+      if (nd < 0 || nd >= N) {
+        msg = "mesh_create: node id out of range in tet " + std::to_string(t);
+        return PIC_E_MESH;
+      }
+      v[k][0] = d->xyz[3 * (int64_t)nd] + (double)ts[8 * t + 2 * k] * Lx;
+      v[k][1] = d->xyz[3 * (int64_t)nd + 1] + (double)ts[8 * t + 2 * k + 1] * Ly;
+      v[k][2] = d->xyz[3 * (int64_t)nd + 2];
+    }
+    const int s = vol6_sign(v[0], v[1], v[2], v[3]);
+    if (s == 0) {
+      msg = "mesh_create: zero-volume tet " + std::to_string(t);
+      return PIC_E_MESH;
+    }
+    if (s < 0) {
+      std::swap(tv[4 * t + 2], tv[4 * t + 3]);
+      std::swap(ts[8 * t + 4], ts[8 * t + 6]);
+      std::swap(ts[8 * t + 5], ts[8 * t + 7]);
+      for (int k = 0; k < 3; ++k) std::swap(v[2][k], v[3][k]);
+    }
+    TetWalk& W = tw[t];
+    TetGeom& G = tg[t];
+    std::memset(&W, 0, sizeof W);
+    std::memset(&G, 0, sizeof G);
+    for (int k = 0; k < 4; ++k)
+      for (int c = 0; c < 3; ++c) W.v[3 * k + c] = v[k][c];
+    const V3 e1 = sub(v[1], v[0]), e2 = sub(v[2], v[0]), e3 = sub(v[3], v[0]);
+    const V3 c1 = cross(e2, e3), c2 = cross(e3, e1), c3 = cross(e1, e2);
+    const double det = dot(e1, c1);
+    D[t] = det;
+    const V3 cs[3] = {c1, c2, c3};
+    for (int r = 0; r < 3; ++r) {
+      G.m[3 * r + 0] = cs[r].x / det;
+      G.m[3 * r + 1] = cs[r].y / det;
+      G.m[3 * r + 2] = cs[r].z / det;
+    }
+    for (int c = 0; c < 3; ++c) G.v0[c] = v[0][c];
+    for (int k = 0; k < 4; ++k) G.node[k] = tv[4 * t + k];
+  }
+  // 2. faces and neighbours
+  {
+    std::vector<FaceKey> keys(4 * T);
+    for (int64_t t = 0; t < T; ++t)
+      for (int f = 0; f < 4; ++f) {
+        int32_t nn[3];
+        int sx[3], sy[3];
+        for (int j = 0; j < 3; ++j) {
+          const int l = kFace[f][j];
+          nn[j] = tv[4 * t + l];
+          sx[j] = ts[8 * t + 2 * l];
+          sy[j] = ts[8 * t + 2 * l + 1];
+        }
+        int ord[3] = {0, 1, 2};
+        std::sort(ord, ord + 3, [&](int a, int b) { return nn[a] < nn[b]; });
+        uint32_t code = 0;
+        for (int j = 1; j < 3; ++j) {
+          const int dx = sx[ord[j]] - sx[ord[0]] + 2;
+          const int dy = sy[ord[j]] - sy[ord[0]] + 2;
+          code = (code << 6) | (uint32_t)(dx << 3) | (uint32_t)dy;
+        }
+        FaceKey& k = keys[4 * t + f];
+        k.hi = ((uint64_t)(uint32_t)nn[ord[0]] << 32) | (uint32_t)nn[ord[1]];
+        k.lo = ((uint64_t)(uint32_t)nn[ord[2]] << 16) | code;
+        k.tet = (int32_t)t;
+        k.face = (int8_t)f;
+        k.s0x = (int8_t)sx[ord[0]];
+        k.s0y = (int8_t)sy[ord[0]];
+      }
+    std::sort(keys.begin(), keys.end());
+    int64_t n_top = 0, n_metal = 0;
+    for (size_t i = 0; i < keys.size();) {
+      size_t j = i + 1;
+      while (j < keys.size() && keys[j].same(keys[i])) ++j;
+      if (j - i > 2) {
+        msg = "mesh_create: non-manifold face";
+        return PIC_E_MESH;
+      }
+      const FaceKey& a = keys[i];
+      if (j - i == 2) {
+        const FaceKey& b = keys[i + 1];
+        tw[a.tet].nbr[a.face] = b.tet;
+        tw[b.tet].nbr[b.face] = a.tet;
+        tw[a.tet].nsh[2 * a.face] = (int8_t)(b.s0x - a.s0x);
+        tw[a.tet].nsh[2 * a.face + 1] = (int8_t)(b.s0y - a.s0y);
+        tw[b.tet].nsh[2 * b.face] = (int8_t)(a.s0x - b.s0x);
+        tw[b.tet].nsh[2 * b.face + 1] = (int8_t)(a.s0y - b.s0y);
+      } else {
+        bool top = true;
+        for (int q = 0; q < 3; ++q)
+          if (tw[a.tet].v[3 * kFace[(int)a.face][q] + 2] != d->z_top) top = false;
+        tw[a.tet].nbr[a.face] = top ? -1 : -2;
+        if (top) ++n_top; else ++n_metal;
+      }
+      i = j;
+    }
+    h->info.n_top = n_top;
+    h->info.n_metal = n_metal;
+  }
+  // 3. Dirichlet nodes and free numbering
+  std::vector<char> dir(N, 0);
+  for (int64_t t = 0; t < T; ++t)
+    for (int f = 0; f < 4; ++f)
+      if (tw[t].nbr[f] == -2)
+        for (int q = 0; q < 3; ++q) dir[tv[4 * t + kFace[f][q]]] = 1;
+  std::vector<int32_t> node2free(N, -1), free2node, dir_nodes;
+  for (int64_t i = 0; i < N; ++i) {
+    if (dir[i]) {
+      dir_nodes.push_back((int32_t)i);
+    } else {
+      node2free[i] = (int32_t)free2node.size();
+      free2node.push_back((int32_t)i);
+    }
+  }
+  const int64_t NF = (int64_t)free2node.size();
+  // 4. node -> tet lists
+  std::vector<int64_t> nt_start(N + 1, 0);
+  for (int64_t q = 0; q < 4 * T; ++q) nt_start[tv[q] + 1]++;
+  for (int64_t i = 0; i < N; ++i) nt_start[i + 1] += nt_start[i];
+  std::vector<int32_t> nt_list(4 * T);
+  {
+    std::vector<int64_t> fill(nt_start.begin(), nt_start.end() - 1);
+    for (int64_t t = 0; t < T; ++t)
+      for (int k = 0; k < 4; ++k) nt_list[fill[tv[4 * t + k]]++] = (int32_t)t;
+  }
+  // 5. rows: K on free rows (free columns), R on all rows (free columns)
+  std::vector<int32_t> rowptr(NF + 1, 0), col;
+  std::vector<double> val;
+  std::vector<int32_t> frow(N + 1, 0), fcol;
+  std::vector<double> fv[3];
+  std::vector<double> invdiag(NF, 0.0), g_unit(NF, 0.0);
+  std::vector<int32_t> nb;
+  std::vector<double> kr, rx, ry, rz;
+  for (int64_t i = 0; i < N; ++i) {
+    nb.clear();
+    for (int64_t q = nt_start[i]; q < nt_start[i + 1]; ++q) {
+      const int32_t t = nt_list[q];
+      for (int k = 0; k < 4; ++k) {
+        const int32_t j = node2free[tv[4 * (int64_t)t + k]];
+        if (j >= 0) nb.push_back(j);
+      }
+    }
+    std::sort(nb.begin(), nb.end());
+    nb.erase(std::unique(nb.begin(), nb.end()), nb.end());
+    kr.assign(nb.size(), 0.0);
+    rx.assign(nb.size(), 0.0);
+    ry.assign(nb.size(), 0.0);
+    rz.assign(nb.size(), 0.0);
+    double Wi = 0.0;
+    for (int64_t q = nt_start[i]; q < nt_start[i + 1]; ++q) {
+      const int32_t t = nt_list[q];
+      const TetGeom& G = tg[t];
+      double g[4][3];
+      for (int c = 0; c < 3; ++c) {
+        g[1][c] = G.m[c];
+        g[2][c] = G.m[3 + c];
+        g[3][c] = G.m[6 + c];
+        g[0][c] = -((G.m[c] + G.m[3 + c]) + G.m[6 + c]);
+      }
+      const double V = D[t] / 6.0;
+      Wi += V;
+      int a = 0;
+      while (tv[4 * (int64_t)t + a] != i) ++a;
+      for (int b = 0; b < 4; ++b) {
+        const int32_t j = node2free[tv[4 * (int64_t)t + b]];
+        if (j < 0) continue;
+        const size_t pos = std::lower_bound(nb.begin(), nb.end(), j) - nb.begin();
+        kr[pos] += V * ((g[a][0] * g[b][0] + g[a][1] * g[b][1]) + g[a][2] * g[b][2]);
+        rx[pos] -= V * g[b][0];
+        ry[pos] -= V * g[b][1];
+        rz[pos] -= V * g[b][2];
+      }
+    }
+    for (size_t p = 0; p < nb.size(); ++p) {
+      fcol.push_back(nb[p]);
+      fv[0].push_back(rx[p] / Wi);
+      fv[1].push_back(ry[p] / Wi);
+      fv[2].push_back(rz[p] / Wi);
+    }
+    frow[i + 1] = (int32_t)fcol.size();
+    const int32_t fi = node2free[i];
+    if (fi >= 0) {
+      for (size_t p = 0; p < nb.size(); ++p) {
+        col.push_back(nb[p]);
+        val.push_back(kr[p]);
+        if (nb[p] == fi) invdiag[fi] = 1.0 / kr[p];
+      }
+      rowptr[fi + 1] = (int32_t)col.size();
+    }
+  }
+  if (col.size() >= (1ull << 31) || fcol.size() >= (1ull << 31)) {
+    msg = "mesh_create: matrix too large for 32-bit row pointers";
+    return PIC_E_ARG;
+  }
+  // 6. Neumann load per unit E0 on the top plane
+  for (int64_t t = 0; t < T; ++t)
+    for (int f = 0; f < 4; ++f) {
+      if (tw[t].nbr[f] != -1) continue;
+      const double* A = &tw[t].v[3 * kFace[f][0]];
+      const double* B = &tw[t].v[3 * kFace[f][1]];
+      const double* C = &tw[t].v[3 * kFace[f][2]];
+      const V3 cr = cross(sub(B, A), sub(C, A));
+      const double area = 0.5 * std::sqrt(dot(cr, cr));
+      for (int q = 0; q < 3; ++q) {
+        const int32_t fi = node2free[tv[4 * t + kFace[f][q]]];
+        if (fi >= 0) g_unit[fi] += area / 3.0;
+      }
+    }
+  // 7. emitting faces
+  std::vector<int32_t> e_tet, e_nodes;
+  std::vector<double> e_abc, e_area, e_nrm;
+  for (int64_t t = 0; t < T; ++t)
+    for (int f = 0; f < 4; ++f) {
+      if (tw[t].nbr[f] != -2) continue;
+      const double* A = &tw[t].v[3 * kFace[f][0]];
+      const double* B = &tw[t].v[3 * kFace[f][1]];
+      const double* C = &tw[t].v[3 * kFace[f][2]];
+      if (!((A[2] + B[2]) + C[2] >= 3.0 * d->emit_zmin)) continue;
+      const V3 cr = cross(sub(B, A), sub(C, A));
+      const double len = std::sqrt(dot(cr, cr));
+      const V3 to = sub(&tw[t].v[3 * f], A);
+      const double sg = dot(cr, to) < 0 ? -1.0 : 1.0;
+      e_tet.push_back((int32_t)t);
+      for (int q = 0; q < 3; ++q) e_nodes.push_back(tv[4 * t + kFace[f][q]]);
+      for (const double* P : {A, B, C})
+        for (int c = 0; c < 3; ++c) e_abc.push_back(P[c]);
+      e_area.push_back(0.5 * len);
+      e_nrm.push_back(sg * cr.x / len);
+      e_nrm.push_back(sg * cr.y / len);
+      e_nrm.push_back(sg * cr.z / len);
+    }
+  // 8. bucket grid
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  double vol = 0.0;
+  for (int64_t t = 0; t < T; ++t) {
+    vol += D[t] / 6.0;
+    for (int q = 0; q < 12; ++q) {
+      lo[q % 3] = std::min(lo[q % 3], tw[t].v[q]);
+      hi[q % 3] = std::max(hi[q % 3], tw[t].v[q]);
+    }
+  }
+  DevMesh& M = h->dm;
+  const double edge = std::cbrt(6.0 * vol / (double)T);
+  for (int k = 0; k < 3; ++k) {
+    const double L = hi[k] - lo[k];
+    int n = (int)std::ceil(L / edge);
+    n = std::max(1, std::min(n, 512));
+    M.nb[k] = n;
+    M.b0[k] = lo[k];
+    M.b1[k] = hi[k];
+    M.binv[k] = (double)n / L;
+  }
+  const int64_t NB = (int64_t)M.nb[0] * M.nb[1] * M.nb[2];
+  std::vector<int32_t> bstart(NB + 1, 0), bitem;
+  {
+    std::vector<int32_t> box(6 * T);
+    for (int64_t t = 0; t < T; ++t) {
+      for (int k = 0; k < 3; ++k) {
+        double a = tw[t].v[k], b = a;
+        for (int q = 1; q < 4; ++q) {
+          a = std::min(a, tw[t].v[3 * q + k]);
+          b = std::max(b, tw[t].v[3 * q + k]);
+        }
+        box[6 * t + k] = bucket_axis(a, M.b0[k], M.binv[k], M.nb[k]);
+        box[6 * t + 3 + k] = bucket_axis(b, M.b0[k], M.binv[k], M.nb[k]);
+      }
+    }
+    for (int pass = 0; pass < 2; ++pass) {
+      std::vector<int32_t> fill;
+      if (pass == 1) fill.assign(bstart.begin(), bstart.end() - 1);
+      for (int64_t t = 0; t < T; ++t) {
+        const int32_t* b = &box[6 * t];
+        for (int x = b[0]; x <= b[3]; ++x)
+          for (int y = b[1]; y <= b[4]; ++y)
+            for (int z = b[2]; z <= b[5]; ++z) {
+              const int64_t id = ((int64_t)x * M.nb[1] + y) * M.nb[2] + z;
+              if (pass == 0) bstart[id + 1]++;
+              else bitem[fill[id]++] = (int32_t)t;
+            }
+      }
+      if (pass == 0) {
+        for (int64_t i = 0; i < NB; ++i) bstart[i + 1] += bstart[i];
+        bitem.resize(bstart[NB]);
+      }
+    }
+  }
+  // 9. upload
+  std::vector<float> val32(val.begin(), val.end()), invdiag32(invdiag.begin(), invdiag.end());
+  std::vector<double> fval;
+  fval.reserve(3 * fcol.size());
+  for (int c = 0; c < 3; ++c) fval.insert(fval.end(), fv[c].begin(), fv[c].end());
+  hipError_t err = hipSuccess;
+  M.n_nodes = N;
+  M.n_tets = T;
+  M.n_free = NF;
+  M.nnz = (int64_t)col.size();
+  M.nnz_field = (int64_t)fcol.size();
+  M.n_emit = (int64_t)e_tet.size();
+  M.Lx = Lx;
+  M.Ly = Ly;
+  M.z_top = d->z_top;
+  M.tw = upload(h, tw, err);
+  M.tg = upload(h, tg, err);
+  M.rowptr = upload(h, rowptr, err);
+  M.col = upload(h, col, err);
+  M.val = upload(h, val, err);
+  M.val32 = upload(h, val32, err);
+  M.invdiag = upload(h, invdiag, err);
+  M.invdiag32 = upload(h, invdiag32, err);
+  M.g_unit = upload(h, g_unit, err);
+  M.free2node = upload(h, free2node, err);
+  M.node2free = upload(h, node2free, err);
+  M.frow = upload(h, frow, err);
+  M.fcol = upload(h, fcol, err);
+  M.fval = upload(h, fval, err);
+  M.e_tet = upload(h, e_tet, err);
+  M.e_nodes = upload(h, e_nodes, err);
+  M.e_abc = upload(h, e_abc, err);
+  M.e_area = upload(h, e_area, err);
+  M.e_nrm = upload(h, e_nrm, err);
+  M.bstart = upload(h, bstart, err);
+  M.bitem = upload(h, bitem, err);
+  h->dir_nodes = upload(h, dir_nodes, err);
+  h->n_dir = (int64_t)dir_nodes.size();
+  // solver scratch
+  const size_t vb = sizeof(double) * (size_t)std::max<int64_t>(NF, 1);
+  for (int k = 0; k < 7; ++k) h->cg_vec[k] = (double*)dev_alloc(h, vb, err);
+  int bpc = 0;
+  if (err == hipSuccess) err = pcg_fp64_occupancy(h->cg_block, &bpc);
+  int dev = 0, ncu = 0;
+  if (err == hipSuccess) err = hipGetDevice(&dev);
+  if (err == hipSuccess) err = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (err == hipSuccess) {
+    h->n_cu = ncu;
+    int g = std::max(1, bpc) * ncu;
+    // enough rows per workgroup to amortise the barrier; multiple of 8 XCDs
+    const int64_t want = std::max<int64_t>(8, (NF + 255) / 256);
+    if (g > want) g = (int)want;
+    if (g >= 8) g -= g % 8;
+    h->cg_grid = g;
+  }
+  h->cg_part = (double*)dev_alloc(h, sizeof(double) * 8 * (size_t)std::max(h->cg_grid, 1), err);
+  h->scratch = (StepScratch*)dev_alloc(h, sizeof(StepScratch), err);
+  h->offsets = (int32_t*)dev_alloc(h, sizeof(int32_t) * (size_t)(M.n_emit + 1), err);
+  h->counts = (int32_t*)dev_alloc(h, sizeof(int32_t) * (size_t)(M.n_emit + 1), err);
+  h->solve_stats = (pic_solve_stats*)dev_alloc(h, sizeof(pic_solve_stats), err);
+  h->locate_count = (int32_t*)dev_alloc(h, sizeof(int32_t), err);
+  if (err != hipSuccess) {
+    msg = std::string("mesh_create: ") + hipGetErrorString(err);
+    return PIC_E_DEVICE;
+  }
+  h->h_e_tet = e_tet;
+  h->h_e_nodes = e_nodes;
+  h->h_e_area = e_area;
+  h->info.n_nodes = N;
+  h->info.n_tets = T;
+  h->info.n_free = NF;
+  h->info.nnz = M.nnz;
+  h->info.nnz_field = M.nnz_field;
+  h->info.n_emit = M.n_emit;
+  return PIC_OK;
+}
+
+void free_mesh(pic_mesh* h) {
+  for (void* p : h->allocs) (void)hipFree(p);
+  h->allocs.clear();
+}
+
+}  // namespace fp

@@ -1,0 +1,72 @@
+// Launch interface of the particle kernels.
+#pragma once
+#include "common.h"
+
+namespace fp {
+
+struct EmitConsts {
+  double a_fn, b_fn, c_s, j_unit;
+};
+
+struct StepArgs {
+  DevMesh m;
+  double *x, *y, *z, *vx, *vy, *vz, *w;
+  int32_t *tet, *birth;
+  int64_t* id;
+  int32_t* n_slots;
+  const double* E;      // nodal field [4 n_nodes]
+  int64_t* charge;      // [n_nodes]
+  const double* s_face; // [n_emit] or null
+  const int32_t* offsets;  // [n_emit + 1] exclusive scan of counts
+  int32_t* queue;       // [capacity] fallback queue
+  StepScratch* scratch;
+  pic_step_stats* stats;
+  double Q, dt, qm_dt;
+  uint64_t seed;
+  uint64_t instance;
+  int64_t step;
+};
+
+struct EmitArgs {
+  DevMesh m;
+  const double* E;
+  EmitConsts c;
+  double phi_w, j_scale, dt, w_sp;
+  uint64_t seed, instance;
+  int64_t step;
+  int64_t capacity;
+  int32_t* counts;   // [n_emit] or null (rate only)
+  int32_t* offsets;  // [n_emit + 1]
+  int32_t* n_slots;
+  StepScratch* scratch;
+  pic_step_stats* stats;  // or null
+  double* rate;           // or null
+  double* face_F;         // or null
+};
+
+struct LocateArgs {
+  DevMesh m;
+  int64_t n;
+  const double *x, *y, *z;
+  int32_t* tet;
+  uint8_t* where;
+  int32_t* queue;
+  int32_t* n_queue;
+};
+
+struct DepositArgs {
+  DevMesh m;
+  int64_t n;
+  const double *x, *y, *z, *w;
+  const int32_t* tet;
+  int64_t* charge;
+};
+
+hipError_t launch_push(const StepArgs& a, int grid, hipStream_t s);
+hipError_t launch_emit(const EmitArgs& a, hipStream_t s);
+hipError_t launch_inject(const StepArgs& a, int grid, hipStream_t s);
+hipError_t launch_fallback(const StepArgs& a, int grid, hipStream_t s);
+hipError_t launch_locate(const LocateArgs& a, int grid, hipStream_t s);
+hipError_t launch_deposit(const DepositArgs& a, int grid, hipStream_t s);
+
+}  // namespace fp

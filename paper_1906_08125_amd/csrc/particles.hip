@@ -1,0 +1,599 @@
+// Particle side of the PIC cycle (Sec. II B 1-3): gather + leapfrog kick +
+// drift + lateral wrap + absorption + neighbour-walk location + fixed-point
+// deposition for the live particles; FN emission counts per face; injection
+// of new particles; exact canonical location for the few particles the walk
+// cannot certify.
+//
+// Particles are SoA arrays; every kernel runs a fixed grid-stride over the
+// slot range read from device memory, so the host never waits for counts.
+// Block b of the grid sweeps a contiguous slot range chosen so that the 8
+// XCDs (block b runs on XCD b mod 8) each see one contiguous eighth of the
+// slots; with particles sorted by tet, neighbouring tets then share an L2.
+#include "common.h"
+#include "particles.h"
+
+namespace fp {
+
+namespace {
+
+constexpr int kMaxWalk = 256;
+constexpr int kBlock = 256;
+
+struct Span {
+  int64_t lo, hi;
+};
+
+// contiguous, XCD-grouped slot span of this block
+__device__ inline Span block_span(int64_t n) {
+  const int G = gridDim.x;
+  const int g = blockIdx.x;
+  int chunk = g;
+  if ((G & 7) == 0) chunk = (g & 7) * (G >> 3) + (g >> 3);
+  const int64_t per = (n + G - 1) / G;
+  Span s;
+  s.lo = (int64_t)chunk * per;
+  s.hi = s.lo + per < n ? s.lo + per : n;
+  if (s.lo > n) s.lo = n;
+  return s;
+}
+
+// Per-block counters, reduced once per block into the step stats.
+struct Acc {
+  long long n_before, q_before, n_anode, q_anode, n_after, q_after;
+  long long n_cathode, q_cathode, n_inj, q_inj, walk_steps;
+  int walk_max;
+};
+
+__device__ inline void acc_zero(Acc& a) {
+  a.n_before = a.q_before = a.n_anode = a.q_anode = a.n_after = a.q_after = 0;
+  a.n_cathode = a.q_cathode = a.n_inj = a.q_inj = a.walk_steps = 0;
+  a.walk_max = 0;
+}
+
+__device__ inline long long wave_sum(long long v) {
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+__device__ inline int wave_max(int v) {
+  for (int off = 32; off >= 1; off >>= 1) {
+    const int o = __shfl_xor(v, off, 64);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
+__device__ inline void atomic_add_ll(int64_t* p, long long v) {
+  if (v != 0)
+    atomicAdd(reinterpret_cast<unsigned long long*>(p), (unsigned long long)v);
+}
+
+// integer sums are exact and order-free, so one atomic per wave suffices
+__device__ inline void acc_flush(const Acc& a, pic_step_stats* st) {
+  const long long v[11] = {a.n_before, a.q_before, a.n_anode,  a.q_anode,
+                           a.n_after,  a.q_after,  a.n_cathode, a.q_cathode,
+                           a.n_inj,    a.q_inj,    a.walk_steps};
+  int64_t* dst[11] = {&st->n_before, &st->q_before, &st->n_anode,
+                      &st->q_anode,  &st->n_after,  &st->q_after,
+                      &st->n_cathode, &st->q_cathode, &st->n_inj,
+                      &st->q_inj,    &st->walk_steps};
+  const bool lead = (threadIdx.x & 63) == 0;
+#pragma unroll
+  for (int k = 0; k < 11; ++k) {
+    const long long s = wave_sum(v[k]);
+    if (lead) atomic_add_ll(dst[k], s);
+  }
+  const int mx = wave_max(a.walk_max);
+  if (lead && mx > 0)
+    atomicMax(reinterpret_cast<unsigned long long*>(&st->walk_max),
+              (unsigned long long)mx);
+}
+
+__device__ inline double4 ld_E(const double* E, int32_t node) {
+  return reinterpret_cast<const double4*>(E)[node];
+}
+
+// Field at p inside tet g: sum_i lambda_i E_i in a fixed order.
+__device__ inline void gather_field(const TetGeom& g, const double* E,
+                                    double x, double y, double z,
+                                    double& ex, double& ey, double& ez) {
+  double lam[4];
+  barycentric(g, x, y, z, lam);
+  const double4 e0 = ld_E(E, g.node[0]);
+  const double4 e1 = ld_E(E, g.node[1]);
+  const double4 e2 = ld_E(E, g.node[2]);
+  const double4 e3 = ld_E(E, g.node[3]);
+  ex = ((lam[0] * e0.x + lam[1] * e1.x) + lam[2] * e2.x) + lam[3] * e3.x;
+  ey = ((lam[0] * e0.y + lam[1] * e1.y) + lam[2] * e2.y) + lam[3] * e3.y;
+  ez = ((lam[0] * e0.z + lam[1] * e1.z) + lam[2] * e2.z) + lam[3] * e3.z;
+}
+
+__device__ inline void deposit_one(const TetGeom& g, double x, double y,
+                                   double z, double w, int64_t* charge) {
+  double lam[4];
+  barycentric(g, x, y, z, lam);
+  int64_t q[4];
+  charge_split(lam, w, q);
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    atomicAdd(reinterpret_cast<unsigned long long*>(charge + g.node[k]),
+              (unsigned long long)q[k]);
+}
+
+// Neighbour walk from tet t with the point's frame offset (sx, sy) relative
+// to t.  Returns the tet when the point is certified strictly inside it in
+// its own frame (then no other tet holds it, so it is the canonical
+// answer), or -1 when the exact bucket scan must decide.
+__device__ inline int walk(const DevMesh& m, double x, double y, double z,
+                           int t, int sx, int sy, int& steps) {
+  for (steps = 0; steps < kMaxWalk; ++steps) {
+    const TetWalk& W = m.tw[t];
+    double v[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) v[k] = W.v[k];
+    const double p[3] = {x + (double)sx * m.Lx, y + (double)sy * m.Ly, z};
+    double o[4], b[4];
+    o[0] = vol6_filtered(p, v + 3, v + 6, v + 9, b[0]);
+    o[1] = vol6_filtered(v, p, v + 6, v + 9, b[1]);
+    o[2] = vol6_filtered(v, v + 3, p, v + 9, b[2]);
+    o[3] = vol6_filtered(v, v + 3, v + 6, p, b[3]);
+    bool inside = true;
+    int exitf = -1;
+    double worst = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (o[i] > b[i]) continue;
+      inside = false;
+      if (o[i] < -b[i] && o[i] < worst) {
+        worst = o[i];
+        exitf = i;
+      }
+    }
+    if (inside) return (sx == 0 && sy == 0) ? t : -1;
+    if (exitf < 0) return -1;
+    const int nb = W.nbr[exitf];
+    if (nb < 0) return -1;
+    sx += W.nsh[2 * exitf];
+    sy += W.nsh[2 * exitf + 1];
+    t = nb;
+  }
+  return -1;
+}
+
+// Canonical location by exact predicates over the bucket's candidates
+// (listed in ascending tet order, so the first hit is the lowest index).
+__device__ int scan_locate(const DevMesh& m, double x, double y, double z) {
+  if (!(x >= m.b0[0] && x <= m.b1[0] && y >= m.b0[1] && y <= m.b1[1] &&
+        z >= m.b0[2] && z <= m.b1[2]))
+    return -1;
+  const int bx = bucket_axis(x, m.b0[0], m.binv[0], m.nb[0]);
+  const int by = bucket_axis(y, m.b0[1], m.binv[1], m.nb[1]);
+  const int bz = bucket_axis(z, m.b0[2], m.binv[2], m.nb[2]);
+  const int64_t id = ((int64_t)bx * m.nb[1] + by) * m.nb[2] + bz;
+  const double p[3] = {x, y, z};
+  for (int q = m.bstart[id]; q < m.bstart[id + 1]; ++q) {
+    const int t = m.bitem[q];
+    const double* v = m.tw[t].v;
+    if (vol6_sign(p, v + 3, v + 6, v + 9) < 0) continue;
+    if (vol6_sign(v, p, v + 6, v + 9) < 0) continue;
+    if (vol6_sign(v, v + 3, p, v + 9) < 0) continue;
+    if (vol6_sign(v, v + 3, v + 6, p) < 0) continue;
+    return t;
+  }
+  return -1;
+}
+
+// After the drift: wrap, absorb at the anode, locate, deposit.
+__device__ inline void settle(const DevMesh& m, const StepArgs& a, int64_t i,
+                              double x, double y, double z, int sx, int sy,
+                              int hint, double w, long long qfx, Acc& acc) {
+  if (z >= m.z_top) {
+    a.tet[i] = -1;
+    acc.n_anode += 1;
+    acc.q_anode += qfx;
+    return;
+  }
+  int steps = 0;
+  const int t = walk(m, x, y, z, hint, sx, sy, steps);
+  acc.walk_steps += steps;
+  if (steps > acc.walk_max) acc.walk_max = steps;
+  if (t >= 0) {
+    a.tet[i] = t;
+    deposit_one(m.tg[t], x, y, z, w, a.charge);
+    acc.n_after += 1;
+    acc.q_after += qfx;
+  } else {
+    a.tet[i] = hint;
+    const int slot = atomicAdd(&a.scratch->n_fallback, 1);
+    a.queue[slot] = (int32_t)i;
+  }
+}
+
+__device__ inline void wrap(const DevMesh& m, double& x, double& y, int& sx,
+                            int& sy) {
+  sx = 0;
+  sy = 0;
+  if (x >= m.Lx) {
+    x = x - m.Lx;
+    sx = 1;
+  } else if (x < 0.0) {
+    x = x + m.Lx;
+    sx = -1;
+  }
+  if (y >= m.Ly) {
+    y = y - m.Ly;
+    sy = 1;
+  } else if (y < 0.0) {
+    y = y + m.Ly;
+    sy = -1;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Live particles: gather E_k, kick (v + QE) + QE, drift, wrap, absorb,
+// walk, deposit.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_push(StepArgs a) {
+  const DevMesh& m = a.m;
+  const int64_t n = *a.n_slots;
+  const Span sp = block_span(n);
+  Acc acc;
+  acc_zero(acc);
+  const double Q = a.Q;
+  const double dt = a.dt;
+  for (int64_t i = sp.lo + threadIdx.x; i < sp.hi; i += blockDim.x) {
+    const int t = a.tet[i];
+    if (t < 0) continue;
+    const double w = a.w[i];
+    const long long qfx = fx_round(w * kFx);
+    acc.n_before += 1;
+    acc.q_before += qfx;
+    double x = a.x[i], y = a.y[i], z = a.z[i];
+    double vx = a.vx[i], vy = a.vy[i], vz = a.vz[i];
+    double ex, ey, ez;
+    gather_field(m.tg[t], a.E, x, y, z, ex, ey, ez);
+    const double qx = Q * ex, qy = Q * ey, qz = Q * ez;
+    vx = (vx + qx) + qx;
+    vy = (vy + qy) + qy;
+    vz = (vz + qz) + qz;
+    x = x + dt * vx;
+    y = y + dt * vy;
+    z = z + dt * vz;
+    int sx, sy;
+    wrap(m, x, y, sx, sy);
+    a.x[i] = x;
+    a.y[i] = y;
+    a.z[i] = z;
+    a.vx[i] = vx;
+    a.vy[i] = vy;
+    a.vz[i] = vz;
+    settle(m, a, i, x, y, z, sx, sy, t, w, qfx, acc);
+  }
+  acc_flush(acc, a.stats);
+}
+
+// ---------------------------------------------------------------------------
+// Emission counts: one workgroup over all emitting faces.  Per face the
+// centroid field ((E_a + E_b) + E_c)/3, the FN current when the field pulls
+// electrons out of the metal, Eq. nsp and the rounding of Eq. rnd_nsp; an
+// exclusive scan of the counts gives every new particle its slot.
+// ---------------------------------------------------------------------------
+__device__ inline double fn_current(double F, double phi, const EmitConsts& c,
+                                    int& clamped) {
+  if (!(F > 1e-3)) return 0.0;
+  double f = c.c_s * F / (phi * phi);
+  if (f >= 1.0) {
+    f = 1.0 - 1e-9;
+    clamped = 1;
+  }
+  const double lf = log(f);
+  const double v = 1.0 - f + (f / 6.0) * lf;
+  const double t = 1.0 + f / 9.0 - (f / 18.0) * lf;
+  const double Fsi = F * 1e9;
+  return c.a_fn * Fsi * Fsi / (phi * t * t) *
+         exp(-v * c.b_fn * (phi * sqrt(phi)) / F);
+}
+
+__device__ inline void face_field(const DevMesh& m, const double* E, int64_t f,
+                                  double& ex, double& ey, double& ez) {
+  const int32_t* nd = m.e_nodes + 3 * f;
+  const double4 a = ld_E(E, nd[0]);
+  const double4 b = ld_E(E, nd[1]);
+  const double4 c = ld_E(E, nd[2]);
+  ex = ((a.x + b.x) + c.x) / 3.0;
+  ey = ((a.y + b.y) + c.y) / 3.0;
+  ez = ((a.z + b.z) + c.z) / 3.0;
+}
+
+constexpr int kEmitBlock = 1024;
+
+__global__ void __launch_bounds__(kEmitBlock) k_emit(EmitArgs a) {
+  const DevMesh& m = a.m;
+  __shared__ long long s_scan[kEmitBlock];
+  __shared__ double s_red[3][kEmitBlock / 64];
+  __shared__ long long s_cl[kEmitBlock / 64];
+  long long offset = 0;
+  double cur_sum = 0.0, F_sum = 0.0, F_max = 0.0;
+  long long n_clamp = 0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int64_t f0 = 0; f0 < m.n_emit; f0 += kEmitBlock) {
+    const int64_t f = f0 + threadIdx.x;
+    long long cnt = 0;
+    double cur = 0.0, F = 0.0;
+    int clamped = 0;
+    if (f < m.n_emit) {
+      double ex, ey, ez;
+      face_field(m, a.E, f, ex, ey, ez);
+      F = sqrt((ex * ex + ey * ey) + ez * ez);
+      const double* nr = m.e_nrm + 3 * f;
+      const double en = (ex * nr[0] + ey * nr[1]) + ez * nr[2];
+      double jd = 0.0;
+      if (en < 0.0)
+        jd = fn_current(F, a.phi_w, a.c, clamped) * a.c.j_unit;
+      jd = jd * a.j_scale;
+      cur = jd * m.e_area[f];
+      if (a.counts) {
+        const double nsp = cur * a.dt / a.w_sp;
+        uint64_t r4[4];
+        philox4x64_10(a.seed, a.instance, (uint64_t)a.step, (uint64_t)f, 0, 0,
+                      r4);
+        const double R = unit_double(r4[0]);
+        const double fl = floor(nsp);
+        double c = (R >= nsp - fl) ? fl : ceil(nsp);
+        if (c > 2097152.0) c = 2097152.0;
+        cnt = (long long)c;
+      }
+      if (a.face_F) a.face_F[f] = F;
+    }
+    // exclusive scan of the counts (Hillis-Steele in LDS)
+    s_scan[threadIdx.x] = cnt;
+    __syncthreads();
+    for (int off = 1; off < kEmitBlock; off <<= 1) {
+      const long long v = threadIdx.x >= off ? s_scan[threadIdx.x - off] : 0;
+      __syncthreads();
+      s_scan[threadIdx.x] += v;
+      __syncthreads();
+    }
+    if (f < m.n_emit && a.counts) {
+      a.counts[f] = (int32_t)cnt;
+      a.offsets[f] = (int32_t)(offset + s_scan[threadIdx.x] - cnt);
+    }
+    offset += s_scan[kEmitBlock - 1];
+    // sums of current and |E|, max |E|, clamp count (fixed order)
+    double v0 = cur, v1 = F, v2 = F;
+    long long vc = clamped;
+    for (int off = 32; off >= 1; off >>= 1) {
+      v0 += __shfl_xor(v0, off, 64);
+      v1 += __shfl_xor(v1, off, 64);
+      const double o2 = __shfl_xor(v2, off, 64);
+      v2 = o2 > v2 ? o2 : v2;
+      vc += __shfl_xor(vc, off, 64);
+    }
+    if (lane == 0) {
+      s_red[0][wave] = v0;
+      s_red[1][wave] = v1;
+      s_red[2][wave] = v2;
+      s_cl[wave] = vc;
+    }
+    __syncthreads();
+    for (int w = 0; w < kEmitBlock / 64; ++w) {
+      cur_sum += s_red[0][w];
+      F_sum += s_red[1][w];
+      F_max = s_red[2][w] > F_max ? s_red[2][w] : F_max;
+      n_clamp += s_cl[w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (a.rate) *a.rate = cur_sum;
+    if (a.stats) {
+      pic_step_stats* st = a.stats;
+      st->emit_current = cur_sum;
+      st->mean_face_E = m.n_emit ? F_sum / (double)m.n_emit : 0.0;
+      st->max_face_E = F_max;
+      st->n_clamp = n_clamp;
+    }
+    if (a.counts) {
+      a.offsets[m.n_emit] = (int32_t)offset;
+      const long long base = *a.n_slots;
+      long long fit = a.capacity - base;
+      if (fit > offset) fit = offset;
+      if (fit < 0) fit = 0;
+      a.scratch->inj_base = (int32_t)base;
+      a.scratch->inj_total = (int32_t)offset;
+      a.scratch->inj_fit = (int32_t)fit;
+      *a.n_slots = (int32_t)(base + fit);
+      if (a.stats) {
+        a.stats->n_trunc = offset - fit;
+        if (offset > fit) a.stats->status = PIC_E_CAPACITY;
+        a.stats->n_slots = base + fit;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Injection (Sec. II B 3, App. E): one thread per new particle.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_inject(StepArgs a) {
+  const DevMesh& m = a.m;
+  const int64_t n = a.scratch->inj_fit;
+  const int64_t base = a.scratch->inj_base;
+  Acc acc;
+  acc_zero(acc);
+  const double dt = a.dt;
+  const int32_t* off = a.offsets;
+  for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
+       s += (int64_t)gridDim.x * blockDim.x) {
+    // face: last f with off[f] <= s
+    int lo = 0, hi = (int)m.n_emit - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (off[mid] <= s) lo = mid; else hi = mid - 1;
+    }
+    const int f = lo;
+    const int64_t o = s - off[f];
+    uint64_t r4[4];
+    philox4x64_10(a.seed, a.instance, (uint64_t)a.step, (uint64_t)f,
+                  (uint64_t)o, 1, r4);
+    double R1 = unit_double(r4[0]), R2 = unit_double(r4[1]);
+    const double R = unit_double(r4[2]);
+    if (R1 + R2 > 1.0) {
+      R1 = 1.0 - R1;
+      R2 = 1.0 - R2;
+    }
+    const double l0 = (1.0 - R1) - R2;
+    const double* A = m.e_abc + 9 * (int64_t)f;
+    const int32_t* nd = m.e_nodes + 3 * (int64_t)f;
+    const double4 ea = ld_E(a.E, nd[0]);
+    const double4 eb = ld_E(a.E, nd[1]);
+    const double4 ec = ld_E(a.E, nd[2]);
+    const double px = (A[0] + R1 * (A[3] - A[0])) + R2 * (A[6] - A[0]);
+    const double py = (A[1] + R1 * (A[4] - A[1])) + R2 * (A[7] - A[1]);
+    const double pz = (A[2] + R1 * (A[5] - A[2])) + R2 * (A[8] - A[2]);
+    const double Ex = (l0 * ea.x + R1 * eb.x) + R2 * ec.x;
+    const double Ey = (l0 * ea.y + R1 * eb.y) + R2 * ec.y;
+    const double Ez = (l0 * ea.z + R1 * eb.z) + R2 * ec.z;
+    const double cv = a.qm_dt * (0.5 + R);
+    const double vx = cv * Ex, vy = cv * Ey, vz = cv * Ez;
+    double x = px + (vx * dt) * R;
+    double y = py + (vy * dt) * R;
+    double z = pz + (vz * dt) * R;
+    x = x + dt * vx;
+    y = y + dt * vy;
+    z = z + dt * vz;
+    int sx, sy;
+    wrap(m, x, y, sx, sy);
+    const int64_t i = base + s;
+    const double w = a.s_face ? a.s_face[f] : 1.0;
+    const long long qfx = fx_round(w * kFx);
+    a.x[i] = x;
+    a.y[i] = y;
+    a.z[i] = z;
+    a.vx[i] = vx;
+    a.vy[i] = vy;
+    a.vz[i] = vz;
+    a.w[i] = w;
+    a.birth[i] = f;
+    a.id[i] = (a.step << 42) | ((int64_t)f << 21) | o;
+    acc.n_inj += 1;
+    acc.q_inj += qfx;
+    settle(m, a, i, x, y, z, sx, sy, m.e_tet[f], w, qfx, acc);
+  }
+  acc_flush(acc, a.stats);
+}
+
+// ---------------------------------------------------------------------------
+// Particles the walk could not certify: exact canonical location; those
+// outside every tet (below the top plane) are absorbed by the cathode.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_fallback(StepArgs a) {
+  const DevMesh& m = a.m;
+  const int64_t n = a.scratch->n_fallback;
+  Acc acc;
+  acc_zero(acc);
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = a.queue[j];
+    const double x = a.x[i], y = a.y[i], z = a.z[i];
+    const double w = a.w[i];
+    const long long qfx = fx_round(w * kFx);
+    const int t = scan_locate(m, x, y, z);
+    if (t >= 0) {
+      a.tet[i] = t;
+      deposit_one(m.tg[t], x, y, z, w, a.charge);
+      acc.n_after += 1;
+      acc.q_after += qfx;
+    } else {
+      a.tet[i] = -1;
+      acc.n_cathode += 1;
+      acc.q_cathode += qfx;
+    }
+  }
+  if (n > 0) {
+    acc_flush(acc, a.stats);
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+      atomicAdd(reinterpret_cast<unsigned long long*>(&a.stats->n_fallback),
+                (unsigned long long)n);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Stand-alone location and deposition entry points.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_locate(LocateArgs a) {
+  const DevMesh& m = a.m;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < a.n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double x = a.x[i], y = a.y[i], z = a.z[i];
+    if (z >= m.z_top) {
+      a.tet[i] = -1;
+      a.where[i] = PIC_WHERE_ANODE;
+      continue;
+    }
+    const int h = a.tet[i];
+    int t = -1, steps = 0;
+    if (h >= 0 && h < m.n_tets) t = walk(m, x, y, z, h, 0, 0, steps);
+    if (t >= 0) {
+      a.tet[i] = t;
+      a.where[i] = PIC_WHERE_INSIDE;
+    } else {
+      const int slot = atomicAdd(a.n_queue, 1);
+      a.queue[slot] = (int32_t)i;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_locate_scan(LocateArgs a) {
+  const DevMesh& m = a.m;
+  const int64_t n = *a.n_queue;
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = a.queue[j];
+    const int t = scan_locate(m, a.x[i], a.y[i], a.z[i]);
+    a.tet[i] = t;
+    a.where[i] = t >= 0 ? PIC_WHERE_INSIDE : PIC_WHERE_OUTSIDE;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_deposit(DepositArgs a) {
+  const DevMesh& m = a.m;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < a.n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int t = a.tet[i];
+    if (t < 0 || t >= m.n_tets) continue;
+    deposit_one(m.tg[t], a.x[i], a.y[i], a.z[i], a.w[i], a.charge);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_push(const StepArgs& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_push, dim3(grid), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_emit(const EmitArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_emit, dim3(1), dim3(kEmitBlock), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_inject(const StepArgs& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_inject, dim3(grid), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_fallback(const StepArgs& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_fallback, dim3(grid), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_locate(const LocateArgs& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_locate, dim3(grid), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(k_locate_scan, dim3(grid), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_deposit(const DepositArgs& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_deposit, dim3(grid), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace fp

@@ -1,0 +1,302 @@
+"""Python binding of libfemocs_pic.so: argument marshalling only.
+
+Torch supplies device memory and the stream; every step of the PIC cycle
+runs in the library's HIP kernels.  The binding raises when the library is
+missing or a GPU is not available -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfemocs_pic.so")
+
+PIC_OK, PIC_E_ARG, PIC_E_DEVICE, PIC_E_MESH = 0, -1, -2, -3
+PIC_E_NOCONV, PIC_E_CAPACITY, PIC_E_NUMERIC = -4, -5, -6
+PIC_FP64, PIC_MIXED = 0, 1
+CHARGE_SCALE = float(2 ** 40)
+
+
+class PicError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"status {status}: {msg}")
+        self.status = status
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [("n_nodes", C.c_int64), ("xyz", C.c_void_p),
+                ("n_tets", C.c_int64), ("tet", C.c_void_p),
+                ("shift", C.c_void_p), ("Lx", C.c_double), ("Ly", C.c_double),
+                ("z_top", C.c_double), ("emit_zmin", C.c_double)]
+
+
+class MeshInfo(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in (
+        "n_nodes", "n_tets", "n_free", "nnz", "nnz_field", "n_emit", "n_top",
+        "n_metal", "device_bytes")]
+
+
+class SolveParams(C.Structure):
+    _fields_ = [("tol", C.c_double), ("inner_tol", C.c_double),
+                ("max_iter", C.c_int32), ("precision", C.c_int32)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("iters", C.c_int64), ("status", C.c_int64),
+                ("restarts", C.c_int64), ("pad", C.c_int64),
+                ("relres", C.c_double), ("bnorm", C.c_double)]
+
+
+class Particles(C.Structure):
+    _fields_ = [("capacity", C.c_int64), ("precision", C.c_int32),
+                ("pad", C.c_int32)] + [(n, C.c_void_p) for n in (
+                    "x", "y", "z", "vx", "vy", "vz", "w", "tet", "birth", "id",
+                    "n_slots")]
+
+
+class Fields(C.Structure):
+    _fields_ = [("phi", C.c_void_p), ("E", C.c_void_p), ("charge", C.c_void_p)]
+
+
+class StepParams(C.Structure):
+    _fields_ = [("dt", C.c_double), ("E0", C.c_double), ("w_sp", C.c_double),
+                ("phi_w", C.c_double), ("j_scale", C.c_double),
+                ("seed", C.c_uint64), ("step0", C.c_int64),
+                ("instance", C.c_int64), ("s_face", C.c_void_p),
+                ("resort_every", C.c_int32), ("pad", C.c_int32),
+                ("solve", SolveParams)]
+
+
+STEP_STATS_FIELDS = (
+    "n_before", "n_inj", "n_anode", "n_cathode", "n_after", "q_before",
+    "q_inj", "q_anode", "q_cathode", "q_after", "cg_iters", "n_clamp",
+    "status", "n_trunc", "walk_steps", "walk_max", "n_fallback", "n_slots")
+STEP_STATS_FLOATS = ("cg_relres", "emit_current", "mean_face_E", "max_face_E")
+STEP_STATS_BYTES = 8 * (len(STEP_STATS_FIELDS) + len(STEP_STATS_FLOATS))
+
+_lib = None
+EXPORTS = ("mesh_create", "mesh_destroy", "mesh_query", "mesh_emit_faces",
+           "locate", "deposit", "poisson_solve", "pic_step", "emission_rate",
+           "pic_last_error")
+
+
+def load_library(path: str = LIB_PATH):
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(
+            f"{path} is missing: build it with `python -m "
+            "paper_1906_08125_amd.build` (hipcc, gfx950)")
+    L = C.CDLL(path)
+    vp, i64, i32, dbl = C.c_void_p, C.c_int64, C.c_int32, C.c_double
+    L.mesh_create.argtypes = [C.POINTER(MeshDesc), vp, C.POINTER(vp)]
+    L.mesh_destroy.argtypes = [vp]
+    L.mesh_query.argtypes = [vp, C.POINTER(MeshInfo)]
+    L.mesh_emit_faces.argtypes = [vp, vp, vp, vp]
+    L.locate.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp]
+    L.deposit.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp]
+    L.poisson_solve.argtypes = [vp, vp, dbl, dbl, vp, vp,
+                                C.POINTER(SolveParams), vp, vp]
+    L.pic_step.argtypes = [vp, C.POINTER(Particles), C.POINTER(Fields),
+                           C.POINTER(StepParams), i32, vp, vp]
+    L.emission_rate.argtypes = [vp, vp, dbl, vp, vp, vp]
+    L.pic_last_error.restype = C.c_char_p
+    for n in EXPORTS:
+        if n != "pic_last_error":
+            getattr(L, n).restype = C.c_int32
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != PIC_OK:
+        raise PicError(status, load_library().pic_last_error().decode())
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("a HIP device is required (no CPU fallback)")
+    return torch
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(torch):
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Mesh:
+    """Device mesh handle (mesh_create)."""
+
+    def __init__(self, tip_mesh, emit_zmin: float):
+        torch = _torch()
+        L = load_library()
+        self._keep = (np.ascontiguousarray(tip_mesh.xyz, np.float64),
+                      np.ascontiguousarray(tip_mesh.tet, np.int32),
+                      np.ascontiguousarray(tip_mesh.shift, np.int8))
+        d = MeshDesc(tip_mesh.n_nodes, self._keep[0].ctypes.data,
+                     tip_mesh.n_tets, self._keep[1].ctypes.data,
+                     self._keep[2].ctypes.data, tip_mesh.Lx, tip_mesh.Ly,
+                     tip_mesh.z_top, emit_zmin)
+        h = C.c_void_p()
+        _check(L.mesh_create(C.byref(d), _stream(torch), C.byref(h)))
+        self._h = h
+        info = MeshInfo()
+        _check(L.mesh_query(h, C.byref(info)))
+        self.info = {k: getattr(info, k) for k, _ in info._fields_}
+        self.n_nodes = info.n_nodes
+        self.n_tets = info.n_tets
+        self.n_free = info.n_free
+        self.n_emit = info.n_emit
+        self.tip = tip_mesh
+        del self._keep
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            load_library().mesh_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def emit_faces(self):
+        F = self.n_emit
+        tet = np.zeros(F, np.int32)
+        nodes = np.zeros((F, 3), np.int32)
+        area = np.zeros(F)
+        _check(load_library().mesh_emit_faces(self._h, tet.ctypes.data,
+                                              nodes.ctypes.data,
+                                              area.ctypes.data))
+        return dict(tet=tet, nodes=nodes, area=area)
+
+    # ---- single calls ---------------------------------------------------
+    def locate(self, x, y, z, tet_inout, where_out):
+        torch = _torch()
+        _check(load_library().locate(self._h, x.numel(), _ptr(x), _ptr(y),
+                                     _ptr(z), _ptr(tet_inout), _ptr(where_out),
+                                     _stream(torch)))
+
+    def deposit(self, x, y, z, tet, w, charge):
+        torch = _torch()
+        _check(load_library().deposit(self._h, x.numel(), _ptr(x), _ptr(y),
+                                      _ptr(z), _ptr(tet), _ptr(w),
+                                      _ptr(charge), _stream(torch)))
+
+    def poisson_solve(self, charge, w_sp, E0, phi, E=None, tol=1e-12,
+                      max_iter=20000, precision=PIC_FP64, inner_tol=1e-4):
+        torch = _torch()
+        st = torch.zeros(6, dtype=torch.float64, device=phi.device)
+        prm = SolveParams(tol, inner_tol, max_iter, precision)
+        _check(load_library().poisson_solve(
+            self._h, _ptr(charge), float(w_sp), float(E0), _ptr(phi), _ptr(E),
+            C.byref(prm), _ptr(st), _stream(torch)))
+        return st
+
+    @staticmethod
+    def solve_stats(st) -> dict:
+        raw = st.cpu().numpy()
+        ints = raw[:4].view(np.int64)
+        return dict(iters=int(ints[0]), status=int(ints[1]),
+                    restarts=int(ints[2]), relres=float(raw[4]),
+                    bnorm=float(raw[5]))
+
+    def emission_rate(self, E, phi_w):
+        torch = _torch()
+        rate = torch.zeros(1, dtype=torch.float64, device=E.device)
+        faceF = torch.zeros(max(self.n_emit, 1), dtype=torch.float64,
+                            device=E.device)
+        _check(load_library().emission_rate(self._h, _ptr(E), float(phi_w),
+                                            _ptr(rate), _ptr(faceF),
+                                            _stream(torch)))
+        return rate, faceF[: self.n_emit]
+
+
+class State:
+    """Device particle SoA + fields for one run."""
+
+    def __init__(self, mesh: Mesh, capacity: int, precision: int = PIC_FP64,
+                 device="cuda"):
+        torch = _torch()
+        self.mesh = mesh
+        self.capacity = int(capacity)
+        self.precision = precision
+        rd = torch.float64 if precision == PIC_FP64 else torch.float32
+        n = self.capacity
+        mk = lambda dt: torch.zeros(n, dtype=dt, device=device)
+        self.x, self.y, self.z = mk(rd), mk(rd), mk(rd)
+        self.vx, self.vy, self.vz = mk(rd), mk(rd), mk(rd)
+        self.w = mk(torch.float64)
+        self.tet = torch.full((n,), -1, dtype=torch.int32, device=device)
+        self.birth = mk(torch.int32)
+        self.id = mk(torch.int64)
+        self.n_slots = torch.zeros(1, dtype=torch.int32, device=device)
+        nn = mesh.n_nodes
+        self.phi = torch.zeros(nn, dtype=torch.float64, device=device)
+        self.E = torch.zeros(4 * nn, dtype=torch.float64, device=device)
+        self.charge = torch.zeros(nn, dtype=torch.int64, device=device)
+        self._p = Particles(n, precision, 0, *[
+            t.data_ptr() for t in (self.x, self.y, self.z, self.vx, self.vy,
+                                   self.vz, self.w, self.tet, self.birth,
+                                   self.id, self.n_slots)])
+        self._f = Fields(self.phi.data_ptr(), self.E.data_ptr(),
+                         self.charge.data_ptr())
+
+    def init_field(self, E0, tol=1e-12, max_iter=20000):
+        st = self.mesh.poisson_solve(None, 0.0, E0, self.phi, self.E, tol,
+                                     max_iter)
+        return st
+
+    def step(self, *, dt, E0, w_sp, phi_w, step0, seed, n_steps=1, instance=0,
+             j_scale=1.0, tol=1e-12, max_iter=20000, s_face=None,
+             resort_every=0, stats=None):
+        torch = _torch()
+        if stats is None:
+            stats = torch.zeros(n_steps * STEP_STATS_BYTES // 8,
+                                dtype=torch.int64, device=self.phi.device)
+        prm = StepParams(dt, E0, w_sp, phi_w, j_scale, seed, step0, instance,
+                         None if s_face is None else s_face.data_ptr(),
+                         resort_every, 0,
+                         SolveParams(tol, 1e-4, max_iter, self.precision))
+        _check(load_library().pic_step(self.mesh.handle, C.byref(self._p),
+                                       C.byref(self._f), C.byref(prm),
+                                       int(n_steps), _ptr(stats),
+                                       _stream(torch)))
+        return stats
+
+    @staticmethod
+    def decode_stats(stats) -> list[dict]:
+        raw = stats.cpu().numpy().view(np.int64).reshape(-1, STEP_STATS_BYTES // 8)
+        out = []
+        ni = len(STEP_STATS_FIELDS)
+        for row in raw:
+            d = {k: int(v) for k, v in zip(STEP_STATS_FIELDS, row[:ni])}
+            fl = row[ni:].view(np.float64)
+            d.update({k: float(v) for k, v in zip(STEP_STATS_FLOATS, fl)})
+            out.append(d)
+        return out
+
+    def live(self) -> dict:
+        """Host copy of the live particles (tet >= 0)."""
+        n = int(self.n_slots.item())
+        tet = self.tet[:n].cpu().numpy()
+        keep = tet >= 0
+        g = lambda t: t[:n].cpu().numpy()[keep]
+        return dict(x=g(self.x).astype(np.float64), y=g(self.y).astype(np.float64),
+                    z=g(self.z).astype(np.float64), vx=g(self.vx).astype(np.float64),
+                    vy=g(self.vy).astype(np.float64), vz=g(self.vz).astype(np.float64),
+                    w=g(self.w), tet=tet[keep], birth=g(self.birth), id=g(self.id))

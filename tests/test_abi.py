@@ -1,0 +1,48 @@
+"""The C ABI library loads on the host and exports every entry point the
+public header declares; host-side argument checks reject bad input before
+any device work (no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "femocs_pic.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    return re.findall(r"PIC_API\s+[\w\s\*]+?\b(\w+)\s*\(", src)
+
+
+def test_header_declares_the_boundary():
+    names = set(declared_functions())
+    for n in ("mesh_create", "pic_step", "poisson_solve", "deposit", "locate",
+              "mesh_destroy", "pic_last_error"):
+        assert n in names, n
+
+
+def test_library_exports_header_symbols():
+    from paper_1906_08125_amd import pic
+    if not os.path.exists(pic.LIB_PATH):
+        pytest.skip("library not built")
+    lib = C.CDLL(pic.LIB_PATH)
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+
+
+def test_host_argument_checks():
+    from paper_1906_08125_amd import pic
+    if not os.path.exists(pic.LIB_PATH):
+        pytest.skip("library not built")
+    L = pic.load_library()
+    h = C.c_void_p()
+    assert L.mesh_create(None, None, C.byref(h)) == pic.PIC_E_ARG
+    d = pic.MeshDesc(0, None, 0, None, None, 1.0, 1.0, 1.0, 0.0)
+    assert L.mesh_create(C.byref(d), None, C.byref(h)) == pic.PIC_E_ARG
+    assert b"empty" in L.pic_last_error()
+    assert L.locate(None, 1, None, None, None, None, None, None) == pic.PIC_E_ARG
+    assert L.deposit(None, 1, None, None, None, None, None, None, None) == \
+        pic.PIC_E_ARG
+    assert L.pic_step(None, None, None, None, 1, None, None) == pic.PIC_E_ARG

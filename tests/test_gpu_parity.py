@@ -1,0 +1,302 @@
+"""Parity of the HIP library (through its C ABI) with the FP64 oracle.
+
+Integer results (tet ids, where-codes, fixed-point charge, particle counts,
+collected charge) must be bit-exact; floating-point results meet the
+relative-L2 bound of 1e-9 (potential, positions)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1906_08125_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def pic():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1906_08125_amd import pic as P
+    P.load_library()
+    return P
+
+
+def _dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def _rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+MESHES = {
+    "small_tip": lambda: W.kuhn_tip_mesh(3, 3, 4, 0.5, 0.5, 1.0),
+    "plates": lambda: W.kuhn_tip_mesh(4, 4, 8, 0.5),
+    "tiny_tip": lambda: W.config_tiny().mesh(),
+}
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+def test_mesh_counts_and_faces(pic, name):
+    tip = MESHES[name]()
+    zmin = 0.01 if name != "plates" else -1.0
+    om = O.OracleMesh(tip, zmin)
+    gm = pic.Mesh(tip, zmin)
+    i = gm.info
+    print(name, i)
+    assert (i["n_nodes"], i["n_tets"], i["n_free"], i["nnz"], i["n_emit"],
+            i["n_top"], i["n_metal"]) == (om.n_nodes, om.n_tets, om.n_free,
+                                          om.nnz, om.n_emit, om.n_top,
+                                          om.n_metal)
+    ge = gm.emit_faces()
+    oe = om.emit()
+    assert (ge["tet"] == oe["tet"]).all()
+    assert (ge["nodes"] == oe["nodes"]).all()
+    assert (ge["area"] == oe["area"]).all()
+
+
+def test_poisson_plates_closed_form(pic):
+    tip = MESHES["plates"]()
+    gm = pic.Mesh(tip, 0.01)
+    phi = torch.zeros(tip.n_nodes, dtype=torch.float64, device="cuda")
+    E = torch.zeros(4 * tip.n_nodes, dtype=torch.float64, device="cuda")
+    st = gm.poisson_solve(None, 0.0, 0.7, phi, E, tol=1e-13)
+    s = gm.solve_stats(st)
+    assert s["status"] == 0 and s["relres"] <= 1e-13
+    assert np.abs(phi.cpu().numpy() - 0.7 * tip.xyz[:, 2]).max() < 1e-11
+    e = E.cpu().numpy().reshape(-1, 4)
+    assert np.abs(e[:, :3] - np.array([0, 0, -0.7])).max() < 1e-10
+    assert (e[:, 3] == 0).all()
+
+
+@pytest.mark.parametrize("name", ["small_tip", "tiny_tip"])
+def test_poisson_matches_oracle(pic, name):
+    tip = MESHES[name]()
+    om = O.OracleMesh(tip, 0.01)
+    gm = pic.Mesh(tip, 0.01)
+    rng = np.random.default_rng(3)
+    c = rng.integers(-2**44, 2**44, tip.n_nodes).astype(np.int64)
+    phi_o, info = om.poisson_solve(c, 1e-3, 0.4, tol=1e-12)
+    E_o = om.field(phi_o)
+    phi = torch.zeros(tip.n_nodes, dtype=torch.float64, device="cuda")
+    E = torch.zeros(4 * tip.n_nodes, dtype=torch.float64, device="cuda")
+    st = gm.poisson_solve(_dev(c), 1e-3, 0.4, phi, E, tol=1e-12)
+    s = gm.solve_stats(st)
+    print(name, s, info)
+    assert s["status"] == 0 and s["relres"] <= 1e-12
+    assert abs(s["iters"] - info["iters"]) <= 3
+    assert _rel(phi.cpu().numpy(), phi_o) < 1e-9
+    e = E.cpu().numpy().reshape(-1, 4)[:, :3]
+    assert _rel(e, E_o) < 1e-9
+    # warm start from the solution: zero iterations, unchanged potential
+    phi2 = phi.clone()
+    st2 = gm.poisson_solve(_dev(c), 1e-3, 0.4, phi2, None, tol=1e-12)
+    assert gm.solve_stats(st2)["iters"] == 0
+    assert torch.equal(phi2, phi)
+
+
+def _locate_case(pic, tip, pts, hint=None):
+    om = O.OracleMesh(tip, 0.01)
+    gm = pic.Mesh(tip, 0.01)
+    t_o, w_o = om.locate(pts, hint)
+    x, y, z = (_dev(pts[:, k].copy()) for k in range(3))
+    h = np.full(len(pts), -1, np.int32) if hint is None else hint
+    tet = _dev(h.astype(np.int32))
+    where = torch.zeros(len(pts), dtype=torch.uint8, device="cuda")
+    gm.locate(x, y, z, tet, where)
+    assert (tet.cpu().numpy() == t_o).all()
+    assert (where.cpu().numpy() == w_o).all()
+    return t_o
+
+
+@pytest.mark.parametrize("name", ["small_tip", "tiny_tip"])
+def test_locate_bit_exact(pic, name):
+    tip = MESHES[name]()
+    pts = np.concatenate([W.random_points_in_box(tip, 20000, 5),
+                          W.lattice_points(tip, 5000, 6)])
+    t_o = _locate_case(pic, tip, pts)
+    # hints: the answer itself, a random tet, and -1
+    rng = np.random.default_rng(1)
+    om = O.OracleMesh(tip, 0.01)
+    hint = np.where(rng.random(len(pts)) < 0.5, t_o,
+                    rng.integers(0, om.n_tets, len(pts))).astype(np.int32)
+    _locate_case(pic, tip, pts, hint)
+
+
+def test_locate_empty(pic):
+    tip = MESHES["small_tip"]()
+    gm = pic.Mesh(tip, 0.01)
+    e = torch.zeros(0, dtype=torch.float64, device="cuda")
+    gm.locate(e, e, e, torch.zeros(0, dtype=torch.int32, device="cuda"),
+              torch.zeros(0, dtype=torch.uint8, device="cuda"))
+
+
+@pytest.mark.parametrize("name", ["small_tip", "tiny_tip"])
+def test_deposit_bit_exact(pic, name):
+    tip = MESHES[name]()
+    om = O.OracleMesh(tip, 0.01)
+    gm = pic.Mesh(tip, 0.01)
+    pts = np.concatenate([W.random_points_in_box(tip, 30000, 7),
+                          W.lattice_points(tip, 3000, 8)])
+    tet, where = om.locate(pts)
+    keep = where == 0
+    pts, tet = pts[keep], tet[keep]
+    w = np.random.default_rng(2).uniform(0.1, 2.0, len(pts))
+    c_o = om.deposit(pts, tet, w)
+    c = torch.zeros(tip.n_nodes, dtype=torch.int64, device="cuda")
+    args = [_dev(pts[:, k].copy()) for k in range(3)]
+    gm.deposit(*args, _dev(tet), _dev(w), c)
+    assert (c.cpu().numpy() == c_o).all()
+    # order independence on the device
+    perm = np.random.default_rng(3).permutation(len(pts))
+    c2 = torch.zeros_like(c)
+    gm.deposit(*[_dev(pts[perm, k].copy()) for k in range(3)],
+               _dev(tet[perm]), _dev(w[perm]), c2)
+    assert torch.equal(c, c2)
+
+
+def test_emission_rate_matches_oracle(pic):
+    cfg = W.config_tiny()
+    tip = cfg.mesh()
+    om = O.OracleMesh(tip, cfg.emit_zmin)
+    ost = O.OracleState(om, 10)
+    ost.init_field(cfg.E0, tol=1e-12)
+    r_o, F_o = om.emission_rate(ost.E, cfg.phi_w)
+    gm = pic.Mesh(tip, cfg.emit_zmin)
+    gs = pic.State(gm, 10)
+    gs.init_field(cfg.E0, tol=1e-12)
+    rate, F = gm.emission_rate(gs.E, cfg.phi_w)
+    assert abs(rate.item() / r_o - 1) < 1e-8
+    assert _rel(F.cpu().numpy(), F_o) < 1e-10
+
+
+def _run_pair(pic, cfg, n_steps, live_charge, n_live, cap, seed=None):
+    """live_charge: electrons in flight wanted (None = physical emission)."""
+    tip = cfg.mesh()
+    om = O.OracleMesh(tip, cfg.emit_zmin)
+    ost = O.OracleState(om, cap)
+    ost.init_field(cfg.E0, tol=cfg.tol)
+    rate, _ = om.emission_rate(ost.E, cfg.phi_w)
+    per_run = rate * cfg.dt * cfg.transit_steps
+    j_scale = 1.0 if live_charge is None else live_charge / per_run
+    w_sp = per_run * j_scale / n_live
+    gm = pic.Mesh(tip, cfg.emit_zmin)
+    gs = pic.State(gm, cap)
+    gs.init_field(cfg.E0, tol=cfg.tol)
+    kw = dict(dt=cfg.dt, E0=cfg.E0, w_sp=w_sp, phi_w=cfg.phi_w,
+              seed=cfg.seed if seed is None else seed, j_scale=j_scale,
+              tol=cfg.tol)
+    so_all, sg_all = [], []
+    for k in range(n_steps):
+        so_all.append(ost.step(step=k, **kw))
+        sg_all.append(pic.State.decode_stats(gs.step(step0=k, **kw))[0])
+    torch.cuda.synchronize()
+    return om, ost, gm, gs, so_all, sg_all
+
+
+def _compare_runs(ost, gs, so_all, sg_all):
+    for k, (so, sg) in enumerate(zip(so_all, sg_all)):
+        for key in ("n_inj", "n_anode", "n_cathode", "n_after", "q_before",
+                    "q_inj", "q_anode", "q_cathode", "q_after", "status",
+                    "n_trunc", "n_clamp"):
+            assert so[key] == sg[key], (k, key, so[key], sg[key])
+        assert abs(so["cg_iters"] - sg["cg_iters"]) <= 3
+        assert sg["cg_relres"] <= 1e-12 or sg["cg_iters"] == 0
+        for key in ("emit_current", "mean_face_E", "max_face_E"):
+            assert abs(sg[key] - so[key]) <= 1e-9 * abs(so[key]) + 1e-300
+        # fixed-point conservation on the device
+        assert sg["q_before"] + sg["q_inj"] - sg["q_anode"] - \
+            sg["q_cathode"] == sg["q_after"]
+    P, Q = gs.live(), ost.particles()
+    assert P["id"].size == Q["id"].size
+    a = np.argsort(P["id"])
+    b = np.argsort(Q["id"])
+    assert (P["id"][a] == Q["id"][b]).all()
+    assert (P["tet"][a] == Q["tet"][b]).all()
+    assert (P["birth"][a] == Q["birth"][b]).all()
+    assert (P["w"][a] == Q["w"][b]).all()
+    pos_g = np.stack([P["x"][a], P["y"][a], P["z"][a]], 1)
+    pos_o = np.stack([Q["x"][b], Q["y"][b], Q["z"][b]], 1)
+    assert _rel(pos_g, pos_o) < 1e-9
+    vel_g = np.stack([P["vx"][a], P["vy"][a], P["vz"][a]], 1)
+    vel_o = np.stack([Q["vx"][b], Q["vy"][b], Q["vz"][b]], 1)
+    assert _rel(vel_g, vel_o) < 1e-9
+    assert _rel(gs.phi.cpu().numpy(), ost.phi) < 1e-9
+    # total deposited charge is exact (per-node values may differ in the
+    # last unit where positions differ by rounding)
+    assert int(gs.charge.sum().item()) == int(ost.c.sum())
+
+
+def test_pic_step_tiny_physical(pic):
+    """The tiny-tip workload at its physical emission: 10 steps."""
+    cfg = W.config_tiny()
+    om, ost, gm, gs, so, sg = _run_pair(pic, cfg, 10, None, 10_000, 60_000)
+    assert sum(s["n_inj"] for s in sg) > 1000
+    _compare_runs(ost, gs, so, sg)
+
+
+def test_pic_step_tiny_space_charge(pic):
+    """Emission scaled up so that the deposited charge moves the field
+    (coupled parity): 8 steps, some particles reach the anode."""
+    cfg = W.config_tiny()
+    om, ost, gm, gs, so, sg = _run_pair(pic, cfg, 36, 0.01, 3000, 60_000)
+    # the space charge is visible in the potential
+    assert all(s["cg_iters"] > 0 for s in sg[1:])
+    assert sum(s["n_anode"] for s in sg) > 0
+    _compare_runs(ost, gs, so, sg)
+
+
+def test_pic_step_deterministic(pic):
+    cfg = W.config_tiny()
+    outs = []
+    for _ in range(2):
+        _, _, gm, gs, _, sg = _run_pair(pic, cfg, 4, 0.01, 3000, 60_000)
+        P = gs.live()
+        outs.append((P, gs.phi.cpu().numpy().copy(), sg))
+    (P1, f1, s1), (P2, f2, s2) = outs
+    for k in P1:
+        assert (P1[k] == P2[k]).all()
+    assert (f1 == f2).all()
+
+
+def test_wrap_and_absorption_explicit(pic):
+    """Hand-placed particles crossing x = L, x = 0, y = L, reaching the
+    anode and entering the cathode, on both sides."""
+    tip = MESHES["plates"]()
+    om = O.OracleMesh(tip, -1.0)
+    ost = O.OracleState(om, 16)
+    ost.init_field(1e-6, tol=1e-12)
+    L, Lz = tip.Lx, tip.z_top
+    p = np.array([[L - 0.05, 1.0, 2.0], [0.02, 0.5, 1.0], [1.0, L - 0.01, 3.0],
+                  [1.0, 1.0, Lz - 0.1], [1.0, 1.0, 0.1], [0.7, 1.3, 2.2]])
+    v = np.array([[0.3, 0, 0], [-0.1, 0, 0], [0, 0.1, 0], [0, 0, 0.5],
+                  [0, 0, -0.5], [0.01, -0.02, 0.03]])
+    w = np.array([1.0, 0.5, 0.25, 1.0, 0.75, 1.5])
+    tet, _ = om.locate(p)
+    ost.add(p, v, tet, w=w, ids=np.arange(6))
+    gm = pic.Mesh(tip, -1.0)
+    gs = pic.State(gm, 16)
+    gs.init_field(1e-6, tol=1e-12)
+    n = len(p)
+    for k, t in enumerate((gs.x, gs.y, gs.z)):
+        t[:n] = _dev(p[:, k].copy())
+    for k, t in enumerate((gs.vx, gs.vy, gs.vz)):
+        t[:n] = _dev(v[:, k].copy())
+    gs.w[:n] = _dev(w)
+    gs.tet[:n] = _dev(tet)
+    gs.id[:n] = _dev(np.arange(6, dtype=np.int64))
+    gs.n_slots.fill_(n)
+    kw = dict(dt=0.5, E0=1e-6, w_sp=1e-30, phi_w=4.5, seed=1, j_scale=0.0,
+              tol=1e-12)
+    so = ost.step(step=0, **kw)
+    sg = pic.State.decode_stats(gs.step(step0=0, **kw))[0]
+    assert sg["n_anode"] == 1 and sg["n_cathode"] == 1
+    assert sg["q_anode"] == 2**40 and sg["q_cathode"] == int(0.75 * 2**40)
+    _compare_runs(ost, gs, [so], [sg])
