@@ -1,0 +1,209 @@
+"""Benchmark of the electron PIC cycle on one MI355X.
+
+Workload: the production-shaped tip (box 32 x 32 x 64 nm, 64 x 64 x 128
+Kuhn grid, 3,100,504 tets, tip R = 3 nm, H = 30 nm, E0 = 0.5 V/nm, apex
+faces emitting, w_sp set for ~1e6 live superparticles, dt = 0.5 fs,
+PCG tolerance 1e-10).  W warm-up steps bring the run to its steady state
+(~1e6 live), then K steps are timed between device synchronizations.
+
+Prints one JSON line (see the design doc for the roofline byte model).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("PIC steps/s & pushes/s at 3M tets/1M e-; mixed vs FP64 speedup; "
+          "adjoint/fwd")
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def solve_bytes(info, iters):
+    """Algorithmic HBM bytes of one solve launch (warm-started PCG + field
+    recovery): RHS, one true-residual SpMV per (re)start, 2 SpMVs worth of
+    vector traffic per iteration, the potential scatter and R phi."""
+    n, nnz = info["n_free"], info["nnz"]
+    N, nf = info["n_nodes"], info["nnz_field"]
+    rhs = 44 * n                               # charge, map, g, b, phi, x
+    resid = 12 * nnz + 4 * (n + 1) + 32 * n    # val+col, rowptr, b, r, u, D^-1
+    it = 12 * nnz + 4 * (n + 1) + 112 * n      # SpMV + 14 vector streams
+    scatter = 20 * n
+    field = 28 * nf + 4 * (N + 1) + 32 * N     # val(3)+col, rowptr, E write
+    return rhs + resid + iters * it + scatter + field
+
+
+def push_bytes(n_live):
+    """Particle stream of the push kernel: read x,y,z,vx,vy,vz (48 B),
+    tet (4), w (8); write x,y,z,vx,vy,vz (48), tet (4)."""
+    return 112 * n_live
+
+
+def run_gpu(args):
+    import numpy as np
+    import torch
+
+    from paper_1906_08125_amd import pic, workloads as W
+
+    cfg = W.config_production()
+    tip = cfg.mesh()
+    t0 = time.time()
+    gm = pic.Mesh(tip, cfg.emit_zmin)
+    log(f"mesh_create {time.time() - t0:.1f}s {gm.info}")
+    cap = int(args.capacity)
+    gs = pic.State(gm, cap)
+    torch.cuda.synchronize()
+    # cold Laplace solve: CG throughput on the production matrix
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    st = gs.init_field(cfg.E0, tol=cfg.tol)
+    e1.record()
+    torch.cuda.synchronize()
+    cold = gm.solve_stats(st)
+    cold_ms = e0.elapsed_time(e1)
+    log(f"cold solve {cold} {cold_ms:.2f} ms")
+    rate, _ = gm.emission_rate(gs.E, cfg.phi_w)
+    rate = rate.item()
+    w_sp = rate * cfg.dt * cfg.transit_steps / cfg.n_target
+    log(f"emission {rate:.3e} e/fs -> w_sp {w_sp:.3e}")
+    kw = dict(dt=cfg.dt, E0=cfg.E0, w_sp=w_sp, phi_w=cfg.phi_w,
+              seed=cfg.seed, tol=cfg.tol, resort_every=args.resort)
+    step = 0
+    wstats = gs.step(step0=step, n_steps=args.warmup, **kw) if args.warmup else None
+    step += args.warmup
+    torch.cuda.synchronize()
+    if wstats is not None:
+        last = pic.State.decode_stats(wstats)[-1]
+        log(f"after warmup: {last}")
+    stats = torch.zeros(args.steps * pic.STEP_STATS_BYTES // 8,
+                        dtype=torch.int64, device="cuda")
+    # timed region: K steps, bracketed by synchronizations
+    gm.profile(True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    gs.step(step0=step, n_steps=args.steps, stats=stats, **kw)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    kt = gm.profile_read()
+    gm.profile(False)
+    rows = pic.State.decode_stats(stats)
+    for r in rows:
+        if r["status"] != 0:
+            raise RuntimeError(f"step status {r['status']}: {r}")
+    pushes = sum(r["n_before"] + r["n_inj"] for r in rows)
+    live_mean = sum(r["n_before"] for r in rows) / len(rows)
+    iters_mean = sum(r["cg_iters"] for r in rows) / len(rows)
+    ms_step = 1e3 * elapsed / args.steps
+    # per-kernel roofline
+    kernels = {}
+    for name, v in kt.items():
+        kernels[name] = dict(ms_total=round(v["ms"], 4), launches=v["launches"],
+                             us_per_launch=round(1e3 * v["ms"] / v["launches"], 2))
+    push_us = kt["push"]["ms"] * 1e3 / kt["push"]["launches"]
+    solve_us = kt["solve"]["ms"] * 1e3 / kt["solve"]["launches"]
+    pb = push_bytes(live_mean)
+    sb = solve_bytes(gm.info, iters_mean)
+    kernels["push"]["algo_bytes"] = pb
+    kernels["push"]["GBps"] = round(pb / push_us / 1e3, 1)
+    kernels["solve"]["algo_bytes"] = sb
+    kernels["solve"]["GBps"] = round(sb / solve_us / 1e3, 1)
+    dom = max(("push", "solve"), key=lambda k: kt[k]["ms"])
+    dom_bytes, dom_us = (pb, push_us) if dom == "push" else (sb, solve_us)
+    achieved = dom_bytes / dom_us / 1e3  # GB/s
+    out = dict(
+        metric=METRIC, value=round(args.steps / elapsed, 3), unit="steps/s",
+        n_gpus=1, steps=args.steps, warmup=args.warmup,
+        ms_per_step=round(ms_step, 4), higher_is_better=True, scaling="weak",
+        vs_baseline=None, dtype="f64", data="synthetic",
+        config=dict(workload=cfg.name, tets=gm.n_tets, nodes=gm.n_nodes,
+                    free_nodes=gm.n_free, nnz=gm.info["nnz"],
+                    live_particles_mean=round(live_mean), precision="fp64",
+                    w_sp=w_sp, dt_fs=cfg.dt, tol=cfg.tol,
+                    resort_every=args.resort),
+        pushes_per_s=round(pushes / elapsed, 1),
+        cg_iters_per_step=iters_mean,
+        cold_solve=dict(iters=cold["iters"], ms=round(cold_ms, 3),
+                        iters_per_s=round(cold["iters"] / cold_ms * 1e3, 1),
+                        relres=cold["relres"]),
+        kernels=kernels,
+        roofline=dict(kernel=dom, bound="hbm", achieved=round(achieved, 1),
+                      peak=HBM_PEAK_GBS, unit="GB/s",
+                      frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None),
+    )
+    return out, dict(cfg=cfg, tip=tip, w_sp=w_sp)
+
+
+def cpu_baseline(cfg, tip, n_particles, n_steps):
+    """The FP64 oracle on the host: the same mesh, a seeded synthetic
+    population of superparticles in the gap above the apex, n_steps steps."""
+    import numpy as np
+
+    from oracle import oracle as O
+
+    om = O.OracleMesh(tip, cfg.emit_zmin)
+    ost = O.OracleState(om, n_particles + 50 * 20000)
+    ost.init_field(cfg.E0, tol=cfg.tol)
+    rate, _ = om.emission_rate(ost.E, cfg.phi_w)
+    w_sp = rate * cfg.dt * cfg.transit_steps / cfg.n_target
+    g = np.random.Generator(np.random.Philox(key=[cfg.seed, 77]))
+    cx, cy = tip.Lx / 2, tip.Ly / 2
+    r = 6.0 * np.sqrt(g.random(n_particles))
+    a = 2 * np.pi * g.random(n_particles)
+    p = np.stack([cx + r * np.cos(a), cy + r * np.sin(a),
+                  cfg.tip_H + (tip.z_top - cfg.tip_H - 0.5) * g.random(n_particles)], 1)
+    v = np.zeros_like(p)
+    v[:, 2] = 0.2 + 1.5 * g.random(n_particles)
+    v[:, :2] = 0.05 * (g.random((n_particles, 2)) - 0.5)
+    tet, where = om.locate(p)
+    keep = where == 0
+    ost.add(p[keep], v[keep], tet[keep])
+    n0 = ost.n
+    t0 = time.perf_counter()
+    for k in range(n_steps):
+        ost.step(dt=cfg.dt, E0=cfg.E0, w_sp=w_sp, phi_w=cfg.phi_w, step=k,
+                 seed=cfg.seed, tol=cfg.tol)
+    dt = time.perf_counter() - t0
+    return dict(value=round(n_steps / dt, 5), unit="steps/s", cores=1,
+                kind="oracle",
+                sample=(f"{n_steps} steps of the FP64 oracle (single thread) on "
+                        f"the same 3.1M-tet mesh with {n0} seeded synthetic "
+                        "superparticles in the gap above the apex"),
+                pushes_per_s=round(n0 * n_steps / dt, 1))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--capacity", type=float, default=2.5e6)
+    ap.add_argument("--resort", type=int, default=10)
+    ap.add_argument("--cpu-particles", type=int, default=1_000_000)
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the multi-GPU layout of this "
+              "PIC cycle is a design (see DESIGN.md), not a build", file=sys.stderr)
+        sys.exit(2)
+    out, ctx = run_gpu(args)
+    if not args.no_cpu_baseline:
+        t0 = time.time()
+        out["cpu_baseline"] = cpu_baseline(ctx["cfg"], ctx["tip"],
+                                           args.cpu_particles, args.cpu_steps)
+        log(f"cpu baseline {time.time() - t0:.1f}s")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -222,6 +222,33 @@ PIC_API pic_status pic_step(pic_mesh* mesh, const pic_particles* particles,
 PIC_API pic_status emission_rate(const pic_mesh* mesh, const double* E, double phi_w,
                          double* rate, double* face_F, void* stream);
 
+/* ------------------------------------------------------------------------ */
+/* Kernel timing (measurement support, not part of the method).  While      */
+/* enabled, pic_step and poisson_solve bracket every kernel they launch     */
+/* with HIP events on the caller's stream; pic_profile_read synchronizes    */
+/* on the last event and returns the summed elapsed milliseconds and the    */
+/* launch count per kernel class since the last enable.  Event objects are  */
+/* created on demand while profiling is on.                                 */
+/* ------------------------------------------------------------------------ */
+enum {
+  PIC_K_PUSH = 0,     /* gather + kick + drift + walk + deposit (live)     */
+  PIC_K_EMIT = 1,     /* per-face FN counts and scan                      */
+  PIC_K_INJECT = 2,   /* new particles                                    */
+  PIC_K_FALLBACK = 3, /* exact location of uncertified particles           */
+  PIC_K_SOLVE = 4,    /* RHS + PCG + nodal field (one cooperative kernel)  */
+  PIC_K_SORT = 5,     /* sort by tet + compaction                         */
+  PIC_K_CLEAR = 6,    /* per-step clears of charge and counters           */
+  PIC_K_COUNT = 8
+};
+
+typedef struct {
+  double ms[PIC_K_COUNT];
+  int64_t launches[PIC_K_COUNT];
+} pic_kernel_times;
+
+PIC_API pic_status pic_profile(pic_mesh* mesh, int32_t enable);
+PIC_API pic_status pic_profile_read(pic_mesh* mesh, pic_kernel_times* out);
+
 PIC_API const char* pic_last_error(void);
 
 #ifdef __cplusplus

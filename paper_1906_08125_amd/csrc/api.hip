@@ -1,6 +1,7 @@
 // The C ABI (include/femocs_pic.h): argument checks, scratch management and
 // the per-step kernel sequence.  Every entry point only enqueues work on the
 // caller's stream.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -8,6 +9,7 @@
 #include "mesh.h"
 #include "particles.h"
 #include "solver.h"
+#include "sort.h"
 
 namespace {
 
@@ -24,18 +26,70 @@ pic_status hip_fail(hipError_t e, const char* where) {
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
-// Grow the particle-capacity scratch (fallback queue) of a handle.
-hipError_t ensure_capacity(pic_mesh* h, int64_t cap) {
-  if (cap <= h->pcap) return hipSuccess;
-  if (h->queue) {
-    hipError_t e = hipFree(h->queue);
+// Grow the particle-capacity scratch (fallback queue, sort buffers) of a
+// handle; later calls with the same or a smaller capacity allocate nothing.
+hipError_t ensure_capacity(pic_mesh* h, int64_t cap, bool sort) {
+  if (cap > h->pcap) {
+    if (h->queue) {
+      hipError_t e = hipFree(h->queue);
+      if (e != hipSuccess) return e;
+      h->queue = nullptr;
+    }
+    hipError_t e = hipMalloc(&h->queue, sizeof(int32_t) * (size_t)std::max<int64_t>(cap, 1));
     if (e != hipSuccess) return e;
-    h->queue = nullptr;
+    h->pcap = cap;
   }
-  hipError_t e = hipMalloc(&h->queue, sizeof(int32_t) * (size_t)std::max<int64_t>(cap, 1));
-  if (e != hipSuccess) return e;
-  h->pcap = cap;
+  if (sort) {
+    const size_t need = fp::sort_scratch_bytes(cap, 8);
+    if (need > h->sort_bytes) {
+      if (h->sort_mem) {
+        hipError_t e = hipFree(h->sort_mem);
+        if (e != hipSuccess) return e;
+        h->sort_mem = nullptr;
+        h->sort_bytes = 0;
+      }
+      hipError_t e = hipMalloc(&h->sort_mem, need);
+      if (e != hipSuccess) return e;
+      h->sort_bytes = need;
+    }
+  }
   return hipSuccess;
+}
+
+// Carve the sort scratch into its arrays.
+fp::SortArgs sort_args(pic_mesh* h, const pic_particles* P, int real_bytes) {
+  fp::SortArgs a;
+  std::memset(&a, 0, sizeof a);
+  const int64_t cap = P->capacity;
+  char* p = (char*)h->sort_mem;
+  auto take = [&](size_t bytes) {
+    char* q = p;
+    p += (bytes + 255) & ~(size_t)255;
+    return (void*)q;
+  };
+  a.n_tets = h->dm.n_tets;
+  a.n_slots = P->n_slots;
+  a.n_live = (int32_t*)take(256);
+  void* real[6] = {P->x, P->y, P->z, P->vx, P->vy, P->vz};
+  for (int f = 0; f < 6; ++f) {
+    a.real[f] = real[f];
+    a.s_real[f] = take((size_t)cap * real_bytes);
+  }
+  a.real_bytes = real_bytes;
+  a.w = P->w;
+  a.tet = P->tet;
+  a.birth = P->birth;
+  a.id = P->id;
+  for (int k = 0; k < 2; ++k) {
+    a.key[k] = (uint32_t*)take((size_t)cap * 4);
+    a.val[k] = (uint32_t*)take((size_t)cap * 4);
+  }
+  a.s_w = (double*)take((size_t)cap * 8);
+  a.s_tet = (int32_t*)take((size_t)cap * 4);
+  a.s_birth = (int32_t*)take((size_t)cap * 4);
+  a.s_id = (int64_t*)take((size_t)cap * 8);
+  a.hist = (uint32_t*)take((size_t)64 * ((cap + 4095) / 4096) * 4);
+  return a;
 }
 
 fp::CgArgs cg_args(const pic_mesh* h, const int64_t* charge, double w_sp,
@@ -60,9 +114,81 @@ fp::CgArgs cg_args(const pic_mesh* h, const int64_t* charge, double w_sp,
   a.p = h->cg_vec[5];
   a.s = h->cg_vec[6];
   a.part = h->cg_part;
+  a.G = h->cg_grid;
+  a.ctrl = h->cg_ctrl;
   a.dir_nodes = h->dir_nodes;
   a.n_dir = h->n_dir;
   return a;
+}
+
+// Enqueue a report of the solver control word into host-mapped memory and
+// return its sequence number; cg_wait spins on the host until it lands.
+hipError_t cg_report(pic_mesh* h, hipStream_t s, int64_t& seq) {
+  seq = ++h->cg_seq;
+  hipError_t e = fp::cg_launch_report(h->cg_ctrl, h->cg_report_dev, seq, s);
+  if (e != hipSuccess) return e;
+  return hipEventRecord(h->rb_event, s);
+}
+
+hipError_t cg_wait(pic_mesh* h, int64_t seq, fp::CgReport& out) {
+  for (long spin = 0;; ++spin) {
+    if (__atomic_load_n(&h->cg_report_host->seq, __ATOMIC_ACQUIRE) == seq) break;
+    if ((spin & 1023) == 1023) {
+      // liveness: once the report kernel has finished its record is visible
+      const hipError_t q = hipEventQuery(h->rb_event);
+      if (q == hipSuccess) {
+        if (__atomic_load_n(&h->cg_report_host->seq, __ATOMIC_ACQUIRE) == seq) break;
+        return hipErrorUnknown;
+      }
+      if (q != hipErrorNotReady) return q;
+    }
+  }
+  out.state = h->cg_report_host->state;
+  out.iters = h->cg_report_host->iters;
+  out.seq = seq;
+  return hipSuccess;
+}
+
+// One Poisson solve: residual and convergence test, the first batch of
+// `spec` CG iterations, a report of the state and -- before waiting for it --
+// the potential scatter and nodal field, so that the host's decision
+// overlaps the field kernel.  When the report says "not converged", further
+// batches follow (a true-residual re-check when the recursive residual
+// converges), and the field is recomputed at the end.  Blocks the calling
+// thread at the waits.  Returns the iterations done.
+hipError_t run_solve(pic_mesh* h, const fp::CgArgs& a, int spec, hipStream_t s,
+                     int64_t* iters_out) {
+  hipError_t e = fp::cg_launch_begin(a, s);
+  if (e != hipSuccess) return e;
+  int it = 0;
+  int batch = spec;
+  if (batch > 0) {
+    if ((e = fp::cg_launch_iters(a, it, batch, s)) != hipSuccess) return e;
+    it += batch;
+  }
+  int64_t seq;
+  if ((e = cg_report(h, s, seq)) != hipSuccess) return e;
+  if ((e = fp::cg_launch_field(a, s)) != hipSuccess) return e;
+  fp::CgReport r;
+  if ((e = cg_wait(h, seq, r)) != hipSuccess) return e;
+  bool extra = false;
+  for (int guard = 0; guard < (1 << 20); ++guard) {
+    if (r.state == fp::CG_DONE || r.state == fp::CG_NOCONV) break;
+    extra = true;
+    if (r.state == fp::CG_RECHECK) {
+      if ((e = fp::cg_launch_recheck(a, s)) != hipSuccess) return e;
+      it = 0;  // a restart (if any) begins from the true residual
+      batch = 16;
+    } else {
+      batch = batch < 8 ? 8 : std::min(2 * batch, 256);
+      if ((e = fp::cg_launch_iters(a, it, batch, s)) != hipSuccess) return e;
+      it += batch;
+    }
+    if ((e = cg_report(h, s, seq)) != hipSuccess) return e;
+    if ((e = cg_wait(h, seq, r)) != hipSuccess) return e;
+  }
+  if (iters_out) *iters_out = r.iters;
+  return extra ? fp::cg_launch_field(a, s) : hipSuccess;
 }
 
 pic_status check_solve(const pic_solve_params* p) {
@@ -74,9 +200,59 @@ pic_status check_solve(const pic_solve_params* p) {
   return PIC_OK;
 }
 
+// Kernel timing: an event before and after each launch while enabled.
+void prof_mark(pic_mesh* h, hipStream_t s) {
+  if (h->ev_used == h->ev_pool.size()) {
+    hipEvent_t ev;
+    if (hipEventCreate(&ev) != hipSuccess) {
+      h->profiling = false;
+      return;
+    }
+    h->ev_pool.push_back(ev);
+  }
+  (void)hipEventRecord(h->ev_pool[h->ev_used++], s);
+}
+
+void prof_begin(pic_mesh* h, int cls, hipStream_t s) {
+  if (!h->profiling) return;
+  h->ev_class.push_back(cls);
+  prof_mark(h, s);
+}
+
+void prof_end(pic_mesh* h, hipStream_t s) {
+  if (!h->profiling) return;
+  prof_mark(h, s);
+}
+
 }  // namespace
 
 extern "C" {
+
+pic_status pic_profile(pic_mesh* h, int32_t enable) {
+  if (!h) return fail(PIC_E_ARG, "pic_profile: null mesh");
+  h->profiling = enable != 0;
+  h->ev_used = 0;
+  h->ev_class.clear();
+  return PIC_OK;
+}
+
+pic_status pic_profile_read(pic_mesh* h, pic_kernel_times* out) {
+  if (!h || !out) return fail(PIC_E_ARG, "pic_profile_read: null argument");
+  std::memset(out, 0, sizeof *out);
+  const size_t pairs = std::min(h->ev_class.size(), h->ev_used / 2);
+  if (pairs == 0) return PIC_OK;
+  hipError_t e = hipEventSynchronize(h->ev_pool[2 * pairs - 1]);
+  if (e != hipSuccess) return hip_fail(e, "pic_profile_read");
+  for (size_t i = 0; i < pairs; ++i) {
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, h->ev_pool[2 * i], h->ev_pool[2 * i + 1]);
+    if (e != hipSuccess) return hip_fail(e, "pic_profile_read");
+    const int c = h->ev_class[i];
+    out->ms[c] += ms;
+    out->launches[c] += 1;
+  }
+  return PIC_OK;
+}
 
 const char* pic_last_error(void) { return g_err.c_str(); }
 
@@ -108,6 +284,7 @@ pic_status mesh_destroy(pic_mesh* h) {
   fp::free_mesh(h);
   if (h->queue) (void)hipFree(h->queue);
   if (h->sort_mem) (void)hipFree(h->sort_mem);
+  for (hipEvent_t ev : h->ev_pool) (void)hipEventDestroy(ev);
   delete h;
   return PIC_OK;
 }
@@ -138,7 +315,7 @@ pic_status locate(const pic_mesh* hc, int64_t n, const double* x,
     return fail(PIC_E_ARG, "locate: null array");
   if (n >= (1ll << 31)) return fail(PIC_E_ARG, "locate: n >= 2^31");
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = ensure_capacity(h, n);
+  hipError_t e = ensure_capacity(h, n, false);
   if (e != hipSuccess) return hip_fail(e, "locate");
   e = hipMemsetAsync(h->locate_count, 0, sizeof(int32_t), s);
   if (e != hipSuccess) return hip_fail(e, "locate");
@@ -193,8 +370,11 @@ pic_status poisson_solve(const pic_mesh* h, const int64_t* charge,
   if (ps != PIC_OK) return ps;
   fp::CgArgs a = cg_args(h, charge, w_sp, E0, phi, E_out, params);
   a.stats = stats;
-  hipError_t e = fp::launch_pcg_fp64(a, h->cg_grid, h->cg_block, (hipStream_t)stream);
+  pic_mesh* hm = const_cast<pic_mesh*>(h);
+  prof_begin(hm, PIC_K_SOLVE, (hipStream_t)stream);
+  hipError_t e = run_solve(hm, a, 0, (hipStream_t)stream, nullptr);
   if (e != hipSuccess) return hip_fail(e, "poisson_solve");
+  prof_end(hm, (hipStream_t)stream);
   return PIC_OK;
 }
 
@@ -240,7 +420,7 @@ pic_status pic_step(pic_mesh* h, const pic_particles* P, const pic_fields* F,
   pic_status ps = check_solve(&prm->solve);
   if (ps != PIC_OK) return ps;
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = ensure_capacity(h, P->capacity);
+  hipError_t e = ensure_capacity(h, P->capacity, prm->resort_every > 0);
   if (e != hipSuccess) return hip_fail(e, "pic_step");
 
   const fp::Phys ph = fp::phys_constants();
@@ -289,9 +469,10 @@ pic_status pic_step(pic_mesh* h, const pic_particles* P, const pic_fields* F,
 
   fp::CgArgs ca = cg_args(h, F->charge, prm->w_sp, prm->E0, F->phi, F->E, &prm->solve);
 
-  const int grid_push = h->n_cu * 8;
-  const int grid_inj = h->n_cu * 2;
-  const int grid_fb = 64;
+  const int grid_push = h->grid_push;
+  const int grid_inj = h->grid_inj;
+  const int grid_fb = h->grid_fb;
+  a.acc_rows = h->acc_rows;
   for (int32_t k = 0; k < n_steps; ++k) {
     const int64_t step = prm->step0 + k;
     pic_step_stats* st = stats + k;
@@ -300,16 +481,43 @@ pic_status pic_step(pic_mesh* h, const pic_particles* P, const pic_fields* F,
     ea.step = step;
     ea.stats = st;
     ca.step_stats = st;
-    if ((e = hipMemsetAsync(st, 0, sizeof(pic_step_stats), s)) != hipSuccess ||
-        (e = hipMemsetAsync(h->scratch, 0, sizeof(fp::StepScratch), s)) != hipSuccess ||
-        (e = hipMemsetAsync(F->charge, 0, sizeof(int64_t) * (size_t)h->dm.n_nodes, s)) != hipSuccess)
-      return hip_fail(e, "pic_step");
+    prof_begin(h, PIC_K_CLEAR, s);
+    if ((e = fp::launch_clear(F->charge, h->dm.n_nodes, st, h->scratch,
+                              h->n_cu * 2, s)) != hipSuccess)
+      return hip_fail(e, "pic_step clear");
+    prof_end(h, s);
+    prof_begin(h, PIC_K_PUSH, s);
+    a.acc_row0 = 0;
     if ((e = fp::launch_push(a, grid_push, s)) != hipSuccess) return hip_fail(e, "pic_step push");
+    prof_end(h, s);
+    prof_begin(h, PIC_K_EMIT, s);
     if ((e = fp::launch_emit(ea, s)) != hipSuccess) return hip_fail(e, "pic_step emit");
+    prof_end(h, s);
+    prof_begin(h, PIC_K_INJECT, s);
+    a.acc_row0 = grid_push;
     if ((e = fp::launch_inject(a, grid_inj, s)) != hipSuccess) return hip_fail(e, "pic_step inject");
+    prof_end(h, s);
+    prof_begin(h, PIC_K_FALLBACK, s);
+    a.acc_row0 = grid_push + grid_inj;
     if ((e = fp::launch_fallback(a, grid_fb, s)) != hipSuccess) return hip_fail(e, "pic_step fallback");
-    if ((e = fp::launch_pcg_fp64(ca, h->cg_grid, h->cg_block, s)) != hipSuccess)
+    if ((e = fp::launch_stats(h->acc_rows, grid_push + grid_inj + grid_fb, st, s)) != hipSuccess)
+      return hip_fail(e, "pic_step stats");
+    prof_end(h, s);
+    prof_begin(h, PIC_K_SOLVE, s);
+    int64_t iters = 0;
+    if ((e = run_solve(h, ca, h->step_spec, s, &iters)) != hipSuccess)
       return hip_fail(e, "pic_step solve");
+    // speculate this many iterations in the next step's first batch
+    h->step_spec = (int)std::min<int64_t>(iters, 256);
+    prof_end(h, s);
+    if (prm->resort_every > 0 && (step + 1) % prm->resort_every == 0) {
+      prof_begin(h, PIC_K_SORT, s);
+      fp::SortArgs sa = sort_args(h, P, 8);
+      sa.stats = st;
+      if ((e = fp::sort_particles(sa, P->capacity, h->n_cu, s)) != hipSuccess)
+        return hip_fail(e, "pic_step sort");
+      prof_end(h, s);
+    }
   }
   return PIC_OK;
 }

@@ -76,6 +76,7 @@ struct DevMesh {
   double b0[3], b1[3], binv[3];
   const int32_t* bstart;     // [nbx*nby*nbz + 1]
   const int32_t* bitem;
+  const int32_t* bseed;      // [nbx*nby*nbz] walk seed per bucket or -1
 };
 
 // ---------------------------------------------------------------------------

@@ -4,6 +4,7 @@
 #include <vector>
 
 #include "common.h"
+#include "solver.h"
 
 struct pic_mesh {
   fp::DevMesh dm{};
@@ -15,7 +16,12 @@ struct pic_mesh {
   double* cg_vec[7] = {};
   double* cg_part = nullptr;
   int cg_grid = 0;
-  int cg_block = 512;
+  fp::CgCtrl* cg_ctrl = nullptr;       // device control word
+  fp::CgReport* cg_report_host = nullptr;  // pinned, device-mapped report
+  fp::CgReport* cg_report_dev = nullptr;   // its device address
+  int64_t cg_seq = 0;
+  hipEvent_t rb_event = nullptr;
+  int step_spec = 0;                   // iterations speculated per step solve
   const int32_t* dir_nodes = nullptr;
   int64_t n_dir = 0;
   // step scratch
@@ -24,6 +30,9 @@ struct pic_mesh {
   int32_t* counts = nullptr;
   pic_solve_stats* solve_stats = nullptr;
   int32_t* locate_count = nullptr;
+  // particle kernel grids and their per-block counter rows
+  int grid_push = 0, grid_inj = 0, grid_fb = 0;
+  int64_t* acc_rows = nullptr;
   // particle-capacity scratch (grown on demand)
   int64_t pcap = 0;
   int32_t* queue = nullptr;
@@ -32,6 +41,11 @@ struct pic_mesh {
   // host copies of the emitting faces
   std::vector<int32_t> h_e_tet, h_e_nodes;
   std::vector<double> h_e_area;
+  // kernel timing: (class, start, stop) per launch while enabled
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<int> ev_class;
 };
 
 namespace fp {

@@ -441,31 +441,58 @@ pic_status build_mesh(const pic_mesh_desc* d, pic_mesh* h, std::string& msg) {
   M.e_nrm = upload(h, e_nrm, err);
   M.bstart = upload(h, bstart, err);
   M.bitem = upload(h, bitem, err);
+  {
+    // walk seeds: lowest-index tet whose centroid lies in each bucket
+    std::vector<int32_t> bseed(NB, -1);
+    for (int64_t t = 0; t < T; ++t) {
+      int b[3];
+      for (int k = 0; k < 3; ++k) {
+        const double c = ((tw[t].v[k] + tw[t].v[3 + k]) + (tw[t].v[6 + k] + tw[t].v[9 + k])) * 0.25;
+        b[k] = bucket_axis(c, M.b0[k], M.binv[k], M.nb[k]);
+      }
+      const int64_t id = ((int64_t)b[0] * M.nb[1] + b[1]) * M.nb[2] + b[2];
+      if (bseed[id] < 0) bseed[id] = (int32_t)t;
+    }
+    M.bseed = upload(h, bseed, err);
+  }
   h->dir_nodes = upload(h, dir_nodes, err);
   h->n_dir = (int64_t)dir_nodes.size();
   // solver scratch
   const size_t vb = sizeof(double) * (size_t)std::max<int64_t>(NF, 1);
   for (int k = 0; k < 7; ++k) h->cg_vec[k] = (double*)dev_alloc(h, vb, err);
-  int bpc = 0;
-  if (err == hipSuccess) err = pcg_fp64_occupancy(h->cg_block, &bpc);
   int dev = 0, ncu = 0;
   if (err == hipSuccess) err = hipGetDevice(&dev);
   if (err == hipSuccess) err = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   if (err == hipSuccess) {
     h->n_cu = ncu;
-    int g = std::max(1, bpc) * ncu;
-    // enough rows per workgroup to amortise the barrier; multiple of 8 XCDs
-    const int64_t want = std::max<int64_t>(8, (NF + 255) / 256);
+    // two 512-thread workgroups per CU; every workgroup of the next kernel
+    // re-reduces this many partials, so more would cost L2 traffic
+    int g = 2 * ncu;
+    const int64_t want = std::max<int64_t>(8, (NF + 63) / 64);
     if (g > want) g = (int)want;
     if (g >= 8) g -= g % 8;
-    h->cg_grid = g;
+    h->cg_grid = std::max(g, 1);
   }
-  h->cg_part = (double*)dev_alloc(h, sizeof(double) * 8 * (size_t)std::max(h->cg_grid, 1), err);
+  h->cg_part = (double*)dev_alloc(h, sizeof(double) * kCgSlots * (size_t)std::max(h->cg_grid, 1), err);
+  h->cg_ctrl = (CgCtrl*)dev_alloc(h, sizeof(CgCtrl), err);
+  if (err == hipSuccess)
+    err = hipHostMalloc((void**)&h->cg_report_host, sizeof(CgReport),
+                        hipHostMallocMapped | hipHostMallocCoherent);
+  if (err == hipSuccess) {
+    std::memset(h->cg_report_host, 0, sizeof(CgReport));
+    err = hipHostGetDevicePointer((void**)&h->cg_report_dev, h->cg_report_host, 0);
+  }
+  if (err == hipSuccess) err = hipEventCreateWithFlags(&h->rb_event, hipEventDisableTiming);
   h->scratch = (StepScratch*)dev_alloc(h, sizeof(StepScratch), err);
   h->offsets = (int32_t*)dev_alloc(h, sizeof(int32_t) * (size_t)(M.n_emit + 1), err);
   h->counts = (int32_t*)dev_alloc(h, sizeof(int32_t) * (size_t)(M.n_emit + 1), err);
   h->solve_stats = (pic_solve_stats*)dev_alloc(h, sizeof(pic_solve_stats), err);
   h->locate_count = (int32_t*)dev_alloc(h, sizeof(int32_t), err);
+  h->grid_push = std::max(8, h->n_cu * 8);
+  h->grid_inj = std::max(8, h->n_cu * 2);
+  h->grid_fb = 64;
+  h->acc_rows = (int64_t*)dev_alloc(
+      h, sizeof(int64_t) * 16 * (size_t)(h->grid_push + h->grid_inj + h->grid_fb), err);
   if (err != hipSuccess) {
     msg = std::string("mesh_create: ") + hipGetErrorString(err);
     return PIC_E_DEVICE;
@@ -485,6 +512,10 @@ pic_status build_mesh(const pic_mesh_desc* d, pic_mesh* h, std::string& msg) {
 void free_mesh(pic_mesh* h) {
   for (void* p : h->allocs) (void)hipFree(p);
   h->allocs.clear();
+  if (h->cg_report_host) (void)hipHostFree(h->cg_report_host);
+  h->cg_report_host = nullptr;
+  if (h->rb_event) (void)hipEventDestroy(h->rb_event);
+  h->rb_event = nullptr;
 }
 
 }  // namespace fp

@@ -4,6 +4,8 @@
 
 namespace fp {
 
+constexpr int kAccFields = 12;  // counters per block row (see acc_flush)
+
 struct EmitConsts {
   double a_fn, b_fn, c_s, j_unit;
 };
@@ -21,6 +23,8 @@ struct StepArgs {
   int32_t* queue;       // [capacity] fallback queue
   StepScratch* scratch;
   pic_step_stats* stats;
+  int64_t* acc_rows;    // [rows][kAccFields] per-block counters
+  int acc_row0;         // first row of this kernel
   double Q, dt, qm_dt;
   uint64_t seed;
   uint64_t instance;
@@ -62,6 +66,10 @@ struct DepositArgs {
   int64_t* charge;
 };
 
+hipError_t launch_clear(int64_t* charge, int64_t n, pic_step_stats* st,
+                        StepScratch* sc, int grid, hipStream_t s);
+hipError_t launch_stats(const int64_t* rows, int n_rows, pic_step_stats* st,
+                        hipStream_t s);
 hipError_t launch_push(const StepArgs& a, int grid, hipStream_t s);
 hipError_t launch_emit(const EmitArgs& a, hipStream_t s);
 hipError_t launch_inject(const StepArgs& a, int grid, hipStream_t s);

@@ -37,7 +37,7 @@ __device__ inline Span block_span(int64_t n) {
   return s;
 }
 
-// Per-block counters, reduced once per block into the step stats.
+// Per-thread counters of one kernel, flushed once per block.
 struct Acc {
   long long n_before, q_before, n_anode, q_anode, n_after, q_after;
   long long n_cathode, q_cathode, n_inj, q_inj, walk_steps;
@@ -62,30 +62,34 @@ __device__ inline int wave_max(int v) {
   return v;
 }
 
-__device__ inline void atomic_add_ll(int64_t* p, long long v) {
-  if (v != 0)
-    atomicAdd(reinterpret_cast<unsigned long long*>(p), (unsigned long long)v);
-}
-
-// integer sums are exact and order-free, so one atomic per wave suffices
-__device__ inline void acc_flush(const Acc& a, pic_step_stats* st) {
-  const long long v[11] = {a.n_before, a.q_before, a.n_anode,  a.q_anode,
-                           a.n_after,  a.q_after,  a.n_cathode, a.q_cathode,
-                           a.n_inj,    a.q_inj,    a.walk_steps};
-  int64_t* dst[11] = {&st->n_before, &st->q_before, &st->n_anode,
-                      &st->q_anode,  &st->n_after,  &st->q_after,
-                      &st->n_cathode, &st->q_cathode, &st->n_inj,
-                      &st->q_inj,    &st->walk_steps};
-  const bool lead = (threadIdx.x & 63) == 0;
+// Block totals of the counters written to this block's row of the partials
+// (no atomics: thousands of same-address atomics per step serialize); the
+// stats kernel sums the rows at the end of the step.
+__device__ inline void acc_flush(const Acc& a, int64_t* rows, int row) {
+  __shared__ long long lds[kAccFields][kBlock / 64];
+  const long long v[kAccFields] = {a.n_before, a.q_before, a.n_anode,
+                                   a.q_anode,  a.n_after,  a.q_after,
+                                   a.n_cathode, a.q_cathode, a.n_inj,
+                                   a.q_inj,    a.walk_steps, a.walk_max};
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-  for (int k = 0; k < 11; ++k) {
-    const long long s = wave_sum(v[k]);
-    if (lead) atomic_add_ll(dst[k], s);
+  for (int k = 0; k < kAccFields; ++k) {
+    long long s = v[k];
+    if (k == kAccFields - 1) {
+      s = wave_max((int)s);
+    } else {
+      s = wave_sum(s);
+    }
+    if (lane == 0) lds[k][wave] = s;
   }
-  const int mx = wave_max(a.walk_max);
-  if (lead && mx > 0)
-    atomicMax(reinterpret_cast<unsigned long long*>(&st->walk_max),
-              (unsigned long long)mx);
+  __syncthreads();
+  if (threadIdx.x < kAccFields) {
+    const int k = threadIdx.x;
+    long long s = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w)
+      s = k == kAccFields - 1 ? (lds[k][w] > s ? lds[k][w] : s) : s + lds[k][w];
+    rows[(int64_t)row * kAccFields + k] = s;
+  }
 }
 
 __device__ inline double4 ld_E(const double* E, int32_t node) {
@@ -119,13 +123,38 @@ __device__ inline void deposit_one(const TetGeom& g, double x, double y,
               (unsigned long long)q[k]);
 }
 
+// The seed tet of p's bucket (lowest-index tet whose centroid lies in the
+// bucket), or -1: a walk start within about one cell of p.
+__device__ inline int bucket_guess(const DevMesh& m, double x, double y,
+                                   double z) {
+  if (!(x >= m.b0[0] && x <= m.b1[0] && y >= m.b0[1] && y <= m.b1[1] &&
+        z >= m.b0[2] && z <= m.b1[2]))
+    return -1;
+  const int bx = bucket_axis(x, m.b0[0], m.binv[0], m.nb[0]);
+  const int by = bucket_axis(y, m.b0[1], m.binv[1], m.nb[1]);
+  const int bz = bucket_axis(z, m.b0[2], m.binv[2], m.nb[2]);
+  const int64_t id = ((int64_t)bx * m.nb[1] + by) * m.nb[2] + bz;
+  return m.bseed[id];
+}
+
 // Neighbour walk from tet t with the point's frame offset (sx, sy) relative
-// to t.  Returns the tet when the point is certified strictly inside it in
-// its own frame (then no other tet holds it, so it is the canonical
-// answer), or -1 when the exact bucket scan must decide.
+// to t; after two tets without success it restarts from a tet of the
+// point's bucket.  Returns the tet when the point is certified strictly
+// inside it in its own frame (then no other tet holds it, so it is the
+// canonical answer), or -1 when the exact bucket scan must decide.
 __device__ inline int walk(const DevMesh& m, double x, double y, double z,
                            int t, int sx, int sy, int& steps) {
+  bool jumped = false;
   for (steps = 0; steps < kMaxWalk; ++steps) {
+    if (steps == 2 && !jumped) {
+      jumped = true;
+      const int g = bucket_guess(m, x, y, z);
+      if (g >= 0) {
+        t = g;
+        sx = 0;
+        sy = 0;
+      }
+    }
     const TetWalk& W = m.tw[t];
     double v[12];
 #pragma unroll
@@ -183,9 +212,66 @@ __device__ int scan_locate(const DevMesh& m, double x, double y, double z) {
 }
 
 // After the drift: wrap, absorb at the anode, locate, deposit.
+// Per-workgroup node-charge table in LDS (open addressing on the node id).
+// Particles of one workgroup share few nodes, so accumulating their int64
+// charges here and flushing one global atomic per distinct node removes
+// the same-address contention of per-particle global atomics.  Integer
+// addition is exact and order-free, so the result is unchanged.
+constexpr int kTable = 2048;  // > 4 nodes x the particles of one block
+
+struct ChargeTable {
+  int32_t key[kTable];
+  unsigned long long val[kTable];
+};
+
+__device__ inline void table_clear(ChargeTable& T) {
+  for (int k = threadIdx.x; k < kTable; k += blockDim.x) {
+    T.key[k] = -1;
+    T.val[k] = 0ull;
+  }
+  __syncthreads();
+}
+
+__device__ inline void table_add(ChargeTable& T, int32_t node, int64_t q,
+                                 int64_t* charge) {
+  uint32_t h = ((uint32_t)node * 2654435761u) >> 21;  // 11 bits
+  for (int probe = 0; probe < 64; ++probe) {
+    const int32_t old = atomicCAS(&T.key[h], -1, node);
+    if (old == -1 || old == node) {
+      atomicAdd(&T.val[h], (unsigned long long)q);
+      return;
+    }
+    h = (h + 1) & (kTable - 1);
+  }
+  atomicAdd(reinterpret_cast<unsigned long long*>(charge + node),
+            (unsigned long long)q);
+}
+
+__device__ inline void table_flush(ChargeTable& T, int64_t* charge) {
+  __syncthreads();
+  for (int k = threadIdx.x; k < kTable; k += blockDim.x) {
+    const int32_t node = T.key[k];
+    const unsigned long long v = T.val[k];
+    if (node >= 0 && v != 0ull)
+      atomicAdd(reinterpret_cast<unsigned long long*>(charge + node), v);
+  }
+}
+
+__device__ inline void deposit_table(const TetGeom& g, double x, double y,
+                                     double z, double w, ChargeTable& T,
+                                     int64_t* charge) {
+  double lam[4];
+  barycentric(g, x, y, z, lam);
+  int64_t q[4];
+  charge_split(lam, w, q);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) table_add(T, g.node[k], q[k], charge);
+}
+
 __device__ inline void settle(const DevMesh& m, const StepArgs& a, int64_t i,
                               double x, double y, double z, int sx, int sy,
-                              int hint, double w, long long qfx, Acc& acc) {
+                              int hint, double w, long long qfx, Acc& acc,
+                              ChargeTable& T) {
   if (z >= m.z_top) {
     a.tet[i] = -1;
     acc.n_anode += 1;
@@ -198,7 +284,7 @@ __device__ inline void settle(const DevMesh& m, const StepArgs& a, int64_t i,
   if (steps > acc.walk_max) acc.walk_max = steps;
   if (t >= 0) {
     a.tet[i] = t;
-    deposit_one(m.tg[t], x, y, z, w, a.charge);
+    deposit_table(m.tg[t], x, y, z, w, T, a.charge);
     acc.n_after += 1;
     acc.q_after += qfx;
   } else {
@@ -240,6 +326,8 @@ __global__ void __launch_bounds__(kBlock) k_push(StepArgs a) {
   const Span sp = block_span(n);
   Acc acc;
   acc_zero(acc);
+  __shared__ ChargeTable T;
+  table_clear(T);
   const double Q = a.Q;
   const double dt = a.dt;
   for (int64_t i = sp.lo + threadIdx.x; i < sp.hi; i += blockDim.x) {
@@ -268,9 +356,10 @@ __global__ void __launch_bounds__(kBlock) k_push(StepArgs a) {
     a.vx[i] = vx;
     a.vy[i] = vy;
     a.vz[i] = vz;
-    settle(m, a, i, x, y, z, sx, sy, t, w, qfx, acc);
+    settle(m, a, i, x, y, z, sx, sy, t, w, qfx, acc, T);
   }
-  acc_flush(acc, a.stats);
+  table_flush(T, a.charge);
+  acc_flush(acc, a.acc_rows, a.acc_row0 + blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -422,6 +511,8 @@ __global__ void __launch_bounds__(kBlock) k_inject(StepArgs a) {
   const int64_t base = a.scratch->inj_base;
   Acc acc;
   acc_zero(acc);
+  __shared__ ChargeTable T;
+  table_clear(T);
   const double dt = a.dt;
   const int32_t* off = a.offsets;
   for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
@@ -479,9 +570,10 @@ __global__ void __launch_bounds__(kBlock) k_inject(StepArgs a) {
     a.id[i] = (a.step << 42) | ((int64_t)f << 21) | o;
     acc.n_inj += 1;
     acc.q_inj += qfx;
-    settle(m, a, i, x, y, z, sx, sy, m.e_tet[f], w, qfx, acc);
+    settle(m, a, i, x, y, z, sx, sy, m.e_tet[f], w, qfx, acc, T);
   }
-  acc_flush(acc, a.stats);
+  table_flush(T, a.charge);
+  acc_flush(acc, a.acc_rows, a.acc_row0 + blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -511,11 +603,27 @@ __global__ void __launch_bounds__(kBlock) k_fallback(StepArgs a) {
       acc.q_cathode += qfx;
     }
   }
-  if (n > 0) {
-    acc_flush(acc, a.stats);
-    if (blockIdx.x == 0 && threadIdx.x == 0)
-      atomicAdd(reinterpret_cast<unsigned long long*>(&a.stats->n_fallback),
-                (unsigned long long)n);
+  acc_flush(acc, a.acc_rows, a.acc_row0 + blockIdx.x);
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.stats->n_fallback = n;
+}
+
+// Sum of the counter rows of one step into its stats.
+__global__ void __launch_bounds__(kAccFields * 64) k_stats(const int64_t* rows,
+                                                          int n_rows,
+                                                          pic_step_stats* st) {
+  const int k = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  long long s = 0;
+  for (int r = lane; r < n_rows; r += 64) {
+    const long long v = rows[(int64_t)r * kAccFields + k];
+    s = k == kAccFields - 1 ? (v > s ? v : s) : s + v;
+  }
+  s = k == kAccFields - 1 ? (long long)wave_max((int)s) : wave_sum(s);
+  if (lane == 0) {
+    int64_t* dst[kAccFields] = {&st->n_before, &st->q_before, &st->n_anode,
+                                &st->q_anode,  &st->n_after,  &st->q_after,
+                                &st->n_cathode, &st->q_cathode, &st->n_inj,
+                                &st->q_inj,    &st->walk_steps, &st->walk_max};
+    *dst[k] = s;
   }
 }
 
@@ -567,9 +675,37 @@ __global__ void __launch_bounds__(kBlock) k_deposit(DepositArgs a) {
   }
 }
 
+// Per-step clears: node charges, the step's stats and counters.
+__global__ void __launch_bounds__(kBlock) k_clear(int64_t* charge, int64_t n,
+                                                  pic_step_stats* st,
+                                                  StepScratch* sc) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    charge[i] = 0;
+  if (blockIdx.x == 0) {
+    int64_t* s64 = reinterpret_cast<int64_t*>(st);
+    const int ns = (int)(sizeof(pic_step_stats) / sizeof(int64_t));
+    if (threadIdx.x < ns) s64[threadIdx.x] = 0;
+    int32_t* c32 = reinterpret_cast<int32_t*>(sc);
+    const int nc = (int)(sizeof(StepScratch) / sizeof(int32_t));
+    if (threadIdx.x < nc) c32[threadIdx.x] = 0;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
+hipError_t launch_clear(int64_t* charge, int64_t n, pic_step_stats* st,
+                        StepScratch* sc, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_clear, dim3(grid), dim3(kBlock), 0, s, charge, n, st, sc);
+  return hipGetLastError();
+}
+hipError_t launch_stats(const int64_t* rows, int n_rows, pic_step_stats* st,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_stats, dim3(1), dim3(kAccFields * 64), 0, s, rows, n_rows, st);
+  return hipGetLastError();
+}
+
 hipError_t launch_push(const StepArgs& a, int grid, hipStream_t s) {
   hipLaunchKernelGGL(k_push, dim3(grid), dim3(kBlock), 0, s, a);
   return hipGetLastError();

@@ -1,8 +1,25 @@
-// Launch interface of the cooperative Poisson solver.
+// Launch interface of the Poisson solver kernels.
 #pragma once
 #include "common.h"
 
 namespace fp {
+
+enum { CG_ITER = 0, CG_RECHECK = 1, CG_DONE = 2, CG_NOCONV = 3 };
+
+// Solver control word (device memory; mirrored to pinned host memory).
+struct CgCtrl {
+  int32_t state;
+  int32_t zero_rhs;
+  int64_t iters;        // iterations completed before the current (re)start
+  int64_t iters_final;  // iterations completed when the recursive test fired
+  int64_t restarts;
+  double bb;            // ||b||^2
+  double relres;        // last true relative residual
+  double alpha[2], gamma[2];
+};
+
+constexpr int kCgBlock = 512;
+constexpr int kCgSlots = 10;
 
 struct CgArgs {
   DevMesh m;
@@ -14,15 +31,28 @@ struct CgArgs {
   double* phi;            // [n_nodes] in: guess, out: solution
   double* E;              // [4 n_nodes] or null
   double *b, *x, *r, *u, *w, *p, *s;  // [n_free]
-  double* part;           // [2][4][grid]
+  double* part;           // [kCgSlots][G]
+  int G;                  // workgroups of every solver kernel
+  CgCtrl* ctrl;
   const int32_t* dir_nodes;
   int64_t n_dir;
   pic_solve_stats* stats;      // or null
   pic_step_stats* step_stats;  // or null
 };
 
-hipError_t launch_pcg_fp64(const CgArgs& args, int grid, int block,
-                           hipStream_t s);
-hipError_t pcg_fp64_occupancy(int block, int* blocks_per_cu);
+// Host-visible report of the control word (pinned, device-mapped memory).
+struct CgReport {
+  int64_t seq;     // written last; the host waits for its value
+  int32_t state;
+  int32_t pad;
+  int64_t iters;
+};
+
+hipError_t cg_launch_report(CgCtrl* ctrl, CgReport* host_mapped, int64_t seq,
+                            hipStream_t s);
+hipError_t cg_launch_begin(const CgArgs& a, hipStream_t s);
+hipError_t cg_launch_iters(const CgArgs& a, int it0, int n, hipStream_t s);
+hipError_t cg_launch_recheck(const CgArgs& a, hipStream_t s);
+hipError_t cg_launch_field(const CgArgs& a, hipStream_t s);
 
 }  // namespace fp

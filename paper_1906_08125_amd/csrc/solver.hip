@@ -1,27 +1,32 @@
 // Poisson solve on the free nodes (Eq. poisson with Eq. poisson_bc in the
-// Galerkin form of App. B) as one cooperative persistent kernel: Jacobi-
-// preconditioned CG in the single-reduction (Chronopoulos-Gear) ordering,
-// warm started, with the stopping test re-checked on the true residual, then
-// the nodal field E = R phi for every node.
+// Galerkin form of App. B): Jacobi-preconditioned CG in the single-
+// reduction (Chronopoulos-Gear) ordering, warm started, with the stopping
+// test re-checked on the true residual, then the nodal field E = R phi.
 //
-// Layout: every workgroup owns one contiguous block of rows; block indices
-// are assigned so that the 8 XCDs each sweep one contiguous eighth of the
-// rows (workgroup g runs on XCD g mod 8), which keeps the SpMV's neighbour
-// gathers inside one XCD's L2.  Reductions are deterministic: each
-// workgroup writes a partial in a fixed order and every workgroup sums all
-// partials in the same fixed order after the grid barrier.
-#include <hip/hip_cooperative_groups.h>
-
+// The solve is a chain of ordinary kernel launches (a launch costs ~3 us on
+// MI355X, a device-wide barrier inside a persistent kernel 12-19 us):
+//   resid  : r = b - K x (b from the deposited charge, x = phi), u = D^-1 r
+//   start  : convergence test; w = K u; (r,u), (w,u)
+//   upd(i) : scalars of iteration i; p, s, x, r, u updates; (r,r), (r,u)
+//   spmv(i): w = K u; (w,u)
+//   field  : phi scatter (Dirichlet nodes 0) and E = R x
+// Each kernel writes one partial sum per workgroup; the next kernel reduces
+// all partials in a fixed order in every workgroup (deterministic, same
+// values everywhere), so no cross-workgroup synchronization is needed
+// inside a kernel.  A control word in device memory carries the state
+// (ITER, RECHECK, DONE, NOCONV); kernels whose state does not apply return
+// at once, which lets the host launch iterations in batches.
+//
+// Row blocks are contiguous per workgroup, grouped so that each of the 8 XCDs
+// (workgroup g runs on XCD g mod 8) sweeps one contiguous eighth of the rows.
 #include "common.h"
 #include "solver.h"
-
-namespace cgs = cooperative_groups;
 
 namespace fp {
 
 namespace {
 
-constexpr int kLPR = 8;  // lanes per CSR row in the SpMV
+constexpr int kLPR = 8;  // lanes per CSR row
 
 struct Rows {
   int64_t lo, hi;
@@ -35,15 +40,15 @@ __device__ inline Rows my_rows(int64_t n) {
   const int64_t per = (n + G - 1) / G;
   Rows r;
   r.lo = (int64_t)chunk * per;
-  r.hi = r.lo + per < n ? r.lo + per : n;
   if (r.lo > n) r.lo = n;
+  r.hi = r.lo + per < n ? r.lo + per : n;
   return r;
 }
 
-// Deterministic block sum of up to 3 values per thread; result valid in all
-// threads.  Fixed shuffle pattern inside a wave, fixed wave order in LDS.
+// Deterministic block sum; result valid in every thread.
 template <int NQ>
-__device__ inline void block_sum(double (&v)[NQ], double* lds) {
+__device__ inline void block_sum(double (&v)[NQ]) {
+  __shared__ double lds[NQ][16];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int nw = blockDim.x >> 6;
@@ -52,37 +57,41 @@ __device__ inline void block_sum(double (&v)[NQ], double* lds) {
     double x = v[q];
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
-    if (lane == 0) lds[q * 16 + wave] = x;
+    if (lane == 0) lds[q][wave] = x;
   }
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     double s = 0.0;
-    for (int w = 0; w < nw; ++w) s += lds[q * 16 + w];
+    for (int w = 0; w < nw; ++w) s += lds[q][w];
     v[q] = s;
   }
   __syncthreads();
 }
 
-// Sum of the per-workgroup partials part[q*G + j] over j, identical in every
-// workgroup (same data, same order).
+// Totals of partial sums written by the previous kernel: part[q][0..P).
 template <int NQ>
-__device__ inline void grid_total(const double* part, int G, double (&tot)[NQ],
-                                  double* lds) {
-  double v[NQ];
+__device__ inline void totals(const double* part, int P, int stride,
+                              double (&t)[NQ]) {
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     double s = 0.0;
-    for (int j = threadIdx.x; j < G; j += blockDim.x) s += part[q * G + j];
-    v[q] = s;
+    for (int j = threadIdx.x; j < P; j += blockDim.x) s += part[q * stride + j];
+    t[q] = s;
   }
-  block_sum<NQ>(v, lds);
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) tot[q] = v[q];
+  block_sum<NQ>(t);
 }
 
-// y_i = sum_k val[k] x[col[k]] for the rows of this workgroup; returns via
-// callback on the first lane of each row group.
+template <int NQ>
+__device__ inline void write_partials(double* part, int stride,
+                                      double (&v)[NQ]) {
+  block_sum<NQ>(v);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) part[q * stride + blockIdx.x] = v[q];
+  }
+}
+
 template <typename F>
 __device__ inline void spmv_rows(const DevMesh& m, const double* __restrict__ x,
                                  Rows rows, F&& emit) {
@@ -105,212 +114,310 @@ __device__ inline void spmv_rows(const DevMesh& m, const double* __restrict__ x,
 
 }  // namespace
 
-__global__ void __launch_bounds__(512)
-k_pcg_fp64(CgArgs a) {
-  cgs::grid_group grid = cgs::this_grid();
-  __shared__ double lds[64];
-  const DevMesh& m = a.m;
-  const int64_t n = m.n_free;
-  const int G = gridDim.x;
-  const Rows rows = my_rows(n);
-  double* part = a.part;  // [2][4][G]
-  auto P = [&](int buf, int q) { return part + ((size_t)buf * 4 + q) * G; };
+// Partial-sum slots (each [G] doubles): 0 bb, 1 rr(resid), 2-3 start (ru, wu),
+// 4-5 upd even (rr, ru), 6-7 upd odd, 8 spmv even (wu), 9 spmv odd.
+__device__ inline double* slot(const CgArgs& a, int k) {
+  return a.part + (size_t)k * a.G;
+}
 
-  // right-hand side and warm start
-  {
-    double v[1] = {0.0};
-    for (int64_t i = rows.lo + threadIdx.x; i < rows.hi; i += blockDim.x) {
+// r = b - K x with b_i = coef c_i + E0 g_i and x = phi on free nodes.  The
+// product reads phi through the free->node map, so x need not exist yet.
+__global__ void __launch_bounds__(512) k_cg_resid(CgArgs a) {
+  const DevMesh& m = a.m;
+  const Rows rows = my_rows(m.n_free);
+  double v[2] = {0.0, 0.0};
+  const int sub = threadIdx.x % kLPR;
+  const int grp = threadIdx.x / kLPR;
+  const int ngrp = blockDim.x / kLPR;
+  for (int64_t i0 = rows.lo; i0 < rows.hi; i0 += ngrp) {
+    const int64_t i = i0 + grp;
+    double s = 0.0;
+    if (i < rows.hi) {
+      const int k1 = m.rowptr[i + 1];
+      for (int k = m.rowptr[i] + sub; k < k1; k += kLPR)
+        s += m.val[k] * a.phi[m.free2node[m.col[k]]];
+    }
+#pragma unroll
+    for (int off = kLPR / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off, kLPR);
+    if (i < rows.hi && sub == 0) {
       const int32_t nd = m.free2node[i];
       const double c = a.charge ? (double)a.charge[nd] : 0.0;
       const double bi = a.coef * c + a.E0 * m.g_unit[i];
+      const double ri = bi - s;
       a.b[i] = bi;
       a.x[i] = a.phi[nd];
+      a.r[i] = ri;
+      a.u[i] = ri * m.invdiag[i];
       v[0] += bi * bi;
+      v[1] += ri * ri;
     }
-    block_sum<1>(v, lds);
-    if (threadIdx.x == 0) P(0, 0)[blockIdx.x] = v[0];
   }
-  grid.sync();
-  double bn;
-  {
-    double t[1];
-    grid_total<1>(P(0, 0), G, t, lds);
-    bn = sqrt(t[0]);
-  }
-  int64_t it = 0;
-  int64_t restarts = 0;
-  int status = 0;
-  double relres = 0.0;
-  int buf = 1;
-  if (bn == 0.0) {
-    for (int64_t i = rows.lo + threadIdx.x; i < rows.hi; i += blockDim.x)
-      a.x[i] = 0.0;
-    grid.sync();
+  write_partials<2>(slot(a, 0), a.G, v);
+}
+
+// Re-check of the true residual after the recursive one converged: r = b - Kx.
+__global__ void __launch_bounds__(512) k_cg_recheck(CgArgs a) {
+  if (a.ctrl->state != CG_RECHECK) return;
+  const DevMesh& m = a.m;
+  const Rows rows = my_rows(m.n_free);
+  double v[1] = {0.0};
+  spmv_rows(m, a.x, rows, [&](int64_t i, double s) {
+    const double ri = a.b[i] - s;
+    a.r[i] = ri;
+    a.u[i] = ri * m.invdiag[i];
+    v[0] += ri * ri;
+  });
+  write_partials<1>(slot(a, 1), a.G, v);
+}
+
+// Convergence test on the true residual; when not converged, the first
+// product w = K u of a (re)started CG.  Launched by the host only at the
+// start and after a RECHECK.  Fields written here by workgroup 0 (state,
+// iters, relres, restarts) are never read by other workgroups of this
+// launch; they read iters_final and bb, which are stable here.
+__global__ void __launch_bounds__(512) k_cg_start(CgArgs a, int after_recheck) {
+  CgCtrl* c = a.ctrl;
+  double t[2];
+  if (after_recheck) {
+    double t1[1];
+    totals<1>(slot(a, 1), a.G, 1, t1);
+    t[0] = c->bb;
+    t[1] = t1[0];
   } else {
-    const double thr = a.tol * bn;
-    for (;;) {
-      // true residual r = b - K x, u = D^-1 r
-      {
-        double v[1] = {0.0};
-        spmv_rows(m, a.x, rows, [&](int64_t i, double s) {
-          const double ri = a.b[i] - s;
-          a.r[i] = ri;
-          a.u[i] = ri * m.invdiag[i];
-          v[0] += ri * ri;
-        });
-        block_sum<1>(v, lds);
-        if (threadIdx.x == 0) P(buf, 0)[blockIdx.x] = v[0];
-      }
-      grid.sync();
-      double t1[1];
-      grid_total<1>(P(buf, 0), G, t1, lds);
-      buf ^= 1;
-      relres = sqrt(t1[0]) / bn;
-      if (sqrt(t1[0]) <= thr) break;
-      if (it >= a.max_iter) {
-        status = PIC_E_NOCONV;
-        break;
-      }
-      ++restarts;
-      // w = K u, gamma = (r, u), delta = (w, u)
-      {
-        double v[2] = {0.0, 0.0};
-        spmv_rows(m, a.u, rows, [&](int64_t i, double s) {
-          a.w[i] = s;
-          const double ui = a.u[i];
-          v[0] += a.r[i] * ui;
-          v[1] += s * ui;
-        });
-        block_sum<2>(v, lds);
-        if (threadIdx.x == 0) {
-          P(buf, 0)[blockIdx.x] = v[0];
-          P(buf, 1)[blockIdx.x] = v[1];
-        }
-      }
-      grid.sync();
-      double t2[2];
-      grid_total<2>(P(buf, 0), G, t2, lds);
-      buf ^= 1;
-      double gamma = t2[0];
-      double alpha = gamma / t2[1];
-      double beta = 0.0;
-      bool first = true;
-      bool recheck = false;
-      while (!recheck) {
-        // row-local: p = u + beta p; s = w + beta s; x += alpha p;
-        // r -= alpha s; u = D^-1 r; partial (r, r), (r, u)
-        double v[3] = {0.0, 0.0, 0.0};
-        for (int64_t i = rows.lo + threadIdx.x; i < rows.hi; i += blockDim.x) {
-          const double pi = first ? a.u[i] : a.u[i] + beta * a.p[i];
-          const double si = first ? a.w[i] : a.w[i] + beta * a.s[i];
-          a.p[i] = pi;
-          a.s[i] = si;
-          a.x[i] += alpha * pi;
-          const double ri = a.r[i] - alpha * si;
-          a.r[i] = ri;
-          const double ui = ri * m.invdiag[i];
-          a.u[i] = ui;
-          v[0] += ri * ri;
-          v[1] += ri * ui;
-        }
-        first = false;
-        grid.sync();
-        ++it;
-        // w = K u; partial (w, u)
-        spmv_rows(m, a.u, rows, [&](int64_t i, double s) {
-          a.w[i] = s;
-          v[2] += s * a.u[i];
-        });
-        block_sum<3>(v, lds);
-        if (threadIdx.x == 0) {
-          P(buf, 0)[blockIdx.x] = v[0];
-          P(buf, 1)[blockIdx.x] = v[1];
-          P(buf, 2)[blockIdx.x] = v[2];
-        }
-        grid.sync();
-        double t3[3];
-        grid_total<3>(P(buf, 0), G, t3, lds);
-        buf ^= 1;
-        if (sqrt(t3[0]) <= thr || it >= a.max_iter) {
-          recheck = true;
-          break;
-        }
-        const double g1 = t3[1];
-        beta = g1 / gamma;
-        alpha = g1 / (t3[2] - beta * g1 / alpha);
-        gamma = g1;
-      }
-    }
+    totals<2>(slot(a, 0), a.G, a.G, t);
   }
-  // scatter the solution; Dirichlet nodes hold 0
-  for (int64_t i = rows.lo + threadIdx.x; i < rows.hi; i += blockDim.x)
-    a.phi[m.free2node[i]] = a.x[i];
+  const double bn = sqrt(t[0]);
+  const double rn = sqrt(t[1]);
+  const int64_t done_iters = c->iters_final;
+  const bool done = bn == 0.0 || rn <= a.tol * bn;
+  const bool noconv = !done && done_iters >= a.max_iter;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (!after_recheck) c->bb = t[0];
+    c->iters = done_iters;
+    c->relres = bn > 0.0 ? rn / bn : 0.0;
+    c->state = done ? CG_DONE : (noconv ? CG_NOCONV : CG_ITER);
+    if (!done && !noconv) c->restarts += 1;
+    if (bn == 0.0) c->zero_rhs = 1;
+  }
+  if (done || noconv) return;
+  const DevMesh& m = a.m;
+  const Rows rows = my_rows(m.n_free);
+  double v[2] = {0.0, 0.0};
+  spmv_rows(m, a.u, rows, [&](int64_t i, double s) {
+    a.w[i] = s;
+    const double ui = a.u[i];
+    v[0] += a.r[i] * ui;
+    v[1] += s * ui;
+  });
+  write_partials<2>(slot(a, 2), a.G, v);
+}
+
+// Iteration it (0-based since the last (re)start, global count in ctrl):
+// scalars from the previous products, then the row-local updates.
+__global__ void __launch_bounds__(512) k_cg_upd(CgArgs a, int it) {
+  CgCtrl* c = a.ctrl;
+  if (c->state != CG_ITER) return;
+  double alpha, beta, gamma;
+  if (it == 0) {
+    double t[2];
+    totals<2>(slot(a, 2), a.G, a.G, t);
+    gamma = t[0];
+    alpha = gamma / t[1];
+    beta = 0.0;
+  } else {
+    const int pb = (it - 1) & 1;
+    double t3[3];
+    {
+      double t2[2];
+      totals<2>(slot(a, 4 + 2 * pb), a.G, a.G, t2);
+      double t1[1];
+      totals<1>(slot(a, 8 + pb), a.G, 1, t1);
+      t3[0] = t2[0];
+      t3[1] = t2[1];
+      t3[2] = t1[0];
+    }
+    // it iterations done since the (re)start; c->iters is stable while
+    // iterating, so every workgroup takes the same decision
+    const double rn = sqrt(t3[0]);
+    const double bn = sqrt(c->bb);
+    if (rn <= a.tol * bn || c->iters + it >= a.max_iter) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        c->state = CG_RECHECK;
+        c->iters_final = c->iters + it;
+      }
+      return;
+    }
+    const double g_prev = c->gamma[pb];
+    const double a_prev = c->alpha[pb];
+    gamma = t3[1];
+    beta = gamma / g_prev;
+    alpha = gamma / (t3[2] - beta * gamma / a_prev);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    c->gamma[it & 1] = gamma;
+    c->alpha[it & 1] = alpha;
+  }
+  const DevMesh& m = a.m;
+  const Rows rows = my_rows(m.n_free);
+  double v[2] = {0.0, 0.0};
+  const bool first = it == 0;
+  for (int64_t i = rows.lo + threadIdx.x; i < rows.hi; i += blockDim.x) {
+    const double pi = first ? a.u[i] : a.u[i] + beta * a.p[i];
+    const double si = first ? a.w[i] : a.w[i] + beta * a.s[i];
+    a.p[i] = pi;
+    a.s[i] = si;
+    a.x[i] += alpha * pi;
+    const double ri = a.r[i] - alpha * si;
+    a.r[i] = ri;
+    const double ui = ri * m.invdiag[i];
+    a.u[i] = ui;
+    v[0] += ri * ri;
+    v[1] += ri * ui;
+  }
+  write_partials<2>(slot(a, 4 + 2 * (it & 1)), a.G, v);
+}
+
+__global__ void __launch_bounds__(512) k_cg_spmv(CgArgs a, int it) {
+  if (a.ctrl->state != CG_ITER) return;
+  const DevMesh& m = a.m;
+  const Rows rows = my_rows(m.n_free);
+  double v[1] = {0.0};
+  spmv_rows(m, a.u, rows, [&](int64_t i, double s) {
+    a.w[i] = s;
+    v[0] += s * a.u[i];
+  });
+  write_partials<1>(slot(a, 8 + (it & 1)), a.G, v);
+}
+
+// phi on every node (Dirichlet nodes 0) and the nodal field E = R x.
+__global__ void __launch_bounds__(512) k_cg_field(CgArgs a) {
+  const DevMesh& m = a.m;
+  const CgCtrl* c = a.ctrl;
+  const bool zero = c->zero_rhs != 0;
   {
+    const Rows rows = my_rows(m.n_free);
+    for (int64_t i = rows.lo + threadIdx.x; i < rows.hi; i += blockDim.x) {
+      const double xi = zero ? 0.0 : a.x[i];
+      if (zero) a.x[i] = 0.0;
+      a.phi[m.free2node[i]] = xi;
+    }
     const Rows dr = my_rows(a.n_dir);
     for (int64_t i = dr.lo + threadIdx.x; i < dr.hi; i += blockDim.x)
       a.phi[a.dir_nodes[i]] = 0.0;
   }
-  // nodal field E_i = sum_j R_ij x_j (x is complete after the last barrier)
-  if (a.E) {
-    const Rows fr = my_rows(m.n_nodes);
-    const int sub = threadIdx.x % kLPR;
-    const int grp = threadIdx.x / kLPR;
-    const int ngrp = blockDim.x / kLPR;
-    const int64_t nf = m.nnz_field;
-    for (int64_t i0 = fr.lo; i0 < fr.hi; i0 += ngrp) {
-      const int64_t i = i0 + grp;
-      double ex = 0.0, ey = 0.0, ez = 0.0;
-      if (i < fr.hi) {
-        const int k1 = m.frow[i + 1];
-        for (int k = m.frow[i] + sub; k < k1; k += kLPR) {
-          const double xj = a.x[m.fcol[k]];
-          ex += m.fval[k] * xj;
-          ey += m.fval[nf + k] * xj;
-          ez += m.fval[2 * nf + k] * xj;
-        }
-      }
-#pragma unroll
-      for (int off = kLPR / 2; off >= 1; off >>= 1) {
-        ex += __shfl_xor(ex, off, kLPR);
-        ey += __shfl_xor(ey, off, kLPR);
-        ez += __shfl_xor(ez, off, kLPR);
-      }
-      if (i < fr.hi && sub == 0) {
-        double4 e;
-        e.x = ex;
-        e.y = ey;
-        e.z = ez;
-        e.w = 0.0;
-        reinterpret_cast<double4*>(a.E)[i] = e;
-      }
-    }
-  }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const int64_t st = c->state == CG_NOCONV ? PIC_E_NOCONV : 0;
     if (a.stats) {
-      a.stats->iters = it;
-      a.stats->status = status;
-      a.stats->restarts = restarts;
-      a.stats->relres = relres;
-      a.stats->bnorm = bn;
+      a.stats->iters = c->iters;
+      a.stats->status = st;
+      a.stats->restarts = c->restarts;
+      a.stats->relres = c->relres;
+      a.stats->bnorm = sqrt(c->bb);
     }
     if (a.step_stats) {
-      a.step_stats->cg_iters = it;
-      a.step_stats->cg_relres = relres;
-      if (status != 0 && a.step_stats->status == 0) a.step_stats->status = status;
+      a.step_stats->cg_iters = c->iters;
+      a.step_stats->cg_relres = c->relres;
+      if (st != 0 && a.step_stats->status == 0) a.step_stats->status = st;
+    }
+  }
+  if (!a.E) return;
+  const Rows fr = my_rows(m.n_nodes);
+  const int sub = threadIdx.x % kLPR;
+  const int grp = threadIdx.x / kLPR;
+  const int ngrp = blockDim.x / kLPR;
+  const int64_t nf = m.nnz_field;
+  for (int64_t i0 = fr.lo; i0 < fr.hi; i0 += ngrp) {
+    const int64_t i = i0 + grp;
+    double ex = 0.0, ey = 0.0, ez = 0.0;
+    if (i < fr.hi && !zero) {
+      const int k1 = m.frow[i + 1];
+      for (int k = m.frow[i] + sub; k < k1; k += kLPR) {
+        const double xj = a.x[m.fcol[k]];
+        ex += m.fval[k] * xj;
+        ey += m.fval[nf + k] * xj;
+        ez += m.fval[2 * nf + k] * xj;
+      }
+    }
+#pragma unroll
+    for (int off = kLPR / 2; off >= 1; off >>= 1) {
+      ex += __shfl_xor(ex, off, kLPR);
+      ey += __shfl_xor(ey, off, kLPR);
+      ez += __shfl_xor(ez, off, kLPR);
+    }
+    if (i < fr.hi && sub == 0) {
+      double4 e;
+      e.x = ex;
+      e.y = ey;
+      e.z = ez;
+      e.w = 0.0;
+      reinterpret_cast<double4*>(a.E)[i] = e;
     }
   }
 }
 
-hipError_t launch_pcg_fp64(const CgArgs& args, int grid, int block,
-                           hipStream_t s) {
-  void* kargs[] = {(void*)&args};
-  return hipLaunchCooperativeKernel((const void*)k_pcg_fp64, dim3(grid),
-                                    dim3(block), kargs, 0, s);
+__global__ void k_cg_reset(CgCtrl* c) {
+  if (threadIdx.x == 0) {
+    CgCtrl z;
+    z.state = CG_ITER;
+    z.zero_rhs = 0;
+    z.iters = 0;
+    z.iters_final = 0;
+    z.restarts = 0;
+    z.bb = 0.0;
+    z.relres = 0.0;
+    z.alpha[0] = z.alpha[1] = 0.0;
+    z.gamma[0] = z.gamma[1] = 0.0;
+    *c = z;
+  }
 }
 
-hipError_t pcg_fp64_occupancy(int block, int* blocks_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      blocks_per_cu, (const void*)k_pcg_fp64, block, 0);
+// Copies the control state to host-mapped memory; the sequence number is
+// stored last with system-scope release so the host sees a complete record.
+__global__ void k_cg_report(const CgCtrl* c, CgReport* r, int64_t seq) {
+  if (threadIdx.x == 0) {
+    r->state = c->state;
+    r->iters = c->state == CG_RECHECK ? c->iters_final : c->iters;
+    __hip_atomic_store(&r->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
+hipError_t cg_launch_report(CgCtrl* ctrl, CgReport* host_mapped, int64_t seq,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_report, dim3(1), dim3(64), 0, s, ctrl, host_mapped, seq);
+  return hipGetLastError();
+}
+
+#define LAUNCH(kern, ...)                                                \
+  do {                                                                      \
+    hipLaunchKernelGGL(kern, dim3(a.G), dim3(kCgBlock), 0, s, __VA_ARGS__); \
+    hipError_t e_ = hipGetLastError();                                      \
+    if (e_ != hipSuccess) return e_;                                        \
+  } while (0)
+
+hipError_t cg_launch_begin(const CgArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_reset, dim3(1), dim3(64), 0, s, a.ctrl);
+  LAUNCH(k_cg_resid, a);
+  LAUNCH(k_cg_start, a, 0);
+  return hipSuccess;
+}
+
+hipError_t cg_launch_iters(const CgArgs& a, int it0, int n, hipStream_t s) {
+  for (int k = 0; k < n; ++k) {
+    LAUNCH(k_cg_upd, a, it0 + k);
+    LAUNCH(k_cg_spmv, a, it0 + k);
+  }
+  return hipSuccess;
+}
+
+hipError_t cg_launch_recheck(const CgArgs& a, hipStream_t s) {
+  LAUNCH(k_cg_recheck, a);
+  LAUNCH(k_cg_start, a, 1);
+  return hipSuccess;
+}
+
+hipError_t cg_launch_field(const CgArgs& a, hipStream_t s) {
+  LAUNCH(k_cg_field, a);
+  return hipSuccess;
 }
 
 }  // namespace fp

@@ -80,7 +80,13 @@ STEP_STATS_BYTES = 8 * (len(STEP_STATS_FIELDS) + len(STEP_STATS_FLOATS))
 _lib = None
 EXPORTS = ("mesh_create", "mesh_destroy", "mesh_query", "mesh_emit_faces",
            "locate", "deposit", "poisson_solve", "pic_step", "emission_rate",
-           "pic_last_error")
+           "pic_profile", "pic_profile_read", "pic_last_error")
+KERNEL_CLASSES = ("push", "emit", "inject", "fallback", "solve", "sort",
+                  "clear", "spare")
+
+
+class KernelTimes(C.Structure):
+    _fields_ = [("ms", C.c_double * 8), ("launches", C.c_int64 * 8)]
 
 
 def load_library(path: str = LIB_PATH):
@@ -105,6 +111,8 @@ def load_library(path: str = LIB_PATH):
     L.pic_step.argtypes = [vp, C.POINTER(Particles), C.POINTER(Fields),
                            C.POINTER(StepParams), i32, vp, vp]
     L.emission_rate.argtypes = [vp, vp, dbl, vp, vp, vp]
+    L.pic_profile.argtypes = [vp, i32]
+    L.pic_profile_read.argtypes = [vp, C.POINTER(KernelTimes)]
     L.pic_last_error.restype = C.c_char_p
     for n in EXPORTS:
         if n != "pic_last_error":
@@ -173,6 +181,15 @@ class Mesh:
             self.close()
         except Exception:
             pass
+
+    def profile(self, enable: bool):
+        _check(load_library().pic_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        kt = KernelTimes()
+        _check(load_library().pic_profile_read(self._h, C.byref(kt)))
+        return {n: dict(ms=kt.ms[i], launches=kt.launches[i])
+                for i, n in enumerate(KERNEL_CLASSES) if kt.launches[i]}
 
     def emit_faces(self):
         F = self.n_emit

@@ -177,7 +177,8 @@ def test_emission_rate_matches_oracle(pic):
     assert _rel(F.cpu().numpy(), F_o) < 1e-10
 
 
-def _run_pair(pic, cfg, n_steps, live_charge, n_live, cap, seed=None):
+def _run_pair(pic, cfg, n_steps, live_charge, n_live, cap, seed=None,
+              resort_every=0):
     """live_charge: electrons in flight wanted (None = physical emission)."""
     tip = cfg.mesh()
     om = O.OracleMesh(tip, cfg.emit_zmin)
@@ -196,7 +197,8 @@ def _run_pair(pic, cfg, n_steps, live_charge, n_live, cap, seed=None):
     so_all, sg_all = [], []
     for k in range(n_steps):
         so_all.append(ost.step(step=k, **kw))
-        sg_all.append(pic.State.decode_stats(gs.step(step0=k, **kw))[0])
+        sg_all.append(pic.State.decode_stats(
+            gs.step(step0=k, resort_every=resort_every, **kw))[0])
     torch.cuda.synchronize()
     return om, ost, gm, gs, so_all, sg_all
 
@@ -246,7 +248,8 @@ def test_pic_step_tiny_space_charge(pic):
     """Emission scaled up so that the deposited charge moves the field
     (coupled parity): 8 steps, some particles reach the anode."""
     cfg = W.config_tiny()
-    om, ost, gm, gs, so, sg = _run_pair(pic, cfg, 36, 0.01, 3000, 60_000)
+    om, ost, gm, gs, so, sg = _run_pair(pic, cfg, 36, 0.01, 3000, 60_000,
+                                        resort_every=5)
     # the space charge is visible in the potential
     assert all(s["cg_iters"] > 0 for s in sg[1:])
     assert sum(s["n_anode"] for s in sg) > 0
@@ -257,7 +260,8 @@ def test_pic_step_deterministic(pic):
     cfg = W.config_tiny()
     outs = []
     for _ in range(2):
-        _, _, gm, gs, _, sg = _run_pair(pic, cfg, 4, 0.01, 3000, 60_000)
+        _, _, gm, gs, _, sg = _run_pair(pic, cfg, 8, 0.01, 3000, 60_000,
+                                        resort_every=3)
         P = gs.live()
         outs.append((P, gs.phi.cpu().numpy().copy(), sg))
     (P1, f1, s1), (P2, f2, s2) = outs
@@ -300,3 +304,16 @@ def test_wrap_and_absorption_explicit(pic):
     assert sg["n_anode"] == 1 and sg["n_cathode"] == 1
     assert sg["q_anode"] == 2**40 and sg["q_cathode"] == int(0.75 * 2**40)
     _compare_runs(ost, gs, [so], [sg])
+
+
+def test_resort_compacts_and_orders(pic):
+    """After a re-sort the slots hold exactly the live particles, ordered by
+    tet (ties in the previous slot order), with the particle set unchanged."""
+    cfg = W.config_tiny()
+    _, ost, gm, gs, so, sg = _run_pair(pic, cfg, 6, None, 10_000, 60_000,
+                                       resort_every=6)
+    n = int(gs.n_slots.item())
+    tet = gs.tet[:n].cpu().numpy()
+    assert n == sg[-1]["n_after"] == sg[-1]["n_slots"]
+    assert (tet >= 0).all() and (np.diff(tet) >= 0).all()
+    _compare_runs(ost, gs, so, sg)
