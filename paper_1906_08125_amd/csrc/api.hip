@@ -121,15 +121,9 @@ fp::CgArgs cg_args(const pic_mesh* h, const int64_t* charge, double w_sp,
   return a;
 }
 
-// Enqueue a report of the solver control word into host-mapped memory and
-// return its sequence number; cg_wait spins on the host until it lands.
-hipError_t cg_report(pic_mesh* h, hipStream_t s, int64_t& seq) {
-  seq = ++h->cg_seq;
-  hipError_t e = fp::cg_launch_report(h->cg_ctrl, h->cg_report_dev, seq, s);
-  if (e != hipSuccess) return e;
-  return hipEventRecord(h->rb_event, s);
-}
-
+// Wait (spinning on the host) for the solver report with sequence number seq;
+// the event recorded after the reporting kernel guards against a report that
+// never arrives.
 hipError_t cg_wait(pic_mesh* h, int64_t seq, fp::CgReport& out) {
   for (long spin = 0;; ++spin) {
     if (__atomic_load_n(&h->cg_report_host->seq, __ATOMIC_ACQUIRE) == seq) break;
@@ -156,18 +150,20 @@ hipError_t cg_wait(pic_mesh* h, int64_t seq, fp::CgReport& out) {
 // batches follow (a true-residual re-check when the recursive residual
 // converges), and the field is recomputed at the end.  Blocks the calling
 // thread at the waits.  Returns the iterations done.
-hipError_t run_solve(pic_mesh* h, const fp::CgArgs& a, int spec, hipStream_t s,
+hipError_t run_solve(pic_mesh* h, const fp::CgArgs& a0, int spec, hipStream_t s,
                      int64_t* iters_out) {
-  hipError_t e = fp::cg_launch_begin(a, s);
+  fp::CgArgs a = a0;
+  a.report = h->cg_report_dev;
+  int64_t seq = ++h->cg_seq;
+  hipError_t e = fp::cg_launch_begin(a, spec > 0 ? 0 : seq, s);
   if (e != hipSuccess) return e;
   int it = 0;
   int batch = spec;
   if (batch > 0) {
-    if ((e = fp::cg_launch_iters(a, it, batch, s)) != hipSuccess) return e;
+    if ((e = fp::cg_launch_iters(a, it, batch, seq, s)) != hipSuccess) return e;
     it += batch;
   }
-  int64_t seq;
-  if ((e = cg_report(h, s, seq)) != hipSuccess) return e;
+  if ((e = hipEventRecord(h->rb_event, s)) != hipSuccess) return e;
   if ((e = fp::cg_launch_field(a, s)) != hipSuccess) return e;
   fp::CgReport r;
   if ((e = cg_wait(h, seq, r)) != hipSuccess) return e;
@@ -175,16 +171,17 @@ hipError_t run_solve(pic_mesh* h, const fp::CgArgs& a, int spec, hipStream_t s,
   for (int guard = 0; guard < (1 << 20); ++guard) {
     if (r.state == fp::CG_DONE || r.state == fp::CG_NOCONV) break;
     extra = true;
+    seq = ++h->cg_seq;
     if (r.state == fp::CG_RECHECK) {
-      if ((e = fp::cg_launch_recheck(a, s)) != hipSuccess) return e;
+      if ((e = fp::cg_launch_recheck(a, seq, s)) != hipSuccess) return e;
       it = 0;  // a restart (if any) begins from the true residual
       batch = 16;
     } else {
       batch = batch < 8 ? 8 : std::min(2 * batch, 256);
-      if ((e = fp::cg_launch_iters(a, it, batch, s)) != hipSuccess) return e;
+      if ((e = fp::cg_launch_iters(a, it, batch, seq, s)) != hipSuccess) return e;
       it += batch;
     }
-    if ((e = cg_report(h, s, seq)) != hipSuccess) return e;
+    if ((e = hipEventRecord(h->rb_event, s)) != hipSuccess) return e;
     if ((e = cg_wait(h, seq, r)) != hipSuccess) return e;
   }
   if (iters_out) *iters_out = r.iters;
@@ -473,6 +470,7 @@ pic_status pic_step(pic_mesh* h, const pic_particles* P, const pic_fields* F,
   const int grid_inj = h->grid_inj;
   const int grid_fb = h->grid_fb;
   a.acc_rows = h->acc_rows;
+  a.acc_stride = grid_push + grid_inj + grid_fb;
   for (int32_t k = 0; k < n_steps; ++k) {
     const int64_t step = prm->step0 + k;
     pic_step_stats* st = stats + k;
@@ -481,21 +479,15 @@ pic_status pic_step(pic_mesh* h, const pic_particles* P, const pic_fields* F,
     ea.step = step;
     ea.stats = st;
     ca.step_stats = st;
-    prof_begin(h, PIC_K_CLEAR, s);
-    if ((e = fp::launch_clear(F->charge, h->dm.n_nodes, st, h->scratch,
-                              h->n_cu * 2, s)) != hipSuccess)
-      return hip_fail(e, "pic_step clear");
+    // clears + emission counts, then live and new particles in one launch
+    prof_begin(h, PIC_K_EMIT, s);
+    if ((e = fp::launch_begin(ea, F->charge, h->dm.n_nodes, h->n_cu * 2, s)) != hipSuccess)
+      return hip_fail(e, "pic_step begin");
     prof_end(h, s);
     prof_begin(h, PIC_K_PUSH, s);
     a.acc_row0 = 0;
-    if ((e = fp::launch_push(a, grid_push, s)) != hipSuccess) return hip_fail(e, "pic_step push");
-    prof_end(h, s);
-    prof_begin(h, PIC_K_EMIT, s);
-    if ((e = fp::launch_emit(ea, s)) != hipSuccess) return hip_fail(e, "pic_step emit");
-    prof_end(h, s);
-    prof_begin(h, PIC_K_INJECT, s);
-    a.acc_row0 = grid_push;
-    if ((e = fp::launch_inject(a, grid_inj, s)) != hipSuccess) return hip_fail(e, "pic_step inject");
+    if ((e = fp::launch_particles(a, grid_push, grid_inj, s)) != hipSuccess)
+      return hip_fail(e, "pic_step particles");
     prof_end(h, s);
     prof_begin(h, PIC_K_FALLBACK, s);
     a.acc_row0 = grid_push + grid_inj;

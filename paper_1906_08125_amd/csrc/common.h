@@ -24,6 +24,7 @@ struct Phys {
 };
 Phys phys_constants();  // host
 
+constexpr int kSell = 64;                     // rows per sliced-ELL slice
 constexpr double kFx = 1099511627776.0;       // 2^40
 constexpr double kFxInv = 1.0 / 1099511627776.0;
 
@@ -61,6 +62,16 @@ struct DevMesh {
   const double* g_unit;      // Neumann load per unit E0 [n_free]
   const int32_t* free2node;  // [n_free]
   const int32_t* node2free;  // [n_nodes], -1 for Dirichlet
+  // the same two operators in sliced ELLPACK (kSell rows per slice)
+  int64_t k_nslices, f_nslices, f_np;
+  const int32_t* k_sptr;   // [k_nslices + 1] slice offsets
+  const int32_t* k_scol;
+  const double* k_sval;
+  const float* k_sval32;
+  const int32_t* f_sptr;
+  const int32_t* f_scol;
+  const double* f_sval;    // [3][f_np]
+  const float* f_sval32;   // [3][f_np]
   // nodal field operator: rows all nodes, columns free indices
   const int32_t* frow;
   const int32_t* fcol;
@@ -77,6 +88,12 @@ struct DevMesh {
   const int32_t* bstart;     // [nbx*nby*nbz + 1]
   const int32_t* bitem;
   const int32_t* bseed;      // [nbx*nby*nbz] walk seed per bucket or -1
+  // walk seeds on a grid twice as fine: the tet holding each sub-cell
+  // centre (or the coarse seed where the centre is in the metal)
+  int32_t fnb[3];
+  double finv[3];
+  int32_t* fseed;            // [fnb_x*fnb_y*fnb_z]
+  double jump_len2;          // displacements beyond this start at the seed
 };
 
 // ---------------------------------------------------------------------------

@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "mesh.h"
+#include "particles.h"
 #include "solver.h"
 
 namespace fp {
@@ -313,6 +314,43 @@ pic_status build_mesh(const pic_mesh_desc* d, pic_mesh* h, std::string& msg) {
     msg = "mesh_create: matrix too large for 32-bit row pointers";
     return PIC_E_ARG;
   }
+  // sliced ELLPACK copies (slices of kSell rows, column-major inside a
+  // slice): lane r of a wave reads entry j of row r at sptr[s] + j kSell + r,
+  // so every load of a wave is one contiguous run.  Padding entries have
+  // value 0 and a valid column.
+  auto to_sell = [&](const std::vector<int32_t>& rp, const std::vector<int32_t>& cl,
+                     const std::vector<const std::vector<double>*>& vs, int64_t nrows,
+                     int32_t pad_col, std::vector<int32_t>& sptr,
+                     std::vector<int32_t>& scol, std::vector<double>& sval) {
+    const int64_t ns = (nrows + kSell - 1) / kSell;
+    sptr.assign(ns + 1, 0);
+    for (int64_t s = 0; s < ns; ++s) {
+      int32_t w = 0;
+      for (int64_t r = s * kSell; r < std::min<int64_t>(nrows, (s + 1) * kSell); ++r)
+        w = std::max(w, rp[r + 1] - rp[r]);
+      sptr[s + 1] = sptr[s] + w * kSell;
+    }
+    const int64_t np = sptr[ns];
+    scol.assign(np, pad_col);
+    sval.assign(np * vs.size(), 0.0);
+    for (int64_t s = 0; s < ns; ++s)
+      for (int64_t r = s * kSell; r < std::min<int64_t>(nrows, (s + 1) * kSell); ++r)
+        for (int32_t k = rp[r]; k < rp[r + 1]; ++k) {
+          const int64_t p = sptr[s] + (int64_t)(k - rp[r]) * kSell + (r - s * kSell);
+          scol[p] = cl[k];
+          for (size_t q = 0; q < vs.size(); ++q) sval[q * np + p] = (*vs[q])[k];
+        }
+    return np;
+  };
+  std::vector<int32_t> k_sptr, k_scol, f_sptr, f_scol;
+  std::vector<double> k_sval, f_sval;
+  const int64_t k_np = to_sell(rowptr, col, {&val}, NF, 0, k_sptr, k_scol, k_sval);
+  const int64_t f_np = to_sell(frow, fcol, {&fv[0], &fv[1], &fv[2]}, N, 0, f_sptr,
+                               f_scol, f_sval);
+  if (k_np >= (1ll << 31) || f_np >= (1ll << 31)) {
+    msg = "mesh_create: padded matrix too large for 32-bit offsets";
+    return PIC_E_ARG;
+  }
   // 6. Neumann load per unit E0 on the top plane
   for (int64_t t = 0; t < T; ++t)
     for (int f = 0; f < 4; ++f) {
@@ -442,6 +480,22 @@ pic_status build_mesh(const pic_mesh_desc* d, pic_mesh* h, std::string& msg) {
   M.bstart = upload(h, bstart, err);
   M.bitem = upload(h, bitem, err);
   {
+    std::vector<float> k_sval32(k_sval.begin(), k_sval.end());
+    std::vector<float> f_sval32(f_sval.begin(), f_sval.end());
+    M.k_nslices = (int64_t)k_sptr.size() - 1;
+    M.k_sptr = upload(h, k_sptr, err);
+    M.k_scol = upload(h, k_scol, err);
+    M.k_sval = upload(h, k_sval, err);
+    M.k_sval32 = upload(h, k_sval32, err);
+    M.f_nslices = (int64_t)f_sptr.size() - 1;
+    M.f_np = f_np;
+    M.f_sptr = upload(h, f_sptr, err);
+    M.f_scol = upload(h, f_scol, err);
+    M.f_sval = upload(h, f_sval, err);
+    M.f_sval32 = upload(h, f_sval32, err);
+    (void)k_np;
+  }
+  {
     // walk seeds: lowest-index tet whose centroid lies in each bucket
     std::vector<int32_t> bseed(NB, -1);
     for (int64_t t = 0; t < T; ++t) {
@@ -488,6 +542,16 @@ pic_status build_mesh(const pic_mesh_desc* d, pic_mesh* h, std::string& msg) {
   h->counts = (int32_t*)dev_alloc(h, sizeof(int32_t) * (size_t)(M.n_emit + 1), err);
   h->solve_stats = (pic_solve_stats*)dev_alloc(h, sizeof(pic_solve_stats), err);
   h->locate_count = (int32_t*)dev_alloc(h, sizeof(int32_t), err);
+  // fine walk seeds, located on the device with the exact canonical scan
+  for (int k = 0; k < 3; ++k) {
+    M.fnb[k] = 2 * M.nb[k];
+    M.finv[k] = 2.0 * M.binv[k];
+  }
+  M.jump_len2 = (0.25 * edge) * (0.25 * edge);
+  M.fseed = (int32_t*)dev_alloc(
+      h, sizeof(int32_t) * (size_t)M.fnb[0] * M.fnb[1] * M.fnb[2], err);
+  if (err == hipSuccess) err = launch_seed_build(M, std::max(8, h->n_cu * 8), nullptr);
+  if (err == hipSuccess) err = hipDeviceSynchronize();
   h->grid_push = std::max(8, h->n_cu * 8);
   h->grid_inj = std::max(8, h->n_cu * 2);
   h->grid_fb = 64;

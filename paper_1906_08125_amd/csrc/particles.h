@@ -25,6 +25,7 @@ struct StepArgs {
   pic_step_stats* stats;
   int64_t* acc_rows;    // [rows][kAccFields] per-block counters
   int acc_row0;         // first row of this kernel
+  int acc_stride;       // rows of all kernels (field-major layout)
   double Q, dt, qm_dt;
   uint64_t seed;
   uint64_t instance;
@@ -66,13 +67,14 @@ struct DepositArgs {
   int64_t* charge;
 };
 
-hipError_t launch_clear(int64_t* charge, int64_t n, pic_step_stats* st,
-                        StepScratch* sc, int grid, hipStream_t s);
+hipError_t launch_begin(const EmitArgs& a, int64_t* charge, int64_t n_nodes,
+                        int grid, hipStream_t s);
+hipError_t launch_particles(const StepArgs& a, int g_push, int g_inj,
+                            hipStream_t s);
 hipError_t launch_stats(const int64_t* rows, int n_rows, pic_step_stats* st,
                         hipStream_t s);
-hipError_t launch_push(const StepArgs& a, int grid, hipStream_t s);
+hipError_t launch_seed_build(const DevMesh& m, int grid, hipStream_t s);
 hipError_t launch_emit(const EmitArgs& a, hipStream_t s);
-hipError_t launch_inject(const StepArgs& a, int grid, hipStream_t s);
 hipError_t launch_fallback(const StepArgs& a, int grid, hipStream_t s);
 hipError_t launch_locate(const LocateArgs& a, int grid, hipStream_t s);
 hipError_t launch_deposit(const DepositArgs& a, int grid, hipStream_t s);

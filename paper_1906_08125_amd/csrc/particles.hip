@@ -23,10 +23,8 @@ struct Span {
   int64_t lo, hi;
 };
 
-// contiguous, XCD-grouped slot span of this block
-__device__ inline Span block_span(int64_t n) {
-  const int G = gridDim.x;
-  const int g = blockIdx.x;
+// contiguous, XCD-grouped slot span of workgroup g of G
+__device__ inline Span block_span(int64_t n, int G, int g) {
   int chunk = g;
   if ((G & 7) == 0) chunk = (g & 7) * (G >> 3) + (g >> 3);
   const int64_t per = (n + G - 1) / G;
@@ -65,7 +63,8 @@ __device__ inline int wave_max(int v) {
 // Block totals of the counters written to this block's row of the partials
 // (no atomics: thousands of same-address atomics per step serialize); the
 // stats kernel sums the rows at the end of the step.
-__device__ inline void acc_flush(const Acc& a, int64_t* rows, int row) {
+__device__ inline void acc_flush(const Acc& a, int64_t* rows, int row,
+                                 int stride) {
   __shared__ long long lds[kAccFields][kBlock / 64];
   const long long v[kAccFields] = {a.n_before, a.q_before, a.n_anode,
                                    a.q_anode,  a.n_after,  a.q_after,
@@ -88,7 +87,7 @@ __device__ inline void acc_flush(const Acc& a, int64_t* rows, int row) {
     long long s = 0;
     for (int w = 0; w < (int)(blockDim.x >> 6); ++w)
       s = k == kAccFields - 1 ? (lds[k][w] > s ? lds[k][w] : s) : s + lds[k][w];
-    rows[(int64_t)row * kAccFields + k] = s;
+    rows[(int64_t)k * stride + row] = s;  // field-major: coalesced sums
   }
 }
 
@@ -137,19 +136,34 @@ __device__ inline int bucket_guess(const DevMesh& m, double x, double y,
   return m.bseed[id];
 }
 
+// The fine-grid seed of p (the tet holding the centre of p's sub-cell).
+__device__ inline int fine_seed(const DevMesh& m, double x, double y,
+                                double z) {
+  if (!(x >= m.b0[0] && x <= m.b1[0] && y >= m.b0[1] && y <= m.b1[1] &&
+        z >= m.b0[2] && z <= m.b1[2]))
+    return -1;
+  const int bx = bucket_axis(x, m.b0[0], m.finv[0], m.fnb[0]);
+  const int by = bucket_axis(y, m.b0[1], m.finv[1], m.fnb[1]);
+  const int bz = bucket_axis(z, m.b0[2], m.finv[2], m.fnb[2]);
+  return m.fseed[((int64_t)bx * m.fnb[1] + by) * m.fnb[2] + bz];
+}
+
 // Neighbour walk from tet t with the point's frame offset (sx, sy) relative
-// to t; after two tets without success it restarts from a tet of the
-// point's bucket.  Returns the tet when the point is certified strictly
-// inside it in its own frame (then no other tet holds it, so it is the
-// canonical answer), or -1 when the exact bucket scan must decide.
+// to t.  A point that moved far (far = true), or is not in t, restarts from
+// the fine-grid seed of its sub-cell.  Returns the tet when the point is
+// certified strictly inside it in its own frame (then no other tet holds
+// it, so it is the canonical answer), or -1 when the exact bucket scan must
+// decide.
 __device__ inline int walk(const DevMesh& m, double x, double y, double z,
-                           int t, int sx, int sy, int& steps) {
+                           int t, int sx, int sy, int& steps,
+                           bool far = false) {
   bool jumped = false;
   for (steps = 0; steps < kMaxWalk; ++steps) {
-    if (steps == 2 && !jumped) {
+    if (!jumped && (far || steps == 1)) {
       jumped = true;
-      const int g = bucket_guess(m, x, y, z);
-      if (g >= 0) {
+      int g = fine_seed(m, x, y, z);
+      if (g < 0) g = bucket_guess(m, x, y, z);
+      if (g >= 0 && !(g == t && sx == 0 && sy == 0)) {
         t = g;
         sx = 0;
         sy = 0;
@@ -271,7 +285,7 @@ __device__ inline void deposit_table(const TetGeom& g, double x, double y,
 __device__ inline void settle(const DevMesh& m, const StepArgs& a, int64_t i,
                               double x, double y, double z, int sx, int sy,
                               int hint, double w, long long qfx, Acc& acc,
-                              ChargeTable& T) {
+                              ChargeTable& T, bool far) {
   if (z >= m.z_top) {
     a.tet[i] = -1;
     acc.n_anode += 1;
@@ -279,7 +293,7 @@ __device__ inline void settle(const DevMesh& m, const StepArgs& a, int64_t i,
     return;
   }
   int steps = 0;
-  const int t = walk(m, x, y, z, hint, sx, sy, steps);
+  const int t = walk(m, x, y, z, hint, sx, sy, steps, far);
   acc.walk_steps += steps;
   if (steps > acc.walk_max) acc.walk_max = steps;
   if (t >= 0) {
@@ -316,58 +330,6 @@ __device__ inline void wrap(const DevMesh& m, double& x, double& y, int& sx,
 
 }  // namespace
 
-// ---------------------------------------------------------------------------
-// Live particles: gather E_k, kick (v + QE) + QE, drift, wrap, absorb,
-// walk, deposit.
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlock) k_push(StepArgs a) {
-  const DevMesh& m = a.m;
-  const int64_t n = *a.n_slots;
-  const Span sp = block_span(n);
-  Acc acc;
-  acc_zero(acc);
-  __shared__ ChargeTable T;
-  table_clear(T);
-  const double Q = a.Q;
-  const double dt = a.dt;
-  for (int64_t i = sp.lo + threadIdx.x; i < sp.hi; i += blockDim.x) {
-    const int t = a.tet[i];
-    if (t < 0) continue;
-    const double w = a.w[i];
-    const long long qfx = fx_round(w * kFx);
-    acc.n_before += 1;
-    acc.q_before += qfx;
-    double x = a.x[i], y = a.y[i], z = a.z[i];
-    double vx = a.vx[i], vy = a.vy[i], vz = a.vz[i];
-    double ex, ey, ez;
-    gather_field(m.tg[t], a.E, x, y, z, ex, ey, ez);
-    const double qx = Q * ex, qy = Q * ey, qz = Q * ez;
-    vx = (vx + qx) + qx;
-    vy = (vy + qy) + qy;
-    vz = (vz + qz) + qz;
-    x = x + dt * vx;
-    y = y + dt * vy;
-    z = z + dt * vz;
-    int sx, sy;
-    wrap(m, x, y, sx, sy);
-    a.x[i] = x;
-    a.y[i] = y;
-    a.z[i] = z;
-    a.vx[i] = vx;
-    a.vy[i] = vy;
-    a.vz[i] = vz;
-    settle(m, a, i, x, y, z, sx, sy, t, w, qfx, acc, T);
-  }
-  table_flush(T, a.charge);
-  acc_flush(acc, a.acc_rows, a.acc_row0 + blockIdx.x);
-}
-
-// ---------------------------------------------------------------------------
-// Emission counts: one workgroup over all emitting faces.  Per face the
-// centroid field ((E_a + E_b) + E_c)/3, the FN current when the field pulls
-// electrons out of the metal, Eq. nsp and the rounding of Eq. rnd_nsp; an
-// exclusive scan of the counts gives every new particle its slot.
-// ---------------------------------------------------------------------------
 __device__ inline double fn_current(double F, double phi, const EmitConsts& c,
                                     int& clamped) {
   if (!(F > 1e-3)) return 0.0;
@@ -395,18 +357,24 @@ __device__ inline void face_field(const DevMesh& m, const double* E, int64_t f,
   ez = ((a.z + b.z) + c.z) / 3.0;
 }
 
-constexpr int kEmitBlock = 1024;
 
-__global__ void __launch_bounds__(kEmitBlock) k_emit(EmitArgs a) {
+// ---------------------------------------------------------------------------
+// Emission counts (one workgroup): per emitting face the centroid field
+// ((E_a + E_b) + E_c)/3, the FN current when the field pulls electrons out of
+// the metal, Eq. nsp and the rounding of Eq. rnd_nsp; an exclusive scan of
+// the counts gives every new particle its slot.
+// ---------------------------------------------------------------------------
+template <int NT>
+__device__ void emit_block(const EmitArgs& a) {
   const DevMesh& m = a.m;
-  __shared__ long long s_scan[kEmitBlock];
-  __shared__ double s_red[3][kEmitBlock / 64];
-  __shared__ long long s_cl[kEmitBlock / 64];
+  __shared__ long long s_scan[NT / 64];
+  __shared__ double s_red[3][NT / 64];
+  __shared__ long long s_cl[NT / 64];
   long long offset = 0;
   double cur_sum = 0.0, F_sum = 0.0, F_max = 0.0;
   long long n_clamp = 0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int64_t f0 = 0; f0 < m.n_emit; f0 += kEmitBlock) {
+  for (int64_t f0 = 0; f0 < m.n_emit; f0 += NT) {
     const int64_t f = f0 + threadIdx.x;
     long long cnt = 0;
     double cur = 0.0, F = 0.0;
@@ -435,20 +403,14 @@ __global__ void __launch_bounds__(kEmitBlock) k_emit(EmitArgs a) {
       }
       if (a.face_F) a.face_F[f] = F;
     }
-    // exclusive scan of the counts (Hillis-Steele in LDS)
-    s_scan[threadIdx.x] = cnt;
-    __syncthreads();
-    for (int off = 1; off < kEmitBlock; off <<= 1) {
-      const long long v = threadIdx.x >= off ? s_scan[threadIdx.x - off] : 0;
-      __syncthreads();
-      s_scan[threadIdx.x] += v;
-      __syncthreads();
+    // exclusive scan of the counts: shuffle scan per wave, then waves
+    long long inc = cnt;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const long long o = __shfl_up(inc, off, 64);
+      if (lane >= off) inc += o;
     }
-    if (f < m.n_emit && a.counts) {
-      a.counts[f] = (int32_t)cnt;
-      a.offsets[f] = (int32_t)(offset + s_scan[threadIdx.x] - cnt);
-    }
-    offset += s_scan[kEmitBlock - 1];
+    if (lane == 63) s_scan[wave] = inc;
     // sums of current and |E|, max |E|, clamp count (fixed order)
     double v0 = cur, v1 = F, v2 = F;
     long long vc = clamped;
@@ -466,12 +428,20 @@ __global__ void __launch_bounds__(kEmitBlock) k_emit(EmitArgs a) {
       s_cl[wave] = vc;
     }
     __syncthreads();
-    for (int w = 0; w < kEmitBlock / 64; ++w) {
+    long long before = 0, chunk = 0;
+    for (int w = 0; w < NT / 64; ++w) {
+      if (w < wave) before += s_scan[w];
+      chunk += s_scan[w];
       cur_sum += s_red[0][w];
       F_sum += s_red[1][w];
       F_max = s_red[2][w] > F_max ? s_red[2][w] : F_max;
       n_clamp += s_cl[w];
     }
+    if (f < m.n_emit && a.counts) {
+      a.counts[f] = (int32_t)cnt;
+      a.offsets[f] = (int32_t)(offset + before + inc - cnt);
+    }
+    offset += chunk;
     __syncthreads();
   }
   if (threadIdx.x == 0) {
@@ -502,21 +472,90 @@ __global__ void __launch_bounds__(kEmitBlock) k_emit(EmitArgs a) {
   }
 }
 
+constexpr int kBeginBlock = 1024;
+
+__global__ void __launch_bounds__(kBlock) k_emit(EmitArgs a) {
+  emit_block<kBlock>(a);
+}
+
+// Start of a step: workgroup 0 clears the step's stats and counters and
+// computes the emission counts; the others clear the node charges.
+__global__ void __launch_bounds__(kBeginBlock) k_begin(EmitArgs a,
+                                                       int64_t* charge,
+                                                       int64_t n_nodes) {
+  if (blockIdx.x == 0) {  // dispatched first: the emission path is the longest
+    int64_t* s64 = reinterpret_cast<int64_t*>(a.stats);
+    const int ns = (int)(sizeof(pic_step_stats) / sizeof(int64_t));
+    if (threadIdx.x < ns) s64[threadIdx.x] = 0;
+    int32_t* c32 = reinterpret_cast<int32_t*>(a.scratch);
+    const int nc = (int)(sizeof(StepScratch) / sizeof(int32_t));
+    if (threadIdx.x < nc) c32[threadIdx.x] = 0;
+    __syncthreads();
+    emit_block<kBeginBlock>(a);
+    return;
+  }
+  const int64_t G = gridDim.x - 1;
+  for (int64_t i = (blockIdx.x - 1) * (int64_t)blockDim.x + threadIdx.x;
+       i < n_nodes; i += G * blockDim.x)
+    charge[i] = 0;
+}
+
 // ---------------------------------------------------------------------------
-// Injection (Sec. II B 3, App. E): one thread per new particle.
+// The particle kernel of a step.  Workgroups [0, g_push) advance the live
+// particles (gather E_k, kick (v + QE) + QE, drift, wrap, absorb, walk,
+// deposit); the remaining workgroups inject the new ones (Sec. II B 3,
+// App. E: sample the face, Eq. sp_velocity, Eq. sp_displacement, drift,
+// wrap, absorb, walk, deposit).  Both halves only read the slots below the
+// pre-injection count, so they run side by side.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlock) k_inject(StepArgs a) {
+__device__ inline void push_role(const StepArgs& a, int g, int G, Acc& acc,
+                                 ChargeTable& T) {
+  const DevMesh& m = a.m;
+  const int64_t n = a.scratch->inj_base;
+  const Span sp = block_span(n, G, g);
+  const double Q = a.Q;
+  const double dt = a.dt;
+  for (int64_t i = sp.lo + threadIdx.x; i < sp.hi; i += blockDim.x) {
+    const int t = a.tet[i];
+    if (t < 0) continue;
+    const double w = a.w[i];
+    const long long qfx = fx_round(w * kFx);
+    acc.n_before += 1;
+    acc.q_before += qfx;
+    double x = a.x[i], y = a.y[i], z = a.z[i];
+    double vx = a.vx[i], vy = a.vy[i], vz = a.vz[i];
+    double ex, ey, ez;
+    gather_field(m.tg[t], a.E, x, y, z, ex, ey, ez);
+    const double qx = Q * ex, qy = Q * ey, qz = Q * ez;
+    vx = (vx + qx) + qx;
+    vy = (vy + qy) + qy;
+    vz = (vz + qz) + qz;
+    const double dx = dt * vx, dy = dt * vy, dz = dt * vz;
+    const bool far = (dx * dx + dy * dy) + dz * dz > m.jump_len2;
+    x = x + dx;
+    y = y + dy;
+    z = z + dz;
+    int sx, sy;
+    wrap(m, x, y, sx, sy);
+    a.x[i] = x;
+    a.y[i] = y;
+    a.z[i] = z;
+    a.vx[i] = vx;
+    a.vy[i] = vy;
+    a.vz[i] = vz;
+    settle(m, a, i, x, y, z, sx, sy, t, w, qfx, acc, T, far);
+  }
+}
+
+__device__ inline void inject_role(const StepArgs& a, int g, int G, Acc& acc,
+                                   ChargeTable& T) {
   const DevMesh& m = a.m;
   const int64_t n = a.scratch->inj_fit;
   const int64_t base = a.scratch->inj_base;
-  Acc acc;
-  acc_zero(acc);
-  __shared__ ChargeTable T;
-  table_clear(T);
   const double dt = a.dt;
   const int32_t* off = a.offsets;
-  for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
-       s += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t s = g * (int64_t)blockDim.x + threadIdx.x; s < n;
+       s += (int64_t)G * blockDim.x) {
     // face: last f with off[f] <= s
     int lo = 0, hi = (int)m.n_emit - 1;
     while (lo < hi) {
@@ -570,10 +609,21 @@ __global__ void __launch_bounds__(kBlock) k_inject(StepArgs a) {
     a.id[i] = (a.step << 42) | ((int64_t)f << 21) | o;
     acc.n_inj += 1;
     acc.q_inj += qfx;
-    settle(m, a, i, x, y, z, sx, sy, m.e_tet[f], w, qfx, acc, T);
+    settle(m, a, i, x, y, z, sx, sy, m.e_tet[f], w, qfx, acc, T, false);
   }
+}
+
+__global__ void __launch_bounds__(kBlock) k_particles(StepArgs a, int g_push) {
+  Acc acc;
+  acc_zero(acc);
+  __shared__ ChargeTable T;
+  table_clear(T);
+  if ((int)blockIdx.x < g_push)
+    push_role(a, blockIdx.x, g_push, acc, T);
+  else
+    inject_role(a, blockIdx.x - g_push, gridDim.x - g_push, acc, T);
   table_flush(T, a.charge);
-  acc_flush(acc, a.acc_rows, a.acc_row0 + blockIdx.x);
+  acc_flush(acc, a.acc_rows, a.acc_row0 + blockIdx.x, a.acc_stride);
 }
 
 // ---------------------------------------------------------------------------
@@ -603,27 +653,36 @@ __global__ void __launch_bounds__(kBlock) k_fallback(StepArgs a) {
       acc.q_cathode += qfx;
     }
   }
-  acc_flush(acc, a.acc_rows, a.acc_row0 + blockIdx.x);
+  acc_flush(acc, a.acc_rows, a.acc_row0 + blockIdx.x, a.acc_stride);
   if (blockIdx.x == 0 && threadIdx.x == 0) a.stats->n_fallback = n;
 }
 
-// Sum of the counter rows of one step into its stats.
-__global__ void __launch_bounds__(kAccFields * 64) k_stats(const int64_t* rows,
-                                                          int n_rows,
-                                                          pic_step_stats* st) {
-  const int k = threadIdx.x >> 6, lane = threadIdx.x & 63;
+// Sum of the counter rows of one step into its stats: one workgroup per
+// counter, a fixed-order tree inside the workgroup.
+__global__ void __launch_bounds__(kBlock) k_stats(const int64_t* rows,
+                                                  int n_rows,
+                                                  pic_step_stats* st) {
+  __shared__ long long lds[kBlock / 64];
+  const int k = blockIdx.x;
+  const bool is_max = k == kAccFields - 1;
   long long s = 0;
-  for (int r = lane; r < n_rows; r += 64) {
-    const long long v = rows[(int64_t)r * kAccFields + k];
-    s = k == kAccFields - 1 ? (v > s ? v : s) : s + v;
+  for (int r = threadIdx.x; r < n_rows; r += blockDim.x) {
+    const long long v = rows[(int64_t)k * n_rows + r];
+    s = is_max ? (v > s ? v : s) : s + v;
   }
-  s = k == kAccFields - 1 ? (long long)wave_max((int)s) : wave_sum(s);
-  if (lane == 0) {
+  s = is_max ? (long long)wave_max((int)s) : wave_sum(s);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) lds[wave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long t = 0;
+    for (int w = 0; w < kBlock / 64; ++w)
+      t = is_max ? (lds[w] > t ? lds[w] : t) : t + lds[w];
     int64_t* dst[kAccFields] = {&st->n_before, &st->q_before, &st->n_anode,
                                 &st->q_anode,  &st->n_after,  &st->q_after,
                                 &st->n_cathode, &st->q_cathode, &st->n_inj,
                                 &st->q_inj,    &st->walk_steps, &st->walk_max};
-    *dst[k] = s;
+    *dst[k] = t;
   }
 }
 
@@ -675,47 +734,51 @@ __global__ void __launch_bounds__(kBlock) k_deposit(DepositArgs a) {
   }
 }
 
-// Per-step clears: node charges, the step's stats and counters.
-__global__ void __launch_bounds__(kBlock) k_clear(int64_t* charge, int64_t n,
-                                                  pic_step_stats* st,
-                                                  StepScratch* sc) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    charge[i] = 0;
-  if (blockIdx.x == 0) {
-    int64_t* s64 = reinterpret_cast<int64_t*>(st);
-    const int ns = (int)(sizeof(pic_step_stats) / sizeof(int64_t));
-    if (threadIdx.x < ns) s64[threadIdx.x] = 0;
-    int32_t* c32 = reinterpret_cast<int32_t*>(sc);
-    const int nc = (int)(sizeof(StepScratch) / sizeof(int32_t));
-    if (threadIdx.x < nc) c32[threadIdx.x] = 0;
+// Fine walk seeds: the canonical tet of every sub-cell centre (exact scan),
+// or the coarse seed where the centre lies in the metal.
+__global__ void __launch_bounds__(kBlock) k_seed_build(DevMesh m) {
+  const int64_t n = (int64_t)m.fnb[0] * m.fnb[1] * m.fnb[2];
+  for (int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; id < n;
+       id += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t iz = id % m.fnb[2];
+    const int64_t iy = (id / m.fnb[2]) % m.fnb[1];
+    const int64_t ix = id / ((int64_t)m.fnb[2] * m.fnb[1]);
+    const double x = m.b0[0] + ((double)ix + 0.5) / m.finv[0];
+    const double y = m.b0[1] + ((double)iy + 0.5) / m.finv[1];
+    const double z = m.b0[2] + ((double)iz + 0.5) / m.finv[2];
+    int t = scan_locate(m, x, y, z);
+    if (t < 0) t = bucket_guess(m, x, y, z);
+    m.fseed[id] = t;
   }
 }
+
 
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_clear(int64_t* charge, int64_t n, pic_step_stats* st,
-                        StepScratch* sc, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_clear, dim3(grid), dim3(kBlock), 0, s, charge, n, st, sc);
+hipError_t launch_begin(const EmitArgs& a, int64_t* charge, int64_t n_nodes,
+                        int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_begin, dim3(grid + 1), dim3(kBeginBlock), 0, s, a, charge,
+                     n_nodes);
+  return hipGetLastError();
+}
+hipError_t launch_particles(const StepArgs& a, int g_push, int g_inj,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_particles, dim3(g_push + g_inj), dim3(kBlock), 0, s, a,
+                     g_push);
+  return hipGetLastError();
+}
+hipError_t launch_seed_build(const DevMesh& m, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_seed_build, dim3(grid), dim3(kBlock), 0, s, m);
   return hipGetLastError();
 }
 hipError_t launch_stats(const int64_t* rows, int n_rows, pic_step_stats* st,
                         hipStream_t s) {
-  hipLaunchKernelGGL(k_stats, dim3(1), dim3(kAccFields * 64), 0, s, rows, n_rows, st);
-  return hipGetLastError();
-}
-
-hipError_t launch_push(const StepArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_push, dim3(grid), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(k_stats, dim3(kAccFields), dim3(kBlock), 0, s, rows, n_rows, st);
   return hipGetLastError();
 }
 hipError_t launch_emit(const EmitArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_emit, dim3(1), dim3(kEmitBlock), 0, s, a);
-  return hipGetLastError();
-}
-hipError_t launch_inject(const StepArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_inject, dim3(grid), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(k_emit, dim3(1), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 hipError_t launch_fallback(const StepArgs& a, int grid, hipStream_t s) {

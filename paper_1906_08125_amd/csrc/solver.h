@@ -18,6 +18,14 @@ struct CgCtrl {
   double alpha[2], gamma[2];
 };
 
+// Host-visible report of the control word (pinned, device-mapped memory).
+struct CgReport {
+  int64_t seq;     // written last; the host waits for its value
+  int32_t state;
+  int32_t pad;
+  int64_t iters;
+};
+
 constexpr int kCgBlock = 512;
 constexpr int kCgSlots = 10;
 
@@ -34,25 +42,19 @@ struct CgArgs {
   double* part;           // [kCgSlots][G]
   int G;                  // workgroups of every solver kernel
   CgCtrl* ctrl;
+  CgReport* report;       // host-mapped report record (device address)
   const int32_t* dir_nodes;
   int64_t n_dir;
   pic_solve_stats* stats;      // or null
   pic_step_stats* step_stats;  // or null
 };
 
-// Host-visible report of the control word (pinned, device-mapped memory).
-struct CgReport {
-  int64_t seq;     // written last; the host waits for its value
-  int32_t state;
-  int32_t pad;
-  int64_t iters;
-};
-
-hipError_t cg_launch_report(CgCtrl* ctrl, CgReport* host_mapped, int64_t seq,
-                            hipStream_t s);
-hipError_t cg_launch_begin(const CgArgs& a, hipStream_t s);
-hipError_t cg_launch_iters(const CgArgs& a, int it0, int n, hipStream_t s);
-hipError_t cg_launch_recheck(const CgArgs& a, hipStream_t s);
+// seq != 0: the last kernel of the launch writes the state with this
+// sequence number into args.report (host-mapped).
+hipError_t cg_launch_begin(const CgArgs& a, int64_t seq, hipStream_t s);
+hipError_t cg_launch_iters(const CgArgs& a, int it0, int n, int64_t seq,
+                           hipStream_t s);
+hipError_t cg_launch_recheck(const CgArgs& a, int64_t seq, hipStream_t s);
 hipError_t cg_launch_field(const CgArgs& a, hipStream_t s);
 
 }  // namespace fp

@@ -5,7 +5,9 @@
 //
 // The solve is a chain of ordinary kernel launches (a launch costs ~3 us on
 // MI355X, a device-wide barrier inside a persistent kernel 12-19 us):
-//   resid  : r = b - K x (b from the deposited charge, x = phi), u = D^-1 r
+//   load   : x = phi on free nodes; b from the deposited charge; (b,b);
+//            resets the control word
+//   resid  : r = b - K x, u = D^-1 r; (r,r)   (also the true-residual re-check)
 //   start  : convergence test; w = K u; (r,u), (w,u)
 //   upd(i) : scalars of iteration i; p, s, x, r, u updates; (r,r), (r,u)
 //   spmv(i): w = K u; (w,u)
@@ -15,10 +17,15 @@
 // values everywhere), so no cross-workgroup synchronization is needed
 // inside a kernel.  A control word in device memory carries the state
 // (ITER, RECHECK, DONE, NOCONV); kernels whose state does not apply return
-// at once, which lets the host launch iterations in batches.
+// at once, which lets the host launch iterations in batches.  The last
+// kernel before each host wait also writes the state, with a sequence
+// number, into host-mapped memory that the host polls.
 //
-// Row blocks are contiguous per workgroup, grouped so that each of the 8 XCDs
-// (workgroup g runs on XCD g mod 8) sweeps one contiguous eighth of the rows.
+// K and R are stored in sliced ELLPACK (64 rows per slice, column-major in
+// the slice): one row per lane, so every load of a wave is contiguous.
+// Slices are split into contiguous blocks per workgroup, grouped so that each
+// of the 8 XCDs (workgroup g runs on XCD g mod 8) sweeps one contiguous
+// eighth of the matrix, which keeps neighbour gathers of x in one L2.
 #include "common.h"
 #include "solver.h"
 
@@ -26,19 +33,17 @@ namespace fp {
 
 namespace {
 
-constexpr int kLPR = 8;  // lanes per CSR row
-
-struct Rows {
+struct Range {
   int64_t lo, hi;
 };
 
-__device__ inline Rows my_rows(int64_t n) {
+__device__ inline Range my_range(int64_t n) {
   const int G = gridDim.x;
   const int g = blockIdx.x;
   int chunk = g;
   if ((G & 7) == 0) chunk = (g & 7) * (G >> 3) + (g >> 3);
   const int64_t per = (n + G - 1) / G;
-  Rows r;
+  Range r;
   r.lo = (int64_t)chunk * per;
   if (r.lo > n) r.lo = n;
   r.hi = r.lo + per < n ? r.lo + per : n;
@@ -69,7 +74,7 @@ __device__ inline void block_sum(double (&v)[NQ]) {
   __syncthreads();
 }
 
-// Totals of partial sums written by the previous kernel: part[q][0..P).
+// Totals of partial sums written by the previous kernel: part[q*stride + j].
 template <int NQ>
 __device__ inline void totals(const double* part, int P, int stride,
                               double (&t)[NQ]) {
@@ -92,23 +97,24 @@ __device__ inline void write_partials(double* part, int stride,
   }
 }
 
+// y_r = sum_j val[j] x[col[j]] over the rows of this workgroup's slices;
+// emit(r, y_r) for every row r < nrows.
 template <typename F>
-__device__ inline void spmv_rows(const DevMesh& m, const double* __restrict__ x,
-                                 Rows rows, F&& emit) {
-  const int sub = threadIdx.x % kLPR;
-  const int grp = threadIdx.x / kLPR;
-  const int ngrp = blockDim.x / kLPR;
-  for (int64_t i0 = rows.lo; i0 < rows.hi; i0 += ngrp) {
-    const int64_t i = i0 + grp;
-    double s = 0.0;
-    if (i < rows.hi) {
-      const int k1 = m.rowptr[i + 1];
-      for (int k = m.rowptr[i] + sub; k < k1; k += kLPR)
-        s += m.val[k] * x[m.col[k]];
-    }
-#pragma unroll
-    for (int off = kLPR / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off, kLPR);
-    if (i < rows.hi && sub == 0) emit(i, s);
+__device__ inline void spmv_sell(const int32_t* __restrict__ sptr,
+                                 const int32_t* __restrict__ scol,
+                                 const double* __restrict__ sval,
+                                 const double* __restrict__ x, int64_t nslices,
+                                 int64_t nrows, F&& emit) {
+  const Range sl = my_range(nslices);
+  const int lane = threadIdx.x & (kSell - 1);
+  const int sub = threadIdx.x / kSell;
+  const int nsub = blockDim.x / kSell;
+  for (int64_t s = sl.lo + sub; s < sl.hi; s += nsub) {
+    const int64_t r = s * kSell + lane;
+    const int32_t p0 = sptr[s], p1 = sptr[s + 1];
+    double acc = 0.0;
+    for (int32_t p = p0 + lane; p < p1; p += kSell) acc += sval[p] * x[scol[p]];
+    if (r < nrows) emit(r, acc);
   }
 }
 
@@ -120,53 +126,58 @@ __device__ inline double* slot(const CgArgs& a, int k) {
   return a.part + (size_t)k * a.G;
 }
 
-// r = b - K x with b_i = coef c_i + E0 g_i and x = phi on free nodes.  The
-// product reads phi through the free->node map, so x need not exist yet.
-__global__ void __launch_bounds__(512) k_cg_resid(CgArgs a) {
-  const DevMesh& m = a.m;
-  const Rows rows = my_rows(m.n_free);
-  double v[2] = {0.0, 0.0};
-  const int sub = threadIdx.x % kLPR;
-  const int grp = threadIdx.x / kLPR;
-  const int ngrp = blockDim.x / kLPR;
-  for (int64_t i0 = rows.lo; i0 < rows.hi; i0 += ngrp) {
-    const int64_t i = i0 + grp;
-    double s = 0.0;
-    if (i < rows.hi) {
-      const int k1 = m.rowptr[i + 1];
-      for (int k = m.rowptr[i] + sub; k < k1; k += kLPR)
-        s += m.val[k] * a.phi[m.free2node[m.col[k]]];
-    }
-#pragma unroll
-    for (int off = kLPR / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off, kLPR);
-    if (i < rows.hi && sub == 0) {
-      const int32_t nd = m.free2node[i];
-      const double c = a.charge ? (double)a.charge[nd] : 0.0;
-      const double bi = a.coef * c + a.E0 * m.g_unit[i];
-      const double ri = bi - s;
-      a.b[i] = bi;
-      a.x[i] = a.phi[nd];
-      a.r[i] = ri;
-      a.u[i] = ri * m.invdiag[i];
-      v[0] += bi * bi;
-      v[1] += ri * ri;
-    }
-  }
-  write_partials<2>(slot(a, 0), a.G, v);
+// x = phi on free nodes and b_i = coef c_i + E0 g_i.
+__device__ inline void ctrl_reset(CgCtrl* c) {
+  CgCtrl z;
+  z.state = CG_ITER;
+  z.zero_rhs = 0;
+  z.iters = 0;
+  z.iters_final = 0;
+  z.restarts = 0;
+  z.bb = 0.0;
+  z.relres = 0.0;
+  z.alpha[0] = z.alpha[1] = 0.0;
+  z.gamma[0] = z.gamma[1] = 0.0;
+  *c = z;
 }
 
-// Re-check of the true residual after the recursive one converged: r = b - Kx.
-__global__ void __launch_bounds__(512) k_cg_recheck(CgArgs a) {
-  if (a.ctrl->state != CG_RECHECK) return;
+// Copy of the control state to host-mapped memory; the sequence number is
+// stored last with system-scope release so the host sees a complete record.
+__device__ inline void report(const CgCtrl* c, CgReport* r, int64_t seq,
+                              int32_t state) {
+  r->state = state;
+  r->iters = state == CG_RECHECK ? c->iters_final : c->iters;
+  __hip_atomic_store(&r->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+__global__ void __launch_bounds__(512) k_cg_load(CgArgs a) {
   const DevMesh& m = a.m;
-  const Rows rows = my_rows(m.n_free);
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctrl_reset(a.ctrl);
+  const Range rows = my_range(m.n_free);
   double v[1] = {0.0};
-  spmv_rows(m, a.x, rows, [&](int64_t i, double s) {
-    const double ri = a.b[i] - s;
-    a.r[i] = ri;
-    a.u[i] = ri * m.invdiag[i];
-    v[0] += ri * ri;
-  });
+  for (int64_t i = rows.lo + threadIdx.x; i < rows.hi; i += blockDim.x) {
+    const int32_t nd = m.free2node[i];
+    const double c = a.charge ? (double)a.charge[nd] : 0.0;
+    const double bi = a.coef * c + a.E0 * m.g_unit[i];
+    a.b[i] = bi;
+    a.x[i] = a.phi[nd];
+    v[0] += bi * bi;
+  }
+  write_partials<1>(slot(a, 0), a.G, v);
+}
+
+// r = b - K x, u = D^-1 r, (r,r): the initial residual, and the re-check of
+// the true residual once the recursive one has converged.
+__global__ void __launch_bounds__(512) k_cg_resid(CgArgs a) {
+  const DevMesh& m = a.m;
+  double v[1] = {0.0};
+  spmv_sell(m.k_sptr, m.k_scol, m.k_sval, a.x, m.k_nslices, m.n_free,
+            [&](int64_t i, double s) {
+              const double ri = a.b[i] - s;
+              a.r[i] = ri;
+              a.u[i] = ri * m.invdiag[i];
+              v[0] += ri * ri;
+            });
   write_partials<1>(slot(a, 1), a.G, v);
 }
 
@@ -175,7 +186,8 @@ __global__ void __launch_bounds__(512) k_cg_recheck(CgArgs a) {
 // start and after a RECHECK.  Fields written here by workgroup 0 (state,
 // iters, relres, restarts) are never read by other workgroups of this
 // launch; they read iters_final and bb, which are stable here.
-__global__ void __launch_bounds__(512) k_cg_start(CgArgs a, int after_recheck) {
+__global__ void __launch_bounds__(512) k_cg_start(CgArgs a, int after_recheck,
+                                                 int64_t seq) {
   CgCtrl* c = a.ctrl;
   double t[2];
   if (after_recheck) {
@@ -195,25 +207,30 @@ __global__ void __launch_bounds__(512) k_cg_start(CgArgs a, int after_recheck) {
     if (!after_recheck) c->bb = t[0];
     c->iters = done_iters;
     c->relres = bn > 0.0 ? rn / bn : 0.0;
-    c->state = done ? CG_DONE : (noconv ? CG_NOCONV : CG_ITER);
+    const int32_t state = done ? CG_DONE : (noconv ? CG_NOCONV : CG_ITER);
+    c->state = state;
     if (!done && !noconv) c->restarts += 1;
     if (bn == 0.0) c->zero_rhs = 1;
+    if (seq) {
+      __threadfence_system();
+      report(c, a.report, seq, state);
+    }
   }
   if (done || noconv) return;
   const DevMesh& m = a.m;
-  const Rows rows = my_rows(m.n_free);
   double v[2] = {0.0, 0.0};
-  spmv_rows(m, a.u, rows, [&](int64_t i, double s) {
-    a.w[i] = s;
-    const double ui = a.u[i];
-    v[0] += a.r[i] * ui;
-    v[1] += s * ui;
-  });
+  spmv_sell(m.k_sptr, m.k_scol, m.k_sval, a.u, m.k_nslices, m.n_free,
+            [&](int64_t i, double s) {
+              a.w[i] = s;
+              const double ui = a.u[i];
+              v[0] += a.r[i] * ui;
+              v[1] += s * ui;
+            });
   write_partials<2>(slot(a, 2), a.G, v);
 }
 
-// Iteration it (0-based since the last (re)start, global count in ctrl):
-// scalars from the previous products, then the row-local updates.
+// Iteration it (0-based since the last (re)start): scalars from the
+// previous products, then the row-local updates.
 __global__ void __launch_bounds__(512) k_cg_upd(CgArgs a, int it) {
   CgCtrl* c = a.ctrl;
   if (c->state != CG_ITER) return;
@@ -258,7 +275,7 @@ __global__ void __launch_bounds__(512) k_cg_upd(CgArgs a, int it) {
     c->alpha[it & 1] = alpha;
   }
   const DevMesh& m = a.m;
-  const Rows rows = my_rows(m.n_free);
+  const Range rows = my_range(m.n_free);
   double v[2] = {0.0, 0.0};
   const bool first = it == 0;
   for (int64_t i = rows.lo + threadIdx.x; i < rows.hi; i += blockDim.x) {
@@ -277,15 +294,18 @@ __global__ void __launch_bounds__(512) k_cg_upd(CgArgs a, int it) {
   write_partials<2>(slot(a, 4 + 2 * (it & 1)), a.G, v);
 }
 
-__global__ void __launch_bounds__(512) k_cg_spmv(CgArgs a, int it) {
-  if (a.ctrl->state != CG_ITER) return;
+__global__ void __launch_bounds__(512) k_cg_spmv(CgArgs a, int it,
+                                                int64_t seq) {
+  const int32_t state = a.ctrl->state;
+  if (seq && blockIdx.x == 0 && threadIdx.x == 0) report(a.ctrl, a.report, seq, state);
+  if (state != CG_ITER) return;
   const DevMesh& m = a.m;
-  const Rows rows = my_rows(m.n_free);
   double v[1] = {0.0};
-  spmv_rows(m, a.u, rows, [&](int64_t i, double s) {
-    a.w[i] = s;
-    v[0] += s * a.u[i];
-  });
+  spmv_sell(m.k_sptr, m.k_scol, m.k_sval, a.u, m.k_nslices, m.n_free,
+            [&](int64_t i, double s) {
+              a.w[i] = s;
+              v[0] += s * a.u[i];
+            });
   write_partials<1>(slot(a, 8 + (it & 1)), a.G, v);
 }
 
@@ -295,13 +315,12 @@ __global__ void __launch_bounds__(512) k_cg_field(CgArgs a) {
   const CgCtrl* c = a.ctrl;
   const bool zero = c->zero_rhs != 0;
   {
-    const Rows rows = my_rows(m.n_free);
+    const Range rows = my_range(m.n_free);
     for (int64_t i = rows.lo + threadIdx.x; i < rows.hi; i += blockDim.x) {
       const double xi = zero ? 0.0 : a.x[i];
-      if (zero) a.x[i] = 0.0;
       a.phi[m.free2node[i]] = xi;
     }
-    const Rows dr = my_rows(a.n_dir);
+    const Range dr = my_range(a.n_dir);
     for (int64_t i = dr.lo + threadIdx.x; i < dr.hi; i += blockDim.x)
       a.phi[a.dir_nodes[i]] = 0.0;
   }
@@ -321,97 +340,60 @@ __global__ void __launch_bounds__(512) k_cg_field(CgArgs a) {
     }
   }
   if (!a.E) return;
-  const Rows fr = my_rows(m.n_nodes);
-  const int sub = threadIdx.x % kLPR;
-  const int grp = threadIdx.x / kLPR;
-  const int ngrp = blockDim.x / kLPR;
-  const int64_t nf = m.nnz_field;
-  for (int64_t i0 = fr.lo; i0 < fr.hi; i0 += ngrp) {
-    const int64_t i = i0 + grp;
+  const Range sl = my_range(m.f_nslices);
+  const int lane = threadIdx.x & (kSell - 1);
+  const int sub = threadIdx.x / kSell;
+  const int nsub = blockDim.x / kSell;
+  const int64_t np = m.f_np;
+  for (int64_t s = sl.lo + sub; s < sl.hi; s += nsub) {
+    const int64_t r = s * kSell + lane;
+    const int32_t p0 = m.f_sptr[s], p1 = m.f_sptr[s + 1];
     double ex = 0.0, ey = 0.0, ez = 0.0;
-    if (i < fr.hi && !zero) {
-      const int k1 = m.frow[i + 1];
-      for (int k = m.frow[i] + sub; k < k1; k += kLPR) {
-        const double xj = a.x[m.fcol[k]];
-        ex += m.fval[k] * xj;
-        ey += m.fval[nf + k] * xj;
-        ez += m.fval[2 * nf + k] * xj;
+    if (!zero) {
+      for (int32_t p = p0 + lane; p < p1; p += kSell) {
+        const double xj = a.x[m.f_scol[p]];
+        ex += m.f_sval[p] * xj;
+        ey += m.f_sval[np + p] * xj;
+        ez += m.f_sval[2 * np + p] * xj;
       }
     }
-#pragma unroll
-    for (int off = kLPR / 2; off >= 1; off >>= 1) {
-      ex += __shfl_xor(ex, off, kLPR);
-      ey += __shfl_xor(ey, off, kLPR);
-      ez += __shfl_xor(ez, off, kLPR);
-    }
-    if (i < fr.hi && sub == 0) {
+    if (r < m.n_nodes) {
       double4 e;
       e.x = ex;
       e.y = ey;
       e.z = ez;
       e.w = 0.0;
-      reinterpret_cast<double4*>(a.E)[i] = e;
+      reinterpret_cast<double4*>(a.E)[r] = e;
     }
   }
 }
 
-__global__ void k_cg_reset(CgCtrl* c) {
-  if (threadIdx.x == 0) {
-    CgCtrl z;
-    z.state = CG_ITER;
-    z.zero_rhs = 0;
-    z.iters = 0;
-    z.iters_final = 0;
-    z.restarts = 0;
-    z.bb = 0.0;
-    z.relres = 0.0;
-    z.alpha[0] = z.alpha[1] = 0.0;
-    z.gamma[0] = z.gamma[1] = 0.0;
-    *c = z;
-  }
-}
-
-// Copies the control state to host-mapped memory; the sequence number is
-// stored last with system-scope release so the host sees a complete record.
-__global__ void k_cg_report(const CgCtrl* c, CgReport* r, int64_t seq) {
-  if (threadIdx.x == 0) {
-    r->state = c->state;
-    r->iters = c->state == CG_RECHECK ? c->iters_final : c->iters;
-    __hip_atomic_store(&r->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-  }
-}
-
-hipError_t cg_launch_report(CgCtrl* ctrl, CgReport* host_mapped, int64_t seq,
-                            hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_report, dim3(1), dim3(64), 0, s, ctrl, host_mapped, seq);
-  return hipGetLastError();
-}
-
-#define LAUNCH(kern, ...)                                                \
+#define LAUNCH(kern, ...)                                                   \
   do {                                                                      \
     hipLaunchKernelGGL(kern, dim3(a.G), dim3(kCgBlock), 0, s, __VA_ARGS__); \
     hipError_t e_ = hipGetLastError();                                      \
     if (e_ != hipSuccess) return e_;                                        \
   } while (0)
 
-hipError_t cg_launch_begin(const CgArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_reset, dim3(1), dim3(64), 0, s, a.ctrl);
+hipError_t cg_launch_begin(const CgArgs& a, int64_t seq, hipStream_t s) {
+  LAUNCH(k_cg_load, a);
   LAUNCH(k_cg_resid, a);
-  LAUNCH(k_cg_start, a, 0);
+  LAUNCH(k_cg_start, a, 0, seq);
   return hipSuccess;
 }
 
-hipError_t cg_launch_iters(const CgArgs& a, int it0, int n, hipStream_t s) {
+hipError_t cg_launch_iters(const CgArgs& a, int it0, int n, int64_t seq,
+                           hipStream_t s) {
   for (int k = 0; k < n; ++k) {
     LAUNCH(k_cg_upd, a, it0 + k);
-    LAUNCH(k_cg_spmv, a, it0 + k);
+    LAUNCH(k_cg_spmv, a, it0 + k, k == n - 1 ? seq : (int64_t)0);
   }
   return hipSuccess;
 }
 
-hipError_t cg_launch_recheck(const CgArgs& a, hipStream_t s) {
-  LAUNCH(k_cg_recheck, a);
-  LAUNCH(k_cg_start, a, 1);
+hipError_t cg_launch_recheck(const CgArgs& a, int64_t seq, hipStream_t s) {
+  LAUNCH(k_cg_resid, a);
+  LAUNCH(k_cg_start, a, 1, seq);
   return hipSuccess;
 }
 

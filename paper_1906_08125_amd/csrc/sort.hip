@@ -57,28 +57,65 @@ __global__ void __launch_bounds__(kThreads) k_sort_hist(SortArgs a, int src,
   }
 }
 
-// Exclusive scan of hist (bin-major) in one block.
+// Exclusive scan of hist (bin-major) in one block: every wave owns 4 bins;
+// it sums their per-block counts, the 64 bin totals are scanned in LDS, and
+// each wave then rescans its bins (64 counts at a time, shuffle scan) from
+// the bin's offset.
+// The counts of a bin's run of kScanRun blocks are loaded into registers
+// before any arithmetic, so the loads of a wave are in flight together.
+constexpr int kScanRun = 16 * 64;
+
 __global__ void __launch_bounds__(1024) k_sort_scan(SortArgs a, int nblocks) {
-  __shared__ uint32_t part[1024];
-  const int64_t total = (int64_t)kBins * nblocks;
-  const int64_t per = (total + blockDim.x - 1) / blockDim.x;
-  const int64_t lo = threadIdx.x * per;
-  const int64_t hi = lo + per < total ? lo + per : total;
-  uint32_t s = 0;
-  for (int64_t i = lo; i < hi; ++i) s += a.hist[i];
-  part[threadIdx.x] = s;
-  __syncthreads();
-  for (int off = 1; off < (int)blockDim.x; off <<= 1) {
-    const uint32_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
-    __syncthreads();
-    part[threadIdx.x] += v;
-    __syncthreads();
+  __shared__ uint32_t bin_total[kBins];
+  __shared__ uint32_t bin_off[kBins];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nwaves = blockDim.x >> 6;
+  for (int b = wave; b < kBins; b += nwaves) {
+    uint32_t s = 0;
+    for (int j0 = 0; j0 < nblocks; j0 += kScanRun) {
+      uint32_t v[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const int j = j0 + k * 64 + lane;
+        v[k] = j < nblocks ? a.hist[(int64_t)b * nblocks + j] : 0u;
+      }
+#pragma unroll
+      for (int k = 0; k < 16; ++k) s += v[k];
+    }
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) bin_total[b] = s;
   }
-  uint32_t run = part[threadIdx.x] - s;
-  for (int64_t i = lo; i < hi; ++i) {
-    const uint32_t v = a.hist[i];
-    a.hist[i] = run;
-    run += v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int b = 0; b < kBins; ++b) {
+      bin_off[b] = run;
+      run += bin_total[b];
+    }
+  }
+  __syncthreads();
+  for (int b = wave; b < kBins; b += nwaves) {
+    uint32_t carry = bin_off[b];
+    for (int j0 = 0; j0 < nblocks; j0 += kScanRun) {
+      uint32_t v[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const int j = j0 + k * 64 + lane;
+        v[k] = j < nblocks ? a.hist[(int64_t)b * nblocks + j] : 0u;
+      }
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const int j = j0 + k * 64 + lane;
+        uint32_t inc = v[k];
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+          const uint32_t o = __shfl_up(inc, off, 64);
+          if (lane >= off) inc += o;
+        }
+        if (j < nblocks) a.hist[(int64_t)b * nblocks + j] = carry + inc - v[k];
+        carry += __shfl(inc, 63, 64);
+      }
+    }
   }
 }
 
