@@ -43,48 +43,30 @@ def solve_bytes(info, iters):
     return rhs + resid + iters * it + scatter + field
 
 
-def push_bytes(n_live):
-    """Particle stream of the push kernel: read x,y,z,vx,vy,vz (48 B),
-    tet (4), w (8); write x,y,z,vx,vy,vz (48), tet (4)."""
-    return 112 * n_live
+def push_bytes(n_live, real_bytes=8):
+    """Particle stream of the push kernel: read x,y,z,vx,vy,vz (6 reals),
+    tet (4), w (8); write x,y,z,vx,vy,vz (6 reals), tet (4)."""
+    return (12 * real_bytes + 16) * n_live
 
 
-def run_gpu(args):
-    import numpy as np
+def run_leg(gm, cfg, w_sp, precision, args):
+    """Warm-up then K timed steps of one run at the given precision."""
     import torch
 
-    from paper_1906_08125_amd import pic, workloads as W
+    from paper_1906_08125_amd import pic
 
-    cfg = W.config_production()
-    tip = cfg.mesh()
-    t0 = time.time()
-    gm = pic.Mesh(tip, cfg.emit_zmin)
-    log(f"mesh_create {time.time() - t0:.1f}s {gm.info}")
-    cap = int(args.capacity)
-    gs = pic.State(gm, cap)
-    torch.cuda.synchronize()
-    # cold Laplace solve: CG throughput on the production matrix
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    st = gs.init_field(cfg.E0, tol=cfg.tol)
-    e1.record()
-    torch.cuda.synchronize()
-    cold = gm.solve_stats(st)
-    cold_ms = e0.elapsed_time(e1)
-    log(f"cold solve {cold} {cold_ms:.2f} ms")
-    rate, _ = gm.emission_rate(gs.E, cfg.phi_w)
-    rate = rate.item()
-    w_sp = rate * cfg.dt * cfg.transit_steps / cfg.n_target
-    log(f"emission {rate:.3e} e/fs -> w_sp {w_sp:.3e}")
+    gs = pic.State(gm, int(args.capacity), precision=precision,
+                   inner_tol=args.inner_tol)
+    gs.init_field(cfg.E0, tol=cfg.tol)
     kw = dict(dt=cfg.dt, E0=cfg.E0, w_sp=w_sp, phi_w=cfg.phi_w,
               seed=cfg.seed, tol=cfg.tol, resort_every=args.resort)
     step = 0
-    wstats = gs.step(step0=step, n_steps=args.warmup, **kw) if args.warmup else None
+    if args.warmup:
+        wstats = gs.step(step0=step, n_steps=args.warmup, **kw)
+        torch.cuda.synchronize()
+        log(f"after warmup ({precision}): "
+            f"{pic.State.decode_stats(wstats)[-1]}")
     step += args.warmup
-    torch.cuda.synchronize()
-    if wstats is not None:
-        last = pic.State.decode_stats(wstats)[-1]
-        log(f"after warmup: {last}")
     stats = torch.zeros(args.steps * pic.STEP_STATS_BYTES // 8,
                         dtype=torch.int64, device="cuda")
     # timed region: K steps, bracketed by synchronizations
@@ -100,6 +82,40 @@ def run_gpu(args):
     for r in rows:
         if r["status"] != 0:
             raise RuntimeError(f"step status {r['status']}: {r}")
+    return dict(elapsed=elapsed, kt=kt, rows=rows, state=gs)
+
+
+def run_gpu(args):
+    import torch
+
+    from paper_1906_08125_amd import pic, workloads as W
+
+    cfg = W.config_production()
+    tip = cfg.mesh()
+    t0 = time.time()
+    gm = pic.Mesh(tip, cfg.emit_zmin)
+    log(f"mesh_create {time.time() - t0:.1f}s {gm.info}")
+    # cold Laplace solve: CG throughput on the production matrix
+    phi = torch.zeros(gm.n_nodes, dtype=torch.float64, device="cuda")
+    E = torch.zeros(4 * gm.n_nodes, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    st = gm.poisson_solve(None, 0.0, cfg.E0, phi, E, tol=cfg.tol)
+    e1.record()
+    torch.cuda.synchronize()
+    cold = gm.solve_stats(st)
+    cold_ms = e0.elapsed_time(e1)
+    log(f"cold solve {cold} {cold_ms:.2f} ms")
+    rate, _ = gm.emission_rate(E, cfg.phi_w)
+    rate = rate.item()
+    w_sp = rate * cfg.dt * cfg.transit_steps / cfg.n_target
+    log(f"emission {rate:.3e} e/fs -> w_sp {w_sp:.3e}")
+    del phi, E
+
+    leg = run_leg(gm, cfg, w_sp, pic.PIC_FP64, args)
+    elapsed, kt, rows = leg["elapsed"], leg["kt"], leg["rows"]
+    del leg
     pushes = sum(r["n_before"] + r["n_inj"] for r in rows)
     live_mean = sum(r["n_before"] for r in rows) / len(rows)
     iters_mean = sum(r["cg_iters"] for r in rows) / len(rows)
@@ -120,6 +136,30 @@ def run_gpu(args):
     dom = max(("push", "solve"), key=lambda k: kt[k]["ms"])
     dom_bytes, dom_us = (pb, push_us) if dom == "push" else (sb, solve_us)
     achieved = dom_bytes / dom_us / 1e3  # GB/s
+
+    mixed = None
+    if not args.no_mixed:
+        torch.cuda.empty_cache()
+        ml = run_leg(gm, cfg, w_sp, pic.PIC_MIXED, args)
+        mr = ml["rows"]
+        m_live = sum(r["n_before"] for r in mr) / len(mr)
+        mk = ml["kt"]
+        m_push_us = mk["push"]["ms"] * 1e3 / mk["push"]["launches"]
+        mixed = dict(
+            value=round(args.steps / ml["elapsed"], 3), unit="steps/s",
+            ms_per_step=round(1e3 * ml["elapsed"] / args.steps, 4),
+            speedup_vs_fp64=round(elapsed / ml["elapsed"], 4),
+            pushes_per_s=round(sum(r["n_before"] + r["n_inj"] for r in mr)
+                               / ml["elapsed"], 1),
+            live_particles_mean=round(m_live),
+            cg_iters_per_step=sum(r["cg_iters"] for r in mr) / len(mr),
+            inner_tol=args.inner_tol,
+            kernels={n: dict(ms_total=round(v["ms"], 4),
+                             launches=v["launches"],
+                             us_per_launch=round(1e3 * v["ms"] / v["launches"], 2))
+                     for n, v in mk.items()},
+            push_GBps=round(push_bytes(m_live, 4) / m_push_us / 1e3, 1))
+        del ml
     out = dict(
         metric=METRIC, value=round(args.steps / elapsed, 3), unit="steps/s",
         n_gpus=1, steps=args.steps, warmup=args.warmup,
@@ -136,6 +176,7 @@ def run_gpu(args):
                         iters_per_s=round(cold["iters"] / cold_ms * 1e3, 1),
                         relres=cold["relres"]),
         kernels=kernels,
+        mixed=mixed,
         roofline=dict(kernel=dom, bound="hbm", achieved=round(achieved, 1),
                       peak=HBM_PEAK_GBS, unit="GB/s",
                       frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None),
@@ -191,6 +232,10 @@ def main():
     ap.add_argument("--cpu-particles", type=int, default=1_000_000)
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-precision leg")
+    ap.add_argument("--inner-tol", type=float, default=1e-4,
+                    help="FP32 inner CG target of the mixed leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the multi-GPU layout of this "

@@ -134,9 +134,17 @@ PIC_API pic_status deposit(const pic_mesh* mesh, int64_t n, const double* x,
 /* started from phi, stopped when ||b - K phi||_2 <= tol ||b||_2 (checked   */
 /* on the true residual).  phi: device [n_nodes] f64 (in: guess, out:       */
 /* solution, 0 on Dirichlet nodes).  charge: device [n_nodes] or NULL.      */
-/* E_out: device [4*n_nodes] f64 or NULL: nodal field (x, y, z, 0), the      */
-/* volume-weighted mean of -grad(phi) over the tets holding each node.       */
+/* E_out: device [4*n_nodes] or NULL: nodal field (x, y, z, 0), the         */
+/* volume-weighted mean of -grad(phi) over the tets holding each node;       */
+/* f64 for PIC_FP64, f32 for PIC_MIXED.                                      */
 /* stats: device pic_solve_stats or NULL.                                   */
+/* PIC_MIXED (not in the paper): the CG recursion runs in FP32 against K    */
+/* rounded to FP32; phi, b, the true residual, every reduction and the      */
+/* stopping tests stay FP64.  When the FP32 recursion has reduced its       */
+/* residual below max(tol ||b||, inner_tol ||r_restart||), the true         */
+/* residual is recomputed in FP64 and the recursion restarted from it       */
+/* (iterative refinement) until tol holds on the true residual.             */
+/* inner_tol must lie in [1e-7, 0.5] for PIC_MIXED (ignored for PIC_FP64).   */
 /* ------------------------------------------------------------------------ */
 typedef struct {
   double tol;        /* relative residual target                         */
@@ -155,7 +163,7 @@ typedef struct {
 } pic_solve_stats;
 
 PIC_API pic_status poisson_solve(const pic_mesh* mesh, const int64_t* charge,
-                         double w_sp, double E0, double* phi, double* E_out,
+                         double w_sp, double E0, double* phi, void* E_out,
                          const pic_solve_params* params,
                          pic_solve_stats* stats, void* stream);
 
@@ -177,7 +185,8 @@ typedef struct {
 
 typedef struct {
   double* phi;      /* device [n_nodes] potential                         */
-  double* E;        /* device [4*n_nodes] nodal field of phi              */
+  void* E;          /* device [4*n_nodes] nodal field of phi: f64, or f32 */
+                    /* when particles->precision is PIC_MIXED             */
   int64_t* charge;  /* device [n_nodes] fixed-point charge of last step   */
 } pic_fields;
 
@@ -211,6 +220,12 @@ typedef struct {
  * (Eq. leapfrog2), wrap laterally, absorb at z >= z_top (anode) or outside
  * the vacuum (cathode), locate, deposit, solve for phi_{k+1} and recover the
  * nodal field.  fields->E must hold the field of phi on entry.
+ * Mixed precision (particles->precision PIC_MIXED, not in the paper):
+ * positions, velocities and fields->E are FP32, and the field gather, kick,
+ * drift and wrap run in FP32; the barycentric weights of the stored FP32
+ * position (widened exactly to FP64), locating, deposition, injection and
+ * emission stay FP64, so charge and tet ids follow the stored positions
+ * exactly.  params->solve.precision chooses the solver independently.
  * stats: device [n_steps] pic_step_stats (overwritten). */
 PIC_API pic_status pic_step(pic_mesh* mesh, const pic_particles* particles,
                     const pic_fields* fields, const pic_step_params* params,

@@ -28,7 +28,8 @@ bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
 // Grow the particle-capacity scratch (fallback queue, sort buffers) of a
 // handle; later calls with the same or a smaller capacity allocate nothing.
-hipError_t ensure_capacity(pic_mesh* h, int64_t cap, bool sort) {
+hipError_t ensure_capacity(pic_mesh* h, int64_t cap, bool sort,
+                           int real_bytes) {
   if (cap > h->pcap) {
     if (h->queue) {
       hipError_t e = hipFree(h->queue);
@@ -40,7 +41,7 @@ hipError_t ensure_capacity(pic_mesh* h, int64_t cap, bool sort) {
     h->pcap = cap;
   }
   if (sort) {
-    const size_t need = fp::sort_scratch_bytes(cap, 8);
+    const size_t need = fp::sort_scratch_bytes(cap, real_bytes);
     if (need > h->sort_bytes) {
       if (h->sort_mem) {
         hipError_t e = hipFree(h->sort_mem);
@@ -93,7 +94,7 @@ fp::SortArgs sort_args(pic_mesh* h, const pic_particles* P, int real_bytes) {
 }
 
 fp::CgArgs cg_args(const pic_mesh* h, const int64_t* charge, double w_sp,
-                   double E0, double* phi, double* E,
+                   double E0, double* phi, void* E, bool e32,
                    const pic_solve_params* prm) {
   const fp::Phys ph = fp::phys_constants();
   fp::CgArgs a;
@@ -113,6 +114,14 @@ fp::CgArgs cg_args(const pic_mesh* h, const int64_t* charge, double w_sp,
   a.w = h->cg_vec[4];
   a.p = h->cg_vec[5];
   a.s = h->cg_vec[6];
+  a.mixed = prm->precision == PIC_MIXED;
+  a.e32 = e32;
+  a.inner_tol = prm->inner_tol;
+  a.r32 = h->cg_vec32[0];
+  a.u32 = h->cg_vec32[1];
+  a.w32 = h->cg_vec32[2];
+  a.p32 = h->cg_vec32[3];
+  a.s32 = h->cg_vec32[4];
   a.part = h->cg_part;
   a.G = h->cg_grid;
   a.ctrl = h->cg_ctrl;
@@ -192,8 +201,11 @@ pic_status check_solve(const pic_solve_params* p) {
   if (!p) return fail(PIC_E_ARG, "solve params are null");
   if (!finite_pos(p->tol) || p->max_iter < 0)
     return fail(PIC_E_ARG, "solve params: tol must be > 0, max_iter >= 0");
-  if (p->precision != PIC_FP64)
-    return fail(PIC_E_ARG, "solve params: unsupported precision");
+  if (p->precision != PIC_FP64 && p->precision != PIC_MIXED)
+    return fail(PIC_E_ARG, "solve params: unknown precision");
+  if (p->precision == PIC_MIXED &&
+      !(p->inner_tol >= 1e-7 && p->inner_tol <= 0.5))
+    return fail(PIC_E_ARG, "solve params: inner_tol must be in [1e-7, 0.5]");
   return PIC_OK;
 }
 
@@ -312,7 +324,7 @@ pic_status locate(const pic_mesh* hc, int64_t n, const double* x,
     return fail(PIC_E_ARG, "locate: null array");
   if (n >= (1ll << 31)) return fail(PIC_E_ARG, "locate: n >= 2^31");
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = ensure_capacity(h, n, false);
+  hipError_t e = ensure_capacity(h, n, false, 8);
   if (e != hipSuccess) return hip_fail(e, "locate");
   e = hipMemsetAsync(h->locate_count, 0, sizeof(int32_t), s);
   if (e != hipSuccess) return hip_fail(e, "locate");
@@ -357,7 +369,7 @@ pic_status deposit(const pic_mesh* h, int64_t n, const double* x,
 }
 
 pic_status poisson_solve(const pic_mesh* h, const int64_t* charge,
-                         double w_sp, double E0, double* phi, double* E_out,
+                         double w_sp, double E0, double* phi, void* E_out,
                          const pic_solve_params* params,
                          pic_solve_stats* stats, void* stream) {
   if (!h || !phi) return fail(PIC_E_ARG, "poisson_solve: null mesh or phi");
@@ -365,7 +377,8 @@ pic_status poisson_solve(const pic_mesh* h, const int64_t* charge,
     return fail(PIC_E_ARG, "poisson_solve: non-finite w_sp or E0");
   pic_status ps = check_solve(params);
   if (ps != PIC_OK) return ps;
-  fp::CgArgs a = cg_args(h, charge, w_sp, E0, phi, E_out, params);
+  fp::CgArgs a = cg_args(h, charge, w_sp, E0, phi, E_out,
+                         params->precision == PIC_MIXED, params);
   a.stats = stats;
   pic_mesh* hm = const_cast<pic_mesh*>(h);
   prof_begin(hm, PIC_K_SOLVE, (hipStream_t)stream);
@@ -401,8 +414,9 @@ pic_status pic_step(pic_mesh* h, const pic_particles* P, const pic_fields* F,
     return fail(PIC_E_ARG, "pic_step: null argument");
   if (n_steps < 0) return fail(PIC_E_ARG, "pic_step: n_steps < 0");
   if (n_steps == 0) return PIC_OK;
-  if (P->precision != PIC_FP64)
-    return fail(PIC_E_ARG, "pic_step: unsupported particle precision");
+  if (P->precision != PIC_FP64 && P->precision != PIC_MIXED)
+    return fail(PIC_E_ARG, "pic_step: unknown particle precision");
+  const bool f32 = P->precision == PIC_MIXED;
   if (P->capacity <= 0 || P->capacity >= (1ll << 31))
     return fail(PIC_E_ARG, "pic_step: capacity must be in [1, 2^31)");
   if (!P->x || !P->y || !P->z || !P->vx || !P->vy || !P->vz || !P->w ||
@@ -417,19 +431,20 @@ pic_status pic_step(pic_mesh* h, const pic_particles* P, const pic_fields* F,
   pic_status ps = check_solve(&prm->solve);
   if (ps != PIC_OK) return ps;
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = ensure_capacity(h, P->capacity, prm->resort_every > 0);
+  hipError_t e = ensure_capacity(h, P->capacity, prm->resort_every > 0, f32 ? 4 : 8);
   if (e != hipSuccess) return hip_fail(e, "pic_step");
 
   const fp::Phys ph = fp::phys_constants();
   fp::StepArgs a;
   std::memset(&a, 0, sizeof a);
   a.m = h->dm;
-  a.x = (double*)P->x;
-  a.y = (double*)P->y;
-  a.z = (double*)P->z;
-  a.vx = (double*)P->vx;
-  a.vy = (double*)P->vy;
-  a.vz = (double*)P->vz;
+  a.x = P->x;
+  a.y = P->y;
+  a.z = P->z;
+  a.vx = P->vx;
+  a.vy = P->vy;
+  a.vz = P->vz;
+  a.f32 = f32;
   a.w = P->w;
   a.tet = P->tet;
   a.birth = P->birth;
@@ -451,6 +466,7 @@ pic_status pic_step(pic_mesh* h, const pic_particles* P, const pic_fields* F,
   std::memset(&ea, 0, sizeof ea);
   ea.m = h->dm;
   ea.E = F->E;
+  ea.f32 = f32;
   ea.c = {ph.a_fn, ph.b_fn, ph.c_s, ph.j_unit};
   ea.phi_w = prm->phi_w;
   ea.j_scale = prm->j_scale;
@@ -464,7 +480,8 @@ pic_status pic_step(pic_mesh* h, const pic_particles* P, const pic_fields* F,
   ea.n_slots = P->n_slots;
   ea.scratch = h->scratch;
 
-  fp::CgArgs ca = cg_args(h, F->charge, prm->w_sp, prm->E0, F->phi, F->E, &prm->solve);
+  fp::CgArgs ca = cg_args(h, F->charge, prm->w_sp, prm->E0, F->phi, F->E, f32,
+                          &prm->solve);
 
   const int grid_push = h->grid_push;
   const int grid_inj = h->grid_inj;
@@ -504,7 +521,7 @@ pic_status pic_step(pic_mesh* h, const pic_particles* P, const pic_fields* F,
     prof_end(h, s);
     if (prm->resort_every > 0 && (step + 1) % prm->resort_every == 0) {
       prof_begin(h, PIC_K_SORT, s);
-      fp::SortArgs sa = sort_args(h, P, 8);
+      fp::SortArgs sa = sort_args(h, P, f32 ? 4 : 8);
       sa.stats = st;
       if ((e = fp::sort_particles(sa, P->capacity, h->n_cu, s)) != hipSuccess)
         return hip_fail(e, "pic_step sort");

@@ -52,17 +52,15 @@ struct DevMesh {
   double Lx, Ly, z_top;
   const TetWalk* tw;
   const TetGeom* tg;
-  // stiffness on free nodes (CSR, int32 rowptr), Jacobi inverse diagonal
-  const int32_t* rowptr;
-  const int32_t* col;
-  const double* val;
-  const float* val32;
+  // Jacobi inverse diagonal of the stiffness on free nodes
   const double* invdiag;
   const float* invdiag32;
   const double* g_unit;      // Neumann load per unit E0 [n_free]
   const int32_t* free2node;  // [n_free]
   const int32_t* node2free;  // [n_nodes], -1 for Dirichlet
-  // the same two operators in sliced ELLPACK (kSell rows per slice)
+  // stiffness K (rows and columns free nodes) and nodal field operator R
+  // (rows all nodes, columns free nodes, three components) in sliced
+  // ELLPACK, kSell rows per slice
   int64_t k_nslices, f_nslices, f_np;
   const int32_t* k_sptr;   // [k_nslices + 1] slice offsets
   const int32_t* k_scol;
@@ -72,10 +70,7 @@ struct DevMesh {
   const int32_t* f_scol;
   const double* f_sval;    // [3][f_np]
   const float* f_sval32;   // [3][f_np]
-  // nodal field operator: rows all nodes, columns free indices
-  const int32_t* frow;
-  const int32_t* fcol;
-  const double* fval;        // [3][nnz_field]
+  const double4* f_rowsum; // [n_nodes] FP64 row sums of R (w unused)
   // emitting faces
   const int32_t* e_tet;
   const int32_t* e_nodes;    // [3*n_emit]

@@ -14,6 +14,7 @@ struct pic_mesh {
   int n_cu = 0;
   // solver scratch: b, x, r, u, w, p, s (f64) and the partial sums
   double* cg_vec[7] = {};
+  float* cg_vec32[5] = {};             // r, u, w, p, s of the FP32 recursion
   double* cg_part = nullptr;
   int cg_grid = 0;
   fp::CgCtrl* cg_ctrl = nullptr;       // device control word

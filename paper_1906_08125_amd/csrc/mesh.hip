@@ -444,10 +444,17 @@ pic_status build_mesh(const pic_mesh_desc* d, pic_mesh* h, std::string& msg) {
     }
   }
   // 9. upload
-  std::vector<float> val32(val.begin(), val.end()), invdiag32(invdiag.begin(), invdiag.end());
-  std::vector<double> fval;
-  fval.reserve(3 * fcol.size());
-  for (int c = 0; c < 3; ++c) fval.insert(fval.end(), fv[c].begin(), fv[c].end());
+  std::vector<float> invdiag32(invdiag.begin(), invdiag.end());
+  std::vector<double4> f_rowsum(N);
+  for (int64_t i = 0; i < N; ++i) {
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+    for (int32_t p = frow[i]; p < frow[i + 1]; ++p) {
+      sx += fv[0][p];
+      sy += fv[1][p];
+      sz += fv[2][p];
+    }
+    f_rowsum[i] = make_double4(sx, sy, sz, 0.0);
+  }
   hipError_t err = hipSuccess;
   M.n_nodes = N;
   M.n_tets = T;
@@ -460,18 +467,12 @@ pic_status build_mesh(const pic_mesh_desc* d, pic_mesh* h, std::string& msg) {
   M.z_top = d->z_top;
   M.tw = upload(h, tw, err);
   M.tg = upload(h, tg, err);
-  M.rowptr = upload(h, rowptr, err);
-  M.col = upload(h, col, err);
-  M.val = upload(h, val, err);
-  M.val32 = upload(h, val32, err);
   M.invdiag = upload(h, invdiag, err);
   M.invdiag32 = upload(h, invdiag32, err);
   M.g_unit = upload(h, g_unit, err);
   M.free2node = upload(h, free2node, err);
   M.node2free = upload(h, node2free, err);
-  M.frow = upload(h, frow, err);
-  M.fcol = upload(h, fcol, err);
-  M.fval = upload(h, fval, err);
+  M.f_rowsum = upload(h, f_rowsum, err);
   M.e_tet = upload(h, e_tet, err);
   M.e_nodes = upload(h, e_nodes, err);
   M.e_abc = upload(h, e_abc, err);
@@ -514,6 +515,7 @@ pic_status build_mesh(const pic_mesh_desc* d, pic_mesh* h, std::string& msg) {
   // solver scratch
   const size_t vb = sizeof(double) * (size_t)std::max<int64_t>(NF, 1);
   for (int k = 0; k < 7; ++k) h->cg_vec[k] = (double*)dev_alloc(h, vb, err);
+  for (int k = 0; k < 5; ++k) h->cg_vec32[k] = (float*)dev_alloc(h, vb / 2, err);
   int dev = 0, ncu = 0;
   if (err == hipSuccess) err = hipGetDevice(&dev);
   if (err == hipSuccess) err = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);

@@ -12,11 +12,13 @@ struct EmitConsts {
 
 struct StepArgs {
   DevMesh m;
-  double *x, *y, *z, *vx, *vy, *vz, *w;
+  void *x, *y, *z, *vx, *vy, *vz;  // double, or float when f32
+  double* w;
   int32_t *tet, *birth;
   int64_t* id;
   int32_t* n_slots;
-  const double* E;      // nodal field [4 n_nodes]
+  const void* E;        // nodal field [4 n_nodes], double or float (f32)
+  int f32;              // mixed precision: float particles and field
   int64_t* charge;      // [n_nodes]
   const double* s_face; // [n_emit] or null
   const int32_t* offsets;  // [n_emit + 1] exclusive scan of counts
@@ -34,7 +36,8 @@ struct StepArgs {
 
 struct EmitArgs {
   DevMesh m;
-  const double* E;
+  const void* E;        // double [4 n_nodes], or float when f32
+  int f32;
   EmitConsts c;
   double phi_w, j_scale, dt, w_sp;
   uint64_t seed, instance;

@@ -91,20 +91,25 @@ __device__ inline void acc_flush(const Acc& a, int64_t* rows, int row,
   }
 }
 
-__device__ inline double4 ld_E(const double* E, int32_t node) {
+// Nodal field at one node, widened to double when stored in float.
+__device__ inline double4 ld_E(const void* E, int f32, int32_t node) {
+  if (f32) {
+    const float4 e = reinterpret_cast<const float4*>(E)[node];
+    return make_double4(e.x, e.y, e.z, e.w);
+  }
   return reinterpret_cast<const double4*>(E)[node];
 }
 
 // Field at p inside tet g: sum_i lambda_i E_i in a fixed order.
-__device__ inline void gather_field(const TetGeom& g, const double* E,
+__device__ inline void gather_field(const TetGeom& g, const void* E,
                                     double x, double y, double z,
                                     double& ex, double& ey, double& ez) {
   double lam[4];
   barycentric(g, x, y, z, lam);
-  const double4 e0 = ld_E(E, g.node[0]);
-  const double4 e1 = ld_E(E, g.node[1]);
-  const double4 e2 = ld_E(E, g.node[2]);
-  const double4 e3 = ld_E(E, g.node[3]);
+  const double4 e0 = ld_E(E, 0, g.node[0]);
+  const double4 e1 = ld_E(E, 0, g.node[1]);
+  const double4 e2 = ld_E(E, 0, g.node[2]);
+  const double4 e3 = ld_E(E, 0, g.node[3]);
   ex = ((lam[0] * e0.x + lam[1] * e1.x) + lam[2] * e2.x) + lam[3] * e3.x;
   ey = ((lam[0] * e0.y + lam[1] * e1.y) + lam[2] * e2.y) + lam[3] * e3.y;
   ez = ((lam[0] * e0.z + lam[1] * e1.z) + lam[2] * e2.z) + lam[3] * e3.z;
@@ -346,12 +351,13 @@ __device__ inline double fn_current(double F, double phi, const EmitConsts& c,
          exp(-v * c.b_fn * (phi * sqrt(phi)) / F);
 }
 
-__device__ inline void face_field(const DevMesh& m, const double* E, int64_t f,
-                                  double& ex, double& ey, double& ez) {
+__device__ inline void face_field(const DevMesh& m, const void* E, int f32,
+                                  int64_t f, double& ex, double& ey,
+                                  double& ez) {
   const int32_t* nd = m.e_nodes + 3 * f;
-  const double4 a = ld_E(E, nd[0]);
-  const double4 b = ld_E(E, nd[1]);
-  const double4 c = ld_E(E, nd[2]);
+  const double4 a = ld_E(E, f32, nd[0]);
+  const double4 b = ld_E(E, f32, nd[1]);
+  const double4 c = ld_E(E, f32, nd[2]);
   ex = ((a.x + b.x) + c.x) / 3.0;
   ey = ((a.y + b.y) + c.y) / 3.0;
   ez = ((a.z + b.z) + c.z) / 3.0;
@@ -381,7 +387,7 @@ __device__ void emit_block(const EmitArgs& a) {
     int clamped = 0;
     if (f < m.n_emit) {
       double ex, ey, ez;
-      face_field(m, a.E, f, ex, ey, ez);
+      face_field(m, a.E, a.f32, f, ex, ey, ez);
       F = sqrt((ex * ex + ey * ey) + ez * ez);
       const double* nr = m.e_nrm + 3 * f;
       const double en = (ex * nr[0] + ey * nr[1]) + ez * nr[2];
@@ -508,13 +514,20 @@ __global__ void __launch_bounds__(kBeginBlock) k_begin(EmitArgs a,
 // wrap, absorb, walk, deposit).  Both halves only read the slots below the
 // pre-injection count, so they run side by side.
 // ---------------------------------------------------------------------------
-__device__ inline void push_role(const StepArgs& a, int g, int G, Acc& acc,
-                                 ChargeTable& T) {
+// Live particles, FP64 storage: the fixed arithmetic shared with the oracle.
+__device__ inline void push_role64(const StepArgs& a, int g, int G, Acc& acc,
+                                   ChargeTable& T) {
   const DevMesh& m = a.m;
   const int64_t n = a.scratch->inj_base;
   const Span sp = block_span(n, G, g);
   const double Q = a.Q;
   const double dt = a.dt;
+  double* X = (double*)a.x;
+  double* Y = (double*)a.y;
+  double* Z = (double*)a.z;
+  double* VX = (double*)a.vx;
+  double* VY = (double*)a.vy;
+  double* VZ = (double*)a.vz;
   for (int64_t i = sp.lo + threadIdx.x; i < sp.hi; i += blockDim.x) {
     const int t = a.tet[i];
     if (t < 0) continue;
@@ -522,8 +535,8 @@ __device__ inline void push_role(const StepArgs& a, int g, int G, Acc& acc,
     const long long qfx = fx_round(w * kFx);
     acc.n_before += 1;
     acc.q_before += qfx;
-    double x = a.x[i], y = a.y[i], z = a.z[i];
-    double vx = a.vx[i], vy = a.vy[i], vz = a.vz[i];
+    double x = X[i], y = Y[i], z = Z[i];
+    double vx = VX[i], vy = VY[i], vz = VZ[i];
     double ex, ey, ez;
     gather_field(m.tg[t], a.E, x, y, z, ex, ey, ez);
     const double qx = Q * ex, qy = Q * ey, qz = Q * ez;
@@ -537,12 +550,83 @@ __device__ inline void push_role(const StepArgs& a, int g, int G, Acc& acc,
     z = z + dz;
     int sx, sy;
     wrap(m, x, y, sx, sy);
-    a.x[i] = x;
-    a.y[i] = y;
-    a.z[i] = z;
-    a.vx[i] = vx;
-    a.vy[i] = vy;
-    a.vz[i] = vz;
+    X[i] = x;
+    Y[i] = y;
+    Z[i] = z;
+    VX[i] = vx;
+    VY[i] = vy;
+    VZ[i] = vz;
+    settle(m, a, i, x, y, z, sx, sy, t, w, qfx, acc, T, far);
+  }
+}
+
+// Live particles, mixed precision: FP32 position, velocity, field gather,
+// kick and drift; the barycentric weights, the walk and the deposition take
+// the stored FP32 position widened exactly to FP64.
+__device__ inline void push_role32(const StepArgs& a, int g, int G, Acc& acc,
+                                   ChargeTable& T) {
+  const DevMesh& m = a.m;
+  const int64_t n = a.scratch->inj_base;
+  const Span sp = block_span(n, G, g);
+  const float Q = (float)a.Q;
+  const float dt = (float)a.dt;
+  const float Lx = (float)m.Lx, Ly = (float)m.Ly;
+  const float4* E = reinterpret_cast<const float4*>(a.E);
+  float* X = (float*)a.x;
+  float* Y = (float*)a.y;
+  float* Z = (float*)a.z;
+  float* VX = (float*)a.vx;
+  float* VY = (float*)a.vy;
+  float* VZ = (float*)a.vz;
+  for (int64_t i = sp.lo + threadIdx.x; i < sp.hi; i += blockDim.x) {
+    const int t = a.tet[i];
+    if (t < 0) continue;
+    const double w = a.w[i];
+    const long long qfx = fx_round(w * kFx);
+    acc.n_before += 1;
+    acc.q_before += qfx;
+    float x = X[i], y = Y[i], z = Z[i];
+    float vx = VX[i], vy = VY[i], vz = VZ[i];
+    const TetGeom& G4 = m.tg[t];
+    double lam[4];
+    barycentric(G4, x, y, z, lam);
+    const float l0 = (float)lam[0], l1 = (float)lam[1], l2 = (float)lam[2],
+                l3 = (float)lam[3];
+    const float4 e0 = E[G4.node[0]], e1 = E[G4.node[1]], e2 = E[G4.node[2]],
+                 e3 = E[G4.node[3]];
+    const float ex = ((l0 * e0.x + l1 * e1.x) + l2 * e2.x) + l3 * e3.x;
+    const float ey = ((l0 * e0.y + l1 * e1.y) + l2 * e2.y) + l3 * e3.y;
+    const float ez = ((l0 * e0.z + l1 * e1.z) + l2 * e2.z) + l3 * e3.z;
+    const float qx = Q * ex, qy = Q * ey, qz = Q * ez;
+    vx = (vx + qx) + qx;
+    vy = (vy + qy) + qy;
+    vz = (vz + qz) + qz;
+    const float dx = dt * vx, dy = dt * vy, dz = dt * vz;
+    const bool far = (double)((dx * dx + dy * dy) + dz * dz) > m.jump_len2;
+    x = x + dx;
+    y = y + dy;
+    z = z + dz;
+    int sx = 0, sy = 0;
+    if (x >= Lx) {
+      x = x - Lx;
+      sx = 1;
+    } else if (x < 0.0f) {
+      x = x + Lx;
+      sx = -1;
+    }
+    if (y >= Ly) {
+      y = y - Ly;
+      sy = 1;
+    } else if (y < 0.0f) {
+      y = y + Ly;
+      sy = -1;
+    }
+    X[i] = x;
+    Y[i] = y;
+    Z[i] = z;
+    VX[i] = vx;
+    VY[i] = vy;
+    VZ[i] = vz;
     settle(m, a, i, x, y, z, sx, sy, t, w, qfx, acc, T, far);
   }
 }
@@ -576,9 +660,9 @@ __device__ inline void inject_role(const StepArgs& a, int g, int G, Acc& acc,
     const double l0 = (1.0 - R1) - R2;
     const double* A = m.e_abc + 9 * (int64_t)f;
     const int32_t* nd = m.e_nodes + 3 * (int64_t)f;
-    const double4 ea = ld_E(a.E, nd[0]);
-    const double4 eb = ld_E(a.E, nd[1]);
-    const double4 ec = ld_E(a.E, nd[2]);
+    const double4 ea = ld_E(a.E, a.f32, nd[0]);
+    const double4 eb = ld_E(a.E, a.f32, nd[1]);
+    const double4 ec = ld_E(a.E, a.f32, nd[2]);
     const double px = (A[0] + R1 * (A[3] - A[0])) + R2 * (A[6] - A[0]);
     const double py = (A[1] + R1 * (A[4] - A[1])) + R2 * (A[7] - A[1]);
     const double pz = (A[2] + R1 * (A[5] - A[2])) + R2 * (A[8] - A[2]);
@@ -598,12 +682,26 @@ __device__ inline void inject_role(const StepArgs& a, int g, int G, Acc& acc,
     const int64_t i = base + s;
     const double w = a.s_face ? a.s_face[f] : 1.0;
     const long long qfx = fx_round(w * kFx);
-    a.x[i] = x;
-    a.y[i] = y;
-    a.z[i] = z;
-    a.vx[i] = vx;
-    a.vy[i] = vy;
-    a.vz[i] = vz;
+    if (a.f32) {
+      // stored in FP32; the walk and deposition use the stored values
+      const float xf = (float)x, yf = (float)y, zf = (float)z;
+      ((float*)a.x)[i] = xf;
+      ((float*)a.y)[i] = yf;
+      ((float*)a.z)[i] = zf;
+      ((float*)a.vx)[i] = (float)vx;
+      ((float*)a.vy)[i] = (float)vy;
+      ((float*)a.vz)[i] = (float)vz;
+      x = xf;
+      y = yf;
+      z = zf;
+    } else {
+      ((double*)a.x)[i] = x;
+      ((double*)a.y)[i] = y;
+      ((double*)a.z)[i] = z;
+      ((double*)a.vx)[i] = vx;
+      ((double*)a.vy)[i] = vy;
+      ((double*)a.vz)[i] = vz;
+    }
     a.w[i] = w;
     a.birth[i] = f;
     a.id[i] = (a.step << 42) | ((int64_t)f << 21) | o;
@@ -618,9 +716,12 @@ __global__ void __launch_bounds__(kBlock) k_particles(StepArgs a, int g_push) {
   acc_zero(acc);
   __shared__ ChargeTable T;
   table_clear(T);
-  if ((int)blockIdx.x < g_push)
-    push_role(a, blockIdx.x, g_push, acc, T);
-  else
+  if ((int)blockIdx.x < g_push) {
+    if (a.f32)
+      push_role32(a, blockIdx.x, g_push, acc, T);
+    else
+      push_role64(a, blockIdx.x, g_push, acc, T);
+  } else
     inject_role(a, blockIdx.x - g_push, gridDim.x - g_push, acc, T);
   table_flush(T, a.charge);
   acc_flush(acc, a.acc_rows, a.acc_row0 + blockIdx.x, a.acc_stride);
@@ -638,7 +739,16 @@ __global__ void __launch_bounds__(kBlock) k_fallback(StepArgs a) {
   for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
        j += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = a.queue[j];
-    const double x = a.x[i], y = a.y[i], z = a.z[i];
+    double x, y, z;
+    if (a.f32) {
+      x = ((const float*)a.x)[i];
+      y = ((const float*)a.y)[i];
+      z = ((const float*)a.z)[i];
+    } else {
+      x = ((const double*)a.x)[i];
+      y = ((const double*)a.y)[i];
+      z = ((const double*)a.z)[i];
+    }
     const double w = a.w[i];
     const long long qfx = fx_round(w * kFx);
     const int t = scan_locate(m, x, y, z);

@@ -15,6 +15,7 @@ struct CgCtrl {
   int64_t restarts;
   double bb;            // ||b||^2
   double relres;        // last true relative residual
+  double rstart;        // ||r|| at the last (re)start (mixed inner target)
   double alpha[2], gamma[2];
 };
 
@@ -37,8 +38,18 @@ struct CgArgs {
   double tol;
   int64_t max_iter;
   double* phi;            // [n_nodes] in: guess, out: solution
-  double* E;              // [4 n_nodes] or null
+  void* E;                // [4 n_nodes] double (float if mixed) or null
   double *b, *x, *r, *u, *w, *p, *s;  // [n_free]
+  // Mixed precision: the CG recursion runs in FP32 (r, u, w, p, s below)
+  // against K in FP32, while x, b, the true residual, every reduction and
+  // the stopping tests stay FP64.  The recursion stops once its residual
+  // falls below max(tol ||b||, inner_tol ||r_start||); the true residual is
+  // then recomputed in FP64 and the FP32 recursion restarted from it
+  // (iterative refinement) until tol is met.
+  int mixed;
+  int e32;                // E in FP32 from R in FP32 (difference form)
+  double inner_tol;
+  float *r32, *u32, *w32, *p32, *s32;  // [n_free]
   double* part;           // [kCgSlots][G]
   int G;                  // workgroups of every solver kernel
   CgCtrl* ctrl;

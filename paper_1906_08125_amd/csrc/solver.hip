@@ -99,11 +99,11 @@ __device__ inline void write_partials(double* part, int stride,
 
 // y_r = sum_j val[j] x[col[j]] over the rows of this workgroup's slices;
 // emit(r, y_r) for every row r < nrows.
-template <typename F>
+template <typename T, typename F>
 __device__ inline void spmv_sell(const int32_t* __restrict__ sptr,
                                  const int32_t* __restrict__ scol,
-                                 const double* __restrict__ sval,
-                                 const double* __restrict__ x, int64_t nslices,
+                                 const T* __restrict__ sval,
+                                 const T* __restrict__ x, int64_t nslices,
                                  int64_t nrows, F&& emit) {
   const Range sl = my_range(nslices);
   const int lane = threadIdx.x & (kSell - 1);
@@ -112,7 +112,7 @@ __device__ inline void spmv_sell(const int32_t* __restrict__ sptr,
   for (int64_t s = sl.lo + sub; s < sl.hi; s += nsub) {
     const int64_t r = s * kSell + lane;
     const int32_t p0 = sptr[s], p1 = sptr[s + 1];
-    double acc = 0.0;
+    T acc = T(0);
     for (int32_t p = p0 + lane; p < p1; p += kSell) acc += sval[p] * x[scol[p]];
     if (r < nrows) emit(r, acc);
   }
@@ -126,7 +126,6 @@ __device__ inline double* slot(const CgArgs& a, int k) {
   return a.part + (size_t)k * a.G;
 }
 
-// x = phi on free nodes and b_i = coef c_i + E0 g_i.
 __device__ inline void ctrl_reset(CgCtrl* c) {
   CgCtrl z;
   z.state = CG_ITER;
@@ -136,6 +135,7 @@ __device__ inline void ctrl_reset(CgCtrl* c) {
   z.restarts = 0;
   z.bb = 0.0;
   z.relres = 0.0;
+  z.rstart = 0.0;
   z.alpha[0] = z.alpha[1] = 0.0;
   z.gamma[0] = z.gamma[1] = 0.0;
   *c = z;
@@ -150,6 +150,7 @@ __device__ inline void report(const CgCtrl* c, CgReport* r, int64_t seq,
   __hip_atomic_store(&r->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
+// x = phi on free nodes and b_i = coef c_i + E0 g_i; (b,b).
 __global__ void __launch_bounds__(512) k_cg_load(CgArgs a) {
   const DevMesh& m = a.m;
   if (blockIdx.x == 0 && threadIdx.x == 0) ctrl_reset(a.ctrl);
@@ -168,16 +169,28 @@ __global__ void __launch_bounds__(512) k_cg_load(CgArgs a) {
 
 // r = b - K x, u = D^-1 r, (r,r): the initial residual, and the re-check of
 // the true residual once the recursive one has converged.
+// Mixed precision: the FP64 residual is rounded once into the FP32
+// recursion vectors.
 __global__ void __launch_bounds__(512) k_cg_resid(CgArgs a) {
   const DevMesh& m = a.m;
   double v[1] = {0.0};
-  spmv_sell(m.k_sptr, m.k_scol, m.k_sval, a.x, m.k_nslices, m.n_free,
-            [&](int64_t i, double s) {
-              const double ri = a.b[i] - s;
-              a.r[i] = ri;
-              a.u[i] = ri * m.invdiag[i];
-              v[0] += ri * ri;
-            });
+  if (a.mixed) {
+    spmv_sell(m.k_sptr, m.k_scol, m.k_sval, a.x, m.k_nslices, m.n_free,
+              [&](int64_t i, double s) {
+                const double ri = a.b[i] - s;
+                a.r32[i] = (float)ri;
+                a.u32[i] = (float)(ri * m.invdiag[i]);
+                v[0] += ri * ri;
+              });
+  } else {
+    spmv_sell(m.k_sptr, m.k_scol, m.k_sval, a.x, m.k_nslices, m.n_free,
+              [&](int64_t i, double s) {
+                const double ri = a.b[i] - s;
+                a.r[i] = ri;
+                a.u[i] = ri * m.invdiag[i];
+                v[0] += ri * ri;
+              });
+  }
   write_partials<1>(slot(a, 1), a.G, v);
 }
 
@@ -207,6 +220,7 @@ __global__ void __launch_bounds__(512) k_cg_start(CgArgs a, int after_recheck,
     if (!after_recheck) c->bb = t[0];
     c->iters = done_iters;
     c->relres = bn > 0.0 ? rn / bn : 0.0;
+    c->rstart = rn;
     const int32_t state = done ? CG_DONE : (noconv ? CG_NOCONV : CG_ITER);
     c->state = state;
     if (!done && !noconv) c->restarts += 1;
@@ -219,13 +233,23 @@ __global__ void __launch_bounds__(512) k_cg_start(CgArgs a, int after_recheck,
   if (done || noconv) return;
   const DevMesh& m = a.m;
   double v[2] = {0.0, 0.0};
-  spmv_sell(m.k_sptr, m.k_scol, m.k_sval, a.u, m.k_nslices, m.n_free,
-            [&](int64_t i, double s) {
-              a.w[i] = s;
-              const double ui = a.u[i];
-              v[0] += a.r[i] * ui;
-              v[1] += s * ui;
-            });
+  if (a.mixed) {
+    spmv_sell(m.k_sptr, m.k_scol, m.k_sval32, a.u32, m.k_nslices, m.n_free,
+              [&](int64_t i, float s) {
+                a.w32[i] = s;
+                const double ui = a.u32[i];
+                v[0] += (double)a.r32[i] * ui;
+                v[1] += (double)s * ui;
+              });
+  } else {
+    spmv_sell(m.k_sptr, m.k_scol, m.k_sval, a.u, m.k_nslices, m.n_free,
+              [&](int64_t i, double s) {
+                a.w[i] = s;
+                const double ui = a.u[i];
+                v[0] += a.r[i] * ui;
+                v[1] += s * ui;
+              });
+  }
   write_partials<2>(slot(a, 2), a.G, v);
 }
 
@@ -257,7 +281,9 @@ __global__ void __launch_bounds__(512) k_cg_upd(CgArgs a, int it) {
     // iterating, so every workgroup takes the same decision
     const double rn = sqrt(t3[0]);
     const double bn = sqrt(c->bb);
-    if (rn <= a.tol * bn || c->iters + it >= a.max_iter) {
+    double thr = a.tol * bn;
+    if (a.mixed) thr = fmax(thr, a.inner_tol * c->rstart);
+    if (rn <= thr || c->iters + it >= a.max_iter) {
       if (blockIdx.x == 0 && threadIdx.x == 0) {
         c->state = CG_RECHECK;
         c->iters_final = c->iters + it;
@@ -278,6 +304,24 @@ __global__ void __launch_bounds__(512) k_cg_upd(CgArgs a, int it) {
   const Range rows = my_range(m.n_free);
   double v[2] = {0.0, 0.0};
   const bool first = it == 0;
+  if (a.mixed) {
+    const float al = (float)alpha, be = (float)beta;
+    for (int64_t i = rows.lo + threadIdx.x; i < rows.hi; i += blockDim.x) {
+      const float pi = first ? a.u32[i] : a.u32[i] + be * a.p32[i];
+      const float si = first ? a.w32[i] : a.w32[i] + be * a.s32[i];
+      a.p32[i] = pi;
+      a.s32[i] = si;
+      a.x[i] += alpha * (double)pi;
+      const float ri = a.r32[i] - al * si;
+      a.r32[i] = ri;
+      const float ui = ri * m.invdiag32[i];
+      a.u32[i] = ui;
+      v[0] += (double)ri * ri;
+      v[1] += (double)ri * ui;
+    }
+    write_partials<2>(slot(a, 4 + 2 * (it & 1)), a.G, v);
+    return;
+  }
   for (int64_t i = rows.lo + threadIdx.x; i < rows.hi; i += blockDim.x) {
     const double pi = first ? a.u[i] : a.u[i] + beta * a.p[i];
     const double si = first ? a.w[i] : a.w[i] + beta * a.s[i];
@@ -301,12 +345,56 @@ __global__ void __launch_bounds__(512) k_cg_spmv(CgArgs a, int it,
   if (state != CG_ITER) return;
   const DevMesh& m = a.m;
   double v[1] = {0.0};
-  spmv_sell(m.k_sptr, m.k_scol, m.k_sval, a.u, m.k_nslices, m.n_free,
-            [&](int64_t i, double s) {
-              a.w[i] = s;
-              v[0] += s * a.u[i];
-            });
+  if (a.mixed) {
+    spmv_sell(m.k_sptr, m.k_scol, m.k_sval32, a.u32, m.k_nslices, m.n_free,
+              [&](int64_t i, float s) {
+                a.w32[i] = s;
+                v[0] += (double)s * a.u32[i];
+              });
+  } else {
+    spmv_sell(m.k_sptr, m.k_scol, m.k_sval, a.u, m.k_nslices, m.n_free,
+              [&](int64_t i, double s) {
+                a.w[i] = s;
+                v[0] += s * a.u[i];
+              });
+  }
   write_partials<1>(slot(a, 8 + (it & 1)), a.G, v);
+}
+
+// Mixed precision: E = R x in the difference form
+//   E_i = sum_j R_ij (x_j - phi_i) + S_i phi_i,   S_i = sum_j R_ij (FP64),
+// with R in FP32: the differences are of the size of E h, so rounding R
+// costs a relative error of about 2^-24 in E, while R_ij x_j alone would
+// lose the ratio |phi| / (|E| h) to cancellation.  E is stored in FP32.
+__device__ inline void field_mixed(const CgArgs& a, bool zero) {
+  const DevMesh& m = a.m;
+  const Range sl = my_range(m.f_nslices);
+  const int lane = threadIdx.x & (kSell - 1);
+  const int sub = threadIdx.x / kSell;
+  const int nsub = blockDim.x / kSell;
+  const int64_t np = m.f_np;
+  for (int64_t s = sl.lo + sub; s < sl.hi; s += nsub) {
+    const int64_t r = s * kSell + lane;
+    if (r >= m.n_nodes) continue;
+    const int32_t p0 = m.f_sptr[s], p1 = m.f_sptr[s + 1];
+    double ex = 0.0, ey = 0.0, ez = 0.0;
+    if (!zero) {
+      const int32_t fi = m.node2free[r];
+      const double pi = fi >= 0 ? a.x[fi] : 0.0;
+      for (int32_t p = p0 + lane; p < p1; p += kSell) {
+        const double d = a.x[m.f_scol[p]] - pi;
+        ex += (double)m.f_sval32[p] * d;
+        ey += (double)m.f_sval32[np + p] * d;
+        ez += (double)m.f_sval32[2 * np + p] * d;
+      }
+      const double4 S = m.f_rowsum[r];
+      ex += S.x * pi;
+      ey += S.y * pi;
+      ez += S.z * pi;
+    }
+    reinterpret_cast<float4*>(a.E)[r] =
+        make_float4((float)ex, (float)ey, (float)ez, 0.0f);
+  }
 }
 
 // phi on every node (Dirichlet nodes 0) and the nodal field E = R x.
@@ -340,6 +428,10 @@ __global__ void __launch_bounds__(512) k_cg_field(CgArgs a) {
     }
   }
   if (!a.E) return;
+  if (a.e32) {
+    field_mixed(a, zero);
+    return;
+  }
   const Range sl = my_range(m.f_nslices);
   const int lane = threadIdx.x & (kSell - 1);
   const int sub = threadIdx.x / kSell;

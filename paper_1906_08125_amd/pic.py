@@ -247,11 +247,17 @@ class State:
     """Device particle SoA + fields for one run."""
 
     def __init__(self, mesh: Mesh, capacity: int, precision: int = PIC_FP64,
-                 device="cuda"):
+                 device="cuda", solve_precision: int | None = None,
+                 inner_tol: float = 1e-4):
+        """precision: PIC_FP64, or PIC_MIXED for FP32 particles and field;
+        solve_precision (default: precision) picks the Poisson solver."""
         torch = _torch()
         self.mesh = mesh
         self.capacity = int(capacity)
         self.precision = precision
+        self.solve_precision = (precision if solve_precision is None
+                                else solve_precision)
+        self.inner_tol = inner_tol
         rd = torch.float64 if precision == PIC_FP64 else torch.float32
         n = self.capacity
         mk = lambda dt: torch.zeros(n, dtype=dt, device=device)
@@ -264,7 +270,7 @@ class State:
         self.n_slots = torch.zeros(1, dtype=torch.int32, device=device)
         nn = mesh.n_nodes
         self.phi = torch.zeros(nn, dtype=torch.float64, device=device)
-        self.E = torch.zeros(4 * nn, dtype=torch.float64, device=device)
+        self.E = torch.zeros(4 * nn, dtype=rd, device=device)
         self.charge = torch.zeros(nn, dtype=torch.int64, device=device)
         self._p = Particles(n, precision, 0, *[
             t.data_ptr() for t in (self.x, self.y, self.z, self.vx, self.vy,
@@ -274,8 +280,10 @@ class State:
                          self.charge.data_ptr())
 
     def init_field(self, E0, tol=1e-12, max_iter=20000):
+        """phi and E of the empty gap (the field type follows precision)."""
         st = self.mesh.poisson_solve(None, 0.0, E0, self.phi, self.E, tol,
-                                     max_iter)
+                                     max_iter, precision=self.precision,
+                                     inner_tol=self.inner_tol)
         return st
 
     def step(self, *, dt, E0, w_sp, phi_w, step0, seed, n_steps=1, instance=0,
@@ -288,7 +296,8 @@ class State:
         prm = StepParams(dt, E0, w_sp, phi_w, j_scale, seed, step0, instance,
                          None if s_face is None else s_face.data_ptr(),
                          resort_every, 0,
-                         SolveParams(tol, 1e-4, max_iter, self.precision))
+                         SolveParams(tol, self.inner_tol, max_iter,
+                                     self.solve_precision))
         _check(load_library().pic_step(self.mesh.handle, C.byref(self._p),
                                        C.byref(self._f), C.byref(prm),
                                        int(n_steps), _ptr(stats),

@@ -178,8 +178,11 @@ def test_emission_rate_matches_oracle(pic):
 
 
 def _run_pair(pic, cfg, n_steps, live_charge, n_live, cap, seed=None,
-              resort_every=0):
-    """live_charge: electrons in flight wanted (None = physical emission)."""
+              resort_every=0, precision=0, solve_precision=None,
+              phi_err=None):
+    """live_charge: electrons in flight wanted (None = physical emission).
+    phi_err: a list that receives the relative L2 distance of the device
+    potential from the oracle's after every step."""
     tip = cfg.mesh()
     om = O.OracleMesh(tip, cfg.emit_zmin)
     ost = O.OracleState(om, cap)
@@ -189,7 +192,8 @@ def _run_pair(pic, cfg, n_steps, live_charge, n_live, cap, seed=None,
     j_scale = 1.0 if live_charge is None else live_charge / per_run
     w_sp = per_run * j_scale / n_live
     gm = pic.Mesh(tip, cfg.emit_zmin)
-    gs = pic.State(gm, cap)
+    gs = pic.State(gm, cap, precision=precision,
+                   solve_precision=solve_precision)
     gs.init_field(cfg.E0, tol=cfg.tol)
     kw = dict(dt=cfg.dt, E0=cfg.E0, w_sp=w_sp, phi_w=cfg.phi_w,
               seed=cfg.seed if seed is None else seed, j_scale=j_scale,
@@ -199,6 +203,8 @@ def _run_pair(pic, cfg, n_steps, live_charge, n_live, cap, seed=None,
         so_all.append(ost.step(step=k, **kw))
         sg_all.append(pic.State.decode_stats(
             gs.step(step0=k, resort_every=resort_every, **kw))[0])
+        if phi_err is not None:
+            phi_err.append(_rel(gs.phi.cpu().numpy(), ost.phi))
     torch.cuda.synchronize()
     return om, ost, gm, gs, so_all, sg_all
 
@@ -317,3 +323,78 @@ def test_resort_compacts_and_orders(pic):
     assert n == sg[-1]["n_after"] == sg[-1]["n_slots"]
     assert (tet >= 0).all() and (np.diff(tet) >= 0).all()
     _compare_runs(ost, gs, so, sg)
+
+
+# ---------------------------------------------------------------------------
+# Mixed precision: FP32 particles, field and CG recursion against the FP64
+# oracle.  Bound: relative L2 <= 1e-6 for the potential (every step) and the
+# positions; the particle sets may differ by the rare particle whose count,
+# absorption or injection decision sits within FP32 rounding of a threshold.
+
+def _compare_mixed(ost, gs, so_all, sg_all, phi_err, bound=1e-6):
+    assert max(phi_err) < bound, phi_err
+    for k, (so, sg) in enumerate(zip(so_all, sg_all)):
+        assert sg["status"] == 0
+        assert sg["cg_relres"] <= 1e-9 or sg["cg_iters"] == 0
+        assert sg["q_before"] + sg["q_inj"] - sg["q_anode"] - \
+            sg["q_cathode"] == sg["q_after"]
+        for key in ("n_inj", "n_anode", "n_cathode", "n_after"):
+            assert abs(so[key] - sg[key]) <= 2 + 1e-3 * so[key], (k, key)
+    P, Q = gs.live(), ost.particles()
+    common, ia, ib = np.intersect1d(P["id"], Q["id"], return_indices=True)
+    assert common.size >= 0.999 * max(P["id"].size, Q["id"].size)
+    pos_g = np.stack([P["x"][ia], P["y"][ia], P["z"][ia]], 1)
+    pos_o = np.stack([Q["x"][ib], Q["y"][ib], Q["z"][ib]], 1)
+    assert _rel(pos_g, pos_o) < bound
+    vel_g = np.stack([P["vx"][ia], P["vy"][ia], P["vz"][ia]], 1)
+    vel_o = np.stack([Q["vx"][ib], Q["vy"][ib], Q["vz"][ib]], 1)
+    assert _rel(vel_g, vel_o) < bound
+    # where the FP32 positions sit in the same tet, the ids agree exactly
+    assert (P["tet"][ia] == Q["tet"][ib]).mean() > 0.999
+
+
+def test_poisson_mixed_refinement(pic):
+    """FP32 recursion + FP64 refinement reaches the FP64 tolerance on the
+    true residual; phi then matches the oracle like the FP64 solver."""
+    cfg = W.config_tiny()
+    tip = cfg.mesh()
+    om = O.OracleMesh(tip, cfg.emit_zmin)
+    rng = np.random.default_rng(7)
+    c = rng.integers(-2**44, 2**44, tip.n_nodes).astype(np.int64)
+    phi_o, info = om.poisson_solve(c, 1e-3, cfg.E0, tol=1e-12)
+    assert info["status"] == 0
+    E_o = om.field(phi_o)
+    gm = pic.Mesh(tip, cfg.emit_zmin)
+    phi = torch.zeros(tip.n_nodes, dtype=torch.float64, device="cuda")
+    E = torch.zeros(4 * tip.n_nodes, dtype=torch.float32, device="cuda")
+    st = gm.poisson_solve(_dev(c), 1e-3, cfg.E0, phi, E, tol=1e-11,
+                          precision=pic.PIC_MIXED, inner_tol=1e-3)
+    s = pic.Mesh.solve_stats(st)
+    assert s["status"] == 0 and s["relres"] <= 1e-11
+    assert s["restarts"] >= 2          # refinement sweeps did happen
+    assert _rel(phi.cpu().numpy(), phi_o) < 1e-9
+    Eg = E.cpu().numpy().reshape(-1, 4)[:, :3].astype(np.float64)
+    assert _rel(Eg, E_o) < 1e-6
+
+
+def test_pic_step_mixed_tiny(pic):
+    """Mixed precision PIC on the tiny tip, physical emission, 10 steps."""
+    cfg = W.config_tiny()
+    err = []
+    om, ost, gm, gs, so, sg = _run_pair(pic, cfg, 10, None, 10_000, 60_000,
+                                        precision=pic.PIC_MIXED,
+                                        phi_err=err)
+    assert gs.x.dtype == torch.float32 and gs.E.dtype == torch.float32
+    _compare_mixed(ost, gs, so, sg, err)
+
+
+def test_pic_step_mixed_space_charge(pic):
+    """Mixed precision with space charge and re-sorting, 36 steps."""
+    cfg = W.config_tiny()
+    err = []
+    om, ost, gm, gs, so, sg = _run_pair(pic, cfg, 36, 0.01, 3000, 60_000,
+                                        resort_every=5,
+                                        precision=pic.PIC_MIXED,
+                                        phi_err=err)
+    assert all(s["cg_iters"] > 0 for s in sg[1:])
+    _compare_mixed(ost, gs, so, sg, err)
