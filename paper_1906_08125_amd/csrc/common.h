@@ -135,25 +135,31 @@ __host__ __device__ inline double vol6_filtered(const double* a,
 // multilinearly into 6 x 8 triple products, each turned into four doubles
 // that sum to it exactly, and all of them are accumulated into one
 // nonoverlapping expansion (Shewchuk 1997, Grow-Expansion with zero
-// elimination).  The sign of the largest component is the answer.
+// elimination).  The sign of the largest component is the answer.  When
+// every difference is exact (all low parts zero, the usual case for a point
+// near the tet) only the 6 products of high parts are nonzero, and the
+// expansion stays short.
 __host__ __device__ inline int vol6_sign_exact(const double* a,
                                                const double* b,
                                                const double* c,
                                                const double* d) {
   double U[3][2], V[3][2], W[3][2];
+  bool tails = false;
   for (int k = 0; k < 3; ++k) {
     ef_sum(b[k], -a[k], U[k][0], U[k][1]);
     ef_sum(c[k], -a[k], V[k][0], V[k][1]);
     ef_sum(d[k], -a[k], W[k][0], W[k][1]);
+    tails = tails || U[k][1] != 0.0 || V[k][1] != 0.0 || W[k][1] != 0.0;
   }
   // permutations of (x, y, z) for rows (U, V, W) and their signs
   const int P[6][3] = {{0, 1, 2}, {1, 2, 0}, {2, 0, 1},
                        {0, 2, 1}, {2, 1, 0}, {1, 0, 2}};
   double ex[200];
   int len = 0;
+  const int nh = tails ? 8 : 1;
   for (int s = 0; s < 6; ++s) {
     const double sg = s < 3 ? 1.0 : -1.0;
-    for (int h = 0; h < 8; ++h) {
+    for (int h = 0; h < nh; ++h) {
       const double f0 = U[P[s][0]][h & 1];
       const double f1 = V[P[s][1]][(h >> 1) & 1];
       const double f2 = W[P[s][2]][(h >> 2) & 1];

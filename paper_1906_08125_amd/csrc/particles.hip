@@ -230,6 +230,37 @@ __device__ int scan_locate(const DevMesh& m, double x, double y, double z) {
   return -1;
 }
 
+// The same canonical location with the 64 lanes of a wave testing 64
+// candidates at a time (the point is uniform across the wave; every lane
+// must call it).  The lowest lane holding the point gives the lowest index.
+__device__ int scan_locate_wave(const DevMesh& m, double x, double y,
+                                double z) {
+  if (!(x >= m.b0[0] && x <= m.b1[0] && y >= m.b0[1] && y <= m.b1[1] &&
+        z >= m.b0[2] && z <= m.b1[2]))
+    return -1;
+  const int bx = bucket_axis(x, m.b0[0], m.binv[0], m.nb[0]);
+  const int by = bucket_axis(y, m.b0[1], m.binv[1], m.nb[1]);
+  const int bz = bucket_axis(z, m.b0[2], m.binv[2], m.nb[2]);
+  const int64_t id = ((int64_t)bx * m.nb[1] + by) * m.nb[2] + bz;
+  const double p[3] = {x, y, z};
+  const int lane = threadIdx.x & 63;
+  const int q1 = m.bstart[id + 1];
+  for (int base = m.bstart[id]; base < q1; base += 64) {
+    const int q = base + lane;
+    bool hit = false;
+    if (q < q1) {
+      const double* v = m.tw[m.bitem[q]].v;
+      hit = vol6_sign(p, v + 3, v + 6, v + 9) >= 0 &&
+            vol6_sign(v, p, v + 6, v + 9) >= 0 &&
+            vol6_sign(v, v + 3, p, v + 9) >= 0 &&
+            vol6_sign(v, v + 3, v + 6, p) >= 0;
+    }
+    const unsigned long long mask = __ballot(hit);
+    if (mask) return m.bitem[base + __ffsll((long long)mask) - 1];
+  }
+  return -1;
+}
+
 // After the drift: wrap, absorb at the anode, locate, deposit.
 // Per-workgroup node-charge table in LDS (open addressing on the node id).
 // Particles of one workgroup share few nodes, so accumulating their int64
@@ -736,8 +767,11 @@ __global__ void __launch_bounds__(kBlock) k_fallback(StepArgs a) {
   const int64_t n = a.scratch->n_fallback;
   Acc acc;
   acc_zero(acc);
-  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
-       j += (int64_t)gridDim.x * blockDim.x) {
+  // one wave per queued particle
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  const bool lead = (threadIdx.x & 63) == 0;
+  for (int64_t j = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
+       j < n; j += waves) {
     const int64_t i = a.queue[j];
     double x, y, z;
     if (a.f32) {
@@ -751,7 +785,8 @@ __global__ void __launch_bounds__(kBlock) k_fallback(StepArgs a) {
     }
     const double w = a.w[i];
     const long long qfx = fx_round(w * kFx);
-    const int t = scan_locate(m, x, y, z);
+    const int t = scan_locate_wave(m, x, y, z);
+    if (!lead) continue;
     if (t >= 0) {
       a.tet[i] = t;
       deposit_one(m.tg[t], x, y, z, w, a.charge);
@@ -825,12 +860,16 @@ __global__ void __launch_bounds__(kBlock) k_locate(LocateArgs a) {
 __global__ void __launch_bounds__(kBlock) k_locate_scan(LocateArgs a) {
   const DevMesh& m = a.m;
   const int64_t n = *a.n_queue;
-  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
-       j += (int64_t)gridDim.x * blockDim.x) {
+  // one wave per queued point
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t j = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
+       j < n; j += waves) {
     const int64_t i = a.queue[j];
-    const int t = scan_locate(m, a.x[i], a.y[i], a.z[i]);
-    a.tet[i] = t;
-    a.where[i] = t >= 0 ? PIC_WHERE_INSIDE : PIC_WHERE_OUTSIDE;
+    const int t = scan_locate_wave(m, a.x[i], a.y[i], a.z[i]);
+    if ((threadIdx.x & 63) == 0) {
+      a.tet[i] = t;
+      a.where[i] = t >= 0 ? PIC_WHERE_INSIDE : PIC_WHERE_OUTSIDE;
+    }
   }
 }
 
