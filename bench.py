@@ -30,17 +30,18 @@ def log(*a):
 
 
 def solve_bytes(info, iters):
-    """Algorithmic HBM bytes of one solve launch (warm-started PCG + field
-    recovery): RHS, one true-residual SpMV per (re)start, 2 SpMVs worth of
-    vector traffic per iteration, the potential scatter and R phi."""
+    """Algorithmic HBM bytes of one step's solve: the fused residual + field
+    pass over phi (rows: node map, own phi, charge, Neumann load, x, r, u,
+    D^-1, E; entries: node column, K, R (3)), the convergence test, and per
+    CG iteration the update (7 vector reads, 5 writes) and the K u product
+    (column + value per entry, u and w per row).  A re-check after
+    iterations adds a scatter and another fused pass."""
     n, nnz = info["n_free"], info["nnz"]
     N, nf = info["n_nodes"], info["nnz_field"]
-    rhs = 44 * n                               # charge, map, g, b, phi, x
-    resid = 12 * nnz + 4 * (n + 1) + 32 * n    # val+col, rowptr, b, r, u, D^-1
-    it = 12 * nnz + 4 * (n + 1) + 112 * n      # SpMV + 14 vector streams
-    scatter = 20 * n
-    field = 28 * nf + 4 * (N + 1) + 32 * N     # val(3)+col, rowptr, E write
-    return rhs + resid + iters * it + scatter + field
+    fused = 100 * n + 36 * nnz + 28 * (nf - nnz) + 40 * (N - n)
+    it = 96 * n + 12 * nnz + 16 * n
+    recheck = (20 * n + fused) if iters > 0 else 0
+    return fused + iters * it + recheck
 
 
 def push_bytes(n_live, real_bytes=8):
@@ -234,6 +235,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision leg")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run one plain 1 GiB device copy (the "
+                         "reference kernel for HBM byte counters)")
     ap.add_argument("--inner-tol", type=float, default=1e-4,
                     help="FP32 inner CG target of the mixed leg")
     args = ap.parse_args()
@@ -241,6 +245,14 @@ def main():
         print("bench.py runs on one GPU only: the multi-GPU layout of this "
               "PIC cycle is a design (see DESIGN.md), not a build", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 1 GiB read + 1 GiB written")
+        del src, dst
     out, ctx = run_gpu(args)
     if not args.no_cpu_baseline:
         t0 = time.time()

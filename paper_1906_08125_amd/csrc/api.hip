@@ -107,7 +107,6 @@ fp::CgArgs cg_args(const pic_mesh* h, const int64_t* charge, double w_sp,
   a.max_iter = prm->max_iter;
   a.phi = phi;
   a.E = E;
-  a.b = h->cg_vec[0];
   a.x = h->cg_vec[1];
   a.r = h->cg_vec[2];
   a.u = h->cg_vec[3];
@@ -152,12 +151,12 @@ hipError_t cg_wait(pic_mesh* h, int64_t seq, fp::CgReport& out) {
   return hipSuccess;
 }
 
-// One Poisson solve: residual and convergence test, the first batch of
-// `spec` CG iterations, a report of the state and -- before waiting for it --
-// the potential scatter and nodal field, so that the host's decision
-// overlaps the field kernel.  When the report says "not converged", further
-// batches follow (a true-residual re-check when the recursive residual
-// converges), and the field is recomputed at the end.  Blocks the calling
+// One Poisson solve: the resfield pass (residual of the warm start and the
+// field of phi) and the convergence test, then -- before waiting -- a first
+// batch of `spec` CG iterations (they return at once if the test passed).
+// While the report says "not converged", further batches follow, and a
+// re-check (scatter + resfield + test) when the recursive residual has
+// converged.  The field is always that of the final phi.  Blocks the calling
 // thread at the waits.  Returns the iterations done.
 hipError_t run_solve(pic_mesh* h, const fp::CgArgs& a0, int spec, hipStream_t s,
                      int64_t* iters_out) {
@@ -173,13 +172,10 @@ hipError_t run_solve(pic_mesh* h, const fp::CgArgs& a0, int spec, hipStream_t s,
     it += batch;
   }
   if ((e = hipEventRecord(h->rb_event, s)) != hipSuccess) return e;
-  if ((e = fp::cg_launch_field(a, s)) != hipSuccess) return e;
   fp::CgReport r;
   if ((e = cg_wait(h, seq, r)) != hipSuccess) return e;
-  bool extra = false;
   for (int guard = 0; guard < (1 << 20); ++guard) {
     if (r.state == fp::CG_DONE || r.state == fp::CG_NOCONV) break;
-    extra = true;
     seq = ++h->cg_seq;
     if (r.state == fp::CG_RECHECK) {
       if ((e = fp::cg_launch_recheck(a, seq, s)) != hipSuccess) return e;
@@ -194,7 +190,7 @@ hipError_t run_solve(pic_mesh* h, const fp::CgArgs& a0, int spec, hipStream_t s,
     if ((e = cg_wait(h, seq, r)) != hipSuccess) return e;
   }
   if (iters_out) *iters_out = r.iters;
-  return extra ? fp::cg_launch_field(a, s) : hipSuccess;
+  return hipSuccess;
 }
 
 pic_status check_solve(const pic_solve_params* p) {

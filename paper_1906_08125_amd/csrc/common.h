@@ -58,18 +58,25 @@ struct DevMesh {
   const double* g_unit;      // Neumann load per unit E0 [n_free]
   const int32_t* free2node;  // [n_free]
   const int32_t* node2free;  // [n_nodes], -1 for Dirichlet
-  // stiffness K (rows and columns free nodes) and nodal field operator R
-  // (rows all nodes, columns free nodes, three components) in sliced
-  // ELLPACK, kSell rows per slice
-  int64_t k_nslices, f_nslices, f_np;
+  // Stiffness K (rows and columns free nodes) in sliced ELLPACK, kSell rows
+  // per slice.  The nodal field operator R (rows all nodes, columns free
+  // nodes, three components) has, on a free row, exactly the columns of
+  // that row of K: its free rows share K's layout (k_sptr, slot order) with
+  // columns given as node ids (k_ncol), so one pass over phi yields both
+  // K phi and R phi.  Its Dirichlet rows (dir_nodes order) form a second,
+  // small sliced ELLPACK.
+  int64_t k_nslices, k_np, d_nslices, d_np;
   const int32_t* k_sptr;   // [k_nslices + 1] slice offsets
-  const int32_t* k_scol;
+  const int32_t* k_scol;   // free-index columns
+  const int32_t* k_ncol;   // the same columns as node ids
   const double* k_sval;
   const float* k_sval32;
-  const int32_t* f_sptr;
-  const int32_t* f_scol;
-  const double* f_sval;    // [3][f_np]
-  const float* f_sval32;   // [3][f_np]
+  const double* r_sval;    // [3][k_np] R on the free rows
+  const float* r_sval32;   // [3][k_np]
+  const int32_t* d_sptr;   // [d_nslices + 1]
+  const int32_t* d_ncol;   // node-id columns
+  const double* d_sval;    // [3][d_np] R on the Dirichlet rows
+  const float* d_sval32;   // [3][d_np]
   const double4* f_rowsum; // [n_nodes] FP64 row sums of R (w unused)
   // emitting faces
   const int32_t* e_tet;

@@ -342,12 +342,37 @@ pic_status build_mesh(const pic_mesh_desc* d, pic_mesh* h, std::string& msg) {
         }
     return np;
   };
-  std::vector<int32_t> k_sptr, k_scol, f_sptr, f_scol;
-  std::vector<double> k_sval, f_sval;
+  // R on the free rows in K's column order (both rows list the sorted free
+  // neighbours of the node), and R on the Dirichlet rows
+  std::vector<double> rf[3];
+  for (int64_t fi = 0; fi < NF; ++fi) {
+    const int32_t n = free2node[fi];
+    for (int32_t p = frow[n]; p < frow[n + 1]; ++p)
+      for (int c = 0; c < 3; ++c) rf[c].push_back(fv[c][p]);
+  }
+  std::vector<int32_t> ncol(col.size());
+  for (size_t k = 0; k < col.size(); ++k) ncol[k] = free2node[col[k]];
+  const int64_t ND = (int64_t)dir_nodes.size();
+  std::vector<int32_t> drow(ND + 1, 0), dcol;
+  std::vector<double> dv[3];
+  for (int64_t di = 0; di < ND; ++di) {
+    const int32_t n = dir_nodes[di];
+    for (int32_t p = frow[n]; p < frow[n + 1]; ++p) {
+      dcol.push_back(free2node[fcol[p]]);
+      for (int c = 0; c < 3; ++c) dv[c].push_back(fv[c][p]);
+    }
+    drow[di + 1] = (int32_t)dcol.size();
+  }
+  std::vector<int32_t> k_sptr, k_scol, k_ncol, d_sptr, d_ncol, k_sptr2;
+  std::vector<double> k_sval, r_sval, d_sval;
   const int64_t k_np = to_sell(rowptr, col, {&val}, NF, 0, k_sptr, k_scol, k_sval);
-  const int64_t f_np = to_sell(frow, fcol, {&fv[0], &fv[1], &fv[2]}, N, 0, f_sptr,
-                               f_scol, f_sval);
-  if (k_np >= (1ll << 31) || f_np >= (1ll << 31)) {
+  {
+    to_sell(rowptr, ncol, {&rf[0], &rf[1], &rf[2]}, NF, free2node.empty() ? 0 : free2node[0],
+            k_sptr2, k_ncol, r_sval);
+  }
+  const int64_t d_np = to_sell(drow, dcol, {&dv[0], &dv[1], &dv[2]}, ND,
+                               free2node.empty() ? 0 : free2node[0], d_sptr, d_ncol, d_sval);
+  if (k_np >= (1ll << 31) || d_np >= (1ll << 31)) {
     msg = "mesh_create: padded matrix too large for 32-bit offsets";
     return PIC_E_ARG;
   }
@@ -482,19 +507,23 @@ pic_status build_mesh(const pic_mesh_desc* d, pic_mesh* h, std::string& msg) {
   M.bitem = upload(h, bitem, err);
   {
     std::vector<float> k_sval32(k_sval.begin(), k_sval.end());
-    std::vector<float> f_sval32(f_sval.begin(), f_sval.end());
+    std::vector<float> r_sval32(r_sval.begin(), r_sval.end());
+    std::vector<float> d_sval32(d_sval.begin(), d_sval.end());
     M.k_nslices = (int64_t)k_sptr.size() - 1;
+    M.k_np = k_np;
     M.k_sptr = upload(h, k_sptr, err);
     M.k_scol = upload(h, k_scol, err);
+    M.k_ncol = upload(h, k_ncol, err);
     M.k_sval = upload(h, k_sval, err);
     M.k_sval32 = upload(h, k_sval32, err);
-    M.f_nslices = (int64_t)f_sptr.size() - 1;
-    M.f_np = f_np;
-    M.f_sptr = upload(h, f_sptr, err);
-    M.f_scol = upload(h, f_scol, err);
-    M.f_sval = upload(h, f_sval, err);
-    M.f_sval32 = upload(h, f_sval32, err);
-    (void)k_np;
+    M.r_sval = upload(h, r_sval, err);
+    M.r_sval32 = upload(h, r_sval32, err);
+    M.d_nslices = (int64_t)d_sptr.size() - 1;
+    M.d_np = d_np;
+    M.d_sptr = upload(h, d_sptr, err);
+    M.d_ncol = upload(h, d_ncol, err);
+    M.d_sval = upload(h, d_sval, err);
+    M.d_sval32 = upload(h, d_sval32, err);
   }
   {
     // walk seeds: lowest-index tet whose centroid lies in each bucket

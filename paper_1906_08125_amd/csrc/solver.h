@@ -39,7 +39,7 @@ struct CgArgs {
   int64_t max_iter;
   double* phi;            // [n_nodes] in: guess, out: solution
   void* E;                // [4 n_nodes] double (float if mixed) or null
-  double *b, *x, *r, *u, *w, *p, *s;  // [n_free]
+  double *x, *r, *u, *w, *p, *s;  // [n_free]
   // Mixed precision: the CG recursion runs in FP32 (r, u, w, p, s below)
   // against K in FP32, while x, b, the true residual, every reduction and
   // the stopping tests stay FP64.  The recursion stops once its residual
@@ -66,6 +66,5 @@ hipError_t cg_launch_begin(const CgArgs& a, int64_t seq, hipStream_t s);
 hipError_t cg_launch_iters(const CgArgs& a, int it0, int n, int64_t seq,
                            hipStream_t s);
 hipError_t cg_launch_recheck(const CgArgs& a, int64_t seq, hipStream_t s);
-hipError_t cg_launch_field(const CgArgs& a, hipStream_t s);
 
 }  // namespace fp

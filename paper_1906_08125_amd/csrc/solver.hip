@@ -1,17 +1,22 @@
 // Poisson solve on the free nodes (Eq. poisson with Eq. poisson_bc in the
 // Galerkin form of App. B): Jacobi-preconditioned CG in the single-
 // reduction (Chronopoulos-Gear) ordering, warm started, with the stopping
-// test re-checked on the true residual, then the nodal field E = R phi.
+// test re-checked on the true residual, and the nodal field E = R phi.
 //
 // The solve is a chain of ordinary kernel launches (a launch costs ~3 us on
 // MI355X, a device-wide barrier inside a persistent kernel 12-19 us):
-//   load   : x = phi on free nodes; b from the deposited charge; (b,b);
-//            resets the control word
-//   resid  : r = b - K x, u = D^-1 r; (r,r)   (also the true-residual re-check)
-//   start  : convergence test; w = K u; (r,u), (w,u)
-//   upd(i) : scalars of iteration i; p, s, x, r, u updates; (r,r), (r,u)
-//   spmv(i): w = K u; (w,u)
-//   field  : phi scatter (Dirichlet nodes 0) and E = R x
+//   resfield: one pass over phi: b on the fly, r = b - K phi, u = D^-1 r,
+//             x = phi on free nodes, E = R phi on every node, phi = 0 on
+//             Dirichlet nodes; (b,b), (r,r)
+//   start   : convergence test on that true residual; stats; when not
+//             converged, w = K u, (r,u), (w,u)
+//   upd(i)  : scalars of iteration i; p, s, x, r, u updates; (r,r), (r,u)
+//   spmv(i) : w = K u; (w,u)
+//   scatter : phi = x on free nodes, before the re-check (a resfield pass)
+// K and R share the sparsity of the free rows, so the field of phi comes out
+// of the same pass that tests phi: when the warm start already meets the
+// tolerance (no iteration), the step's solve is two launches, and whenever
+// the solver stops, E belongs to the final phi.
 // Each kernel writes one partial sum per workgroup; the next kernel reduces
 // all partials in a fixed order in every workgroup (deterministic, same
 // values everywhere), so no cross-workgroup synchronization is needed
@@ -21,11 +26,11 @@
 // kernel before each host wait also writes the state, with a sequence
 // number, into host-mapped memory that the host polls.
 //
-// K and R are stored in sliced ELLPACK (64 rows per slice, column-major in
-// the slice): one row per lane, so every load of a wave is contiguous.
-// Slices are split into contiguous blocks per workgroup, grouped so that each
-// of the 8 XCDs (workgroup g runs on XCD g mod 8) sweeps one contiguous
-// eighth of the matrix, which keeps neighbour gathers of x in one L2.
+// Storage is sliced ELLPACK (64 rows per slice, column-major in the slice):
+// one row per lane, so every load of a wave is contiguous.  Slices are split
+// into contiguous blocks per workgroup, grouped so that each of the 8 XCDs
+// (workgroup g runs on XCD g mod 8) sweeps one contiguous eighth of the
+// matrix, which keeps neighbour gathers in one L2.
 #include "common.h"
 #include "solver.h"
 
@@ -150,84 +155,183 @@ __device__ inline void report(const CgCtrl* c, CgReport* r, int64_t seq,
   __hip_atomic_store(&r->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-// x = phi on free nodes and b_i = coef c_i + E0 g_i; (b,b).
-__global__ void __launch_bounds__(512) k_cg_load(CgArgs a) {
-  const DevMesh& m = a.m;
-  if (blockIdx.x == 0 && threadIdx.x == 0) ctrl_reset(a.ctrl);
-  const Range rows = my_range(m.n_free);
-  double v[1] = {0.0};
-  for (int64_t i = rows.lo + threadIdx.x; i < rows.hi; i += blockDim.x) {
-    const int32_t nd = m.free2node[i];
-    const double c = a.charge ? (double)a.charge[nd] : 0.0;
-    const double bi = a.coef * c + a.E0 * m.g_unit[i];
-    a.b[i] = bi;
-    a.x[i] = a.phi[nd];
-    v[0] += bi * bi;
-  }
-  write_partials<1>(slot(a, 0), a.G, v);
-}
-
-// r = b - K x, u = D^-1 r, (r,r): the initial residual, and the re-check of
-// the true residual once the recursive one has converged.
+// The pass over phi (see the file comment).  reset != 0 starts a new solve
+// (control word cleared by workgroup 0; no other workgroup reads it here).
 // Mixed precision: the FP64 residual is rounded once into the FP32
-// recursion vectors.
-__global__ void __launch_bounds__(512) k_cg_resid(CgArgs a) {
+// recursion vectors.  FP32 field (e32): E = R phi in the difference form
+//   E_i = sum_j R_ij (phi_j - phi_i) + S_i phi_i,   S_i = sum_j R_ij (FP64),
+// with R in FP32: the differences are of the size of E h, so rounding R
+// costs a relative error of about 2^-24 in E, while R_ij phi_j alone would
+// lose the ratio |phi| / (|E| h) to cancellation.
+__global__ void __launch_bounds__(512) k_cg_resfield(CgArgs a, int reset) {
   const DevMesh& m = a.m;
-  double v[1] = {0.0};
-  if (a.mixed) {
-    spmv_sell(m.k_sptr, m.k_scol, m.k_sval, a.x, m.k_nslices, m.n_free,
-              [&](int64_t i, double s) {
-                const double ri = a.b[i] - s;
-                a.r32[i] = (float)ri;
-                a.u32[i] = (float)(ri * m.invdiag[i]);
-                v[0] += ri * ri;
-              });
-  } else {
-    spmv_sell(m.k_sptr, m.k_scol, m.k_sval, a.x, m.k_nslices, m.n_free,
-              [&](int64_t i, double s) {
-                const double ri = a.b[i] - s;
-                a.r[i] = ri;
-                a.u[i] = ri * m.invdiag[i];
-                v[0] += ri * ri;
-              });
+  if (reset && blockIdx.x == 0 && threadIdx.x == 0) ctrl_reset(a.ctrl);
+  const int lane = threadIdx.x & (kSell - 1);
+  const int sub = threadIdx.x / kSell;
+  const int nsub = blockDim.x / kSell;
+  const bool withE = a.E != nullptr;
+  const bool e32 = a.e32 != 0;
+  const int64_t np = m.k_np;
+  double v[2] = {0.0, 0.0};
+  {
+    const Range sl = my_range(m.k_nslices);
+    for (int64_t s = sl.lo + sub; s < sl.hi; s += nsub) {
+      const int64_t r = s * kSell + lane;
+      const bool row = r < m.n_free;
+      const int32_t nd = row ? m.free2node[r] : 0;
+      const double pi = row ? a.phi[nd] : 0.0;
+      const int32_t p0 = m.k_sptr[s], p1 = m.k_sptr[s + 1];
+      double kx = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;
+      if (!withE) {
+        for (int32_t p = p0 + lane; p < p1; p += kSell)
+          kx += m.k_sval[p] * a.phi[m.k_ncol[p]];
+      } else if (!e32) {
+        for (int32_t p = p0 + lane; p < p1; p += kSell) {
+          const double xj = a.phi[m.k_ncol[p]];
+          kx += m.k_sval[p] * xj;
+          ex += m.r_sval[p] * xj;
+          ey += m.r_sval[np + p] * xj;
+          ez += m.r_sval[2 * np + p] * xj;
+        }
+      } else {
+        for (int32_t p = p0 + lane; p < p1; p += kSell) {
+          const double xj = a.phi[m.k_ncol[p]];
+          kx += m.k_sval[p] * xj;
+          const double d = xj - pi;
+          ex += (double)m.r_sval32[p] * d;
+          ey += (double)m.r_sval32[np + p] * d;
+          ez += (double)m.r_sval32[2 * np + p] * d;
+        }
+      }
+      if (!row) continue;
+      const double c = a.charge ? (double)a.charge[nd] : 0.0;
+      const double bi = a.coef * c + a.E0 * m.g_unit[r];
+      const double ri = bi - kx;
+      a.x[r] = pi;
+      if (a.mixed) {
+        a.r32[r] = (float)ri;
+        a.u32[r] = (float)(ri * m.invdiag[r]);
+      } else {
+        a.r[r] = ri;
+        a.u[r] = ri * m.invdiag[r];
+      }
+      v[0] += bi * bi;
+      v[1] += ri * ri;
+      if (withE) {
+        if (e32) {
+          const double4 S = m.f_rowsum[nd];
+          reinterpret_cast<float4*>(a.E)[nd] =
+              make_float4((float)(ex + S.x * pi), (float)(ey + S.y * pi),
+                          (float)(ez + S.z * pi), 0.0f);
+        } else {
+          reinterpret_cast<double4*>(a.E)[nd] = make_double4(ex, ey, ez, 0.0);
+        }
+      }
+    }
   }
-  write_partials<1>(slot(a, 1), a.G, v);
+  // Dirichlet rows: phi = 0 there (never read above: columns are free
+  // nodes), E = R phi
+  {
+    const Range dr = my_range(a.n_dir);
+    for (int64_t i = dr.lo + threadIdx.x; i < dr.hi; i += blockDim.x)
+      a.phi[a.dir_nodes[i]] = 0.0;
+  }
+  if (withE) {
+    const int64_t dnp = m.d_np;
+    const Range sl = my_range(m.d_nslices);
+    for (int64_t s = sl.lo + sub; s < sl.hi; s += nsub) {
+      const int64_t r = s * kSell + lane;
+      const int32_t p0 = m.d_sptr[s], p1 = m.d_sptr[s + 1];
+      double ex = 0.0, ey = 0.0, ez = 0.0;
+      if (!e32) {
+        for (int32_t p = p0 + lane; p < p1; p += kSell) {
+          const double xj = a.phi[m.d_ncol[p]];
+          ex += m.d_sval[p] * xj;
+          ey += m.d_sval[dnp + p] * xj;
+          ez += m.d_sval[2 * dnp + p] * xj;
+        }
+      } else {
+        for (int32_t p = p0 + lane; p < p1; p += kSell) {
+          const double xj = a.phi[m.d_ncol[p]];
+          ex += (double)m.d_sval32[p] * xj;
+          ey += (double)m.d_sval32[dnp + p] * xj;
+          ez += (double)m.d_sval32[2 * dnp + p] * xj;
+        }
+      }
+      if (r >= a.n_dir) continue;
+      const int32_t nd = a.dir_nodes[r];
+      if (e32)
+        reinterpret_cast<float4*>(a.E)[nd] =
+            make_float4((float)ex, (float)ey, (float)ez, 0.0f);
+      else
+        reinterpret_cast<double4*>(a.E)[nd] = make_double4(ex, ey, ez, 0.0);
+    }
+  }
+  write_partials<2>(slot(a, 0), a.G, v);
 }
 
-// Convergence test on the true residual; when not converged, the first
-// product w = K u of a (re)started CG.  Launched by the host only at the
-// start and after a RECHECK.  Fields written here by workgroup 0 (state,
-// iters, relres, restarts) are never read by other workgroups of this
-// launch; they read iters_final and bb, which are stable here.
-__global__ void __launch_bounds__(512) k_cg_start(CgArgs a, int after_recheck,
-                                                 int64_t seq) {
+// phi = x on the free nodes (before a re-check pass).
+__global__ void __launch_bounds__(512) k_cg_scatter(CgArgs a) {
+  const DevMesh& m = a.m;
+  const Range rows = my_range(m.n_free);
+  for (int64_t i = rows.lo + threadIdx.x; i < rows.hi; i += blockDim.x)
+    a.phi[m.free2node[i]] = a.x[i];
+}
+
+// Convergence test on the true residual of the last resfield pass; when the
+// solve ends, its statistics; when not converged, the first product w = K u
+// of a (re)started CG.  Fields written here by workgroup 0 (state, iters,
+// bb, relres, rstart, restarts) are never read by other workgroups of this
+// launch; they read iters_final, which is stable here.  A zero right-hand
+// side gives phi = 0 and E = 0, written by every workgroup.
+__global__ void __launch_bounds__(512) k_cg_start(CgArgs a, int64_t seq) {
   CgCtrl* c = a.ctrl;
   double t[2];
-  if (after_recheck) {
-    double t1[1];
-    totals<1>(slot(a, 1), a.G, 1, t1);
-    t[0] = c->bb;
-    t[1] = t1[0];
-  } else {
-    totals<2>(slot(a, 0), a.G, a.G, t);
-  }
+  totals<2>(slot(a, 0), a.G, a.G, t);
   const double bn = sqrt(t[0]);
   const double rn = sqrt(t[1]);
   const int64_t done_iters = c->iters_final;
   const bool done = bn == 0.0 || rn <= a.tol * bn;
   const bool noconv = !done && done_iters >= a.max_iter;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    if (!after_recheck) c->bb = t[0];
+    c->bb = t[0];
     c->iters = done_iters;
-    c->relres = bn > 0.0 ? rn / bn : 0.0;
+    const double relres = bn > 0.0 ? rn / bn : 0.0;
+    c->relres = relres;
     c->rstart = rn;
     const int32_t state = done ? CG_DONE : (noconv ? CG_NOCONV : CG_ITER);
     c->state = state;
     if (!done && !noconv) c->restarts += 1;
     if (bn == 0.0) c->zero_rhs = 1;
+    if (done || noconv) {
+      const int64_t st = noconv ? PIC_E_NOCONV : 0;
+      if (a.stats) {
+        a.stats->iters = done_iters;
+        a.stats->status = st;
+        a.stats->restarts = c->restarts;
+        a.stats->relres = relres;
+        a.stats->bnorm = bn;
+      }
+      if (a.step_stats) {
+        a.step_stats->cg_iters = done_iters;
+        a.step_stats->cg_relres = relres;
+        if (st != 0 && a.step_stats->status == 0) a.step_stats->status = st;
+      }
+    }
     if (seq) {
       __threadfence_system();
       report(c, a.report, seq, state);
+    }
+  }
+  if (bn == 0.0) {
+    const DevMesh& m = a.m;
+    const Range nr = my_range(m.n_nodes);
+    for (int64_t i = nr.lo + threadIdx.x; i < nr.hi; i += blockDim.x) {
+      a.phi[i] = 0.0;
+      if (a.E && a.e32)
+        reinterpret_cast<float4*>(a.E)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+      else if (a.E)
+        reinterpret_cast<double4*>(a.E)[i] = make_double4(0.0, 0.0, 0.0, 0.0);
     }
   }
   if (done || noconv) return;
@@ -361,105 +465,6 @@ __global__ void __launch_bounds__(512) k_cg_spmv(CgArgs a, int it,
   write_partials<1>(slot(a, 8 + (it & 1)), a.G, v);
 }
 
-// Mixed precision: E = R x in the difference form
-//   E_i = sum_j R_ij (x_j - phi_i) + S_i phi_i,   S_i = sum_j R_ij (FP64),
-// with R in FP32: the differences are of the size of E h, so rounding R
-// costs a relative error of about 2^-24 in E, while R_ij x_j alone would
-// lose the ratio |phi| / (|E| h) to cancellation.  E is stored in FP32.
-__device__ inline void field_mixed(const CgArgs& a, bool zero) {
-  const DevMesh& m = a.m;
-  const Range sl = my_range(m.f_nslices);
-  const int lane = threadIdx.x & (kSell - 1);
-  const int sub = threadIdx.x / kSell;
-  const int nsub = blockDim.x / kSell;
-  const int64_t np = m.f_np;
-  for (int64_t s = sl.lo + sub; s < sl.hi; s += nsub) {
-    const int64_t r = s * kSell + lane;
-    if (r >= m.n_nodes) continue;
-    const int32_t p0 = m.f_sptr[s], p1 = m.f_sptr[s + 1];
-    double ex = 0.0, ey = 0.0, ez = 0.0;
-    if (!zero) {
-      const int32_t fi = m.node2free[r];
-      const double pi = fi >= 0 ? a.x[fi] : 0.0;
-      for (int32_t p = p0 + lane; p < p1; p += kSell) {
-        const double d = a.x[m.f_scol[p]] - pi;
-        ex += (double)m.f_sval32[p] * d;
-        ey += (double)m.f_sval32[np + p] * d;
-        ez += (double)m.f_sval32[2 * np + p] * d;
-      }
-      const double4 S = m.f_rowsum[r];
-      ex += S.x * pi;
-      ey += S.y * pi;
-      ez += S.z * pi;
-    }
-    reinterpret_cast<float4*>(a.E)[r] =
-        make_float4((float)ex, (float)ey, (float)ez, 0.0f);
-  }
-}
-
-// phi on every node (Dirichlet nodes 0) and the nodal field E = R x.
-__global__ void __launch_bounds__(512) k_cg_field(CgArgs a) {
-  const DevMesh& m = a.m;
-  const CgCtrl* c = a.ctrl;
-  const bool zero = c->zero_rhs != 0;
-  {
-    const Range rows = my_range(m.n_free);
-    for (int64_t i = rows.lo + threadIdx.x; i < rows.hi; i += blockDim.x) {
-      const double xi = zero ? 0.0 : a.x[i];
-      a.phi[m.free2node[i]] = xi;
-    }
-    const Range dr = my_range(a.n_dir);
-    for (int64_t i = dr.lo + threadIdx.x; i < dr.hi; i += blockDim.x)
-      a.phi[a.dir_nodes[i]] = 0.0;
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    const int64_t st = c->state == CG_NOCONV ? PIC_E_NOCONV : 0;
-    if (a.stats) {
-      a.stats->iters = c->iters;
-      a.stats->status = st;
-      a.stats->restarts = c->restarts;
-      a.stats->relres = c->relres;
-      a.stats->bnorm = sqrt(c->bb);
-    }
-    if (a.step_stats) {
-      a.step_stats->cg_iters = c->iters;
-      a.step_stats->cg_relres = c->relres;
-      if (st != 0 && a.step_stats->status == 0) a.step_stats->status = st;
-    }
-  }
-  if (!a.E) return;
-  if (a.e32) {
-    field_mixed(a, zero);
-    return;
-  }
-  const Range sl = my_range(m.f_nslices);
-  const int lane = threadIdx.x & (kSell - 1);
-  const int sub = threadIdx.x / kSell;
-  const int nsub = blockDim.x / kSell;
-  const int64_t np = m.f_np;
-  for (int64_t s = sl.lo + sub; s < sl.hi; s += nsub) {
-    const int64_t r = s * kSell + lane;
-    const int32_t p0 = m.f_sptr[s], p1 = m.f_sptr[s + 1];
-    double ex = 0.0, ey = 0.0, ez = 0.0;
-    if (!zero) {
-      for (int32_t p = p0 + lane; p < p1; p += kSell) {
-        const double xj = a.x[m.f_scol[p]];
-        ex += m.f_sval[p] * xj;
-        ey += m.f_sval[np + p] * xj;
-        ez += m.f_sval[2 * np + p] * xj;
-      }
-    }
-    if (r < m.n_nodes) {
-      double4 e;
-      e.x = ex;
-      e.y = ey;
-      e.z = ez;
-      e.w = 0.0;
-      reinterpret_cast<double4*>(a.E)[r] = e;
-    }
-  }
-}
-
 #define LAUNCH(kern, ...)                                                   \
   do {                                                                      \
     hipLaunchKernelGGL(kern, dim3(a.G), dim3(kCgBlock), 0, s, __VA_ARGS__); \
@@ -468,9 +473,8 @@ __global__ void __launch_bounds__(512) k_cg_field(CgArgs a) {
   } while (0)
 
 hipError_t cg_launch_begin(const CgArgs& a, int64_t seq, hipStream_t s) {
-  LAUNCH(k_cg_load, a);
-  LAUNCH(k_cg_resid, a);
-  LAUNCH(k_cg_start, a, 0, seq);
+  LAUNCH(k_cg_resfield, a, 1);
+  LAUNCH(k_cg_start, a, seq);
   return hipSuccess;
 }
 
@@ -484,13 +488,9 @@ hipError_t cg_launch_iters(const CgArgs& a, int it0, int n, int64_t seq,
 }
 
 hipError_t cg_launch_recheck(const CgArgs& a, int64_t seq, hipStream_t s) {
-  LAUNCH(k_cg_resid, a);
-  LAUNCH(k_cg_start, a, 1, seq);
-  return hipSuccess;
-}
-
-hipError_t cg_launch_field(const CgArgs& a, hipStream_t s) {
-  LAUNCH(k_cg_field, a);
+  LAUNCH(k_cg_scatter, a);
+  LAUNCH(k_cg_resfield, a, 0);
+  LAUNCH(k_cg_start, a, seq);
   return hipSuccess;
 }
 
