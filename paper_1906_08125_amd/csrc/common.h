@@ -39,11 +39,17 @@ struct alignas(128) TetWalk {   // vertices (unwrapped) + adjacency
 };
 static_assert(sizeof(TetWalk) == 128, "TetWalk is one line");
 
-struct alignas(128) TetGeom {   // barycentric map + vertex ids
+// Barycentric map, vertex ids and neighbours: the one record the particle
+// loop reads per tet visited.  nbr[k] is the tet across the face opposite
+// vertex k in bits 0-27 (kNoNbr when the face is on the boundary), and the
+// frame offset (sx + 1, sy + 1) of that tet in bits 28-29 and 30-31.
+constexpr uint32_t kNoNbr = 0x0FFFFFFFu;
+constexpr int64_t kMaxTets = kNoNbr;
+struct alignas(128) TetGeom {
   double v0[3];
   double m[9];      // rows m1, m2, m3
   int32_t node[4];
-  int32_t pad[4];
+  uint32_t nbr[4];
 };
 static_assert(sizeof(TetGeom) == 128, "TetGeom is one line");
 
@@ -96,6 +102,7 @@ struct DevMesh {
   double finv[3];
   int32_t* fseed;            // [fnb_x*fnb_y*fnb_z]
   double jump_len2;          // displacements beyond this start at the seed
+  double lam_c;              // bound factor of the barycentric inside test
 };
 
 // ---------------------------------------------------------------------------

@@ -59,6 +59,48 @@ inline V3 cross(V3 a, V3 b) {
 }
 inline double dot(V3 a, V3 b) { return (a.x * b.x + a.y * b.y) + a.z * b.z; }
 
+// Rounding-error bound of a computed barycentric map, as a multiple of
+// u max_j |m_kj| (u = 2^-53): with e_i = v_i - v0, c = e x e and D = e1.c1
+// all rounded, and m = c / D rounded, the exact map m* of the exact vertices
+// satisfies |m_kj - m*_kj| <= eta_kj, where (standard model, first order
+// terms with margin)
+//   err(e)   <= u |e|,      err(c_kj) <= 4.01 u P_kj,  P = |a_y b_z| + |a_z b_y|...
+//   err(D)   <= 4.02 u (sum_j |e1_j| |c1_j| + sum_j |e1_j| P1_j)
+//   eta_kj    = 1.0001 u |m_kj| + (err(c_kj) + (|c_kj| + err(c_kj)) err(D) /
+//               (|D| - err(D))) / |D|.
+// Returns max_kj eta_kj / (u max_j |m_kj|), or a huge value for a tet whose
+// determinant is not resolved (err(D) >= |D| / 2).
+inline double lam_error_ratio(V3 e1, V3 e2, V3 e3, const V3 cs[3], double D,
+                              const double* m) {
+  const double u = 1.1102230246251565e-16;
+  auto ab = [](V3 a) { return V3{std::fabs(a.x), std::fabs(a.y), std::fabs(a.z)}; };
+  auto pcross = [](V3 a, V3 b) {
+    return V3{a.y * b.z + a.z * b.y, a.z * b.x + a.x * b.z, a.x * b.y + a.y * b.x};
+  };
+  const V3 a1 = ab(e1), a2 = ab(e2), a3 = ab(e3);
+  const V3 P[3] = {pcross(a2, a3), pcross(a3, a1), pcross(a1, a2)};
+  const V3 c1 = ab(cs[0]);
+  const double errD = 4.02 * u *
+      ((a1.x * c1.x + a1.y * c1.y + a1.z * c1.z) +
+       (a1.x * P[0].x + a1.y * P[0].y + a1.z * P[0].z));
+  const double aD = std::fabs(D);
+  if (!(errD < 0.5 * aD)) return 1e300;
+  double worst = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    const double ck[3] = {std::fabs(cs[k].x), std::fabs(cs[k].y), std::fabs(cs[k].z)};
+    const double pk[3] = {P[k].x, P[k].y, P[k].z};
+    double M = 0.0;
+    for (int j = 0; j < 3; ++j) M = std::max(M, std::fabs(m[3 * k + j]));
+    for (int j = 0; j < 3; ++j) {
+      const double ec = 4.01 * u * pk[j];
+      const double eta = 1.0001 * u * std::fabs(m[3 * k + j]) +
+                         (ec + (ck[j] + ec) * errD / (aD - errD)) / aD;
+      worst = std::max(worst, 1.001 * eta / (u * M));
+    }
+  }
+  return worst;
+}
+
 struct FaceKey {
   uint64_t hi, lo;
   int32_t tet;
@@ -106,8 +148,8 @@ pic_status build_mesh(const pic_mesh_desc* d, pic_mesh* h, std::string& msg) {
     msg = "mesh_create: lateral periods must be positive and z_top finite";
     return PIC_E_ARG;
   }
-  if (N >= (1ll << 31) || T >= (1ll << 31)) {
-    msg = "mesh_create: more than 2^31 nodes or tets";
+  if (N >= (1ll << 31) || T >= kMaxTets) {
+    msg = "mesh_create: more than 2^31 nodes or 2^28 - 1 tets";
     return PIC_E_ARG;
   }
   const double Lx = d->Lx, Ly = d->Ly;
@@ -118,6 +160,7 @@ pic_status build_mesh(const pic_mesh_desc* d, pic_mesh* h, std::string& msg) {
   std::vector<TetGeom> tg(T);
   std::vector<double> D(T);
   // 1. orientation, unwrapped vertices, barycentric maps
+  double kappa = 0.0;
   for (int64_t t = 0; t < T; ++t) {
     double v[4][3];
     for (int k = 0; k < 4; ++k) {
@@ -159,6 +202,7 @@ pic_status build_mesh(const pic_mesh_desc* d, pic_mesh* h, std::string& msg) {
     }
     for (int c = 0; c < 3; ++c) G.v0[c] = v[0][c];
     for (int k = 0; k < 4; ++k) G.node[k] = tv[4 * t + k];
+    kappa = std::max(kappa, lam_error_ratio(e1, e2, e3, cs, det, G.m));
   }
   // 2. faces and neighbours
   {
@@ -219,6 +263,18 @@ pic_status build_mesh(const pic_mesh_desc* d, pic_mesh* h, std::string& msg) {
     h->info.n_top = n_top;
     h->info.n_metal = n_metal;
   }
+  // neighbours with their frame offsets, packed into the barycentric record
+  for (int64_t t = 0; t < T; ++t)
+    for (int f = 0; f < 4; ++f) {
+      const int32_t nb = tw[t].nbr[f];
+      if (nb >= 0 && (std::abs(tw[t].nsh[2 * f]) > 1 || std::abs(tw[t].nsh[2 * f + 1]) > 1)) {
+        msg = "mesh_create: neighbouring tets more than one period apart";
+        return PIC_E_MESH;
+      }
+      tg[t].nbr[f] = nb < 0 ? kNoNbr
+                            : ((uint32_t)nb | ((uint32_t)(tw[t].nsh[2 * f] + 1) << 28) |
+                               ((uint32_t)(tw[t].nsh[2 * f + 1] + 1) << 30));
+    }
   // 3. Dirichlet nodes and free numbering
   std::vector<char> dir(N, 0);
   for (int64_t t = 0; t < T; ++t)
@@ -579,6 +635,8 @@ pic_status build_mesh(const pic_mesh_desc* d, pic_mesh* h, std::string& msg) {
     M.finv[k] = 2.0 * M.binv[k];
   }
   M.jump_len2 = (0.25 * edge) * (0.25 * edge);
+  // |lambda_k - lambda*_k| <= lam_c max_j |m_kj| |d|_1 (see lam_test)
+  M.lam_c = (4.01 + 1.01 * kappa) * 1.1102230246251565e-16;
   M.fseed = (int32_t*)dev_alloc(
       h, sizeof(int32_t) * (size_t)M.fnb[0] * M.fnb[1] * M.fnb[2], err);
   if (err == hipSuccess) err = launch_seed_build(M, std::max(8, h->n_cu * 8), nullptr);

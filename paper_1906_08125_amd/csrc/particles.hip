@@ -153,17 +153,59 @@ __device__ inline int fine_seed(const DevMesh& m, double x, double y,
   return m.fseed[((int64_t)bx * m.fnb[1] + by) * m.fnb[2] + bz];
 }
 
+// Barycentric coordinates of p in tet g (the fixed arithmetic of
+// barycentric()) with a certificate.  With d = p - v0 and
+// M_k = max_j |m_kj|, each computed lambda_k (k = 1..3) lies within
+// B_k = lam_c M_k |d|_1 of the exact barycentric coordinate of p in the tet
+// of the exact vertices (lam_c bounds the rounding of the stored map, of d
+// and of the dot product; it is set up with the mesh), and lambda_0 within
+// B_0 = 3.01 u (1 + sum_k |lambda_k|) + sum_k B_k.  Returns true when every
+// lambda_k > B_k, i.e. p is certainly strictly inside.  Otherwise exitf is
+// the face (opposite vertex k) with the most negative lambda_k among those
+// certainly negative (lambda_k < -B_k), or -1 when there is none.
+__device__ inline bool lam_test(const TetGeom& g, double x, double y, double z,
+                                double C, double lam[4], int& exitf) {
+  barycentric(g, x, y, z, lam);
+  const double dx = x - g.v0[0], dy = y - g.v0[1], dz = z - g.v0[2];
+  const double dn = (fabs(dx) + fabs(dy)) + fabs(dz);
+  double B[4];
+#pragma unroll
+  for (int k = 1; k < 4; ++k) {
+    const double* r = g.m + 3 * (k - 1);
+    const double M = fmax(fmax(fabs(r[0]), fabs(r[1])), fabs(r[2]));
+    B[k] = (C * M) * dn;
+  }
+  B[0] = 3.01 * 1.1102230246251565e-16 *
+             (((1.0 + fabs(lam[1])) + fabs(lam[2])) + fabs(lam[3])) +
+         1.0001 * ((B[1] + B[2]) + B[3]);
+  bool inside = true;
+  exitf = -1;
+  double worst = 0.0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (lam[k] > B[k]) continue;
+    inside = false;
+    if (lam[k] < -B[k] && lam[k] < worst) {
+      worst = lam[k];
+      exitf = k;
+    }
+  }
+  return inside;
+}
+
 // Neighbour walk from tet t with the point's frame offset (sx, sy) relative
-// to t.  A point that moved far (far = true), or is not in t, restarts from
-// the fine-grid seed of its sub-cell.  Returns the tet when the point is
-// certified strictly inside it in its own frame (then no other tet holds
-// it, so it is the canonical answer), or -1 when the exact bucket scan must
-// decide.
+// to t; G holds the record of t on entry.  A point that moved far (far =
+// true), or is not in t, restarts from the fine-grid seed of its sub-cell.
+// Returns the tet when the point is certified strictly inside it in its own
+// frame (then no other tet holds it, so it is the canonical answer), with
+// lam its barycentric coordinates there and G its record, or -1 when the
+// exact bucket scan must decide.
 __device__ inline int walk(const DevMesh& m, double x, double y, double z,
-                           int t, int sx, int sy, int& steps,
-                           bool far = false) {
+                           int t, int sx, int sy, int& steps, bool far,
+                           TetGeom& G, double lam[4]) {
   bool jumped = false;
   for (steps = 0; steps < kMaxWalk; ++steps) {
+    bool reload = steps > 0;
     if (!jumped && (far || steps == 1)) {
       jumped = true;
       int g = fine_seed(m, x, y, z);
@@ -172,37 +214,24 @@ __device__ inline int walk(const DevMesh& m, double x, double y, double z,
         t = g;
         sx = 0;
         sy = 0;
+        reload = true;
       }
     }
-    const TetWalk& W = m.tw[t];
-    double v[12];
-#pragma unroll
-    for (int k = 0; k < 12; ++k) v[k] = W.v[k];
-    const double p[3] = {x + (double)sx * m.Lx, y + (double)sy * m.Ly, z};
-    double o[4], b[4];
-    o[0] = vol6_filtered(p, v + 3, v + 6, v + 9, b[0]);
-    o[1] = vol6_filtered(v, p, v + 6, v + 9, b[1]);
-    o[2] = vol6_filtered(v, v + 3, p, v + 9, b[2]);
-    o[3] = vol6_filtered(v, v + 3, v + 6, p, b[3]);
-    bool inside = true;
-    int exitf = -1;
-    double worst = 0.0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      if (o[i] > b[i]) continue;
-      inside = false;
-      if (o[i] < -b[i] && o[i] < worst) {
-        worst = o[i];
-        exitf = i;
-      }
-    }
-    if (inside) return (sx == 0 && sy == 0) ? t : -1;
+    if (reload) G = m.tg[t];
+    int exitf;
+    if (lam_test(G, x + (double)sx * m.Lx, y + (double)sy * m.Ly, z, m.lam_c,
+                 lam, exitf))
+      return (sx == 0 && sy == 0) ? t : -1;
     if (exitf < 0) return -1;
-    const int nb = W.nbr[exitf];
-    if (nb < 0) return -1;
-    sx += W.nsh[2 * exitf];
-    sy += W.nsh[2 * exitf + 1];
-    t = nb;
+    // (selects, not an indexed load: G stays in registers)
+    const uint32_t nb = exitf == 0 ? G.nbr[0]
+                        : exitf == 1 ? G.nbr[1]
+                        : exitf == 2 ? G.nbr[2]
+                                     : G.nbr[3];
+    if ((nb & kNoNbr) == kNoNbr) return -1;
+    sx += (int)((nb >> 28) & 3u) - 1;
+    sy += (int)(nb >> 30) - 1;
+    t = (int)(nb & kNoNbr);
   }
   return -1;
 }
@@ -307,21 +336,20 @@ __device__ inline void table_flush(ChargeTable& T, int64_t* charge) {
   }
 }
 
-__device__ inline void deposit_table(const TetGeom& g, double x, double y,
-                                     double z, double w, ChargeTable& T,
+__device__ inline void deposit_table(const TetGeom& g, const double lam[4],
+                                     double w, ChargeTable& T,
                                      int64_t* charge) {
-  double lam[4];
-  barycentric(g, x, y, z, lam);
   int64_t q[4];
   charge_split(lam, w, q);
 #pragma unroll
   for (int k = 0; k < 4; ++k) table_add(T, g.node[k], q[k], charge);
 }
 
+// G: the record of the hint tet.
 __device__ inline void settle(const DevMesh& m, const StepArgs& a, int64_t i,
                               double x, double y, double z, int sx, int sy,
-                              int hint, double w, long long qfx, Acc& acc,
-                              ChargeTable& T, bool far) {
+                              int hint, TetGeom& G, double w, long long qfx,
+                              Acc& acc, ChargeTable& T, bool far) {
   if (z >= m.z_top) {
     a.tet[i] = -1;
     acc.n_anode += 1;
@@ -329,12 +357,13 @@ __device__ inline void settle(const DevMesh& m, const StepArgs& a, int64_t i,
     return;
   }
   int steps = 0;
-  const int t = walk(m, x, y, z, hint, sx, sy, steps, far);
+  double lam[4];
+  const int t = walk(m, x, y, z, hint, sx, sy, steps, far, G, lam);
   acc.walk_steps += steps;
   if (steps > acc.walk_max) acc.walk_max = steps;
   if (t >= 0) {
     a.tet[i] = t;
-    deposit_table(m.tg[t], x, y, z, w, T, a.charge);
+    deposit_table(G, lam, w, T, a.charge);
     acc.n_after += 1;
     acc.q_after += qfx;
   } else {
@@ -568,8 +597,9 @@ __device__ inline void push_role64(const StepArgs& a, int g, int G, Acc& acc,
     acc.q_before += qfx;
     double x = X[i], y = Y[i], z = Z[i];
     double vx = VX[i], vy = VY[i], vz = VZ[i];
+    TetGeom G = m.tg[t];
     double ex, ey, ez;
-    gather_field(m.tg[t], a.E, x, y, z, ex, ey, ez);
+    gather_field(G, a.E, x, y, z, ex, ey, ez);
     const double qx = Q * ex, qy = Q * ey, qz = Q * ez;
     vx = (vx + qx) + qx;
     vy = (vy + qy) + qy;
@@ -587,7 +617,7 @@ __device__ inline void push_role64(const StepArgs& a, int g, int G, Acc& acc,
     VX[i] = vx;
     VY[i] = vy;
     VZ[i] = vz;
-    settle(m, a, i, x, y, z, sx, sy, t, w, qfx, acc, T, far);
+    settle(m, a, i, x, y, z, sx, sy, t, G, w, qfx, acc, T, far);
   }
 }
 
@@ -618,7 +648,7 @@ __device__ inline void push_role32(const StepArgs& a, int g, int G, Acc& acc,
     acc.q_before += qfx;
     float x = X[i], y = Y[i], z = Z[i];
     float vx = VX[i], vy = VY[i], vz = VZ[i];
-    const TetGeom& G4 = m.tg[t];
+    TetGeom G4 = m.tg[t];
     double lam[4];
     barycentric(G4, x, y, z, lam);
     const float l0 = (float)lam[0], l1 = (float)lam[1], l2 = (float)lam[2],
@@ -658,7 +688,7 @@ __device__ inline void push_role32(const StepArgs& a, int g, int G, Acc& acc,
     VX[i] = vx;
     VY[i] = vy;
     VZ[i] = vz;
-    settle(m, a, i, x, y, z, sx, sy, t, w, qfx, acc, T, far);
+    settle(m, a, i, x, y, z, sx, sy, t, G4, w, qfx, acc, T, far);
   }
 }
 
@@ -738,7 +768,9 @@ __device__ inline void inject_role(const StepArgs& a, int g, int G, Acc& acc,
     a.id[i] = (a.step << 42) | ((int64_t)f << 21) | o;
     acc.n_inj += 1;
     acc.q_inj += qfx;
-    settle(m, a, i, x, y, z, sx, sy, m.e_tet[f], w, qfx, acc, T, false);
+    const int h = m.e_tet[f];
+    TetGeom G = m.tg[h];
+    settle(m, a, i, x, y, z, sx, sy, h, G, w, qfx, acc, T, false);
   }
 }
 
@@ -846,7 +878,11 @@ __global__ void __launch_bounds__(kBlock) k_locate(LocateArgs a) {
     }
     const int h = a.tet[i];
     int t = -1, steps = 0;
-    if (h >= 0 && h < m.n_tets) t = walk(m, x, y, z, h, 0, 0, steps);
+    if (h >= 0 && h < m.n_tets) {
+      TetGeom G = m.tg[h];
+      double lam[4];
+      t = walk(m, x, y, z, h, 0, 0, steps, false, G, lam);
+    }
     if (t >= 0) {
       a.tet[i] = t;
       a.where[i] = PIC_WHERE_INSIDE;
