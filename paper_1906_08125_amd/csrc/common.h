@@ -44,6 +44,7 @@ static_assert(sizeof(TetWalk) == 128, "TetWalk is one line");
 // vertex k in bits 0-27 (kNoNbr when the face is on the boundary), and the
 // frame offset (sx + 1, sy + 1) of that tet in bits 28-29 and 30-31.
 constexpr uint32_t kNoNbr = 0x0FFFFFFFu;
+constexpr int kFineSeed = 4;  // seed sub-cells per bucket edge
 constexpr int64_t kMaxTets = kNoNbr;
 struct alignas(128) TetGeom {
   double v0[3];
@@ -96,8 +97,8 @@ struct DevMesh {
   const int32_t* bstart;     // [nbx*nby*nbz + 1]
   const int32_t* bitem;
   const int32_t* bseed;      // [nbx*nby*nbz] walk seed per bucket or -1
-  // walk seeds on a grid twice as fine: the tet holding each sub-cell
-  // centre (or the coarse seed where the centre is in the metal)
+  // walk seeds on a grid kFineSeed times finer: the tet holding each
+  // sub-cell centre (or the coarse seed where the centre is in the metal)
   int32_t fnb[3];
   double finv[3];
   int32_t* fseed;            // [fnb_x*fnb_y*fnb_z]

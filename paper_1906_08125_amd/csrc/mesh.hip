@@ -631,8 +631,8 @@ pic_status build_mesh(const pic_mesh_desc* d, pic_mesh* h, std::string& msg) {
   h->locate_count = (int32_t*)dev_alloc(h, sizeof(int32_t), err);
   // fine walk seeds, located on the device with the exact canonical scan
   for (int k = 0; k < 3; ++k) {
-    M.fnb[k] = 2 * M.nb[k];
-    M.finv[k] = 2.0 * M.binv[k];
+    M.fnb[k] = kFineSeed * M.nb[k];
+    M.finv[k] = (double)kFineSeed * M.binv[k];
   }
   M.jump_len2 = (0.25 * edge) * (0.25 * edge);
   // |lambda_k - lambda*_k| <= lam_c max_j |m_kj| |d|_1 (see lam_test)

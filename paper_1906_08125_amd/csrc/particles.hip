@@ -774,13 +774,15 @@ __device__ inline void inject_role(const StepArgs& a, int g, int G, Acc& acc,
   }
 }
 
+// One instance per storage precision, so that only one push is compiled in.
+template <bool F32>
 __global__ void __launch_bounds__(kBlock) k_particles(StepArgs a, int g_push) {
   Acc acc;
   acc_zero(acc);
   __shared__ ChargeTable T;
   table_clear(T);
   if ((int)blockIdx.x < g_push) {
-    if (a.f32)
+    if (F32)
       push_role32(a, blockIdx.x, g_push, acc, T);
     else
       push_role64(a, blockIdx.x, g_push, acc, T);
@@ -949,8 +951,12 @@ hipError_t launch_begin(const EmitArgs& a, int64_t* charge, int64_t n_nodes,
 }
 hipError_t launch_particles(const StepArgs& a, int g_push, int g_inj,
                             hipStream_t s) {
-  hipLaunchKernelGGL(k_particles, dim3(g_push + g_inj), dim3(kBlock), 0, s, a,
-                     g_push);
+  if (a.f32)
+    hipLaunchKernelGGL(k_particles<true>, dim3(g_push + g_inj), dim3(kBlock), 0,
+                       s, a, g_push);
+  else
+    hipLaunchKernelGGL(k_particles<false>, dim3(g_push + g_inj), dim3(kBlock),
+                       0, s, a, g_push);
   return hipGetLastError();
 }
 hipError_t launch_seed_build(const DevMesh& m, int grid, hipStream_t s) {
