@@ -968,6 +968,32 @@ void om_field(const omesh* m, const double* phi, double* E3) {
   free(acc);
 }
 
+void om_field_adj(const omesh* m, const double* Ebar3, double* phibar) {
+  /* E_i = (1/W_i) sum_{t ∋ i} V_t (-grad phi_t), grad phi_t =
+   * sum_b phi_(t,b) g_b: so d<Ebar, E>/d phi_j = sum_t sum_{b: node j}
+   * -g_b . (V_t sum_{a in t} Ebar_(t,a) / W_(t,a)) */
+  memset(phibar, 0, sizeof(double) * m->n_nodes);
+  for (int64_t t = 0; t < m->n_tets; ++t) {
+    const double* mm = m->mm + 9 * t;
+    const int32_t* tv = m->tet + 4 * t;
+    double g[4][3];
+    for (int k = 0; k < 3; ++k) {
+      g[1][k] = mm[k];
+      g[2][k] = mm[3 + k];
+      g[3][k] = mm[6 + k];
+      g[0][k] = -((mm[k] + mm[3 + k]) + mm[6 + k]);
+    }
+    double V = m->D[t] / 6.0, A[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < 4; ++a) {
+      const double Wa = m->W[tv[a]];
+      if (!(Wa > 0)) continue;
+      for (int k = 0; k < 3; ++k) A[k] += Ebar3[3 * (int64_t)tv[a] + k] / Wa;
+    }
+    for (int b = 0; b < 4; ++b)
+      phibar[tv[b]] -= V * ((g[b][0] * A[0] + g[b][1] * A[1]) + g[b][2] * A[2]);
+  }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Injection (Sec. II B 3, Eq. nsp, Eq. rnd_nsp, Eq. sp_velocity,            */
 /* Eq. sp_displacement, App. E).                                            */
@@ -1053,8 +1079,9 @@ int om_inject(const omesh* m, oparticles* P, const double* E3,
     double fl = floor(nsp);
     double cnt = (R >= nsp - fl) ? fl : ceil(nsp); /* Eq. rnd_nsp */
     if (cnt > (double)(1 << 21)) cnt = (double)(1 << 21);
-    int64_t cnt_i = (int64_t)cnt;
+    int64_t cnt_i = prm->counts_in ? prm->counts_in[f] : (int64_t)cnt;
     if (counts) counts[f] = cnt_i;
+    if (prm->counts_out) prm->counts_out[f] = cnt_i;
     double s = prm->s_face ? prm->s_face[f] : 1.0;
     const double* A = m->e_abc + 9 * f;
     const double* B = A + 3;
@@ -1087,6 +1114,13 @@ int om_inject(const omesh* m, oparticles* P, const double* E3,
       }
       if (face_pts)
         for (int k = 0; k < 3; ++k) face_pts[3 * n + k] = x[k];
+      if (prm->inj_out) {
+        double* io = prm->inj_out + 4 * (n - P->n);
+        io[0] = R1;
+        io[1] = R2;
+        io[2] = Rf;
+        io[3] = (double)f;
+      }
       P->x[n] = r[0];
       P->y[n] = r[1];
       P->z[n] = r[2];
@@ -1144,9 +1178,11 @@ int om_pic_step(const omesh* m, oparticles* P, double* phi, double* E3,
     if (y >= m->Ly) y = y - m->Ly;
     else if (y < 0.0) y = y + m->Ly;
     int64_t q = charge_of(P->w[i]);
+    if (prm->fate_out) prm->fate_out[i] = 0;
     if (z >= m->z_top) {
       st->n_anode++;
       st->q_anode += q;
+      if (prm->fate_out) prm->fate_out[i] = 1;
       continue;
     }
     double p[3] = {x, y, z};
@@ -1154,6 +1190,7 @@ int om_pic_step(const omesh* m, oparticles* P, double* phi, double* E3,
     if (t < 0) {
       st->n_cathode++;
       st->q_cathode += q;
+      if (prm->fate_out) prm->fate_out[i] = 2;
       continue;
     }
     /* stable compaction */

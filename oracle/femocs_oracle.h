@@ -82,6 +82,11 @@ void om_spmv(const omesh* m, const double* x, double* y);
 /* Nodal field: volume-weighted mean of -grad(phi) over incident tets. */
 void om_field(const omesh* m, const double* phi, double* E3);
 
+/* Transpose of om_field: phibar[j] = sum_i sum_k R_(i k),j Ebar3[3 i + k]
+ * over all nodes j (the derivative of <Ebar, E(phi)> with respect to
+ * phi_j).  Test infrastructure for the adjoint. */
+void om_field_adj(const omesh* m, const double* Ebar3, double* phibar);
+
 /* Murphy-Good Fowler-Nordheim current density in A/m^2 (F in V/nm, phi_w
  * in eV).  *clamped is set when the Schottky parameter had to be clamped. */
 double om_fn_current(double F, double phi_w, int* clamped);
@@ -105,6 +110,15 @@ typedef struct {
   int32_t max_iter;
   int32_t pad;
   const double* s_face; /* per emitting face weight multiplier or NULL */
+  /* frozen emission counts per emitting face (replace Eq. nsp and
+   * Eq. rnd_nsp) or NULL; the counts used are written to counts_out */
+  const int64_t* counts_in;
+  int64_t* counts_out;
+  /* per particle of the step, in the order of the pre-step particles then
+   * the injected ones: fate (0 kept, 1 anode, 2 cathode) and, for the
+   * injected ones (index - n_before), (R1, R2, R, face) */
+  int8_t* fate_out;
+  double* inj_out;
 } ostep_params;
 
 typedef struct {

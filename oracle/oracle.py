@@ -71,6 +71,7 @@ def lib():
     L.om_rhs.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_double, _dp]
     L.om_spmv.argtypes = [C.c_void_p, _dp, _dp]
     L.om_field.argtypes = [C.c_void_p, _dp, _dp]
+    L.om_field_adj.argtypes = [C.c_void_p, _dp, _dp]
     L.om_fn_current.restype = C.c_double
     L.om_fn_current.argtypes = [C.c_double, C.c_double, C.POINTER(C.c_int)]
     L.om_constants.argtypes = [_dp]
@@ -100,7 +101,9 @@ class _StepParams(C.Structure):
                 ("phi_w", C.c_double), ("j_scale", C.c_double),
                 ("tol", C.c_double), ("seed", C.c_uint64), ("step", C.c_int64),
                 ("instance", C.c_int64), ("max_iter", C.c_int32),
-                ("pad", C.c_int32), ("s_face", C.c_void_p)]
+                ("pad", C.c_int32), ("s_face", C.c_void_p),
+                ("counts_in", C.c_void_p), ("counts_out", C.c_void_p),
+                ("fate_out", C.c_void_p), ("inj_out", C.c_void_p)]
 
 
 class _StepStats(C.Structure):
@@ -264,6 +267,13 @@ class OracleMesh:
                                    int(max_iter), C.byref(it), C.byref(rr))
         return phi, dict(status=s, iters=it.value, relres=rr.value)
 
+    def field_adj(self, Ebar):
+        """Transpose of field(): d<Ebar, field(phi)>/d phi over all nodes."""
+        out = np.zeros(self.n_nodes)
+        lib().om_field_adj(self._h, np.ascontiguousarray(
+            np.asarray(Ebar, np.float64).reshape(-1)), out)
+        return out
+
     def field(self, phi):
         E = np.zeros((self.n_nodes, 3))
         lib().om_field(self._h, np.ascontiguousarray(phi, np.float64),
@@ -313,24 +323,48 @@ class OracleState:
         return info
 
     def step(self, *, dt, E0, w_sp, phi_w, step, seed, instance=0,
-             j_scale=1.0, tol=1e-12, max_iter=20000, s_face=None) -> dict:
+             j_scale=1.0, tol=1e-12, max_iter=20000, s_face=None,
+             counts_in=None, detail=None) -> dict:
+        """One PIC step.  counts_in: frozen emission counts per face.
+        detail: a dict that receives the counts used, the fate of every
+        particle of the step (pre-step particles, then the injected ones:
+        0 kept, 1 anode, 2 cathode) and the injection draws
+        (R1, R2, R, face) of the injected ones."""
         ps = self._struct()
         pr = _StepParams()
         pr.dt, pr.E0, pr.w_sp, pr.phi_w = dt, E0, w_sp, phi_w
         pr.j_scale, pr.tol = j_scale, tol
         pr.seed, pr.step, pr.instance = seed, step, instance
         pr.max_iter = max_iter
-        sf = None
+        sf = ci = None
         if s_face is not None:
             sf = np.ascontiguousarray(s_face, np.float64)
             pr.s_face = sf.ctypes.data
+        if counts_in is not None:
+            ci = np.ascontiguousarray(counts_in, np.int64)
+            pr.counts_in = ci.ctypes.data
+        if detail is not None:
+            co = np.zeros(max(self.om.n_emit, 1), np.int64)
+            fate = np.zeros(self.cap, np.int8)
+            inj = np.zeros((self.cap, 4))
+            pr.counts_out = co.ctypes.data
+            pr.fate_out = fate.ctypes.data
+            pr.inj_out = inj.ctypes.data
+        n0 = self.n
         st = _StepStats()
         E = np.ascontiguousarray(self.E.reshape(-1))
         lib().om_pic_step(self.om._h, C.byref(ps), self.phi, E, self.c,
                           C.byref(pr), C.byref(st))
         self.E = E.reshape(-1, 3)
         self.n = ps.n
-        return st.as_dict()
+        out = st.as_dict()
+        if detail is not None:
+            n_all = n0 + out["n_inj"]
+            detail["counts"] = co[: self.om.n_emit].copy()
+            detail["fate"] = fate[:n_all].copy()
+            detail["inj"] = inj[: out["n_inj"]].copy()
+            detail["n_before"] = n0
+        return out
 
     def inject(self, *, dt, E0, w_sp, phi_w, step, seed, instance=0,
                j_scale=1.0, s_face=None):
