@@ -238,6 +238,51 @@ PIC_API pic_status emission_rate(const pic_mesh* mesh, const double* E, double p
                          double* rate, double* face_F, void* stream);
 
 /* ------------------------------------------------------------------------ */
+/* Adjoint of one step (an addition: the paper has no adjoint).             */
+/* Objective over a window of T steps: J = wQ J_Q + wE J_E with J_Q the     */
+/* charge (in e) the anode collects, w_sp sum w, and J_E the mean over the  */
+/* emitting faces and the post-solve fields E_1..E_T of |E| at the face     */
+/* centroid.  Parameters: E0 (Eq. poisson_bc) and s_f, the multiplier of    */
+/* the weight of every superparticle born at face f (params->s_face; in-    */
+/* flight ones included).  Held fixed: emission counts (Eq. rnd_nsp), the   */
+/* injection draws, the absorption events and the containing tets; the      */
+/* fixed-point rounding of the deposition is taken as exact.                */
+/*                                                                          */
+/* pre: the state at the start of step k (a checkpoint).  post: the state   */
+/* pic_step made from it with the same params and resort_every = 0 (slot i  */
+/* < pre n_slots is the same superparticle; later slots are the ones        */
+/* injected in step k).  Fk: phi_k and E_k; Fk1: E_{k+1}.  Both particle    */
+/* sets have the precision of pre->precision, the fields the matching type.  */
+/* adj: in: the adjoint of the post-step state (rb, vb per post slot) and,  */
+/* in Eb, the adjoint of E_{k+1} from the gathers of step k + 1; out: the   */
+/* adjoint of the pre-step state (pre slots; later slots zeroed) and, in    */
+/* Eb, that of E_k from this step's gathers.  dJ_dE0 and dJ_ds accumulate.  */
+/* mode PIC_ADJ_INITIAL ends a window: the reverse of the solve that gave   */
+/* phi_0 from the charge of pre and E0 (Eb in: adjoint of E_0; post, Fk1    */
+/* unused; rb, vb untouched).  mu: device [n_nodes] adjoint potential,      */
+/* warm start in, solution out.  Solves use params->solve.                  */
+/* ------------------------------------------------------------------------ */
+enum { PIC_ADJ_STEP = 0, PIC_ADJ_INITIAL = 1 };
+
+typedef struct {
+  double* rb;       /* device [3*capacity] f64, component-major           */
+  double* vb;       /* device [3*capacity] f64                            */
+  double* Eb;       /* device [4*n_nodes] f64 (x, y, z, unused)           */
+  double* mu;       /* device [n_nodes] f64                               */
+  double* dJ_dE0;   /* device scalar f64, accumulated                     */
+  double* dJ_ds;    /* device [n_emit] f64, accumulated                   */
+  double wQ, wE;    /* objective weights                                  */
+  int32_t T;        /* window length (J_E is a mean over T fields)        */
+  int32_t mode;     /* PIC_ADJ_STEP or PIC_ADJ_INITIAL                    */
+} pic_adjoint;
+
+PIC_API pic_status adjoint_step(pic_mesh* mesh, const pic_particles* pre,
+                        const pic_particles* post, const pic_fields* Fk,
+                        const pic_fields* Fk1, const pic_step_params* params,
+                        const pic_adjoint* adj, pic_solve_stats* stats,
+                        void* stream);
+
+/* ------------------------------------------------------------------------ */
 /* Kernel timing (measurement support, not part of the method).  While      */
 /* enabled, pic_step and poisson_solve bracket every kernel they launch     */
 /* with HIP events on the caller's stream; pic_profile_read synchronizes    */
@@ -246,13 +291,14 @@ PIC_API pic_status emission_rate(const pic_mesh* mesh, const double* E, double p
 /* created on demand while profiling is on.                                 */
 /* ------------------------------------------------------------------------ */
 enum {
-  PIC_K_PUSH = 0,     /* gather + kick + drift + walk + deposit (live)     */
-  PIC_K_EMIT = 1,     /* per-face FN counts and scan                      */
-  PIC_K_INJECT = 2,   /* new particles                                    */
-  PIC_K_FALLBACK = 3, /* exact location of uncertified particles           */
-  PIC_K_SOLVE = 4,    /* RHS + PCG + nodal field (one cooperative kernel)  */
+  PIC_K_PUSH = 0,     /* live + injected: gather, kick, drift, walk, deposit */
+  PIC_K_EMIT = 1,     /* per-step clears, per-face FN counts and scan      */
+  PIC_K_INJECT = 2,   /* (injection runs inside PIC_K_PUSH)                */
+  PIC_K_FALLBACK = 3, /* exact location of uncertified particles, stats    */
+  PIC_K_SOLVE = 4,    /* residual + nodal field pass, PCG iterations      */
   PIC_K_SORT = 5,     /* sort by tet + compaction                         */
   PIC_K_CLEAR = 6,    /* per-step clears of charge and counters           */
+  PIC_K_ADJOINT = 7,  /* adjoint_step (its solve included)                */
   PIC_K_COUNT = 8
 };
 

@@ -1,0 +1,54 @@
+// Launch interface of the adjoint kernels (reverse of one PIC step).
+#pragma once
+#include "common.h"
+
+namespace fp {
+
+constexpr int kAdjBlock = 256;
+
+struct AdjArgs {
+  DevMesh m;
+  // pre-step (checkpoint) particles
+  const void *px, *py, *pz;
+  const int32_t* ptet;
+  const int32_t* n_pre;     // device scalar
+  // post-step particles (the same slots, then the injected ones)
+  const void *qx, *qy, *qz;
+  const int32_t* qtet;
+  const double* qw;
+  const int32_t* qbirth;
+  const int64_t* qid;
+  const int32_t* n_post;    // device scalar
+  int f32;                  // positions stored in FP32
+  const void* Ek;           // E_k [4 n_nodes]
+  const void* Ek1;          // E_{k+1}
+  int e32;                  // fields stored in FP32
+  const double* s_face;     // weight multipliers or null (all 1)
+  int64_t cap;
+  double* rb;               // [3][cap] adjoint of positions
+  double* vb;               // [3][cap] adjoint of velocities
+  double* Eb;               // [4 n_nodes] adjoint of the field
+  const double* mu;         // [n_nodes] adjoint potential (0 on Dirichlet)
+  double* rhs;              // [n_free] R^T Eb
+  double* sc;               // [cap] weight-adjoint contribution per slot
+  double* av;               // [5][cap] gather-adjoint vector a, then R1, R2
+  long long* acc_E;         // [3 n_nodes] fixed-point accumulators
+  long long* acc_s;         // [n_emit]
+  double* part;             // partial sums / maxima, see the kernels
+  int G;                    // workgroups of the node kernels
+  int Gp;                   // workgroups of the particle kernels
+  double dt, qm, w_sp, coef_real, wQ, wE;
+  int32_t T, initial;
+  uint64_t seed, instance;
+  int64_t step;
+  double* dJ_dE0;           // device scalar (+=)
+  double* dJ_ds;            // device [n_emit] (+=)
+};
+
+// objective term of E_{k+1} into Eb, then R^T Eb into rhs; clears the
+// accumulators
+hipError_t adj_launch_pre_solve(const AdjArgs& a, hipStream_t s);
+// after the solve of K mu = rhs: the particle reverse and the scatters
+hipError_t adj_launch_post_solve(const AdjArgs& a, hipStream_t s);
+
+}  // namespace fp

@@ -6,6 +6,7 @@
 #include <cstring>
 #include <string>
 
+#include "adjoint.h"
 #include "mesh.h"
 #include "particles.h"
 #include "solver.h"
@@ -289,6 +290,7 @@ pic_status mesh_destroy(pic_mesh* h) {
   fp::free_mesh(h);
   if (h->queue) (void)hipFree(h->queue);
   if (h->sort_mem) (void)hipFree(h->sort_mem);
+  if (h->adj_mem) (void)hipFree(h->adj_mem);
   for (hipEvent_t ev : h->ev_pool) (void)hipEventDestroy(ev);
   delete h;
   return PIC_OK;
@@ -524,6 +526,122 @@ pic_status pic_step(pic_mesh* h, const pic_particles* P, const pic_fields* F,
       prof_end(h, s);
     }
   }
+  return PIC_OK;
+}
+
+pic_status adjoint_step(pic_mesh* h, const pic_particles* pre,
+                        const pic_particles* post, const pic_fields* Fk,
+                        const pic_fields* Fk1, const pic_step_params* prm,
+                        const pic_adjoint* adj, pic_solve_stats* stats,
+                        void* stream) {
+  if (!h || !pre || !Fk || !prm || !adj)
+    return fail(PIC_E_ARG, "adjoint_step: null argument");
+  const bool initial = adj->mode == PIC_ADJ_INITIAL;
+  if (adj->mode != PIC_ADJ_STEP && !initial)
+    return fail(PIC_E_ARG, "adjoint_step: unknown mode");
+  if (!initial && (!post || !Fk1 || !Fk1->E || !Fk->E))
+    return fail(PIC_E_ARG, "adjoint_step: a step needs post, E_k and E_{k+1}");
+  if (!adj->rb || !adj->vb || !adj->Eb || !adj->mu || !adj->dJ_dE0 || !adj->dJ_ds)
+    return fail(PIC_E_ARG, "adjoint_step: null adjoint array");
+  if (adj->T <= 0 || !std::isfinite(adj->wQ) || !std::isfinite(adj->wE))
+    return fail(PIC_E_ARG, "adjoint_step: T must be > 0 and the weights finite");
+  if (pre->precision != PIC_FP64 && pre->precision != PIC_MIXED)
+    return fail(PIC_E_ARG, "adjoint_step: unknown particle precision");
+  if (!initial && (post->precision != pre->precision || post->capacity != pre->capacity))
+    return fail(PIC_E_ARG, "adjoint_step: pre and post differ in precision or capacity");
+  if (pre->capacity <= 0 || pre->capacity >= (1ll << 31))
+    return fail(PIC_E_ARG, "adjoint_step: capacity must be in [1, 2^31)");
+  if (!finite_pos(prm->dt) || !finite_pos(prm->w_sp))
+    return fail(PIC_E_ARG, "adjoint_step: invalid step parameters");
+  pic_status ps = check_solve(&prm->solve);
+  if (ps != PIC_OK) return ps;
+  const pic_particles* Q = initial ? pre : post;
+  if (!pre->x || !pre->tet || !pre->n_slots || !Q->x || !Q->y || !Q->z ||
+      !Q->w || !Q->tet || !Q->birth || !Q->id || !Q->n_slots)
+    return fail(PIC_E_ARG, "adjoint_step: null particle array");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t cap = pre->capacity;
+  const int64_t N = h->dm.n_nodes, F = h->dm.n_emit;
+  const int Gp = h->n_cu * 4;
+  const int G = h->cg_grid;
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t need = al(8 * (size_t)cap) + al(40 * (size_t)cap) + al(24 * (size_t)N) +
+                      al(8 * (size_t)std::max<int64_t>(F, 1)) + al(8 * (size_t)(G + 2 * Gp));
+  if (need > h->adj_bytes) {
+    if (h->adj_mem) {
+      hipError_t e = hipFree(h->adj_mem);
+      if (e != hipSuccess) return hip_fail(e, "adjoint_step");
+      h->adj_mem = nullptr;
+      h->adj_bytes = 0;
+    }
+    hipError_t e = hipMalloc(&h->adj_mem, need);
+    if (e != hipSuccess) return hip_fail(e, "adjoint_step");
+    h->adj_bytes = need;
+  }
+  char* p = (char*)h->adj_mem;
+  auto take = [&](size_t b) {
+    char* q = p;
+    p += al(b);
+    return (void*)q;
+  };
+  const fp::Phys ph = fp::phys_constants();
+  fp::AdjArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.m = h->dm;
+  a.px = pre->x;
+  a.py = pre->y;
+  a.pz = pre->z;
+  a.ptet = pre->tet;
+  a.n_pre = pre->n_slots;
+  a.qx = Q->x;
+  a.qy = Q->y;
+  a.qz = Q->z;
+  a.qtet = Q->tet;
+  a.qw = Q->w;
+  a.qbirth = Q->birth;
+  a.qid = Q->id;
+  a.n_post = Q->n_slots;
+  a.f32 = pre->precision == PIC_MIXED;
+  a.Ek = Fk->E;
+  a.Ek1 = initial ? nullptr : Fk1->E;
+  a.e32 = a.f32;
+  a.s_face = prm->s_face;
+  a.cap = cap;
+  a.rb = adj->rb;
+  a.vb = adj->vb;
+  a.Eb = adj->Eb;
+  a.mu = adj->mu;
+  a.rhs = h->cg_vec[0];
+  a.sc = (double*)take(8 * (size_t)cap);
+  a.av = (double*)take(40 * (size_t)cap);
+  a.acc_E = (long long*)take(24 * (size_t)N);
+  a.acc_s = (long long*)take(8 * (size_t)std::max<int64_t>(F, 1));
+  a.part = (double*)take(8 * (size_t)(G + 2 * Gp));
+  a.G = G;
+  a.Gp = Gp;
+  a.dt = prm->dt;
+  a.qm = ph.qm;
+  a.w_sp = prm->w_sp;
+  a.coef_real = (-ph.e_eps) * prm->w_sp;
+  a.wQ = adj->wQ;
+  a.wE = adj->wE;
+  a.T = adj->T;
+  a.initial = initial ? 1 : 0;
+  a.seed = prm->seed;
+  a.instance = (uint64_t)prm->instance;
+  a.step = prm->step0;
+  a.dJ_dE0 = adj->dJ_dE0;
+  a.dJ_ds = adj->dJ_ds;
+  prof_begin(h, PIC_K_ADJOINT, s);
+  hipError_t e = fp::adj_launch_pre_solve(a, s);
+  if (e != hipSuccess) return hip_fail(e, "adjoint_step");
+  fp::CgArgs ca = cg_args(h, nullptr, 0.0, 0.0, adj->mu, nullptr, false, &prm->solve);
+  ca.rhs = a.rhs;
+  ca.stats = stats;
+  int64_t iters = 0;
+  if ((e = run_solve(h, ca, 0, s, &iters)) != hipSuccess) return hip_fail(e, "adjoint_step solve");
+  if ((e = fp::adj_launch_post_solve(a, s)) != hipSuccess) return hip_fail(e, "adjoint_step");
+  prof_end(h, s);
   return PIC_OK;
 }
 

@@ -85,6 +85,14 @@ struct DevMesh {
   const double* d_sval;    // [3][d_np] R on the Dirichlet rows
   const float* d_sval32;   // [3][d_np]
   const double4* f_rowsum; // [n_nodes] FP64 row sums of R (w unused)
+  // R^T (rows free nodes j, entries R_ij): the part over free i in K's
+  // layout (slot of (j, i) holds R_ij), the part over Dirichlet i in a
+  // sliced ELLPACK of its own over the free rows
+  const double* rt_sval;   // [3][k_np]
+  int64_t t_nslices, t_np;
+  const int32_t* t_sptr;
+  const int32_t* t_ncol;   // Dirichlet node ids
+  const double* t_sval;    // [3][t_np]
   // emitting faces
   const int32_t* e_tet;
   const int32_t* e_nodes;    // [3*n_emit]

@@ -39,6 +39,8 @@ struct pic_mesh {
   int32_t* queue = nullptr;
   void* sort_mem = nullptr;
   size_t sort_bytes = 0;
+  void* adj_mem = nullptr;             // adjoint scratch (grown on demand)
+  size_t adj_bytes = 0;
   // host copies of the emitting faces
   std::vector<int32_t> h_e_tet, h_e_nodes;
   std::vector<double> h_e_area;

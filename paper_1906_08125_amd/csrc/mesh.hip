@@ -419,7 +419,48 @@ pic_status build_mesh(const pic_mesh_desc* d, pic_mesh* h, std::string& msg) {
     }
     drow[di + 1] = (int32_t)dcol.size();
   }
-  std::vector<int32_t> k_sptr, k_scol, k_ncol, d_sptr, d_ncol, k_sptr2;
+  // R^T: for free row j, the value R_ij at K's slot of (j, i) for free i,
+  // and the entries of Dirichlet rows i in a CSR over the free rows j
+  std::vector<double> rtv[3];
+  for (int c = 0; c < 3; ++c) rtv[c].assign(col.size(), 0.0);
+  std::vector<int32_t> trow(NF + 1, 0), tcol;
+  std::vector<double> tv3[3];
+  {
+    for (int64_t i = 0; i < N; ++i) {
+      const int32_t fi = node2free[i];
+      for (int32_t p = frow[i]; p < frow[i + 1]; ++p) {
+        const int32_t j = fcol[p];
+        if (fi >= 0) {
+          const int32_t* b = col.data() + rowptr[j];
+          const int32_t* e = col.data() + rowptr[j + 1];
+          const int32_t* hit = std::lower_bound(b, e, fi);
+          if (hit == e || *hit != fi) {
+            msg = "mesh_create: field operator and stiffness patterns differ";
+            return PIC_E_MESH;
+          }
+          const size_t k = (size_t)(hit - col.data());
+          for (int c = 0; c < 3; ++c) rtv[c][k] = fv[c][p];
+        } else {
+          trow[j + 1]++;
+        }
+      }
+    }
+    for (int64_t j = 0; j < NF; ++j) trow[j + 1] += trow[j];
+    tcol.assign(trow[NF], 0);
+    for (int c = 0; c < 3; ++c) tv3[c].assign(trow[NF], 0.0);
+    std::vector<int32_t> fill(trow.begin(), trow.end() - 1);
+    for (int64_t i = 0; i < N; ++i) {
+      if (node2free[i] >= 0) continue;
+      for (int32_t p = frow[i]; p < frow[i + 1]; ++p) {
+        const int32_t j = fcol[p];
+        const int32_t q = fill[j]++;
+        tcol[q] = (int32_t)i;
+        for (int c = 0; c < 3; ++c) tv3[c][q] = fv[c][p];
+      }
+    }
+  }
+  std::vector<int32_t> k_sptr, k_scol, k_ncol, d_sptr, d_ncol, k_sptr2, t_sptr, t_ncol;
+  std::vector<double> rt_sval, t_sval;
   std::vector<double> k_sval, r_sval, d_sval;
   const int64_t k_np = to_sell(rowptr, col, {&val}, NF, 0, k_sptr, k_scol, k_sval);
   {
@@ -428,6 +469,13 @@ pic_status build_mesh(const pic_mesh_desc* d, pic_mesh* h, std::string& msg) {
   }
   const int64_t d_np = to_sell(drow, dcol, {&dv[0], &dv[1], &dv[2]}, ND,
                                free2node.empty() ? 0 : free2node[0], d_sptr, d_ncol, d_sval);
+  {
+    std::vector<int32_t> unused_cols;
+    to_sell(rowptr, col, {&rtv[0], &rtv[1], &rtv[2]}, NF, 0, k_sptr2, unused_cols, rt_sval);
+  }
+  const int32_t pad_dir = dir_nodes.empty() ? 0 : dir_nodes[0];
+  const int64_t t_np = to_sell(trow, tcol, {&tv3[0], &tv3[1], &tv3[2]}, NF, pad_dir,
+                               t_sptr, t_ncol, t_sval);
   if (k_np >= (1ll << 31) || d_np >= (1ll << 31)) {
     msg = "mesh_create: padded matrix too large for 32-bit offsets";
     return PIC_E_ARG;
@@ -580,6 +628,12 @@ pic_status build_mesh(const pic_mesh_desc* d, pic_mesh* h, std::string& msg) {
     M.d_ncol = upload(h, d_ncol, err);
     M.d_sval = upload(h, d_sval, err);
     M.d_sval32 = upload(h, d_sval32, err);
+    M.rt_sval = upload(h, rt_sval, err);
+    M.t_nslices = (int64_t)t_sptr.size() - 1;
+    M.t_np = t_np;
+    M.t_sptr = upload(h, t_sptr, err);
+    M.t_ncol = upload(h, t_ncol, err);
+    M.t_sval = upload(h, t_sval, err);
   }
   {
     // walk seeds: lowest-index tet whose centroid lies in each bucket

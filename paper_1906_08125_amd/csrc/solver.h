@@ -33,6 +33,7 @@ constexpr int kCgSlots = 10;
 struct CgArgs {
   DevMesh m;
   const int64_t* charge;  // [n_nodes] or null
+  const double* rhs;      // [n_free] right-hand side replacing the load, or null
   double coef;            // (-e/eps0) w_sp 2^-40
   double E0;
   double tol;

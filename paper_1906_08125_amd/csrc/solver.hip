@@ -204,8 +204,13 @@ __global__ void __launch_bounds__(512) k_cg_resfield(CgArgs a, int reset) {
         }
       }
       if (!row) continue;
-      const double c = a.charge ? (double)a.charge[nd] : 0.0;
-      const double bi = a.coef * c + a.E0 * m.g_unit[r];
+      double bi;
+      if (a.rhs) {
+        bi = a.rhs[r];
+      } else {
+        const double c = a.charge ? (double)a.charge[nd] : 0.0;
+        bi = a.coef * c + a.E0 * m.g_unit[r];
+      }
       const double ri = bi - kx;
       a.x[r] = pi;
       if (a.mixed) {

@@ -77,12 +77,22 @@ STEP_STATS_FIELDS = (
 STEP_STATS_FLOATS = ("cg_relres", "emit_current", "mean_face_E", "max_face_E")
 STEP_STATS_BYTES = 8 * (len(STEP_STATS_FIELDS) + len(STEP_STATS_FLOATS))
 
+class AdjointArgs(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("rb", "vb", "Eb", "mu", "dJ_dE0",
+                                          "dJ_ds")] + [
+        ("wQ", C.c_double), ("wE", C.c_double), ("T", C.c_int32),
+        ("mode", C.c_int32)]
+
+
+PIC_ADJ_STEP, PIC_ADJ_INITIAL = 0, 1
+
 _lib = None
 EXPORTS = ("mesh_create", "mesh_destroy", "mesh_query", "mesh_emit_faces",
            "locate", "deposit", "poisson_solve", "pic_step", "emission_rate",
-           "pic_profile", "pic_profile_read", "pic_last_error")
+           "adjoint_step", "pic_profile", "pic_profile_read",
+           "pic_last_error")
 KERNEL_CLASSES = ("push", "emit", "inject", "fallback", "solve", "sort",
-                  "clear", "spare")
+                  "clear", "adjoint")
 
 
 class KernelTimes(C.Structure):
@@ -111,6 +121,10 @@ def load_library(path: str = LIB_PATH):
     L.pic_step.argtypes = [vp, C.POINTER(Particles), C.POINTER(Fields),
                            C.POINTER(StepParams), i32, vp, vp]
     L.emission_rate.argtypes = [vp, vp, dbl, vp, vp, vp]
+    L.adjoint_step.argtypes = [vp, C.POINTER(Particles), C.POINTER(Particles),
+                               C.POINTER(Fields), C.POINTER(Fields),
+                               C.POINTER(StepParams), C.POINTER(AdjointArgs),
+                               vp, vp]
     L.pic_profile.argtypes = [vp, i32]
     L.pic_profile_read.argtypes = [vp, C.POINTER(KernelTimes)]
     L.pic_last_error.restype = C.c_char_p
@@ -326,3 +340,171 @@ class State:
                     z=g(self.z).astype(np.float64), vx=g(self.vx).astype(np.float64),
                     vy=g(self.vy).astype(np.float64), vz=g(self.vz).astype(np.float64),
                     w=g(self.w), tet=tet[keep], birth=g(self.birth), id=g(self.id))
+
+
+# ---------------------------------------------------------------------------
+# Adjoint window: T steps with per-step checkpoints (forward) and the
+# reverse sweep that recomputes each step from its checkpoint and calls
+# adjoint_step (backward).
+# ---------------------------------------------------------------------------
+_PARTICLE_ARRAYS = ("x", "y", "z", "vx", "vy", "vz", "w", "tet", "birth", "id",
+                    "n_slots")
+
+
+class _Checkpoint:
+    """Device copies of a state's particles, phi and E."""
+
+    def __init__(self, st: "State"):
+        for k in _PARTICLE_ARRAYS + ("phi", "E"):
+            setattr(self, k, getattr(st, k).clone())
+        self.capacity = st.capacity
+        self.precision = st.precision
+        self.p = Particles(st.capacity, st.precision, 0, *[
+            getattr(self, k).data_ptr() for k in _PARTICLE_ARRAYS])
+        self.f = Fields(self.phi.data_ptr(), self.E.data_ptr(), 0)
+
+    def restore(self, st: "State"):
+        for k in _PARTICLE_ARRAYS + ("phi", "E"):
+            getattr(st, k).copy_(getattr(self, k))
+
+
+class Window:
+    """T steps from the population currently in `state`.  The parameters
+    are E0 and s (per emitting face: the weight of every superparticle born
+    there is s_f times its base weight, the in-flight ones included); the
+    objective is J = wQ J_Q + wE J_E (collected charge in e; mean |E| over
+    the emitting-face centroids and the fields E_1..E_T)."""
+
+    def __init__(self, mesh: Mesh, state: "State", T: int, step0: int, *,
+                 dt, w_sp, phi_w, seed, j_scale=1.0, instance=0, tol=1e-10,
+                 max_iter=20000):
+        torch = _torch()
+        self.mesh, self.state, self.T, self.step0 = mesh, state, int(T), int(step0)
+        self.kw = dict(dt=dt, w_sp=w_sp, phi_w=phi_w, seed=seed,
+                       j_scale=j_scale, instance=instance, tol=tol,
+                       max_iter=max_iter)
+        self.base = _Checkpoint(state)        # population with base weights
+        self.scratch = State(mesh, state.capacity, state.precision,
+                             solve_precision=state.solve_precision,
+                             inner_tol=state.inner_tol)
+        self.cks = []
+        self.charge = torch.zeros(mesh.n_nodes, dtype=torch.int64,
+                                  device=state.phi.device)
+
+    def _params(self, E0, s, step0):
+        k = self.kw
+        return StepParams(k["dt"], E0, k["w_sp"], k["phi_w"], k["j_scale"],
+                          k["seed"], step0, k["instance"], s.data_ptr(), 0, 0,
+                          SolveParams(k["tol"], self.state.inner_tol,
+                                      k["max_iter"], self.state.solve_precision))
+
+    def _initial_field(self, st: "State", E0):
+        """phi_0 and E_0 from the in-flight charge (weights already set)."""
+        torch = _torch()
+        n = int(st.n_slots.item())
+        self.charge.zero_()
+        if n:
+            f64 = lambda t: t[:n].to(torch.float64)
+            self.mesh.deposit(f64(st.x), f64(st.y), f64(st.z), st.tet[:n],
+                              st.w[:n], self.charge)
+        self.mesh.poisson_solve(self.charge, self.kw["w_sp"], E0, st.phi,
+                                st.E, tol=self.kw["tol"],
+                                max_iter=self.kw["max_iter"],
+                                precision=st.precision,
+                                inner_tol=st.inner_tol)
+
+    def _face_mean(self, E):
+        torch = _torch()
+        _, F = self.mesh.emission_rate(E.to(torch.float64), self.kw["phi_w"])
+        return F.mean() if F.numel() else torch.zeros((), dtype=torch.float64,
+                                                      device=E.device)
+
+    def forward(self, E0: float, s):
+        """Runs the window from the base population; returns (J_Q, J_E) as
+        device scalars and keeps the checkpoints."""
+        torch = _torch()
+        st, k = self.state, self.kw
+        self.base.restore(st)
+        live = st.tet >= 0
+        sb = s.to(torch.float64)[st.birth.long().clamp(min=0)]
+        st.w.copy_(torch.where(live, self.base.w * sb, self.base.w))
+        self._initial_field(st, E0)
+        self.cks = []
+        JQ = torch.zeros((), dtype=torch.float64, device=st.phi.device)
+        JE = torch.zeros((), dtype=torch.float64, device=st.phi.device)
+        for j in range(self.T):
+            self.cks.append(_Checkpoint(st))
+            stats = st.step(dt=k["dt"], E0=E0, w_sp=k["w_sp"], phi_w=k["phi_w"],
+                            step0=self.step0 + j, seed=k["seed"],
+                            instance=k["instance"], j_scale=k["j_scale"],
+                            tol=k["tol"], max_iter=k["max_iter"], s_face=s,
+                            resort_every=0)
+            row = stats.view(-1)
+            JQ = JQ + row[STEP_STATS_FIELDS.index("q_anode")].to(torch.float64) * (
+                k["w_sp"] / CHARGE_SCALE)
+            JE = JE + self._face_mean(st.E) / self.T
+        return JQ, JE
+
+    def backward(self, E0: float, s, wQ=1.0, wE=1.0):
+        """dJ/dE0 (device scalar) and dJ/ds (device [n_emit]) of the last
+        forward, recomputing each step from its checkpoint."""
+        torch = _torch()
+        st, sc, k = self.state, self.scratch, self.kw
+        dev = st.phi.device
+        cap, N = st.capacity, self.mesh.n_nodes
+        z = lambda n: torch.zeros(n, dtype=torch.float64, device=dev)
+        rb, vb, Eb, mu = z(3 * cap), z(3 * cap), z(4 * N), z(N)
+        dE0, ds = z(1), z(max(self.mesh.n_emit, 1))
+        adj = AdjointArgs(rb.data_ptr(), vb.data_ptr(), Eb.data_ptr(),
+                          mu.data_ptr(), dE0.data_ptr(), ds.data_ptr(),
+                          float(wQ), float(wE), self.T, PIC_ADJ_STEP)
+        L = load_library()
+        for j in range(self.T - 1, -1, -1):
+            ck = self.cks[j]
+            ck.restore(sc)
+            sc.step(dt=k["dt"], E0=E0, w_sp=k["w_sp"], phi_w=k["phi_w"],
+                    step0=self.step0 + j, seed=k["seed"], instance=k["instance"],
+                    j_scale=k["j_scale"], tol=k["tol"], max_iter=k["max_iter"],
+                    s_face=s, resort_every=0)
+            prm = self._params(E0, s, self.step0 + j)
+            _check(L.adjoint_step(self.mesh.handle, C.byref(ck.p),
+                                  C.byref(sc._p), C.byref(ck.f),
+                                  C.byref(sc._f), C.byref(prm), C.byref(adj),
+                                  None, _stream(torch)))
+        adj.mode = PIC_ADJ_INITIAL
+        ck = self.cks[0]
+        prm = self._params(E0, s, self.step0)
+        _check(L.adjoint_step(self.mesh.handle, C.byref(ck.p), None,
+                              C.byref(ck.f), None, C.byref(prm), C.byref(adj),
+                              None, _stream(torch)))
+        return dE0[0], ds[: self.mesh.n_emit]
+
+
+def _window_function():
+    torch = _torch()
+
+    class PICWindowFn(torch.autograd.Function):
+        """J(E0, s) = wQ J_Q + wE J_E of a Window, with the hand-written
+        adjoint as its backward."""
+
+        @staticmethod
+        def forward(ctx, E0, s, window, wQ, wE):
+            e0 = float(E0)
+            s64 = s.detach().to(torch.float64).contiguous()
+            JQ, JE = window.forward(e0, s64)
+            ctx.window, ctx.e0, ctx.w = window, e0, (wQ, wE)
+            ctx.save_for_backward(s64)
+            return (wQ * JQ + wE * JE).to(E0.dtype)
+
+        @staticmethod
+        def backward(ctx, g):
+            (s64,) = ctx.saved_tensors
+            dE0, ds = ctx.window.backward(ctx.e0, s64, *ctx.w)
+            return (g * dE0).to(g.dtype), (g * ds).to(s64.dtype), None, None, None
+
+    return PICWindowFn
+
+
+def window_objective(E0, s, window: Window, wQ=1.0, wE=1.0):
+    """Differentiable J(E0, s) (torch.autograd) over `window`."""
+    return _window_function().apply(E0, s, window, wQ, wE)

@@ -19,7 +19,7 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = set(declared_functions())
     for n in ("mesh_create", "pic_step", "poisson_solve", "deposit", "locate",
-              "mesh_destroy", "pic_last_error"):
+              "adjoint_step", "mesh_destroy", "pic_last_error"):
         assert n in names, n
 
 
@@ -46,3 +46,5 @@ def test_host_argument_checks():
     assert L.deposit(None, 1, None, None, None, None, None, None, None) == \
         pic.PIC_E_ARG
     assert L.pic_step(None, None, None, None, 1, None, None) == pic.PIC_E_ARG
+    assert L.adjoint_step(None, None, None, None, None, None, None, None,
+                          None) == pic.PIC_E_ARG
