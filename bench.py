@@ -161,6 +161,10 @@ def run_gpu(args):
                      for n, v in mk.items()},
             push_GBps=round(push_bytes(m_live, 4) / m_push_us / 1e3, 1))
         del ml
+    adjoint = None
+    if not args.no_adjoint:
+        torch.cuda.empty_cache()
+        adjoint = run_adjoint_leg(gm, cfg, rate, args)
     out = dict(
         metric=METRIC, value=round(args.steps / elapsed, 3), unit="steps/s",
         n_gpus=1, steps=args.steps, warmup=args.warmup,
@@ -178,11 +182,59 @@ def run_gpu(args):
                         relres=cold["relres"]),
         kernels=kernels,
         mixed=mixed,
+        adjoint=adjoint,
         roofline=dict(kernel=dom, bound="hbm", achieved=round(achieved, 1),
                       peak=HBM_PEAK_GBS, unit="GB/s",
                       frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None),
     )
     return out, dict(cfg=cfg, tip=tip, w_sp=w_sp)
+
+
+def run_adjoint_leg(gm, cfg, rate, args):
+    """Adjoint window on the production mesh: mixed precision (FP32
+    particles and field, FP64-refined forward and transposed solves), about
+    2e5 live superparticles after 100 warm-up steps, a window of 20 steps
+    with per-step checkpoints; the backward recomputes every step from its
+    checkpoint.  Reports forward and backward wall time on the device."""
+    import torch
+
+    from paper_1906_08125_amd import pic
+
+    n_target = 2e5
+    w_sp = rate * cfg.dt * cfg.transit_steps / n_target
+    gs = pic.State(gm, int(6e5), precision=pic.PIC_MIXED,
+                   inner_tol=args.inner_tol)
+    gs.init_field(cfg.E0, tol=cfg.tol)
+    warm = 100
+    gs.step(dt=cfg.dt, E0=cfg.E0, w_sp=w_sp, phi_w=cfg.phi_w, step0=0,
+            seed=cfg.seed, tol=cfg.tol, resort_every=10, n_steps=warm)
+    torch.cuda.synchronize()
+    live = int((gs.tet[: int(gs.n_slots.item())] >= 0).sum().item())
+    T = args.adjoint_steps
+    win = pic.Window(gm, gs, T=T, step0=warm, dt=cfg.dt, w_sp=w_sp,
+                     phi_w=cfg.phi_w, seed=cfg.seed, tol=cfg.tol)
+    s = torch.ones(gm.n_emit, dtype=torch.float64, device="cuda")
+    times = []
+    for rep in range(2):  # the first pass warms the allocator
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        JQ, JE = win.forward(cfg.E0, s)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        dE0, ds = win.backward(cfg.E0, s)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        times.append((t1 - t0, t2 - t1))
+    fwd, bwd = times[-1]
+    recs = [pic.Mesh.solve_stats(win.adjoint_solve_stats[6 * j: 6 * j + 6])
+            for j in range(T + 1)]
+    return dict(window_steps=T, live_particles=live, precision="mixed",
+                adjoint_cg_iters=[r["iters"] for r in recs],
+                fwd_ms=round(1e3 * fwd, 3), bwd_ms=round(1e3 * bwd, 3),
+                adjoint_over_fwd=round(bwd / fwd, 4),
+                J_E=float(JE), J_Q=float(JQ), dJ_dE0=float(dE0),
+                dJ_ds_norm=float(ds.norm()),
+                note="backward includes the recompute of every step")
 
 
 def cpu_baseline(cfg, tip, n_particles, n_steps):
@@ -235,6 +287,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision leg")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the adjoint window leg")
+    ap.add_argument("--adjoint-steps", type=int, default=20)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain 1 GiB device copy (the "
                          "reference kernel for HBM byte counters)")

@@ -260,7 +260,10 @@ PIC_API pic_status emission_rate(const pic_mesh* mesh, const double* E, double p
 /* mode PIC_ADJ_INITIAL ends a window: the reverse of the solve that gave   */
 /* phi_0 from the charge of pre and E0 (Eb in: adjoint of E_0; post, Fk1    */
 /* unused; rb, vb untouched).  mu: device [n_nodes] adjoint potential,      */
-/* warm start in, solution out.  Solves use params->solve.                  */
+/* warm start in, solution out.  Solves use params->solve; with bref (device */
+/* scalar, or NULL) the test is ||r|| <= tol max(||b||, *bref), and *bref is */
+/* raised to ||b||: over a window it holds the largest right-hand side, so  */
+/* every solve is accurate relative to the scale of the whole gradient.     */
 /* ------------------------------------------------------------------------ */
 enum { PIC_ADJ_STEP = 0, PIC_ADJ_INITIAL = 1 };
 
@@ -271,6 +274,7 @@ typedef struct {
   double* mu;       /* device [n_nodes] f64                               */
   double* dJ_dE0;   /* device scalar f64, accumulated                     */
   double* dJ_ds;    /* device [n_emit] f64, accumulated                   */
+  double* bref;     /* device scalar f64 (in/out) or NULL, see above      */
   double wQ, wE;    /* objective weights                                  */
   int32_t T;        /* window length (J_E is a mean over T fields)        */
   int32_t mode;     /* PIC_ADJ_STEP or PIC_ADJ_INITIAL                    */

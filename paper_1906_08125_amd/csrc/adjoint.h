@@ -1,6 +1,7 @@
 // Launch interface of the adjoint kernels (reverse of one PIC step).
 #pragma once
 #include "common.h"
+#include "solver.h"
 
 namespace fp {
 
@@ -43,6 +44,8 @@ struct AdjArgs {
   int64_t step;
   double* dJ_dE0;           // device scalar (+=)
   double* dJ_ds;            // device [n_emit] (+=)
+  double* bref;             // running max of the solves' ||b||, or null
+  const CgCtrl* ctrl;       // the solver's control word (||b||^2 of the solve)
 };
 
 // objective term of E_{k+1} into Eb, then R^T Eb into rhs; clears the

@@ -23,7 +23,6 @@
 // largest contribution (so no sum can overflow), added with integer
 // atomics (exact, order-free) and converted back once.
 #include "adjoint.h"
-#include "solver.h"
 
 namespace fp {
 
@@ -384,7 +383,11 @@ __global__ void __launch_bounds__(512) k_adj_finish(AdjArgs a) {
     double v = 0.0;
     for (int j = threadIdx.x; j < a.G; j += blockDim.x) v += a.part[j];
     v = block_sum<512>(v);
-    if (threadIdx.x == 0) *a.dJ_dE0 += v;
+    if (threadIdx.x == 0) {
+      *a.dJ_dE0 += v;
+      // the solve's ||b||^2 sits in the solver's control word
+      if (a.bref) *a.bref = fmax(*a.bref, sqrt(a.ctrl->bb));
+    }
   }
 }
 

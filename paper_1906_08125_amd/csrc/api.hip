@@ -632,11 +632,14 @@ pic_status adjoint_step(pic_mesh* h, const pic_particles* pre,
   a.step = prm->step0;
   a.dJ_dE0 = adj->dJ_dE0;
   a.dJ_ds = adj->dJ_ds;
+  a.bref = adj->bref;
+  a.ctrl = h->cg_ctrl;
   prof_begin(h, PIC_K_ADJOINT, s);
   hipError_t e = fp::adj_launch_pre_solve(a, s);
   if (e != hipSuccess) return hip_fail(e, "adjoint_step");
   fp::CgArgs ca = cg_args(h, nullptr, 0.0, 0.0, adj->mu, nullptr, false, &prm->solve);
   ca.rhs = a.rhs;
+  ca.bref = adj->bref;
   ca.stats = stats;
   int64_t iters = 0;
   if ((e = run_solve(h, ca, 0, s, &iters)) != hipSuccess) return hip_fail(e, "adjoint_step solve");

@@ -34,6 +34,9 @@ struct CgArgs {
   DevMesh m;
   const int64_t* charge;  // [n_nodes] or null
   const double* rhs;      // [n_free] right-hand side replacing the load, or null
+  // optional reference norm: the stopping test becomes
+  // ||r|| <= tol max(||b||, *bref) (a scale shared by a sequence of solves)
+  const double* bref;
   double coef;            // (-e/eps0) w_sp 2^-40
   double E0;
   double tol;

@@ -296,7 +296,8 @@ __global__ void __launch_bounds__(512) k_cg_start(CgArgs a, int64_t seq) {
   const double bn = sqrt(t[0]);
   const double rn = sqrt(t[1]);
   const int64_t done_iters = c->iters_final;
-  const bool done = bn == 0.0 || rn <= a.tol * bn;
+  const double bs = a.bref ? fmax(bn, *a.bref) : bn;
+  const bool done = bn == 0.0 || rn <= a.tol * bs;
   const bool noconv = !done && done_iters >= a.max_iter;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     c->bb = t[0];
@@ -390,7 +391,7 @@ __global__ void __launch_bounds__(512) k_cg_upd(CgArgs a, int it) {
     // iterating, so every workgroup takes the same decision
     const double rn = sqrt(t3[0]);
     const double bn = sqrt(c->bb);
-    double thr = a.tol * bn;
+    double thr = a.tol * (a.bref ? fmax(bn, *a.bref) : bn);
     if (a.mixed) thr = fmax(thr, a.inner_tol * c->rstart);
     if (rn <= thr || c->iters + it >= a.max_iter) {
       if (blockIdx.x == 0 && threadIdx.x == 0) {

@@ -79,7 +79,7 @@ STEP_STATS_BYTES = 8 * (len(STEP_STATS_FIELDS) + len(STEP_STATS_FLOATS))
 
 class AdjointArgs(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in ("rb", "vb", "Eb", "mu", "dJ_dE0",
-                                          "dJ_ds")] + [
+                                          "dJ_ds", "bref")] + [
         ("wQ", C.c_double), ("wE", C.c_double), ("T", C.c_int32),
         ("mode", C.c_int32)]
 
@@ -454,11 +454,13 @@ class Window:
         cap, N = st.capacity, self.mesh.n_nodes
         z = lambda n: torch.zeros(n, dtype=torch.float64, device=dev)
         rb, vb, Eb, mu = z(3 * cap), z(3 * cap), z(4 * N), z(N)
-        dE0, ds = z(1), z(max(self.mesh.n_emit, 1))
+        dE0, ds, bref = z(1), z(max(self.mesh.n_emit, 1)), z(1)
         adj = AdjointArgs(rb.data_ptr(), vb.data_ptr(), Eb.data_ptr(),
                           mu.data_ptr(), dE0.data_ptr(), ds.data_ptr(),
-                          float(wQ), float(wE), self.T, PIC_ADJ_STEP)
+                          bref.data_ptr(), float(wQ), float(wE), self.T,
+                          PIC_ADJ_STEP)
         L = load_library()
+        sst = torch.zeros(6 * (self.T + 1), dtype=torch.float64, device=dev)
         for j in range(self.T - 1, -1, -1):
             ck = self.cks[j]
             ck.restore(sc)
@@ -470,13 +472,18 @@ class Window:
             _check(L.adjoint_step(self.mesh.handle, C.byref(ck.p),
                                   C.byref(sc._p), C.byref(ck.f),
                                   C.byref(sc._f), C.byref(prm), C.byref(adj),
-                                  None, _stream(torch)))
+                                  C.c_void_p(sst[6 * j:].data_ptr()),
+                                  _stream(torch)))
+        # the first field's adjoint solves another system: start from zero
+        mu.zero_()
         adj.mode = PIC_ADJ_INITIAL
         ck = self.cks[0]
         prm = self._params(E0, s, self.step0)
         _check(L.adjoint_step(self.mesh.handle, C.byref(ck.p), None,
                               C.byref(ck.f), None, C.byref(prm), C.byref(adj),
-                              None, _stream(torch)))
+                              C.c_void_p(sst[6 * self.T:].data_ptr()),
+                              _stream(torch)))
+        self.adjoint_solve_stats = sst   # [T + 1] pic_solve_stats records
         return dE0[0], ds[: self.mesh.n_emit]
 
 
