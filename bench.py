@@ -58,7 +58,11 @@ def run_leg(gm, cfg, w_sp, precision, args):
 
     gs = pic.State(gm, int(args.capacity), precision=precision,
                    inner_tol=args.inner_tol)
-    gs.init_field(cfg.E0, tol=cfg.tol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st0 = gs.init_field(cfg.E0, tol=cfg.tol)
+    torch.cuda.synchronize()
+    cold = dict(pic.Mesh.solve_stats(st0), ms=round(1e3 * (time.perf_counter() - t0), 3))
     kw = dict(dt=cfg.dt, E0=cfg.E0, w_sp=w_sp, phi_w=cfg.phi_w,
               seed=cfg.seed, tol=cfg.tol, resort_every=args.resort)
     step = 0
@@ -83,7 +87,7 @@ def run_leg(gm, cfg, w_sp, precision, args):
     for r in rows:
         if r["status"] != 0:
             raise RuntimeError(f"step status {r['status']}: {r}")
-    return dict(elapsed=elapsed, kt=kt, rows=rows, state=gs)
+    return dict(elapsed=elapsed, kt=kt, rows=rows, state=gs, cold=cold)
 
 
 def run_gpu(args):
@@ -155,6 +159,7 @@ def run_gpu(args):
             live_particles_mean=round(m_live),
             cg_iters_per_step=sum(r["cg_iters"] for r in mr) / len(mr),
             inner_tol=args.inner_tol,
+            cold_solve=ml["cold"],
             kernels={n: dict(ms_total=round(v["ms"], 4),
                              launches=v["launches"],
                              us_per_launch=round(1e3 * v["ms"] / v["launches"], 2))

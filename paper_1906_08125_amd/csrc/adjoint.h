@@ -35,7 +35,7 @@ struct AdjArgs {
   double* av;               // [5][cap] gather-adjoint vector a, then R1, R2
   long long* acc_E;         // [3 n_nodes] fixed-point accumulators
   long long* acc_s;         // [n_emit]
-  double* part;             // partial sums / maxima, see the kernels
+  double* part;             // [G + 2 Gp + 2]: g.mu partials, maxima, scales
   int G;                    // workgroups of the node kernels
   int Gp;                   // workgroups of the particle kernels
   double dt, qm, w_sp, coef_real, wQ, wE;

@@ -102,35 +102,27 @@ __device__ inline double fx_scale(double vmax, int64_t n) {
   return ldexp(1.0, e);
 }
 
-// Scales of the weight (S_s) and field (S_E) scatters from the per-block
-// maxima of the particle kernel; identical in every thread.
+// The scatter scales, written by k_adj_scales after the particle kernel.
 __device__ inline void adj_scales(const AdjArgs& a, double& S_s, double& S_E) {
-  double ms = 0.0, ma = 0.0;
-  for (int j = 0; j < a.Gp; ++j) {
-    ms = fmax(ms, a.part[a.G + j]);
-    ma = fmax(ma, a.part[a.G + a.Gp + j]);
-  }
-  const int64_t n = *a.n_post;
-  S_s = fx_scale(ms, n);
-  S_E = fx_scale(ma, n);
+  S_s = a.part[a.G + 2 * a.Gp];
+  S_E = a.part[a.G + 2 * a.Gp + 1];
 }
 
 }  // namespace
 
-// Objective term of E_{k+1}: d(wE mean_f |e_f|) / dE with the mean over
-// the emitting faces and the T post-solve fields of the window.  One
-// workgroup; contributions are added in face order.
-__global__ void __launch_bounds__(1024) k_adj_obj(AdjArgs a) {
+// Objective term of E_{k+1}: d(wE mean_f |e_f|) / dE, the mean over the
+// emitting faces and the T post-solve fields of the window.  One thread per
+// node of the emitting faces sums its faces in ascending order.
+__global__ void __launch_bounds__(256) k_adj_obj(AdjArgs a) {
   const DevMesh& m = a.m;
-  __shared__ double cb[1024][3];
-  __shared__ int32_t cn[1024][3];
   const int64_t F = m.n_emit;
   if (a.initial || a.wE == 0.0 || F == 0) return;
   const double scale = a.wE / (3.0 * (double)F * (double)a.T);
-  for (int64_t f0 = 0; f0 < F; f0 += 1024) {
-    const int64_t f = f0 + threadIdx.x;
-    if (f < F) {
-      const int32_t* nd = m.e_nodes + 3 * f;
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < m.en_n;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+    for (int32_t q = m.en_ptr[j]; q < m.en_ptr[j + 1]; ++q) {
+      const int32_t* nd = m.e_nodes + 3 * (int64_t)m.en_face[q];
       const double4 A = ld_field(a.Ek1, a.e32, nd[0]);
       const double4 B = ld_field(a.Ek1, a.e32, nd[1]);
       const double4 C = ld_field(a.Ek1, a.e32, nd[2]);
@@ -139,23 +131,14 @@ __global__ void __launch_bounds__(1024) k_adj_obj(AdjArgs a) {
       const double ez = ((A.z + B.z) + C.z) / 3.0;
       const double n = sqrt((ex * ex + ey * ey) + ez * ez);
       const double k = n > 0.0 ? scale / n : 0.0;
-      cb[threadIdx.x][0] = k * ex;
-      cb[threadIdx.x][1] = k * ey;
-      cb[threadIdx.x][2] = k * ez;
-      for (int q = 0; q < 3; ++q) cn[threadIdx.x][q] = nd[q];
+      sx += k * ex;
+      sy += k * ey;
+      sz += k * ez;
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      const int64_t cnt = F - f0 < 1024 ? F - f0 : 1024;
-      for (int64_t j = 0; j < cnt; ++j)
-        for (int q = 0; q < 3; ++q) {
-          double* e = a.Eb + 4 * (int64_t)cn[j][q];
-          e[0] += cb[j][0];
-          e[1] += cb[j][1];
-          e[2] += cb[j][2];
-        }
-    }
-    __syncthreads();
+    double* e = a.Eb + 4 * (int64_t)m.en_node[j];
+    e[0] += sx;
+    e[1] += sy;
+    e[2] += sz;
   }
 }
 
@@ -316,6 +299,23 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj_particles(AdjArgs a) {
   }
 }
 
+// Scales of the weight (S_s) and field (S_E) scatters from the per-block
+// maxima of the particle kernel (one workgroup).
+__global__ void __launch_bounds__(256) k_adj_scales(AdjArgs a) {
+  double ms = 0.0, ma = 0.0;
+  for (int j = threadIdx.x; j < a.Gp; j += blockDim.x) {
+    ms = fmax(ms, a.part[a.G + j]);
+    ma = fmax(ma, a.part[a.G + a.Gp + j]);
+  }
+  ms = block_max<256>(ms);
+  ma = block_max<256>(ma);
+  if (threadIdx.x == 0) {
+    const int64_t n = a.initial ? *a.n_pre : *a.n_post;
+    a.part[a.G + 2 * a.Gp] = fx_scale(ms, n);
+    a.part[a.G + 2 * a.Gp + 1] = fx_scale(ma, n);
+  }
+}
+
 // Fixed-point scatters of the weight contributions (to faces) and of the
 // gather-adjoint vectors (to nodes).
 __global__ void __launch_bounds__(kAdjBlock) k_adj_scatter(AdjArgs a) {
@@ -392,7 +392,8 @@ __global__ void __launch_bounds__(512) k_adj_finish(AdjArgs a) {
 }
 
 hipError_t adj_launch_pre_solve(const AdjArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_adj_obj, dim3(1), dim3(1024), 0, s, a);
+  const int gobj = (int)((a.m.en_n + 255) / 256);
+  hipLaunchKernelGGL(k_adj_obj, dim3(gobj > 0 ? gobj : 1), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_adj_rt, dim3(a.G), dim3(512), 0, s, a);
   return hipGetLastError();
 }
@@ -400,6 +401,7 @@ hipError_t adj_launch_pre_solve(const AdjArgs& a, hipStream_t s) {
 hipError_t adj_launch_post_solve(const AdjArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_adj_mu, dim3(a.G), dim3(512), 0, s, a);
   hipLaunchKernelGGL(k_adj_particles, dim3(a.Gp), dim3(kAdjBlock), 0, s, a);
+  hipLaunchKernelGGL(k_adj_scales, dim3(1), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_adj_scatter, dim3(a.Gp), dim3(kAdjBlock), 0, s, a);
   hipLaunchKernelGGL(k_adj_finish, dim3(a.G), dim3(512), 0, s, a);
   return hipGetLastError();

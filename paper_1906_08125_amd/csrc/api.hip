@@ -566,7 +566,7 @@ pic_status adjoint_step(pic_mesh* h, const pic_particles* pre,
   const int G = h->cg_grid;
   auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
   const size_t need = al(8 * (size_t)cap) + al(40 * (size_t)cap) + al(24 * (size_t)N) +
-                      al(8 * (size_t)std::max<int64_t>(F, 1)) + al(8 * (size_t)(G + 2 * Gp));
+                      al(8 * (size_t)std::max<int64_t>(F, 1)) + al(8 * (size_t)(G + 2 * Gp + 2));
   if (need > h->adj_bytes) {
     if (h->adj_mem) {
       hipError_t e = hipFree(h->adj_mem);
@@ -616,7 +616,7 @@ pic_status adjoint_step(pic_mesh* h, const pic_particles* pre,
   a.av = (double*)take(40 * (size_t)cap);
   a.acc_E = (long long*)take(24 * (size_t)N);
   a.acc_s = (long long*)take(8 * (size_t)std::max<int64_t>(F, 1));
-  a.part = (double*)take(8 * (size_t)(G + 2 * Gp));
+  a.part = (double*)take(8 * (size_t)(G + 2 * Gp + 2));
   a.G = G;
   a.Gp = Gp;
   a.dt = prm->dt;

@@ -99,6 +99,11 @@ struct DevMesh {
   const double* e_abc;       // [9*n_emit]
   const double* e_area;
   const double* e_nrm;       // [3*n_emit], into the vacuum
+  // nodes of the emitting faces and, per node, its faces in ascending order
+  int64_t en_n;
+  const int32_t* en_node;    // [en_n]
+  const int32_t* en_ptr;     // [en_n + 1]
+  const int32_t* en_face;    // [en_ptr[en_n]]
   // bucket grid
   int32_t nb[3];
   double b0[3], b1[3], binv[3];

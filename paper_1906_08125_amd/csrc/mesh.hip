@@ -606,6 +606,25 @@ pic_status build_mesh(const pic_mesh_desc* d, pic_mesh* h, std::string& msg) {
   M.e_nodes = upload(h, e_nodes, err);
   M.e_abc = upload(h, e_abc, err);
   M.e_area = upload(h, e_area, err);
+  {
+    std::vector<std::pair<int32_t, int32_t>> nf;  // (node, face)
+    for (size_t f = 0; f < e_tet.size(); ++f)
+      for (int q = 0; q < 3; ++q) nf.emplace_back(e_nodes[3 * f + q], (int32_t)f);
+    std::sort(nf.begin(), nf.end());
+    std::vector<int32_t> en_node, en_ptr(1, 0), en_face;
+    for (size_t i = 0; i < nf.size(); ++i) {
+      if (i == 0 || nf[i].first != nf[i - 1].first) {
+        if (i > 0) en_ptr.push_back((int32_t)en_face.size());
+        en_node.push_back(nf[i].first);
+      }
+      en_face.push_back(nf[i].second);
+    }
+    if (!nf.empty()) en_ptr.push_back((int32_t)en_face.size());
+    M.en_n = (int64_t)en_node.size();
+    M.en_node = upload(h, en_node, err);
+    M.en_ptr = upload(h, en_ptr, err);
+    M.en_face = upload(h, en_face, err);
+  }
   M.e_nrm = upload(h, e_nrm, err);
   M.bstart = upload(h, bstart, err);
   M.bitem = upload(h, bitem, err);
