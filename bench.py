@@ -197,7 +197,8 @@ def run_gpu(args):
 
 def run_adjoint_leg(gm, cfg, rate, args):
     """Adjoint window on the production mesh: mixed precision (FP32
-    particles and field, FP64-refined forward and transposed solves), about
+    particles and field, FP64-refined forward solves, FP64 transposed
+    solves), about
     2e5 live superparticles after 100 warm-up steps, a window of 20 steps
     with per-step checkpoints; the backward recomputes every step from its
     checkpoint.  Reports forward and backward wall time on the device."""
@@ -234,6 +235,7 @@ def run_adjoint_leg(gm, cfg, rate, args):
     recs = [pic.Mesh.solve_stats(win.adjoint_solve_stats[6 * j: 6 * j + 6])
             for j in range(T + 1)]
     return dict(window_steps=T, live_particles=live, precision="mixed",
+                adjoint_solves="fp64",
                 adjoint_cg_iters=[r["iters"] for r in recs],
                 fwd_ms=round(1e3 * fwd, 3), bwd_ms=round(1e3 * bwd, 3),
                 adjoint_over_fwd=round(bwd / fwd, 4),

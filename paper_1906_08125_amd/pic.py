@@ -377,8 +377,12 @@ class Window:
 
     def __init__(self, mesh: Mesh, state: "State", T: int, step0: int, *,
                  dt, w_sp, phi_w, seed, j_scale=1.0, instance=0, tol=1e-10,
-                 max_iter=20000):
+                 max_iter=20000, adjoint_solve_precision=PIC_FP64):
+        """adjoint_solve_precision: the transposed solves (FP64 by default:
+        on a cold right-hand side the FP32 recursion with FP64 refinement
+        needs more iterations than it saves per iteration)."""
         torch = _torch()
+        self.adj_precision = adjoint_solve_precision
         self.mesh, self.state, self.T, self.step0 = mesh, state, int(T), int(step0)
         self.kw = dict(dt=dt, w_sp=w_sp, phi_w=phi_w, seed=seed,
                        j_scale=j_scale, instance=instance, tol=tol,
@@ -396,7 +400,7 @@ class Window:
         return StepParams(k["dt"], E0, k["w_sp"], k["phi_w"], k["j_scale"],
                           k["seed"], step0, k["instance"], s.data_ptr(), 0, 0,
                           SolveParams(k["tol"], self.state.inner_tol,
-                                      k["max_iter"], self.state.solve_precision))
+                                      k["max_iter"], self.adj_precision))
 
     def _initial_field(self, st: "State", E0):
         """phi_0 and E_0 from the in-flight charge (weights already set)."""
