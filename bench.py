@@ -24,6 +24,24 @@ METRIC = ("PIC steps/s & pushes/s at 3M tets/1M e-; mixed vs FP64 speedup; "
           "adjoint/fwd")
 HBM_PEAK_GBS = 8000.0
 
+# HBM traffic of the dominant kernel (FP64 push) per launch at the
+# production workload, from rocprofv3 FETCH_SIZE and WRITE_SIZE counter runs
+# scaled by a plain 1 GiB copy (profiles/pic_step_fp64_production_tip.md).
+# It is reported only while the kernel sources are the ones profiled.
+PUSH_TRAFFIC = dict(bytes=199.9e6, read=134.3e6, written=65.6e6,
+                    sources=("paper_1906_08125_amd/csrc/particles.hip",
+                             "paper_1906_08125_amd/csrc/common.h"),
+                    sha256=("c4db35d85be8a89b1ae9846bd3124d9dbef8ad94c2406f1606c64c7cfa5ba56b", "c4353e7328c5103c2aa4c818e711b82d9b0a0b073ce8a1762fb7b7907693342a"))
+
+
+def measured_traffic():
+    import hashlib
+    for path, digest in zip(PUSH_TRAFFIC["sources"], PUSH_TRAFFIC["sha256"]):
+        with open(os.path.join(ROOT, path), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != digest:
+                return None
+    return PUSH_TRAFFIC["bytes"]
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -190,7 +208,8 @@ def run_gpu(args):
         adjoint=adjoint,
         roofline=dict(kernel=dom, bound="hbm", achieved=round(achieved, 1),
                       peak=HBM_PEAK_GBS, unit="GB/s",
-                      frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None),
+                      frac=round(achieved / HBM_PEAK_GBS, 4),
+                      traffic=(measured_traffic() if dom == "push" else None)),
     )
     return out, dict(cfg=cfg, tip=tip, w_sp=w_sp)
 
