@@ -477,6 +477,8 @@ pic_status pic_step(pic_mesh* h, const pic_particles* P, const pic_fields* F,
   ea.offsets = h->offsets;
   ea.n_slots = P->n_slots;
   ea.scratch = h->scratch;
+  ea.clear = F->charge;
+  ea.n_clear = h->dm.n_nodes;
 
   fp::CgArgs ca = cg_args(h, F->charge, prm->w_sp, prm->E0, F->phi, F->E, f32,
                           &prm->solve);
@@ -496,7 +498,7 @@ pic_status pic_step(pic_mesh* h, const pic_particles* P, const pic_fields* F,
     ca.step_stats = st;
     // clears + emission counts, then live and new particles in one launch
     prof_begin(h, PIC_K_EMIT, s);
-    if ((e = fp::launch_begin(ea, F->charge, h->dm.n_nodes, h->n_cu * 2, s)) != hipSuccess)
+    if ((e = fp::launch_begin(ea, h->n_cu * 2, s)) != hipSuccess)
       return hip_fail(e, "pic_step begin");
     prof_end(h, s);
     prof_begin(h, PIC_K_PUSH, s);

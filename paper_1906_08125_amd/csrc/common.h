@@ -119,6 +119,33 @@ struct DevMesh {
   double lam_c;              // bound factor of the barycentric inside test
 };
 
+// Virtual workgroup: index and count within the grid of one instance.  A
+// single-instance launch uses (blockIdx.x, gridDim.x); a batched launch
+// maps its blocks onto the instances with a schedule table.
+struct VB {
+  int id, n;
+};
+
+// Schedule of a batched launch: instance i owns blocks [off[i], off[i+1]).
+// Offsets and counts are multiples of 8 so that a block's XCD (block index
+// mod 8) is its virtual index mod 8.
+constexpr int kMaxBatch = 64;
+struct BatchMap {
+  int32_t n_inst;
+  int32_t off[kMaxBatch + 1];
+};
+
+__device__ inline VB batch_block(const BatchMap& b, int& inst) {
+  const int g = (int)blockIdx.x;
+  int i = 0;
+  while (i + 1 < b.n_inst && b.off[i + 1] <= g) ++i;
+  inst = i;
+  VB v;
+  v.id = g - b.off[i];
+  v.n = b.off[i + 1] - b.off[i];
+  return v;
+}
+
 // ---------------------------------------------------------------------------
 // Error-free transformations and orientation predicates.
 // ---------------------------------------------------------------------------

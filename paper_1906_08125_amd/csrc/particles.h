@@ -32,6 +32,8 @@ struct StepArgs {
   uint64_t seed;
   uint64_t instance;
   int64_t step;
+  int g_push;           // workgroups of the push role (the rest inject)
+  int n_blocks;         // workgroups of the particle kernel (batched)
 };
 
 struct EmitArgs {
@@ -50,6 +52,8 @@ struct EmitArgs {
   pic_step_stats* stats;  // or null
   double* rate;           // or null
   double* face_F;         // or null
+  int64_t* clear;         // node charges cleared by k_begin, or null
+  int64_t n_clear;
 };
 
 struct LocateArgs {
@@ -70,8 +74,7 @@ struct DepositArgs {
   int64_t* charge;
 };
 
-hipError_t launch_begin(const EmitArgs& a, int64_t* charge, int64_t n_nodes,
-                        int grid, hipStream_t s);
+hipError_t launch_begin(const EmitArgs& a, int grid, hipStream_t s);
 hipError_t launch_particles(const StepArgs& a, int g_push, int g_inj,
                             hipStream_t s);
 hipError_t launch_stats(const int64_t* rows, int n_rows, pic_step_stats* st,
@@ -81,5 +84,16 @@ hipError_t launch_emit(const EmitArgs& a, hipStream_t s);
 hipError_t launch_fallback(const StepArgs& a, int grid, hipStream_t s);
 hipError_t launch_locate(const LocateArgs& a, int grid, hipStream_t s);
 hipError_t launch_deposit(const DepositArgs& a, int grid, hipStream_t s);
+
+// Batched launches over the instances of device arrays E[] / A[] with the
+// block schedules given (one schedule per kernel kind).
+hipError_t launch_begin_b(const EmitArgs* E, const BatchMap& map, int grid,
+                          hipStream_t s);
+hipError_t launch_particles_b(const StepArgs* A, const BatchMap& map, int grid,
+                              int f32, hipStream_t s);
+hipError_t launch_fallback_b(const StepArgs* A, const BatchMap& map, int grid,
+                             hipStream_t s);
+hipError_t launch_stats_b(const StepArgs* A, const BatchMap& map, int grid,
+                          hipStream_t s);
 
 }  // namespace fp

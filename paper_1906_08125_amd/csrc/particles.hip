@@ -546,10 +546,8 @@ __global__ void __launch_bounds__(kBlock) k_emit(EmitArgs a) {
 
 // Start of a step: workgroup 0 clears the step's stats and counters and
 // computes the emission counts; the others clear the node charges.
-__global__ void __launch_bounds__(kBeginBlock) k_begin(EmitArgs a,
-                                                       int64_t* charge,
-                                                       int64_t n_nodes) {
-  if (blockIdx.x == 0) {  // dispatched first: the emission path is the longest
+__device__ inline void begin_body(const EmitArgs& a, VB vb) {
+  if (vb.id == 0) {  // dispatched first: the emission path is the longest
     int64_t* s64 = reinterpret_cast<int64_t*>(a.stats);
     const int ns = (int)(sizeof(pic_step_stats) / sizeof(int64_t));
     if (threadIdx.x < ns) s64[threadIdx.x] = 0;
@@ -560,10 +558,21 @@ __global__ void __launch_bounds__(kBeginBlock) k_begin(EmitArgs a,
     emit_block<kBeginBlock>(a);
     return;
   }
-  const int64_t G = gridDim.x - 1;
-  for (int64_t i = (blockIdx.x - 1) * (int64_t)blockDim.x + threadIdx.x;
-       i < n_nodes; i += G * blockDim.x)
-    charge[i] = 0;
+  const int64_t G = vb.n - 1;
+  for (int64_t i = (vb.id - 1) * (int64_t)blockDim.x + threadIdx.x;
+       i < a.n_clear; i += G * blockDim.x)
+    a.clear[i] = 0;
+}
+
+__global__ void __launch_bounds__(kBeginBlock) k_begin(EmitArgs a) {
+  begin_body(a, VB{(int)blockIdx.x, (int)gridDim.x});
+}
+
+__global__ void __launch_bounds__(kBeginBlock) k_begin_b(const EmitArgs* E,
+                                                         BatchMap map) {
+  int i;
+  const VB vb = batch_block(map, i);
+  begin_body(E[i], vb);
 }
 
 // ---------------------------------------------------------------------------
@@ -776,35 +785,49 @@ __device__ inline void inject_role(const StepArgs& a, int g, int G, Acc& acc,
 
 // One instance per storage precision, so that only one push is compiled in.
 template <bool F32>
-__global__ void __launch_bounds__(kBlock) k_particles(StepArgs a, int g_push) {
+__device__ inline void particles_body(const StepArgs& a, VB vb) {
   Acc acc;
   acc_zero(acc);
   __shared__ ChargeTable T;
   table_clear(T);
-  if ((int)blockIdx.x < g_push) {
+  const int g_push = a.g_push;
+  if (vb.id < g_push) {
     if (F32)
-      push_role32(a, blockIdx.x, g_push, acc, T);
+      push_role32(a, vb.id, g_push, acc, T);
     else
-      push_role64(a, blockIdx.x, g_push, acc, T);
+      push_role64(a, vb.id, g_push, acc, T);
   } else
-    inject_role(a, blockIdx.x - g_push, gridDim.x - g_push, acc, T);
+    inject_role(a, vb.id - g_push, vb.n - g_push, acc, T);
   table_flush(T, a.charge);
-  acc_flush(acc, a.acc_rows, a.acc_row0 + blockIdx.x, a.acc_stride);
+  acc_flush(acc, a.acc_rows, a.acc_row0 + vb.id, a.acc_stride);
+}
+
+template <bool F32>
+__global__ void __launch_bounds__(kBlock) k_particles(StepArgs a) {
+  particles_body<F32>(a, VB{(int)blockIdx.x, (int)gridDim.x});
+}
+
+template <bool F32>
+__global__ void __launch_bounds__(kBlock) k_particles_b(const StepArgs* A,
+                                                        BatchMap map) {
+  int i;
+  const VB vb = batch_block(map, i);
+  particles_body<F32>(A[i], vb);
 }
 
 // ---------------------------------------------------------------------------
 // Particles the walk could not certify: exact canonical location; those
 // outside every tet (below the top plane) are absorbed by the cathode.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlock) k_fallback(StepArgs a) {
+__device__ inline void fallback_body(const StepArgs& a, VB vb) {
   const DevMesh& m = a.m;
   const int64_t n = a.scratch->n_fallback;
   Acc acc;
   acc_zero(acc);
   // one wave per queued particle
-  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  const int64_t waves = (int64_t)vb.n * (blockDim.x >> 6);
   const bool lead = (threadIdx.x & 63) == 0;
-  for (int64_t j = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
+  for (int64_t j = vb.id * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
        j < n; j += waves) {
     const int64_t i = a.queue[j];
     double x, y, z;
@@ -832,17 +855,26 @@ __global__ void __launch_bounds__(kBlock) k_fallback(StepArgs a) {
       acc.q_cathode += qfx;
     }
   }
-  acc_flush(acc, a.acc_rows, a.acc_row0 + blockIdx.x, a.acc_stride);
-  if (blockIdx.x == 0 && threadIdx.x == 0) a.stats->n_fallback = n;
+  acc_flush(acc, a.acc_rows, a.acc_row0 + vb.id, a.acc_stride);
+  if (vb.id == 0 && threadIdx.x == 0) a.stats->n_fallback = n;
+}
+
+__global__ void __launch_bounds__(kBlock) k_fallback(StepArgs a) {
+  fallback_body(a, VB{(int)blockIdx.x, (int)gridDim.x});
+}
+
+__global__ void __launch_bounds__(kBlock) k_fallback_b(const StepArgs* A,
+                                                       BatchMap map) {
+  int i;
+  const VB vb = batch_block(map, i);
+  fallback_body(A[i], vb);
 }
 
 // Sum of the counter rows of one step into its stats: one workgroup per
 // counter, a fixed-order tree inside the workgroup.
-__global__ void __launch_bounds__(kBlock) k_stats(const int64_t* rows,
-                                                  int n_rows,
-                                                  pic_step_stats* st) {
+__device__ inline void stats_body(const int64_t* rows, int n_rows,
+                                  pic_step_stats* st, int k) {
   __shared__ long long lds[kBlock / 64];
-  const int k = blockIdx.x;
   const bool is_max = k == kAccFields - 1;
   long long s = 0;
   for (int r = threadIdx.x; r < n_rows; r += blockDim.x) {
@@ -863,6 +895,22 @@ __global__ void __launch_bounds__(kBlock) k_stats(const int64_t* rows,
                                 &st->q_inj,    &st->walk_steps, &st->walk_max};
     *dst[k] = t;
   }
+}
+
+__global__ void __launch_bounds__(kBlock) k_stats(const int64_t* rows,
+                                                  int n_rows,
+                                                  pic_step_stats* st) {
+  stats_body(rows, n_rows, st, (int)blockIdx.x);
+}
+
+// Batched: kAccFields workgroups per instance (schedule of 16 per instance).
+__global__ void __launch_bounds__(kBlock) k_stats_b(const StepArgs* A,
+                                                    BatchMap map) {
+  int i;
+  const VB vb = batch_block(map, i);
+  if (vb.id >= kAccFields) return;
+  const StepArgs& a = A[i];
+  stats_body(a.acc_rows, a.acc_stride, a.stats, vb.id);
 }
 
 // ---------------------------------------------------------------------------
@@ -943,20 +991,43 @@ __global__ void __launch_bounds__(kBlock) k_seed_build(DevMesh m) {
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_begin(const EmitArgs& a, int64_t* charge, int64_t n_nodes,
-                        int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_begin, dim3(grid + 1), dim3(kBeginBlock), 0, s, a, charge,
-                     n_nodes);
+hipError_t launch_begin(const EmitArgs& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_begin, dim3(grid + 1), dim3(kBeginBlock), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_begin_b(const EmitArgs* E, const BatchMap& map, int grid,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_begin_b, dim3(grid), dim3(kBeginBlock), 0, s, E, map);
+  return hipGetLastError();
+}
+hipError_t launch_particles_b(const StepArgs* A, const BatchMap& map, int grid,
+                              int f32, hipStream_t s) {
+  if (f32)
+    hipLaunchKernelGGL(k_particles_b<true>, dim3(grid), dim3(kBlock), 0, s, A, map);
+  else
+    hipLaunchKernelGGL(k_particles_b<false>, dim3(grid), dim3(kBlock), 0, s, A, map);
+  return hipGetLastError();
+}
+hipError_t launch_fallback_b(const StepArgs* A, const BatchMap& map, int grid,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_fallback_b, dim3(grid), dim3(kBlock), 0, s, A, map);
+  return hipGetLastError();
+}
+hipError_t launch_stats_b(const StepArgs* A, const BatchMap& map, int grid,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_stats_b, dim3(grid), dim3(kBlock), 0, s, A, map);
   return hipGetLastError();
 }
 hipError_t launch_particles(const StepArgs& a, int g_push, int g_inj,
                             hipStream_t s) {
+  StepArgs b = a;
+  b.g_push = g_push;
   if (a.f32)
     hipLaunchKernelGGL(k_particles<true>, dim3(g_push + g_inj), dim3(kBlock), 0,
-                       s, a, g_push);
+                       s, b);
   else
     hipLaunchKernelGGL(k_particles<false>, dim3(g_push + g_inj), dim3(kBlock),
-                       0, s, a, g_push);
+                       0, s, b);
   return hipGetLastError();
 }
 hipError_t launch_seed_build(const DevMesh& m, int grid, hipStream_t s) {

@@ -17,6 +17,10 @@ struct CgCtrl {
   double relres;        // last true relative residual
   double rstart;        // ||r|| at the last (re)start (mixed inner target)
   double alpha[2], gamma[2];
+  // iteration counters of batched launches (the host does not track each
+  // instance): it_a is read by upd and written by spmv, it_b the reverse,
+  // so no kernel reads a counter that the same launch writes
+  int32_t it_a, it_b;
 };
 
 // Host-visible report of the control word (pinned, device-mapped memory).
@@ -70,5 +74,18 @@ hipError_t cg_launch_begin(const CgArgs& a, int64_t seq, hipStream_t s);
 hipError_t cg_launch_iters(const CgArgs& a, int it0, int n, int64_t seq,
                            hipStream_t s);
 hipError_t cg_launch_recheck(const CgArgs& a, int64_t seq, hipStream_t s);
+
+// Batched launches: one launch per solver kernel covers every instance of
+// args[] (device array) with the block schedule map; mask selects the
+// instances a re-check applies to.  Reports are written by cg_batch_report.
+struct CgBatch {
+  const CgArgs* args;
+  BatchMap map;
+  uint64_t mask;
+};
+hipError_t cg_batch_begin(const CgBatch& b, int grid, hipStream_t s);
+hipError_t cg_batch_iters(const CgBatch& b, int grid, int n, hipStream_t s);
+hipError_t cg_batch_recheck(const CgBatch& b, int grid, hipStream_t s);
+hipError_t cg_batch_report(const CgBatch& b, int64_t seq, hipStream_t s);
 
 }  // namespace fp

@@ -42,9 +42,9 @@ struct Range {
   int64_t lo, hi;
 };
 
-__device__ inline Range my_range(int64_t n) {
-  const int G = gridDim.x;
-  const int g = blockIdx.x;
+__device__ inline Range my_range(int64_t n, VB vb) {
+  const int G = vb.n;
+  const int g = vb.id;
   int chunk = g;
   if ((G & 7) == 0) chunk = (g & 7) * (G >> 3) + (g >> 3);
   const int64_t per = (n + G - 1) / G;
@@ -94,11 +94,11 @@ __device__ inline void totals(const double* part, int P, int stride,
 
 template <int NQ>
 __device__ inline void write_partials(double* part, int stride,
-                                      double (&v)[NQ]) {
+                                      double (&v)[NQ], VB vb) {
   block_sum<NQ>(v);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) part[q * stride + blockIdx.x] = v[q];
+    for (int q = 0; q < NQ; ++q) part[q * stride + vb.id] = v[q];
   }
 }
 
@@ -109,8 +109,8 @@ __device__ inline void spmv_sell(const int32_t* __restrict__ sptr,
                                  const int32_t* __restrict__ scol,
                                  const T* __restrict__ sval,
                                  const T* __restrict__ x, int64_t nslices,
-                                 int64_t nrows, F&& emit) {
-  const Range sl = my_range(nslices);
+                                 int64_t nrows, VB vb, F&& emit) {
+  const Range sl = my_range(nslices, vb);
   const int lane = threadIdx.x & (kSell - 1);
   const int sub = threadIdx.x / kSell;
   const int nsub = blockDim.x / kSell;
@@ -143,6 +143,7 @@ __device__ inline void ctrl_reset(CgCtrl* c) {
   z.rstart = 0.0;
   z.alpha[0] = z.alpha[1] = 0.0;
   z.gamma[0] = z.gamma[1] = 0.0;
+  z.it_a = z.it_b = 0;
   *c = z;
 }
 
@@ -163,9 +164,9 @@ __device__ inline void report(const CgCtrl* c, CgReport* r, int64_t seq,
 // with R in FP32: the differences are of the size of E h, so rounding R
 // costs a relative error of about 2^-24 in E, while R_ij phi_j alone would
 // lose the ratio |phi| / (|E| h) to cancellation.
-__global__ void __launch_bounds__(512) k_cg_resfield(CgArgs a, int reset) {
+__device__ inline void k_cg_resfield_body(const CgArgs& a, int reset, VB vb) {
   const DevMesh& m = a.m;
-  if (reset && blockIdx.x == 0 && threadIdx.x == 0) ctrl_reset(a.ctrl);
+  if (reset && vb.id == 0 && threadIdx.x == 0) ctrl_reset(a.ctrl);
   const int lane = threadIdx.x & (kSell - 1);
   const int sub = threadIdx.x / kSell;
   const int nsub = blockDim.x / kSell;
@@ -174,7 +175,7 @@ __global__ void __launch_bounds__(512) k_cg_resfield(CgArgs a, int reset) {
   const int64_t np = m.k_np;
   double v[2] = {0.0, 0.0};
   {
-    const Range sl = my_range(m.k_nslices);
+    const Range sl = my_range(m.k_nslices, vb);
     for (int64_t s = sl.lo + sub; s < sl.hi; s += nsub) {
       const int64_t r = s * kSell + lane;
       const bool row = r < m.n_free;
@@ -237,13 +238,13 @@ __global__ void __launch_bounds__(512) k_cg_resfield(CgArgs a, int reset) {
   // Dirichlet rows: phi = 0 there (never read above: columns are free
   // nodes), E = R phi
   {
-    const Range dr = my_range(a.n_dir);
+    const Range dr = my_range(a.n_dir, vb);
     for (int64_t i = dr.lo + threadIdx.x; i < dr.hi; i += blockDim.x)
       a.phi[a.dir_nodes[i]] = 0.0;
   }
   if (withE) {
     const int64_t dnp = m.d_np;
-    const Range sl = my_range(m.d_nslices);
+    const Range sl = my_range(m.d_nslices, vb);
     for (int64_t s = sl.lo + sub; s < sl.hi; s += nsub) {
       const int64_t r = s * kSell + lane;
       const int32_t p0 = m.d_sptr[s], p1 = m.d_sptr[s + 1];
@@ -272,13 +273,13 @@ __global__ void __launch_bounds__(512) k_cg_resfield(CgArgs a, int reset) {
         reinterpret_cast<double4*>(a.E)[nd] = make_double4(ex, ey, ez, 0.0);
     }
   }
-  write_partials<2>(slot(a, 0), a.G, v);
+  write_partials<2>(slot(a, 0), a.G, v, vb);
 }
 
 // phi = x on the free nodes (before a re-check pass).
-__global__ void __launch_bounds__(512) k_cg_scatter(CgArgs a) {
+__device__ inline void k_cg_scatter_body(const CgArgs& a, VB vb) {
   const DevMesh& m = a.m;
-  const Range rows = my_range(m.n_free);
+  const Range rows = my_range(m.n_free, vb);
   for (int64_t i = rows.lo + threadIdx.x; i < rows.hi; i += blockDim.x)
     a.phi[m.free2node[i]] = a.x[i];
 }
@@ -289,7 +290,7 @@ __global__ void __launch_bounds__(512) k_cg_scatter(CgArgs a) {
 // bb, relres, rstart, restarts) are never read by other workgroups of this
 // launch; they read iters_final, which is stable here.  A zero right-hand
 // side gives phi = 0 and E = 0, written by every workgroup.
-__global__ void __launch_bounds__(512) k_cg_start(CgArgs a, int64_t seq) {
+__device__ inline void k_cg_start_body(const CgArgs& a, int64_t seq, VB vb) {
   CgCtrl* c = a.ctrl;
   double t[2];
   totals<2>(slot(a, 0), a.G, a.G, t);
@@ -299,7 +300,7 @@ __global__ void __launch_bounds__(512) k_cg_start(CgArgs a, int64_t seq) {
   const double bs = a.bref ? fmax(bn, *a.bref) : bn;
   const bool done = bn == 0.0 || rn <= a.tol * bs;
   const bool noconv = !done && done_iters >= a.max_iter;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (vb.id == 0 && threadIdx.x == 0) {
     c->bb = t[0];
     c->iters = done_iters;
     const double relres = bn > 0.0 ? rn / bn : 0.0;
@@ -307,6 +308,7 @@ __global__ void __launch_bounds__(512) k_cg_start(CgArgs a, int64_t seq) {
     c->rstart = rn;
     const int32_t state = done ? CG_DONE : (noconv ? CG_NOCONV : CG_ITER);
     c->state = state;
+    c->it_a = 0;
     if (!done && !noconv) c->restarts += 1;
     if (bn == 0.0) c->zero_rhs = 1;
     if (done || noconv) {
@@ -331,7 +333,7 @@ __global__ void __launch_bounds__(512) k_cg_start(CgArgs a, int64_t seq) {
   }
   if (bn == 0.0) {
     const DevMesh& m = a.m;
-    const Range nr = my_range(m.n_nodes);
+    const Range nr = my_range(m.n_nodes, vb);
     for (int64_t i = nr.lo + threadIdx.x; i < nr.hi; i += blockDim.x) {
       a.phi[i] = 0.0;
       if (a.E && a.e32)
@@ -344,7 +346,7 @@ __global__ void __launch_bounds__(512) k_cg_start(CgArgs a, int64_t seq) {
   const DevMesh& m = a.m;
   double v[2] = {0.0, 0.0};
   if (a.mixed) {
-    spmv_sell(m.k_sptr, m.k_scol, m.k_sval32, a.u32, m.k_nslices, m.n_free,
+    spmv_sell(m.k_sptr, m.k_scol, m.k_sval32, a.u32, m.k_nslices, m.n_free, vb,
               [&](int64_t i, float s) {
                 a.w32[i] = s;
                 const double ui = a.u32[i];
@@ -352,7 +354,7 @@ __global__ void __launch_bounds__(512) k_cg_start(CgArgs a, int64_t seq) {
                 v[1] += (double)s * ui;
               });
   } else {
-    spmv_sell(m.k_sptr, m.k_scol, m.k_sval, a.u, m.k_nslices, m.n_free,
+    spmv_sell(m.k_sptr, m.k_scol, m.k_sval, a.u, m.k_nslices, m.n_free, vb,
               [&](int64_t i, double s) {
                 a.w[i] = s;
                 const double ui = a.u[i];
@@ -360,14 +362,19 @@ __global__ void __launch_bounds__(512) k_cg_start(CgArgs a, int64_t seq) {
                 v[1] += s * ui;
               });
   }
-  write_partials<2>(slot(a, 2), a.G, v);
+  write_partials<2>(slot(a, 2), a.G, v, vb);
 }
 
 // Iteration it (0-based since the last (re)start): scalars from the
 // previous products, then the row-local updates.
-__global__ void __launch_bounds__(512) k_cg_upd(CgArgs a, int it) {
+// it < 0: take the iteration index from the control word (batched launch).
+__device__ inline void k_cg_upd_body(const CgArgs& a, int it, VB vb) {
   CgCtrl* c = a.ctrl;
   if (c->state != CG_ITER) return;
+  if (it < 0) {
+    it = c->it_a;
+    if (vb.id == 0 && threadIdx.x == 0) c->it_b = it;
+  }
   double alpha, beta, gamma;
   if (it == 0) {
     double t[2];
@@ -394,7 +401,7 @@ __global__ void __launch_bounds__(512) k_cg_upd(CgArgs a, int it) {
     double thr = a.tol * (a.bref ? fmax(bn, *a.bref) : bn);
     if (a.mixed) thr = fmax(thr, a.inner_tol * c->rstart);
     if (rn <= thr || c->iters + it >= a.max_iter) {
-      if (blockIdx.x == 0 && threadIdx.x == 0) {
+      if (vb.id == 0 && threadIdx.x == 0) {
         c->state = CG_RECHECK;
         c->iters_final = c->iters + it;
       }
@@ -406,12 +413,12 @@ __global__ void __launch_bounds__(512) k_cg_upd(CgArgs a, int it) {
     beta = gamma / g_prev;
     alpha = gamma / (t3[2] - beta * gamma / a_prev);
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (vb.id == 0 && threadIdx.x == 0) {
     c->gamma[it & 1] = gamma;
     c->alpha[it & 1] = alpha;
   }
   const DevMesh& m = a.m;
-  const Range rows = my_range(m.n_free);
+  const Range rows = my_range(m.n_free, vb);
   double v[2] = {0.0, 0.0};
   const bool first = it == 0;
   if (a.mixed) {
@@ -429,7 +436,7 @@ __global__ void __launch_bounds__(512) k_cg_upd(CgArgs a, int it) {
       v[0] += (double)ri * ri;
       v[1] += (double)ri * ui;
     }
-    write_partials<2>(slot(a, 4 + 2 * (it & 1)), a.G, v);
+    write_partials<2>(slot(a, 4 + 2 * (it & 1)), a.G, v, vb);
     return;
   }
   for (int64_t i = rows.lo + threadIdx.x; i < rows.hi; i += blockDim.x) {
@@ -445,30 +452,92 @@ __global__ void __launch_bounds__(512) k_cg_upd(CgArgs a, int it) {
     v[0] += ri * ri;
     v[1] += ri * ui;
   }
-  write_partials<2>(slot(a, 4 + 2 * (it & 1)), a.G, v);
+  write_partials<2>(slot(a, 4 + 2 * (it & 1)), a.G, v, vb);
 }
 
-__global__ void __launch_bounds__(512) k_cg_spmv(CgArgs a, int it,
-                                                int64_t seq) {
+__device__ inline void k_cg_spmv_body(const CgArgs& a, int it,
+                                                int64_t seq, VB vb) {
   const int32_t state = a.ctrl->state;
-  if (seq && blockIdx.x == 0 && threadIdx.x == 0) report(a.ctrl, a.report, seq, state);
+  if (seq && vb.id == 0 && threadIdx.x == 0) report(a.ctrl, a.report, seq, state);
   if (state != CG_ITER) return;
+  if (it < 0) {
+    it = a.ctrl->it_b;
+    if (vb.id == 0 && threadIdx.x == 0) a.ctrl->it_a = it + 1;
+  }
   const DevMesh& m = a.m;
   double v[1] = {0.0};
   if (a.mixed) {
-    spmv_sell(m.k_sptr, m.k_scol, m.k_sval32, a.u32, m.k_nslices, m.n_free,
+    spmv_sell(m.k_sptr, m.k_scol, m.k_sval32, a.u32, m.k_nslices, m.n_free, vb,
               [&](int64_t i, float s) {
                 a.w32[i] = s;
                 v[0] += (double)s * a.u32[i];
               });
   } else {
-    spmv_sell(m.k_sptr, m.k_scol, m.k_sval, a.u, m.k_nslices, m.n_free,
+    spmv_sell(m.k_sptr, m.k_scol, m.k_sval, a.u, m.k_nslices, m.n_free, vb,
               [&](int64_t i, double s) {
                 a.w[i] = s;
                 v[0] += s * a.u[i];
               });
   }
-  write_partials<1>(slot(a, 8 + (it & 1)), a.G, v);
+  write_partials<1>(slot(a, 8 + (it & 1)), a.G, v, vb);
+}
+
+// Single-instance kernels.
+__global__ void __launch_bounds__(kCgBlock) k_cg_resfield(CgArgs a, int reset) {
+  k_cg_resfield_body(a, reset, VB{(int)blockIdx.x, (int)gridDim.x});
+}
+__global__ void __launch_bounds__(kCgBlock) k_cg_scatter(CgArgs a) {
+  k_cg_scatter_body(a, VB{(int)blockIdx.x, (int)gridDim.x});
+}
+__global__ void __launch_bounds__(kCgBlock) k_cg_start(CgArgs a, int64_t seq) {
+  k_cg_start_body(a, seq, VB{(int)blockIdx.x, (int)gridDim.x});
+}
+__global__ void __launch_bounds__(kCgBlock) k_cg_upd(CgArgs a, int it) {
+  k_cg_upd_body(a, it, VB{(int)blockIdx.x, (int)gridDim.x});
+}
+__global__ void __launch_bounds__(kCgBlock) k_cg_spmv(CgArgs a, int it,
+                                                     int64_t seq) {
+  k_cg_spmv_body(a, it, seq, VB{(int)blockIdx.x, (int)gridDim.x});
+}
+
+// Batched kernels: block -> (instance, virtual block) by the schedule.
+// gated: skip the instances outside the mask (re-check launches).
+__global__ void __launch_bounds__(kCgBlock) k_cg_resfield_b(CgBatch b, int reset,
+                                                           int gated) {
+  int i;
+  const VB vb = batch_block(b.map, i);
+  if (gated && !((b.mask >> i) & 1ull)) return;
+  k_cg_resfield_body(b.args[i], reset, vb);
+}
+__global__ void __launch_bounds__(kCgBlock) k_cg_scatter_b(CgBatch b) {
+  int i;
+  const VB vb = batch_block(b.map, i);
+  if (!((b.mask >> i) & 1ull)) return;
+  k_cg_scatter_body(b.args[i], vb);
+}
+__global__ void __launch_bounds__(kCgBlock) k_cg_start_b(CgBatch b, int gated) {
+  int i;
+  const VB vb = batch_block(b.map, i);
+  if (gated && !((b.mask >> i) & 1ull)) return;
+  k_cg_start_body(b.args[i], 0, vb);
+}
+__global__ void __launch_bounds__(kCgBlock) k_cg_upd_b(CgBatch b) {
+  int i;
+  const VB vb = batch_block(b.map, i);
+  k_cg_upd_body(b.args[i], -1, vb);
+}
+__global__ void __launch_bounds__(kCgBlock) k_cg_spmv_b(CgBatch b) {
+  int i;
+  const VB vb = batch_block(b.map, i);
+  k_cg_spmv_body(b.args[i], -1, 0, vb);
+}
+// One thread per instance: report the control state with sequence seq.
+__global__ void k_cg_report_b(CgBatch b, int64_t seq) {
+  const int i = threadIdx.x;
+  if (i >= b.map.n_inst) return;
+  const CgArgs& a = b.args[i];
+  __threadfence_system();
+  report(a.ctrl, a.report, seq, a.ctrl->state);
 }
 
 #define LAUNCH(kern, ...)                                                   \
@@ -498,6 +567,39 @@ hipError_t cg_launch_recheck(const CgArgs& a, int64_t seq, hipStream_t s) {
   LAUNCH(k_cg_resfield, a, 0);
   LAUNCH(k_cg_start, a, seq);
   return hipSuccess;
+}
+
+#define BLAUNCH(kern, ...)                                                    \
+  do {                                                                        \
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kCgBlock), 0, s, __VA_ARGS__);  \
+    hipError_t e_ = hipGetLastError();                                        \
+    if (e_ != hipSuccess) return e_;                                          \
+  } while (0)
+
+hipError_t cg_batch_begin(const CgBatch& b, int grid, hipStream_t s) {
+  BLAUNCH(k_cg_resfield_b, b, 1, 0);
+  BLAUNCH(k_cg_start_b, b, 0);
+  return hipSuccess;
+}
+
+hipError_t cg_batch_iters(const CgBatch& b, int grid, int n, hipStream_t s) {
+  for (int k = 0; k < n; ++k) {
+    BLAUNCH(k_cg_upd_b, b);
+    BLAUNCH(k_cg_spmv_b, b);
+  }
+  return hipSuccess;
+}
+
+hipError_t cg_batch_recheck(const CgBatch& b, int grid, hipStream_t s) {
+  BLAUNCH(k_cg_scatter_b, b);
+  BLAUNCH(k_cg_resfield_b, b, 0, 1);
+  BLAUNCH(k_cg_start_b, b, 1);
+  return hipSuccess;
+}
+
+hipError_t cg_batch_report(const CgBatch& b, int64_t seq, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_report_b, dim3(1), dim3(kMaxBatch), 0, s, b, seq);
+  return hipGetLastError();
 }
 
 }  // namespace fp
