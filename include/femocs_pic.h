@@ -287,6 +287,49 @@ PIC_API pic_status adjoint_step(pic_mesh* mesh, const pic_particles* pre,
                         void* stream);
 
 /* ------------------------------------------------------------------------ */
+/* Batched stepping (an addition: many independent instances of the cycle   */
+/* -- each its own mesh_create handle, particles, fields and parameters --  */
+/* advanced together).  Every kernel of a step is launched once for all     */
+/* instances, the blocks of a launch mapped onto the instances by a         */
+/* schedule: per-instance workgroup counts (each rounded up to a multiple    */
+/* of 8, so that a workgroup's XCD follows its index inside its instance).   */
+/* The solves of all instances iterate in the same launches; each stops at  */
+/* its own tolerance.  Results per instance are those of pic_step with the  */
+/* same parameters, up to the rounding order of the solver's reductions     */
+/* (which depends on cg_blocks).                                           */
+/* ------------------------------------------------------------------------ */
+#define PIC_MAX_BATCH 64
+
+typedef struct pic_batch pic_batch;
+
+typedef struct {
+  int32_t push_blocks[PIC_MAX_BATCH];   /* live-particle workgroups, 8..push max  */
+  int32_t inject_blocks[PIC_MAX_BATCH]; /* injection workgroups, 8..inject max    */
+  int32_t cg_blocks[PIC_MAX_BATCH];     /* solver workgroups, 8..cg max           */
+  int32_t clear_blocks[PIC_MAX_BATCH];  /* step-start workgroups (>= 8)           */
+  int32_t fallback_blocks;              /* per instance, 8..fallback max          */
+  int32_t pad;
+} pic_batch_schedule;
+
+/* meshes: host array [n] of handles, 1 <= n <= PIC_MAX_BATCH, each used by
+ * at most this batch while it steps.  limits (optional): the upper bounds
+ * of each instance's counts (push, inject, cg, fallback) as [4*n]. */
+PIC_API pic_status pic_batch_create(pic_mesh* const* meshes, int32_t n,
+                            pic_batch** out, int32_t* limits);
+PIC_API pic_status pic_batch_destroy(pic_batch* batch);
+
+/* n_steps steps of every instance i with particles[i], fields[i] and
+ * params[i] (all of one precision), under sched.  stats: device
+ * [n_steps * n] pic_step_stats, step-major (stats[k * n + i]).  Blocks the
+ * calling thread at the solves, like pic_step. */
+PIC_API pic_status pic_batch_step(pic_batch* batch,
+                          const pic_particles* particles,
+                          const pic_fields* fields,
+                          const pic_step_params* params,
+                          const pic_batch_schedule* sched, int32_t n_steps,
+                          pic_step_stats* stats, void* stream);
+
+/* ------------------------------------------------------------------------ */
 /* Kernel timing (measurement support, not part of the method).  While      */
 /* enabled, pic_step and poisson_solve bracket every kernel they launch     */
 /* with HIP events on the caller's stream; pic_profile_read synchronizes    */

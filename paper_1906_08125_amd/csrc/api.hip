@@ -12,6 +12,16 @@
 #include "solver.h"
 #include "sort.h"
 
+struct pic_batch {
+  std::vector<pic_mesh*> h;
+  void* d_args = nullptr;   // per-step argument arrays (device)
+  void* h_args = nullptr;   // their pinned staging copy
+  size_t args_bytes = 0;
+  hipEvent_t uploaded = nullptr;  // staging copy consumed
+  hipEvent_t reported = nullptr;  // liveness of the report waits
+  int64_t seq = 0;
+};
+
 namespace {
 
 thread_local std::string g_err;
@@ -204,6 +214,94 @@ pic_status check_solve(const pic_solve_params* p) {
       !(p->inner_tol >= 1e-7 && p->inner_tol <= 0.5))
     return fail(PIC_E_ARG, "solve params: inner_tol must be in [1e-7, 0.5]");
   return PIC_OK;
+}
+
+pic_status check_step(const pic_particles* P, const pic_fields* F,
+                      const pic_step_params* prm, int32_t n_steps,
+                      const char* who) {
+  const std::string w(who);
+  if (P->precision != PIC_FP64 && P->precision != PIC_MIXED)
+    return fail(PIC_E_ARG, w + ": unknown particle precision");
+  if (P->capacity <= 0 || P->capacity >= (1ll << 31))
+    return fail(PIC_E_ARG, w + ": capacity must be in [1, 2^31)");
+  if (!P->x || !P->y || !P->z || !P->vx || !P->vy || !P->vz || !P->w ||
+      !P->tet || !P->birth || !P->id || !P->n_slots)
+    return fail(PIC_E_ARG, w + ": null particle array");
+  if (!F->phi || !F->E || !F->charge)
+    return fail(PIC_E_ARG, w + ": null field array");
+  if (!finite_pos(prm->dt) || !std::isfinite(prm->E0) || !finite_pos(prm->w_sp) ||
+      !finite_pos(prm->phi_w) || !std::isfinite(prm->j_scale) || prm->j_scale < 0 ||
+      prm->step0 < 0 || prm->step0 + n_steps >= (1ll << 21) || prm->resort_every < 0)
+    return fail(PIC_E_ARG, w + ": invalid step parameters");
+  return check_solve(&prm->solve);
+}
+
+// The kernel arguments of one instance's step (the per-step fields -- step
+// index and stats record -- are set by the caller).
+struct StepSet {
+  fp::StepArgs a;
+  fp::EmitArgs ea;
+  fp::CgArgs ca;
+};
+
+StepSet step_set(pic_mesh* h, const pic_particles* P, const pic_fields* F,
+                 const pic_step_params* prm, int g_push, int g_inj, int g_fb) {
+  const bool f32 = P->precision == PIC_MIXED;
+  const fp::Phys ph = fp::phys_constants();
+  StepSet ss;
+  fp::StepArgs& a = ss.a;
+  std::memset(&a, 0, sizeof a);
+  a.m = h->dm;
+  a.x = P->x;
+  a.y = P->y;
+  a.z = P->z;
+  a.vx = P->vx;
+  a.vy = P->vy;
+  a.vz = P->vz;
+  a.f32 = f32;
+  a.w = P->w;
+  a.tet = P->tet;
+  a.birth = P->birth;
+  a.id = P->id;
+  a.n_slots = P->n_slots;
+  a.E = F->E;
+  a.charge = F->charge;
+  a.s_face = prm->s_face;
+  a.offsets = h->offsets;
+  a.queue = h->queue;
+  a.scratch = h->scratch;
+  a.dt = prm->dt;
+  a.qm_dt = ph.qm * prm->dt;
+  a.Q = (ph.qm * prm->dt) * 0.5;
+  a.seed = prm->seed;
+  a.instance = (uint64_t)prm->instance;
+  a.acc_rows = h->acc_rows;
+  a.acc_stride = g_push + g_inj + g_fb;
+  a.g_push = g_push;
+  a.n_blocks = g_push + g_inj;
+
+  fp::EmitArgs& ea = ss.ea;
+  std::memset(&ea, 0, sizeof ea);
+  ea.m = h->dm;
+  ea.E = F->E;
+  ea.f32 = f32;
+  ea.c = {ph.a_fn, ph.b_fn, ph.c_s, ph.j_unit};
+  ea.phi_w = prm->phi_w;
+  ea.j_scale = prm->j_scale;
+  ea.dt = prm->dt;
+  ea.w_sp = prm->w_sp;
+  ea.seed = prm->seed;
+  ea.instance = (uint64_t)prm->instance;
+  ea.capacity = P->capacity;
+  ea.counts = h->counts;
+  ea.offsets = h->offsets;
+  ea.n_slots = P->n_slots;
+  ea.scratch = h->scratch;
+  ea.clear = F->charge;
+  ea.n_clear = h->dm.n_nodes;
+
+  ss.ca = cg_args(h, F->charge, prm->w_sp, prm->E0, F->phi, F->E, f32, &prm->solve);
+  return ss;
 }
 
 // Kernel timing: an event before and after each launch while enabled.
@@ -412,82 +510,20 @@ pic_status pic_step(pic_mesh* h, const pic_particles* P, const pic_fields* F,
     return fail(PIC_E_ARG, "pic_step: null argument");
   if (n_steps < 0) return fail(PIC_E_ARG, "pic_step: n_steps < 0");
   if (n_steps == 0) return PIC_OK;
-  if (P->precision != PIC_FP64 && P->precision != PIC_MIXED)
-    return fail(PIC_E_ARG, "pic_step: unknown particle precision");
-  const bool f32 = P->precision == PIC_MIXED;
-  if (P->capacity <= 0 || P->capacity >= (1ll << 31))
-    return fail(PIC_E_ARG, "pic_step: capacity must be in [1, 2^31)");
-  if (!P->x || !P->y || !P->z || !P->vx || !P->vy || !P->vz || !P->w ||
-      !P->tet || !P->birth || !P->id || !P->n_slots)
-    return fail(PIC_E_ARG, "pic_step: null particle array");
-  if (!F->phi || !F->E || !F->charge)
-    return fail(PIC_E_ARG, "pic_step: null field array");
-  if (!finite_pos(prm->dt) || !std::isfinite(prm->E0) || !finite_pos(prm->w_sp) ||
-      !finite_pos(prm->phi_w) || !std::isfinite(prm->j_scale) || prm->j_scale < 0 ||
-      prm->step0 < 0 || prm->step0 + n_steps >= (1ll << 21) || prm->resort_every < 0)
-    return fail(PIC_E_ARG, "pic_step: invalid step parameters");
-  pic_status ps = check_solve(&prm->solve);
+  pic_status ps = check_step(P, F, prm, n_steps, "pic_step");
   if (ps != PIC_OK) return ps;
+  const bool f32 = P->precision == PIC_MIXED;
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = ensure_capacity(h, P->capacity, prm->resort_every > 0, f32 ? 4 : 8);
   if (e != hipSuccess) return hip_fail(e, "pic_step");
 
-  const fp::Phys ph = fp::phys_constants();
-  fp::StepArgs a;
-  std::memset(&a, 0, sizeof a);
-  a.m = h->dm;
-  a.x = P->x;
-  a.y = P->y;
-  a.z = P->z;
-  a.vx = P->vx;
-  a.vy = P->vy;
-  a.vz = P->vz;
-  a.f32 = f32;
-  a.w = P->w;
-  a.tet = P->tet;
-  a.birth = P->birth;
-  a.id = P->id;
-  a.n_slots = P->n_slots;
-  a.E = F->E;
-  a.charge = F->charge;
-  a.s_face = prm->s_face;
-  a.offsets = h->offsets;
-  a.queue = h->queue;
-  a.scratch = h->scratch;
-  a.dt = prm->dt;
-  a.qm_dt = ph.qm * prm->dt;
-  a.Q = (ph.qm * prm->dt) * 0.5;
-  a.seed = prm->seed;
-  a.instance = (uint64_t)prm->instance;
-
-  fp::EmitArgs ea;
-  std::memset(&ea, 0, sizeof ea);
-  ea.m = h->dm;
-  ea.E = F->E;
-  ea.f32 = f32;
-  ea.c = {ph.a_fn, ph.b_fn, ph.c_s, ph.j_unit};
-  ea.phi_w = prm->phi_w;
-  ea.j_scale = prm->j_scale;
-  ea.dt = prm->dt;
-  ea.w_sp = prm->w_sp;
-  ea.seed = prm->seed;
-  ea.instance = (uint64_t)prm->instance;
-  ea.capacity = P->capacity;
-  ea.counts = h->counts;
-  ea.offsets = h->offsets;
-  ea.n_slots = P->n_slots;
-  ea.scratch = h->scratch;
-  ea.clear = F->charge;
-  ea.n_clear = h->dm.n_nodes;
-
-  fp::CgArgs ca = cg_args(h, F->charge, prm->w_sp, prm->E0, F->phi, F->E, f32,
-                          &prm->solve);
-
+  StepSet ss = step_set(h, P, F, prm, h->grid_push, h->grid_inj, h->grid_fb);
+  fp::StepArgs& a = ss.a;
+  fp::EmitArgs& ea = ss.ea;
+  fp::CgArgs& ca = ss.ca;
   const int grid_push = h->grid_push;
   const int grid_inj = h->grid_inj;
   const int grid_fb = h->grid_fb;
-  a.acc_rows = h->acc_rows;
-  a.acc_stride = grid_push + grid_inj + grid_fb;
   for (int32_t k = 0; k < n_steps; ++k) {
     const int64_t step = prm->step0 + k;
     pic_step_stats* st = stats + k;
@@ -502,12 +538,10 @@ pic_status pic_step(pic_mesh* h, const pic_particles* P, const pic_fields* F,
       return hip_fail(e, "pic_step begin");
     prof_end(h, s);
     prof_begin(h, PIC_K_PUSH, s);
-    a.acc_row0 = 0;
     if ((e = fp::launch_particles(a, grid_push, grid_inj, s)) != hipSuccess)
       return hip_fail(e, "pic_step particles");
     prof_end(h, s);
     prof_begin(h, PIC_K_FALLBACK, s);
-    a.acc_row0 = grid_push + grid_inj;
     if ((e = fp::launch_fallback(a, grid_fb, s)) != hipSuccess) return hip_fail(e, "pic_step fallback");
     if ((e = fp::launch_stats(h->acc_rows, grid_push + grid_inj + grid_fb, st, s)) != hipSuccess)
       return hip_fail(e, "pic_step stats");
@@ -647,6 +681,236 @@ pic_status adjoint_step(pic_mesh* h, const pic_particles* pre,
   if ((e = run_solve(h, ca, 0, s, &iters)) != hipSuccess) return hip_fail(e, "adjoint_step solve");
   if ((e = fp::adj_launch_post_solve(a, s)) != hipSuccess) return hip_fail(e, "adjoint_step");
   prof_end(h, s);
+  return PIC_OK;
+}
+
+pic_status pic_batch_create(pic_mesh* const* meshes, int32_t n,
+                            pic_batch** out, int32_t* limits) {
+  if (!meshes || !out || n < 1 || n > PIC_MAX_BATCH)
+    return fail(PIC_E_ARG, "pic_batch_create: need 1..PIC_MAX_BATCH meshes");
+  *out = nullptr;
+  for (int i = 0; i < n; ++i) {
+    if (!meshes[i]) return fail(PIC_E_ARG, "pic_batch_create: null mesh");
+    for (int j = 0; j < i; ++j)
+      if (meshes[j] == meshes[i])
+        return fail(PIC_E_ARG, "pic_batch_create: a mesh appears twice");
+  }
+  pic_batch* b = new pic_batch();
+  b->h.assign(meshes, meshes + n);
+  hipError_t e = hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->reported, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    pic_batch_destroy(b);
+    return hip_fail(e, "pic_batch_create");
+  }
+  if (limits)
+    for (int i = 0; i < n; ++i) {
+      limits[4 * i + 0] = meshes[i]->grid_push;
+      limits[4 * i + 1] = meshes[i]->grid_inj;
+      limits[4 * i + 2] = meshes[i]->cg_grid;
+      limits[4 * i + 3] = meshes[i]->grid_fb;
+    }
+  *out = b;
+  return PIC_OK;
+}
+
+pic_status pic_batch_destroy(pic_batch* b) {
+  if (!b) return PIC_OK;
+  (void)hipDeviceSynchronize();
+  if (b->d_args) (void)hipFree(b->d_args);
+  if (b->h_args) (void)hipHostFree(b->h_args);
+  if (b->uploaded) (void)hipEventDestroy(b->uploaded);
+  if (b->reported) (void)hipEventDestroy(b->reported);
+  delete b;
+  return PIC_OK;
+}
+
+namespace {
+
+int round8(int x) { return (x + 7) & ~7; }
+
+fp::BatchMap batch_map(const std::vector<int>& counts) {
+  fp::BatchMap m;
+  std::memset(&m, 0, sizeof m);
+  m.n_inst = (int32_t)counts.size();
+  for (size_t i = 0; i < counts.size(); ++i) m.off[i + 1] = m.off[i] + counts[i];
+  return m;
+}
+
+// Wait until every instance's report carries seq.
+hipError_t batch_wait(pic_batch* b, int64_t seq) {
+  for (pic_mesh* h : b->h) {
+    for (long spin = 0;; ++spin) {
+      if (__atomic_load_n(&h->cg_report_host->seq, __ATOMIC_ACQUIRE) == seq) break;
+      if ((spin & 1023) == 1023) {
+        const hipError_t q = hipEventQuery(b->reported);
+        if (q == hipSuccess) {
+          if (__atomic_load_n(&h->cg_report_host->seq, __ATOMIC_ACQUIRE) == seq) break;
+          return hipErrorUnknown;
+        }
+        if (q != hipErrorNotReady) return q;
+      }
+    }
+  }
+  return hipSuccess;
+}
+
+int64_t batch_next_seq(pic_batch* b) {
+  int64_t s = b->seq;
+  for (pic_mesh* h : b->h) s = std::max(s, h->cg_seq);
+  b->seq = s + 1;
+  for (pic_mesh* h : b->h) h->cg_seq = b->seq;
+  return b->seq;
+}
+
+}  // namespace
+
+pic_status pic_batch_step(pic_batch* b, const pic_particles* P,
+                          const pic_fields* F, const pic_step_params* prm,
+                          const pic_batch_schedule* sc, int32_t n_steps,
+                          pic_step_stats* stats, void* stream) {
+  if (!b || !P || !F || !prm || !sc || !stats)
+    return fail(PIC_E_ARG, "pic_batch_step: null argument");
+  if (n_steps < 0) return fail(PIC_E_ARG, "pic_batch_step: n_steps < 0");
+  if (n_steps == 0) return PIC_OK;
+  const int n = (int)b->h.size();
+  const bool f32 = P[0].precision == PIC_MIXED;
+  std::vector<int> c_push(n), c_inj(n), c_cg(n), c_clear(n), c_fb(n), c_stats(n, 16);
+  const int fb = round8(std::max(sc->fallback_blocks, 8));
+  for (int i = 0; i < n; ++i) {
+    pic_mesh* h = b->h[i];
+    pic_status ps = check_step(&P[i], &F[i], &prm[i], n_steps, "pic_batch_step");
+    if (ps != PIC_OK) return ps;
+    if ((P[i].precision == PIC_MIXED) != f32)
+      return fail(PIC_E_ARG, "pic_batch_step: instances differ in precision");
+    c_push[i] = round8(std::max(sc->push_blocks[i], 8));
+    c_inj[i] = round8(std::max(sc->inject_blocks[i], 8));
+    c_cg[i] = round8(std::max(sc->cg_blocks[i], 8));
+    c_clear[i] = round8(std::max(sc->clear_blocks[i], 8));
+    c_fb[i] = fb;
+    if (c_push[i] > h->grid_push || c_inj[i] > h->grid_inj || c_cg[i] > h->cg_grid ||
+        fb > h->grid_fb)
+      return fail(PIC_E_ARG, "pic_batch_step: schedule beyond the instance's limits");
+  }
+  hipStream_t s = (hipStream_t)stream;
+  for (int i = 0; i < n; ++i) {
+    hipError_t e = ensure_capacity(b->h[i], P[i].capacity, prm[i].resort_every > 0,
+                                   f32 ? 4 : 8);
+    if (e != hipSuccess) return hip_fail(e, "pic_batch_step");
+  }
+  // per-step argument arrays: [k][i] StepArgs, EmitArgs, CgArgs
+  const size_t sa = sizeof(fp::StepArgs), se = sizeof(fp::EmitArgs), sg = sizeof(fp::CgArgs);
+  const size_t per = (size_t)n * (sa + se + sg);
+  const size_t need = per * (size_t)n_steps;
+  hipError_t e = hipEventSynchronize(b->uploaded);  // staging free again
+  if (e != hipSuccess) return hip_fail(e, "pic_batch_step");
+  if (need > b->args_bytes) {
+    if (b->d_args) (void)hipFree(b->d_args);
+    if (b->h_args) (void)hipHostFree(b->h_args);
+    b->d_args = b->h_args = nullptr;
+    b->args_bytes = 0;
+    if ((e = hipMalloc(&b->d_args, need)) != hipSuccess) return hip_fail(e, "pic_batch_step");
+    if ((e = hipHostMalloc(&b->h_args, need, hipHostMallocDefault)) != hipSuccess)
+      return hip_fail(e, "pic_batch_step");
+    b->args_bytes = need;
+  }
+  char* hb = (char*)b->h_args;
+  for (int i = 0; i < n; ++i) {
+    StepSet ss = step_set(b->h[i], &P[i], &F[i], &prm[i], c_push[i], c_inj[i], fb);
+    ss.ca.G = c_cg[i];
+    ss.ca.report = b->h[i]->cg_report_dev;
+    for (int32_t k = 0; k < n_steps; ++k) {
+      const int64_t step = prm[i].step0 + k;
+      pic_step_stats* st = stats + (size_t)k * n + i;
+      char* base = hb + per * k;
+      fp::StepArgs a = ss.a;
+      a.step = step;
+      a.stats = st;
+      fp::EmitArgs ea = ss.ea;
+      ea.step = step;
+      ea.stats = st;
+      fp::CgArgs ca = ss.ca;
+      ca.step_stats = st;
+      std::memcpy(base + sa * i, &a, sa);
+      std::memcpy(base + sa * n + se * i, &ea, se);
+      std::memcpy(base + (sa + se) * n + sg * i, &ca, sg);
+    }
+  }
+  if ((e = hipMemcpyAsync(b->d_args, b->h_args, need, hipMemcpyHostToDevice, s)) != hipSuccess)
+    return hip_fail(e, "pic_batch_step");
+  if ((e = hipEventRecord(b->uploaded, s)) != hipSuccess) return hip_fail(e, "pic_batch_step");
+  std::vector<int> c_part(n);
+  for (int i = 0; i < n; ++i) c_part[i] = c_push[i] + c_inj[i];
+  const fp::BatchMap m_clear = batch_map(c_clear), m_part = batch_map(c_part),
+                     m_fb = batch_map(c_fb), m_stats = batch_map(c_stats),
+                     m_cg = batch_map(c_cg);
+  const int g_clear = m_clear.off[n], g_part = m_part.off[n], g_fb = m_fb.off[n],
+            g_stats = m_stats.off[n], g_cg = m_cg.off[n];
+  pic_mesh* h0 = b->h[0];
+  for (int32_t k = 0; k < n_steps; ++k) {
+    char* base = (char*)b->d_args + per * k;
+    const fp::StepArgs* A = (const fp::StepArgs*)base;
+    const fp::EmitArgs* E = (const fp::EmitArgs*)(base + sa * n);
+    fp::CgBatch cb;
+    cb.args = (const fp::CgArgs*)(base + (sa + se) * n);
+    cb.map = m_cg;
+    cb.mask = 0;
+    prof_begin(h0, PIC_K_EMIT, s);
+    if ((e = fp::launch_begin_b(E, m_clear, g_clear, s)) != hipSuccess)
+      return hip_fail(e, "pic_batch_step begin");
+    prof_end(h0, s);
+    prof_begin(h0, PIC_K_PUSH, s);
+    if ((e = fp::launch_particles_b(A, m_part, g_part, f32 ? 1 : 0, s)) != hipSuccess)
+      return hip_fail(e, "pic_batch_step particles");
+    prof_end(h0, s);
+    prof_begin(h0, PIC_K_FALLBACK, s);
+    if ((e = fp::launch_fallback_b(A, m_fb, g_fb, s)) != hipSuccess ||
+        (e = fp::launch_stats_b(A, m_stats, g_stats, s)) != hipSuccess)
+      return hip_fail(e, "pic_batch_step fallback");
+    prof_end(h0, s);
+    // the solves of all instances, in shared launches
+    prof_begin(h0, PIC_K_SOLVE, s);
+    int64_t seq = batch_next_seq(b);
+    if ((e = fp::cg_batch_begin(cb, g_cg, s)) != hipSuccess ||
+        (e = fp::cg_batch_report(cb, seq, s)) != hipSuccess ||
+        (e = hipEventRecord(b->reported, s)) != hipSuccess ||
+        (e = batch_wait(b, seq)) != hipSuccess)
+      return hip_fail(e, "pic_batch_step solve");
+    int batch = 0;
+    for (int guard = 0; guard < (1 << 20); ++guard) {
+      uint64_t mask = 0;
+      bool iterating = false;
+      for (int i = 0; i < n; ++i) {
+        const int32_t st = b->h[i]->cg_report_host->state;
+        if (st == fp::CG_RECHECK) mask |= 1ull << i;
+        if (st == fp::CG_ITER) iterating = true;
+      }
+      if (!mask && !iterating) break;
+      seq = batch_next_seq(b);
+      cb.mask = mask;
+      if (mask && (e = fp::cg_batch_recheck(cb, g_cg, s)) != hipSuccess)
+        return hip_fail(e, "pic_batch_step solve");
+      batch = batch < 8 ? 8 : std::min(2 * batch, 256);
+      if (mask) batch = std::min(batch, 16);
+      if ((e = fp::cg_batch_iters(cb, g_cg, batch, s)) != hipSuccess ||
+          (e = fp::cg_batch_report(cb, seq, s)) != hipSuccess ||
+          (e = hipEventRecord(b->reported, s)) != hipSuccess ||
+          (e = batch_wait(b, seq)) != hipSuccess)
+        return hip_fail(e, "pic_batch_step solve");
+    }
+    prof_end(h0, s);
+    for (int i = 0; i < n; ++i) {
+      const int64_t step = prm[i].step0 + k;
+      if (prm[i].resort_every > 0 && (step + 1) % prm[i].resort_every == 0) {
+        prof_begin(h0, PIC_K_SORT, s);
+        fp::SortArgs sa2 = sort_args(b->h[i], &P[i], f32 ? 4 : 8);
+        sa2.stats = stats + (size_t)k * n + i;
+        if ((e = fp::sort_particles(sa2, P[i].capacity, b->h[i]->n_cu, s)) != hipSuccess)
+          return hip_fail(e, "pic_batch_step sort");
+        prof_end(h0, s);
+      }
+    }
+  }
   return PIC_OK;
 }
 

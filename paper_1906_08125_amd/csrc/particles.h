@@ -25,15 +25,15 @@ struct StepArgs {
   int32_t* queue;       // [capacity] fallback queue
   StepScratch* scratch;
   pic_step_stats* stats;
-  int64_t* acc_rows;    // [rows][kAccFields] per-block counters
-  int acc_row0;         // first row of this kernel
-  int acc_stride;       // rows of all kernels (field-major layout)
+  int64_t* acc_rows;    // [kAccFields][acc_stride] per-block counters
+  int acc_stride;       // rows of both kernels (field-major layout)
   double Q, dt, qm_dt;
   uint64_t seed;
   uint64_t instance;
   int64_t step;
   int g_push;           // workgroups of the push role (the rest inject)
-  int n_blocks;         // workgroups of the particle kernel (batched)
+  int n_blocks;         // workgroups of the particle kernel (the fallback
+                        // kernel's counter rows follow theirs)
 };
 
 struct EmitArgs {

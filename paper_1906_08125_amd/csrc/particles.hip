@@ -799,7 +799,7 @@ __device__ inline void particles_body(const StepArgs& a, VB vb) {
   } else
     inject_role(a, vb.id - g_push, vb.n - g_push, acc, T);
   table_flush(T, a.charge);
-  acc_flush(acc, a.acc_rows, a.acc_row0 + vb.id, a.acc_stride);
+  acc_flush(acc, a.acc_rows, vb.id, a.acc_stride);
 }
 
 template <bool F32>
@@ -855,7 +855,8 @@ __device__ inline void fallback_body(const StepArgs& a, VB vb) {
       acc.q_cathode += qfx;
     }
   }
-  acc_flush(acc, a.acc_rows, a.acc_row0 + vb.id, a.acc_stride);
+  // counter rows after those of the particle kernel
+  acc_flush(acc, a.acc_rows, a.n_blocks + vb.id, a.acc_stride);
   if (vb.id == 0 && threadIdx.x == 0) a.stats->n_fallback = n;
 }
 

@@ -85,11 +85,21 @@ class AdjointArgs(C.Structure):
 
 
 PIC_ADJ_STEP, PIC_ADJ_INITIAL = 0, 1
+PIC_MAX_BATCH = 64
+
+
+class BatchSchedule(C.Structure):
+    _fields_ = [("push_blocks", C.c_int32 * PIC_MAX_BATCH),
+                ("inject_blocks", C.c_int32 * PIC_MAX_BATCH),
+                ("cg_blocks", C.c_int32 * PIC_MAX_BATCH),
+                ("clear_blocks", C.c_int32 * PIC_MAX_BATCH),
+                ("fallback_blocks", C.c_int32), ("pad", C.c_int32)]
 
 _lib = None
 EXPORTS = ("mesh_create", "mesh_destroy", "mesh_query", "mesh_emit_faces",
            "locate", "deposit", "poisson_solve", "pic_step", "emission_rate",
-           "adjoint_step", "pic_profile", "pic_profile_read",
+           "adjoint_step", "pic_batch_create", "pic_batch_destroy",
+           "pic_batch_step", "pic_profile", "pic_profile_read",
            "pic_last_error")
 KERNEL_CLASSES = ("push", "emit", "inject", "fallback", "solve", "sort",
                   "clear", "adjoint")
@@ -121,6 +131,11 @@ def load_library(path: str = LIB_PATH):
     L.pic_step.argtypes = [vp, C.POINTER(Particles), C.POINTER(Fields),
                            C.POINTER(StepParams), i32, vp, vp]
     L.emission_rate.argtypes = [vp, vp, dbl, vp, vp, vp]
+    L.pic_batch_create.argtypes = [C.POINTER(vp), i32, C.POINTER(vp), vp]
+    L.pic_batch_destroy.argtypes = [vp]
+    L.pic_batch_step.argtypes = [vp, C.POINTER(Particles), C.POINTER(Fields),
+                                 C.POINTER(StepParams),
+                                 C.POINTER(BatchSchedule), i32, vp, vp]
     L.adjoint_step.argtypes = [vp, C.POINTER(Particles), C.POINTER(Particles),
                                C.POINTER(Fields), C.POINTER(Fields),
                                C.POINTER(StepParams), C.POINTER(AdjointArgs),
@@ -519,3 +534,115 @@ def _window_function():
 def window_objective(E0, s, window: Window, wQ=1.0, wE=1.0):
     """Differentiable J(E0, s) (torch.autograd) over `window`."""
     return _window_function().apply(E0, s, window, wQ, wE)
+
+
+
+# ---------------------------------------------------------------------------
+# Batched stepping of independent instances, with a schedule autotuner.
+# ---------------------------------------------------------------------------
+class Batch:
+    """Instances (Mesh, State, per-instance step keywords) advanced together
+    by pic_batch_step.  The schedule gives each instance a number of
+    workgroups per kernel from its size: live particles per push workgroup
+    (push_tile) and free rows per solver workgroup (cg_rows);
+    `autotune` picks these two from measured step times."""
+
+    def __init__(self, meshes, states, params):
+        torch = _torch()
+        L = load_library()
+        self.meshes, self.states, self.params = list(meshes), list(states), list(params)
+        n = len(self.meshes)
+        arr = (C.c_void_p * n)(*[m.handle for m in self.meshes])
+        lim = (C.c_int32 * (4 * n))()
+        h = C.c_void_p()
+        _check(L.pic_batch_create(arr, n, C.byref(h), lim))
+        self._h = h
+        self.limits = np.array(list(lim), dtype=np.int64).reshape(n, 4)
+        self.push_tile, self.cg_rows = 4096, 1024
+        self.inject_blocks, self.clear_blocks, self.fallback_blocks = 16, 16, 8
+        self.tuning = []
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            load_library().pic_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def schedule(self, push_tile=None, cg_rows=None) -> BatchSchedule:
+        pt = push_tile or self.push_tile
+        cr = cg_rows or self.cg_rows
+        sc = BatchSchedule()
+        r8 = lambda x: max(8, (int(x) + 7) // 8 * 8)
+        for i, (m, st) in enumerate(zip(self.meshes, self.states)):
+            live = int(st.n_slots.item())
+            lim = self.limits[i]
+            sc.push_blocks[i] = min(r8(-(-live // pt)), int(lim[0]) // 8 * 8)
+            sc.inject_blocks[i] = min(r8(self.inject_blocks), int(lim[1]) // 8 * 8)
+            sc.cg_blocks[i] = min(r8(-(-m.n_free // cr)), int(lim[2]) // 8 * 8)
+            sc.clear_blocks[i] = r8(self.clear_blocks)
+        sc.fallback_blocks = min(self.fallback_blocks, int(self.limits[:, 3].min()) // 8 * 8)
+        return sc
+
+    def step(self, step0, n_steps=1, sched=None, stats=None):
+        torch = _torch()
+        n = len(self.meshes)
+        if stats is None:
+            stats = torch.zeros(n_steps * n * STEP_STATS_BYTES // 8,
+                                dtype=torch.int64, device="cuda")
+        P = (Particles * n)(*[st._p for st in self.states])
+        F = (Fields * n)(*[st._f for st in self.states])
+        prms = []
+        for st, kw in zip(self.states, self.params):
+            sf = kw.get("s_face")
+            prms.append(StepParams(
+                kw["dt"], kw["E0"], kw["w_sp"], kw["phi_w"], kw.get("j_scale", 1.0),
+                kw["seed"], step0, kw.get("instance", 0),
+                None if sf is None else sf.data_ptr(), kw.get("resort_every", 0), 0,
+                SolveParams(kw.get("tol", 1e-10), st.inner_tol,
+                            kw.get("max_iter", 20000), st.solve_precision)))
+        S = (StepParams * n)(*prms)
+        sc = sched if sched is not None else self.schedule()
+        _check(load_library().pic_batch_step(self._h, P, F, S, C.byref(sc),
+                                             int(n_steps), _ptr(stats),
+                                             _stream(torch)))
+        return stats
+
+    @staticmethod
+    def decode(stats, n):
+        rows = State.decode_stats(stats)
+        return [rows[k * n:(k + 1) * n] for k in range(len(rows) // n)]
+
+    def autotune(self, step0, push_tiles=(1024, 2048, 4096, 8192),
+                 cg_rows=(512, 1024, 2048, 4096), steps=2):
+        """Times `steps` batched steps from a snapshot for every (push_tile,
+        cg_rows) pair, restores the snapshot and keeps the fastest pair."""
+        torch = _torch()
+        snaps = [_Checkpoint(st) for st in self.states]
+        best = None
+        self.tuning = []
+        for pt in push_tiles:
+            for cr in cg_rows:
+                for snap, st in zip(snaps, self.states):
+                    snap.restore(st)
+                sc = self.schedule(pt, cr)
+                self.step(step0, 1, sc)          # warm the schedule
+                for snap, st in zip(snaps, self.states):
+                    snap.restore(st)
+                torch.cuda.synchronize()
+                import time as _t
+                w0 = _t.perf_counter()
+                self.step(step0, steps, sc)
+                torch.cuda.synchronize()
+                ms = 1e3 * (_t.perf_counter() - w0) / steps
+                self.tuning.append((pt, cr, ms))
+                if best is None or ms < best[2]:
+                    best = (pt, cr, ms)
+        for snap, st in zip(snaps, self.states):
+            snap.restore(st)
+        self.push_tile, self.cg_rows = best[0], best[1]
+        return best
