@@ -184,6 +184,10 @@ def run_gpu(args):
                      for n, v in mk.items()},
             push_GBps=round(push_bytes(m_live, 4) / m_push_us / 1e3, 1))
         del ml
+    batch = None
+    if args.batch_instances > 0:
+        torch.cuda.empty_cache()
+        batch = run_batch_leg(args)
     adjoint = None
     if not args.no_adjoint:
         torch.cuda.empty_cache()
@@ -206,6 +210,7 @@ def run_gpu(args):
         kernels=kernels,
         mixed=mixed,
         adjoint=adjoint,
+        batch=batch,
         roofline=dict(kernel=dom, bound="hbm", achieved=round(achieved, 1),
                       peak=HBM_PEAK_GBS, unit="GB/s",
                       frac=round(achieved / HBM_PEAK_GBS, 4),
@@ -263,6 +268,88 @@ def run_adjoint_leg(gm, cfg, rate, args):
                 note="backward includes the recompute of every step")
 
 
+def run_batch_leg(args):
+    """Uneven tip instances (grid n x n x 2n, n in 32..64, tip and field
+    drawn per instance, 1e4..1e6 superparticles each) advanced together by
+    pic_batch_step in mixed precision with the autotuned schedule, against
+    the plain FP64 form: the same instances stepped one after another by
+    pic_step.  Both from the empty gap: W warm-up steps, then K timed."""
+    import torch
+
+    from paper_1906_08125_amd import pic, workloads as W
+
+    cfgs = W.batch_configs(args.batch_instances, seed=4)
+    t0 = time.time()
+    meshes, kws = [], []
+    for c in cfgs:
+        gm = pic.Mesh(c.mesh(), c.emit_zmin)
+        phi = torch.zeros(gm.n_nodes, dtype=torch.float64, device="cuda")
+        E = torch.zeros(4 * gm.n_nodes, dtype=torch.float64, device="cuda")
+        gm.poisson_solve(None, 0.0, c.E0, phi, E, tol=c.tol)
+        rate, _ = gm.emission_rate(E, c.phi_w)
+        w_sp = rate.item() * c.dt * c.transit_steps / c.n_target
+        meshes.append(gm)
+        kws.append(dict(dt=c.dt, E0=c.E0, w_sp=w_sp, phi_w=c.phi_w, seed=c.seed,
+                        instance=len(kws), tol=c.tol, resort_every=10))
+        del phi, E
+    log(f"batch: {len(cfgs)} instances, "
+        f"{sum(m.n_tets for m in meshes) / 1e6:.1f}M tets, "
+        f"setup {time.time() - t0:.1f}s")
+    warm, K = args.batch_warmup, args.batch_steps
+
+    def states(precision):
+        out = []
+        for c, m, kw in zip(cfgs, meshes, kws):
+            st = pic.State(m, int(2.5 * c.n_target) + 50_000, precision=precision)
+            st.init_field(c.E0, tol=c.tol)
+            out.append(st)
+        return out
+
+    # batched, mixed precision, autotuned
+    sts = states(pic.PIC_MIXED)
+    batch = pic.Batch(meshes, sts, kws)
+    batch.step(0, warm)
+    best = batch.autotune(warm)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    stats = batch.step(warm, K)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - w0
+    rows = pic.Batch.decode(stats, len(cfgs))
+    for r in rows:
+        for x in r:
+            if x["status"] != 0:
+                raise RuntimeError(f"batch step status {x['status']}")
+    pushes = sum(x["n_before"] + x["n_inj"] for r in rows for x in r)
+    batch.close()
+    del sts
+    torch.cuda.empty_cache()
+    # plain FP64, one instance after another
+    sts = states(pic.PIC_FP64)
+    t_seq = 0.0
+    for st, kw in zip(sts, kws):
+        st.step(step0=0, n_steps=warm, **kw)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        st.step(step0=warm, n_steps=K, **kw)
+        torch.cuda.synchronize()
+        t_seq += time.perf_counter() - w0
+    del sts
+    torch.cuda.empty_cache()
+    n = len(cfgs)
+    return dict(instances=n, tets=int(sum(m.n_tets for m in meshes)),
+                live_particles=int(sum(x["n_after"] for x in rows[-1])),
+                warmup=warm, steps=K, precision="mixed",
+                instance_steps_per_s=round(n * K / t_batch, 1),
+                pushes_per_s=round(pushes / t_batch, 1),
+                ms_per_batch_step=round(1e3 * t_batch / K, 4),
+                fp64_sequential_ms_per_step=round(1e3 * t_seq / K, 4),
+                speedup_vs_fp64_sequential=round(t_seq / t_batch, 4),
+                schedule=dict(push_tile=best[0], cg_rows=best[1]),
+                autotune=[dict(push_tile=a, cg_rows=b, ms=round(c, 4))
+                          for a, b, c in batch.tuning])
+
+
 def cpu_baseline(cfg, tip, n_particles, n_steps):
     """The FP64 oracle on the host: the same mesh, a seeded synthetic
     population of superparticles in the gap above the apex, n_steps steps."""
@@ -316,6 +403,10 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint window leg")
     ap.add_argument("--adjoint-steps", type=int, default=20)
+    ap.add_argument("--batch-instances", type=int, default=32,
+                    help="instances of the batched leg (0: skip it)")
+    ap.add_argument("--batch-warmup", type=int, default=30)
+    ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain 1 GiB device copy (the "
                          "reference kernel for HBM byte counters)")

@@ -729,11 +729,19 @@ namespace {
 
 int round8(int x) { return (x + 7) & ~7; }
 
-fp::BatchMap batch_map(const std::vector<int>& counts) {
+// Map over the instances with active[i] (all when active is empty).
+fp::BatchMap batch_map(const std::vector<int>& counts,
+                       const std::vector<char>& active = {}) {
   fp::BatchMap m;
   std::memset(&m, 0, sizeof m);
-  m.n_inst = (int32_t)counts.size();
-  for (size_t i = 0; i < counts.size(); ++i) m.off[i + 1] = m.off[i] + counts[i];
+  int j = 0;
+  for (size_t i = 0; i < counts.size(); ++i) {
+    if (!active.empty() && !active[i]) continue;
+    m.inst[j] = (int8_t)i;
+    m.off[j + 1] = m.off[j] + counts[i];
+    ++j;
+  }
+  m.n_seg = j;
   return m;
 }
 
@@ -846,6 +854,7 @@ pic_status pic_batch_step(pic_batch* b, const pic_particles* P,
                      m_cg = batch_map(c_cg);
   const int g_clear = m_clear.off[n], g_part = m_part.off[n], g_fb = m_fb.off[n],
             g_stats = m_stats.off[n], g_cg = m_cg.off[n];
+  (void)g_cg;
   pic_mesh* h0 = b->h[0];
   for (int32_t k = 0; k < n_steps; ++k) {
     char* base = (char*)b->d_args + per * k;
@@ -868,36 +877,83 @@ pic_status pic_batch_step(pic_batch* b, const pic_particles* P,
         (e = fp::launch_stats_b(A, m_stats, g_stats, s)) != hipSuccess)
       return hip_fail(e, "pic_batch_step fallback");
     prof_end(h0, s);
-    // the solves of all instances, in shared launches
+    // the solves of all instances, in shared launches: the first round
+    // speculates as many iterations as the previous step needed; later
+    // rounds launch only the instances still iterating
     prof_begin(h0, PIC_K_SOLVE, s);
     int64_t seq = batch_next_seq(b);
-    if ((e = fp::cg_batch_begin(cb, g_cg, s)) != hipSuccess ||
-        (e = fp::cg_batch_report(cb, seq, s)) != hipSuccess ||
+    // speculation: the instances that iterated in the previous step get as
+    // many iterations before the first wait
+    std::vector<char> spec_on(n, 0);
+    std::vector<int> spec_n(n, 0);
+    int spec = 0;
+    for (int i = 0; i < n; ++i)
+      if (b->h[i]->step_spec > 0) {
+        spec_on[i] = 1;
+        spec_n[i] = b->h[i]->step_spec;
+        spec = std::max(spec, b->h[i]->step_spec);
+      }
+    // host copies of this step's solver arguments (a round with a single
+    // active instance launches its own kernels: no batch indirection)
+    auto host_cg = [&](int i) -> const fp::CgArgs& {
+      return *(const fp::CgArgs*)(hb + per * k + (sa + se) * n + sg * i);
+    };
+    // counts: per instance (speculation) or one for all (count >= 0)
+    auto iterate = [&](const std::vector<char>& act, uint64_t mask, int count,
+                       const std::vector<int>* counts) {
+      int cnt = 0;
+      for (int i = 0; i < n; ++i) cnt += act[i] ? 1 : 0;
+      if (cnt == 0) return hipSuccess;
+      hipError_t r;
+      if (cnt <= 2) {  // few instances: their own launches, full grids
+        for (int i = 0; i < n; ++i) {
+          if (!act[i]) continue;
+          const fp::CgArgs& ai = host_cg(i);
+          if ((mask >> i) & 1ull)
+            if ((r = fp::cg_launch_recheck(ai, 0, s)) != hipSuccess) return r;
+          const int c = counts ? (*counts)[i] : count;
+          if ((r = fp::cg_launch_iters_dev(ai, c, s)) != hipSuccess) return r;
+        }
+        return hipSuccess;
+      }
+      if (counts)
+        for (int i = 0; i < n; ++i)
+          if (act[i]) count = std::max(count, (*counts)[i]);
+      fp::CgBatch ca = cb;
+      ca.map = batch_map(c_cg, act);
+      ca.mask = mask;
+      const int grid = ca.map.off[ca.map.n_seg];
+      if (mask && (r = fp::cg_batch_recheck(ca, grid, s)) != hipSuccess) return r;
+      return fp::cg_batch_iters(ca, grid, count, s);
+    };
+    if ((e = fp::cg_batch_begin(cb, m_cg.off[m_cg.n_seg], s)) != hipSuccess ||
+        (spec > 0 && (e = iterate(spec_on, 0, 0, &spec_n)) != hipSuccess) ||
+        (e = fp::cg_batch_report(cb, n, seq, s)) != hipSuccess ||
         (e = hipEventRecord(b->reported, s)) != hipSuccess ||
         (e = batch_wait(b, seq)) != hipSuccess)
       return hip_fail(e, "pic_batch_step solve");
-    int batch = 0;
+    int batch = spec;
     for (int guard = 0; guard < (1 << 20); ++guard) {
       uint64_t mask = 0;
-      bool iterating = false;
+      std::vector<char> active(n, 0);
+      bool any = false;
       for (int i = 0; i < n; ++i) {
         const int32_t st = b->h[i]->cg_report_host->state;
         if (st == fp::CG_RECHECK) mask |= 1ull << i;
-        if (st == fp::CG_ITER) iterating = true;
+        if (st == fp::CG_RECHECK || st == fp::CG_ITER) active[i] = any = true;
       }
-      if (!mask && !iterating) break;
+      if (!any) break;
       seq = batch_next_seq(b);
-      cb.mask = mask;
-      if (mask && (e = fp::cg_batch_recheck(cb, g_cg, s)) != hipSuccess)
-        return hip_fail(e, "pic_batch_step solve");
       batch = batch < 8 ? 8 : std::min(2 * batch, 256);
       if (mask) batch = std::min(batch, 16);
-      if ((e = fp::cg_batch_iters(cb, g_cg, batch, s)) != hipSuccess ||
-          (e = fp::cg_batch_report(cb, seq, s)) != hipSuccess ||
+      if ((e = iterate(active, mask, batch, nullptr)) != hipSuccess ||
+          (e = fp::cg_batch_report(cb, n, seq, s)) != hipSuccess ||
           (e = hipEventRecord(b->reported, s)) != hipSuccess ||
           (e = batch_wait(b, seq)) != hipSuccess)
         return hip_fail(e, "pic_batch_step solve");
     }
+    for (int i = 0; i < n; ++i)
+      b->h[i]->step_spec = (int)std::min<int64_t>(b->h[i]->cg_report_host->iters, 256);
     prof_end(h0, s);
     for (int i = 0; i < n; ++i) {
       const int64_t step = prm[i].step0 + k;

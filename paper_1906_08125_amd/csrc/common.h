@@ -126,23 +126,24 @@ struct VB {
   int id, n;
 };
 
-// Schedule of a batched launch: instance i owns blocks [off[i], off[i+1]).
-// Offsets and counts are multiples of 8 so that a block's XCD (block index
-// mod 8) is its virtual index mod 8.
+// Schedule of a batched launch: segment j (instance inst[j]) owns blocks
+// [off[j], off[j+1]).  Offsets and counts are multiples of 8 so that a
+// block's XCD (block index mod 8) is its virtual index mod 8.
 constexpr int kMaxBatch = 64;
 struct BatchMap {
-  int32_t n_inst;
+  int32_t n_seg;
   int32_t off[kMaxBatch + 1];
+  int8_t inst[kMaxBatch];
 };
 
 __device__ inline VB batch_block(const BatchMap& b, int& inst) {
   const int g = (int)blockIdx.x;
-  int i = 0;
-  while (i + 1 < b.n_inst && b.off[i + 1] <= g) ++i;
-  inst = i;
+  int j = 0;
+  while (j + 1 < b.n_seg && b.off[j + 1] <= g) ++j;
+  inst = b.inst[j];
   VB v;
-  v.id = g - b.off[i];
-  v.n = b.off[i + 1] - b.off[i];
+  v.id = g - b.off[j];
+  v.n = b.off[j + 1] - b.off[j];
   return v;
 }
 

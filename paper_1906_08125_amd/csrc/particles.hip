@@ -572,7 +572,8 @@ __global__ void __launch_bounds__(kBeginBlock) k_begin_b(const EmitArgs* E,
                                                          BatchMap map) {
   int i;
   const VB vb = batch_block(map, i);
-  begin_body(E[i], vb);
+  const EmitArgs a = E[i];  // a private copy: no aliasing with the stores
+  begin_body(a, vb);
 }
 
 // ---------------------------------------------------------------------------
@@ -812,7 +813,8 @@ __global__ void __launch_bounds__(kBlock) k_particles_b(const StepArgs* A,
                                                         BatchMap map) {
   int i;
   const VB vb = batch_block(map, i);
-  particles_body<F32>(A[i], vb);
+  const StepArgs a = A[i];  // a private copy: no aliasing with the stores
+  particles_body<F32>(a, vb);
 }
 
 // ---------------------------------------------------------------------------
@@ -868,7 +870,8 @@ __global__ void __launch_bounds__(kBlock) k_fallback_b(const StepArgs* A,
                                                        BatchMap map) {
   int i;
   const VB vb = batch_block(map, i);
-  fallback_body(A[i], vb);
+  const StepArgs a = A[i];
+  fallback_body(a, vb);
 }
 
 // Sum of the counter rows of one step into its stats: one workgroup per

@@ -74,6 +74,8 @@ hipError_t cg_launch_begin(const CgArgs& a, int64_t seq, hipStream_t s);
 hipError_t cg_launch_iters(const CgArgs& a, int it0, int n, int64_t seq,
                            hipStream_t s);
 hipError_t cg_launch_recheck(const CgArgs& a, int64_t seq, hipStream_t s);
+// n iterations numbered by the device counters (no report)
+hipError_t cg_launch_iters_dev(const CgArgs& a, int n, hipStream_t s);
 
 // Batched launches: one launch per solver kernel covers every instance of
 // args[] (device array) with the block schedule map; mask selects the
@@ -86,6 +88,7 @@ struct CgBatch {
 hipError_t cg_batch_begin(const CgBatch& b, int grid, hipStream_t s);
 hipError_t cg_batch_iters(const CgBatch& b, int grid, int n, hipStream_t s);
 hipError_t cg_batch_recheck(const CgBatch& b, int grid, hipStream_t s);
-hipError_t cg_batch_report(const CgBatch& b, int64_t seq, hipStream_t s);
+// reports instances 0 .. n - 1 (all of the batch, whatever the map)
+hipError_t cg_batch_report(const CgBatch& b, int n, int64_t seq, hipStream_t s);
 
 }  // namespace fp

@@ -507,34 +507,39 @@ __global__ void __launch_bounds__(kCgBlock) k_cg_resfield_b(CgBatch b, int reset
   int i;
   const VB vb = batch_block(b.map, i);
   if (gated && !((b.mask >> i) & 1ull)) return;
-  k_cg_resfield_body(b.args[i], reset, vb);
+  const CgArgs a = b.args[i];  // a private copy: no aliasing with the stores
+  k_cg_resfield_body(a, reset, vb);
 }
 __global__ void __launch_bounds__(kCgBlock) k_cg_scatter_b(CgBatch b) {
   int i;
   const VB vb = batch_block(b.map, i);
   if (!((b.mask >> i) & 1ull)) return;
-  k_cg_scatter_body(b.args[i], vb);
+  const CgArgs a = b.args[i];
+  k_cg_scatter_body(a, vb);
 }
 __global__ void __launch_bounds__(kCgBlock) k_cg_start_b(CgBatch b, int gated) {
   int i;
   const VB vb = batch_block(b.map, i);
   if (gated && !((b.mask >> i) & 1ull)) return;
-  k_cg_start_body(b.args[i], 0, vb);
+  const CgArgs a = b.args[i];
+  k_cg_start_body(a, 0, vb);
 }
 __global__ void __launch_bounds__(kCgBlock) k_cg_upd_b(CgBatch b) {
   int i;
   const VB vb = batch_block(b.map, i);
-  k_cg_upd_body(b.args[i], -1, vb);
+  const CgArgs a = b.args[i];
+  k_cg_upd_body(a, -1, vb);
 }
 __global__ void __launch_bounds__(kCgBlock) k_cg_spmv_b(CgBatch b) {
   int i;
   const VB vb = batch_block(b.map, i);
-  k_cg_spmv_body(b.args[i], -1, 0, vb);
+  const CgArgs a = b.args[i];
+  k_cg_spmv_body(a, -1, 0, vb);
 }
 // One thread per instance: report the control state with sequence seq.
-__global__ void k_cg_report_b(CgBatch b, int64_t seq) {
+__global__ void k_cg_report_b(CgBatch b, int n, int64_t seq) {
   const int i = threadIdx.x;
-  if (i >= b.map.n_inst) return;
+  if (i >= n) return;
   const CgArgs& a = b.args[i];
   __threadfence_system();
   report(a.ctrl, a.report, seq, a.ctrl->state);
@@ -558,6 +563,14 @@ hipError_t cg_launch_iters(const CgArgs& a, int it0, int n, int64_t seq,
   for (int k = 0; k < n; ++k) {
     LAUNCH(k_cg_upd, a, it0 + k);
     LAUNCH(k_cg_spmv, a, it0 + k, k == n - 1 ? seq : (int64_t)0);
+  }
+  return hipSuccess;
+}
+
+hipError_t cg_launch_iters_dev(const CgArgs& a, int n, hipStream_t s) {
+  for (int k = 0; k < n; ++k) {
+    LAUNCH(k_cg_upd, a, -1);
+    LAUNCH(k_cg_spmv, a, -1, (int64_t)0);
   }
   return hipSuccess;
 }
@@ -597,8 +610,8 @@ hipError_t cg_batch_recheck(const CgBatch& b, int grid, hipStream_t s) {
   return hipSuccess;
 }
 
-hipError_t cg_batch_report(const CgBatch& b, int64_t seq, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_report_b, dim3(1), dim3(kMaxBatch), 0, s, b, seq);
+hipError_t cg_batch_report(const CgBatch& b, int n, int64_t seq, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_report_b, dim3(1), dim3(kMaxBatch), 0, s, b, n, seq);
   return hipGetLastError();
 }
 

@@ -561,6 +561,7 @@ class Batch:
         self.push_tile, self.cg_rows = 4096, 1024
         self.inject_blocks, self.clear_blocks, self.fallback_blocks = 16, 16, 8
         self.tuning = []
+        self.last_iters = [0] * n
 
     def close(self):
         if getattr(self, "_h", None) is not None:
@@ -583,7 +584,11 @@ class Batch:
             lim = self.limits[i]
             sc.push_blocks[i] = min(r8(-(-live // pt)), int(lim[0]) // 8 * 8)
             sc.inject_blocks[i] = min(r8(self.inject_blocks), int(lim[1]) // 8 * 8)
-            sc.cg_blocks[i] = min(r8(-(-m.n_free // cr)), int(lim[2]) // 8 * 8)
+            # an instance whose solve iterated gets the full solver grid,
+            # the others (one residual pass per step) a grid by cg_rows
+            full = int(lim[2]) // 8 * 8
+            sc.cg_blocks[i] = full if self.last_iters[i] > 0 else min(
+                r8(-(-m.n_free // cr)), full)
             sc.clear_blocks[i] = r8(self.clear_blocks)
         sc.fallback_blocks = min(self.fallback_blocks, int(self.limits[:, 3].min()) // 8 * 8)
         return sc
@@ -610,6 +615,8 @@ class Batch:
         _check(load_library().pic_batch_step(self._h, P, F, S, C.byref(sc),
                                              int(n_steps), _ptr(stats),
                                              _stream(torch)))
+        last = stats.view(n_steps, n, -1)[-1, :, STEP_STATS_FIELDS.index("cg_iters")]
+        self.last_iters = [int(v) for v in last.cpu()]
         return stats
 
     @staticmethod
