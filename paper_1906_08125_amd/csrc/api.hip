@@ -162,6 +162,65 @@ hipError_t cg_wait(pic_mesh* h, int64_t seq, fp::CgReport& out) {
   return hipSuccess;
 }
 
+void drop_graphs(pic_mesh* h) {
+  for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
+  h->graphs.clear();
+}
+
+// n CG iterations (numbered by the device counters) as replays of captured
+// graphs of 2^j iterations: a launch chain of short kernels is bound by the
+// host's submission rate, a graph is submitted at once.  The graphs are
+// kept per handle, keyed by the kernel arguments (the fields the iteration
+// kernels do not read are cleared so that every step of a run shares them).
+hipError_t iterate_graphs(pic_mesh* h, const fp::CgArgs& a0, int n, hipStream_t s) {
+  fp::CgArgs a = a0;
+  a.stats = nullptr;
+  a.step_stats = nullptr;
+  a.report = nullptr;
+  a.charge = nullptr;
+  a.rhs = nullptr;
+  a.E = nullptr;
+  a.coef = a.E0 = 0.0;
+  hipError_t e;
+  if (!h->cap_stream &&
+      (e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+    return e;
+  for (int bit = 8; bit >= 0; --bit) {
+    const int cnt = 1 << bit;
+    while (n >= cnt) {
+      hipGraphExec_t exec = nullptr;
+      for (auto& g : h->graphs)
+        if (g.count == cnt && std::memcmp(&g.key, &a, sizeof a) == 0) {
+          exec = g.exec;
+          break;
+        }
+      if (!exec) {
+        if (h->graphs.size() >= 64) drop_graphs(h);
+        hipGraph_t graph = nullptr;
+        if ((e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+          return e;
+        const hipError_t le = fp::cg_launch_iters_dev(a, cnt, h->cap_stream);
+        if ((e = hipStreamEndCapture(h->cap_stream, &graph)) != hipSuccess) return e;
+        if (le != hipSuccess) {
+          (void)hipGraphDestroy(graph);
+          return le;
+        }
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return e;
+        pic_mesh::IterGraph ig;
+        std::memcpy(&ig.key, &a, sizeof a);
+        ig.count = cnt;
+        ig.exec = exec;
+        h->graphs.push_back(ig);
+      }
+      if ((e = hipGraphLaunch(exec, s)) != hipSuccess) return e;
+      n -= cnt;
+    }
+  }
+  return hipSuccess;
+}
+
 // One Poisson solve: the resfield pass (residual of the warm start and the
 // field of phi) and the convergence test, then -- before waiting -- a first
 // batch of `spec` CG iterations (they return at once if the test passed).
@@ -176,11 +235,11 @@ hipError_t run_solve(pic_mesh* h, const fp::CgArgs& a0, int spec, hipStream_t s,
   int64_t seq = ++h->cg_seq;
   hipError_t e = fp::cg_launch_begin(a, spec > 0 ? 0 : seq, s);
   if (e != hipSuccess) return e;
-  int it = 0;
   int batch = spec;
   if (batch > 0) {
-    if ((e = fp::cg_launch_iters(a, it, batch, seq, s)) != hipSuccess) return e;
-    it += batch;
+    if ((e = iterate_graphs(h, a, batch, s)) != hipSuccess ||
+        (e = fp::cg_launch_report(a, seq, s)) != hipSuccess)
+      return e;
   }
   if ((e = hipEventRecord(h->rb_event, s)) != hipSuccess) return e;
   fp::CgReport r;
@@ -190,12 +249,12 @@ hipError_t run_solve(pic_mesh* h, const fp::CgArgs& a0, int spec, hipStream_t s,
     seq = ++h->cg_seq;
     if (r.state == fp::CG_RECHECK) {
       if ((e = fp::cg_launch_recheck(a, seq, s)) != hipSuccess) return e;
-      it = 0;  // a restart (if any) begins from the true residual
       batch = 16;
     } else {
       batch = batch < 8 ? 8 : std::min(2 * batch, 256);
-      if ((e = fp::cg_launch_iters(a, it, batch, seq, s)) != hipSuccess) return e;
-      it += batch;
+      if ((e = iterate_graphs(h, a, batch, s)) != hipSuccess ||
+          (e = fp::cg_launch_report(a, seq, s)) != hipSuccess)
+        return e;
     }
     if ((e = hipEventRecord(h->rb_event, s)) != hipSuccess) return e;
     if ((e = cg_wait(h, seq, r)) != hipSuccess) return e;
@@ -389,6 +448,8 @@ pic_status mesh_destroy(pic_mesh* h) {
   if (h->queue) (void)hipFree(h->queue);
   if (h->sort_mem) (void)hipFree(h->sort_mem);
   if (h->adj_mem) (void)hipFree(h->adj_mem);
+  drop_graphs(h);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   for (hipEvent_t ev : h->ev_pool) (void)hipEventDestroy(ev);
   delete h;
   return PIC_OK;
@@ -912,7 +973,7 @@ pic_status pic_batch_step(pic_batch* b, const pic_particles* P,
           if ((mask >> i) & 1ull)
             if ((r = fp::cg_launch_recheck(ai, 0, s)) != hipSuccess) return r;
           const int c = counts ? (*counts)[i] : count;
-          if ((r = fp::cg_launch_iters_dev(ai, c, s)) != hipSuccess) return r;
+          if ((r = iterate_graphs(b->h[i], ai, c, s)) != hipSuccess) return r;
         }
         return hipSuccess;
       }

@@ -41,6 +41,14 @@ struct pic_mesh {
   size_t sort_bytes = 0;
   void* adj_mem = nullptr;             // adjoint scratch (grown on demand)
   size_t adj_bytes = 0;
+  // CG iteration batches captured as HIP graphs (kernel arguments, count)
+  struct IterGraph {
+    fp::CgArgs key;
+    int count;
+    hipGraphExec_t exec;
+  };
+  std::vector<IterGraph> graphs;
+  hipStream_t cap_stream = nullptr;    // private stream used only to capture
   // host copies of the emitting faces
   std::vector<int32_t> h_e_tet, h_e_nodes;
   std::vector<double> h_e_area;

@@ -76,6 +76,8 @@ hipError_t cg_launch_iters(const CgArgs& a, int it0, int n, int64_t seq,
 hipError_t cg_launch_recheck(const CgArgs& a, int64_t seq, hipStream_t s);
 // n iterations numbered by the device counters (no report)
 hipError_t cg_launch_iters_dev(const CgArgs& a, int n, hipStream_t s);
+// the control state with sequence number seq into a.report
+hipError_t cg_launch_report(const CgArgs& a, int64_t seq, hipStream_t s);
 
 // Batched launches: one launch per solver kernel covers every instance of
 // args[] (device array) with the block schedule map; mask selects the

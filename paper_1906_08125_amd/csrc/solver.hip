@@ -500,6 +500,12 @@ __global__ void __launch_bounds__(kCgBlock) k_cg_spmv(CgArgs a, int it,
   k_cg_spmv_body(a, it, seq, VB{(int)blockIdx.x, (int)gridDim.x});
 }
 
+__global__ void k_cg_report(CgArgs a, int64_t seq) {
+  if (threadIdx.x != 0) return;
+  __threadfence_system();
+  report(a.ctrl, a.report, seq, a.ctrl->state);
+}
+
 // Batched kernels: block -> (instance, virtual block) by the schedule.
 // gated: skip the instances outside the mask (re-check launches).
 __global__ void __launch_bounds__(kCgBlock) k_cg_resfield_b(CgBatch b, int reset,
@@ -565,6 +571,11 @@ hipError_t cg_launch_iters(const CgArgs& a, int it0, int n, int64_t seq,
     LAUNCH(k_cg_spmv, a, it0 + k, k == n - 1 ? seq : (int64_t)0);
   }
   return hipSuccess;
+}
+
+hipError_t cg_launch_report(const CgArgs& a, int64_t seq, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_report, dim3(1), dim3(64), 0, s, a, seq);
+  return hipGetLastError();
 }
 
 hipError_t cg_launch_iters_dev(const CgArgs& a, int n, hipStream_t s) {
