@@ -100,7 +100,8 @@ fp::SortArgs sort_args(pic_mesh* h, const pic_particles* P, int real_bytes) {
   a.s_tet = (int32_t*)take((size_t)cap * 4);
   a.s_birth = (int32_t*)take((size_t)cap * 4);
   a.s_id = (int64_t*)take((size_t)cap * 8);
-  a.hist = (uint32_t*)take((size_t)64 * ((cap + 4095) / 4096) * 4);
+  a.hist = (uint32_t*)take((size_t)fp::kSortBins * fp::sort_tiles(cap) * 4);
+  a.total = (uint32_t*)take((size_t)fp::kSortBins * 4);
   return a;
 }
 

@@ -538,7 +538,7 @@ __device__ void emit_block(const EmitArgs& a) {
   }
 }
 
-constexpr int kBeginBlock = 1024;
+constexpr int kBeginBlock = 512;  // 1024 would cap registers below the emission path's needs
 
 __global__ void __launch_bounds__(kBlock) k_emit(EmitArgs a) {
   emit_block<kBlock>(a);

@@ -4,6 +4,9 @@
 
 namespace fp {
 
+constexpr int kSortBins = 256;   // 8-bit digits
+constexpr int kSortTile = 4096;  // items per workgroup of a pass
+
 struct SortArgs {
   int64_t n_tets;
   int32_t* n_slots;       // in: slots in use, out: live particles
@@ -19,7 +22,8 @@ struct SortArgs {
   // scratch
   uint32_t* key[2];
   uint32_t* val[2];
-  uint32_t* hist;
+  uint32_t* hist;         // [kSortBins][sort_tiles(capacity)]
+  uint32_t* total;        // [kSortBins]
   void* s_real[6];
   double* s_w;
   int32_t* s_tet;
@@ -30,5 +34,6 @@ struct SortArgs {
 hipError_t sort_particles(const SortArgs& a, int64_t capacity, int n_cu,
                           hipStream_t s);
 size_t sort_scratch_bytes(int64_t capacity, int real_bytes);
+int sort_tiles(int64_t capacity);
 
 }  // namespace fp

@@ -1,10 +1,20 @@
 // Particle re-sort by containing tet with compaction: a stable LSD radix
 // sort of (key = tet, or n_tets for a free slot; value = slot index) with
-// 6-bit digits, then a gather of every particle array into scratch and a
-// copy back.  Stable ranking comes from each thread owning a contiguous
-// run of items: per-thread digit counts, a per-digit prefix over threads in
-// LDS, and a prefix over blocks from one scan kernel -- no atomics, so the
-// order (and everything computed after it) is deterministic.
+// 8-bit digits, then a gather of every particle array into scratch and a
+// copy back.
+//
+// One pass over a digit is three launches:
+//   k_sort_hist     digit counts of every tile of kSortTile items;
+//   k_sort_scan     one workgroup per digit: exclusive scan of that digit's
+//                   counts over the tiles, and the digit's total;
+//   k_sort_scatter  every wave ranks the 64 items of a round among the
+//                   lanes with the same digit (eight ballots; lanes are in
+//                   item order, so the rank is stable), per-wave digit
+//                   counters in LDS carry the rank across rounds and waves,
+//                   the tile is reordered by digit in LDS and written out in
+//                   runs that are contiguous in the destination.
+// No atomic operation decides an order, so the permutation (and everything
+// computed after it) is deterministic.
 #include "common.h"
 #include "sort.h"
 
@@ -12,21 +22,35 @@ namespace fp {
 
 namespace {
 
-constexpr int kBins = 64;  // 6-bit digits
+constexpr int kBins = kSortBins;
 constexpr int kThreads = 256;
-constexpr int kPer = 16;   // items per thread
-constexpr int kTile = kThreads * kPer;
+constexpr int kWaves = kThreads / 64;
+constexpr int kRounds = kSortTile / kThreads;  // rounds of 64 items per wave
+static_assert(kThreads == kBins, "one thread per digit in the tile sums");
+static_assert(kSortTile == kWaves * kRounds * 64, "tile = waves x rounds x 64");
 
-// counts[b][t] of the digits of thread t's items (b < kBins)
-__device__ inline void thread_counts(const uint32_t* key, int64_t n,
-                                     int64_t base, int shift,
-                                     uint16_t (*cnt)[kThreads]) {
-  for (int b = 0; b < kBins; ++b) cnt[b][threadIdx.x] = 0;
-  const int64_t i0 = base + (int64_t)threadIdx.x * kPer;
-  for (int k = 0; k < kPer; ++k) {
-    const int64_t i = i0 + k;
-    if (i < n) cnt[(key[i] >> shift) & (kBins - 1)][threadIdx.x] += 1;
+// Exclusive prefix of v over the threads of the workgroup (thread order);
+// *total receives the sum.  Every thread must call it.
+__device__ inline uint32_t block_exscan(uint32_t v, uint32_t* wsum,
+                                        uint32_t* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t inc = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t o = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += o;
   }
+  if (lane == 63) wsum[wave] = inc;
+  __syncthreads();
+  uint32_t before = 0, all = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) {
+    if (w < wave) before += wsum[w];
+    all += wsum[w];
+  }
+  __syncthreads();
+  *total = all;
+  return before + inc - v;
 }
 
 }  // namespace
@@ -42,121 +66,125 @@ __global__ void __launch_bounds__(kThreads) k_sort_keys(SortArgs a) {
   }
 }
 
-// Per-block digit totals: hist[bin * nblocks + block].
+// Digit counts of tile b: hist[digit * ntiles + b].  (Integer counts: the
+// order of the LDS additions does not matter.)
 __global__ void __launch_bounds__(kThreads) k_sort_hist(SortArgs a, int src,
                                                         int shift) {
-  __shared__ uint16_t cnt[kBins][kThreads];
+  __shared__ uint32_t cnt[kBins];
   const int64_t n = *a.n_slots;
-  const int64_t base = (int64_t)blockIdx.x * kTile;
-  thread_counts(a.key[src], n, base, shift, cnt);
+  cnt[threadIdx.x] = 0;
   __syncthreads();
-  if (threadIdx.x < kBins) {
-    uint32_t s = 0;
-    for (int t = 0; t < kThreads; ++t) s += cnt[threadIdx.x][t];
-    a.hist[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = s;
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  const uint32_t* key = a.key[src];
+  for (int k = threadIdx.x; k < kSortTile; k += kThreads) {
+    const int64_t i = base + k;
+    if (i < n) atomicAdd(&cnt[(key[i] >> shift) & (kBins - 1)], 1u);
   }
+  __syncthreads();
+  a.hist[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = cnt[threadIdx.x];
 }
 
-// Exclusive scan of hist (bin-major) in one block: every wave owns 4 bins;
-// it sums their per-block counts, the 64 bin totals are scanned in LDS, and
-// each wave then rescans its bins (64 counts at a time, shuffle scan) from
-// the bin's offset.
-// The counts of a bin's run of kScanRun blocks are loaded into registers
-// before any arithmetic, so the loads of a wave are in flight together.
-constexpr int kScanRun = 16 * 64;
-
-__global__ void __launch_bounds__(1024) k_sort_scan(SortArgs a, int nblocks) {
-  __shared__ uint32_t bin_total[kBins];
-  __shared__ uint32_t bin_off[kBins];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nwaves = blockDim.x >> 6;
-  for (int b = wave; b < kBins; b += nwaves) {
-    uint32_t s = 0;
-    for (int j0 = 0; j0 < nblocks; j0 += kScanRun) {
-      uint32_t v[16];
-#pragma unroll
-      for (int k = 0; k < 16; ++k) {
-        const int j = j0 + k * 64 + lane;
-        v[k] = j < nblocks ? a.hist[(int64_t)b * nblocks + j] : 0u;
-      }
-#pragma unroll
-      for (int k = 0; k < 16; ++k) s += v[k];
-    }
-    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
-    if (lane == 0) bin_total[b] = s;
+// Workgroup d: exclusive scan of hist[d][0..ntiles) in place, total[d].
+__global__ void __launch_bounds__(kThreads) k_sort_scan(SortArgs a,
+                                                        int ntiles) {
+  __shared__ uint32_t wsum[kWaves];
+  uint32_t* row = a.hist + (int64_t)blockIdx.x * ntiles;
+  uint32_t carry = 0;
+  for (int j0 = 0; j0 < ntiles; j0 += kThreads) {
+    const int j = j0 + threadIdx.x;
+    const uint32_t v = j < ntiles ? row[j] : 0u;
+    uint32_t chunk;
+    const uint32_t ex = block_exscan(v, wsum, &chunk);
+    if (j < ntiles) row[j] = carry + ex;
+    carry += chunk;
   }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t run = 0;
-    for (int b = 0; b < kBins; ++b) {
-      bin_off[b] = run;
-      run += bin_total[b];
-    }
-  }
-  __syncthreads();
-  for (int b = wave; b < kBins; b += nwaves) {
-    uint32_t carry = bin_off[b];
-    for (int j0 = 0; j0 < nblocks; j0 += kScanRun) {
-      uint32_t v[16];
-#pragma unroll
-      for (int k = 0; k < 16; ++k) {
-        const int j = j0 + k * 64 + lane;
-        v[k] = j < nblocks ? a.hist[(int64_t)b * nblocks + j] : 0u;
-      }
-#pragma unroll
-      for (int k = 0; k < 16; ++k) {
-        const int j = j0 + k * 64 + lane;
-        uint32_t inc = v[k];
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-          const uint32_t o = __shfl_up(inc, off, 64);
-          if (lane >= off) inc += o;
-        }
-        if (j < nblocks) a.hist[(int64_t)b * nblocks + j] = carry + inc - v[k];
-        carry += __shfl(inc, 63, 64);
-      }
-    }
-  }
+  if (threadIdx.x == 0) a.total[blockIdx.x] = carry;
 }
 
 __global__ void __launch_bounds__(kThreads) k_sort_scatter(SortArgs a, int src,
                                                            int shift) {
-  __shared__ uint16_t cnt[kBins][kThreads];
-  __shared__ uint32_t pre[kBins][kThreads];
+  __shared__ uint32_t wc[kWaves][kBins];  // per-wave digit counts, then bases
+  __shared__ uint32_t tstart[kBins];      // first slot of a digit in the tile
+  __shared__ uint32_t gbase[kBins];       // destination of that slot
+  __shared__ uint32_t s_key[kSortTile];
+  __shared__ uint32_t s_val[kSortTile];
+  __shared__ uint32_t wsum[kWaves];
   const int64_t n = *a.n_slots;
-  const int64_t base = (int64_t)blockIdx.x * kTile;
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  if (base >= n) return;  // the whole workgroup: no barrier is skipped
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) wc[w][threadIdx.x] = 0;
+  __syncthreads();
   const uint32_t* key = a.key[src];
   const uint32_t* val = a.val[src];
-  thread_counts(key, n, base, shift, cnt);
-  __syncthreads();
-  // per-bin exclusive prefix over threads: 4 threads per bin, 64 each
-  {
-    const int b = threadIdx.x >> 2, q = threadIdx.x & 3;
-    uint32_t s = 0;
-    for (int t = q * 64; t < q * 64 + 64; ++t) {
-      pre[b][t] = s;
-      s += cnt[b][t];
+  // wave w owns items [w, w + 1) * kRounds * 64 of the tile, round r the
+  // 64 items from r * 64 on: lane order is item order
+  const int64_t w0 = base + (int64_t)wave * kRounds * 64 + lane;
+  uint32_t kr[kRounds], vr[kRounds], rk[kRounds];
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const int64_t i = w0 + r * 64;
+    kr[r] = i < n ? key[i] : 0u;
+    vr[r] = i < n ? val[i] : 0u;
+  }
+  const uint64_t below_me = (1ull << lane) - 1ull;
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const bool ok = w0 + r * 64 < n;
+    const uint32_t d = (kr[r] >> shift) & (kBins - 1);
+    // lanes holding an item with the same digit as this lane
+    uint64_t peers = __ballot(ok);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      const bool one = (d >> bit) & 1u;
+      const uint64_t m = __ballot(one);
+      peers &= one ? m : ~m;
     }
-    // combine the 4 quarter sums (in LDS order, deterministic)
-    __shared__ uint32_t qs[kBins][4];
-    qs[b][q] = s;
-    __syncthreads();
-    uint32_t add = 0;
-    for (int k = 0; k < q; ++k) add += qs[b][k];
-    for (int t = q * 64; t < q * 64 + 64; ++t) pre[b][t] += add;
+    const uint32_t prev = wc[wave][d];
+    rk[r] = prev + (uint32_t)__popcll(peers & below_me);
+    // the highest lane of each digit group advances the wave's counter
+    // (after every lane of the wave has read it: LDS keeps a wave's order)
+    if (ok && (peers >> lane) == 1ull)
+      wc[wave][d] = prev + (uint32_t)__popcll(peers);
   }
   __syncthreads();
-  const int64_t i0 = base + (int64_t)threadIdx.x * kPer;
-  for (int k = 0; k < kPer; ++k) {
-    const int64_t i = i0 + k;
-    if (i >= n) break;
-    const uint32_t kk = key[i];
-    const int b = (kk >> shift) & (kBins - 1);
-    const uint32_t pos = a.hist[(int64_t)b * gridDim.x + blockIdx.x] +
-                         pre[b][threadIdx.x];
-    pre[b][threadIdx.x] += 1;
-    a.key[src ^ 1][pos] = kk;
-    a.val[src ^ 1][pos] = val[i];
+  {
+    // thread b: the digit's wave bases inside the tile, its first slot in
+    // the tile and the destination of that slot
+    const int b = threadIdx.x;
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+      const uint32_t c = wc[w][b];
+      wc[w][b] = cnt;
+      cnt += c;
+    }
+    uint32_t all;
+    const uint32_t ts = block_exscan(cnt, wsum, &all);
+    const uint32_t bb = block_exscan(a.total[b], wsum, &all);
+    tstart[b] = ts;
+    gbase[b] = bb + a.hist[(int64_t)b * gridDim.x + blockIdx.x];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    if (w0 + r * 64 >= n) continue;
+    const uint32_t d = (kr[r] >> shift) & (kBins - 1);
+    const uint32_t p = tstart[d] + wc[wave][d] + rk[r];
+    s_key[p] = kr[r];
+    s_val[p] = vr[r];
+  }
+  __syncthreads();
+  const int m = n - base < kSortTile ? (int)(n - base) : kSortTile;
+  uint32_t* okey = a.key[src ^ 1];
+  uint32_t* oval = a.val[src ^ 1];
+  for (int j = threadIdx.x; j < m; j += kThreads) {
+    const uint32_t kk = s_key[j];
+    const uint32_t d = (kk >> shift) & (kBins - 1);
+    const uint32_t pos = gbase[d] + ((uint32_t)j - tstart[d]);
+    okey[pos] = kk;
+    oval[pos] = s_val[j];
   }
 }
 
@@ -210,18 +238,22 @@ __global__ void __launch_bounds__(kThreads) k_sort_copyback(SortArgs a) {
   }
 }
 
+int sort_tiles(int64_t capacity) {
+  return (int)((capacity + kSortTile - 1) / kSortTile);
+}
+
 hipError_t sort_particles(const SortArgs& a, int64_t capacity, int n_cu,
                           hipStream_t s) {
-  const int nblocks = (int)((capacity + kTile - 1) / kTile);
+  const int ntiles = sort_tiles(capacity);
   const int grid = n_cu * 4;
   hipLaunchKernelGGL(k_sort_keys, dim3(grid), dim3(kThreads), 0, s, a);
   int bits = 1;
   while ((1ll << bits) <= a.n_tets) ++bits;
   int src = 0;
-  for (int shift = 0; shift < bits; shift += 6) {
-    hipLaunchKernelGGL(k_sort_hist, dim3(nblocks), dim3(kThreads), 0, s, a, src, shift);
-    hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, s, a, nblocks);
-    hipLaunchKernelGGL(k_sort_scatter, dim3(nblocks), dim3(kThreads), 0, s, a, src, shift);
+  for (int shift = 0; shift < bits; shift += 8) {
+    hipLaunchKernelGGL(k_sort_hist, dim3(ntiles), dim3(kThreads), 0, s, a, src, shift);
+    hipLaunchKernelGGL(k_sort_scan, dim3(kBins), dim3(kThreads), 0, s, a, ntiles);
+    hipLaunchKernelGGL(k_sort_scatter, dim3(ntiles), dim3(kThreads), 0, s, a, src, shift);
     src ^= 1;
   }
   hipLaunchKernelGGL(k_sort_gather, dim3(grid), dim3(kThreads), 0, s, a, src);
@@ -230,9 +262,9 @@ hipError_t sort_particles(const SortArgs& a, int64_t capacity, int n_cu,
 }
 
 size_t sort_scratch_bytes(int64_t capacity, int real_bytes) {
-  const int64_t nblocks = (capacity + kTile - 1) / kTile;
+  const int64_t ntiles = sort_tiles(capacity);
   return (size_t)capacity * (16 + 6 * (size_t)real_bytes + 8 + 4 + 4 + 8) +
-         (size_t)kBins * nblocks * 4 + 4096;
+         (size_t)kBins * ntiles * 4 + kBins * 4 + 8192;
 }
 
 }  // namespace fp

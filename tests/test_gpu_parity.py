@@ -322,7 +322,41 @@ def test_resort_compacts_and_orders(pic):
     tet = gs.tet[:n].cpu().numpy()
     assert n == sg[-1]["n_after"] == sg[-1]["n_slots"]
     assert (tet >= 0).all() and (np.diff(tet) >= 0).all()
+    # before this first re-sort the slots held the injected particles in
+    # injection order, which is id order: a stable sort keeps ties that way
+    ids = gs.id[:n].cpu().numpy()
+    assert (np.diff(ids)[np.diff(tet) == 0] > 0).all()
     _compare_runs(ost, gs, so, sg)
+
+
+def test_resort_three_digit_passes(pic):
+    """A mesh of more than 2^16 tets (three 8-bit digit passes) and a
+    population spanning several sort tiles: a run that re-sorts after its
+    last step holds exactly the particles of the same run without re-sort,
+    compacted, ordered by tet, ties in slot (= injection = id) order."""
+    cfg = W.batch_configs(1)[0]
+    tip = cfg.mesh()
+    gm = pic.Mesh(tip, cfg.emit_zmin)
+    assert gm.n_tets >= 1 << 16
+    out = []
+    for every in (0, 8):
+        gs = pic.State(gm, 200_000)
+        gs.init_field(cfg.E0, tol=cfg.tol)
+        rate, _ = gm.emission_rate(gs.E, cfg.phi_w)
+        w_sp = rate.item() * cfg.dt * cfg.transit_steps / 100_000
+        st = pic.State.decode_stats(gs.step(
+            step0=0, n_steps=8, dt=cfg.dt, E0=cfg.E0, w_sp=w_sp,
+            phi_w=cfg.phi_w, seed=cfg.seed, tol=cfg.tol, resort_every=every))
+        out.append((gs, st))
+    (ga, sa), (gb, sb) = out
+    A, B = ga.live(), gb.live()
+    assert B["id"].size == sb[-1]["n_after"] == int(gb.n_slots.item())
+    assert B["id"].size > 3 * 4096
+    assert (np.diff(B["tet"]) >= 0).all()
+    assert (np.diff(B["id"])[np.diff(B["tet"]) == 0] > 0).all()
+    a, b = np.argsort(A["id"]), np.argsort(B["id"])
+    for key in ("id", "x", "y", "z", "vx", "vy", "vz", "w", "tet", "birth"):
+        assert (A[key][a] == B[key][b]).all(), key
 
 
 # ---------------------------------------------------------------------------
