@@ -94,20 +94,36 @@ def run_leg(gm, cfg, w_sp, precision, args):
     step += args.warmup
     stats = torch.zeros(args.steps * pic.STEP_STATS_BYTES // 8,
                         dtype=torch.int64, device="cuda")
-    # timed region: K steps, bracketed by synchronizations
-    gm.profile(True)
+    # timed region: K steps, bracketed by synchronizations; HIP events
+    # bracket the push kernel (the dominant one) only: every event is a
+    # packet of its own in the stream and costs GPU time
+    gm.profile(True, classes=("push",))
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     gs.step(step0=step, n_steps=args.steps, stats=stats, **kw)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
-    kt = gm.profile_read()
+    kt_timed = gm.profile_read()
     gm.profile(False)
     rows = pic.State.decode_stats(stats)
-    for r in rows:
+    step += args.steps
+    # per-class breakdown: a further, untimed stretch of steps with every
+    # kernel class bracketed
+    kt = {}
+    if args.breakdown_steps > 0:
+        gm.profile(True)
+        bstats = gs.step(step0=step, n_steps=args.breakdown_steps, **kw)
+        torch.cuda.synchronize()
+        kt = gm.profile_read()
+        gm.profile(False)
+        rows_b = pic.State.decode_stats(bstats)
+    else:
+        rows_b = []
+    for r in rows + rows_b:
         if r["status"] != 0:
             raise RuntimeError(f"step status {r['status']}: {r}")
-    return dict(elapsed=elapsed, kt=kt, rows=rows, state=gs, cold=cold)
+    return dict(elapsed=elapsed, kt=kt, kt_timed=kt_timed, rows=rows,
+                rows_b=rows_b, state=gs, cold=cold)
 
 
 def run_gpu(args):
@@ -143,26 +159,36 @@ def run_gpu(args):
 
     leg = run_leg(gm, cfg, w_sp, pic.PIC_FP64, args)
     elapsed, kt, rows = leg["elapsed"], leg["kt"], leg["rows"]
+    kt_timed, rows_b = leg["kt_timed"], leg["rows_b"]
     del leg
     pushes = sum(r["n_before"] + r["n_inj"] for r in rows)
     live_mean = sum(r["n_before"] for r in rows) / len(rows)
-    iters_mean = sum(r["cg_iters"] for r in rows) / len(rows)
     ms_step = 1e3 * elapsed / args.steps
-    # per-kernel roofline
+    # per-kernel times of the breakdown stretch; the push also from the
+    # timed region (the roofline figure)
     kernels = {}
     for name, v in kt.items():
         kernels[name] = dict(ms_total=round(v["ms"], 4), launches=v["launches"],
                              us_per_launch=round(1e3 * v["ms"] / v["launches"], 2))
-    push_us = kt["push"]["ms"] * 1e3 / kt["push"]["launches"]
-    solve_us = kt["solve"]["ms"] * 1e3 / kt["solve"]["launches"]
+    push_us = kt_timed["push"]["ms"] * 1e3 / kt_timed["push"]["launches"]
     pb = push_bytes(live_mean)
-    sb = solve_bytes(gm.info, iters_mean)
-    kernels["push"]["algo_bytes"] = pb
-    kernels["push"]["GBps"] = round(pb / push_us / 1e3, 1)
-    kernels["solve"]["algo_bytes"] = sb
-    kernels["solve"]["GBps"] = round(sb / solve_us / 1e3, 1)
-    dom = max(("push", "solve"), key=lambda k: kt[k]["ms"])
-    dom_bytes, dom_us = (pb, push_us) if dom == "push" else (sb, solve_us)
+    kernels["push_timed"] = dict(
+        ms_total=round(kt_timed["push"]["ms"], 4),
+        launches=kt_timed["push"]["launches"], us_per_launch=round(push_us, 2),
+        algo_bytes=pb, GBps=round(pb / push_us / 1e3, 1))
+    dom, dom_bytes, dom_us = "push", pb, push_us
+    if "solve" in kt and rows_b:
+        solve_us = kt["solve"]["ms"] * 1e3 / kt["solve"]["launches"]
+        iters_b = sum(r["cg_iters"] for r in rows_b) / len(rows_b)
+        live_b = sum(r["n_before"] for r in rows_b) / len(rows_b)
+        sb = solve_bytes(gm.info, iters_b)
+        kernels["solve"]["algo_bytes"] = sb
+        kernels["solve"]["GBps"] = round(sb / solve_us / 1e3, 1)
+        pbb = push_bytes(live_b)
+        kernels["push"]["algo_bytes"] = pbb
+        kernels["push"]["GBps"] = round(pbb / (kt["push"]["ms"] * 1e3 / kt["push"]["launches"]) / 1e3, 1)
+        if kt["solve"]["ms"] > kt["push"]["ms"]:
+            dom, dom_bytes, dom_us = "solve", sb, solve_us
     achieved = dom_bytes / dom_us / 1e3  # GB/s
 
     mixed = None
@@ -172,7 +198,8 @@ def run_gpu(args):
         mr = ml["rows"]
         m_live = sum(r["n_before"] for r in mr) / len(mr)
         mk = ml["kt"]
-        m_push_us = mk["push"]["ms"] * 1e3 / mk["push"]["launches"]
+        mt = ml["kt_timed"]["push"]
+        m_push_us = mt["ms"] * 1e3 / mt["launches"]
         mixed = dict(
             value=round(args.steps / ml["elapsed"], 3), unit="steps/s",
             ms_per_step=round(1e3 * ml["elapsed"] / args.steps, 4),
@@ -208,7 +235,7 @@ def run_gpu(args):
                     w_sp=w_sp, dt_fs=cfg.dt, tol=cfg.tol,
                     resort_every=args.resort),
         pushes_per_s=round(pushes / elapsed, 1),
-        cg_iters_per_step=iters_mean,
+        cg_iters_per_step=sum(r["cg_iters"] for r in rows) / len(rows),
         cold_solve=dict(iters=cold["iters"], ms=round(cold_ms, 3),
                         iters_per_s=round(cold["iters"] / cold_ms * 1e3, 1),
                         relres=cold["relres"]),
@@ -400,6 +427,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--capacity", type=float, default=2.5e6)
     ap.add_argument("--resort", type=int, default=10)
+    ap.add_argument("--breakdown-steps", type=int, default=20,
+                    help="untimed steps after the timed ones with every "
+                         "kernel class bracketed by events (0: none)")
     ap.add_argument("--cpu-particles", type=int, default=1_000_000)
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")

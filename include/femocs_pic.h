@@ -331,11 +331,13 @@ PIC_API pic_status pic_batch_step(pic_batch* batch,
 
 /* ------------------------------------------------------------------------ */
 /* Kernel timing (measurement support, not part of the method).  While      */
-/* enabled, pic_step and poisson_solve bracket every kernel they launch     */
-/* with HIP events on the caller's stream; pic_profile_read synchronizes    */
-/* on the last event and returns the summed elapsed milliseconds and the    */
-/* launch count per kernel class since the last enable.  Event objects are  */
-/* created on demand while profiling is on.                                 */
+/* enabled, pic_step and poisson_solve bracket the kernels of the selected  */
+/* classes with HIP events on the caller's stream; pic_profile_read         */
+/* synchronizes on the last event and returns the summed elapsed            */
+/* milliseconds and the launch count per kernel class since the last        */
+/* enable.  Every event is a packet of its own in the stream and costs      */
+/* GPU time: select only the classes wanted.  Event objects are created on  */
+/* demand while profiling is on.                                            */
 /* ------------------------------------------------------------------------ */
 enum {
   PIC_K_PUSH = 0,     /* live + injected: gather, kick, drift, walk, deposit */
@@ -354,7 +356,10 @@ typedef struct {
   int64_t launches[PIC_K_COUNT];
 } pic_kernel_times;
 
-PIC_API pic_status pic_profile(pic_mesh* mesh, int32_t enable);
+/* classes: bitmask of (1 << PIC_K_*), PIC_PROFILE_ALL for every class, 0  */
+/* to stop.                                                                 */
+#define PIC_PROFILE_ALL 0xFF
+PIC_API pic_status pic_profile(pic_mesh* mesh, int32_t classes);
 PIC_API pic_status pic_profile_read(pic_mesh* mesh, pic_kernel_times* out);
 
 PIC_API const char* pic_last_error(void);

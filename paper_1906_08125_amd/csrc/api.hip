@@ -229,25 +229,45 @@ hipError_t iterate_graphs(pic_mesh* h, const fp::CgArgs& a0, int n, hipStream_t 
 // re-check (scatter + resfield + test) when the recursive residual has
 // converged.  The field is always that of the final phi.  Blocks the calling
 // thread at the waits.  Returns the iterations done.
-hipError_t run_solve(pic_mesh* h, const fp::CgArgs& a0, int spec, hipStream_t s,
-                     int64_t* iters_out) {
-  fp::CgArgs a = a0;
+// First round of a solve: the residual pass and convergence test, spec
+// speculated iterations, and the report of the state; *seq_out receives the
+// report's sequence number.  Nothing waits here.
+hipError_t solve_start(pic_mesh* h, fp::CgArgs& a, int spec, hipStream_t s,
+                       int64_t* seq_out) {
   a.report = h->cg_report_dev;
-  int64_t seq = ++h->cg_seq;
+  const int64_t seq = ++h->cg_seq;
   hipError_t e = fp::cg_launch_begin(a, spec > 0 ? 0 : seq, s);
   if (e != hipSuccess) return e;
-  int batch = spec;
-  if (batch > 0) {
-    if ((e = iterate_graphs(h, a, batch, s)) != hipSuccess ||
+  if (spec > 0) {
+    if ((e = iterate_graphs(h, a, spec, s)) != hipSuccess ||
         (e = fp::cg_launch_report(a, seq, s)) != hipSuccess)
       return e;
   }
   if ((e = hipEventRecord(h->rb_event, s)) != hipSuccess) return e;
+  *seq_out = seq;
+  return hipSuccess;
+}
+
+void prof_begin(pic_mesh* h, int cls, hipStream_t s);
+void prof_end(pic_mesh* h, hipStream_t s);
+constexpr int kProfNoCount = 0x100;  // time the bracket, count no launch
+
+// Waits for the report of the first round and enqueues further rounds (a
+// true-residual re-check, or twice as many iterations as the last round)
+// until the solve has ended.  *first_state: the state the first report
+// carried.  Further rounds are timed as solve time while profiling.
+hipError_t solve_finish(pic_mesh* h, const fp::CgArgs& a, int spec,
+                        int64_t seq, hipStream_t s, int64_t* iters_out,
+                        int32_t* first_state) {
   fp::CgReport r;
-  if ((e = cg_wait(h, seq, r)) != hipSuccess) return e;
+  hipError_t e = cg_wait(h, seq, r);
+  if (e != hipSuccess) return e;
+  if (first_state) *first_state = r.state;
+  int batch = spec;
   for (int guard = 0; guard < (1 << 20); ++guard) {
     if (r.state == fp::CG_DONE || r.state == fp::CG_NOCONV) break;
     seq = ++h->cg_seq;
+    prof_begin(h, PIC_K_SOLVE | kProfNoCount, s);
     if (r.state == fp::CG_RECHECK) {
       if ((e = fp::cg_launch_recheck(a, seq, s)) != hipSuccess) return e;
       batch = 16;
@@ -257,11 +277,21 @@ hipError_t run_solve(pic_mesh* h, const fp::CgArgs& a0, int spec, hipStream_t s,
           (e = fp::cg_launch_report(a, seq, s)) != hipSuccess)
         return e;
     }
+    prof_end(h, s);
     if ((e = hipEventRecord(h->rb_event, s)) != hipSuccess) return e;
     if ((e = cg_wait(h, seq, r)) != hipSuccess) return e;
   }
   if (iters_out) *iters_out = r.iters;
   return hipSuccess;
+}
+
+hipError_t run_solve(pic_mesh* h, const fp::CgArgs& a0, int spec, hipStream_t s,
+                     int64_t* iters_out) {
+  fp::CgArgs a = a0;
+  int64_t seq = 0;
+  hipError_t e = solve_start(h, a, spec, s, &seq);
+  if (e != hipSuccess) return e;
+  return solve_finish(h, a, spec, seq, s, iters_out, nullptr);
 }
 
 pic_status check_solve(const pic_solve_params* p) {
@@ -378,13 +408,15 @@ void prof_mark(pic_mesh* h, hipStream_t s) {
 }
 
 void prof_begin(pic_mesh* h, int cls, hipStream_t s) {
-  if (!h->profiling) return;
+  h->prof_open = h->profiling && ((h->prof_mask >> (cls & 0xff)) & 1u);
+  if (!h->prof_open) return;
   h->ev_class.push_back(cls);
   prof_mark(h, s);
 }
 
 void prof_end(pic_mesh* h, hipStream_t s) {
-  if (!h->profiling) return;
+  if (!h->prof_open) return;
+  h->prof_open = false;
   prof_mark(h, s);
 }
 
@@ -392,9 +424,11 @@ void prof_end(pic_mesh* h, hipStream_t s) {
 
 extern "C" {
 
-pic_status pic_profile(pic_mesh* h, int32_t enable) {
+pic_status pic_profile(pic_mesh* h, int32_t classes) {
   if (!h) return fail(PIC_E_ARG, "pic_profile: null mesh");
-  h->profiling = enable != 0;
+  h->prof_mask = (uint32_t)classes & PIC_PROFILE_ALL;
+  h->profiling = h->prof_mask != 0;
+  h->prof_open = false;
   h->ev_used = 0;
   h->ev_class.clear();
   return PIC_OK;
@@ -412,8 +446,9 @@ pic_status pic_profile_read(pic_mesh* h, pic_kernel_times* out) {
     e = hipEventElapsedTime(&ms, h->ev_pool[2 * i], h->ev_pool[2 * i + 1]);
     if (e != hipSuccess) return hip_fail(e, "pic_profile_read");
     const int c = h->ev_class[i];
-    out->ms[c] += ms;
-    out->launches[c] += 1;
+    if (c < 0) continue;  // a gated launch that did not run
+    out->ms[c & 0xff] += ms;
+    if (!(c & kProfNoCount)) out->launches[c & 0xff] += 1;
   }
   return PIC_OK;
 }
@@ -580,41 +615,54 @@ pic_status pic_step(pic_mesh* h, const pic_particles* P, const pic_fields* F,
   if (e != hipSuccess) return hip_fail(e, "pic_step");
 
   StepSet ss = step_set(h, P, F, prm, h->grid_push, h->grid_inj, h->grid_fb);
-  fp::StepArgs& a = ss.a;
-  fp::EmitArgs& ea = ss.ea;
+  const fp::StepArgs& a = ss.a;
+  const fp::EmitArgs& ea = ss.ea;
   fp::CgArgs& ca = ss.ca;
   const int grid_push = h->grid_push;
   const int grid_inj = h->grid_inj;
   const int grid_fb = h->grid_fb;
+  // The kernels of step k before its solve: clears + emission counts, the
+  // live and new particles in one launch, the exact fallback, the counters.
+  // gate: null, or the control state of the previous solve (see below).
+  // *prof0 receives the first profile slot of these launches.
+  auto pre_solve = [&](int32_t k, const int32_t* gate, size_t* prof0) -> hipError_t {
+    fp::StepArgs ak = a;
+    fp::EmitArgs ek = ea;
+    ak.step = ek.step = prm->step0 + k;
+    ak.stats = ek.stats = stats + k;
+    ak.gate = ek.gate = gate;
+    *prof0 = h->ev_class.size();
+    hipError_t e;
+    prof_begin(h, PIC_K_EMIT, s);
+    if ((e = fp::launch_begin(ek, h->n_cu * 2, s)) != hipSuccess) return e;
+    prof_end(h, s);
+    prof_begin(h, PIC_K_PUSH, s);
+    if ((e = fp::launch_particles(ak, grid_push, grid_inj, s)) != hipSuccess) return e;
+    prof_end(h, s);
+    prof_begin(h, PIC_K_FALLBACK, s);
+    if ((e = fp::launch_fallback(ak, grid_fb, s)) != hipSuccess) return e;
+    if ((e = fp::launch_stats(h->acc_rows, grid_push + grid_inj + grid_fb,
+                              stats + k, gate, s)) != hipSuccess)
+      return e;
+    prof_end(h, s);
+    return hipSuccess;
+  };
+  // The host learns the outcome of a solve from its report.  Rather than
+  // leave the GPU idle meanwhile, the next step's pre-solve kernels are
+  // enqueued right behind the first report, gated on the solve's state:
+  // they run if that round ended the solve (the usual case: a warm start
+  // that already meets the tolerance) and do nothing otherwise, in which
+  // case they are enqueued again once the solve has ended.
+  bool pre_done = false;
   for (int32_t k = 0; k < n_steps; ++k) {
     const int64_t step = prm->step0 + k;
     pic_step_stats* st = stats + k;
-    a.step = step;
-    a.stats = st;
-    ea.step = step;
-    ea.stats = st;
-    ca.step_stats = st;
-    // clears + emission counts, then live and new particles in one launch
-    prof_begin(h, PIC_K_EMIT, s);
-    if ((e = fp::launch_begin(ea, h->n_cu * 2, s)) != hipSuccess)
-      return hip_fail(e, "pic_step begin");
-    prof_end(h, s);
-    prof_begin(h, PIC_K_PUSH, s);
-    if ((e = fp::launch_particles(a, grid_push, grid_inj, s)) != hipSuccess)
+    size_t p0 = 0;
+    if (!pre_done && (e = pre_solve(k, nullptr, &p0)) != hipSuccess)
       return hip_fail(e, "pic_step particles");
-    prof_end(h, s);
-    prof_begin(h, PIC_K_FALLBACK, s);
-    if ((e = fp::launch_fallback(a, grid_fb, s)) != hipSuccess) return hip_fail(e, "pic_step fallback");
-    if ((e = fp::launch_stats(h->acc_rows, grid_push + grid_inj + grid_fb, st, s)) != hipSuccess)
-      return hip_fail(e, "pic_step stats");
-    prof_end(h, s);
-    prof_begin(h, PIC_K_SOLVE, s);
-    int64_t iters = 0;
-    if ((e = run_solve(h, ca, h->step_spec, s, &iters)) != hipSuccess)
-      return hip_fail(e, "pic_step solve");
-    // speculate this many iterations in the next step's first batch
-    h->step_spec = (int)std::min<int64_t>(iters, 256);
-    prof_end(h, s);
+    // the re-sort touches only particles and the solve only the charge:
+    // the sort goes first so that the next step's kernels can follow the
+    // solve directly
     if (prm->resort_every > 0 && (step + 1) % prm->resort_every == 0) {
       prof_begin(h, PIC_K_SORT, s);
       fp::SortArgs sa = sort_args(h, P, f32 ? 4 : 8);
@@ -623,6 +671,27 @@ pic_status pic_step(pic_mesh* h, const pic_particles* P, const pic_fields* F,
         return hip_fail(e, "pic_step sort");
       prof_end(h, s);
     }
+    ca.step_stats = st;
+    const int spec = h->step_spec;
+    int64_t seq = 0;
+    prof_begin(h, PIC_K_SOLVE, s);
+    if ((e = solve_start(h, ca, spec, s, &seq)) != hipSuccess)
+      return hip_fail(e, "pic_step solve");
+    prof_end(h, s);
+    const bool ahead = k + 1 < n_steps;
+    size_t p1 = 0;
+    if (ahead && (e = pre_solve(k + 1, &ca.ctrl->state, &p1)) != hipSuccess)
+      return hip_fail(e, "pic_step particles");
+    const size_t p1e = h->ev_class.size();
+    int64_t iters = 0;
+    int32_t first = fp::CG_ITER;
+    if ((e = solve_finish(h, ca, spec, seq, s, &iters, &first)) != hipSuccess)
+      return hip_fail(e, "pic_step solve");
+    pre_done = ahead && (first == fp::CG_DONE || first == fp::CG_NOCONV);
+    if (ahead && !pre_done)
+      for (size_t i = p1; i < p1e; ++i) h->ev_class[i] = -1;
+    // speculate this many iterations in the next step's first round
+    h->step_spec = (int)std::min<int64_t>(iters, 256);
   }
   return PIC_OK;
 }

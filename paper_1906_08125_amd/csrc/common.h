@@ -195,6 +195,52 @@ __host__ __device__ inline double vol6_filtered(const double* a,
 // every difference is exact (all low parts zero, the usual case for a point
 // near the tet) only the 6 products of high parts are nonzero, and the
 // expansion stays short.
+// The case without low parts: the determinant is exactly the sum of 24
+// doubles (six triple products, each split exactly into four).  Its sign by
+// distillation (iterated VecSum, Ogita, Rump and Oishi 2005): a cascade of
+// error-free sums keeps the exact total while concentrating it in the last
+// element S; once S exceeds the sum R of the others' magnitudes (with a
+// margin for the rounding of R), the sign of S is that of the total.
+// Every index is fixed at compile time, so the terms stay in registers.
+// Returns 2 when 64 passes do not decide (the caller falls back to the
+// general expansion).
+__host__ __device__ inline int vol6_sign_exact_short(const double (*U)[2],
+                                                     const double (*V)[2],
+                                                     const double (*W)[2]) {
+  const int P[6][3] = {{0, 1, 2}, {1, 2, 0}, {2, 0, 1},
+                       {0, 2, 1}, {2, 1, 0}, {1, 0, 2}};
+  double t[24];
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    const double sg = s < 3 ? 1.0 : -1.0;
+    double p, e, p1, e1, p2, e2;
+    ef_prod(U[P[s][0]][0], V[P[s][1]][0], p, e);
+    ef_prod(p, W[P[s][2]][0], p1, e1);
+    ef_prod(e, W[P[s][2]][0], p2, e2);
+    t[4 * s] = sg * p1;
+    t[4 * s + 1] = sg * e1;
+    t[4 * s + 2] = sg * p2;
+    t[4 * s + 3] = sg * e2;
+  }
+  const double margin = 1.0 + 64.0 * 1.1102230246251565e-16;
+  for (int pass = 0; pass < 64; ++pass) {
+#pragma unroll
+    for (int i = 0; i < 23; ++i) {
+      double sum, err;
+      ef_sum(t[i], t[i + 1], sum, err);
+      t[i] = err;
+      t[i + 1] = sum;
+    }
+    double R = 0.0;
+#pragma unroll
+    for (int i = 0; i < 23; ++i) R += fabs(t[i]);
+    const double S = t[23];
+    if (R == 0.0) return S > 0.0 ? 1 : (S < 0.0 ? -1 : 0);
+    if (fabs(S) > R * margin) return S > 0.0 ? 1 : -1;
+  }
+  return 2;
+}
+
 __host__ __device__ inline int vol6_sign_exact(const double* a,
                                                const double* b,
                                                const double* c,
@@ -206,6 +252,10 @@ __host__ __device__ inline int vol6_sign_exact(const double* a,
     ef_sum(c[k], -a[k], V[k][0], V[k][1]);
     ef_sum(d[k], -a[k], W[k][0], W[k][1]);
     tails = tails || U[k][1] != 0.0 || V[k][1] != 0.0 || W[k][1] != 0.0;
+  }
+  if (!tails) {
+    const int sg = vol6_sign_exact_short(U, V, W);
+    if (sg != 2) return sg;
   }
   // permutations of (x, y, z) for rows (U, V, W) and their signs
   const int P[6][3] = {{0, 1, 2}, {1, 2, 0}, {2, 0, 1},

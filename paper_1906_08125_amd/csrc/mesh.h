@@ -57,6 +57,8 @@ struct pic_mesh {
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<int> ev_class;
+  uint32_t prof_mask = 0;   // classes timed (1 << PIC_K_*)
+  bool prof_open = false;   // the last prof_begin recorded an event
 };
 
 namespace fp {

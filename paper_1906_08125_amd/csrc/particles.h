@@ -34,6 +34,10 @@ struct StepArgs {
   int g_push;           // workgroups of the push role (the rest inject)
   int n_blocks;         // workgroups of the particle kernel (the fallback
                         // kernel's counter rows follow theirs)
+  // null, or the previous solve's control state: a launch enqueued before
+  // that solve's outcome is known does nothing unless the solve has ended
+  // (CG_DONE or CG_NOCONV)
+  const int32_t* gate;
 };
 
 struct EmitArgs {
@@ -54,6 +58,7 @@ struct EmitArgs {
   double* face_F;         // or null
   int64_t* clear;         // node charges cleared by k_begin, or null
   int64_t n_clear;
+  const int32_t* gate;    // as StepArgs::gate
 };
 
 struct LocateArgs {
@@ -78,7 +83,7 @@ hipError_t launch_begin(const EmitArgs& a, int grid, hipStream_t s);
 hipError_t launch_particles(const StepArgs& a, int g_push, int g_inj,
                             hipStream_t s);
 hipError_t launch_stats(const int64_t* rows, int n_rows, pic_step_stats* st,
-                        hipStream_t s);
+                        const int32_t* gate, hipStream_t s);
 hipError_t launch_seed_build(const DevMesh& m, int grid, hipStream_t s);
 hipError_t launch_emit(const EmitArgs& a, hipStream_t s);
 hipError_t launch_fallback(const StepArgs& a, int grid, hipStream_t s);

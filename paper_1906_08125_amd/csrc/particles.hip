@@ -11,6 +11,7 @@
 // slots; with particles sorted by tet, neighbouring tets then share an L2.
 #include "common.h"
 #include "particles.h"
+#include "solver.h"
 
 namespace fp {
 
@@ -33,6 +34,14 @@ __device__ inline Span block_span(int64_t n, int G, int g) {
   s.hi = s.lo + per < n ? s.lo + per : n;
   if (s.lo > n) s.lo = n;
   return s;
+}
+
+// A launch gated on a solve whose outcome was not known when it was
+// enqueued runs only if that solve has ended.
+__device__ inline bool gate_closed(const int32_t* gate) {
+  if (!gate) return false;
+  const int32_t st = *gate;
+  return st != CG_DONE && st != CG_NOCONV;
 }
 
 // Per-thread counters of one kernel, flushed once per block.
@@ -547,6 +556,7 @@ __global__ void __launch_bounds__(kBlock) k_emit(EmitArgs a) {
 // Start of a step: workgroup 0 clears the step's stats and counters and
 // computes the emission counts; the others clear the node charges.
 __device__ inline void begin_body(const EmitArgs& a, VB vb) {
+  if (gate_closed(a.gate)) return;
   if (vb.id == 0) {  // dispatched first: the emission path is the longest
     int64_t* s64 = reinterpret_cast<int64_t*>(a.stats);
     const int ns = (int)(sizeof(pic_step_stats) / sizeof(int64_t));
@@ -787,6 +797,7 @@ __device__ inline void inject_role(const StepArgs& a, int g, int G, Acc& acc,
 // One instance per storage precision, so that only one push is compiled in.
 template <bool F32>
 __device__ inline void particles_body(const StepArgs& a, VB vb) {
+  if (gate_closed(a.gate)) return;
   Acc acc;
   acc_zero(acc);
   __shared__ ChargeTable T;
@@ -822,6 +833,7 @@ __global__ void __launch_bounds__(kBlock) k_particles_b(const StepArgs* A,
 // outside every tet (below the top plane) are absorbed by the cathode.
 // ---------------------------------------------------------------------------
 __device__ inline void fallback_body(const StepArgs& a, VB vb) {
+  if (gate_closed(a.gate)) return;
   const DevMesh& m = a.m;
   const int64_t n = a.scratch->n_fallback;
   Acc acc;
@@ -903,7 +915,9 @@ __device__ inline void stats_body(const int64_t* rows, int n_rows,
 
 __global__ void __launch_bounds__(kBlock) k_stats(const int64_t* rows,
                                                   int n_rows,
-                                                  pic_step_stats* st) {
+                                                  pic_step_stats* st,
+                                                  const int32_t* gate) {
+  if (gate_closed(gate)) return;
   stats_body(rows, n_rows, st, (int)blockIdx.x);
 }
 
@@ -1039,8 +1053,8 @@ hipError_t launch_seed_build(const DevMesh& m, int grid, hipStream_t s) {
   return hipGetLastError();
 }
 hipError_t launch_stats(const int64_t* rows, int n_rows, pic_step_stats* st,
-                        hipStream_t s) {
-  hipLaunchKernelGGL(k_stats, dim3(kAccFields), dim3(kBlock), 0, s, rows, n_rows, st);
+                        const int32_t* gate, hipStream_t s) {
+  hipLaunchKernelGGL(k_stats, dim3(kAccFields), dim3(kBlock), 0, s, rows, n_rows, st, gate);
   return hipGetLastError();
 }
 hipError_t launch_emit(const EmitArgs& a, hipStream_t s) {

@@ -118,7 +118,23 @@ __device__ inline void spmv_sell(const int32_t* __restrict__ sptr,
     const int64_t r = s * kSell + lane;
     const int32_t p0 = sptr[s], p1 = sptr[s + 1];
     T acc = T(0);
-    for (int32_t p = p0 + lane; p < p1; p += kSell) acc += sval[p] * x[scol[p]];
+    int32_t p = p0 + lane;
+    // four entries per trip (slice widths are uniform across the wave):
+    // their loads are in flight together, the sum keeps the entry order
+    for (; p + 3 * kSell < p1; p += 4 * kSell) {
+      int32_t c[4];
+      T v[4], xv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        c[u] = scol[p + u * kSell];
+        v[u] = sval[p + u * kSell];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) xv[u] = x[c[u]];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc += v[u] * xv[u];
+    }
+    for (; p < p1; p += kSell) acc += sval[p] * x[scol[p]];
     if (r < nrows) emit(r, acc);
   }
 }
@@ -183,11 +199,49 @@ __device__ inline void k_cg_resfield_body(const CgArgs& a, int reset, VB vb) {
       const double pi = row ? a.phi[nd] : 0.0;
       const int32_t p0 = m.k_sptr[s], p1 = m.k_sptr[s + 1];
       double kx = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;
+      // four entries per trip where the slice allows (uniform across the
+      // wave): their loads are in flight together; sums in entry order
+      int32_t p = p0 + lane;
       if (!withE) {
-        for (int32_t p = p0 + lane; p < p1; p += kSell)
+        for (; p + 3 * kSell < p1; p += 4 * kSell) {
+          int32_t c[4];
+          double kv[4], xj[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            c[u] = m.k_ncol[p + u * kSell];
+            kv[u] = m.k_sval[p + u * kSell];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) xj[u] = a.phi[c[u]];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) kx += kv[u] * xj[u];
+        }
+        for (; p < p1; p += kSell)
           kx += m.k_sval[p] * a.phi[m.k_ncol[p]];
       } else if (!e32) {
-        for (int32_t p = p0 + lane; p < p1; p += kSell) {
+        for (; p + 3 * kSell < p1; p += 4 * kSell) {
+          int32_t c[4];
+          double kv[4], rx[4], ry[4], rz[4], xj[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int32_t q = p + u * kSell;
+            c[u] = m.k_ncol[q];
+            kv[u] = m.k_sval[q];
+            rx[u] = m.r_sval[q];
+            ry[u] = m.r_sval[np + q];
+            rz[u] = m.r_sval[2 * np + q];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) xj[u] = a.phi[c[u]];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            kx += kv[u] * xj[u];
+            ex += rx[u] * xj[u];
+            ey += ry[u] * xj[u];
+            ez += rz[u] * xj[u];
+          }
+        }
+        for (; p < p1; p += kSell) {
           const double xj = a.phi[m.k_ncol[p]];
           kx += m.k_sval[p] * xj;
           ex += m.r_sval[p] * xj;
@@ -195,7 +249,31 @@ __device__ inline void k_cg_resfield_body(const CgArgs& a, int reset, VB vb) {
           ez += m.r_sval[2 * np + p] * xj;
         }
       } else {
-        for (int32_t p = p0 + lane; p < p1; p += kSell) {
+        for (; p + 3 * kSell < p1; p += 4 * kSell) {
+          int32_t c[4];
+          double kv[4], xj[4];
+          float rx[4], ry[4], rz[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int32_t q = p + u * kSell;
+            c[u] = m.k_ncol[q];
+            kv[u] = m.k_sval[q];
+            rx[u] = m.r_sval32[q];
+            ry[u] = m.r_sval32[np + q];
+            rz[u] = m.r_sval32[2 * np + q];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) xj[u] = a.phi[c[u]];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            kx += kv[u] * xj[u];
+            const double d = xj[u] - pi;
+            ex += (double)rx[u] * d;
+            ey += (double)ry[u] * d;
+            ez += (double)rz[u] * d;
+          }
+        }
+        for (; p < p1; p += kSell) {
           const double xj = a.phi[m.k_ncol[p]];
           kx += m.k_sval[p] * xj;
           const double d = xj - pi;

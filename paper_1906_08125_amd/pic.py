@@ -211,8 +211,15 @@ class Mesh:
         except Exception:
             pass
 
-    def profile(self, enable: bool):
-        _check(load_library().pic_profile(self._h, 1 if enable else 0))
+    def profile(self, enable: bool = True, classes=None):
+        """Time the kernels of the named classes (KERNEL_CLASSES; all when
+        None) with HIP events on the stream; enable=False stops.  Each
+        event costs GPU time, so time only what is read."""
+        mask = 0
+        if enable:
+            mask = 0xFF if classes is None else sum(
+                1 << KERNEL_CLASSES.index(c) for c in classes)
+        _check(load_library().pic_profile(self._h, mask))
 
     def profile_read(self) -> dict:
         kt = KernelTimes()
