@@ -181,6 +181,7 @@ hipError_t iterate_graphs(pic_mesh* h, const fp::CgArgs& a0, int n, hipStream_t 
   a.charge = nullptr;
   a.rhs = nullptr;
   a.E = nullptr;
+  a.keep_field = 0;
   a.coef = a.E0 = 0.0;
   hipError_t e;
   if (!h->cap_stream &&
@@ -631,13 +632,14 @@ pic_status pic_step(pic_mesh* h, const pic_particles* P, const pic_fields* F,
     ak.step = ek.step = prm->step0 + k;
     ak.stats = ek.stats = stats + k;
     ak.gate = ek.gate = gate;
+    ek.defer = 1;  // the emission runs inside the particle kernel
     *prof0 = h->ev_class.size();
     hipError_t e;
     prof_begin(h, PIC_K_EMIT, s);
     if ((e = fp::launch_begin(ek, h->n_cu * 2, s)) != hipSuccess) return e;
     prof_end(h, s);
     prof_begin(h, PIC_K_PUSH, s);
-    if ((e = fp::launch_particles(ak, grid_push, grid_inj, s)) != hipSuccess) return e;
+    if ((e = fp::launch_particles(ak, &ek, grid_push, grid_inj, s)) != hipSuccess) return e;
     prof_end(h, s);
     prof_begin(h, PIC_K_FALLBACK, s);
     if ((e = fp::launch_fallback(ak, grid_fb, s)) != hipSuccess) return e;
@@ -672,6 +674,9 @@ pic_status pic_step(pic_mesh* h, const pic_particles* P, const pic_fields* F,
       prof_end(h, s);
     }
     ca.step_stats = st;
+    // after the first step of this call, E = R phi still holds from the
+    // previous solve (every solve ends with a field pass over its final phi)
+    ca.keep_field = k > 0 ? 1 : 0;
     const int spec = h->step_spec;
     int64_t seq = 0;
     prof_begin(h, PIC_K_SOLVE, s);
@@ -970,6 +975,7 @@ pic_status pic_batch_step(pic_batch* b, const pic_particles* P,
       ea.stats = st;
       fp::CgArgs ca = ss.ca;
       ca.step_stats = st;
+      ca.keep_field = k > 0 ? 1 : 0;  // as in pic_step
       std::memcpy(base + sa * i, &a, sa);
       std::memcpy(base + sa * n + se * i, &ea, se);
       std::memcpy(base + (sa + se) * n + sg * i, &ca, sg);

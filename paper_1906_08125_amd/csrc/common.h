@@ -392,7 +392,8 @@ struct StepScratch {
   int32_t inj_total;
   int32_t inj_fit;
   int32_t n_live;
-  int32_t pad[3];
+  int32_t emitted;  // set once the emission counts of the step are published
+  int32_t pad[2];
 };
 
 }  // namespace fp

@@ -59,6 +59,9 @@ struct EmitArgs {
   int64_t* clear;         // node charges cleared by k_begin, or null
   int64_t n_clear;
   const int32_t* gate;    // as StepArgs::gate
+  // the emission counts are computed by the first workgroup of the particle
+  // kernel (launch_particles with these arguments), not by k_begin
+  int defer;
 };
 
 struct LocateArgs {
@@ -80,8 +83,10 @@ struct DepositArgs {
 };
 
 hipError_t launch_begin(const EmitArgs& a, int grid, hipStream_t s);
-hipError_t launch_particles(const StepArgs& a, int g_push, int g_inj,
-                            hipStream_t s);
+// e: the step's emission, computed by workgroup 0 while the others push
+// (e.defer set; the injecting workgroups wait for it), or null
+hipError_t launch_particles(const StepArgs& a, const EmitArgs* e, int g_push,
+                            int g_inj, hipStream_t s);
 hipError_t launch_stats(const int64_t* rows, int n_rows, pic_step_stats* st,
                         const int32_t* gate, hipStream_t s);
 hipError_t launch_seed_build(const DevMesh& m, int grid, hipStream_t s);

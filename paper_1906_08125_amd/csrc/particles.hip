@@ -565,6 +565,12 @@ __device__ inline void begin_body(const EmitArgs& a, VB vb) {
     const int nc = (int)(sizeof(StepScratch) / sizeof(int32_t));
     if (threadIdx.x < nc) c32[threadIdx.x] = 0;
     __syncthreads();
+    if (a.defer) {
+      // the particle kernel emits; its pushing workgroups need the slot
+      // count before injection now
+      if (threadIdx.x == 0) a.scratch->inj_base = *a.n_slots;
+      return;
+    }
     emit_block<kBeginBlock>(a);
     return;
   }
@@ -794,10 +800,45 @@ __device__ inline void inject_role(const StepArgs& a, int g, int G, Acc& acc,
   }
 }
 
+// The emission of the step computed inside the particle kernel: workgroup 0
+// (dispatched first, so resident before any workgroup that waits for it)
+// computes the counts and offsets, then publishes them; the injecting
+// workgroups (dispatched last) wait for the flag.  The wait is bounded: a
+// flag not seen in time (never expected) skips the injection and marks the
+// step with a device error.
+__device__ inline void emit_publish(const EmitArgs& e) {
+  emit_block<kBlock>(e);
+  __threadfence();  // every thread's counts and offsets reach L2
+  __syncthreads();
+  if (threadIdx.x == 0)
+    __hip_atomic_store(&e.scratch->emitted, 1, __ATOMIC_RELEASE,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline bool emit_wait(const StepArgs& a) {
+  __shared__ int seen;
+  if (threadIdx.x == 0) {
+    int ok = 0;
+    for (int it = 0; it < (1 << 22); ++it) {
+      if (__hip_atomic_load(&a.scratch->emitted, __ATOMIC_ACQUIRE,
+                            __HIP_MEMORY_SCOPE_AGENT) != 0) {
+        ok = 1;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    if (!ok && a.stats) a.stats->status = PIC_E_DEVICE;
+    seen = ok;
+  }
+  __syncthreads();
+  __atomic_thread_fence(__ATOMIC_ACQUIRE);
+  return seen != 0;
+}
+
 // One instance per storage precision, so that only one push is compiled in.
+// wait: the injecting workgroups wait for the emission (see emit_wait).
 template <bool F32>
-__device__ inline void particles_body(const StepArgs& a, VB vb) {
-  if (gate_closed(a.gate)) return;
+__device__ inline void particles_body(const StepArgs& a, VB vb, bool wait) {
   Acc acc;
   acc_zero(acc);
   __shared__ ChargeTable T;
@@ -808,15 +849,26 @@ __device__ inline void particles_body(const StepArgs& a, VB vb) {
       push_role32(a, vb.id, g_push, acc, T);
     else
       push_role64(a, vb.id, g_push, acc, T);
-  } else
+  } else if (!wait || emit_wait(a)) {
     inject_role(a, vb.id - g_push, vb.n - g_push, acc, T);
+  }
   table_flush(T, a.charge);
   acc_flush(acc, a.acc_rows, vb.id, a.acc_stride);
 }
 
+// With the emission inside (e.defer), workgroup 0 only emits and the
+// particle workgroups are 1 .. gridDim.x - 1 (virtual index one less: the
+// XCD grouping of the slot spans is a fixed rotation of the hardware's).
 template <bool F32>
-__global__ void __launch_bounds__(kBlock) k_particles(StepArgs a) {
-  particles_body<F32>(a, VB{(int)blockIdx.x, (int)gridDim.x});
+__global__ void __launch_bounds__(kBlock) k_particles(StepArgs a, EmitArgs e) {
+  if (gate_closed(a.gate)) return;
+  if (!e.defer) {
+    particles_body<F32>(a, VB{(int)blockIdx.x, (int)gridDim.x}, false);
+  } else if (blockIdx.x == 0) {
+    emit_publish(e);
+  } else {
+    particles_body<F32>(a, VB{(int)blockIdx.x - 1, (int)gridDim.x - 1}, true);
+  }
 }
 
 template <bool F32>
@@ -825,7 +877,7 @@ __global__ void __launch_bounds__(kBlock) k_particles_b(const StepArgs* A,
   int i;
   const VB vb = batch_block(map, i);
   const StepArgs a = A[i];  // a private copy: no aliasing with the stores
-  particles_body<F32>(a, vb);
+  particles_body<F32>(a, vb, false);
 }
 
 // ---------------------------------------------------------------------------
@@ -1036,16 +1088,21 @@ hipError_t launch_stats_b(const StepArgs* A, const BatchMap& map, int grid,
   hipLaunchKernelGGL(k_stats_b, dim3(grid), dim3(kBlock), 0, s, A, map);
   return hipGetLastError();
 }
-hipError_t launch_particles(const StepArgs& a, int g_push, int g_inj,
-                            hipStream_t s) {
+hipError_t launch_particles(const StepArgs& a, const EmitArgs* e, int g_push,
+                            int g_inj, hipStream_t s) {
   StepArgs b = a;
   b.g_push = g_push;
+  EmitArgs ee;
+  if (e) {
+    ee = *e;
+  } else {
+    ee = EmitArgs{};
+  }
+  const int grid = g_push + g_inj + (ee.defer ? 1 : 0);
   if (a.f32)
-    hipLaunchKernelGGL(k_particles<true>, dim3(g_push + g_inj), dim3(kBlock), 0,
-                       s, b);
+    hipLaunchKernelGGL(k_particles<true>, dim3(grid), dim3(kBlock), 0, s, b, ee);
   else
-    hipLaunchKernelGGL(k_particles<false>, dim3(g_push + g_inj), dim3(kBlock),
-                       0, s, b);
+    hipLaunchKernelGGL(k_particles<false>, dim3(grid), dim3(kBlock), 0, s, b, ee);
   return hipGetLastError();
 }
 hipError_t launch_seed_build(const DevMesh& m, int grid, hipStream_t s) {

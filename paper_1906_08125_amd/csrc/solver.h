@@ -60,6 +60,10 @@ struct CgArgs {
   float *r32, *u32, *w32, *p32, *s32;  // [n_free]
   double* part;           // [kCgSlots][G]
   int G;                  // workgroups of every solver kernel
+  // E already equals R phi for the incoming phi (the previous solve of the
+  // same fields ended with it and nothing has changed phi since): the first
+  // pass of the solve computes the residual only
+  int keep_field;
   CgCtrl* ctrl;
   CgReport* report;       // host-mapped report record (device address)
   const int32_t* dir_nodes;

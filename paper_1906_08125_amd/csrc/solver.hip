@@ -186,7 +186,7 @@ __device__ inline void k_cg_resfield_body(const CgArgs& a, int reset, VB vb) {
   const int lane = threadIdx.x & (kSell - 1);
   const int sub = threadIdx.x / kSell;
   const int nsub = blockDim.x / kSell;
-  const bool withE = a.E != nullptr;
+  const bool withE = a.E != nullptr && !(reset && a.keep_field);
   const bool e32 = a.e32 != 0;
   const int64_t np = m.k_np;
   double v[2] = {0.0, 0.0};
