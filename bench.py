@@ -151,6 +151,26 @@ def run_gpu(args):
     cold = gm.solve_stats(st)
     cold_ms = e0.elapsed_time(e1)
     log(f"cold solve {cold} {cold_ms:.2f} ms")
+    # the same cold solve preconditioned by AMG: the first call builds the
+    # hierarchy (host setup, timed apart), the second is timed
+    phi.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gm.poisson_solve(None, 0.0, cfg.E0, phi, E, tol=cfg.tol,
+                     precond=pic.PIC_PRECOND_AMG)
+    torch.cuda.synchronize()
+    amg_setup_ms = 1e3 * (time.perf_counter() - t0)
+    phi.zero_()
+    torch.cuda.synchronize()
+    e0.record()
+    st = gm.poisson_solve(None, 0.0, cfg.E0, phi, E, tol=cfg.tol,
+                          precond=pic.PIC_PRECOND_AMG)
+    e1.record()
+    torch.cuda.synchronize()
+    cold_amg = gm.solve_stats(st)
+    cold_amg_ms = e0.elapsed_time(e1)
+    log(f"cold solve (AMG) {cold_amg} {cold_amg_ms:.2f} ms, "
+        f"first call with setup {amg_setup_ms:.1f} ms")
     rate, _ = gm.emission_rate(E, cfg.phi_w)
     rate = rate.item()
     w_sp = rate * cfg.dt * cfg.transit_steps / cfg.n_target
@@ -238,7 +258,11 @@ def run_gpu(args):
         cg_iters_per_step=sum(r["cg_iters"] for r in rows) / len(rows),
         cold_solve=dict(iters=cold["iters"], ms=round(cold_ms, 3),
                         iters_per_s=round(cold["iters"] / cold_ms * 1e3, 1),
-                        relres=cold["relres"]),
+                        relres=cold["relres"], precond="jacobi"),
+        cold_solve_amg=dict(iters=cold_amg["iters"], ms=round(cold_amg_ms, 3),
+                            relres=cold_amg["relres"],
+                            first_call_with_setup_ms=round(amg_setup_ms, 1),
+                            speedup_vs_jacobi=round(cold_ms / cold_amg_ms, 2)),
         kernels=kernels,
         mixed=mixed,
         adjoint=adjoint,
@@ -254,10 +278,11 @@ def run_gpu(args):
 def run_adjoint_leg(gm, cfg, rate, args):
     """Adjoint window on the production mesh: mixed precision (FP32
     particles and field, FP64-refined forward solves, FP64 transposed
-    solves), about
-    2e5 live superparticles after 100 warm-up steps, a window of 20 steps
-    with per-step checkpoints; the backward recomputes every step from its
-    checkpoint.  Reports forward and backward wall time on the device."""
+    solves preconditioned as --adjoint-precond says), about 2e5 live
+    superparticles after 100 warm-up steps, a window of 20 steps with
+    per-step checkpoints; the backward recomputes every step from its
+    checkpoint.  Reports forward and backward wall time on the device (the
+    second of two passes: the first also builds the AMG hierarchy)."""
     import torch
 
     from paper_1906_08125_amd import pic
@@ -273,8 +298,11 @@ def run_adjoint_leg(gm, cfg, rate, args):
     torch.cuda.synchronize()
     live = int((gs.tet[: int(gs.n_slots.item())] >= 0).sum().item())
     T = args.adjoint_steps
+    precond = pic.PIC_PRECOND_AMG if args.adjoint_precond == "amg" \
+        else pic.PIC_PRECOND_JACOBI
     win = pic.Window(gm, gs, T=T, step0=warm, dt=cfg.dt, w_sp=w_sp,
-                     phi_w=cfg.phi_w, seed=cfg.seed, tol=cfg.tol)
+                     phi_w=cfg.phi_w, seed=cfg.seed, tol=cfg.tol,
+                     adjoint_precond=precond)
     s = torch.ones(gm.n_emit, dtype=torch.float64, device="cuda")
     times = []
     for rep in range(2):  # the first pass warms the allocator
@@ -291,7 +319,7 @@ def run_adjoint_leg(gm, cfg, rate, args):
     recs = [pic.Mesh.solve_stats(win.adjoint_solve_stats[6 * j: 6 * j + 6])
             for j in range(T + 1)]
     return dict(window_steps=T, live_particles=live, precision="mixed",
-                adjoint_solves="fp64",
+                adjoint_solves="fp64", adjoint_precond=args.adjoint_precond,
                 adjoint_cg_iters=[r["iters"] for r in recs],
                 fwd_ms=round(1e3 * fwd, 3), bwd_ms=round(1e3 * bwd, 3),
                 adjoint_over_fwd=round(bwd / fwd, 4),
@@ -438,6 +466,9 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint window leg")
     ap.add_argument("--adjoint-steps", type=int, default=20)
+    ap.add_argument("--adjoint-precond", choices=("amg", "jacobi"),
+                    default="amg",
+                    help="preconditioner of the adjoint's transposed solves")
     ap.add_argument("--batch-instances", type=int, default=32,
                     help="instances of the batched leg (0: skip it)")
     ap.add_argument("--batch-warmup", type=int, default=30)

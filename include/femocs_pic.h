@@ -130,7 +130,7 @@ PIC_API pic_status deposit(const pic_mesh* mesh, int64_t n, const double* x,
 /* ------------------------------------------------------------------------ */
 /* Poisson solve (Eq. poisson with Eq. poisson_bc, Galerkin form of App. B) */
 /* K phi_f = b_f on free nodes, b_i = (-e/eps0) w_sp c_i 2^-40 + E0 g_i,    */
-/* Jacobi-preconditioned CG (the paper only says "iteratively"), warm       */
+/* preconditioned CG (the paper only says "iteratively"; params->precond),  */
 /* started from phi, stopped when ||b - K phi||_2 <= tol ||b||_2 (checked   */
 /* on the true residual).  phi: device [n_nodes] f64 (in: guess, out:       */
 /* solution, 0 on Dirichlet nodes).  charge: device [n_nodes] or NULL.      */
@@ -146,11 +146,22 @@ PIC_API pic_status deposit(const pic_mesh* mesh, int64_t n, const double* x,
 /* (iterative refinement) until tol holds on the true residual.             */
 /* inner_tol must lie in [1e-7, 0.5] for PIC_MIXED (ignored for PIC_FP64).   */
 /* ------------------------------------------------------------------------ */
+/* precond (not in the paper, which names no preconditioner):              */
+/*   PIC_PRECOND_JACOBI  diagonal scaling (default);                        */
+/*   PIC_PRECOND_AMG     one V(1,1)-cycle of smoothed-aggregation algebraic */
+/*                       multigrid (Jacobi smoothing, dense coarsest solve) */
+/*                       per iteration; PIC_FP64 only.  The hierarchy is    */
+/*                       built on the host from the mesh's K on the first   */
+/*                       solve that asks for it (seconds at 5e5 unknowns)   */
+/*                       and kept with the mesh.                            */
+enum { PIC_PRECOND_JACOBI = 0, PIC_PRECOND_AMG = 1 };
 typedef struct {
   double tol;        /* relative residual target                         */
   double inner_tol;  /* mixed precision: FP32 inner solve target          */
   int32_t max_iter;  /* iteration cap (PIC_E_NOCONV in stats beyond it)   */
   int32_t precision; /* PIC_FP64 or PIC_MIXED (FP32 inner CG + FP64 IR)   */
+  int32_t precond;   /* PIC_PRECOND_JACOBI or PIC_PRECOND_AMG             */
+  int32_t pad;
 } pic_solve_params;
 
 typedef struct {

@@ -15,8 +15,8 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfemocs_pic.so")
-SOURCES = ["mesh.hip", "solver.hip", "particles.hip", "sort.hip", "adjoint.hip",
-           "api.hip"]
+SOURCES = ["mesh.hip", "solver.hip", "amg.hip", "particles.hip", "sort.hip",
+           "adjoint.hip", "api.hip"]
 ARCH = os.environ.get("FEMOCS_PIC_ARCH", "gfx950")
 
 

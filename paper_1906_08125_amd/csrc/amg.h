@@ -1,0 +1,64 @@
+// Smoothed-aggregation algebraic multigrid as a CG preconditioner for the
+// FP64 solve (an alternative to Jacobi; the paper names no preconditioner).
+#pragma once
+#include "common.h"
+#include "solver.h"
+
+namespace fp {
+
+constexpr int kAmgMaxLevels = 8;
+constexpr int kAmgCoarseMax = 512;  // the coarsest operator is inverted densely
+
+// A sparse matrix of the hierarchy.  lpr = 1: the sliced ELLPACK layout of
+// the solver (kSell rows per slice, column-major inside a slice, padding
+// entries 0 with column 0; one lane per row), for short rows.  lpr > 1
+// (a power of two up to 64): CSR with lpr lanes per row and a shuffle
+// reduction, for the long rows of the Galerkin operators and restrictions.
+struct SellMat {
+  int64_t nrows, nslices;  // (nslices: SELL only)
+  int lpr;
+  const int32_t* sptr;     // SELL slice offsets, or CSR row offsets [nrows+1]
+  const int32_t* col;
+  const double* val;
+};
+
+// One level of the hierarchy.  Level 0 is K on the free nodes; b of level 0
+// is the CG residual and its smoothed output is the CG vector u.
+struct AmgLevel {
+  SellMat A;
+  const double* invdiag;
+  double omega;   // Jacobi weight 4 / (3 lambda_max(D^-1 A))
+  SellMat P;      // prolongation from the next level (rows: this level)
+  SellMat R;      // restriction P^T (rows: the next level)
+  double* b;      // right-hand side (levels > 0)
+  double* x;      // pre-smoothed iterate, then corrected
+  double* r;      // residual after pre-smoothing
+  double* t;      // post-smoothed iterate (levels > 0)
+};
+
+struct AmgDev {
+  int n_levels;   // levels with a smoother; the dense coarsest level follows
+  AmgLevel lv[kAmgMaxLevels];
+  int64_t n_coarse;
+  const double* coarse_inv;  // [n_coarse][n_coarse] inverse, row-major
+  double* coarse_b;
+  double* coarse_x;
+  int64_t rows[kAmgMaxLevels + 1];  // rows per level (the coarsest last)
+};
+
+// Builds the hierarchy of the FP64 stiffness of m on the host (strength of
+// connection, three-phase aggregation, Jacobi-smoothed prolongation,
+// Galerkin products, dense inverse of the coarsest operator) and uploads it
+// with alloc().  Returns hipSuccess and fills d, or an error.
+hipError_t amg_build(const DevMesh& m, hipStream_t s,
+                     void* (*alloc)(void* ctx, size_t bytes), void* ctx,
+                     AmgDev& d, std::string& msg);
+
+// n iterations of CG preconditioned by one V(1,1)-cycle, in the
+// Chronopoulos-Gear ordering [V-cycle, w = K u, update], numbered by the
+// device counters of the control word; no report.  The first V-cycle
+// kernel of every iteration after the first tests the recursive residual.
+hipError_t amg_launch_iters(const CgArgs& a, const AmgDev& d, int n,
+                            hipStream_t s);
+
+}  // namespace fp

@@ -201,7 +201,9 @@ hipError_t iterate_graphs(pic_mesh* h, const fp::CgArgs& a0, int n, hipStream_t 
         hipGraph_t graph = nullptr;
         if ((e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
           return e;
-        const hipError_t le = fp::cg_launch_iters_dev(a, cnt, h->cap_stream);
+        const hipError_t le =
+            a.amg ? fp::amg_launch_iters(a, *(const fp::AmgDev*)a.amg, cnt, h->cap_stream)
+                  : fp::cg_launch_iters_dev(a, cnt, h->cap_stream);
         if ((e = hipStreamEndCapture(h->cap_stream, &graph)) != hipSuccess) return e;
         if (le != hipSuccess) {
           (void)hipGraphDestroy(graph);
@@ -273,7 +275,8 @@ hipError_t solve_finish(pic_mesh* h, const fp::CgArgs& a, int spec,
       if ((e = fp::cg_launch_recheck(a, seq, s)) != hipSuccess) return e;
       batch = 16;
     } else {
-      batch = batch < 8 ? 8 : std::min(2 * batch, 256);
+      // (an AMG iteration is some fifteen launches and needs few rounds)
+      batch = batch < 8 ? 8 : std::min(2 * batch, a.amg ? 32 : 256);
       if ((e = iterate_graphs(h, a, batch, s)) != hipSuccess ||
           (e = fp::cg_launch_report(a, seq, s)) != hipSuccess)
         return e;
@@ -304,6 +307,34 @@ pic_status check_solve(const pic_solve_params* p) {
   if (p->precision == PIC_MIXED &&
       !(p->inner_tol >= 1e-7 && p->inner_tol <= 0.5))
     return fail(PIC_E_ARG, "solve params: inner_tol must be in [1e-7, 0.5]");
+  if (p->precond != PIC_PRECOND_JACOBI && p->precond != PIC_PRECOND_AMG)
+    return fail(PIC_E_ARG, "solve params: unknown preconditioner");
+  if (p->precond == PIC_PRECOND_AMG && p->precision != PIC_FP64)
+    return fail(PIC_E_ARG, "solve params: the AMG preconditioner is FP64 only");
+  return PIC_OK;
+}
+
+void* amg_alloc(void* ctx, size_t bytes) {
+  hipError_t err = hipSuccess;
+  void* p = fp::dev_alloc((pic_mesh*)ctx, bytes, err);
+  return err == hipSuccess ? p : nullptr;
+}
+
+// Points a.amg at the handle's hierarchy when the parameters ask for AMG,
+// building it on first use.
+pic_status use_precond(pic_mesh* h, const pic_solve_params* p, fp::CgArgs& a,
+                       hipStream_t s, const char* who) {
+  a.amg = nullptr;
+  if (p->precond != PIC_PRECOND_AMG) return PIC_OK;
+  if (!h->amg_ready) {
+    std::string msg;
+    const hipError_t e = fp::amg_build(h->dm, s, amg_alloc, h, h->amg, msg);
+    if (e != hipSuccess)
+      return fail(PIC_E_DEVICE, std::string(who) + ": " +
+                                    (msg.empty() ? hipGetErrorString(e) : msg));
+    h->amg_ready = true;
+  }
+  a.amg = &h->amg;
   return PIC_OK;
 }
 
@@ -575,6 +606,8 @@ pic_status poisson_solve(const pic_mesh* h, const int64_t* charge,
                          params->precision == PIC_MIXED, params);
   a.stats = stats;
   pic_mesh* hm = const_cast<pic_mesh*>(h);
+  if ((ps = use_precond(hm, params, a, (hipStream_t)stream, "poisson_solve")) != PIC_OK)
+    return ps;
   prof_begin(hm, PIC_K_SOLVE, (hipStream_t)stream);
   hipError_t e = run_solve(hm, a, 0, (hipStream_t)stream, nullptr);
   if (e != hipSuccess) return hip_fail(e, "poisson_solve");
@@ -616,6 +649,7 @@ pic_status pic_step(pic_mesh* h, const pic_particles* P, const pic_fields* F,
   if (e != hipSuccess) return hip_fail(e, "pic_step");
 
   StepSet ss = step_set(h, P, F, prm, h->grid_push, h->grid_inj, h->grid_fb);
+  if ((ps = use_precond(h, &prm->solve, ss.ca, s, "pic_step")) != PIC_OK) return ps;
   const fp::StepArgs& a = ss.a;
   const fp::EmitArgs& ea = ss.ea;
   fp::CgArgs& ca = ss.ca;
@@ -810,6 +844,10 @@ pic_status adjoint_step(pic_mesh* h, const pic_particles* pre,
   hipError_t e = fp::adj_launch_pre_solve(a, s);
   if (e != hipSuccess) return hip_fail(e, "adjoint_step");
   fp::CgArgs ca = cg_args(h, nullptr, 0.0, 0.0, adj->mu, nullptr, false, &prm->solve);
+  {
+    const pic_status pq = use_precond(h, &prm->solve, ca, s, "adjoint_step");
+    if (pq != PIC_OK) return pq;
+  }
   ca.rhs = a.rhs;
   ca.bref = adj->bref;
   ca.stats = stats;
@@ -927,6 +965,8 @@ pic_status pic_batch_step(pic_batch* b, const pic_particles* P,
     if (ps != PIC_OK) return ps;
     if ((P[i].precision == PIC_MIXED) != f32)
       return fail(PIC_E_ARG, "pic_batch_step: instances differ in precision");
+    if (prm[i].solve.precond != PIC_PRECOND_JACOBI)
+      return fail(PIC_E_ARG, "pic_batch_step: batched solves use the Jacobi preconditioner");
     c_push[i] = round8(std::max(sc->push_blocks[i], 8));
     c_inj[i] = round8(std::max(sc->inject_blocks[i], 8));
     c_cg[i] = round8(std::max(sc->cg_blocks[i], 8));

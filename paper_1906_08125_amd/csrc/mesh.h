@@ -3,6 +3,7 @@
 #include <string>
 #include <vector>
 
+#include "amg.h"
 #include "common.h"
 #include "solver.h"
 
@@ -49,6 +50,9 @@ struct pic_mesh {
   };
   std::vector<IterGraph> graphs;
   hipStream_t cap_stream = nullptr;    // private stream used only to capture
+  // AMG hierarchy of K (built on the first solve that asks for it)
+  fp::AmgDev amg{};
+  bool amg_ready = false;
   // host copies of the emitting faces
   std::vector<int32_t> h_e_tet, h_e_nodes;
   std::vector<double> h_e_area;

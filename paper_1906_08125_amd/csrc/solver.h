@@ -65,6 +65,9 @@ struct CgArgs {
   // pass of the solve computes the residual only
   int keep_field;
   CgCtrl* ctrl;
+  // host address of the AMG hierarchy (AmgDev) when the solve is
+  // preconditioned by it, else null (Jacobi); FP64 only
+  const void* amg;
   CgReport* report;       // host-mapped report record (device address)
   const int32_t* dir_nodes;
   int64_t n_dir;

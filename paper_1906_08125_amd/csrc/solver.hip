@@ -31,6 +31,7 @@
 // into contiguous blocks per workgroup, grouped so that each of the 8 XCDs
 // (workgroup g runs on XCD g mod 8) sweeps one contiguous eighth of the
 // matrix, which keeps neighbour gathers in one L2.
+#include "amg.h"
 #include "common.h"
 #include "solver.h"
 
@@ -421,6 +422,7 @@ __device__ inline void k_cg_start_body(const CgArgs& a, int64_t seq, VB vb) {
     }
   }
   if (done || noconv) return;
+  if (a.amg) return;  // its iterations start with the V-cycle
   const DevMesh& m = a.m;
   double v[2] = {0.0, 0.0};
   if (a.mixed) {
@@ -627,6 +629,243 @@ __global__ void k_cg_report_b(CgBatch b, int n, int64_t seq) {
   const CgArgs& a = b.args[i];
   __threadfence_system();
   report(a.ctrl, a.report, seq, a.ctrl->state);
+}
+
+// ---------------------------------------------------------------------------
+// CG preconditioned by one smoothed-aggregation V(1,1)-cycle (FP64).  Each
+// iteration is [V-cycle u = M r, w = K u, update], the Chronopoulos-Gear
+// recurrences being the same for any symmetric positive definite M.
+// Partial-sum slots of parity p = it & 1: 4 + 2p (r,r) from the update,
+// 5 + 2p (r,u) from the last V-cycle kernel, 8 + p (w,u) from the product.
+// Counters: the V-cycle and the product read it_a, the product copies it to
+// it_b, the update reads it_b and sets it_a = it_b + 1.  The first V-cycle
+// kernel of every iteration after the first applies the stopping test to
+// the recursive residual.  Every kernel returns at once unless the state is
+// ITER.
+// ---------------------------------------------------------------------------
+namespace {
+
+// emit(r, sum_j val_rj g(col_rj)) for every row r of M in this workgroup's
+// share.  SELL (lpr = 1): one lane per row, entries in order, four loads in
+// flight per trip.  CSR (lpr > 1): lpr lanes per row, each summing every
+// lpr-th entry, then a fixed shuffle tree; every group of a workgroup makes
+// the same number of trips, so the shuffles run on whole waves.
+template <typename Gf, typename Ef>
+__device__ inline void amg_rows(const SellMat& M, VB vb, Gf&& g, Ef&& emit) {
+  if (M.lpr == 1) {
+    const Range sl = my_range(M.nslices, vb);
+    const int lane = threadIdx.x & (kSell - 1);
+    for (int64_t s = sl.lo + threadIdx.x / kSell; s < sl.hi;
+         s += blockDim.x / kSell) {
+      const int32_t p1 = M.sptr[s + 1];
+      int32_t p = M.sptr[s] + lane;
+      double acc = 0.0;
+      for (; p + 3 * kSell < p1; p += 4 * kSell) {
+        int32_t c[4];
+        double v[4], xv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          c[u] = M.col[p + u * kSell];
+          v[u] = M.val[p + u * kSell];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) xv[u] = g(c[u]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc += v[u] * xv[u];
+      }
+      for (; p < p1; p += kSell) acc += M.val[p] * g(M.col[p]);
+      const int64_t r = s * kSell + lane;
+      if (r < M.nrows) emit(r, acc);
+    }
+    return;
+  }
+  const int lpr = M.lpr;
+  const Range rows = my_range(M.nrows, vb);
+  const int sub = threadIdx.x & (lpr - 1);
+  const int grp = threadIdx.x / lpr, ngrp = blockDim.x / lpr;
+  for (int64_t r0 = rows.lo; r0 < rows.hi; r0 += ngrp) {
+    const int64_t r = r0 + grp;
+    double acc = 0.0;
+    if (r < rows.hi)
+      for (int32_t p = M.sptr[r] + sub; p < M.sptr[r + 1]; p += lpr)
+        acc += M.val[p] * g(M.col[p]);
+    for (int off = lpr >> 1; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, lpr);
+    if (r < rows.hi && sub == 0) emit(r, acc);
+  }
+}
+
+// The stopping test on the recursive residual of the previous update
+// (iterations after the first of a (re)start); true when the solve leaves
+// the iteration (every workgroup decides alike).
+__device__ inline bool amg_stop(const CgArgs& a, VB vb) {
+  CgCtrl* c = a.ctrl;
+  const int it = c->it_a;
+  if (it == 0) return false;
+  double t[1];
+  totals<1>(slot(a, 4 + 2 * ((it - 1) & 1)), a.G, 1, t);
+  const double rn = sqrt(t[0]);
+  const double bn = sqrt(c->bb);
+  const double thr = a.tol * (a.bref ? fmax(bn, *a.bref) : bn);
+  if (rn <= thr || c->iters + it >= a.max_iter) {
+    if (vb.id == 0 && threadIdx.x == 0) {
+      c->state = CG_RECHECK;
+      c->iters_final = c->iters + it;
+    }
+    return true;
+  }
+  return false;
+}
+
+}  // namespace
+
+// Pre-smoothing from zero and the residual: x = w D^-1 b,
+// r = b - A x = b - w sum_j a_ij d_j^-1 b_j.
+__global__ void __launch_bounds__(kCgBlock) k_amg_down(CgArgs a, AmgLevel L,
+                                                       int level) {
+  if (a.ctrl->state != CG_ITER) return;
+  const VB vb{(int)blockIdx.x, (int)gridDim.x};
+  if (level == 0 && amg_stop(a, vb)) return;
+  const double* __restrict__ b = level == 0 ? a.r : L.b;
+  const double* __restrict__ dinv = L.invdiag;
+  amg_rows(L.A, vb, [&](int32_t c) { return b[c] * dinv[c]; },
+           [&](int64_t r, double ax) {
+             const double br = b[r];
+             L.x[r] = L.omega * (dinv[r] * br);
+             L.r[r] = br - L.omega * ax;
+           });
+}
+
+// y = M x for the rows of M (restriction and prolongation; add: y += M x).
+__global__ void __launch_bounds__(kCgBlock) k_amg_apply(CgArgs a, SellMat M,
+                                                        const double* x,
+                                                        double* y, int add) {
+  if (a.ctrl->state != CG_ITER) return;
+  const VB vb{(int)blockIdx.x, (int)gridDim.x};
+  amg_rows(M, vb, [&](int32_t c) { return x[c]; },
+           [&](int64_t r, double v) { y[r] = add ? y[r] + v : v; });
+}
+
+// Coarsest level: x = A^-1 b with the dense inverse, one wave per row.
+__global__ void __launch_bounds__(kCgBlock) k_amg_coarse(CgArgs a, int64_t n,
+                                                         const double* inv,
+                                                         const double* b,
+                                                         double* x) {
+  if (a.ctrl->state != CG_ITER) return;
+  const VB vb{(int)blockIdx.x, (int)gridDim.x};
+  const Range rows = my_range(n, vb);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int64_t i0 = rows.lo; i0 < rows.hi; i0 += blockDim.x >> 6) {
+    const int64_t i = i0 + wave;
+    double s = 0.0;
+    if (i < rows.hi)
+      for (int64_t j = lane; j < n; j += 64) s += inv[i * n + j] * b[j];
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (i < rows.hi && lane == 0) x[i] = s;
+  }
+}
+
+// Post-smoothing: out = x + w D^-1 (b - A x); on level 0 out is u and the
+// workgroups write their share of (r,u).
+__global__ void __launch_bounds__(kCgBlock) k_amg_post(CgArgs a, AmgLevel L,
+                                                       int level) {
+  if (a.ctrl->state != CG_ITER) return;
+  const VB vb{(int)blockIdx.x, (int)gridDim.x};
+  const double* __restrict__ b = level == 0 ? a.r : L.b;
+  double* out = level == 0 ? a.u : L.t;
+  const double* __restrict__ x = L.x;
+  double v[1] = {0.0};
+  amg_rows(L.A, vb, [&](int32_t c) { return x[c]; },
+           [&](int64_t r, double ax) {
+             const double br = b[r];
+             const double o = x[r] + L.omega * (L.invdiag[r] * (br - ax));
+             out[r] = o;
+             v[0] += br * o;
+           });
+  if (level == 0) write_partials<1>(slot(a, 5 + 2 * (a.ctrl->it_a & 1)), a.G, v, vb);
+}
+
+// w = K u and (w,u); it_b = it_a.
+__global__ void __launch_bounds__(kCgBlock) k_amg_spmv(CgArgs a) {
+  CgCtrl* c = a.ctrl;
+  if (c->state != CG_ITER) return;
+  const VB vb{(int)blockIdx.x, (int)gridDim.x};
+  const int it = c->it_a;
+  if (vb.id == 0 && threadIdx.x == 0) c->it_b = it;
+  const DevMesh& m = a.m;
+  double v[1] = {0.0};
+  spmv_sell(m.k_sptr, m.k_scol, m.k_sval, a.u, m.k_nslices, m.n_free, vb,
+            [&](int64_t i, double s) {
+              a.w[i] = s;
+              v[0] += s * a.u[i];
+            });
+  write_partials<1>(slot(a, 8 + (it & 1)), a.G, v, vb);
+}
+
+// Scalars of iteration it from (r,u) and (w,u), then p, s, x, r and (r,r);
+// it_a = it + 1.
+__global__ void __launch_bounds__(kCgBlock) k_amg_upd(CgArgs a) {
+  CgCtrl* c = a.ctrl;
+  if (c->state != CG_ITER) return;
+  const VB vb{(int)blockIdx.x, (int)gridDim.x};
+  const int it = c->it_b;
+  const int pb = it & 1;
+  double t1[1], t2[1];
+  totals<1>(slot(a, 5 + 2 * pb), a.G, 1, t1);
+  totals<1>(slot(a, 8 + pb), a.G, 1, t2);
+  const double gamma = t1[0];
+  double alpha, beta;
+  if (it == 0) {
+    beta = 0.0;
+    alpha = gamma / t2[0];
+  } else {
+    beta = gamma / c->gamma[pb ^ 1];
+    alpha = gamma / (t2[0] - beta * gamma / c->alpha[pb ^ 1]);
+  }
+  if (vb.id == 0 && threadIdx.x == 0) {
+    c->gamma[pb] = gamma;
+    c->alpha[pb] = alpha;
+    c->it_a = it + 1;
+  }
+  const Range rows = my_range(a.m.n_free, vb);
+  double v[1] = {0.0};
+  for (int64_t i = rows.lo + threadIdx.x; i < rows.hi; i += blockDim.x) {
+    const double pi = it == 0 ? a.u[i] : a.u[i] + beta * a.p[i];
+    const double si = it == 0 ? a.w[i] : a.w[i] + beta * a.s[i];
+    a.p[i] = pi;
+    a.s[i] = si;
+    a.x[i] += alpha * pi;
+    const double ri = a.r[i] - alpha * si;
+    a.r[i] = ri;
+    v[0] += ri * ri;
+  }
+  write_partials<1>(slot(a, 4 + 2 * pb), a.G, v, vb);
+}
+
+hipError_t amg_launch_iters(const CgArgs& a, const AmgDev& d, int n,
+                            hipStream_t s) {
+  const dim3 g(a.G), b(kCgBlock);
+  const int L = d.n_levels;
+  for (int k = 0; k < n; ++k) {
+    for (int l = 0; l < L; ++l) {
+      const AmgLevel& lv = d.lv[l];
+      hipLaunchKernelGGL(k_amg_down, g, b, 0, s, a, lv, l);
+      double* nb = l + 1 < L ? d.lv[l + 1].b : d.coarse_b;
+      hipLaunchKernelGGL(k_amg_apply, g, b, 0, s, a, lv.R, (const double*)lv.r, nb, 0);
+    }
+    hipLaunchKernelGGL(k_amg_coarse, g, b, 0, s, a, d.n_coarse, d.coarse_inv,
+                       (const double*)d.coarse_b, d.coarse_x);
+    for (int l = L - 1; l >= 0; --l) {
+      const AmgLevel& lv = d.lv[l];
+      const double* y = l + 1 < L ? d.lv[l + 1].t : d.coarse_x;
+      hipLaunchKernelGGL(k_amg_apply, g, b, 0, s, a, lv.P, y, lv.x, 1);
+      hipLaunchKernelGGL(k_amg_post, g, b, 0, s, a, lv, l);
+    }
+    hipLaunchKernelGGL(k_amg_spmv, g, b, 0, s, a);
+    hipLaunchKernelGGL(k_amg_upd, g, b, 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 #define LAUNCH(kern, ...)                                                   \

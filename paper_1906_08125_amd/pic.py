@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libfemocs_pic.so")
 PIC_OK, PIC_E_ARG, PIC_E_DEVICE, PIC_E_MESH = 0, -1, -2, -3
 PIC_E_NOCONV, PIC_E_CAPACITY, PIC_E_NUMERIC = -4, -5, -6
 PIC_FP64, PIC_MIXED = 0, 1
+PIC_PRECOND_JACOBI, PIC_PRECOND_AMG = 0, 1
 CHARGE_SCALE = float(2 ** 40)
 
 
@@ -41,7 +42,8 @@ class MeshInfo(C.Structure):
 
 class SolveParams(C.Structure):
     _fields_ = [("tol", C.c_double), ("inner_tol", C.c_double),
-                ("max_iter", C.c_int32), ("precision", C.c_int32)]
+                ("max_iter", C.c_int32), ("precision", C.c_int32),
+                ("precond", C.c_int32), ("pad", C.c_int32)]
 
 
 class SolveStats(C.Structure):
@@ -251,10 +253,11 @@ class Mesh:
                                       _ptr(charge), _stream(torch)))
 
     def poisson_solve(self, charge, w_sp, E0, phi, E=None, tol=1e-12,
-                      max_iter=20000, precision=PIC_FP64, inner_tol=1e-4):
+                      max_iter=20000, precision=PIC_FP64, inner_tol=1e-4,
+                      precond=PIC_PRECOND_JACOBI):
         torch = _torch()
         st = torch.zeros(6, dtype=torch.float64, device=phi.device)
-        prm = SolveParams(tol, inner_tol, max_iter, precision)
+        prm = SolveParams(tol, inner_tol, max_iter, precision, precond)
         _check(load_library().poisson_solve(
             self._h, _ptr(charge), float(w_sp), float(E0), _ptr(phi), _ptr(E),
             C.byref(prm), _ptr(st), _stream(torch)))
@@ -284,9 +287,10 @@ class State:
 
     def __init__(self, mesh: Mesh, capacity: int, precision: int = PIC_FP64,
                  device="cuda", solve_precision: int | None = None,
-                 inner_tol: float = 1e-4):
+                 inner_tol: float = 1e-4, precond: int = PIC_PRECOND_JACOBI):
         """precision: PIC_FP64, or PIC_MIXED for FP32 particles and field;
-        solve_precision (default: precision) picks the Poisson solver."""
+        solve_precision (default: precision) picks the Poisson solver;
+        precond its preconditioner (PIC_PRECOND_AMG: FP64 solves only)."""
         torch = _torch()
         self.mesh = mesh
         self.capacity = int(capacity)
@@ -294,6 +298,7 @@ class State:
         self.solve_precision = (precision if solve_precision is None
                                 else solve_precision)
         self.inner_tol = inner_tol
+        self.precond = precond
         rd = torch.float64 if precision == PIC_FP64 else torch.float32
         n = self.capacity
         mk = lambda dt: torch.zeros(n, dtype=dt, device=device)
@@ -317,9 +322,10 @@ class State:
 
     def init_field(self, E0, tol=1e-12, max_iter=20000):
         """phi and E of the empty gap (the field type follows precision)."""
-        st = self.mesh.poisson_solve(None, 0.0, E0, self.phi, self.E, tol,
-                                     max_iter, precision=self.precision,
-                                     inner_tol=self.inner_tol)
+        st = self.mesh.poisson_solve(
+            None, 0.0, E0, self.phi, self.E, tol, max_iter,
+            precision=self.precision, inner_tol=self.inner_tol,
+            precond=self.precond if self.precision == PIC_FP64 else PIC_PRECOND_JACOBI)
         return st
 
     def step(self, *, dt, E0, w_sp, phi_w, step0, seed, n_steps=1, instance=0,
@@ -333,7 +339,7 @@ class State:
                          None if s_face is None else s_face.data_ptr(),
                          resort_every, 0,
                          SolveParams(tol, self.inner_tol, max_iter,
-                                     self.solve_precision))
+                                     self.solve_precision, self.precond))
         _check(load_library().pic_step(self.mesh.handle, C.byref(self._p),
                                        C.byref(self._f), C.byref(prm),
                                        int(n_steps), _ptr(stats),
@@ -399,12 +405,14 @@ class Window:
 
     def __init__(self, mesh: Mesh, state: "State", T: int, step0: int, *,
                  dt, w_sp, phi_w, seed, j_scale=1.0, instance=0, tol=1e-10,
-                 max_iter=20000, adjoint_solve_precision=PIC_FP64):
+                 max_iter=20000, adjoint_solve_precision=PIC_FP64,
+                 adjoint_precond=PIC_PRECOND_JACOBI):
         """adjoint_solve_precision: the transposed solves (FP64 by default:
         on a cold right-hand side the FP32 recursion with FP64 refinement
         needs more iterations than it saves per iteration)."""
         torch = _torch()
         self.adj_precision = adjoint_solve_precision
+        self.adj_precond = adjoint_precond
         self.mesh, self.state, self.T, self.step0 = mesh, state, int(T), int(step0)
         self.kw = dict(dt=dt, w_sp=w_sp, phi_w=phi_w, seed=seed,
                        j_scale=j_scale, instance=instance, tol=tol,
@@ -422,7 +430,8 @@ class Window:
         return StepParams(k["dt"], E0, k["w_sp"], k["phi_w"], k["j_scale"],
                           k["seed"], step0, k["instance"], s.data_ptr(), 0, 0,
                           SolveParams(k["tol"], self.state.inner_tol,
-                                      k["max_iter"], self.adj_precision))
+                                      k["max_iter"], self.adj_precision,
+                                      self.adj_precond))
 
     def _initial_field(self, st: "State", E0):
         """phi_0 and E_0 from the in-flight charge (weights already set)."""

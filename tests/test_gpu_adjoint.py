@@ -30,7 +30,7 @@ def case():
     return cfg, tip, om, win, (JQ, JE, gE, gQ)
 
 
-def _device_window(pic, cfg, tip, win, precision):
+def _device_window(pic, cfg, tip, win, precision, adjoint_precond=0):
     gm = pic.Mesh(tip, cfg.emit_zmin)
     gs = pic.State(gm, win.cap, precision=precision)
     I = win.init
@@ -45,7 +45,8 @@ def _device_window(pic, cfg, tip, win, precision):
     gs.n_slots.fill_(n)
     gw = pic.Window(gm, gs, T=win.T, step0=win.step0, dt=cfg.dt,
                     w_sp=win.w_sp, phi_w=cfg.phi_w, seed=cfg.seed,
-                    j_scale=win.j_scale, tol=1e-13)
+                    j_scale=win.j_scale, tol=1e-13,
+                    adjoint_precond=adjoint_precond)
     return gm, gs, gw
 
 
@@ -54,9 +55,11 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
-def test_adjoint_fp64_matches_oracle(pic, case):
+@pytest.mark.parametrize("precond", [0, 1], ids=["jacobi", "amg"])
+def test_adjoint_fp64_matches_oracle(pic, case, precond):
+    """precond: that of the transposed solves (Jacobi or AMG)."""
     cfg, tip, om, win, (JQ, JE, gE, gQ) = case
-    gm, gs, gw = _device_window(pic, cfg, tip, win, pic.PIC_FP64)
+    gm, gs, gw = _device_window(pic, cfg, tip, win, pic.PIC_FP64, precond)
     s = torch.ones(om.n_emit, dtype=torch.float64, device="cuda")
     jq, je = gw.forward(cfg.E0, s)
     print("J", float(jq), JQ, float(je), JE)

@@ -102,6 +102,40 @@ def test_poisson_matches_oracle(pic, name):
     assert torch.equal(phi2, phi)
 
 
+@pytest.mark.parametrize("name", ["small_tip", "tiny_tip"])
+def test_poisson_amg_matches_oracle(pic, name):
+    """The smoothed-aggregation AMG preconditioner: the same potential and
+    field as the oracle's Jacobi-PCG solution to the paper's tolerance, in
+    a small fraction of the Jacobi iterations; the hierarchy is reused by a
+    second solve and a warm start from the solution needs no iteration."""
+    tip = MESHES[name]()
+    om = O.OracleMesh(tip, 0.01)
+    gm = pic.Mesh(tip, 0.01)
+    rng = np.random.default_rng(5)
+    c = rng.integers(-2**44, 2**44, tip.n_nodes).astype(np.int64)
+    phi_o, info = om.poisson_solve(c, 1e-3, 0.4, tol=1e-12)
+    E_o = om.field(phi_o)
+    for rep in range(2):
+        phi = torch.zeros(tip.n_nodes, dtype=torch.float64, device="cuda")
+        E = torch.zeros(4 * tip.n_nodes, dtype=torch.float64, device="cuda")
+        st = gm.poisson_solve(_dev(c), 1e-3, 0.4, phi, E, tol=1e-12,
+                              precond=pic.PIC_PRECOND_AMG)
+        s = gm.solve_stats(st)
+        print(name, rep, s, info["iters"])
+        assert s["status"] == 0 and s["relres"] <= 1e-12
+        assert s["iters"] * 4 <= info["iters"]
+        assert _rel(phi.cpu().numpy(), phi_o) < 1e-9
+        e = E.cpu().numpy().reshape(-1, 4)[:, :3]
+        assert _rel(e, E_o) < 1e-9
+    st2 = gm.poisson_solve(_dev(c), 1e-3, 0.4, phi, None, tol=1e-12,
+                           precond=pic.PIC_PRECOND_AMG)
+    assert gm.solve_stats(st2)["iters"] == 0
+    # the AMG preconditioner is FP64 only
+    with pytest.raises(pic.PicError):
+        gm.poisson_solve(_dev(c), 1e-3, 0.4, phi, None, tol=1e-12,
+                         precision=pic.PIC_MIXED, precond=pic.PIC_PRECOND_AMG)
+
+
 def _locate_case(pic, tip, pts, hint=None):
     om = O.OracleMesh(tip, 0.01)
     gm = pic.Mesh(tip, 0.01)
@@ -179,7 +213,7 @@ def test_emission_rate_matches_oracle(pic):
 
 def _run_pair(pic, cfg, n_steps, live_charge, n_live, cap, seed=None,
               resort_every=0, precision=0, solve_precision=None,
-              phi_err=None):
+              phi_err=None, precond=0):
     """live_charge: electrons in flight wanted (None = physical emission).
     phi_err: a list that receives the relative L2 distance of the device
     potential from the oracle's after every step."""
@@ -193,7 +227,7 @@ def _run_pair(pic, cfg, n_steps, live_charge, n_live, cap, seed=None,
     w_sp = per_run * j_scale / n_live
     gm = pic.Mesh(tip, cfg.emit_zmin)
     gs = pic.State(gm, cap, precision=precision,
-                   solve_precision=solve_precision)
+                   solve_precision=solve_precision, precond=precond)
     gs.init_field(cfg.E0, tol=cfg.tol)
     kw = dict(dt=cfg.dt, E0=cfg.E0, w_sp=w_sp, phi_w=cfg.phi_w,
               seed=cfg.seed if seed is None else seed, j_scale=j_scale,
@@ -209,13 +243,16 @@ def _run_pair(pic, cfg, n_steps, live_charge, n_live, cap, seed=None,
     return om, ost, gm, gs, so_all, sg_all
 
 
-def _compare_runs(ost, gs, so_all, sg_all):
+def _compare_runs(ost, gs, so_all, sg_all, same_solver=True):
     for k, (so, sg) in enumerate(zip(so_all, sg_all)):
         for key in ("n_inj", "n_anode", "n_cathode", "n_after", "q_before",
                     "q_inj", "q_anode", "q_cathode", "q_after", "status",
                     "n_trunc", "n_clamp"):
             assert so[key] == sg[key], (k, key, so[key], sg[key])
-        assert abs(so["cg_iters"] - sg["cg_iters"]) <= 3
+        if same_solver:
+            assert abs(so["cg_iters"] - sg["cg_iters"]) <= 3
+        else:
+            assert sg["cg_iters"] <= so["cg_iters"] + 1
         assert sg["cg_relres"] <= 1e-12 or sg["cg_iters"] == 0
         for key in ("emit_current", "mean_face_E", "max_face_E"):
             assert abs(sg[key] - so[key]) <= 1e-9 * abs(so[key]) + 1e-300
@@ -260,6 +297,18 @@ def test_pic_step_tiny_space_charge(pic):
     assert all(s["cg_iters"] > 0 for s in sg[1:])
     assert sum(s["n_anode"] for s in sg) > 0
     _compare_runs(ost, gs, so, sg)
+
+
+def test_pic_step_space_charge_amg(pic):
+    """The coupled space-charge run with the AMG-preconditioned solve: every
+    count, charge and particle as in the oracle (whose solve is Jacobi-PCG
+    to the same tolerance), with fewer iterations per step."""
+    cfg = W.config_tiny()
+    om, ost, gm, gs, so, sg = _run_pair(pic, cfg, 12, 0.01, 3000, 60_000,
+                                        resort_every=5,
+                                        precond=pic.PIC_PRECOND_AMG)
+    assert sum(s["cg_iters"] for s in sg) < sum(s["cg_iters"] for s in so)
+    _compare_runs(ost, gs, so, sg, same_solver=False)
 
 
 def test_pic_step_deterministic(pic):
