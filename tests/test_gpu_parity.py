@@ -123,7 +123,7 @@ def test_poisson_amg_matches_oracle(pic, name):
         s = gm.solve_stats(st)
         print(name, rep, s, info["iters"])
         assert s["status"] == 0 and s["relres"] <= 1e-12
-        assert s["iters"] * 4 <= info["iters"]
+        assert s["iters"] <= max(info["iters"] // 4, 10)
         assert _rel(phi.cpu().numpy(), phi_o) < 1e-9
         e = E.cpu().numpy().reshape(-1, 4)[:, :3]
         assert _rel(e, E_o) < 1e-9
