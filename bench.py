@@ -28,10 +28,10 @@ HBM_PEAK_GBS = 8000.0
 # production workload, from rocprofv3 FETCH_SIZE and WRITE_SIZE counter runs
 # scaled by a plain 1 GiB copy (profiles/pic_step_fp64_production_tip.md).
 # It is reported only while the kernel sources are the ones profiled.
-PUSH_TRAFFIC = dict(bytes=199.9e6, read=134.3e6, written=65.6e6,
+PUSH_TRAFFIC = dict(bytes=199.6e6, read=134.0e6, written=65.6e6,
                     sources=("paper_1906_08125_amd/csrc/particles.hip",
                              "paper_1906_08125_amd/csrc/common.h"),
-                    sha256=("c4db35d85be8a89b1ae9846bd3124d9dbef8ad94c2406f1606c64c7cfa5ba56b", "c4353e7328c5103c2aa4c818e711b82d9b0a0b073ce8a1762fb7b7907693342a"))
+                    sha256=("94af7d41850ca1342c5b958cfbe4d865bb4cc9354cabefd4c0660919f236057e", "3d650f3287f1f729a4305a57451ae7a94f15317ef9081d515e4abdd68e910046"))
 
 
 def measured_traffic():
