@@ -318,19 +318,66 @@ __global__ void __launch_bounds__(256) k_adj_scales(AdjArgs a) {
 
 // Fixed-point scatters of the weight contributions (to faces) and of the
 // gather-adjoint vectors (to nodes).
+// Per-workgroup accumulation before the global integer atomics: thousands
+// of superparticles add into the same face (born there) and, sorted by tet,
+// into the same few nodes, and same-address atomics in L2 serialize.  A
+// workgroup sums its contributions in LDS -- a node table (open addressing)
+// and, when the faces fit, one slot per face -- and flushes one atomic per
+// distinct node component and face.  Integer addition is exact and
+// order-free, so the totals are unchanged.
+constexpr int kAdjTable = 1024;  // > 4 nodes x the superparticles of a chunk
+constexpr int kAdjFaces = 2048;
+
+struct AdjTable {
+  int32_t key[kAdjTable];
+  unsigned long long v[3][kAdjTable];
+  unsigned long long face[kAdjFaces];
+};
+
+__device__ inline void adj_node_add(AdjTable& T, int32_t node, const long long q[3],
+                                    long long* acc) {
+  uint32_t h = ((uint32_t)node * 2654435761u) >> 22;  // 10 bits
+  for (int probe = 0; probe < 64; ++probe) {
+    const int32_t old = atomicCAS(&T.key[h], -1, node);
+    if (old == -1 || old == node) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        if (q[k]) atomicAdd(&T.v[k][h], (unsigned long long)q[k]);
+      return;
+    }
+    h = (h + 1) & (kAdjTable - 1);
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    if (q[k]) atomicAdd((unsigned long long*)(acc + 3 * (int64_t)node + k),
+                        (unsigned long long)q[k]);
+}
+
 __global__ void __launch_bounds__(kAdjBlock) k_adj_scatter(AdjArgs a) {
   const DevMesh& m = a.m;
+  __shared__ AdjTable T;
+  const bool faces_lds = m.n_emit <= kAdjFaces;
+  for (int k = threadIdx.x; k < kAdjTable; k += blockDim.x) {
+    T.key[k] = -1;
+    T.v[0][k] = T.v[1][k] = T.v[2][k] = 0ull;
+  }
+  for (int k = threadIdx.x; k < kAdjFaces; k += blockDim.x) T.face[k] = 0ull;
+  __syncthreads();
   double S_s, S_E;
   adj_scales(a, S_s, S_E);
   const int64_t npre = *a.n_pre;
   const int64_t n = a.initial ? npre : *a.n_post;
   const int64_t cap = a.cap;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
+  const Range rg = my_range(n);
+  for (int64_t i = rg.lo + threadIdx.x; i < rg.hi; i += blockDim.x) {
     const double sc = a.sc[i];
-    if (sc != 0.0)
-      atomicAdd((unsigned long long*)(a.acc_s + a.qbirth[i]),
-                (unsigned long long)__double2ll_rn(sc * S_s));
+    if (sc != 0.0) {
+      const long long q = __double2ll_rn(sc * S_s);
+      if (faces_lds)
+        atomicAdd(&T.face[a.qbirth[i]], (unsigned long long)q);
+      else
+        atomicAdd((unsigned long long*)(a.acc_s + a.qbirth[i]), (unsigned long long)q);
+    }
     if (a.initial || a.qtet[i] < 0) continue;
     const double av[3] = {a.av[i], a.av[cap + i], a.av[2 * cap + i]};
     if (i < npre) {
@@ -341,23 +388,40 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj_scatter(AdjArgs a) {
       double lam[4];
       barycentric(G0, px, py, pz, lam);
 #pragma unroll
-      for (int l = 0; l < 4; ++l)
+      for (int l = 0; l < 4; ++l) {
+        long long q[3];
 #pragma unroll
-        for (int k = 0; k < 3; ++k)
-          atomicAdd((unsigned long long*)(a.acc_E + 3 * (int64_t)G0.node[l] + k),
-                    (unsigned long long)__double2ll_rn(lam[l] * av[k] * S_E));
+        for (int k = 0; k < 3; ++k) q[k] = __double2ll_rn(lam[l] * av[k] * S_E);
+        adj_node_add(T, G0.node[l], q, a.acc_E);
+      }
     } else {
       const double R1 = a.av[3 * cap + i], R2 = a.av[4 * cap + i];
       const double wgt[3] = {(1.0 - R1) - R2, R1, R2};
       const int32_t* nd = m.e_nodes + 3 * (int64_t)a.qbirth[i];
 #pragma unroll
-      for (int q = 0; q < 3; ++q)
+      for (int f = 0; f < 3; ++f) {
+        long long q[3];
 #pragma unroll
-        for (int k = 0; k < 3; ++k)
-          atomicAdd((unsigned long long*)(a.acc_E + 3 * (int64_t)nd[q] + k),
-                    (unsigned long long)__double2ll_rn(wgt[q] * av[k] * S_E));
+        for (int k = 0; k < 3; ++k) q[k] = __double2ll_rn(wgt[f] * av[k] * S_E);
+        adj_node_add(T, nd[f], q, a.acc_E);
+      }
     }
   }
+  __syncthreads();
+  for (int k = threadIdx.x; k < kAdjTable; k += blockDim.x) {
+    const int32_t node = T.key[k];
+    if (node < 0) continue;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const unsigned long long v = T.v[c][k];
+      if (v) atomicAdd((unsigned long long*)(a.acc_E + 3 * (int64_t)node + c), v);
+    }
+  }
+  if (faces_lds)
+    for (int k = threadIdx.x; k < m.n_emit; k += blockDim.x) {
+      const unsigned long long v = T.face[k];
+      if (v) atomicAdd((unsigned long long*)(a.acc_s + k), v);
+    }
 }
 
 // Eb = the field adjoint of E_k (from the accumulators); dJ/ds and dJ/dE0.
