@@ -125,6 +125,7 @@ fp::CgArgs cg_args(const pic_mesh* h, const int64_t* charge, double w_sp,
   a.w = h->cg_vec[4];
   a.p = h->cg_vec[5];
   a.s = h->cg_vec[6];
+  a.bprev = h->cg_bprev;
   a.mixed = prm->precision == PIC_MIXED;
   a.e32 = e32;
   a.inner_tol = prm->inner_tol;
@@ -182,6 +183,7 @@ hipError_t iterate_graphs(pic_mesh* h, const fp::CgArgs& a0, int n, hipStream_t 
   a.rhs = nullptr;
   a.E = nullptr;
   a.keep_field = 0;
+  a.incremental = 0;
   a.coef = a.E0 = 0.0;
   hipError_t e;
   if (!h->cap_stream &&
@@ -711,6 +713,9 @@ pic_status pic_step(pic_mesh* h, const pic_particles* P, const pic_fields* F,
     // after the first step of this call, E = R phi still holds from the
     // previous solve (every solve ends with a field pass over its final phi)
     ca.keep_field = k > 0 ? 1 : 0;
+    // and its true residual and right-hand side: the first pass of this
+    // solve needs no product with K
+    ca.incremental = k > 0 ? 1 : 0;
     const int spec = h->step_spec;
     int64_t seq = 0;
     prof_begin(h, PIC_K_SOLVE, s);
@@ -1015,7 +1020,10 @@ pic_status pic_batch_step(pic_batch* b, const pic_particles* P,
       ea.stats = st;
       fp::CgArgs ca = ss.ca;
       ca.step_stats = st;
-      ca.keep_field = k > 0 ? 1 : 0;  // as in pic_step
+      ca.keep_field = k > 0 ? 1 : 0;
+    // and its true residual and right-hand side: the first pass of this
+    // solve needs no product with K
+    ca.incremental = k > 0 ? 1 : 0;  // as in pic_step
       std::memcpy(base + sa * i, &a, sa);
       std::memcpy(base + sa * n + se * i, &ea, se);
       std::memcpy(base + (sa + se) * n + sg * i, &ca, sg);

@@ -15,6 +15,7 @@ struct pic_mesh {
   int n_cu = 0;
   // solver scratch: b, x, r, u, w, p, s (f64) and the partial sums
   double* cg_vec[7] = {};
+  double* cg_bprev = nullptr;          // right-hand side of the last pass
   float* cg_vec32[5] = {};             // r, u, w, p, s of the FP32 recursion
   double* cg_part = nullptr;
   int cg_grid = 0;

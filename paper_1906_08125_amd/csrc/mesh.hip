@@ -673,6 +673,7 @@ pic_status build_mesh(const pic_mesh_desc* d, pic_mesh* h, std::string& msg) {
   // solver scratch
   const size_t vb = sizeof(double) * (size_t)std::max<int64_t>(NF, 1);
   for (int k = 0; k < 7; ++k) h->cg_vec[k] = (double*)dev_alloc(h, vb, err);
+  h->cg_bprev = (double*)dev_alloc(h, vb, err);
   for (int k = 0; k < 5; ++k) h->cg_vec32[k] = (float*)dev_alloc(h, vb / 2, err);
   int dev = 0, ncu = 0;
   if (err == hipSuccess) err = hipGetDevice(&dev);

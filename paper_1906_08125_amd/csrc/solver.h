@@ -64,6 +64,13 @@ struct CgArgs {
   // same fields ended with it and nothing has changed phi since): the first
   // pass of the solve computes the residual only
   int keep_field;
+  // The first pass forms the residual from the previous one instead of a
+  // product with K: b - K phi = (b - b_prev) + r_prev, where r_prev (in r)
+  // is the true residual that the previous solve of the same system ended
+  // with (every solve ends with a residual pass over its final phi) and
+  // b_prev its right-hand side; valid while phi is unchanged since.
+  int incremental;
+  double* bprev;          // [n_free] right-hand side of the last pass
   CgCtrl* ctrl;
   // host address of the AMG hierarchy (AmgDev) when the solve is
   // preconditioned by it, else null (Jacobi); FP64 only

@@ -293,7 +293,9 @@ __device__ inline void k_cg_resfield_body(const CgArgs& a, int reset, VB vb) {
       }
       const double ri = bi - kx;
       a.x[r] = pi;
+      if (a.bprev) a.bprev[r] = bi;
       if (a.mixed) {
+        a.r[r] = ri;  // (kept for an incremental next pass)
         a.r32[r] = (float)ri;
         a.u32[r] = (float)(ri * m.invdiag[r]);
       } else {
@@ -351,6 +353,36 @@ __device__ inline void k_cg_resfield_body(const CgArgs& a, int reset, VB vb) {
       else
         reinterpret_cast<double4*>(a.E)[nd] = make_double4(ex, ey, ez, 0.0);
     }
+  }
+  write_partials<2>(slot(a, 0), a.G, v, vb);
+}
+
+// First pass of a solve whose previous solve (same system, phi unchanged
+// since) ended with the true residual r and right-hand side b_prev: r =
+// (b - b_prev) + r, the same quantity as b - K phi without the product with
+// K; x = phi, u = D^-1 r, (b,b), (r,r) as in the full pass.  The field is
+// that of phi already.
+__device__ inline void k_cg_resinc_body(const CgArgs& a, VB vb) {
+  const DevMesh& m = a.m;
+  if (vb.id == 0 && threadIdx.x == 0) ctrl_reset(a.ctrl);
+  const Range rows = my_range(m.n_free, vb);
+  double v[2] = {0.0, 0.0};
+  for (int64_t i = rows.lo + threadIdx.x; i < rows.hi; i += blockDim.x) {
+    const int32_t nd = m.free2node[i];
+    const double c = a.charge ? (double)a.charge[nd] : 0.0;
+    const double bi = a.coef * c + a.E0 * m.g_unit[i];
+    const double ri = (bi - a.bprev[i]) + a.r[i];
+    a.r[i] = ri;
+    a.bprev[i] = bi;
+    a.x[i] = a.phi[nd];
+    if (a.mixed) {
+      a.r32[i] = (float)ri;
+      a.u32[i] = (float)(ri * m.invdiag[i]);
+    } else {
+      a.u[i] = ri * m.invdiag[i];
+    }
+    v[0] += bi * bi;
+    v[1] += ri * ri;
   }
   write_partials<2>(slot(a, 0), a.G, v, vb);
 }
@@ -568,6 +600,9 @@ __global__ void __launch_bounds__(kCgBlock) k_cg_resfield(CgArgs a, int reset) {
 }
 __global__ void __launch_bounds__(kCgBlock) k_cg_scatter(CgArgs a) {
   k_cg_scatter_body(a, VB{(int)blockIdx.x, (int)gridDim.x});
+}
+__global__ void __launch_bounds__(kCgBlock) k_cg_resinc(CgArgs a) {
+  k_cg_resinc_body(a, VB{(int)blockIdx.x, (int)gridDim.x});
 }
 __global__ void __launch_bounds__(kCgBlock) k_cg_start(CgArgs a, int64_t seq) {
   k_cg_start_body(a, seq, VB{(int)blockIdx.x, (int)gridDim.x});
@@ -876,7 +911,10 @@ hipError_t amg_launch_iters(const CgArgs& a, const AmgDev& d, int n,
   } while (0)
 
 hipError_t cg_launch_begin(const CgArgs& a, int64_t seq, hipStream_t s) {
-  LAUNCH(k_cg_resfield, a, 1);
+  if (a.incremental && !a.rhs && a.bprev)
+    LAUNCH(k_cg_resinc, a);
+  else
+    LAUNCH(k_cg_resfield, a, 1);
   LAUNCH(k_cg_start, a, seq);
   return hipSuccess;
 }

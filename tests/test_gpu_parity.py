@@ -327,11 +327,15 @@ def test_pic_step_deterministic(pic):
 
 @pytest.mark.parametrize("live_charge", [None, 0.01])
 def test_pic_step_many_per_call(pic, live_charge):
-    """Twelve steps in one pic_step call (each step's pre-solve kernels are
-    enqueued behind the previous solve's first report, gated on its
-    outcome) leave bit-identical particles, fields and per-step records to
-    twelve calls of one step.  With space charge every solve iterates past
-    its first round, so the gated launches are skipped and enqueued again."""
+    """Twelve steps in one pic_step call against twelve calls of one step.
+    Inside a call, each step's pre-solve kernels are enqueued behind the
+    previous solve's first report, gated on its outcome, and the first pass
+    of each later solve forms the residual from the previous one ((b -
+    b_prev) + r_prev, the same quantity as b - K phi up to rounding).  With
+    physical emission no solve iterates and both runs agree bit for bit but
+    for the reported residual; with space charge every solve iterates past
+    its first round (the gated launches are skipped and enqueued again) and
+    the two runs agree to the solver tolerance."""
     cfg = W.config_tiny()
     gm = pic.Mesh(cfg.mesh(), cfg.emit_zmin)
     runs = []
@@ -349,15 +353,35 @@ def test_pic_step_many_per_call(pic, live_charge):
             recs += pic.State.decode_stats(gs.step(step0=k0, n_steps=per_call, **kw))
         runs.append((gs, recs))
     (ga, ra), (gb, rb) = runs
-    assert ra == rb
-    if live_charge is not None:
-        assert sum(r["cg_iters"] > 0 for r in ra) >= 10
+    exact = live_charge is None
+    for a, b in zip(ra, rb):
+        for key in ("n_before", "n_inj", "n_anode", "n_cathode", "n_after",
+                    "q_before", "q_inj", "q_anode", "q_cathode", "q_after",
+                    "status", "n_trunc", "n_fallback", "n_slots"):
+            assert a[key] == b[key], key
+        assert b["cg_relres"] <= cfg.tol
+        if exact:
+            assert a["cg_iters"] == b["cg_iters"] == 0
+        else:
+            assert a["cg_iters"] > 0 and abs(a["cg_iters"] - b["cg_iters"]) <= 3
     n = int(ga.n_slots.item())
     assert n == int(gb.n_slots.item())
-    for key in ("x", "y", "z", "vx", "vy", "vz", "w", "tet", "birth", "id"):
+    for key in ("tet", "birth", "id", "w"):
         assert torch.equal(getattr(ga, key)[:n], getattr(gb, key)[:n]), key
-    for key in ("phi", "E", "charge"):
-        assert torch.equal(getattr(ga, key), getattr(gb, key)), key
+    for key in ("x", "y", "z", "vx", "vy", "vz"):
+        A, B = getattr(ga, key)[:n], getattr(gb, key)[:n]
+        if exact:
+            assert torch.equal(A, B), key
+        else:
+            assert ((A - B).norm() / B.norm()).item() <= 1e-9, key
+    for key in ("phi", "E"):
+        A, B = getattr(ga, key), getattr(gb, key)
+        if exact:
+            assert torch.equal(A, B), key
+        else:
+            assert ((A - B).norm() / B.norm()).item() <= 1e-9, key
+    dq = (ga.charge - gb.charge).abs().max().item()
+    assert dq == 0 if exact else dq <= 16
 
 
 def test_wrap_and_absorption_explicit(pic):
