@@ -237,6 +237,13 @@ typedef struct {
  * position (widened exactly to FP64), locating, deposition, injection and
  * emission stay FP64, so charge and tet ids follow the stored positions
  * exactly.  params->solve.precision chooses the solver independently.
+ * Within one call, each later solve starts from the previous one: its first
+ * pass forms the residual as (b - b_prev) + r_prev rather than b - K phi
+ * (equal up to rounding) and keeps the field, which already belongs to phi;
+ * so one call of n steps and n calls of one step agree to the solver
+ * tolerance, bit for bit when no solve iterates.  The host waits for each
+ * solve's convergence report; the next step's kernels are already queued
+ * behind it and do nothing if the solve needs more rounds.
  * stats: device [n_steps] pic_step_stats (overwritten). */
 PIC_API pic_status pic_step(pic_mesh* mesh, const pic_particles* particles,
                     const pic_fields* fields, const pic_step_params* params,
