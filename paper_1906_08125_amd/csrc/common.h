@@ -54,11 +54,21 @@ struct alignas(128) TetGeom {
 };
 static_assert(sizeof(TetGeom) == 128, "TetGeom is one line");
 
+// FP32 copy of the map and vertex ids, for the mixed-precision field
+// gather only (the walk and the deposition use TetGeom).
+struct alignas(64) TetGeom32 {
+  float v0[3];
+  float m[9];
+  int32_t node[4];
+};
+static_assert(sizeof(TetGeom32) == 64, "TetGeom32 is half a line");
+
 struct DevMesh {
   int64_t n_nodes, n_tets, n_free, nnz, nnz_field, n_emit;
   double Lx, Ly, z_top;
   const TetWalk* tw;
   const TetGeom* tg;
+  const TetGeom32* tg32;
   // Jacobi inverse diagonal of the stiffness on free nodes
   const double* invdiag;
   const float* invdiag32;

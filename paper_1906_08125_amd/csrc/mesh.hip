@@ -596,6 +596,15 @@ pic_status build_mesh(const pic_mesh_desc* d, pic_mesh* h, std::string& msg) {
   M.z_top = d->z_top;
   M.tw = upload(h, tw, err);
   M.tg = upload(h, tg, err);
+  {
+    std::vector<TetGeom32> tg32(T);
+    for (int64_t t = 0; t < T; ++t) {
+      for (int k = 0; k < 3; ++k) tg32[t].v0[k] = (float)tg[t].v0[k];
+      for (int k = 0; k < 9; ++k) tg32[t].m[k] = (float)tg[t].m[k];
+      for (int k = 0; k < 4; ++k) tg32[t].node[k] = tg[t].node[k];
+    }
+    M.tg32 = upload(h, tg32, err);
+  }
   M.invdiag = upload(h, invdiag, err);
   M.invdiag32 = upload(h, invdiag32, err);
   M.g_unit = upload(h, g_unit, err);

@@ -211,10 +211,10 @@ __device__ inline bool lam_test(const TetGeom& g, double x, double y, double z,
 // exact bucket scan must decide.
 __device__ inline int walk(const DevMesh& m, double x, double y, double z,
                            int t, int sx, int sy, int& steps, bool far,
-                           TetGeom& G, double lam[4]) {
+                           TetGeom& G, double lam[4], bool have_G = true) {
   bool jumped = false;
   for (steps = 0; steps < kMaxWalk; ++steps) {
-    bool reload = steps > 0;
+    bool reload = steps > 0 || !have_G;
     if (!jumped && (far || steps == 1)) {
       jumped = true;
       int g = fine_seed(m, x, y, z);
@@ -354,11 +354,12 @@ __device__ inline void deposit_table(const TetGeom& g, const double lam[4],
   for (int k = 0; k < 4; ++k) table_add(T, g.node[k], q[k], charge);
 }
 
-// G: the record of the hint tet.
+// G: the record of the hint tet (have_G), or to be loaded when needed.
 __device__ inline void settle(const DevMesh& m, const StepArgs& a, int64_t i,
                               double x, double y, double z, int sx, int sy,
                               int hint, TetGeom& G, double w, long long qfx,
-                              Acc& acc, ChargeTable& T, bool far) {
+                              Acc& acc, ChargeTable& T, bool far,
+                              bool have_G = true) {
   if (z >= m.z_top) {
     a.tet[i] = -1;
     acc.n_anode += 1;
@@ -367,7 +368,7 @@ __device__ inline void settle(const DevMesh& m, const StepArgs& a, int64_t i,
   }
   int steps = 0;
   double lam[4];
-  const int t = walk(m, x, y, z, hint, sx, sy, steps, far, G, lam);
+  const int t = walk(m, x, y, z, hint, sx, sy, steps, far, G, lam, have_G);
   acc.walk_steps += steps;
   if (steps > acc.walk_max) acc.walk_max = steps;
   if (t >= 0) {
@@ -674,13 +675,16 @@ __device__ inline void push_role32(const StepArgs& a, int g, int G, Acc& acc,
     acc.q_before += qfx;
     float x = X[i], y = Y[i], z = Z[i];
     float vx = VX[i], vy = VY[i], vz = VZ[i];
-    TetGeom G4 = m.tg[t];
-    double lam[4];
-    barycentric(G4, x, y, z, lam);
-    const float l0 = (float)lam[0], l1 = (float)lam[1], l2 = (float)lam[2],
-                l3 = (float)lam[3];
-    const float4 e0 = E[G4.node[0]], e1 = E[G4.node[1]], e2 = E[G4.node[2]],
-                 e3 = E[G4.node[3]];
+    // FP32 gather from the FP32 record (half the bytes of the FP64 one,
+    // which the walk loads only when it needs the hint tet itself)
+    const TetGeom32 G32 = m.tg32[t];
+    const float dx0 = x - G32.v0[0], dy0 = y - G32.v0[1], dz0 = z - G32.v0[2];
+    const float l1 = (G32.m[0] * dx0 + G32.m[1] * dy0) + G32.m[2] * dz0;
+    const float l2 = (G32.m[3] * dx0 + G32.m[4] * dy0) + G32.m[5] * dz0;
+    const float l3 = (G32.m[6] * dx0 + G32.m[7] * dy0) + G32.m[8] * dz0;
+    const float l0 = ((1.0f - l1) - l2) - l3;
+    const float4 e0 = E[G32.node[0]], e1 = E[G32.node[1]],
+                 e2 = E[G32.node[2]], e3 = E[G32.node[3]];
     const float ex = ((l0 * e0.x + l1 * e1.x) + l2 * e2.x) + l3 * e3.x;
     const float ey = ((l0 * e0.y + l1 * e1.y) + l2 * e2.y) + l3 * e3.y;
     const float ez = ((l0 * e0.z + l1 * e1.z) + l2 * e2.z) + l3 * e3.z;
@@ -714,7 +718,8 @@ __device__ inline void push_role32(const StepArgs& a, int g, int G, Acc& acc,
     VX[i] = vx;
     VY[i] = vy;
     VZ[i] = vz;
-    settle(m, a, i, x, y, z, sx, sy, t, G4, w, qfx, acc, T, far);
+    TetGeom G4;
+    settle(m, a, i, x, y, z, sx, sy, t, G4, w, qfx, acc, T, far, false);
   }
 }
 
