@@ -28,10 +28,10 @@ HBM_PEAK_GBS = 8000.0
 # production workload, from rocprofv3 FETCH_SIZE and WRITE_SIZE counter runs
 # scaled by a plain 1 GiB copy (profiles/pic_step_fp64_production_tip.md).
 # It is reported only while the kernel sources are the ones profiled.
-PUSH_TRAFFIC = dict(bytes=199.6e6, read=134.0e6, written=65.6e6,
+PUSH_TRAFFIC = dict(bytes=199.4e6, read=133.9e6, written=65.6e6,
                     sources=("paper_1906_08125_amd/csrc/particles.hip",
                              "paper_1906_08125_amd/csrc/common.h"),
-                    sha256=("94af7d41850ca1342c5b958cfbe4d865bb4cc9354cabefd4c0660919f236057e", "3d650f3287f1f729a4305a57451ae7a94f15317ef9081d515e4abdd68e910046"))
+                    sha256=("84690ce040cf4bcec75258ca282e93e8439c6db669ba9fddbc7f3618631440b4", "7d8f3c2344d581d986633cc1e8597ea0062a3ad5736211095600e29a54930541"))
 
 
 def measured_traffic():
