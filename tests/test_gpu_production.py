@@ -1,0 +1,151 @@
+"""Parity at the production size (3,100,504 tets, ~1e6 superparticles), in
+the launch configuration the benchmark times (FP64, many steps per call,
+re-sort every 10 steps).  The oracle cannot run this workload whole in a
+test, so it checks what it can compute one by one or that holds at any
+size:
+
+* one step of sampled superparticles replayed from the device state before
+  it (gather with the oracle's barycentric coordinates, kick, drift, wrap,
+  absorption) against the device state after it, positions to 1e-12;
+* the containing tet of every sampled survivor: the oracle's exact
+  canonical location of the device's position, bit-exact;
+* the node charges: the oracle's deposition of all live device particles,
+  bit-exact, and their total against the particles' fixed-point weights;
+* the potential: its true residual under the oracle's K and right-hand
+  side within the solver tolerance; the nodal field: the oracle's R of the
+  device potential to 1e-12;
+* the emission: the oracle's FN rate of the device field to 1e-12;
+* after the re-sort: compacted slots, ordered by tet."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1906_08125_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def setup():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1906_08125_amd import pic
+    pic.load_library()
+    cfg = W.config_production()
+    tip = cfg.mesh()
+    om = O.OracleMesh(tip, cfg.emit_zmin)
+    gm = pic.Mesh(tip, cfg.emit_zmin)
+    gs = pic.State(gm, 2_500_000)
+    gs.init_field(cfg.E0, tol=cfg.tol)
+    rate, _ = gm.emission_rate(gs.E, cfg.phi_w)
+    w_sp = rate.item() * cfg.dt * cfg.transit_steps / cfg.n_target
+    kw = dict(dt=cfg.dt, E0=cfg.E0, w_sp=w_sp, phi_w=cfg.phi_w, seed=cfg.seed,
+              tol=cfg.tol, resort_every=cfg.resort_every)
+    gs.step(step0=0, n_steps=50, **kw)
+    torch.cuda.synchronize()
+    return pic, cfg, om, gm, gs, kw
+
+
+def _host(gs):
+    n = int(gs.n_slots.item())
+    g = lambda t: t[:n].cpu().numpy()
+    return dict(n=n, x=g(gs.x), y=g(gs.y), z=g(gs.z), vx=g(gs.vx), vy=g(gs.vy),
+                vz=g(gs.vz), w=g(gs.w), tet=g(gs.tet), id=g(gs.id),
+                phi=gs.phi.cpu().numpy(), E=gs.E.cpu().numpy().reshape(-1, 4)[:, :3],
+                charge=gs.charge.cpu().numpy())
+
+
+def _fields_and_charge(om, cfg, kw, S):
+    live = S["tet"] >= 0
+    p = np.stack([S["x"], S["y"], S["z"]], 1)[live]
+    c = om.deposit(p, S["tet"][live], S["w"][live])
+    assert np.array_equal(c, S["charge"])
+    q = np.rint(S["w"][live] * 2.0**40).astype(np.int64)
+    assert int(S["charge"].sum()) == int(q.sum())
+    fid, _ = om.free()
+    free = np.flatnonzero(fid >= 0)
+    free = free[np.argsort(fid[free])]
+    b = om.rhs(S["charge"], kw["w_sp"], cfg.E0)
+    r = b - om.spmv(S["phi"][free])
+    assert np.linalg.norm(r) <= 1.5 * cfg.tol * np.linalg.norm(b)
+    E = om.field(S["phi"])
+    assert np.linalg.norm(E - S["E"]) <= 1e-12 * np.linalg.norm(E)
+
+
+def test_production_step_sampled(setup):
+    pic, cfg, om, gm, gs, kw = setup
+    A = _host(gs)
+    gs.step(step0=50, n_steps=1, **kw)
+    B = _host(gs)
+    _fields_and_charge(om, cfg, kw, B)
+    # emission rate of the field the step started from
+    r_dev, _ = gm.emission_rate(torch.from_numpy(
+        np.concatenate([A["E"], np.zeros((len(A["E"]), 1))], 1).reshape(-1)).cuda(),
+        cfg.phi_w)
+    r_or, _ = om.emission_rate(A["E"], cfg.phi_w)
+    assert abs(r_dev.item() - r_or) <= 1e-12 * r_or
+    # one step of 3000 sampled pre-step superparticles
+    live = np.flatnonzero(A["tet"] >= 0)
+    rng = np.random.default_rng(11)
+    pick = rng.choice(live, size=min(3000, live.size), replace=False)
+    where_b = {int(i): k for k, i in enumerate(B["id"]) if B["tet"][k] >= 0}
+    k_ = O.constants()
+    Q = (k_["qm"] * cfg.dt) * 0.5
+    Lx, Ly, ztop = gm.tip.Lx, gm.tip.Ly, gm.tip.z_top
+    tets = om.tets()
+    nodes = tets["tet"]
+    survivors = []
+    for i in pick:
+        p = np.array([A["x"][i], A["y"][i], A["z"][i]])
+        v = np.array([A["vx"][i], A["vy"][i], A["vz"][i]])
+        t = int(A["tet"][i])
+        lam = om.lam(t, p)
+        e = A["E"][nodes[t]]
+        E = ((lam[0] * e[0] + lam[1] * e[1]) + lam[2] * e[2]) + lam[3] * e[3]
+        qE = Q * E
+        v = (v + qE) + qE
+        p = p + cfg.dt * v
+        if p[0] >= Lx:
+            p[0] -= Lx
+        elif p[0] < 0.0:
+            p[0] += Lx
+        if p[1] >= Ly:
+            p[1] -= Ly
+        elif p[1] < 0.0:
+            p[1] += Ly
+        k = where_b.get(int(A["id"][i]))
+        if p[2] >= ztop:
+            assert k is None, "anode-absorbed on the device too"
+            continue
+        if k is None:  # absorbed by the cathode: outside every vacuum tet
+            tt, wh = om.locate(p[None, :])
+            assert tt[0] < 0 and wh[0] == 2
+            continue
+        q = np.array([B["x"][k], B["y"][k], B["z"][k]])
+        assert np.abs(q - p).max() <= 1e-12 * max(1.0, np.abs(p).max())
+        assert np.abs(np.array([B["vx"][k], B["vy"][k], B["vz"][k]]) - v).max() \
+            <= 1e-12 * max(1.0, np.abs(v).max())
+        survivors.append(k)
+    assert len(survivors) > 0.9 * len(pick)
+    ks = np.array(survivors)
+    pts = np.stack([B["x"][ks], B["y"][ks], B["z"][ks]], 1)
+    tt, wh = om.locate(pts)
+    assert np.array_equal(tt, B["tet"][ks])
+
+
+def test_production_multi_step_call(setup):
+    """Ten steps in one call, ending with a re-sort."""
+    pic, cfg, om, gm, gs, kw = setup
+    gs.step(step0=51, n_steps=9, **kw)   # steps 51..59: (59 + 1) % 10 == 0
+    torch.cuda.synchronize()
+    C = _host(gs)
+    assert (C["tet"] >= 0).all() and (np.diff(C["tet"]) >= 0).all()
+    assert C["n"] > 500_000
+    _fields_and_charge(om, cfg, kw, C)
+    # canonical location of a sample after the multi-step call
+    rng = np.random.default_rng(12)
+    ks = rng.choice(C["n"], size=3000, replace=False)
+    tt, wh = om.locate(np.stack([C["x"][ks], C["y"][ks], C["z"][ks]], 1))
+    assert np.array_equal(tt, C["tet"][ks])
