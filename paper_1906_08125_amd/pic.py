@@ -272,7 +272,11 @@ class Mesh:
                     bnorm=float(raw[5]))
 
     def emission_rate(self, E, phi_w):
+        """FN rate (e/fs) and |E| per emitting face for the FP64 nodal field
+        E [4 n_nodes]."""
         torch = _torch()
+        if E.dtype != torch.float64:
+            raise TypeError("emission_rate takes the FP64 nodal field")
         rate = torch.zeros(1, dtype=torch.float64, device=E.device)
         faceF = torch.zeros(max(self.n_emit, 1), dtype=torch.float64,
                             device=E.device)

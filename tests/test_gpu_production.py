@@ -15,7 +15,12 @@ size:
   side within the solver tolerance; the nodal field: the oracle's R of the
   device potential to 1e-12;
 * the emission: the oracle's FN rate of the device field to 1e-12;
-* after the re-sort: compacted slots, ordered by tet."""
+* after the re-sort: compacted slots, ordered by tet.
+
+Mixed precision (FP32 particles and field) runs the same checks with the
+FP32 bound: replayed positions, velocities and the field to 1e-6; the
+location and deposition of the stored FP32 positions (widened exactly)
+stay bit-exact."""
 import numpy as np
 import pytest
 
@@ -28,36 +33,43 @@ torch = pytest.importorskip("torch")
 
 
 @pytest.fixture(scope="module")
-def setup():
+def prod():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_1906_08125_amd import pic
     pic.load_library()
     cfg = W.config_production()
     tip = cfg.mesh()
-    om = O.OracleMesh(tip, cfg.emit_zmin)
-    gm = pic.Mesh(tip, cfg.emit_zmin)
-    gs = pic.State(gm, 2_500_000)
+    return pic, cfg, O.OracleMesh(tip, cfg.emit_zmin), pic.Mesh(tip, cfg.emit_zmin)
+
+
+@pytest.fixture(scope="module", params=["fp64", "mixed"])
+def setup(request, prod):
+    pic, cfg, om, gm = prod
+    gs = pic.State(gm, 2_500_000, precision=pic.PIC_FP64
+                   if request.param == "fp64" else pic.PIC_MIXED)
     gs.init_field(cfg.E0, tol=cfg.tol)
-    rate, _ = gm.emission_rate(gs.E, cfg.phi_w)
+    rate, _ = gm.emission_rate(gs.E.to(torch.float64), cfg.phi_w)
     w_sp = rate.item() * cfg.dt * cfg.transit_steps / cfg.n_target
     kw = dict(dt=cfg.dt, E0=cfg.E0, w_sp=w_sp, phi_w=cfg.phi_w, seed=cfg.seed,
               tol=cfg.tol, resort_every=cfg.resort_every)
     gs.step(step0=0, n_steps=50, **kw)
     torch.cuda.synchronize()
-    return pic, cfg, om, gm, gs, kw
+    return pic, cfg, om, gm, gs, kw, (1e-12 if request.param == "fp64" else 1e-6)
 
 
 def _host(gs):
     n = int(gs.n_slots.item())
-    g = lambda t: t[:n].cpu().numpy()
+    g = lambda t: t[:n].cpu().numpy().astype(np.float64)
+    i = lambda t: t[:n].cpu().numpy()
     return dict(n=n, x=g(gs.x), y=g(gs.y), z=g(gs.z), vx=g(gs.vx), vy=g(gs.vy),
-                vz=g(gs.vz), w=g(gs.w), tet=g(gs.tet), id=g(gs.id),
-                phi=gs.phi.cpu().numpy(), E=gs.E.cpu().numpy().reshape(-1, 4)[:, :3],
+                vz=g(gs.vz), w=g(gs.w), tet=i(gs.tet), id=i(gs.id),
+                phi=gs.phi.cpu().numpy(),
+                E=gs.E.cpu().numpy().astype(np.float64).reshape(-1, 4)[:, :3],
                 charge=gs.charge.cpu().numpy())
 
 
-def _fields_and_charge(om, cfg, kw, S):
+def _fields_and_charge(om, cfg, kw, S, ftol):
     live = S["tet"] >= 0
     p = np.stack([S["x"], S["y"], S["z"]], 1)[live]
     c = om.deposit(p, S["tet"][live], S["w"][live])
@@ -71,21 +83,21 @@ def _fields_and_charge(om, cfg, kw, S):
     r = b - om.spmv(S["phi"][free])
     assert np.linalg.norm(r) <= 1.5 * cfg.tol * np.linalg.norm(b)
     E = om.field(S["phi"])
-    assert np.linalg.norm(E - S["E"]) <= 1e-12 * np.linalg.norm(E)
+    assert np.linalg.norm(E - S["E"]) <= ftol * np.linalg.norm(E)
 
 
 def test_production_step_sampled(setup):
-    pic, cfg, om, gm, gs, kw = setup
+    pic, cfg, om, gm, gs, kw, ftol = setup
     A = _host(gs)
     gs.step(step0=50, n_steps=1, **kw)
     B = _host(gs)
-    _fields_and_charge(om, cfg, kw, B)
+    _fields_and_charge(om, cfg, kw, B, ftol)
     # emission rate of the field the step started from
     r_dev, _ = gm.emission_rate(torch.from_numpy(
         np.concatenate([A["E"], np.zeros((len(A["E"]), 1))], 1).reshape(-1)).cuda(),
         cfg.phi_w)
     r_or, _ = om.emission_rate(A["E"], cfg.phi_w)
-    assert abs(r_dev.item() - r_or) <= 1e-12 * r_or
+    assert abs(r_dev.item() - r_or) <= ftol * r_or
     # one step of 3000 sampled pre-step superparticles
     live = np.flatnonzero(A["tet"] >= 0)
     rng = np.random.default_rng(11)
@@ -97,6 +109,11 @@ def test_production_step_sampled(setup):
     tets = om.tets()
     nodes = tets["tet"]
     survivors = []
+    # FP32 storage can put a particle on the other side of a decision
+    # boundary (anode plane, lateral wrap, metal surface) than the FP64
+    # replay when it lies within rounding of it: counted, none allowed
+    # in FP64, a few in mixed precision
+    mism = 0
     for i in pick:
         p = np.array([A["x"][i], A["y"][i], A["z"][i]])
         v = np.array([A["vx"][i], A["vy"][i], A["vz"][i]])
@@ -116,18 +133,21 @@ def test_production_step_sampled(setup):
         elif p[1] < 0.0:
             p[1] += Ly
         k = where_b.get(int(A["id"][i]))
-        if p[2] >= ztop:
-            assert k is None, "anode-absorbed on the device too"
+        if p[2] >= ztop:  # anode-absorbed on the device too
+            mism += k is not None
             continue
         if k is None:  # absorbed by the cathode: outside every vacuum tet
             tt, wh = om.locate(p[None, :])
-            assert tt[0] < 0 and wh[0] == 2
+            mism += not (tt[0] < 0 and wh[0] == 2)
             continue
         q = np.array([B["x"][k], B["y"][k], B["z"][k]])
-        assert np.abs(q - p).max() <= 1e-12 * max(1.0, np.abs(p).max())
+        if np.abs(q - p).max() > ftol * max(1.0, np.abs(p).max()):
+            mism += 1  # (wrapped on the other side)
+            continue
         assert np.abs(np.array([B["vx"][k], B["vy"][k], B["vz"][k]]) - v).max() \
-            <= 1e-12 * max(1.0, np.abs(v).max())
+            <= ftol * max(1.0, np.abs(v).max())
         survivors.append(k)
+    assert mism <= (0 if ftol < 1e-9 else 3), mism
     assert len(survivors) > 0.9 * len(pick)
     ks = np.array(survivors)
     pts = np.stack([B["x"][ks], B["y"][ks], B["z"][ks]], 1)
@@ -137,13 +157,13 @@ def test_production_step_sampled(setup):
 
 def test_production_multi_step_call(setup):
     """Ten steps in one call, ending with a re-sort."""
-    pic, cfg, om, gm, gs, kw = setup
+    pic, cfg, om, gm, gs, kw, ftol = setup
     gs.step(step0=51, n_steps=9, **kw)   # steps 51..59: (59 + 1) % 10 == 0
     torch.cuda.synchronize()
     C = _host(gs)
     assert (C["tet"] >= 0).all() and (np.diff(C["tet"]) >= 0).all()
     assert C["n"] > 500_000
-    _fields_and_charge(om, cfg, kw, C)
+    _fields_and_charge(om, cfg, kw, C, ftol)
     # canonical location of a sample after the multi-step call
     rng = np.random.default_rng(12)
     ks = rng.choice(C["n"], size=3000, replace=False)
