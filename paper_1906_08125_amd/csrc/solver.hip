@@ -444,6 +444,10 @@ __device__ inline void k_cg_start_body(const CgArgs& a, int64_t seq, VB vb) {
   }
   if (bn == 0.0) {
     const DevMesh& m = a.m;
+    // phi = 0 solves it; its residual (b = 0) is 0, which is what the next
+    // solve's incremental first pass builds on
+    const Range fr = my_range(m.n_free, vb);
+    for (int64_t i = fr.lo + threadIdx.x; i < fr.hi; i += blockDim.x) a.r[i] = 0.0;
     const Range nr = my_range(m.n_nodes, vb);
     for (int64_t i = nr.lo + threadIdx.x; i < nr.hi; i += blockDim.x) {
       a.phi[i] = 0.0;
