@@ -1020,10 +1020,10 @@ pic_status pic_batch_step(pic_batch* b, const pic_particles* P,
       ea.stats = st;
       fp::CgArgs ca = ss.ca;
       ca.step_stats = st;
+      // as in pic_step: the field and the true residual of the previous
+      // solve still hold, so the first pass needs no product with K or R
       ca.keep_field = k > 0 ? 1 : 0;
-    // and its true residual and right-hand side: the first pass of this
-    // solve needs no product with K
-    ca.incremental = k > 0 ? 1 : 0;  // as in pic_step
+      ca.incremental = k > 0 ? 1 : 0;
       std::memcpy(base + sa * i, &a, sa);
       std::memcpy(base + sa * n + se * i, &ea, se);
       std::memcpy(base + (sa + se) * n + sg * i, &ca, sg);
@@ -1111,7 +1111,7 @@ pic_status pic_batch_step(pic_batch* b, const pic_particles* P,
       if (mask && (r = fp::cg_batch_recheck(ca, grid, s)) != hipSuccess) return r;
       return fp::cg_batch_iters(ca, grid, count, s);
     };
-    if ((e = fp::cg_batch_begin(cb, m_cg.off[m_cg.n_seg], s)) != hipSuccess ||
+    if ((e = fp::cg_batch_begin(cb, m_cg.off[m_cg.n_seg], k > 0 ? 1 : 0, s)) != hipSuccess ||
         (spec > 0 && (e = iterate(spec_on, 0, 0, &spec_n)) != hipSuccess) ||
         (e = fp::cg_batch_report(cb, n, seq, s)) != hipSuccess ||
         (e = hipEventRecord(b->reported, s)) != hipSuccess ||

@@ -101,7 +101,10 @@ struct CgBatch {
   BatchMap map;
   uint64_t mask;
 };
-hipError_t cg_batch_begin(const CgBatch& b, int grid, hipStream_t s);
+// incremental: every instance's first pass forms its residual from its
+// previous solve (CgArgs::incremental; all instances alike)
+hipError_t cg_batch_begin(const CgBatch& b, int grid, int incremental,
+                          hipStream_t s);
 hipError_t cg_batch_iters(const CgBatch& b, int grid, int n, hipStream_t s);
 hipError_t cg_batch_recheck(const CgBatch& b, int grid, hipStream_t s);
 // reports instances 0 .. n - 1 (all of the batch, whatever the map)

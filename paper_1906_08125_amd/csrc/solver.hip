@@ -635,6 +635,12 @@ __global__ void __launch_bounds__(kCgBlock) k_cg_resfield_b(CgBatch b, int reset
   const CgArgs a = b.args[i];  // a private copy: no aliasing with the stores
   k_cg_resfield_body(a, reset, vb);
 }
+__global__ void __launch_bounds__(kCgBlock) k_cg_resinc_b(CgBatch b) {
+  int i;
+  const VB vb = batch_block(b.map, i);
+  const CgArgs a = b.args[i];
+  k_cg_resinc_body(a, vb);
+}
 __global__ void __launch_bounds__(kCgBlock) k_cg_scatter_b(CgBatch b) {
   int i;
   const VB vb = batch_block(b.map, i);
@@ -959,8 +965,12 @@ hipError_t cg_launch_recheck(const CgArgs& a, int64_t seq, hipStream_t s) {
     if (e_ != hipSuccess) return e_;                                          \
   } while (0)
 
-hipError_t cg_batch_begin(const CgBatch& b, int grid, hipStream_t s) {
-  BLAUNCH(k_cg_resfield_b, b, 1, 0);
+hipError_t cg_batch_begin(const CgBatch& b, int grid, int incremental,
+                          hipStream_t s) {
+  if (incremental)
+    BLAUNCH(k_cg_resinc_b, b);
+  else
+    BLAUNCH(k_cg_resfield_b, b, 1, 0);
   BLAUNCH(k_cg_start_b, b, 0);
   return hipSuccess;
 }
