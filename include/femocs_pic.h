@@ -201,6 +201,16 @@ typedef struct {
   int64_t* charge;  /* device [n_nodes] fixed-point charge of last step   */
 } pic_fields;
 
+/* Field the particles see (the paper's gather interpolates "with the      */
+/* element's shape functions", which leaves open which field):              */
+/*   PIC_FIELD_NODAL  E(r) = sum_i lambda_i(r) E_i with the nodal field     */
+/*                    E_i of fields->E (default);                          */
+/*   PIC_FIELD_CELL   E(r) = -(grad phi)_t, constant in the tet t holding   */
+/*                    r, from fields->phi; the injection field is that of   */
+/*                    the emitting face's tet, and so is the field the FN   */
+/*                    current is evaluated at.                              */
+enum { PIC_FIELD_NODAL = 0, PIC_FIELD_CELL = 1 };
+
 typedef struct {
   double dt;        /* time step (fs)                                     */
   double E0;        /* applied field (V/nm)                               */
@@ -212,7 +222,7 @@ typedef struct {
   int64_t instance; /* Philox key word 1                                  */
   const double* s_face; /* device [n_emit] weight per emitting face or NULL */
   int32_t resort_every; /* sort by tet + compact every k steps (0: never) */
-  int32_t pad;
+  int32_t field_mode;   /* PIC_FIELD_NODAL or PIC_FIELD_CELL              */
   pic_solve_params solve;
 } pic_step_params;
 
@@ -275,6 +285,8 @@ PIC_API pic_status emission_rate(const pic_mesh* mesh, const double* E, double p
 /* in Eb, the adjoint of E_{k+1} from the gathers of step k + 1; out: the   */
 /* adjoint of the pre-step state (pre slots; later slots zeroed) and, in    */
 /* Eb, that of E_k from this step's gathers.  dJ_dE0 and dJ_ds accumulate.  */
+/* Only the nodal field mode (PIC_FIELD_NODAL) has an adjoint: another     */
+/* field_mode is PIC_E_ARG.                                                 */
 /* mode PIC_ADJ_INITIAL ends a window: the reverse of the solve that gave   */
 /* phi_0 from the charge of pre and E0 (Eb in: adjoint of E_0; post, Fk1    */
 /* unused; rb, vb untouched).  mu: device [n_nodes] adjoint potential,      */

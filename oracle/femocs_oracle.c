@@ -939,25 +939,41 @@ int om_poisson_solve(const omesh* m, const int64_t* c, double w_sp, double E0,
   return status;
 }
 
+/* Gradient of the linear-element potential in tet t: grad lambda_k are
+ * the rows m_k (k = 1..3) and grad lambda_0 = -(m_1 + m_2 + m_3). */
+static void tet_grad(const omesh* m, int64_t t, const double* phi,
+                     double* grad) {
+  const double* mm = m->mm + 9 * t;
+  const int32_t* tv = m->tet + 4 * t;
+  for (int k = 0; k < 3; ++k) {
+    const double g0 = -((mm[k] + mm[3 + k]) + mm[6 + k]);
+    grad[k] = ((phi[tv[0]] * g0 + phi[tv[1]] * mm[k]) +
+               phi[tv[2]] * mm[3 + k]) + phi[tv[3]] * mm[6 + k];
+  }
+}
+
+/* Cell field (reading R2, cell variant): E = -(grad phi)_t, constant in
+ * tet t. */
+static void cell_field(const omesh* m, int64_t t, const double* phi,
+                       double* E) {
+  double grad[3];
+  tet_grad(m, t, phi, grad);
+  for (int k = 0; k < 3; ++k) E[k] = -grad[k];
+}
+
+void om_cell_field(const omesh* m, const double* phi, double* E3t) {
+  for (int64_t t = 0; t < m->n_tets; ++t) cell_field(m, t, phi, E3t + 3 * t);
+}
+
 /* Nodal field (reading of Sec. II B 2: the field interpolated with the
  * element's shape functions needs nodal values): E_i = sum_t V_t (-grad
  * phi)_t / sum_t V_t over the tets holding node i. */
 void om_field(const omesh* m, const double* phi, double* E3) {
   double* acc = (double*)calloc(3 * m->n_nodes, sizeof(double));
   for (int64_t t = 0; t < m->n_tets; ++t) {
-    const double* mm = m->mm + 9 * t;
     const int32_t* tv = m->tet + 4 * t;
-    double g[4][3];
-    for (int k = 0; k < 3; ++k) {
-      g[1][k] = mm[k];
-      g[2][k] = mm[3 + k];
-      g[3][k] = mm[6 + k];
-      g[0][k] = -((mm[k] + mm[3 + k]) + mm[6 + k]);
-    }
     double grad[3];
-    for (int k = 0; k < 3; ++k)
-      grad[k] = ((phi[tv[0]] * g[0][k] + phi[tv[1]] * g[1][k]) +
-                 phi[tv[2]] * g[2][k]) + phi[tv[3]] * g[3][k];
+    tet_grad(m, t, phi, grad);
     double V = m->D[t] / 6.0;
     for (int a = 0; a < 4; ++a)
       for (int k = 0; k < 3; ++k) acc[3 * (int64_t)tv[a] + k] += V * (-grad[k]);
@@ -1007,36 +1023,51 @@ static void face_centroid_field(const omesh* m, int64_t f, const double* E3,
 }
 
 /* emission current density of face f in e nm^-2 fs^-1 (0 when the field
- * does not pull electrons out of the metal), and |E| at the centroid */
+ * does not pull electrons out of the metal), and |E| at the centroid; the
+ * centroid field is the nodal one, or with phi (cell mode) the field of the
+ * face's vacuum tet */
 static double face_emission(const omesh* m, int64_t f, const double* E3,
-                            double phi_w, double* F_out, int* clamped) {
+                            const double* phi, double phi_w, double* F_out,
+                            int* clamped) {
   consts_t k = constants();
   double Ec[3];
-  face_centroid_field(m, f, E3, Ec);
+  if (phi)
+    cell_field(m, m->e_tet[f], phi, Ec);
+  else
+    face_centroid_field(m, f, E3, Ec);
   double F = sqrt(vdot(Ec, Ec));
   if (F_out) *F_out = F;
   if (!(vdot(Ec, m->e_nrm + 3 * f) < 0.0)) return 0.0;
   return om_fn_current(F, phi_w, clamped) * k.j_unit;
 }
 
-double om_emission_rate(const omesh* m, const double* E3, double phi_w,
-                        double* faceF) {
+double om_emission_rate_mode(const omesh* m, const double* E3,
+                             const double* phi, double phi_w, double* faceF) {
   double tot = 0.0;
   for (int64_t f = 0; f < m->n_emit; ++f) {
     int cl = 0;
     double F;
-    double j = face_emission(m, f, E3, phi_w, &F, &cl);
+    double j = face_emission(m, f, E3, phi, phi_w, &F, &cl);
     if (faceF) faceF[f] = F;
     tot += j * m->e_area[f];
   }
   return tot;
 }
 
+double om_emission_rate(const omesh* m, const double* E3, double phi_w,
+                        double* faceF) {
+  return om_emission_rate_mode(m, E3, NULL, phi_w, faceF);
+}
+
 /* ------------------------------------------------------------------------ */
 /* One PIC step (Sec. II B 1-3; Fig. 3 ordering).                            */
 /* ------------------------------------------------------------------------ */
 static void gather(const omesh* m, int32_t t, const double* p,
-                   const double* E3, double* Ep) {
+                   const double* E3, const double* phi_cell, double* Ep) {
+  if (phi_cell) {
+    cell_field(m, t, phi_cell, Ep);
+    return;
+  }
   double lam[4];
   om_lambda(m, t, p, lam);
   const int32_t* tv = m->tet + 4 * (int64_t)t;
@@ -1061,12 +1092,13 @@ int om_inject(const omesh* m, oparticles* P, const double* E3,
               int64_t* counts) {
   consts_t K = constants();
   const double dt = prm->dt;
+  const double* phi_cell = prm->field_mode == 1 ? prm->phi : NULL;
   double Fsum = 0.0, Fmax = 0.0;
   int64_t n = P->n;
   for (int64_t f = 0; f < m->n_emit; ++f) {
     int cl = 0;
     double F;
-    double jd = face_emission(m, f, E3, prm->phi_w, &F, &cl) * prm->j_scale;
+    double jd = face_emission(m, f, E3, phi_cell, prm->phi_w, &F, &cl) * prm->j_scale;
     st->n_clamp += cl;
     Fsum += F;
     if (F > Fmax) Fmax = F;
@@ -1107,6 +1139,7 @@ int om_inject(const omesh* m, oparticles* P, const double* E3,
         Ex[k] = (l0 * E3[3 * (int64_t)nd[0] + k] + R1 * E3[3 * (int64_t)nd[1] + k]) +
                 R2 * E3[3 * (int64_t)nd[2] + k];
       }
+      if (phi_cell) cell_field(m, m->e_tet[f], phi_cell, Ex);
       double cv = (K.qm * dt) * (0.5 + Rf); /* Eq. sp_velocity */
       for (int k = 0; k < 3; ++k) {
         v0[k] = cv * Ex[k];
@@ -1154,9 +1187,13 @@ int om_pic_step(const omesh* m, oparticles* P, double* phi, double* E3,
 
   /* 1. gather E_k at r_k and kick: v <- (v + Q E) + Q E (Eq. leapfrog3 of
    *    the previous step followed by Eq. leapfrog1 of this one) */
+  ostep_params pr = *prm;  /* the potential of step k for the cell mode */
+  pr.phi = phi;
+  prm = &pr;
+  const double* phi_cell = prm->field_mode == 1 ? phi : NULL;
   for (int64_t i = 0; i < n0; ++i) {
     double p[3] = {P->x[i], P->y[i], P->z[i]}, Ep[3];
-    gather(m, P->tet[i], p, E3, Ep);
+    gather(m, P->tet[i], p, E3, phi_cell, Ep);
     double qe0 = Q * Ep[0], qe1 = Q * Ep[1], qe2 = Q * Ep[2];
     P->vx[i] = (P->vx[i] + qe0) + qe0;
     P->vy[i] = (P->vy[i] + qe1) + qe1;

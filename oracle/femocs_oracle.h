@@ -108,7 +108,7 @@ typedef struct {
   int64_t step;
   int64_t instance;
   int32_t max_iter;
-  int32_t pad;
+  int32_t field_mode;   /* 0 nodal field, 1 cell field (reading R2) */
   const double* s_face; /* per emitting face weight multiplier or NULL */
   /* frozen emission counts per emitting face (replace Eq. nsp and
    * Eq. rnd_nsp) or NULL; the counts used are written to counts_out */
@@ -119,6 +119,9 @@ typedef struct {
    * injected ones (index - n_before), (R1, R2, R, face) */
   int8_t* fate_out;
   double* inj_out;
+  /* the potential phi_k (cell field mode: the field of tet t is
+   * -(grad phi_k)_t); om_pic_step sets it to its own phi */
+  const double* phi;
 } ostep_params;
 
 typedef struct {
@@ -142,6 +145,14 @@ int om_pic_step(const omesh* m, oparticles* p, double* phi, double* E3,
  * current sum_f J_f A_f in e/fs, per-face |E| at centroids. */
 double om_emission_rate(const omesh* m, const double* E3, double phi_w,
                         double* faceF);
+/* The same with phi non-null: the cell field mode (each face at the field
+ * of its vacuum tet). */
+double om_emission_rate_mode(const omesh* m, const double* E3,
+                             const double* phi, double phi_w, double* faceF);
+
+/* Cell field of every tet (reading R2, cell variant): E3t [T][3] =
+ * -(grad phi)_t. */
+void om_cell_field(const omesh* m, const double* phi, double* E3t);
 
 #ifdef __cplusplus
 }

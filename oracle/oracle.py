@@ -71,6 +71,7 @@ def lib():
     L.om_rhs.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_double, _dp]
     L.om_spmv.argtypes = [C.c_void_p, _dp, _dp]
     L.om_field.argtypes = [C.c_void_p, _dp, _dp]
+    L.om_cell_field.argtypes = [C.c_void_p, _dp, _dp]
     L.om_field_adj.argtypes = [C.c_void_p, _dp, _dp]
     L.om_fn_current.restype = C.c_double
     L.om_fn_current.argtypes = [C.c_double, C.c_double, C.POINTER(C.c_int)]
@@ -84,6 +85,9 @@ def lib():
                             C.c_void_p, C.c_void_p, C.c_void_p]
     L.om_emission_rate.restype = C.c_double
     L.om_emission_rate.argtypes = [C.c_void_p, _dp, C.c_double, C.c_void_p]
+    L.om_emission_rate_mode.restype = C.c_double
+    L.om_emission_rate_mode.argtypes = [C.c_void_p, _dp, C.c_void_p, C.c_double,
+                                        C.c_void_p]
     _lib = L
     return L
 
@@ -101,9 +105,10 @@ class _StepParams(C.Structure):
                 ("phi_w", C.c_double), ("j_scale", C.c_double),
                 ("tol", C.c_double), ("seed", C.c_uint64), ("step", C.c_int64),
                 ("instance", C.c_int64), ("max_iter", C.c_int32),
-                ("pad", C.c_int32), ("s_face", C.c_void_p),
+                ("field_mode", C.c_int32), ("s_face", C.c_void_p),
                 ("counts_in", C.c_void_p), ("counts_out", C.c_void_p),
-                ("fate_out", C.c_void_p), ("inj_out", C.c_void_p)]
+                ("fate_out", C.c_void_p), ("inj_out", C.c_void_p),
+                ("phi", C.c_void_p)]
 
 
 class _StepStats(C.Structure):
@@ -274,16 +279,30 @@ class OracleMesh:
             np.asarray(Ebar, np.float64).reshape(-1)), out)
         return out
 
+    def cell_field(self, phi):
+        """Field of every tet in the cell reading (R2): -(grad phi)_t."""
+        E = np.zeros((self.n_tets, 3))
+        lib().om_cell_field(self._h, np.ascontiguousarray(phi, np.float64),
+                            E.reshape(-1))
+        return E
+
     def field(self, phi):
         E = np.zeros((self.n_nodes, 3))
         lib().om_field(self._h, np.ascontiguousarray(phi, np.float64),
                        E.reshape(-1))
         return E
 
-    def emission_rate(self, E, phi_w):
+    def emission_rate(self, E, phi_w, phi=None):
+        """Total emission current and per-face |E|: at the nodal field E, or
+        (phi given) in the cell field mode, each face at its tet's field."""
         F = np.zeros(max(self.n_emit, 1))
-        r = lib().om_emission_rate(self._h, np.ascontiguousarray(E.reshape(-1)),
-                                   float(phi_w), F.ctypes.data)
+        E = np.ascontiguousarray(E.reshape(-1), dtype=np.float64)
+        if phi is None:
+            r = lib().om_emission_rate(self._h, E, float(phi_w), F.ctypes.data)
+        else:
+            phi = np.ascontiguousarray(phi, dtype=np.float64)
+            r = lib().om_emission_rate_mode(self._h, E, phi.ctypes.data,
+                                            float(phi_w), F.ctypes.data)
         return r, F[: self.n_emit]
 
 
@@ -324,7 +343,7 @@ class OracleState:
 
     def step(self, *, dt, E0, w_sp, phi_w, step, seed, instance=0,
              j_scale=1.0, tol=1e-12, max_iter=20000, s_face=None,
-             counts_in=None, detail=None) -> dict:
+             counts_in=None, detail=None, field_mode=0) -> dict:
         """One PIC step.  counts_in: frozen emission counts per face.
         detail: a dict that receives the counts used, the fate of every
         particle of the step (pre-step particles, then the injected ones:
@@ -336,6 +355,7 @@ class OracleState:
         pr.j_scale, pr.tol = j_scale, tol
         pr.seed, pr.step, pr.instance = seed, step, instance
         pr.max_iter = max_iter
+        pr.field_mode = field_mode
         sf = ci = None
         if s_face is not None:
             sf = np.ascontiguousarray(s_face, np.float64)
@@ -367,7 +387,7 @@ class OracleState:
         return out
 
     def inject(self, *, dt, E0, w_sp, phi_w, step, seed, instance=0,
-               j_scale=1.0, s_face=None):
+               j_scale=1.0, s_face=None, field_mode=0):
         """Injection alone (appends to the state); returns the stats, the
         per-face rounded counts and the sampled face points of the new
         particles."""
@@ -375,6 +395,8 @@ class OracleState:
         pr = _StepParams()
         pr.dt, pr.E0, pr.w_sp, pr.phi_w = dt, E0, w_sp, phi_w
         pr.j_scale, pr.seed, pr.step, pr.instance = j_scale, seed, step, instance
+        pr.field_mode = field_mode
+        pr.phi = self.phi.ctypes.data
         sf = None
         if s_face is not None:
             sf = np.ascontiguousarray(s_face, np.float64)

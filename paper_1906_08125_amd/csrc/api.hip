@@ -357,6 +357,8 @@ pic_status check_step(const pic_particles* P, const pic_fields* F,
       !finite_pos(prm->phi_w) || !std::isfinite(prm->j_scale) || prm->j_scale < 0 ||
       prm->step0 < 0 || prm->step0 + n_steps >= (1ll << 21) || prm->resort_every < 0)
     return fail(PIC_E_ARG, w + ": invalid step parameters");
+  if (prm->field_mode != PIC_FIELD_NODAL && prm->field_mode != PIC_FIELD_CELL)
+    return fail(PIC_E_ARG, w + ": unknown field mode");
   return check_solve(&prm->solve);
 }
 
@@ -389,6 +391,8 @@ StepSet step_set(pic_mesh* h, const pic_particles* P, const pic_fields* F,
   a.id = P->id;
   a.n_slots = P->n_slots;
   a.E = F->E;
+  a.cell = prm->field_mode == PIC_FIELD_CELL;
+  a.phi = F->phi;
   a.charge = F->charge;
   a.s_face = prm->s_face;
   a.offsets = h->offsets;
@@ -409,6 +413,8 @@ StepSet step_set(pic_mesh* h, const pic_particles* P, const pic_fields* F,
   ea.m = h->dm;
   ea.E = F->E;
   ea.f32 = f32;
+  ea.cell = a.cell;
+  ea.phi = F->phi;
   ea.c = {ph.a_fn, ph.b_fn, ph.c_s, ph.j_unit};
   ea.phi_w = prm->phi_w;
   ea.j_scale = prm->j_scale;
@@ -764,6 +770,8 @@ pic_status adjoint_step(pic_mesh* h, const pic_particles* pre,
     return fail(PIC_E_ARG, "adjoint_step: capacity must be in [1, 2^31)");
   if (!finite_pos(prm->dt) || !finite_pos(prm->w_sp))
     return fail(PIC_E_ARG, "adjoint_step: invalid step parameters");
+  if (prm->field_mode != PIC_FIELD_NODAL)
+    return fail(PIC_E_ARG, "adjoint_step: only the nodal field mode has an adjoint");
   pic_status ps = check_solve(&prm->solve);
   if (ps != PIC_OK) return ps;
   const pic_particles* Q = initial ? pre : post;

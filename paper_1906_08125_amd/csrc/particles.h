@@ -38,6 +38,9 @@ struct StepArgs {
   // that solve's outcome is known does nothing unless the solve has ended
   // (CG_DONE or CG_NOCONV)
   const int32_t* gate;
+  // cell field mode: the field in tet t is -(grad phi)_t, from phi
+  int cell;
+  const double* phi;
 };
 
 struct EmitArgs {
@@ -62,6 +65,8 @@ struct EmitArgs {
   // the emission counts are computed by the first workgroup of the particle
   // kernel (launch_particles with these arguments), not by k_begin
   int defer;
+  int cell;               // as StepArgs::cell (face field of the face's tet)
+  const double* phi;
 };
 
 struct LocateArgs {

@@ -124,6 +124,24 @@ __device__ inline void gather_field(const TetGeom& g, const void* E,
   ez = ((lam[0] * e0.z + lam[1] * e1.z) + lam[2] * e2.z) + lam[3] * e3.z;
 }
 
+// Cell field of a tet (cell mode): E = -(grad phi)_t with grad lambda_k the
+// rows m_k (k = 1..3) and grad lambda_0 = -(m_1 + m_2 + m_3), summed in a
+// fixed order.
+__device__ inline void cell_field(const TetGeom& g, const double* phi,
+                                  double& ex, double& ey, double& ez) {
+  const double p0 = phi[g.node[0]], p1 = phi[g.node[1]], p2 = phi[g.node[2]],
+               p3 = phi[g.node[3]];
+  double e[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double g0 = -((g.m[k] + g.m[3 + k]) + g.m[6 + k]);
+    e[k] = -(((p0 * g0 + p1 * g.m[k]) + p2 * g.m[3 + k]) + p3 * g.m[6 + k]);
+  }
+  ex = e[0];
+  ey = e[1];
+  ez = e[2];
+}
+
 __device__ inline void deposit_one(const TetGeom& g, double x, double y,
                                    double z, double w, int64_t* charge) {
   double lam[4];
@@ -457,7 +475,10 @@ __device__ void emit_block(const EmitArgs& a) {
     int clamped = 0;
     if (f < m.n_emit) {
       double ex, ey, ez;
-      face_field(m, a.E, a.f32, f, ex, ey, ez);
+      if (a.cell)
+        cell_field(m.tg[m.e_tet[f]], a.phi, ex, ey, ez);
+      else
+        face_field(m, a.E, a.f32, f, ex, ey, ez);
       F = sqrt((ex * ex + ey * ey) + ez * ez);
       const double* nr = m.e_nrm + 3 * f;
       const double en = (ex * nr[0] + ey * nr[1]) + ez * nr[2];
@@ -626,7 +647,10 @@ __device__ inline void push_role64(const StepArgs& a, int g, int G, Acc& acc,
     double vx = VX[i], vy = VY[i], vz = VZ[i];
     TetGeom G = m.tg[t];
     double ex, ey, ez;
-    gather_field(G, a.E, x, y, z, ex, ey, ez);
+    if (a.cell)
+      cell_field(G, a.phi, ex, ey, ez);
+    else
+      gather_field(G, a.E, x, y, z, ex, ey, ez);
     const double qx = Q * ex, qy = Q * ey, qz = Q * ez;
     vx = (vx + qx) + qx;
     vy = (vy + qy) + qy;
@@ -678,16 +702,29 @@ __device__ inline void push_role32(const StepArgs& a, int g, int G, Acc& acc,
     // FP32 gather from the FP32 record (half the bytes of the FP64 one,
     // which the walk loads only when it needs the hint tet itself)
     const TetGeom32 G32 = m.tg32[t];
-    const float dx0 = x - G32.v0[0], dy0 = y - G32.v0[1], dz0 = z - G32.v0[2];
-    const float l1 = (G32.m[0] * dx0 + G32.m[1] * dy0) + G32.m[2] * dz0;
-    const float l2 = (G32.m[3] * dx0 + G32.m[4] * dy0) + G32.m[5] * dz0;
-    const float l3 = (G32.m[6] * dx0 + G32.m[7] * dy0) + G32.m[8] * dz0;
-    const float l0 = ((1.0f - l1) - l2) - l3;
-    const float4 e0 = E[G32.node[0]], e1 = E[G32.node[1]],
-                 e2 = E[G32.node[2]], e3 = E[G32.node[3]];
-    const float ex = ((l0 * e0.x + l1 * e1.x) + l2 * e2.x) + l3 * e3.x;
-    const float ey = ((l0 * e0.y + l1 * e1.y) + l2 * e2.y) + l3 * e3.y;
-    const float ez = ((l0 * e0.z + l1 * e1.z) + l2 * e2.z) + l3 * e3.z;
+    float ex, ey, ez;
+    if (a.cell) {
+      // -(grad phi)_t from the potential differences to vertex 0 (FP64
+      // differences, FP32 products: no cancellation of the potential's size)
+      const double p0 = a.phi[G32.node[0]];
+      const float d1 = (float)(a.phi[G32.node[1]] - p0);
+      const float d2 = (float)(a.phi[G32.node[2]] - p0);
+      const float d3 = (float)(a.phi[G32.node[3]] - p0);
+      ex = -((d1 * G32.m[0] + d2 * G32.m[3]) + d3 * G32.m[6]);
+      ey = -((d1 * G32.m[1] + d2 * G32.m[4]) + d3 * G32.m[7]);
+      ez = -((d1 * G32.m[2] + d2 * G32.m[5]) + d3 * G32.m[8]);
+    } else {
+      const float dx0 = x - G32.v0[0], dy0 = y - G32.v0[1], dz0 = z - G32.v0[2];
+      const float l1 = (G32.m[0] * dx0 + G32.m[1] * dy0) + G32.m[2] * dz0;
+      const float l2 = (G32.m[3] * dx0 + G32.m[4] * dy0) + G32.m[5] * dz0;
+      const float l3 = (G32.m[6] * dx0 + G32.m[7] * dy0) + G32.m[8] * dz0;
+      const float l0 = ((1.0f - l1) - l2) - l3;
+      const float4 e0 = E[G32.node[0]], e1 = E[G32.node[1]],
+                   e2 = E[G32.node[2]], e3 = E[G32.node[3]];
+      ex = ((l0 * e0.x + l1 * e1.x) + l2 * e2.x) + l3 * e3.x;
+      ey = ((l0 * e0.y + l1 * e1.y) + l2 * e2.y) + l3 * e3.y;
+      ez = ((l0 * e0.z + l1 * e1.z) + l2 * e2.z) + l3 * e3.z;
+    }
     const float qx = Q * ex, qy = Q * ey, qz = Q * ez;
     vx = (vx + qx) + qx;
     vy = (vy + qy) + qy;
@@ -751,16 +788,21 @@ __device__ inline void inject_role(const StepArgs& a, int g, int G, Acc& acc,
     }
     const double l0 = (1.0 - R1) - R2;
     const double* A = m.e_abc + 9 * (int64_t)f;
-    const int32_t* nd = m.e_nodes + 3 * (int64_t)f;
-    const double4 ea = ld_E(a.E, a.f32, nd[0]);
-    const double4 eb = ld_E(a.E, a.f32, nd[1]);
-    const double4 ec = ld_E(a.E, a.f32, nd[2]);
     const double px = (A[0] + R1 * (A[3] - A[0])) + R2 * (A[6] - A[0]);
     const double py = (A[1] + R1 * (A[4] - A[1])) + R2 * (A[7] - A[1]);
     const double pz = (A[2] + R1 * (A[5] - A[2])) + R2 * (A[8] - A[2]);
-    const double Ex = (l0 * ea.x + R1 * eb.x) + R2 * ec.x;
-    const double Ey = (l0 * ea.y + R1 * eb.y) + R2 * ec.y;
-    const double Ez = (l0 * ea.z + R1 * eb.z) + R2 * ec.z;
+    double Ex, Ey, Ez;
+    if (a.cell) {
+      cell_field(m.tg[m.e_tet[f]], a.phi, Ex, Ey, Ez);
+    } else {
+      const int32_t* nd = m.e_nodes + 3 * (int64_t)f;
+      const double4 ea = ld_E(a.E, a.f32, nd[0]);
+      const double4 eb = ld_E(a.E, a.f32, nd[1]);
+      const double4 ec = ld_E(a.E, a.f32, nd[2]);
+      Ex = (l0 * ea.x + R1 * eb.x) + R2 * ec.x;
+      Ey = (l0 * ea.y + R1 * eb.y) + R2 * ec.y;
+      Ez = (l0 * ea.z + R1 * eb.z) + R2 * ec.z;
+    }
     const double cv = a.qm_dt * (0.5 + R);
     const double vx = cv * Ex, vy = cv * Ey, vz = cv * Ez;
     double x = px + (vx * dt) * R;

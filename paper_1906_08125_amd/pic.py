@@ -18,6 +18,7 @@ PIC_OK, PIC_E_ARG, PIC_E_DEVICE, PIC_E_MESH = 0, -1, -2, -3
 PIC_E_NOCONV, PIC_E_CAPACITY, PIC_E_NUMERIC = -4, -5, -6
 PIC_FP64, PIC_MIXED = 0, 1
 PIC_PRECOND_JACOBI, PIC_PRECOND_AMG = 0, 1
+PIC_FIELD_NODAL, PIC_FIELD_CELL = 0, 1
 CHARGE_SCALE = float(2 ** 40)
 
 
@@ -68,7 +69,7 @@ class StepParams(C.Structure):
                 ("phi_w", C.c_double), ("j_scale", C.c_double),
                 ("seed", C.c_uint64), ("step0", C.c_int64),
                 ("instance", C.c_int64), ("s_face", C.c_void_p),
-                ("resort_every", C.c_int32), ("pad", C.c_int32),
+                ("resort_every", C.c_int32), ("field_mode", C.c_int32),
                 ("solve", SolveParams)]
 
 
@@ -334,14 +335,14 @@ class State:
 
     def step(self, *, dt, E0, w_sp, phi_w, step0, seed, n_steps=1, instance=0,
              j_scale=1.0, tol=1e-12, max_iter=20000, s_face=None,
-             resort_every=0, stats=None):
+             resort_every=0, field_mode=PIC_FIELD_NODAL, stats=None):
         torch = _torch()
         if stats is None:
             stats = torch.zeros(n_steps * STEP_STATS_BYTES // 8,
                                 dtype=torch.int64, device=self.phi.device)
         prm = StepParams(dt, E0, w_sp, phi_w, j_scale, seed, step0, instance,
                          None if s_face is None else s_face.data_ptr(),
-                         resort_every, 0,
+                         resort_every, field_mode,
                          SolveParams(tol, self.inner_tol, max_iter,
                                      self.solve_precision, self.precond))
         _check(load_library().pic_step(self.mesh.handle, C.byref(self._p),
@@ -627,7 +628,8 @@ class Batch:
             prms.append(StepParams(
                 kw["dt"], kw["E0"], kw["w_sp"], kw["phi_w"], kw.get("j_scale", 1.0),
                 kw["seed"], step0, kw.get("instance", 0),
-                None if sf is None else sf.data_ptr(), kw.get("resort_every", 0), 0,
+                None if sf is None else sf.data_ptr(), kw.get("resort_every", 0),
+                kw.get("field_mode", PIC_FIELD_NODAL),
                 SolveParams(kw.get("tol", 1e-10), st.inner_tol,
                             kw.get("max_iter", 20000), st.solve_precision)))
         S = (StepParams * n)(*prms)

@@ -213,7 +213,7 @@ def test_emission_rate_matches_oracle(pic):
 
 def _run_pair(pic, cfg, n_steps, live_charge, n_live, cap, seed=None,
               resort_every=0, precision=0, solve_precision=None,
-              phi_err=None, precond=0):
+              phi_err=None, precond=0, field_mode=0):
     """live_charge: electrons in flight wanted (None = physical emission).
     phi_err: a list that receives the relative L2 distance of the device
     potential from the oracle's after every step."""
@@ -221,7 +221,8 @@ def _run_pair(pic, cfg, n_steps, live_charge, n_live, cap, seed=None,
     om = O.OracleMesh(tip, cfg.emit_zmin)
     ost = O.OracleState(om, cap)
     ost.init_field(cfg.E0, tol=cfg.tol)
-    rate, _ = om.emission_rate(ost.E, cfg.phi_w)
+    rate, _ = om.emission_rate(ost.E, cfg.phi_w,
+                               ost.phi if field_mode == 1 else None)
     per_run = rate * cfg.dt * cfg.transit_steps
     j_scale = 1.0 if live_charge is None else live_charge / per_run
     w_sp = per_run * j_scale / n_live
@@ -234,9 +235,10 @@ def _run_pair(pic, cfg, n_steps, live_charge, n_live, cap, seed=None,
               tol=cfg.tol)
     so_all, sg_all = [], []
     for k in range(n_steps):
-        so_all.append(ost.step(step=k, **kw))
+        so_all.append(ost.step(step=k, field_mode=field_mode, **kw))
         sg_all.append(pic.State.decode_stats(
-            gs.step(step0=k, resort_every=resort_every, **kw))[0])
+            gs.step(step0=k, resort_every=resort_every, field_mode=field_mode,
+                    **kw))[0])
         if phi_err is not None:
             phi_err.append(_rel(gs.phi.cpu().numpy(), ost.phi))
     torch.cuda.synchronize()
@@ -309,6 +311,61 @@ def test_pic_step_space_charge_amg(pic):
                                         precond=pic.PIC_PRECOND_AMG)
     assert sum(s["cg_iters"] for s in sg) < sum(s["cg_iters"] for s in so)
     _compare_runs(ost, gs, so, sg, same_solver=False)
+
+
+def test_pic_step_cell_field(pic):
+    """The cell field mode (E = -(grad phi)_t in the particle's tet; the
+    emitting face's tet for the FN current and the injection velocity) with
+    space charge and re-sorting: every count, charge and particle as in the
+    oracle's cell mode."""
+    cfg = W.config_tiny()
+    om, ost, gm, gs, so, sg = _run_pair(pic, cfg, 24, 0.01, 3000, 60_000,
+                                        resort_every=5,
+                                        field_mode=pic.PIC_FIELD_CELL)
+    assert sum(s["n_inj"] for s in sg) > 1000
+    assert all(s["cg_iters"] > 0 for s in sg[1:])
+    _compare_runs(ost, gs, so, sg)
+
+
+def test_pic_step_cell_field_differs_from_nodal(pic):
+    """The two field modes give different trajectories (the mode reaches
+    the kernels), and the cell-mode FN current is that of the oracle's
+    per-tet field of the device potential."""
+    cfg = W.config_tiny()
+    runs = []
+    for mode in (pic.PIC_FIELD_NODAL, pic.PIC_FIELD_CELL):
+        om, ost, gm, gs, so, sg = _run_pair(pic, cfg, 4, None, 10_000, 60_000,
+                                            field_mode=mode)
+        runs.append((gs.live(), sg))
+    (P0, s0), (P1, s1) = runs
+    assert s0[0]["emit_current"] != s1[0]["emit_current"]
+    a, b = np.argsort(P0["id"]), np.argsort(P1["id"])
+    n = min(a.size, b.size)
+    assert not np.array_equal(P0["z"][a][:n], P1["z"][b][:n])
+
+
+def test_pic_step_cell_field_mixed(pic):
+    """The cell field mode in mixed precision (FP32 particles; the field
+    from FP64 potential differences rounded to FP32)."""
+    cfg = W.config_tiny()
+    err = []
+    om, ost, gm, gs, so, sg = _run_pair(pic, cfg, 12, 0.01, 3000, 60_000,
+                                        resort_every=5,
+                                        precision=pic.PIC_MIXED,
+                                        phi_err=err,
+                                        field_mode=pic.PIC_FIELD_CELL)
+    _compare_mixed(ost, gs, so, sg, err)
+
+
+def test_field_mode_checked(pic):
+    cfg = W.config_tiny()
+    tip = cfg.mesh()
+    gm = pic.Mesh(tip, cfg.emit_zmin)
+    gs = pic.State(gm, 1000)
+    gs.init_field(cfg.E0, tol=cfg.tol)
+    with pytest.raises(pic.PicError):
+        gs.step(dt=cfg.dt, E0=cfg.E0, w_sp=1e-3, phi_w=cfg.phi_w, step0=0,
+                seed=1, field_mode=7)
 
 
 def test_pic_step_deterministic(pic):

@@ -156,6 +156,58 @@ def test_plates_linear_potential(plates_mesh):
     assert np.abs(E - np.array([0, 0, -E0])).max() < 1e-10
 
 
+def test_cell_field_of_linear_potential(small_tip_mesh, tiny_mesh):
+    """Reading R2, cell variant: the field of a tet is -(grad phi)_t, so a
+    nodal potential phi = a.x + c gives -a in every tet (and the nodal
+    recovery gives -a at every node); a sign or index slip in the gradient
+    rows breaks it."""
+    a = np.array([0.3, -1.25, 2.0])
+    for mesh in (small_tip_mesh, tiny_mesh):
+        om = O.OracleMesh(mesh, 0.01)
+        T = om.tets()
+        Et = om.cell_field(mesh.xyz @ a + 7.0)
+        assert Et.shape == (om.n_tets, 3)
+        # (tets across the lateral seam carry unwrapped vertices, where a
+        # potential linear in x or y is not)
+        inner = np.all(T["vert"] == mesh.xyz[T["tet"]], axis=(1, 2))
+        assert inner.sum() > 0.3 * om.n_tets
+        assert np.abs(Et[inner] + a).max() <= 1e-12 * 8
+        # linear in z (not periodic): -e_z in every tet and at every node
+        phz = mesh.xyz[:, 2] * 2.0 + 7.0
+        Ez = om.cell_field(phz)
+        assert np.abs(Ez[:, :2]).max() <= 1e-12
+        assert np.abs(Ez[:, 2] + 2.0).max() <= 1e-12
+        En = om.field(phz)
+        assert np.abs(En[:, :2]).max() <= 1e-12
+        assert np.abs(En[:, 2] + 2.0).max() <= 1e-12
+
+
+def test_cell_mode_emission_uses_the_face_tet(small_tip_mesh):
+    """Cell mode emission: every emitting face sees the field of its own
+    vacuum tet.  With phi = -4 z^2 (a field growing with height, so that
+    another tet's field differs), |E| per face equals the pinned per-tet
+    field of the face's tet, and the total is the sum of the FN current
+    (emitting only where the field points into the metal) over the
+    faces' areas; with a linear potential both modes agree."""
+    om = O.OracleMesh(small_tip_mesh, 0.01)
+    em = om.emit()
+    phi = -4.0 * small_tip_mesh.xyz[:, 2] ** 2
+    Et = om.cell_field(phi)[em["tet"]]
+    E0 = np.zeros((om.n_nodes, 3))
+    r, F = om.emission_rate(E0, 4.5, phi)
+    assert np.array_equal(F, np.sqrt((Et ** 2).sum(1)))
+    pull = (Et * em["normal"]).sum(1) < 0
+    assert pull.sum() > 0
+    j_unit = O.constants()["j_unit"]
+    want = sum(O.fn_current(F[f], 4.5)[0] * j_unit * em["area"][f]
+               for f in np.flatnonzero(pull))
+    assert abs(r - want) <= 1e-12 * want
+    phz = small_tip_mesh.xyz[:, 2] * -2.0
+    rn, Fn = om.emission_rate(om.field(phz), 4.5)
+    rc, Fc = om.emission_rate(E0, 4.5, phz)
+    assert abs(rn - rc) <= 1e-10 * rn and np.abs(Fn - Fc).max() <= 1e-12
+
+
 def test_plates_uniform_charge_closed_form(plates_mesh):
     """SPs on the nodes with weight rho0 h^3 (half on the top plane) load
     the P1 system uniformly; P1 is nodally exact for the quadratic
@@ -420,9 +472,11 @@ def test_injection_velocity_displacement(plates_mesh):
 # exact charge conservation
 # ---------------------------------------------------------------------------
 
-def test_uniform_field_trajectory_closed_form(plates_mesh):
+@pytest.mark.parametrize("mode", [0, 1], ids=["nodal", "cell"])
+def test_uniform_field_trajectory_closed_form(plates_mesh, mode):
     """Leapfrog is exact for constant acceleration: after its first step a
-    particle satisfies r_n = r_1 + (n-1) dt v0 + a dt^2 n(n-1)/2."""
+    particle satisfies r_n = r_1 + (n-1) dt v0 + a dt^2 n(n-1)/2 (the
+    uniform field is the same in the nodal and the cell reading)."""
     om, st = _face_field_state(plates_mesh, E0=5.0)
     k = O.constants()
     rate, _ = om.emission_rate(st.E, 4.5)
@@ -433,7 +487,7 @@ def test_uniform_field_trajectory_closed_form(plates_mesh):
     first = {}
     for step in range(8):
         s = st.step(dt=dt, E0=5.0, w_sp=w_sp, phi_w=4.5, step=step, seed=1,
-                    j_scale=js, tol=1e-13)
+                    j_scale=js, tol=1e-13, field_mode=mode)
         assert s["status"] == 0
         P = st.particles()
         for i, pid in enumerate(P["id"]):
