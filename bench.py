@@ -28,10 +28,10 @@ HBM_PEAK_GBS = 8000.0
 # production workload, from rocprofv3 FETCH_SIZE and WRITE_SIZE counter runs
 # scaled by a plain 1 GiB copy (profiles/pic_step_fp64_production_tip.md).
 # It is reported only while the kernel sources are the ones profiled.
-PUSH_TRAFFIC = dict(bytes=199.4e6, read=133.9e6, written=65.6e6,
+PUSH_TRAFFIC = dict(bytes=200.0e6, read=134.4e6, written=65.6e6,
                     sources=("paper_1906_08125_amd/csrc/particles.hip",
                              "paper_1906_08125_amd/csrc/common.h"),
-                    sha256=("84690ce040cf4bcec75258ca282e93e8439c6db669ba9fddbc7f3618631440b4", "7d8f3c2344d581d986633cc1e8597ea0062a3ad5736211095600e29a54930541"))
+                    sha256=("1a9c2020ee14baedf7b5241d9176d2148fc579285e1d2aae351b67fca7da1d5b", "7d8f3c2344d581d986633cc1e8597ea0062a3ad5736211095600e29a54930541"))
 
 
 def measured_traffic():
