@@ -187,6 +187,21 @@ def config_production() -> RunConfig:
                      0.5, 4.5, 0.5, 100, 1e-10, 1_000_000, 27.0, 2, 10, T)
 
 
+def config_diode(E0: float, nx: int = 32, nz: int = 50, h: float = 0.364,
+                 dt: float = 0.02, n_steps: int = 1600) -> RunConfig:
+    """Planar vacuum diode (the paper's PIC check, Sec. III A: a flat
+    field emitter of area about 135 nm^2 facing the anode across an 18.2 nm
+    gap): the plain box without a tip, the whole cathode plane z = 0
+    emitting (emit_zmin = 0), lateral periodicity making the diode
+    one-dimensional.  Default: 32 x 32 x 50 cubes of 0.364 nm, so A =
+    135.7 nm^2 and d = 18.2 nm.  E0 is the anode field (the Neumann
+    condition of the top plane); n_target is not used (the weight is set
+    from the expected current by the caller)."""
+    T = transit_steps(nz * h, 0.0, E0, dt)
+    return RunConfig(f"planar_diode_{nx}x{nx}x{nz}", nx, nx, nz, h, 0.0, 0.0,
+                     E0, 4.5, dt, n_steps, 1e-10, 0, 0.0, 5, 20, T)
+
+
 def philox_uniform_stream(seed: int, n: int) -> np.ndarray:
     """Plain seeded uniforms for *input* generation (instance draws, test
     points).  Not used by the method itself."""
