@@ -1060,6 +1060,110 @@ double om_emission_rate(const omesh* m, const double* E3, double phi_w,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Binary collisions (App. F).                                               */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t tet;
+  uint64_t key;
+  int64_t id, idx;
+} coll_key;
+
+static int coll_cmp(const void* pa, const void* pb) {
+  const coll_key* a = (const coll_key*)pa;
+  const coll_key* b = (const coll_key*)pb;
+  if (a->tet != b->tet) return a->tet < b->tet ? -1 : 1;
+  if (a->key != b->key) return a->key < b->key ? -1 : 1;
+  if (a->id != b->id) return a->id < b->id ? -1 : 1;
+  return 0;
+}
+
+/* One elastic collision of particles a and b (Eq. vel12 - Eq. variance):
+ * nv = n Lambda dt_coll / V of the cell times the variance factor (1, or
+ * 1/2 for the odd-count triple); draws from Philox at (step, lead, 4, j). */
+static void collide_pair(oparticles* P, int64_t a, int64_t b, double nv,
+                         const ocollide_params* prm, int64_t lead, int j) {
+  consts_t K = constants();
+  double ux = P->vx[b] - P->vx[a];
+  double uy = P->vy[b] - P->vy[a];
+  double uz = P->vz[b] - P->vz[a];
+  double u = sqrt(ux * ux + uy * uy + uz * uz);
+  if (!(u > 0.0)) return;
+  /* Eq. variance: q^4 / (2 pi eps0^2 m^2) = (q/m)^2 (q/eps0)^2 / (2 pi) */
+  double qe = K.qm * K.e_eps;
+  double var = qe * qe / (2.0 * PI_) * nv / (u * u * u);
+  uint64_t ctr[4] = {(uint64_t)prm->step, (uint64_t)lead, 4, (uint64_t)j}, w[4];
+  om_philox4x64(prm->seed, (uint64_t)prm->instance, ctr, w);
+  double U1 = 1.0 - u01(w[0]), U2 = u01(w[1]), U3 = u01(w[2]);
+  double g = sqrt(-2.0 * log(U1)) * cos(2.0 * PI_ * U2); /* Box-Muller */
+  double delta = sqrt(var) * g;
+  double st = 2.0 * delta / (1.0 + delta * delta);          /* sin theta */
+  double omc = 2.0 * delta * delta / (1.0 + delta * delta); /* 1 - cos theta */
+  double ph = 2.0 * PI_ * U3;
+  double up = sqrt(ux * ux + uy * uy);
+  double d[3];
+  if (up > 0.0) {
+    /* Eq. rot_mat applied to u (Eq. scat_vel) */
+    double A = st * sin(ph) * u / up;
+    double bx = st * cos(ph) * ux / up, by = st * cos(ph) * uy / up;
+    d[0] = -omc * ux + A * uy + bx * uz;
+    d[1] = -A * ux - omc * uy + by * uz;
+    d[2] = -bx * ux - by * uy - omc * uz;
+  } else {
+    /* u along z: the azimuth is measured from the x axis */
+    d[0] = u * st * cos(ph);
+    d[1] = u * st * sin(ph);
+    d[2] = -omc * uz;
+  }
+  P->vx[a] -= 0.5 * d[0];
+  P->vy[a] -= 0.5 * d[1];
+  P->vz[a] -= 0.5 * d[2];
+  P->vx[b] += 0.5 * d[0];
+  P->vy[b] += 0.5 * d[1];
+  P->vz[b] += 0.5 * d[2];
+}
+
+void om_collide(const omesh* m, oparticles* P, const ocollide_params* prm) {
+  const double lambda = 13.0; /* Landau logarithm of Eq. variance */
+  coll_key* k = (coll_key*)malloc(sizeof(coll_key) * (P->n > 0 ? P->n : 1));
+  int64_t n = 0;
+  for (int64_t i = 0; i < P->n; ++i) {
+    if (P->tet[i] < 0) continue;
+    uint64_t ctr[4] = {(uint64_t)prm->step, (uint64_t)P->id[i], 3, 0}, w[4];
+    om_philox4x64(prm->seed, (uint64_t)prm->instance, ctr, w);
+    k[n].tet = P->tet[i];
+    k[n].key = w[0];
+    k[n].id = P->id[i];
+    k[n].idx = i;
+    ++n;
+  }
+  qsort(k, (size_t)n, sizeof(coll_key), coll_cmp);
+  for (int64_t g0 = 0; g0 < n;) {
+    int64_t g1 = g0 + 1;
+    while (g1 < n && k[g1].tet == k[g0].tet) ++g1;
+    int64_t cnt = g1 - g0;
+    if (cnt >= 2) {
+      double ws = 0.0;
+      for (int64_t r = g0; r < g1; ++r) ws += P->w[k[r].idx];
+      double V = m->D[k[g0].tet] / 6.0;
+      double nv = (prm->w_sp * ws) * lambda * prm->dt_coll / V;
+      int64_t r0 = g0;
+      if (cnt & 1) {
+        /* odd count: the first three collide pairwise at half variance */
+        int64_t a = k[g0].idx, b = k[g0 + 1].idx, c = k[g0 + 2].idx;
+        collide_pair(P, a, b, 0.5 * nv, prm, k[g0].id, 0);
+        collide_pair(P, b, c, 0.5 * nv, prm, k[g0].id, 1);
+        collide_pair(P, c, a, 0.5 * nv, prm, k[g0].id, 2);
+        r0 = g0 + 3;
+      }
+      for (int64_t r = r0; r + 1 < g1; r += 2)
+        collide_pair(P, k[r].idx, k[r + 1].idx, nv, prm, k[r].id, 0);
+    }
+    g0 = g1;
+  }
+  free(k);
+}
+
+/* ------------------------------------------------------------------------ */
 /* One PIC step (Sec. II B 1-3; Fig. 3 ordering).                            */
 /* ------------------------------------------------------------------------ */
 static void gather(const omesh* m, int32_t t, const double* p,
@@ -1258,5 +1362,16 @@ int om_pic_step(const omesh* m, oparticles* P, double* phi, double* E3,
   st->cg_relres = rel;
   if (s != 0 && st->status == 0) st->status = s;
   om_field(m, phi, E3);
+
+  /* 8. binary collisions (App. F) standing for collide_every steps */
+  if (prm->collide_every > 0 && (prm->step + 1) % prm->collide_every == 0) {
+    ocollide_params cp;
+    cp.dt_coll = dt * (double)prm->collide_every;
+    cp.w_sp = prm->w_sp;
+    cp.seed = prm->seed;
+    cp.step = prm->step;
+    cp.instance = prm->instance;
+    om_collide(m, P, &cp);
+  }
   return (int)st->status;
 }

@@ -122,6 +122,10 @@ typedef struct {
   /* the potential phi_k (cell field mode: the field of tet t is
    * -(grad phi_k)_t); om_pic_step sets it to its own phi */
   const double* phi;
+  /* > 0: binary collisions (om_collide) at the end of every step k with
+   * (k + 1) % collide_every == 0, standing for collide_every steps */
+  int32_t collide_every;
+  int32_t pad_c;
 } ostep_params;
 
 typedef struct {
@@ -134,6 +138,28 @@ typedef struct {
 int om_inject(const omesh* m, oparticles* P, const double* E3,
               const ostep_params* prm, ostep_stats* st, double* face_pts,
               int64_t* counts);
+
+/* Binary Monte Carlo collisions of the superparticles of each tet (App. F
+ * after Takizuka and Abe: group by cell, random pairing, Eq. vel12,
+ * Eq. scat_vel, Eq. rot_mat, Eq. sin_theta, Eq. variance with Lambda = 13,
+ * the odd-count rule).  Readings: delta is tan(theta/2) (the half-angle
+ * forms of Eq. sin_theta); the pair's relative velocity u = v2 - v1 turns
+ * to (I + M) u, i.e. v1 -= Delta v / 2 and v2 += Delta v / 2 (the signs
+ * that conserve energy); q and m of Eq. variance are the electron's and n
+ * is the number of electrons in the cell, w_sp times the sum of the
+ * relative weights (superparticles are treated as identical).  Pairing:
+ * the cell's superparticles ordered by a Philox key of (step, id), then
+ * paired in that order; the draws of a collision are keyed by the id of
+ * the pair's first member. */
+typedef struct {
+  double dt_coll;   /* time the collisions stand for (fs) */
+  double w_sp;      /* electrons per unit relative weight */
+  uint64_t seed;
+  int64_t step;
+  int64_t instance;
+} ocollide_params;
+
+void om_collide(const omesh* m, oparticles* P, const ocollide_params* prm);
 
 /* One step k -> k+1: kick with E_k, inject with E_k, drift, wrap, absorb,
  * locate, deposit, solve for phi_{k+1}, recover E_{k+1}.

@@ -80,6 +80,8 @@ def lib():
     L.om_pic_step.restype = C.c_int
     L.om_pic_step.argtypes = [C.c_void_p, C.c_void_p, _dp, _dp, _i64p,
                               C.c_void_p, C.c_void_p]
+    L.om_collide.restype = None
+    L.om_collide.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
     L.om_inject.restype = C.c_int
     L.om_inject.argtypes = [C.c_void_p, C.c_void_p, _dp, C.c_void_p,
                             C.c_void_p, C.c_void_p, C.c_void_p]
@@ -108,7 +110,14 @@ class _StepParams(C.Structure):
                 ("field_mode", C.c_int32), ("s_face", C.c_void_p),
                 ("counts_in", C.c_void_p), ("counts_out", C.c_void_p),
                 ("fate_out", C.c_void_p), ("inj_out", C.c_void_p),
-                ("phi", C.c_void_p)]
+                ("phi", C.c_void_p), ("collide_every", C.c_int32),
+                ("pad_c", C.c_int32)]
+
+
+class _CollideParams(C.Structure):
+    _fields_ = [("dt_coll", C.c_double), ("w_sp", C.c_double),
+                ("seed", C.c_uint64), ("step", C.c_int64),
+                ("instance", C.c_int64)]
 
 
 class _StepStats(C.Structure):
@@ -343,7 +352,8 @@ class OracleState:
 
     def step(self, *, dt, E0, w_sp, phi_w, step, seed, instance=0,
              j_scale=1.0, tol=1e-12, max_iter=20000, s_face=None,
-             counts_in=None, detail=None, field_mode=0) -> dict:
+             counts_in=None, detail=None, field_mode=0,
+             collide_every=0) -> dict:
         """One PIC step.  counts_in: frozen emission counts per face.
         detail: a dict that receives the counts used, the fate of every
         particle of the step (pre-step particles, then the injected ones:
@@ -356,6 +366,7 @@ class OracleState:
         pr.seed, pr.step, pr.instance = seed, step, instance
         pr.max_iter = max_iter
         pr.field_mode = field_mode
+        pr.collide_every = collide_every
         sf = ci = None
         if s_face is not None:
             sf = np.ascontiguousarray(s_face, np.float64)
@@ -385,6 +396,13 @@ class OracleState:
             detail["inj"] = inj[: out["n_inj"]].copy()
             detail["n_before"] = n0
         return out
+
+    def collide(self, *, dt_coll, w_sp, seed, step, instance=0):
+        """Binary collisions of the current superparticles (velocities
+        change in place)."""
+        ps = self._struct()
+        cp = _CollideParams(dt_coll, w_sp, seed, step, instance)
+        lib().om_collide(self.om._h, C.byref(ps), C.byref(cp))
 
     def inject(self, *, dt, E0, w_sp, phi_w, step, seed, instance=0,
                j_scale=1.0, s_face=None, field_mode=0):
