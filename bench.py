@@ -119,11 +119,23 @@ def run_leg(gm, cfg, w_sp, precision, args):
         rows_b = pic.State.decode_stats(bstats)
     else:
         rows_b = []
+    # binary collisions (App. F) after every re-sort: a further untimed
+    # stretch with the collision launches bracketed
+    kt_coll = {}
+    if args.collide_steps > 0 and precision == pic.PIC_FP64:
+        gm.profile(True, classes=("collide",))
+        cstats = gs.step(step0=step, n_steps=args.collide_steps, collide=1,
+                         **kw)
+        torch.cuda.synchronize()
+        kt_coll = gm.profile_read()
+        gm.profile(False)
+        rows_b = rows_b + pic.State.decode_stats(cstats)
+        step += args.collide_steps
     for r in rows + rows_b:
         if r["status"] != 0:
             raise RuntimeError(f"step status {r['status']}: {r}")
     return dict(elapsed=elapsed, kt=kt, kt_timed=kt_timed, rows=rows,
-                rows_b=rows_b, state=gs, cold=cold)
+                rows_b=rows_b, state=gs, cold=cold, kt_coll=kt_coll)
 
 
 def run_gpu(args):
@@ -180,6 +192,13 @@ def run_gpu(args):
     leg = run_leg(gm, cfg, w_sp, pic.PIC_FP64, args)
     elapsed, kt, rows = leg["elapsed"], leg["kt"], leg["rows"]
     kt_timed, rows_b = leg["kt_timed"], leg["rows_b"]
+    collisions = None
+    if "collide" in leg["kt_coll"]:
+        c = leg["kt_coll"]["collide"]
+        us = 1e3 * c["ms"] / c["launches"]
+        collisions = dict(calls=c["launches"], us_per_call=round(us, 2),
+                          every_steps=args.resort,
+                          us_per_step_amortised=round(us / args.resort, 2))
     del leg
     pushes = sum(r["n_before"] + r["n_inj"] for r in rows)
     live_mean = sum(r["n_before"] for r in rows) / len(rows)
@@ -267,6 +286,7 @@ def run_gpu(args):
         mixed=mixed,
         adjoint=adjoint,
         batch=batch,
+        collisions=collisions,
         roofline=dict(kernel=dom, bound="hbm", achieved=round(achieved, 1),
                       peak=HBM_PEAK_GBS, unit="GB/s",
                       frac=round(achieved / HBM_PEAK_GBS, 4),
@@ -473,6 +493,9 @@ def main():
                     help="instances of the batched leg (0: skip it)")
     ap.add_argument("--batch-warmup", type=int, default=30)
     ap.add_argument("--batch-steps", type=int, default=20)
+    ap.add_argument("--collide-steps", type=int, default=20,
+                    help="untimed steps with binary collisions after every "
+                         "re-sort, to time the collision launches (0: none)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain 1 GiB device copy (the "
                          "reference kernel for HBM byte counters)")

@@ -3,7 +3,7 @@
  * library: the PIC cycle in the vacuum above a field-emitting tip, after
  * Veske et al., "Dynamic coupling between particle-in-cell and atomistic
  * simulations", Phys. Rev. E 101, 053307 (2020), Sec. II A-B and
- * Appendices B and E.
+ * Appendices B, E and F.
  *
  * Conventions shared by every call
  * --------------------------------
@@ -223,6 +223,10 @@ typedef struct {
   const double* s_face; /* device [n_emit] weight per emitting face or NULL */
   int32_t resort_every; /* sort by tet + compact every k steps (0: never) */
   int32_t field_mode;   /* PIC_FIELD_NODAL or PIC_FIELD_CELL              */
+  int32_t collide;      /* 1: binary collisions (see collide) after every */
+                        /* re-sort, standing for resort_every steps       */
+                        /* (needs resort_every > 0); 0: none              */
+  int32_t pad;
   pic_solve_params solve;
 } pic_step_params;
 
@@ -285,8 +289,8 @@ PIC_API pic_status emission_rate(const pic_mesh* mesh, const double* E, double p
 /* in Eb, the adjoint of E_{k+1} from the gathers of step k + 1; out: the   */
 /* adjoint of the pre-step state (pre slots; later slots zeroed) and, in    */
 /* Eb, that of E_k from this step's gathers.  dJ_dE0 and dJ_ds accumulate.  */
-/* Only the nodal field mode (PIC_FIELD_NODAL) has an adjoint: another     */
-/* field_mode is PIC_E_ARG.                                                 */
+/* Only the nodal field mode (PIC_FIELD_NODAL) without collisions has an  */
+/* adjoint: another field_mode, or collide != 0, is PIC_E_ARG.              */
 /* mode PIC_ADJ_INITIAL ends a window: the reverse of the solve that gave   */
 /* phi_0 from the charge of pre and E0 (Eb in: adjoint of E_0; post, Fk1    */
 /* unused; rb, vb untouched).  mu: device [n_nodes] adjoint potential,      */
@@ -315,6 +319,37 @@ PIC_API pic_status adjoint_step(pic_mesh* mesh, const pic_particles* pre,
                         const pic_fields* Fk1, const pic_step_params* params,
                         const pic_adjoint* adj, pic_solve_stats* stats,
                         void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Binary Monte Carlo collisions (App. F, after Takizuka and Abe): the      */
+/* superparticles of each tet are paired at random and every pair collides */
+/* elastically (Eq. vel12, Eq. scat_vel, Eq. rot_mat, Eq. sin_theta), with */
+/* delta = tan(theta/2) normal of variance Eq. variance (Landau logarithm  */
+/* 13); a tet with an odd count collides its first three pairwise at half  */
+/* variance.  q and m of Eq. variance are the electron's, n the electrons  */
+/* in the tet (w_sp times the summed relative weights); superparticles are */
+/* treated as identical.  The relative velocity u = v2 - v1 of a pair turns */
+/* to (I + M) u: v1 -= dv / 2, v2 += dv / 2, conserving momentum and       */
+/* energy.  Pairing: by a Philox key of (step, id) within the tet; draws:  */
+/* Philox at (step, id of the pair's first member).  Velocities change in  */
+/* place; positions, tets and weights are untouched.                        */
+/* particles: slots [0, n_slots) must be sorted by tet (ascending, every   */
+/* slot live), as pic_step's re-sort leaves them.  Slots with tet < 0 are  */
+/* skipped; with tets out of order the grouping is wrong (no access leaves */
+/* the arrays).                                                            */
+/* Uses the handle's particle scratch (allocated on first use for the      */
+/* capacity).  PIC_E_ARG for null pointers or non-positive dt_coll, w_sp.  */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  double dt_coll;   /* time the collisions stand for (fs)                 */
+  double w_sp;      /* electrons per unit relative weight                 */
+  uint64_t seed;
+  int64_t step;     /* counter of the draws                               */
+  int64_t instance;
+} pic_collide_params;
+
+PIC_API pic_status collide(pic_mesh* mesh, const pic_particles* particles,
+                           const pic_collide_params* params, void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* Batched stepping (an addition: many independent instances of the cycle   */
@@ -378,7 +413,8 @@ enum {
   PIC_K_SORT = 5,     /* sort by tet + compaction                         */
   PIC_K_CLEAR = 6,    /* per-step clears of charge and counters           */
   PIC_K_ADJOINT = 7,  /* adjoint_step (its solve included)                */
-  PIC_K_COUNT = 8
+  PIC_K_COLLIDE = 8,  /* binary collisions                                */
+  PIC_K_COUNT = 9
 };
 
 typedef struct {
@@ -388,7 +424,7 @@ typedef struct {
 
 /* classes: bitmask of (1 << PIC_K_*), PIC_PROFILE_ALL for every class, 0  */
 /* to stop.                                                                 */
-#define PIC_PROFILE_ALL 0xFF
+#define PIC_PROFILE_ALL 0x1FF
 PIC_API pic_status pic_profile(pic_mesh* mesh, int32_t classes);
 PIC_API pic_status pic_profile_read(pic_mesh* mesh, pic_kernel_times* out);
 

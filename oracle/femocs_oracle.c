@@ -1074,6 +1074,7 @@ static int coll_cmp(const void* pa, const void* pb) {
   if (a->tet != b->tet) return a->tet < b->tet ? -1 : 1;
   if (a->key != b->key) return a->key < b->key ? -1 : 1;
   if (a->id != b->id) return a->id < b->id ? -1 : 1;
+  if (a->idx != b->idx) return a->idx < b->idx ? -1 : 1;
   return 0;
 }
 

@@ -7,6 +7,7 @@
 #include <string>
 
 #include "adjoint.h"
+#include "collide.h"
 #include "mesh.h"
 #include "particles.h"
 #include "solver.h"
@@ -103,6 +104,41 @@ fp::SortArgs sort_args(pic_mesh* h, const pic_particles* P, int real_bytes) {
   a.hist = (uint32_t*)take((size_t)fp::kSortBins * fp::sort_tiles(cap) * 4);
   a.total = (uint32_t*)take((size_t)fp::kSortBins * 4);
   return a;
+}
+
+// Collision arguments over the sort scratch (free between re-sorts).
+fp::CollideArgs collide_args(pic_mesh* h, const pic_particles* P,
+                             double dt_coll, double w_sp, uint64_t seed,
+                             int64_t step, int64_t instance) {
+  const bool f32 = P->precision == PIC_MIXED;
+  const fp::SortArgs sa = sort_args(h, P, f32 ? 4 : 8);
+  const fp::Phys ph = fp::phys_constants();
+  const double qe = ph.qm * ph.e_eps;
+  fp::CollideArgs c;
+  std::memset(&c, 0, sizeof c);
+  c.m = h->dm;
+  c.n_slots = P->n_slots;
+  c.v[0] = P->vx;
+  c.v[1] = P->vy;
+  c.v[2] = P->vz;
+  c.f32 = f32;
+  c.w = P->w;
+  c.tet = P->tet;
+  c.id = P->id;
+  c.dt_coll = dt_coll;
+  c.w_sp = w_sp;
+  c.c_var = qe * qe / (2.0 * 3.14159265358979323846);
+  c.seed = seed;
+  c.instance = (uint64_t)instance;
+  c.step = step;
+  c.key = (uint64_t*)sa.s_id;
+  c.perm = (int32_t*)sa.key[0];
+  c.seg_s = (int32_t*)sa.key[1];
+  c.seg_n = (int32_t*)sa.val[0];
+  c.seg_q = (long long*)sa.s_w;
+  c.big = (int32_t*)sa.val[1];
+  c.n_big = sa.n_live;
+  return c;
 }
 
 fp::CgArgs cg_args(const pic_mesh* h, const int64_t* charge, double w_sp,
@@ -359,6 +395,8 @@ pic_status check_step(const pic_particles* P, const pic_fields* F,
     return fail(PIC_E_ARG, w + ": invalid step parameters");
   if (prm->field_mode != PIC_FIELD_NODAL && prm->field_mode != PIC_FIELD_CELL)
     return fail(PIC_E_ARG, w + ": unknown field mode");
+  if (prm->collide != 0 && (prm->collide != 1 || prm->resort_every <= 0))
+    return fail(PIC_E_ARG, w + ": collide must be 0, or 1 with resort_every > 0");
   return check_solve(&prm->solve);
 }
 
@@ -642,6 +680,30 @@ pic_status emission_rate(const pic_mesh* h, const double* E, double phi_w,
   return PIC_OK;
 }
 
+pic_status collide(pic_mesh* h, const pic_particles* P,
+                   const pic_collide_params* prm, void* stream) {
+  if (!h || !P || !prm) return fail(PIC_E_ARG, "collide: null argument");
+  if (P->precision != PIC_FP64 && P->precision != PIC_MIXED)
+    return fail(PIC_E_ARG, "collide: unknown particle precision");
+  if (P->capacity <= 0 || P->capacity >= (1ll << 31))
+    return fail(PIC_E_ARG, "collide: capacity must be in [1, 2^31)");
+  if (!P->vx || !P->vy || !P->vz || !P->w || !P->tet || !P->id || !P->n_slots)
+    return fail(PIC_E_ARG, "collide: null particle array");
+  if (!finite_pos(prm->dt_coll) || !finite_pos(prm->w_sp))
+    return fail(PIC_E_ARG, "collide: dt_coll and w_sp must be positive");
+  const bool f32 = P->precision == PIC_MIXED;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = ensure_capacity(h, P->capacity, true, f32 ? 4 : 8);
+  if (e != hipSuccess) return hip_fail(e, "collide");
+  prof_begin(h, PIC_K_COLLIDE, s);
+  const fp::CollideArgs cl = collide_args(h, P, prm->dt_coll, prm->w_sp,
+                                          prm->seed, prm->step, prm->instance);
+  if ((e = fp::collide_particles(cl, h->n_cu, s)) != hipSuccess)
+    return hip_fail(e, "collide");
+  prof_end(h, s);
+  return PIC_OK;
+}
+
 pic_status pic_step(pic_mesh* h, const pic_particles* P, const pic_fields* F,
                     const pic_step_params* prm, int32_t n_steps,
                     pic_step_stats* stats, void* stream) {
@@ -714,6 +776,15 @@ pic_status pic_step(pic_mesh* h, const pic_particles* P, const pic_fields* F,
       if ((e = fp::sort_particles(sa, P->capacity, h->n_cu, s)) != hipSuccess)
         return hip_fail(e, "pic_step sort");
       prof_end(h, s);
+      if (prm->collide) {
+        prof_begin(h, PIC_K_COLLIDE, s);
+        const fp::CollideArgs cl = collide_args(
+            h, P, prm->dt * prm->resort_every, prm->w_sp, prm->seed, step,
+            prm->instance);
+        if ((e = fp::collide_particles(cl, h->n_cu, s)) != hipSuccess)
+          return hip_fail(e, "pic_step collide");
+        prof_end(h, s);
+      }
     }
     ca.step_stats = st;
     // after the first step of this call, E = R phi still holds from the
@@ -770,8 +841,8 @@ pic_status adjoint_step(pic_mesh* h, const pic_particles* pre,
     return fail(PIC_E_ARG, "adjoint_step: capacity must be in [1, 2^31)");
   if (!finite_pos(prm->dt) || !finite_pos(prm->w_sp))
     return fail(PIC_E_ARG, "adjoint_step: invalid step parameters");
-  if (prm->field_mode != PIC_FIELD_NODAL)
-    return fail(PIC_E_ARG, "adjoint_step: only the nodal field mode has an adjoint");
+  if (prm->field_mode != PIC_FIELD_NODAL || prm->collide != 0)
+    return fail(PIC_E_ARG, "adjoint_step: only the nodal field mode without collisions has an adjoint");
   pic_status ps = check_solve(&prm->solve);
   if (ps != PIC_OK) return ps;
   const pic_particles* Q = initial ? pre : post;
@@ -1157,6 +1228,15 @@ pic_status pic_batch_step(pic_batch* b, const pic_particles* P,
         if ((e = fp::sort_particles(sa2, P[i].capacity, b->h[i]->n_cu, s)) != hipSuccess)
           return hip_fail(e, "pic_batch_step sort");
         prof_end(h0, s);
+        if (prm[i].collide) {
+          prof_begin(h0, PIC_K_COLLIDE, s);
+          const fp::CollideArgs cl = collide_args(
+              b->h[i], &P[i], prm[i].dt * prm[i].resort_every, prm[i].w_sp,
+              prm[i].seed, step, prm[i].instance);
+          if ((e = fp::collide_particles(cl, b->h[i]->n_cu, s)) != hipSuccess)
+            return hip_fail(e, "pic_batch_step collide");
+          prof_end(h0, s);
+        }
       }
     }
   }

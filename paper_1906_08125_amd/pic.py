@@ -70,7 +70,14 @@ class StepParams(C.Structure):
                 ("seed", C.c_uint64), ("step0", C.c_int64),
                 ("instance", C.c_int64), ("s_face", C.c_void_p),
                 ("resort_every", C.c_int32), ("field_mode", C.c_int32),
+                ("collide", C.c_int32), ("pad", C.c_int32),
                 ("solve", SolveParams)]
+
+
+class CollideParams(C.Structure):
+    _fields_ = [("dt_coll", C.c_double), ("w_sp", C.c_double),
+                ("seed", C.c_uint64), ("step", C.c_int64),
+                ("instance", C.c_int64)]
 
 
 STEP_STATS_FIELDS = (
@@ -103,13 +110,13 @@ EXPORTS = ("mesh_create", "mesh_destroy", "mesh_query", "mesh_emit_faces",
            "locate", "deposit", "poisson_solve", "pic_step", "emission_rate",
            "adjoint_step", "pic_batch_create", "pic_batch_destroy",
            "pic_batch_step", "pic_profile", "pic_profile_read",
-           "pic_last_error")
+           "pic_last_error", "collide")
 KERNEL_CLASSES = ("push", "emit", "inject", "fallback", "solve", "sort",
-                  "clear", "adjoint")
+                  "clear", "adjoint", "collide")
 
 
 class KernelTimes(C.Structure):
-    _fields_ = [("ms", C.c_double * 8), ("launches", C.c_int64 * 8)]
+    _fields_ = [("ms", C.c_double * 9), ("launches", C.c_int64 * 9)]
 
 
 def load_library(path: str = LIB_PATH):
@@ -144,6 +151,7 @@ def load_library(path: str = LIB_PATH):
                                C.POINTER(StepParams), C.POINTER(AdjointArgs),
                                vp, vp]
     L.pic_profile.argtypes = [vp, i32]
+    L.collide.argtypes = [vp, C.POINTER(Particles), C.POINTER(CollideParams), vp]
     L.pic_profile_read.argtypes = [vp, C.POINTER(KernelTimes)]
     L.pic_last_error.restype = C.c_char_p
     for n in EXPORTS:
@@ -220,7 +228,7 @@ class Mesh:
         event costs GPU time, so time only what is read."""
         mask = 0
         if enable:
-            mask = 0xFF if classes is None else sum(
+            mask = 0x1FF if classes is None else sum(
                 1 << KERNEL_CLASSES.index(c) for c in classes)
         _check(load_library().pic_profile(self._h, mask))
 
@@ -335,14 +343,15 @@ class State:
 
     def step(self, *, dt, E0, w_sp, phi_w, step0, seed, n_steps=1, instance=0,
              j_scale=1.0, tol=1e-12, max_iter=20000, s_face=None,
-             resort_every=0, field_mode=PIC_FIELD_NODAL, stats=None):
+             resort_every=0, field_mode=PIC_FIELD_NODAL, collide=0,
+             stats=None):
         torch = _torch()
         if stats is None:
             stats = torch.zeros(n_steps * STEP_STATS_BYTES // 8,
                                 dtype=torch.int64, device=self.phi.device)
         prm = StepParams(dt, E0, w_sp, phi_w, j_scale, seed, step0, instance,
                          None if s_face is None else s_face.data_ptr(),
-                         resort_every, field_mode,
+                         resort_every, field_mode, int(collide), 0,
                          SolveParams(tol, self.inner_tol, max_iter,
                                      self.solve_precision, self.precond))
         _check(load_library().pic_step(self.mesh.handle, C.byref(self._p),
@@ -350,6 +359,14 @@ class State:
                                        int(n_steps), _ptr(stats),
                                        _stream(torch)))
         return stats
+
+    def collide(self, *, dt_coll, w_sp, seed, step, instance=0):
+        """Binary collisions of the superparticles of each tet (slots grouped
+        by tet, as a re-sort leaves them); velocities change in place."""
+        torch = _torch()
+        prm = CollideParams(dt_coll, w_sp, seed, step, instance)
+        _check(load_library().collide(self.mesh.handle, C.byref(self._p),
+                                      C.byref(prm), _stream(torch)))
 
     @staticmethod
     def decode_stats(stats) -> list[dict]:
@@ -433,7 +450,7 @@ class Window:
     def _params(self, E0, s, step0):
         k = self.kw
         return StepParams(k["dt"], E0, k["w_sp"], k["phi_w"], k["j_scale"],
-                          k["seed"], step0, k["instance"], s.data_ptr(), 0, 0,
+                          k["seed"], step0, k["instance"], s.data_ptr(), 0, 0, 0, 0,
                           SolveParams(k["tol"], self.state.inner_tol,
                                       k["max_iter"], self.adj_precision,
                                       self.adj_precond))
@@ -629,7 +646,7 @@ class Batch:
                 kw["dt"], kw["E0"], kw["w_sp"], kw["phi_w"], kw.get("j_scale", 1.0),
                 kw["seed"], step0, kw.get("instance", 0),
                 None if sf is None else sf.data_ptr(), kw.get("resort_every", 0),
-                kw.get("field_mode", PIC_FIELD_NODAL),
+                kw.get("field_mode", PIC_FIELD_NODAL), int(kw.get("collide", 0)), 0,
                 SolveParams(kw.get("tol", 1e-10), st.inner_tol,
                             kw.get("max_iter", 20000), st.solve_precision)))
         S = (StepParams * n)(*prms)

@@ -48,3 +48,46 @@ def test_host_argument_checks():
     assert L.pic_step(None, None, None, None, 1, None, None) == pic.PIC_E_ARG
     assert L.adjoint_step(None, None, None, None, None, None, None, None,
                           None) == pic.PIC_E_ARG
+
+
+def test_collide_rejects_null():
+    from paper_1906_08125_amd import pic
+    if not os.path.exists(pic.LIB_PATH):
+        pytest.skip("library not built")
+    L = pic.load_library()
+    assert L.collide(None, None, None, None) == pic.PIC_E_ARG
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The binding's ctypes records have the header's sizes and offsets
+    (compiled with the host C compiler)."""
+    import subprocess
+    from paper_1906_08125_amd import pic
+    checks = {
+        "pic_step_params": (pic.StepParams, ["resort_every", "field_mode",
+                                             "collide", "solve"]),
+        "pic_collide_params": (pic.CollideParams, ["dt_coll", "w_sp", "seed",
+                                                   "step", "instance"]),
+        "pic_solve_params": (pic.SolveParams, ["tol", "precond"]),
+        "pic_kernel_times": (pic.KernelTimes, ["ms", "launches"]),
+    }
+    lines = ['#include <stdio.h>', '#include <stddef.h>',
+             f'#include "{HEADER}"', 'int main(void) {']
+    for cname, (_, fields) in checks.items():
+        lines.append(f'  printf("{cname} %zu\\n", sizeof({cname}));')
+        for f in fields:
+            lines.append(f'  printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("  return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    r = subprocess.run(["gcc", str(src), "-o", str(exe)], capture_output=True,
+                       text=True)
+    if r.returncode != 0:
+        pytest.skip("no host C compiler: " + r.stderr[:200])
+    out = dict(l.split() for l in subprocess.run(
+        [str(exe)], capture_output=True, text=True, check=True).stdout.splitlines())
+    for cname, (cls, fields) in checks.items():
+        assert int(out[cname]) == C.sizeof(cls), cname
+        for f in fields:
+            assert int(out[f"{cname}.{f}"]) == getattr(cls, f).offset, (cname, f)
