@@ -352,6 +352,36 @@ PIC_API pic_status collide(pic_mesh* mesh, const pic_particles* particles,
                            const pic_collide_params* params, void* stream);
 
 /* ------------------------------------------------------------------------ */
+/* Surface charge (Sec. II C, Eq. face_charge, Eq. atom_charge,             */
+/* Eq. charge_weight): the charge of every emitting face -- every metal     */
+/* face when the mesh was created with emit_zmin below the cathode --       */
+/* Q_f = eps0 (E_f . n_f) A_f (E_f: the mean of the nodal field at the      */
+/* face's vertices, or in PIC_FIELD_CELL mode the field of the face's tet   */
+/* from phi; n_f into the vacuum), and its distribution to atoms,           */
+/* q_j = sum_f w_fj Q_f with w_fj = exp(-d_fj / r_c) / sum_j'               */
+/* exp(-d_fj' / r_c): normalised over the atoms, so that sum_j q_j =        */
+/* sum_f Q_f (the printed normalisation condition, a sum over faces, would  */
+/* not conserve charge); d_fj from the face centroid, minimum image in x    */
+/* and y.  Charges in e.                                                    */
+/* fields: phi (cell mode) or E (nodal mode; FP64, or FP32 when precision   */
+/* is PIC_MIXED).  face_Q: device [n_emit] out; atom_q: device [n_atoms]    */
+/* out (may be NULL when n_atoms is 0).  Uses a per-handle scratch of two   */
+/* doubles per face (allocated on first use).  PIC_E_ARG for null pointers, */
+/* n_atoms outside [0, 2^31), r_c <= 0 or an unknown mode or precision.     */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  int64_t n_atoms;
+  const double* atoms;  /* device [3*n_atoms] positions (x, y, z), nm      */
+  double r_c;           /* nm (the paper uses 0.1)                         */
+  int32_t field_mode;   /* PIC_FIELD_NODAL or PIC_FIELD_CELL               */
+  int32_t precision;    /* of fields->E: PIC_FP64 or PIC_MIXED (FP32)      */
+} pic_charge_params;
+
+PIC_API pic_status surface_charge(pic_mesh* mesh, const pic_fields* fields,
+                                  const pic_charge_params* params,
+                                  double* face_Q, double* atom_q, void* stream);
+
+/* ------------------------------------------------------------------------ */
 /* Batched stepping (an addition: many independent instances of the cycle   */
 /* -- each its own mesh_create handle, particles, fields and parameters --  */
 /* advanced together).  Every kernel of a step is launched once for all     */

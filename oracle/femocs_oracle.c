@@ -1060,6 +1060,49 @@ double om_emission_rate(const omesh* m, const double* E3, double phi_w,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Surface charge (Eq. face_charge, Eq. atom_charge, Eq. charge_weight).     */
+/* ------------------------------------------------------------------------ */
+static double face_atom_dist(const omesh* m, const double* c, const double* a) {
+  double dx = c[0] - a[0], dy = c[1] - a[1], dz = c[2] - a[2];
+  if (dx > 0.5 * m->Lx) dx -= m->Lx;
+  else if (dx < -0.5 * m->Lx) dx += m->Lx;
+  if (dy > 0.5 * m->Ly) dy -= m->Ly;
+  else if (dy < -0.5 * m->Ly) dy += m->Ly;
+  return sqrt((dx * dx + dy * dy) + dz * dz);
+}
+
+void om_surface_charge(const omesh* m, const double* E3, const double* phi,
+                       int field_mode, int64_t n_atoms, const double* atoms,
+                       double r_c, double* faceQ, double* atomq) {
+  consts_t K = constants();
+  for (int64_t j = 0; j < n_atoms; ++j) atomq[j] = 0.0;
+  for (int64_t f = 0; f < m->n_emit; ++f) {
+    double Ef[3];
+    if (field_mode == 1)
+      cell_field(m, m->e_tet[f], phi, Ef);
+    else
+      face_centroid_field(m, f, E3, Ef);
+    /* Eq. face_charge with the sign of E . n (eps0 = 1 / (e/eps0)) */
+    double Q = (vdot(Ef, m->e_nrm + 3 * f) / K.e_eps) * m->e_area[f];
+    faceQ[f] = Q;
+    if (n_atoms == 0) continue;
+    const double* abc = m->e_abc + 9 * f;
+    double c[3];
+    for (int k = 0; k < 3; ++k) c[k] = ((abc[k] + abc[3 + k]) + abc[6 + k]) / 3.0;
+    double dmin = face_atom_dist(m, c, atoms);
+    for (int64_t j = 1; j < n_atoms; ++j) {
+      double d = face_atom_dist(m, c, atoms + 3 * j);
+      if (d < dmin) dmin = d;
+    }
+    double S = 0.0;
+    for (int64_t j = 0; j < n_atoms; ++j)
+      S += exp(-(face_atom_dist(m, c, atoms + 3 * j) - dmin) / r_c);
+    for (int64_t j = 0; j < n_atoms; ++j)
+      atomq[j] += (Q * exp(-(face_atom_dist(m, c, atoms + 3 * j) - dmin) / r_c)) / S;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Binary collisions (App. F).                                               */
 /* ------------------------------------------------------------------------ */
 typedef struct {

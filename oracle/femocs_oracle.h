@@ -161,6 +161,21 @@ typedef struct {
 
 void om_collide(const omesh* m, oparticles* P, const ocollide_params* prm);
 
+/* Face charge (Eq. face_charge) on the emitting faces (every metal face
+ * when emit_zmin lies below the cathode) and its distribution to atoms
+ * (Eq. atom_charge, Eq. charge_weight).  Q_f = eps0 (E_f . n_f) A_f, E_f the
+ * face field (field_mode 0: mean of the nodal field E3 at the face's
+ * vertices; 1: the cell field of the face's tet from phi), n_f the normal
+ * into the vacuum.  w_fj = exp(-d_fj / r_c) / sum_j' exp(-d_fj' / r_c),
+ * normalised over the atoms so that sum_j q_j = sum_f Q_f (reading of
+ * Eq. charge_cons), d_fj the distance from the face centroid to atom j,
+ * minimum image in x and y; evaluated as exp(-(d_fj - d_f,min) / r_c) over
+ * the same sum (an identity that keeps the terms representable).
+ * faceQ [n_emit], atomq [n_atoms] (out). */
+void om_surface_charge(const omesh* m, const double* E3, const double* phi,
+                       int field_mode, int64_t n_atoms, const double* atoms,
+                       double r_c, double* faceQ, double* atomq);
+
 /* One step k -> k+1: kick with E_k, inject with E_k, drift, wrap, absorb,
  * locate, deposit, solve for phi_{k+1}, recover E_{k+1}.
  * E3 (in: E_k, out: E_{k+1}), phi (in: guess, out: phi_{k+1}), c (out). */

@@ -80,6 +80,10 @@ def lib():
     L.om_pic_step.restype = C.c_int
     L.om_pic_step.argtypes = [C.c_void_p, C.c_void_p, _dp, _dp, _i64p,
                               C.c_void_p, C.c_void_p]
+    L.om_surface_charge.restype = None
+    L.om_surface_charge.argtypes = [C.c_void_p, _dp, C.c_void_p, C.c_int,
+                                    C.c_int64, C.c_void_p, C.c_double, _dp,
+                                    _dp]
     L.om_collide.restype = None
     L.om_collide.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
     L.om_inject.restype = C.c_int
@@ -300,6 +304,21 @@ class OracleMesh:
         lib().om_field(self._h, np.ascontiguousarray(phi, np.float64),
                        E.reshape(-1))
         return E
+
+    def surface_charge(self, E, atoms, r_c=0.1, phi=None):
+        """Face charges of the emitting faces and the atoms' charges (nodal
+        field E, or the cell field of phi when given)."""
+        E = np.ascontiguousarray(E.reshape(-1), dtype=np.float64)
+        atoms = np.ascontiguousarray(atoms, dtype=np.float64).reshape(-1, 3)
+        Q = np.zeros(max(self.n_emit, 1))
+        q = np.zeros(max(len(atoms), 1))
+        ph = None
+        if phi is not None:
+            ph = np.ascontiguousarray(phi, dtype=np.float64)
+        lib().om_surface_charge(self._h, E, None if ph is None else ph.ctypes.data,
+                                0 if ph is None else 1, len(atoms),
+                                atoms.ctypes.data, float(r_c), Q, q)
+        return Q[: self.n_emit], q[: len(atoms)]
 
     def emission_rate(self, E, phi_w, phi=None):
         """Total emission current and per-face |E|: at the nodal field E, or

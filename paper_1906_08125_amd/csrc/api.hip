@@ -8,6 +8,7 @@
 
 #include "adjoint.h"
 #include "collide.h"
+#include "charge.h"
 #include "mesh.h"
 #include "particles.h"
 #include "solver.h"
@@ -562,6 +563,7 @@ pic_status mesh_destroy(pic_mesh* h) {
   if (h->queue) (void)hipFree(h->queue);
   if (h->sort_mem) (void)hipFree(h->sort_mem);
   if (h->adj_mem) (void)hipFree(h->adj_mem);
+  if (h->charge_mem) (void)hipFree(h->charge_mem);
   drop_graphs(h);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   for (hipEvent_t ev : h->ev_pool) (void)hipEventDestroy(ev);
@@ -701,6 +703,48 @@ pic_status collide(pic_mesh* h, const pic_particles* P,
   if ((e = fp::collide_particles(cl, h->n_cu, s)) != hipSuccess)
     return hip_fail(e, "collide");
   prof_end(h, s);
+  return PIC_OK;
+}
+
+pic_status surface_charge(pic_mesh* h, const pic_fields* F,
+                          const pic_charge_params* prm, double* face_Q,
+                          double* atom_q, void* stream) {
+  if (!h || !F || !prm || !face_Q)
+    return fail(PIC_E_ARG, "surface_charge: null argument");
+  if (prm->n_atoms < 0 || prm->n_atoms >= (1ll << 31))
+    return fail(PIC_E_ARG, "surface_charge: n_atoms must be in [0, 2^31)");
+  if (prm->n_atoms > 0 && (!prm->atoms || !atom_q))
+    return fail(PIC_E_ARG, "surface_charge: null atom array");
+  if (!finite_pos(prm->r_c))
+    return fail(PIC_E_ARG, "surface_charge: r_c must be positive");
+  if (prm->field_mode != PIC_FIELD_NODAL && prm->field_mode != PIC_FIELD_CELL)
+    return fail(PIC_E_ARG, "surface_charge: unknown field mode");
+  if (prm->precision != PIC_FP64 && prm->precision != PIC_MIXED)
+    return fail(PIC_E_ARG, "surface_charge: unknown precision");
+  if (prm->field_mode == PIC_FIELD_CELL ? !F->phi : !F->E)
+    return fail(PIC_E_ARG, "surface_charge: null field array");
+  hipStream_t s = (hipStream_t)stream;
+  if (!h->charge_mem && h->dm.n_emit > 0) {
+    hipError_t e = hipMalloc(&h->charge_mem, sizeof(double) * 2 * (size_t)h->dm.n_emit);
+    if (e != hipSuccess) return hip_fail(e, "surface_charge");
+  }
+  fp::ChargeArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.m = h->dm;
+  a.E = F->E;
+  a.f32 = prm->precision == PIC_MIXED;
+  a.phi = F->phi;
+  a.cell = prm->field_mode == PIC_FIELD_CELL;
+  a.e_eps = fp::phys_constants().e_eps;
+  a.n_atoms = prm->n_atoms;
+  a.atoms = prm->atoms;
+  a.r_c = prm->r_c;
+  a.face_Q = face_Q;
+  a.atom_q = atom_q;
+  a.f_min = h->charge_mem;
+  a.f_sum = h->charge_mem ? h->charge_mem + h->dm.n_emit : nullptr;
+  const hipError_t e = fp::surface_charge_launch(a, h->n_cu, s);
+  if (e != hipSuccess) return hip_fail(e, "surface_charge");
   return PIC_OK;
 }
 

@@ -43,6 +43,7 @@ struct pic_mesh {
   size_t sort_bytes = 0;
   void* adj_mem = nullptr;             // adjoint scratch (grown on demand)
   size_t adj_bytes = 0;
+  double* charge_mem = nullptr;        // surface-charge scratch [2][n_emit]
   // CG iteration batches captured as HIP graphs (kernel arguments, count)
   struct IterGraph {
     fp::CgArgs key;

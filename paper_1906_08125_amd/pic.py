@@ -74,6 +74,12 @@ class StepParams(C.Structure):
                 ("solve", SolveParams)]
 
 
+class ChargeParams(C.Structure):
+    _fields_ = [("n_atoms", C.c_int64), ("atoms", C.c_void_p),
+                ("r_c", C.c_double), ("field_mode", C.c_int32),
+                ("precision", C.c_int32)]
+
+
 class CollideParams(C.Structure):
     _fields_ = [("dt_coll", C.c_double), ("w_sp", C.c_double),
                 ("seed", C.c_uint64), ("step", C.c_int64),
@@ -110,7 +116,7 @@ EXPORTS = ("mesh_create", "mesh_destroy", "mesh_query", "mesh_emit_faces",
            "locate", "deposit", "poisson_solve", "pic_step", "emission_rate",
            "adjoint_step", "pic_batch_create", "pic_batch_destroy",
            "pic_batch_step", "pic_profile", "pic_profile_read",
-           "pic_last_error", "collide")
+           "pic_last_error", "collide", "surface_charge")
 KERNEL_CLASSES = ("push", "emit", "inject", "fallback", "solve", "sort",
                   "clear", "adjoint", "collide")
 
@@ -152,6 +158,8 @@ def load_library(path: str = LIB_PATH):
                                vp, vp]
     L.pic_profile.argtypes = [vp, i32]
     L.collide.argtypes = [vp, C.POINTER(Particles), C.POINTER(CollideParams), vp]
+    L.surface_charge.argtypes = [vp, C.POINTER(Fields), C.POINTER(ChargeParams),
+                                 vp, vp, vp]
     L.pic_profile_read.argtypes = [vp, C.POINTER(KernelTimes)]
     L.pic_last_error.restype = C.c_char_p
     for n in EXPORTS:
@@ -231,6 +239,29 @@ class Mesh:
             mask = 0x1FF if classes is None else sum(
                 1 << KERNEL_CLASSES.index(c) for c in classes)
         _check(load_library().pic_profile(self._h, mask))
+
+    def surface_charge(self, atoms, r_c=0.1, E=None, phi=None):
+        """Face charges of the emitting faces and charges of the atoms
+        (device [n, 3] f64): from the nodal field E (f64 or f32), or the
+        cell field of phi when phi is given.  Returns (face_Q, atom_q)."""
+        torch = _torch()
+        atoms = atoms.contiguous()
+        n = int(atoms.shape[0]) if atoms.numel() else 0
+        dev = atoms.device
+        fq = torch.zeros(max(self.n_emit, 1), dtype=torch.float64, device=dev)
+        aq = torch.zeros(max(n, 1), dtype=torch.float64, device=dev)
+        cell = phi is not None
+        prec = PIC_FP64
+        if not cell and E is not None and E.dtype == torch.float32:
+            prec = PIC_MIXED
+        f = Fields(phi.data_ptr() if cell else None,
+                   None if cell or E is None else E.data_ptr(), None)
+        prm = ChargeParams(n, atoms.data_ptr() if n else None, float(r_c),
+                           PIC_FIELD_CELL if cell else PIC_FIELD_NODAL, prec)
+        _check(load_library().surface_charge(self._h, C.byref(f), C.byref(prm),
+                                             fq.data_ptr(), aq.data_ptr(),
+                                             _stream(torch)))
+        return fq[: self.n_emit], aq[:n]
 
     def profile_read(self) -> dict:
         kt = KernelTimes()

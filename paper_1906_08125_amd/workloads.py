@@ -242,6 +242,38 @@ def random_points_in_box(mesh: TipMesh, n: int, seed: int) -> np.ndarray:
     return p
 
 
+def surface_atoms(mesh: TipMesh, density: float = 4.0,
+                  seed: int = 6) -> np.ndarray:
+    """Synthetic surface atoms (stand-ins for the MD atoms of the paper's
+    surface-charge step): seeded uniform points on the analytic metal
+    surface -- the cathode plane z = 0 outside the tip's footprint, the tip
+    cylinder and its hemispherical cap -- at `density` atoms per nm^2."""
+    g = np.random.Generator(np.random.Philox(seed))
+    Lx, Ly, R, H = mesh.Lx, mesh.Ly, mesh.tip_R, mesh.tip_H
+    cx, cy = 0.5 * Lx, 0.5 * Ly
+    n_plane = int(round(density * (Lx * Ly - (np.pi * R * R if R > 0 else 0.0))))
+    pts = []
+    while sum(len(p) for p in pts) < n_plane:
+        p = g.random((n_plane, 3)) * np.array([Lx, Ly, 0.0])
+        if R > 0:
+            p = p[(p[:, 0] - cx) ** 2 + (p[:, 1] - cy) ** 2 >= R * R]
+        pts.append(p)
+    out = [np.concatenate(pts)[:n_plane]]
+    if R > 0:
+        zc = H - R
+        n_cyl = int(round(density * 2 * np.pi * R * zc))
+        a = g.random(n_cyl) * 2 * np.pi
+        z = g.random(n_cyl) * zc
+        out.append(np.stack([cx + R * np.cos(a), cy + R * np.sin(a), z], 1))
+        n_cap = int(round(density * 2 * np.pi * R * R))
+        u = g.random(n_cap)            # uniform on the upper hemisphere
+        a = g.random(n_cap) * 2 * np.pi
+        r = np.sqrt(1.0 - u * u)
+        out.append(np.stack([cx + R * r * np.cos(a), cy + R * r * np.sin(a),
+                             zc + R * u], 1))
+    return np.ascontiguousarray(np.concatenate(out))
+
+
 def lattice_points(mesh: TipMesh, n: int, seed: int) -> np.ndarray:
     """Points on vertices, edge midpoints and face centroids of the grid
     (all binary-exact): degenerate cases for point location."""

@@ -56,6 +56,7 @@ def test_collide_rejects_null():
         pytest.skip("library not built")
     L = pic.load_library()
     assert L.collide(None, None, None, None) == pic.PIC_E_ARG
+    assert L.surface_charge(None, None, None, None, None, None) == pic.PIC_E_ARG
 
 
 def test_struct_layouts_match_the_header(tmp_path):
@@ -70,6 +71,8 @@ def test_struct_layouts_match_the_header(tmp_path):
                                                    "step", "instance"]),
         "pic_solve_params": (pic.SolveParams, ["tol", "precond"]),
         "pic_kernel_times": (pic.KernelTimes, ["ms", "launches"]),
+        "pic_charge_params": (pic.ChargeParams, ["n_atoms", "atoms", "r_c",
+                                                 "field_mode", "precision"]),
     }
     lines = ['#include <stdio.h>', '#include <stddef.h>',
              f'#include "{HEADER}"', 'int main(void) {']
