@@ -259,6 +259,10 @@ def run_gpu(args):
     if args.batch_instances > 0:
         torch.cuda.empty_cache()
         batch = run_batch_leg(args)
+    charge = None
+    if args.charge_calls > 0:
+        torch.cuda.empty_cache()
+        charge = run_charge_leg(tip, args)
     adjoint = None
     if not args.no_adjoint:
         torch.cuda.empty_cache()
@@ -287,12 +291,47 @@ def run_gpu(args):
         adjoint=adjoint,
         batch=batch,
         collisions=collisions,
+        surface_charge=charge,
         roofline=dict(kernel=dom, bound="hbm", achieved=round(achieved, 1),
                       peak=HBM_PEAK_GBS, unit="GB/s",
                       frac=round(achieved / HBM_PEAK_GBS, 4),
                       traffic=(measured_traffic() if dom == "push" else None)),
     )
     return out, dict(cfg=cfg, tip=tip, w_sp=w_sp)
+
+
+def run_charge_leg(tip, args):
+    """Surface charge of every metal face of the production tip (a second
+    mesh handle with all metal faces listed) distributed to seeded surface
+    atoms: time per call with events on the stream."""
+    import torch
+
+    from paper_1906_08125_amd import pic, workloads as W
+
+    t0 = time.time()
+    gmc = pic.Mesh(tip, -1.0)
+    gs = pic.State(gmc, 16)
+    gs.init_field(0.5, tol=1e-10)
+    atoms = torch.from_numpy(W.surface_atoms(tip, density=4.0)).cuda()
+    log(f"surface-charge mesh {time.time() - t0:.1f}s: {gmc.n_emit} faces, "
+        f"{atoms.shape[0]} atoms")
+    gmc.surface_charge(atoms, E=gs.E)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.charge_calls):
+        Q, q = gmc.surface_charge(atoms, E=gs.E)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.charge_calls
+    out = dict(faces=gmc.n_emit, atoms=int(atoms.shape[0]),
+               us_per_call=round(1e3 * ms, 1),
+               face_atom_pairs_per_s=round(3 * gmc.n_emit * atoms.shape[0]
+                                           / (ms * 1e-3), 1),
+               total_charge_e=round(float(Q.sum().item()), 6),
+               conservation=float(q.sum().item() / Q.sum().item()))
+    del gmc, gs
+    return out
 
 
 def run_adjoint_leg(gm, cfg, rate, args):
@@ -493,6 +532,9 @@ def main():
                     help="instances of the batched leg (0: skip it)")
     ap.add_argument("--batch-warmup", type=int, default=30)
     ap.add_argument("--batch-steps", type=int, default=20)
+    ap.add_argument("--charge-calls", type=int, default=5,
+                    help="timed surface-charge calls over every metal face "
+                         "of the production tip (0: skip)")
     ap.add_argument("--collide-steps", type=int, default=20,
                     help="untimed steps with binary collisions after every "
                          "re-sort, to time the collision launches (0: none)")

@@ -365,8 +365,9 @@ PIC_API pic_status collide(pic_mesh* mesh, const pic_particles* particles,
 /* and y.  Charges in e.                                                    */
 /* fields: phi (cell mode) or E (nodal mode; FP64, or FP32 when precision   */
 /* is PIC_MIXED).  face_Q: device [n_emit] out; atom_q: device [n_atoms]    */
-/* out (may be NULL when n_atoms is 0).  Uses a per-handle scratch of two   */
-/* doubles per face (allocated on first use).  PIC_E_ARG for null pointers, */
+/* out (may be NULL when n_atoms is 0).  Uses a per-handle scratch, grown   */
+/* on demand (two doubles per face plus one per atom and face range, at    */
+/* most 1024 ranges).  PIC_E_ARG for null pointers,                         */
 /* n_atoms outside [0, 2^31), r_c <= 0 or an unknown mode or precision.     */
 /* ------------------------------------------------------------------------ */
 typedef struct {

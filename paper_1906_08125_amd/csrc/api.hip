@@ -724,9 +724,18 @@ pic_status surface_charge(pic_mesh* h, const pic_fields* F,
   if (prm->field_mode == PIC_FIELD_CELL ? !F->phi : !F->E)
     return fail(PIC_E_ARG, "surface_charge: null field array");
   hipStream_t s = (hipStream_t)stream;
-  if (!h->charge_mem && h->dm.n_emit > 0) {
-    hipError_t e = hipMalloc(&h->charge_mem, sizeof(double) * 2 * (size_t)h->dm.n_emit);
+  const int n_split = fp::charge_splits(h->dm.n_emit, prm->n_atoms, h->n_cu);
+  const size_t need = 2 * (size_t)h->dm.n_emit + (size_t)n_split * (size_t)prm->n_atoms;
+  if (need > h->charge_cap) {
+    if (h->charge_mem) {
+      hipError_t e = hipFree(h->charge_mem);
+      h->charge_mem = nullptr;
+      h->charge_cap = 0;
+      if (e != hipSuccess) return hip_fail(e, "surface_charge");
+    }
+    hipError_t e = hipMalloc(&h->charge_mem, sizeof(double) * need);
     if (e != hipSuccess) return hip_fail(e, "surface_charge");
+    h->charge_cap = need;
   }
   fp::ChargeArgs a;
   std::memset(&a, 0, sizeof a);
@@ -743,6 +752,8 @@ pic_status surface_charge(pic_mesh* h, const pic_fields* F,
   a.atom_q = atom_q;
   a.f_min = h->charge_mem;
   a.f_sum = h->charge_mem ? h->charge_mem + h->dm.n_emit : nullptr;
+  a.part = h->charge_mem ? h->charge_mem + 2 * h->dm.n_emit : nullptr;
+  a.n_split = n_split;
   const hipError_t e = fp::surface_charge_launch(a, h->n_cu, s);
   if (e != hipSuccess) return hip_fail(e, "surface_charge");
   return PIC_OK;

@@ -18,7 +18,12 @@ struct ChargeArgs {
   double* atom_q;      // out [n_atoms]
   double* f_min;       // scratch [n_emit]: nearest-atom distance
   double* f_sum;       // scratch [n_emit]: weight normalisation
+  double* part;        // scratch [n_split][n_atoms]: per face-range sums
+  int n_split;
 };
+
+// Face ranges of the atom pass: enough workgroups to fill the chip.
+int charge_splits(int64_t n_emit, int64_t n_atoms, int n_cu);
 
 hipError_t surface_charge_launch(const ChargeArgs& a, int n_cu, hipStream_t s);
 

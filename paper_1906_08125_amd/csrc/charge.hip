@@ -9,8 +9,9 @@
 //       the distance from the face centroid to the atom, minimum image in
 //       x and y, evaluated as exp(-(d_fj - d_f,min) / r_c) over the same sum.
 // k_face_charge: one workgroup per face (Q_f, d_f,min, the sum);
-// k_atom_charge: one thread per atom, the faces in LDS tiles, summed in
-// face order (no atomics: the result does not depend on scheduling).
+// k_atom_charge: one thread per (atom, range of faces), the faces in LDS
+// tiles, summed in face order; k_atom_reduce adds the ranges in order (no
+// atomics: the result does not depend on scheduling).
 #include "charge.h"
 
 namespace fp {
@@ -116,6 +117,10 @@ __global__ void __launch_bounds__(kThreads) k_atom_charge(ChargeArgs a) {
   __shared__ double s_min[kFaceTile], s_Q[kFaceTile], s_S[kFaceTile];
   const DevMesh& m = a.m;
   const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  // this workgroup's range of faces
+  const int64_t per = (m.n_emit + gridDim.y - 1) / gridDim.y;
+  const int64_t f_lo = per * blockIdx.y;
+  const int64_t f_hi = f_lo + per < m.n_emit ? f_lo + per : m.n_emit;
   const bool mine = j < a.n_atoms;
   double at[3] = {0.0, 0.0, 0.0};
   if (mine) {
@@ -124,8 +129,8 @@ __global__ void __launch_bounds__(kThreads) k_atom_charge(ChargeArgs a) {
     at[2] = a.atoms[3 * j + 2];
   }
   double q = 0.0;
-  for (int64_t f0 = 0; f0 < m.n_emit; f0 += kFaceTile) {
-    const int tn = (int)(m.n_emit - f0 < kFaceTile ? m.n_emit - f0 : kFaceTile);
+  for (int64_t f0 = f_lo; f0 < f_hi; f0 += kFaceTile) {
+    const int tn = (int)(f_hi - f0 < kFaceTile ? f_hi - f0 : kFaceTile);
     __syncthreads();
     for (int k = threadIdx.x; k < tn; k += blockDim.x) {
       const double3 c = face_centroid(m, f0 + k);
@@ -145,10 +150,27 @@ __global__ void __launch_bounds__(kThreads) k_atom_charge(ChargeArgs a) {
       }
     }
   }
-  if (mine) a.atom_q[j] = q;
+  if (mine) a.part[blockIdx.y * a.n_atoms + j] = q;
+}
+
+__global__ void __launch_bounds__(kThreads) k_atom_reduce(ChargeArgs a) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= a.n_atoms) return;
+  double q = 0.0;
+  for (int k = 0; k < a.n_split; ++k) q += a.part[k * a.n_atoms + j];
+  a.atom_q[j] = q;
 }
 
 }  // namespace
+
+int charge_splits(int64_t n_emit, int64_t n_atoms, int n_cu) {
+  const int64_t blocks = (n_atoms + kThreads - 1) / kThreads;
+  int64_t k = ((int64_t)n_cu * 4 + blocks - 1) / (blocks > 0 ? blocks : 1);
+  const int64_t tiles = (n_emit + kFaceTile - 1) / kFaceTile;
+  if (k > tiles * 4) k = tiles * 4;  // at least a quarter tile per range
+  if (k > 1024) k = 1024;
+  return (int)(k < 1 ? 1 : k);
+}
 
 hipError_t surface_charge_launch(const ChargeArgs& a, int n_cu, hipStream_t s) {
   if (a.m.n_emit == 0) return hipSuccess;
@@ -156,7 +178,8 @@ hipError_t surface_charge_launch(const ChargeArgs& a, int n_cu, hipStream_t s) {
   hipLaunchKernelGGL(k_face_charge, dim3(gf), dim3(kThreads), 0, s, a);
   if (a.n_atoms > 0) {
     const int ga = (int)((a.n_atoms + kThreads - 1) / kThreads);
-    hipLaunchKernelGGL(k_atom_charge, dim3(ga), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL(k_atom_charge, dim3(ga, a.n_split), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL(k_atom_reduce, dim3(ga), dim3(kThreads), 0, s, a);
   }
   return hipGetLastError();
 }

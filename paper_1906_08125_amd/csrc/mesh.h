@@ -43,7 +43,8 @@ struct pic_mesh {
   size_t sort_bytes = 0;
   void* adj_mem = nullptr;             // adjoint scratch (grown on demand)
   size_t adj_bytes = 0;
-  double* charge_mem = nullptr;        // surface-charge scratch [2][n_emit]
+  double* charge_mem = nullptr;        // surface-charge scratch (grown on demand)
+  size_t charge_cap = 0;               // its size in doubles
   // CG iteration batches captured as HIP graphs (kernel arguments, count)
   struct IterGraph {
     fp::CgArgs key;

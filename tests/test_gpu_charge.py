@@ -1,0 +1,88 @@
+"""Surface charge on the GPU (Sec. II C: Eq. face_charge, Eq. atom_charge,
+Eq. charge_weight) against the oracle: the face charges of every metal face
+of the tiny tip and their distribution to seeded surface atoms, from the
+same field (1e-12), in the cell mode, from an FP32 field (1e-6), and from
+each side's own solve (1e-9); total charge conserved on the device."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1906_08125_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def setup():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1906_08125_amd import pic
+    pic.load_library()
+    cfg = W.config_tiny()
+    tip = cfg.mesh()
+    om = O.OracleMesh(tip, -1.0)
+    gm = pic.Mesh(tip, -1.0)
+    assert gm.n_emit == om.n_emit
+    ost = O.OracleState(om, 4)
+    ost.init_field(cfg.E0, tol=1e-12)
+    atoms = W.surface_atoms(tip, density=4.0, seed=9)
+    return pic, cfg, om, gm, ost, atoms
+
+
+def _rel(a, b):
+    return np.linalg.norm(np.asarray(a) - b) / np.linalg.norm(b)
+
+
+def _E4(E3, dtype):
+    E4 = np.zeros((len(E3), 4))
+    E4[:, :3] = E3
+    return torch.from_numpy(E4.reshape(-1)).to(dtype).cuda()
+
+
+@pytest.mark.parametrize("r_c", [0.1, 0.6])
+def test_surface_charge_matches_oracle(setup, r_c):
+    pic, cfg, om, gm, ost, atoms = setup
+    Qo, qo = om.surface_charge(ost.E, atoms, r_c=r_c)
+    Qg, qg = gm.surface_charge(torch.from_numpy(atoms).cuda(), r_c=r_c,
+                               E=_E4(ost.E, torch.float64))
+    Qg, qg = Qg.cpu().numpy(), qg.cpu().numpy()
+    assert _rel(Qg, Qo) < 1e-12
+    assert _rel(qg, qo) < 1e-12
+    assert abs(qg.sum() / Qg.sum() - 1) < 1e-12
+
+
+def test_surface_charge_cell_mode(setup):
+    pic, cfg, om, gm, ost, atoms = setup
+    Qo, qo = om.surface_charge(ost.E, atoms, phi=ost.phi)
+    Qg, qg = gm.surface_charge(torch.from_numpy(atoms).cuda(),
+                               phi=torch.from_numpy(ost.phi).cuda())
+    assert _rel(Qg.cpu().numpy(), Qo) < 1e-12
+    assert _rel(qg.cpu().numpy(), qo) < 1e-12
+
+
+def test_surface_charge_fp32_field_and_own_solve(setup):
+    pic, cfg, om, gm, ost, atoms = setup
+    Qo, qo = om.surface_charge(ost.E, atoms)
+    _, qg = gm.surface_charge(torch.from_numpy(atoms).cuda(),
+                              E=_E4(ost.E, torch.float32))
+    assert _rel(qg.cpu().numpy(), qo) < 1e-6
+    gs = pic.State(gm, 16)
+    gs.init_field(cfg.E0, tol=1e-12)
+    Qs, qs = gm.surface_charge(torch.from_numpy(atoms).cuda(), E=gs.E)
+    assert _rel(Qs.cpu().numpy(), Qo) < 1e-9
+    assert _rel(qs.cpu().numpy(), qo) < 1e-9
+
+
+def test_surface_charge_without_atoms_and_checks(setup):
+    pic, cfg, om, gm, ost, atoms = setup
+    Qo, _ = om.surface_charge(ost.E, np.zeros((0, 3)))
+    Qg, qg = gm.surface_charge(torch.zeros((0, 3), dtype=torch.float64,
+                                           device="cuda"),
+                               E=_E4(ost.E, torch.float64))
+    assert qg.numel() == 0
+    assert _rel(Qg.cpu().numpy(), Qo) < 1e-12
+    with pytest.raises(pic.PicError):
+        gm.surface_charge(torch.from_numpy(atoms).cuda(), r_c=0.0,
+                          E=_E4(ost.E, torch.float64))
