@@ -107,6 +107,9 @@ def run_leg(gm, cfg, w_sp, precision, args):
     gm.profile(False)
     rows = pic.State.decode_stats(stats)
     step += args.steps
+    # state after the timed steps (the two precisions compared there)
+    snap = dict(phi=gs.phi.cpu().numpy().copy(), live=gs.live(),
+                mean_face_E=rows[-1]["mean_face_E"])
     # per-class breakdown: a further, untimed stretch of steps with every
     # kernel class bracketed
     kt = {}
@@ -135,7 +138,26 @@ def run_leg(gm, cfg, w_sp, precision, args):
         if r["status"] != 0:
             raise RuntimeError(f"step status {r['status']}: {r}")
     return dict(elapsed=elapsed, kt=kt, kt_timed=kt_timed, rows=rows,
-                rows_b=rows_b, state=gs, cold=cold, kt_coll=kt_coll)
+                rows_b=rows_b, state=gs, cold=cold, kt_coll=kt_coll, snap=snap)
+
+
+def precision_drift(a, b):
+    """Mixed against FP64 after the same steps: rel-L2 of phi, relative
+    error of the mean apex-face field, and over the superparticles present
+    in both (matched by id) rel-L2 and max abs of the positions."""
+    import numpy as np
+    phi = float(np.linalg.norm(b["phi"] - a["phi"]) / np.linalg.norm(a["phi"]))
+    Pa, Pb = a["live"], b["live"]
+    common, ia, ib = np.intersect1d(Pa["id"], Pb["id"], return_indices=True)
+    pa = np.stack([Pa[c][ia] for c in ("x", "y", "z")], 1)
+    pb = np.stack([Pb[c][ib] for c in ("x", "y", "z")], 1)
+    d = pb - pa
+    return dict(phi_rel_l2=phi,
+                mean_apex_field_rel=abs(b["mean_face_E"] / a["mean_face_E"] - 1),
+                positions_rel_l2=float(np.linalg.norm(d) / np.linalg.norm(pa)),
+                positions_max_abs_nm=float(np.abs(d).max()),
+                matched=int(common.size), fp64_live=int(Pa["id"].size),
+                mixed_live=int(Pb["id"].size))
 
 
 def run_gpu(args):
@@ -192,6 +214,7 @@ def run_gpu(args):
     leg = run_leg(gm, cfg, w_sp, pic.PIC_FP64, args)
     elapsed, kt, rows = leg["elapsed"], leg["kt"], leg["rows"]
     kt_timed, rows_b = leg["kt_timed"], leg["rows_b"]
+    snap64 = leg["snap"]
     collisions = None
     if "collide" in leg["kt_coll"]:
         c = leg["kt_coll"]["collide"]
@@ -253,7 +276,8 @@ def run_gpu(args):
                              launches=v["launches"],
                              us_per_launch=round(1e3 * v["ms"] / v["launches"], 2))
                      for n, v in mk.items()},
-            push_GBps=round(push_bytes(m_live, 4) / m_push_us / 1e3, 1))
+            push_GBps=round(push_bytes(m_live, 4) / m_push_us / 1e3, 1),
+            drift_vs_fp64=precision_drift(snap64, ml["snap"]))
         del ml
     batch = None
     if args.batch_instances > 0:
