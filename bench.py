@@ -205,7 +205,7 @@ def run_gpu(args):
     cold_amg_ms = e0.elapsed_time(e1)
     log(f"cold solve (AMG) {cold_amg} {cold_amg_ms:.2f} ms, "
         f"first call with setup {amg_setup_ms:.1f} ms")
-    rate, _ = gm.emission_rate(E, cfg.phi_w)
+    rate, faceF = gm.emission_rate(E, cfg.phi_w)
     rate = rate.item()
     w_sp = rate * cfg.dt * cfg.transit_steps / cfg.n_target
     log(f"emission {rate:.3e} e/fs -> w_sp {w_sp:.3e}")
@@ -283,6 +283,12 @@ def run_gpu(args):
     if args.batch_instances > 0:
         torch.cuda.empty_cache()
         batch = run_batch_leg(args)
+    stress = None
+    if args.stress_steps > 0:
+        torch.cuda.empty_cache()
+        stress = [run_stress_leg(gm, cfg, rate, faceF, args, pc)
+                  for pc in (pic.PIC_PRECOND_JACOBI, pic.PIC_PRECOND_AMG)]
+        log(f"stress leg {stress}")
     charge = None
     if args.charge_calls > 0:
         torch.cuda.empty_cache()
@@ -316,12 +322,57 @@ def run_gpu(args):
         batch=batch,
         collisions=collisions,
         surface_charge=charge,
+        stress=stress,
         roofline=dict(kernel=dom, bound="hbm", achieved=round(achieved, 1),
                       peak=HBM_PEAK_GBS, unit="GB/s",
                       frac=round(achieved / HBM_PEAK_GBS, 4),
                       traffic=(measured_traffic() if dom == "push" else None)),
     )
     return out, dict(cfg=cfg, tip=tip, w_sp=w_sp)
+
+
+def run_stress_leg(gm, cfg, rate, faceF, args, precond):
+    """The coupled ("stress") variant of the production workload: the FN
+    current scaled by M_J so that the charge in flight is 10 % of the
+    surface charge eps0 sum_f |E_f| A_f of the emitting faces (space charge
+    visible in phi, a CG solve every step); the same 1e6 superparticles."""
+    import torch
+
+    from paper_1906_08125_amd import pic
+
+    eps0 = 8.8541878128e-12 / 1.602176634e-19 * 1e-9   # e V^-1 nm^-1
+    area = gm.emit_faces()["area"]
+    q_target = 0.1 * eps0 * float((faceF.cpu().numpy() * area).sum())
+    per_run = rate * cfg.dt * cfg.transit_steps          # electrons in flight
+    m_j = q_target / per_run
+    w_sp = per_run * m_j / cfg.n_target
+    gs = pic.State(gm, int(args.capacity), precond=precond)
+    gs.init_field(cfg.E0, tol=cfg.tol)
+    kw = dict(dt=cfg.dt, E0=cfg.E0, w_sp=w_sp, phi_w=cfg.phi_w, seed=cfg.seed,
+              tol=cfg.tol, resort_every=args.resort, j_scale=m_j)
+    gs.step(step0=0, n_steps=args.stress_warmup, **kw)
+    torch.cuda.synchronize()
+    stats = torch.zeros(args.stress_steps * pic.STEP_STATS_BYTES // 8,
+                        dtype=torch.int64, device="cuda")
+    t0 = time.perf_counter()
+    gs.step(step0=args.stress_warmup, n_steps=args.stress_steps, stats=stats,
+            **kw)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    rows = pic.State.decode_stats(stats)
+    for r in rows:
+        if r["status"] != 0:
+            raise RuntimeError(f"stress step status {r['status']}: {r}")
+    live_q = rows[-1]["q_after"] / 2.0 ** 40 * w_sp
+    out = dict(precond="amg" if precond == pic.PIC_PRECOND_AMG else "jacobi",
+               M_J=m_j, w_sp=w_sp, value=round(args.stress_steps / el, 2),
+               unit="steps/s", ms_per_step=round(1e3 * el / args.stress_steps, 4),
+               cg_iters_per_step=sum(r["cg_iters"] for r in rows) / len(rows),
+               live_particles=rows[-1]["n_after"], live_charge_e=live_q,
+               target_charge_e=q_target,
+               mean_face_E=rows[-1]["mean_face_E"])
+    del gs
+    return out
 
 
 def run_charge_leg(tip, args):
@@ -556,6 +607,10 @@ def main():
                     help="instances of the batched leg (0: skip it)")
     ap.add_argument("--batch-warmup", type=int, default=30)
     ap.add_argument("--batch-steps", type=int, default=20)
+    ap.add_argument("--stress-steps", type=int, default=20,
+                    help="timed steps of the coupled variant (current scaled "
+                         "so that space charge shows; 0: skip)")
+    ap.add_argument("--stress-warmup", type=int, default=60)
     ap.add_argument("--charge-calls", type=int, default=5,
                     help="timed surface-charge calls over every metal face "
                          "of the production tip (0: skip)")
