@@ -120,3 +120,28 @@ def test_batch_autotune_and_mixed(pic):
         pg = np.stack([P["x"][ia], P["y"][ia], P["z"][ia]], 1)
         po = np.stack([Q["x"][ib], Q["y"][ib], Q["z"][ib]], 1)
         assert _rel(pg, po) < 1e-6
+
+
+def test_batch_with_collisions_matches_oracle(pic):
+    """Binary collisions after every re-sort in the batched path: each
+    instance as in the oracle with collisions every 5 steps."""
+    cap, steps = 40_000, 10
+    cases = [_setup(pic, c, 0.01, 3000, cap) for c in _cases()[:2]]
+    states, params = [], []
+    for tip, om, ost, gm, kw in cases:
+        gs = pic.State(gm, cap)
+        gs.init_field(kw["E0"], tol=kw["tol"])
+        states.append(gs)
+        params.append(dict(kw, resort_every=5, collide=1))
+    batch = pic.Batch([c[3] for c in cases], states, params)
+    so_all = [[] for _ in cases]
+    sg_all = [[] for _ in cases]
+    for k in range(steps):
+        for i, (tip, om, ost, gm, kw) in enumerate(cases):
+            so_all[i].append(ost.step(step=k, collide_every=5, **kw))
+        rows = pic.Batch.decode(batch.step(k, 1), len(cases))[0]
+        for i in range(len(cases)):
+            sg_all[i].append(rows[i])
+    torch.cuda.synchronize()
+    for i, (tip, om, ost, gm, kw) in enumerate(cases):
+        _compare_runs(ost, states[i], so_all[i], sg_all[i])
