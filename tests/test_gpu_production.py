@@ -20,7 +20,9 @@ size:
 Mixed precision (FP32 particles and field) runs the same checks with the
 FP32 bound: replayed positions, velocities and the field to 1e-6; the
 location and deposition of the stored FP32 positions (widened exactly)
-stay bit-exact."""
+stay bit-exact.  The cell field mode (FP64) runs them with the field of
+the particle's tet, and the emission current of the step against the
+oracle's cell-mode FN current."""
 import numpy as np
 import pytest
 
@@ -43,19 +45,21 @@ def prod():
     return pic, cfg, O.OracleMesh(tip, cfg.emit_zmin), pic.Mesh(tip, cfg.emit_zmin)
 
 
-@pytest.fixture(scope="module", params=["fp64", "mixed"])
+@pytest.fixture(scope="module", params=["fp64", "mixed", "fp64_cell"])
 def setup(request, prod):
     pic, cfg, om, gm = prod
-    gs = pic.State(gm, 2_500_000, precision=pic.PIC_FP64
-                   if request.param == "fp64" else pic.PIC_MIXED)
+    gs = pic.State(gm, 2_500_000, precision=pic.PIC_MIXED
+                   if request.param == "mixed" else pic.PIC_FP64)
     gs.init_field(cfg.E0, tol=cfg.tol)
     rate, _ = gm.emission_rate(gs.E.to(torch.float64), cfg.phi_w)
     w_sp = rate.item() * cfg.dt * cfg.transit_steps / cfg.n_target
     kw = dict(dt=cfg.dt, E0=cfg.E0, w_sp=w_sp, phi_w=cfg.phi_w, seed=cfg.seed,
-              tol=cfg.tol, resort_every=cfg.resort_every)
+              tol=cfg.tol, resort_every=cfg.resort_every,
+              field_mode=pic.PIC_FIELD_CELL if request.param == "fp64_cell"
+              else pic.PIC_FIELD_NODAL)
     gs.step(step0=0, n_steps=50, **kw)
     torch.cuda.synchronize()
-    return pic, cfg, om, gm, gs, kw, (1e-12 if request.param == "fp64" else 1e-6)
+    return pic, cfg, om, gm, gs, kw, (1e-6 if request.param == "mixed" else 1e-12)
 
 
 def _host(gs):
@@ -88,16 +92,22 @@ def _fields_and_charge(om, cfg, kw, S, ftol):
 
 def test_production_step_sampled(setup):
     pic, cfg, om, gm, gs, kw, ftol = setup
+    cell = kw["field_mode"] == pic.PIC_FIELD_CELL
     A = _host(gs)
-    gs.step(step0=50, n_steps=1, **kw)
+    srow = pic.State.decode_stats(gs.step(step0=50, n_steps=1, **kw))[0]
     B = _host(gs)
     _fields_and_charge(om, cfg, kw, B, ftol)
     # emission rate of the field the step started from
-    r_dev, _ = gm.emission_rate(torch.from_numpy(
-        np.concatenate([A["E"], np.zeros((len(A["E"]), 1))], 1).reshape(-1)).cuda(),
-        cfg.phi_w)
-    r_or, _ = om.emission_rate(A["E"], cfg.phi_w)
-    assert abs(r_dev.item() - r_or) <= ftol * r_or
+    if cell:
+        r_or, _ = om.emission_rate(A["E"], cfg.phi_w, phi=A["phi"])
+        assert abs(srow["emit_current"] - r_or) <= 1e-12 * r_or
+    else:
+        r_dev, _ = gm.emission_rate(torch.from_numpy(
+            np.concatenate([A["E"], np.zeros((len(A["E"]), 1))], 1).reshape(-1)).cuda(),
+            cfg.phi_w)
+        r_or, _ = om.emission_rate(A["E"], cfg.phi_w)
+        assert abs(r_dev.item() - r_or) <= ftol * r_or
+    Et = om.cell_field(A["phi"]) if cell else None
     # one step of 3000 sampled pre-step superparticles
     live = np.flatnonzero(A["tet"] >= 0)
     rng = np.random.default_rng(11)
@@ -118,9 +128,12 @@ def test_production_step_sampled(setup):
         p = np.array([A["x"][i], A["y"][i], A["z"][i]])
         v = np.array([A["vx"][i], A["vy"][i], A["vz"][i]])
         t = int(A["tet"][i])
-        lam = om.lam(t, p)
-        e = A["E"][nodes[t]]
-        E = ((lam[0] * e[0] + lam[1] * e[1]) + lam[2] * e[2]) + lam[3] * e[3]
+        if cell:
+            E = Et[t]
+        else:
+            lam = om.lam(t, p)
+            e = A["E"][nodes[t]]
+            E = ((lam[0] * e[0] + lam[1] * e[1]) + lam[2] * e[2]) + lam[3] * e[3]
         qE = Q * E
         v = (v + qE) + qE
         p = p + cfg.dt * v
