@@ -286,8 +286,10 @@ def run_gpu(args):
     stress = None
     if args.stress_steps > 0:
         torch.cuda.empty_cache()
-        stress = [run_stress_leg(gm, cfg, rate, faceF, args, pc)
-                  for pc in (pic.PIC_PRECOND_JACOBI, pic.PIC_PRECOND_AMG)]
+        stress = [run_stress_leg(gm, cfg, rate, faceF, args, pc, pr)
+                  for pc, pr in ((pic.PIC_PRECOND_JACOBI, pic.PIC_FP64),
+                                 (pic.PIC_PRECOND_JACOBI, pic.PIC_MIXED),
+                                 (pic.PIC_PRECOND_AMG, pic.PIC_FP64))]
         log(f"stress leg {stress}")
     charge = None
     if args.charge_calls > 0:
@@ -331,7 +333,7 @@ def run_gpu(args):
     return out, dict(cfg=cfg, tip=tip, w_sp=w_sp)
 
 
-def run_stress_leg(gm, cfg, rate, faceF, args, precond):
+def run_stress_leg(gm, cfg, rate, faceF, args, precond, precision=0):
     """The coupled ("stress") variant of the production workload: the FN
     current scaled by M_J so that the charge in flight is 10 % of the
     surface charge eps0 sum_f |E_f| A_f of the emitting faces (space charge
@@ -346,7 +348,8 @@ def run_stress_leg(gm, cfg, rate, faceF, args, precond):
     per_run = rate * cfg.dt * cfg.transit_steps          # electrons in flight
     m_j = q_target / per_run
     w_sp = per_run * m_j / cfg.n_target
-    gs = pic.State(gm, int(args.capacity), precond=precond)
+    gs = pic.State(gm, int(args.capacity), precond=precond,
+                   precision=precision, inner_tol=args.inner_tol)
     gs.init_field(cfg.E0, tol=cfg.tol)
     kw = dict(dt=cfg.dt, E0=cfg.E0, w_sp=w_sp, phi_w=cfg.phi_w, seed=cfg.seed,
               tol=cfg.tol, resort_every=args.resort, j_scale=m_j)
@@ -365,6 +368,7 @@ def run_stress_leg(gm, cfg, rate, faceF, args, precond):
             raise RuntimeError(f"stress step status {r['status']}: {r}")
     live_q = rows[-1]["q_after"] / 2.0 ** 40 * w_sp
     out = dict(precond="amg" if precond == pic.PIC_PRECOND_AMG else "jacobi",
+               precision="mixed" if precision == pic.PIC_MIXED else "fp64",
                M_J=m_j, w_sp=w_sp, value=round(args.stress_steps / el, 2),
                unit="steps/s", ms_per_step=round(1e3 * el / args.stress_steps, 4),
                cg_iters_per_step=sum(r["cg_iters"] for r in rows) / len(rows),
