@@ -6,7 +6,9 @@ faces emitting, w_sp set for ~1e6 live superparticles, dt = 0.5 fs,
 PCG tolerance 1e-10).  W warm-up steps bring the run to its steady state
 (~1e6 live), then K steps are timed between device synchronizations.
 
-Prints one JSON line (see the design doc for the roofline byte model).
+Prints one JSON line.  Roofline byte model of the push: 112 B per live
+superparticle and step in FP64 (read x, y, z, vx, vy, vz, w and the tet
+id; write the six reals and the tet id), 64 B in mixed precision.
 """
 from __future__ import annotations
 
@@ -633,8 +635,9 @@ def main():
                     help="FP32 inner CG target of the mixed leg")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: the multi-GPU layout of this "
-              "PIC cycle is a design (see DESIGN.md), not a build", file=sys.stderr)
+        print("bench.py runs on one GPU only: a multi-GPU layout of this "
+              "PIC cycle (z-slab domains, particle migration, halo exchange "
+              "in the solve) is designed, not implemented", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
         import torch
