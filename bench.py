@@ -585,12 +585,29 @@ def cpu_baseline(cfg, tip, n_particles, n_steps):
         ost.step(dt=cfg.dt, E0=cfg.E0, w_sp=w_sp, phi_w=cfg.phi_w, step=k,
                  seed=cfg.seed, tol=cfg.tol)
     dt = time.perf_counter() - t0
+    # the oracle's binary collisions on the same population (App. F)
+    t1 = time.perf_counter()
+    ost.collide(dt_coll=10 * cfg.dt, w_sp=w_sp, seed=cfg.seed, step=n_steps)
+    coll_s = time.perf_counter() - t1
+    # and its surface charge of every metal face to the seeded atoms
+    from paper_1906_08125_amd import workloads as W
+    omc = O.OracleMesh(tip, -1.0)
+    sc = O.OracleState(omc, 4)
+    sc.init_field(cfg.E0, tol=cfg.tol)
+    atoms = W.surface_atoms(tip, density=4.0)
+    t2 = time.perf_counter()
+    omc.surface_charge(sc.E, atoms)
+    charge_s = time.perf_counter() - t2
     return dict(value=round(n_steps / dt, 5), unit="steps/s", cores=1,
                 kind="oracle",
                 sample=(f"{n_steps} steps of the FP64 oracle (single thread) on "
                         f"the same 3.1M-tet mesh with {n0} seeded synthetic "
-                        "superparticles in the gap above the apex"),
-                pushes_per_s=round(n0 * n_steps / dt, 1))
+                        "superparticles in the gap above the apex; then one "
+                        "collision pass over them and one surface charge of "
+                        f"the {omc.n_emit} metal faces to {len(atoms)} atoms"),
+                pushes_per_s=round(n0 * n_steps / dt, 1),
+                collide_s_per_call=round(coll_s, 4),
+                surface_charge_s_per_call=round(charge_s, 4))
 
 
 def main():
