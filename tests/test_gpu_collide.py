@@ -162,3 +162,28 @@ def test_pic_step_with_collisions_matches_oracle(pic):
     common = min(ia.size, ic.size)
     assert not np.allclose(P["vx"][ia][:common], R["vx"][ic][:common],
                            rtol=1e-6, atol=0)
+
+
+def test_collide_edge_cases(pic, tiny_mesh):
+    """No superparticles, and only singletons (nothing to pair): the call
+    succeeds and no velocity changes; a step with collisions on an empty
+    gap does too."""
+    om = O.OracleMesh(tiny_mesh, 0.01)
+    gm = pic.Mesh(tiny_mesh, 0.01)
+    gs = pic.State(gm, 64)
+    gs.collide(dt_coll=1.0, w_sp=1.0, seed=1, step=0)
+    T = om.tets()
+    tet = np.arange(0, 40, 2, dtype=np.int32)          # one per tet
+    pos = T["vert"].mean(axis=1)[tet]
+    vel = np.random.default_rng(2).normal(size=(tet.size, 3))
+    g1 = _gpu_state(pic, gm, tet, pos, vel, np.arange(tet.size) * 3 + 1,
+                    pic.PIC_FP64)
+    g1.collide(dt_coll=1.0, w_sp=1.0, seed=1, step=0)
+    torch.cuda.synchronize()
+    assert np.array_equal(g1.vx[:tet.size].cpu().numpy(), vel[:, 0])
+    g2 = pic.State(gm, 64)
+    g2.init_field(0.4)
+    st = pic.State.decode_stats(g2.step(dt=0.5, E0=0.4, w_sp=1.0, phi_w=4.5,
+                                        step0=4, seed=1, collide=1,
+                                        resort_every=5, j_scale=0.0))[0]
+    assert st["status"] == 0 and st["n_after"] == 0
