@@ -1140,8 +1140,16 @@ static void collide_pair(oparticles* P, int64_t a, int64_t b, double nv,
   double U1 = 1.0 - u01(w[0]), U2 = u01(w[1]), U3 = u01(w[2]);
   double g = sqrt(-2.0 * log(U1)) * cos(2.0 * PI_ * U2); /* Box-Muller */
   double delta = sqrt(var) * g;
-  double st = 2.0 * delta / (1.0 + delta * delta);          /* sin theta */
-  double omc = 2.0 * delta * delta / (1.0 + delta * delta); /* 1 - cos theta */
+  double st, omc; /* sin theta, 1 - cos theta (Eq. sin_theta) */
+  if (delta != delta) delta = 0.0; /* infinite variance times g = 0 */
+  if (fabs(delta) < 1e100) {
+    st = 2.0 * delta / (1.0 + delta * delta);
+    omc = 2.0 * delta * delta / (1.0 + delta * delta);
+  } else { /* the same limits without overflow: theta -> pi */
+    double r = 1.0 / delta;
+    st = 2.0 * r;
+    omc = 2.0 - 2.0 * r * r;
+  }
   double ph = 2.0 * PI_ * U3;
   double up = sqrt(ux * ux + uy * uy);
   double d[3];

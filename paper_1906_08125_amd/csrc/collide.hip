@@ -80,9 +80,17 @@ __device__ void collide_pair(const CollideArgs& a, int32_t ia, int32_t ib,
   const double U1 = 1.0 - unit_double(r[0]), U2 = unit_double(r[1]),
                U3 = unit_double(r[2]);
   const double g = sqrt(-2.0 * log(U1)) * cos(kTwoPi * U2);
-  const double delta = sqrt(var) * g;
-  const double st = 2.0 * delta / (1.0 + delta * delta);
-  const double omc = 2.0 * delta * delta / (1.0 + delta * delta);
+  double delta = sqrt(var) * g;
+  double st, omc;  // sin theta, 1 - cos theta
+  if (delta != delta) delta = 0.0;  // infinite variance times g = 0
+  if (fabs(delta) < 1e100) {
+    st = 2.0 * delta / (1.0 + delta * delta);
+    omc = 2.0 * delta * delta / (1.0 + delta * delta);
+  } else {  // the same limits without overflow: theta -> pi
+    const double r = 1.0 / delta;
+    st = 2.0 * r;
+    omc = 2.0 - 2.0 * r * r;
+  }
   const double phi = kTwoPi * U3;
   double sp, cp;
   sincos(phi, &sp, &cp);

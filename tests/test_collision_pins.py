@@ -147,3 +147,20 @@ def test_scattering_angles_are_gaussian_in_tan_half_theta(tiny_mesh):
     assert abs((z < 1).mean() - 0.6827) < 0.015
     # the relative speed is unchanged
     assert np.abs(np.linalg.norm(rel1, axis=1) - u).max() < 1e-13
+
+
+def test_extreme_variance_stays_finite(tiny_mesh):
+    """Pairs with nearly equal velocities (relative speed 1e-120 nm/fs:
+    <delta^2> overflows) still conserve momentum and energy and stay
+    finite: Eq. sin_theta in its theta -> pi limit."""
+    rng = np.random.default_rng(61)
+    N = 200
+    base = rng.normal(size=(N, 3))
+    d = _unit(rng, N) * 1e-120
+    groups = [np.stack([base[i], base[i] + d[i]]) for i in range(N)]
+    om, T, st, tet = _state(tiny_mesh, range(N), groups)
+    v0 = np.stack([st.vx[:st.n], st.vy[:st.n], st.vz[:st.n]], 1).copy()
+    st.collide(dt_coll=1.0, w_sp=1.0, seed=3, step=1)
+    v1 = np.stack([st.vx[:st.n], st.vy[:st.n], st.vz[:st.n]], 1)
+    assert np.isfinite(v1).all()
+    assert np.abs(v1 - v0).max() < 1e-100

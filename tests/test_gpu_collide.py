@@ -181,6 +181,18 @@ def test_collide_edge_cases(pic, tiny_mesh):
     g1.collide(dt_coll=1.0, w_sp=1.0, seed=1, step=0)
     torch.cuda.synchronize()
     assert np.array_equal(g1.vx[:tet.size].cpu().numpy(), vel[:, 0])
+    # nearly equal velocities (the variance overflows): finite, as the oracle
+    pair = np.array([5, 5], dtype=np.int32)
+    vv = np.array([[0.3, -0.2, 1.1], [0.3, -0.2, 1.1 + 1e-120]])
+    g3 = _gpu_state(pic, gm, pair, T["vert"].mean(axis=1)[pair], vv,
+                    np.array([7, 9]), pic.PIC_FP64)
+    g3.collide(dt_coll=1.0, w_sp=1.0, seed=1, step=0)
+    o3 = O.OracleState(om, 4)
+    o3.add(T["vert"].mean(axis=1)[pair], vv, pair, ids=np.array([7, 9]))
+    o3.collide(dt_coll=1.0, w_sp=1.0, seed=1, step=0)
+    vg = np.stack([t[:2].cpu().numpy() for t in (g3.vx, g3.vy, g3.vz)], 1)
+    assert np.isfinite(vg).all()
+    assert np.array_equal(vg, np.stack([o3.vx[:2], o3.vy[:2], o3.vz[:2]], 1))
     g2 = pic.State(gm, 64)
     g2.init_field(0.4)
     st = pic.State.decode_stats(g2.step(dt=0.5, E0=0.4, w_sp=1.0, phi_w=4.5,
