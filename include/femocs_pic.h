@@ -227,6 +227,14 @@ typedef struct {
                         /* re-sort, standing for resort_every steps       */
                         /* (needs resort_every > 0); 0: none              */
   int32_t pad;
+  /* device [n_emit] or NULL: frozen emission counts -- each face injects */
+  /* counts_in[f] superparticles (clamped to [0, 2^21]) instead of the     */
+  /* rounding of Eq. rnd_nsp, in every step of the call (finite            */
+  /* differences of a window hold them, as its adjoint does); counts_out:  */
+  /* device [n_emit] or NULL, receives the counts used (the last step's).  */
+  /* pic_batch_step takes neither (PIC_E_ARG).                             */
+  const int32_t* counts_in;
+  int32_t* counts_out;
   pic_solve_params solve;
 } pic_step_params;
 

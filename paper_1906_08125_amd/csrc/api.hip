@@ -454,6 +454,8 @@ StepSet step_set(pic_mesh* h, const pic_particles* P, const pic_fields* F,
   ea.f32 = f32;
   ea.cell = a.cell;
   ea.phi = F->phi;
+  ea.counts_in = prm->counts_in;
+  ea.counts_out = prm->counts_out;
   ea.c = {ph.a_fn, ph.b_fn, ph.c_s, ph.j_unit};
   ea.phi_w = prm->phi_w;
   ea.j_scale = prm->j_scale;
@@ -1102,6 +1104,8 @@ pic_status pic_batch_step(pic_batch* b, const pic_particles* P,
     pic_mesh* h = b->h[i];
     pic_status ps = check_step(&P[i], &F[i], &prm[i], n_steps, "pic_batch_step");
     if (ps != PIC_OK) return ps;
+    if (prm[i].counts_in || prm[i].counts_out)
+      return fail(PIC_E_ARG, "pic_batch_step: frozen emission counts are not batched");
     if ((P[i].precision == PIC_MIXED) != f32)
       return fail(PIC_E_ARG, "pic_batch_step: instances differ in precision");
     if (prm[i].solve.precond != PIC_PRECOND_JACOBI)

@@ -67,6 +67,8 @@ struct EmitArgs {
   int defer;
   int cell;               // as StepArgs::cell (face field of the face's tet)
   const double* phi;
+  const int32_t* counts_in;  // frozen per-face counts (replace the rounding) or null
+  int32_t* counts_out;       // the counts used, or null
 };
 
 struct LocateArgs {

@@ -497,6 +497,11 @@ __device__ void emit_block(const EmitArgs& a) {
         double c = (R >= nsp - fl) ? fl : ceil(nsp);
         if (c > 2097152.0) c = 2097152.0;
         cnt = (long long)c;
+        if (a.counts_in) {
+          const int32_t ci = a.counts_in[f];
+          cnt = ci < 0 ? 0 : (ci > 2097152 ? 2097152 : ci);
+        }
+        if (a.counts_out) a.counts_out[f] = (int32_t)cnt;
       }
       if (a.face_F) a.face_F[f] = F;
     }

@@ -71,6 +71,7 @@ class StepParams(C.Structure):
                 ("instance", C.c_int64), ("s_face", C.c_void_p),
                 ("resort_every", C.c_int32), ("field_mode", C.c_int32),
                 ("collide", C.c_int32), ("pad", C.c_int32),
+                ("counts_in", C.c_void_p), ("counts_out", C.c_void_p),
                 ("solve", SolveParams)]
 
 
@@ -375,7 +376,9 @@ class State:
     def step(self, *, dt, E0, w_sp, phi_w, step0, seed, n_steps=1, instance=0,
              j_scale=1.0, tol=1e-12, max_iter=20000, s_face=None,
              resort_every=0, field_mode=PIC_FIELD_NODAL, collide=0,
-             stats=None):
+             counts_in=None, counts_out=None, stats=None):
+        """counts_in / counts_out: device int32 [n_emit] frozen emission
+        counts / the counts used (see pic_step_params)."""
         torch = _torch()
         if stats is None:
             stats = torch.zeros(n_steps * STEP_STATS_BYTES // 8,
@@ -383,6 +386,8 @@ class State:
         prm = StepParams(dt, E0, w_sp, phi_w, j_scale, seed, step0, instance,
                          None if s_face is None else s_face.data_ptr(),
                          resort_every, field_mode, int(collide), 0,
+                         None if counts_in is None else counts_in.data_ptr(),
+                         None if counts_out is None else counts_out.data_ptr(),
                          SolveParams(tol, self.inner_tol, max_iter,
                                      self.solve_precision, self.precond))
         _check(load_library().pic_step(self.mesh.handle, C.byref(self._p),
@@ -482,6 +487,7 @@ class Window:
         k = self.kw
         return StepParams(k["dt"], E0, k["w_sp"], k["phi_w"], k["j_scale"],
                           k["seed"], step0, k["instance"], s.data_ptr(), 0, 0, 0, 0,
+                          None, None,
                           SolveParams(k["tol"], self.state.inner_tol,
                                       k["max_iter"], self.adj_precision,
                                       self.adj_precond))
@@ -507,9 +513,13 @@ class Window:
         return F.mean() if F.numel() else torch.zeros((), dtype=torch.float64,
                                                       device=E.device)
 
-    def forward(self, E0: float, s):
+    def forward(self, E0: float, s, counts=None):
         """Runs the window from the base population; returns (J_Q, J_E) as
-        device scalars and keeps the checkpoints."""
+        device scalars and keeps the checkpoints.  counts: None, or the
+        per-step emission counts to hold (a list of T device int32 [n_emit],
+        e.g. the `counts` of an earlier forward) -- finite differences of J
+        hold them, as the adjoint does.  The counts used are kept in
+        `counts` (and replayed by backward)."""
         torch = _torch()
         st, k = self.state, self.kw
         self.base.restore(st)
@@ -518,6 +528,8 @@ class Window:
         st.w.copy_(torch.where(live, self.base.w * sb, self.base.w))
         self._initial_field(st, E0)
         self.cks = []
+        used = [torch.zeros(max(self.mesh.n_emit, 1), dtype=torch.int32,
+                            device=st.phi.device) for _ in range(self.T)]
         JQ = torch.zeros((), dtype=torch.float64, device=st.phi.device)
         JE = torch.zeros((), dtype=torch.float64, device=st.phi.device)
         for j in range(self.T):
@@ -526,11 +538,14 @@ class Window:
                             step0=self.step0 + j, seed=k["seed"],
                             instance=k["instance"], j_scale=k["j_scale"],
                             tol=k["tol"], max_iter=k["max_iter"], s_face=s,
-                            resort_every=0)
+                            resort_every=0,
+                            counts_in=None if counts is None else counts[j],
+                            counts_out=used[j])
             row = stats.view(-1)
             JQ = JQ + row[STEP_STATS_FIELDS.index("q_anode")].to(torch.float64) * (
                 k["w_sp"] / CHARGE_SCALE)
             JE = JE + self._face_mean(st.E) / self.T
+        self.counts = used
         return JQ, JE
 
     def backward(self, E0: float, s, wQ=1.0, wE=1.0):
@@ -555,7 +570,7 @@ class Window:
             sc.step(dt=k["dt"], E0=E0, w_sp=k["w_sp"], phi_w=k["phi_w"],
                     step0=self.step0 + j, seed=k["seed"], instance=k["instance"],
                     j_scale=k["j_scale"], tol=k["tol"], max_iter=k["max_iter"],
-                    s_face=s, resort_every=0)
+                    s_face=s, resort_every=0, counts_in=self.counts[j])
             prm = self._params(E0, s, self.step0 + j)
             _check(L.adjoint_step(self.mesh.handle, C.byref(ck.p),
                                   C.byref(sc._p), C.byref(ck.f),
@@ -678,6 +693,7 @@ class Batch:
                 kw["seed"], step0, kw.get("instance", 0),
                 None if sf is None else sf.data_ptr(), kw.get("resort_every", 0),
                 kw.get("field_mode", PIC_FIELD_NODAL), int(kw.get("collide", 0)), 0,
+                None, None,
                 SolveParams(kw.get("tol", 1e-10), st.inner_tol,
                             kw.get("max_iter", 20000), st.solve_precision)))
         S = (StepParams * n)(*prms)

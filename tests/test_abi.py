@@ -66,7 +66,8 @@ def test_struct_layouts_match_the_header(tmp_path):
     from paper_1906_08125_amd import pic
     checks = {
         "pic_step_params": (pic.StepParams, ["resort_every", "field_mode",
-                                             "collide", "solve"]),
+                                             "collide", "counts_in",
+                                             "counts_out", "solve"]),
         "pic_collide_params": (pic.CollideParams, ["dt_coll", "w_sp", "seed",
                                                    "step", "instance"]),
         "pic_solve_params": (pic.SolveParams, ["tol", "precond"]),
