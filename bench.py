@@ -33,7 +33,7 @@ HBM_PEAK_GBS = 8000.0
 PUSH_TRAFFIC = dict(bytes=200.0e6, read=134.4e6, written=65.6e6,
                     sources=("paper_1906_08125_amd/csrc/particles.hip",
                              "paper_1906_08125_amd/csrc/common.h"),
-                    sha256=("1a9c2020ee14baedf7b5241d9176d2148fc579285e1d2aae351b67fca7da1d5b", "7d8f3c2344d581d986633cc1e8597ea0062a3ad5736211095600e29a54930541"))
+                    sha256=("134e33f198c3176cfe6b232d6ed92ef5f7f5f3d69bea0fbcf81858bb7249254c", "7d8f3c2344d581d986633cc1e8597ea0062a3ad5736211095600e29a54930541"))
 
 
 def measured_traffic():
