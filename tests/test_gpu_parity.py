@@ -597,3 +597,36 @@ def test_pic_step_mixed_space_charge(pic):
                                         phi_err=err)
     assert all(s["cg_iters"] > 0 for s in sg[1:])
     _compare_mixed(ost, gs, so, sg, err)
+
+
+def test_pic_step_held_counts(pic):
+    """Emission counts held from outside (counts_in, as finite differences
+    of a window need): counts twice those of the rounding, the same on
+    both sides, for 6 steps of the space-charge run; counts_out returns
+    them."""
+    cfg = W.config_tiny()
+    tip = cfg.mesh()
+    om = O.OracleMesh(tip, cfg.emit_zmin)
+    ost = O.OracleState(om, 60_000)
+    ost.init_field(cfg.E0, tol=cfg.tol)
+    rate, _ = om.emission_rate(ost.E, cfg.phi_w)
+    per_run = rate * cfg.dt * cfg.transit_steps
+    j_scale = 0.01 / per_run
+    w_sp = per_run * j_scale / 3000
+    gm = pic.Mesh(tip, cfg.emit_zmin)
+    gs = pic.State(gm, 60_000)
+    gs.init_field(cfg.E0, tol=cfg.tol)
+    kw = dict(dt=cfg.dt, E0=cfg.E0, w_sp=w_sp, phi_w=cfg.phi_w, seed=cfg.seed,
+              j_scale=j_scale, tol=cfg.tol)
+    rng = np.random.default_rng(4)
+    so_all, sg_all = [], []
+    out = torch.zeros(om.n_emit, dtype=torch.int32, device="cuda")
+    for k in range(6):
+        held = rng.integers(0, 3, om.n_emit)
+        so_all.append(ost.step(step=k, counts_in=held, **kw))
+        sg_all.append(pic.State.decode_stats(gs.step(
+            step0=k, counts_in=torch.from_numpy(held.astype(np.int32)).cuda(),
+            counts_out=out, **kw))[0])
+        assert (out.cpu().numpy() == held).all()
+        assert so_all[-1]["n_inj"] == int(held.sum())
+    _compare_runs(ost, gs, so_all, sg_all)
