@@ -173,7 +173,16 @@ int charge_splits(int64_t n_emit, int64_t n_atoms, int n_cu) {
 }
 
 hipError_t surface_charge_launch(const ChargeArgs& a, int n_cu, hipStream_t s) {
-  if (a.m.n_emit == 0) return hipSuccess;
+  if (a.m.n_emit == 0) {
+    // no faces: every atom's charge is the empty sum
+    if (a.n_atoms > 0) {
+      ChargeArgs z = a;
+      z.n_split = 0;
+      const int ga = (int)((a.n_atoms + kThreads - 1) / kThreads);
+      hipLaunchKernelGGL(k_atom_reduce, dim3(ga), dim3(kThreads), 0, s, z);
+    }
+    return hipGetLastError();
+  }
   const int gf = (int)(a.m.n_emit < (int64_t)n_cu * 16 ? a.m.n_emit : (int64_t)n_cu * 16);
   hipLaunchKernelGGL(k_face_charge, dim3(gf), dim3(kThreads), 0, s, a);
   if (a.n_atoms > 0) {

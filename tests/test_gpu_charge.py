@@ -86,3 +86,16 @@ def test_surface_charge_without_atoms_and_checks(setup):
     with pytest.raises(pic.PicError):
         gm.surface_charge(torch.from_numpy(atoms).cuda(), r_c=0.0,
                           E=_E4(ost.E, torch.float64))
+
+
+def test_surface_charge_no_faces(setup):
+    """A mesh whose emitting set is empty (emit_zmin above the box): the
+    atoms' charges are the empty sum, written as zeros."""
+    pic, cfg, om, gm, ost, atoms = setup
+    g0 = pic.Mesh(cfg.mesh(), 1e9)
+    assert g0.n_emit == 0
+    at = torch.from_numpy(atoms).cuda()
+    E = torch.zeros(4 * g0.n_nodes, dtype=torch.float64, device="cuda")
+    Q, q = g0.surface_charge(at, E=E)
+    q_host = q.cpu().numpy()
+    assert Q.numel() == 0 and q_host.size == len(atoms) and (q_host == 0).all()
