@@ -199,3 +199,13 @@ def test_collide_edge_cases(pic, tiny_mesh):
                                         step0=4, seed=1, collide=1,
                                         resort_every=5, j_scale=0.0))[0]
     assert st["status"] == 0 and st["n_after"] == 0
+
+
+def test_pic_step_with_collisions_mixed(pic):
+    """The same run in mixed precision (FP32 velocities collided in FP64
+    arithmetic): against the FP64 oracle within the mixed-precision bound."""
+    from tests.test_gpu_parity import _compare_mixed
+    cfg = W.config_tiny()
+    ost, gs, so, sg = _run(pic, cfg, 15, 1, precision=pic.PIC_MIXED)
+    err = [_rel(gs.phi.cpu().numpy(), ost.phi)]
+    _compare_mixed(ost, gs, so, sg, err)
