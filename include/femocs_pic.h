@@ -247,12 +247,14 @@ typedef struct {
 } pic_step_stats;
 
 /* Advance n_steps steps k = step0 .. step0+n_steps-1.  Per step: gather the
- * nodal field at each particle and kick (Eq. leapfrog3 then Eq. leapfrog1),
- * inject from the emitting faces with the same field (Eq. nsp,
- * Eq. rnd_nsp, App. E, Eq. sp_velocity, Eq. sp_displacement), drift
- * (Eq. leapfrog2), wrap laterally, absorb at z >= z_top (anode) or outside
- * the vacuum (cathode), locate, deposit, solve for phi_{k+1} and recover the
- * nodal field.  fields->E must hold the field of phi on entry.
+ * field at each particle (params->field_mode) and kick (Eq. leapfrog3 then
+ * Eq. leapfrog1), inject from the emitting faces with the same field
+ * (Eq. nsp, Eq. rnd_nsp -- or the held counts_in --, App. E,
+ * Eq. sp_velocity, Eq. sp_displacement), drift (Eq. leapfrog2), wrap
+ * laterally, absorb at z >= z_top (anode) or outside the vacuum (cathode),
+ * locate, deposit, re-sort by tet every resort_every steps (then collide,
+ * when params->collide), solve for phi_{k+1} and recover the nodal field.
+ * fields->E must hold the field of phi on entry.
  * Mixed precision (particles->precision PIC_MIXED, not in the paper):
  * positions, velocities and fields->E are FP32, and the field gather, kick,
  * drift and wrap run in FP32; the barycentric weights of the stored FP32
