@@ -139,13 +139,13 @@ __device__ inline int before(uint64_t kj, int64_t dj, int32_t j, uint64_t ki,
 }
 
 // Every wave stages the tets, keys, ids and weights of the slots
-// [i0 - 64, i0 + 192) around its 64 slots in LDS; each slot scans its
+// [i0 - 64, i0 + 128) around its 64 slots in LDS; each slot scans its
 // neighbours there (at most kSmallRun + 1 each way) for the run of its
 // tet.  A run of up to kSmallRun is ranked here (each member counts the
 // members before it; the first member sums the weights); the first member
 // of a longer run finds its end by binary search and lists it for
 // k_coll_rank_big.
-constexpr int kWin = 256;    // staged slots per wave
+constexpr int kWin = 192;    // staged slots per wave
 constexpr int kWinLo = 64;   // of them before the wave's first slot
 // the backward scan reads down to li - kSmallRun - 1 >= 0, the forward
 // scan up to li + kSmallRun + 1 < kWin (li = kWinLo + lane)
