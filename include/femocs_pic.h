@@ -231,8 +231,8 @@ typedef struct {
   /* counts_in[f] superparticles (clamped to [0, 2^21]) instead of the     */
   /* rounding of Eq. rnd_nsp, in every step of the call (finite            */
   /* differences of a window hold them, as its adjoint does); counts_out:  */
-  /* device [n_emit] or NULL, receives the counts used (the last step's).  */
-  /* pic_batch_step takes neither (PIC_E_ARG).                             */
+  /* device [n_emit] or NULL, receives the counts used (the last step's;  */
+  /* in pic_batch_step, per instance).                                     */
   const int32_t* counts_in;
   int32_t* counts_out;
   pic_solve_params solve;

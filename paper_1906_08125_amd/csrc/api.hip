@@ -1104,8 +1104,6 @@ pic_status pic_batch_step(pic_batch* b, const pic_particles* P,
     pic_mesh* h = b->h[i];
     pic_status ps = check_step(&P[i], &F[i], &prm[i], n_steps, "pic_batch_step");
     if (ps != PIC_OK) return ps;
-    if (prm[i].counts_in || prm[i].counts_out)
-      return fail(PIC_E_ARG, "pic_batch_step: frozen emission counts are not batched");
     if ((P[i].precision == PIC_MIXED) != f32)
       return fail(PIC_E_ARG, "pic_batch_step: instances differ in precision");
     if (prm[i].solve.precond != PIC_PRECOND_JACOBI)

@@ -693,7 +693,8 @@ class Batch:
                 kw["seed"], step0, kw.get("instance", 0),
                 None if sf is None else sf.data_ptr(), kw.get("resort_every", 0),
                 kw.get("field_mode", PIC_FIELD_NODAL), int(kw.get("collide", 0)), 0,
-                None, None,
+                None if kw.get("counts_in") is None else kw["counts_in"].data_ptr(),
+                None if kw.get("counts_out") is None else kw["counts_out"].data_ptr(),
                 SolveParams(kw.get("tol", 1e-10), st.inner_tol,
                             kw.get("max_iter", 20000), st.solve_precision)))
         S = (StepParams * n)(*prms)

@@ -145,3 +145,28 @@ def test_batch_with_collisions_matches_oracle(pic):
     torch.cuda.synchronize()
     for i, (tip, om, ost, gm, kw) in enumerate(cases):
         _compare_runs(ost, states[i], so_all[i], sg_all[i])
+
+
+def test_batch_held_counts(pic):
+    """Held emission counts per instance in the batched path: every
+    instance injects exactly its counts_in and reports them in counts_out."""
+    cap = 40_000
+    cases = [_setup(pic, c, 0.01, 3000, cap) for c in _cases()[:2]]
+    rng = np.random.default_rng(8)
+    states, params, held, outs = [], [], [], []
+    for tip, om, ost, gm, kw in cases:
+        gs = pic.State(gm, cap)
+        gs.init_field(kw["E0"], tol=kw["tol"])
+        states.append(gs)
+        h = rng.integers(0, 3, om.n_emit).astype(np.int32)
+        held.append(h)
+        o = torch.zeros(om.n_emit, dtype=torch.int32, device="cuda")
+        outs.append(o)
+        params.append(dict(kw, counts_in=torch.from_numpy(h).cuda(),
+                           counts_out=o))
+    batch = pic.Batch([c[3] for c in cases], states, params)
+    rows = pic.Batch.decode(batch.step(0, 1), len(cases))[0]
+    torch.cuda.synchronize()
+    for i in range(len(cases)):
+        assert rows[i]["n_inj"] == int(held[i].sum())
+        assert (outs[i].cpu().numpy() == held[i]).all()
