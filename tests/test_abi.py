@@ -95,3 +95,11 @@ def test_struct_layouts_match_the_header(tmp_path):
         assert int(out[cname]) == C.sizeof(cls), cname
         for f in fields:
             assert int(out[f"{cname}.{f}"]) == getattr(cls, f).offset, (cname, f)
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path, monkeypatch):
+    """No CPU fallback: a missing library is an error, not a slower path."""
+    from paper_1906_08125_amd import pic
+    monkeypatch.setattr(pic, "_lib", None)
+    with pytest.raises(ImportError):
+        pic.load_library(str(tmp_path / "absent.so"))
