@@ -126,6 +126,95 @@ def kuhn_tip_mesh(nx: int, ny: int, nz: int, h: float = 0.5,
                    tip_R=float(tip_R), tip_H=float(tip_H))
 
 
+@dataclasses.dataclass
+class MetalMesh:
+    """Arrays describing the metal domain (host, numpy): the tip solid and a
+    substrate slab under the cathode plane, not periodic (its lateral faces
+    carry no flux)."""
+    xyz: np.ndarray        # float64 [n_nodes, 3]
+    tet: np.ndarray        # int32 [n_tets, 4]
+    faces: np.ndarray      # int32 [n_faces, 3] metal-vacuum interface triangles
+    face_tet: np.ndarray   # int32 [n_faces] the metal tetrahedron of each face
+    dirichlet: np.ndarray  # uint8 [n_nodes] 1 on the substrate's bottom plane
+    z_bottom: float
+
+    @property
+    def n_nodes(self) -> int:
+        return int(self.xyz.shape[0])
+
+    @property
+    def n_tets(self) -> int:
+        return int(self.tet.shape[0])
+
+    @property
+    def n_faces(self) -> int:
+        return int(self.faces.shape[0])
+
+
+def kuhn_metal_mesh(nx: int, ny: int, nz: int, h: float, tip_R: float,
+                    tip_H: float, depth: int) -> MetalMesh:
+    """The metal counterpart of kuhn_tip_mesh(nx, ny, nz, h, tip_R, tip_H):
+    the tetrahedra that mesh removes (those with a vertex strictly inside the
+    tip) plus `depth` layers of Kuhn-split cubes below z = 0.  Nodes are
+    numbered by integer grid position (i, j, k), i in [0, nx], j in [0, ny],
+    k in [-depth, nz], compacted in that order.  The interface faces are the
+    faces that belong to exactly one metal tetrahedron and lie neither on
+    the bottom plane z = -depth h nor on a lateral plane of the box; the
+    Dirichlet nodes are those of the bottom plane."""
+    ii, jj, kk = np.meshgrid(np.arange(nx), np.arange(ny),
+                             np.arange(-depth, nz), indexing="ij")
+    base = np.stack([ii.reshape(-1), jj.reshape(-1), kk.reshape(-1)], 1)
+    offs = np.zeros((6, 4, 3), dtype=np.int64)
+    for p, perm in enumerate(_PERMS):
+        e0 = np.eye(3, dtype=np.int64)[perm[0]]
+        e1 = np.eye(3, dtype=np.int64)[perm[1]]
+        offs[p, 1] = e0
+        offs[p, 2] = e0 + e1
+        offs[p, 3] = (1, 1, 1)
+    vint = (base[:, None, None, :] + offs[None]).reshape(-1, 4, 3)
+    vi, vj, vk = vint[..., 0], vint[..., 1], vint[..., 2]
+    metal = np.repeat(base[:, 2] < 0, 6)       # substrate cubes
+    if tip_R > 0.0:
+        cx, cy = 0.5 * nx * h, 0.5 * ny * h
+        inside = _inside_tip(vi * h, vj * h, vk * h, cx, cy, tip_R, tip_H)
+        metal = metal | inside.any(axis=1)
+    vint = vint[metal]
+    nk = nz + depth + 1
+    gid = (vint[..., 0] * (ny + 1) + vint[..., 1]) * nk + (vint[..., 2] + depth)
+    n_all = (nx + 1) * (ny + 1) * nk
+    used = np.zeros(n_all, dtype=bool)
+    used[gid.reshape(-1)] = True
+    newid = np.full(n_all, -1, dtype=np.int64)
+    newid[used] = np.arange(int(used.sum()))
+    tet = newid[gid].astype(np.int32)
+    old = np.nonzero(used)[0]
+    k = old % nk - depth
+    j = (old // nk) % (ny + 1)
+    i = old // (nk * (ny + 1))
+    xyz = np.stack([i * h, j * h, k * h], axis=1).astype(np.float64)
+    # boundary faces: sorted node triples met once
+    tri = np.concatenate([tet[:, [1, 2, 3]], tet[:, [0, 2, 3]],
+                          tet[:, [0, 1, 3]], tet[:, [0, 1, 2]]])
+    owner = np.tile(np.arange(tet.shape[0], dtype=np.int32), 4)
+    key = np.sort(tri, axis=1)
+    _, first, cnt = np.unique(key, axis=0, return_index=True,
+                              return_counts=True)
+    once = first[cnt == 1]
+    once.sort()
+    f = tri[once]
+    fi, fj, fk = (np.stack([i, j, k], 1)[f][..., a] for a in range(3))
+    on_plane = ((fk == -depth).all(1) | (fi == 0).all(1) | (fi == nx).all(1)
+                | (fj == 0).all(1) | (fj == ny).all(1))
+    keep = ~on_plane
+    dirichlet = (k == -depth).astype(np.uint8)
+    return MetalMesh(xyz=np.ascontiguousarray(xyz),
+                     tet=np.ascontiguousarray(tet),
+                     faces=np.ascontiguousarray(f[keep].astype(np.int32)),
+                     face_tet=np.ascontiguousarray(owner[once][keep]),
+                     dirichlet=np.ascontiguousarray(dirichlet),
+                     z_bottom=float(-depth * h))
+
+
 # --------------------------------------------------------------------------
 # Run configurations.  The five workloads: a tiny tip, a production-shaped
 # tip (about 3.1M tetrahedra), its mixed-precision form, a batch of 32 uneven
