@@ -302,6 +302,10 @@ def run_gpu(args):
     if args.charge_calls > 0:
         torch.cuda.empty_cache()
         charge = run_charge_leg(tip, args)
+    metal = None
+    if args.metal_calls > 0:
+        torch.cuda.empty_cache()
+        metal = run_metal_leg(args)
     adjoint = None
     if not args.no_adjoint:
         torch.cuda.empty_cache()
@@ -331,6 +335,7 @@ def run_gpu(args):
         batch=batch,
         collisions=collisions,
         surface_charge=charge,
+        metal=metal,
         stress=stress,
         roofline=dict(kernel=dom, bound="hbm", achieved=round(achieved, 1),
                       peak=HBM_PEAK_GBS, unit="GB/s",
@@ -417,6 +422,50 @@ def run_charge_leg(tip, args):
                total_charge_e=round(float(Q.sum().item()), 6),
                conservation=float(q.sum().item() / Q.sum().item()))
     del gmc, gs
+    return out
+
+
+def run_metal_leg(args):
+    """Metal-side solves (Sec. II D) on the metal under the production tip:
+    the continuity solve with Joule heating from a synthetic apex-centred
+    emission current, then implicit-Euler heat steps with those sources.
+    Times per call are host wall times (each call waits for its solve)."""
+    import torch
+
+    from paper_1906_08125_amd import pic, workloads as W
+
+    t0 = time.time()
+    m = W.metal_production()
+    gm = pic.Metal(m)
+    torch.cuda.synchronize()
+    setup = time.time() - t0
+    flux, PN = (torch.from_numpy(a).cuda() for a in W.metal_sources(m))
+    sigma = torch.ones(m.n_tets, dtype=torch.float64, device="cuda")
+    gm.continuity_solve(sigma, flux, tol=1e-12)          # code-object load
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.metal_calls):
+        phi, pj, st = gm.continuity_solve(sigma, flux, tol=1e-12)
+    torch.cuda.synchronize()
+    cont_s = (time.perf_counter() - t1) / args.metal_calls
+    T = torch.full((m.n_nodes,), 300.0, dtype=torch.float64, device="cuda")
+    t2 = time.perf_counter()
+    iters = []
+    for _ in range(args.metal_calls):
+        sh = gm.heat_step(T, sigma, pj, PN, Cv=3.45e-3, L=2.0e-8, dt=40.0,
+                          theta=1.0, T_amb=300.0, tol=1e-12)
+        iters.append(sh["iters"])
+    torch.cuda.synchronize()
+    heat_s = (time.perf_counter() - t2) / args.metal_calls
+    out = dict(nodes=m.n_nodes, tets=m.n_tets, interface_faces=m.n_faces,
+               setup_s=round(setup, 2),
+               continuity_ms=round(1e3 * cont_s, 3),
+               continuity_iters=int(st["iters"]),
+               heat_step_ms=round(1e3 * heat_s, 3),
+               heat_iters=iters,
+               us_per_cg_iter=round(1e6 * cont_s / max(st["iters"], 1), 2),
+               T_max=round(float(T.max().item()), 4))
+    log(f"metal leg {out}")
     return out
 
 
@@ -598,16 +647,36 @@ def cpu_baseline(cfg, tip, n_particles, n_steps):
     t2 = time.perf_counter()
     omc.surface_charge(sc.E, atoms)
     charge_s = time.perf_counter() - t2
+    # and its metal-side solves on a bounded sample: the same tip's metal
+    # with a 2 nm substrate (the production metal has a 10 nm one)
+    from oracle import metal as OM
+    mm = W.kuhn_metal_mesh(tip.nx, tip.ny, tip.nz, tip.h, tip.tip_R,
+                           tip.tip_H, 4)
+    flux, PN = W.metal_sources(mm)
+    sig = np.ones(mm.n_tets)
+    t3 = time.perf_counter()
+    mphi = OM.continuity_solve(mm, sig, flux)
+    cont_s = time.perf_counter() - t3
+    t4 = time.perf_counter()
+    OM.heat_step(mm, np.full(mm.n_nodes, 300.0), sig, OM.joule(mm, sig, mphi),
+                 PN, 3.45e-3, 2.0e-8, 40.0, 1.0, 300.0)
+    heat_s = time.perf_counter() - t4
     return dict(value=round(n_steps / dt, 5), unit="steps/s", cores=1,
                 kind="oracle",
                 sample=(f"{n_steps} steps of the FP64 oracle (single thread) on "
                         f"the same 3.1M-tet mesh with {n0} seeded synthetic "
                         "superparticles in the gap above the apex; then one "
                         "collision pass over them and one surface charge of "
-                        f"the {omc.n_emit} metal faces to {len(atoms)} atoms"),
+                        f"the {omc.n_emit} metal faces to {len(atoms)} atoms; "
+                        "one continuity solve and one heat step (sparse LU, "
+                        f"scipy) on the tip's metal with a 2 nm substrate "
+                        f"({mm.n_nodes} nodes)"),
                 pushes_per_s=round(n0 * n_steps / dt, 1),
                 collide_s_per_call=round(coll_s, 4),
-                surface_charge_s_per_call=round(charge_s, 4))
+                surface_charge_s_per_call=round(charge_s, 4),
+                metal_sample_nodes=mm.n_nodes,
+                continuity_s_per_solve=round(cont_s, 4),
+                heat_s_per_step=round(heat_s, 4))
 
 
 def main():
@@ -639,6 +708,9 @@ def main():
                     help="timed steps of the coupled variant (current scaled "
                          "so that space charge shows; 0: skip)")
     ap.add_argument("--stress-warmup", type=int, default=60)
+    ap.add_argument("--metal-calls", type=int, default=3,
+                    help="continuity solves and heat steps timed on the "
+                         "production tip's metal (0: skip)")
     ap.add_argument("--charge-calls", type=int, default=5,
                     help="timed surface-charge calls over every metal face "
                          "of the production tip (0: skip)")

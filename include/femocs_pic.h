@@ -2,8 +2,8 @@
  * femocs_pic.h -- C ABI of the MI355X (gfx950) electron particle-in-cell
  * library: the PIC cycle in the vacuum above a field-emitting tip, after
  * Veske et al., "Dynamic coupling between particle-in-cell and atomistic
- * simulations", Phys. Rev. E 101, 053307 (2020), Sec. II A-B and
- * Appendices B, E and F.
+ * simulations", Phys. Rev. E 101, 053307 (2020), Sec. II A-D and
+ * Appendices B-F.
  *
  * Conventions shared by every call
  * --------------------------------
@@ -391,6 +391,77 @@ typedef struct {
 PIC_API pic_status surface_charge(pic_mesh* mesh, const pic_fields* fields,
                                   const pic_charge_params* params,
                                   double* face_Q, double* atom_q, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Metal-side solves (Sec. II D; weak forms of App. C and App. D): the     */
+/* current continuity equation (Eq. cont with Eq. cont_bc), the Joule heat  */
+/* (Eq. joule) and one Theta-scheme step of the heat equation (Eq. heat,    */
+/* Eq. heat_bc, Eq. heat_theta2) on a separate P1 tetrahedral mesh of the   */
+/* metal.  Matrices are assembled on the device in CSR form from their      */
+/* element definitions and solved by Jacobi-preconditioned CG in FP64.      */
+/* ------------------------------------------------------------------------ */
+typedef struct pic_metal pic_metal;
+
+typedef struct {
+  int64_t n_nodes;
+  const double* xyz;          /* host [n_nodes][3]                               */
+  int64_t n_tets;
+  const int32_t* tets;        /* host [n_tets][4] node ids, any orientation       */
+  int64_t n_faces;
+  const int32_t* faces;       /* host [n_faces][3] metal-vacuum interface (Gamma3) */
+  const uint8_t* dirichlet;   /* host [n_nodes] 1 on Gamma5 (fixed Phi and T)     */
+} pic_metal_desc;
+
+typedef struct {
+  int64_t iters;              /* CG iterations                                  */
+  double relres;              /* ||r|| / ||b|| of the CG recursion at exit       */
+  int32_t converged;
+  int32_t pad;
+} pic_metal_stats;
+
+typedef struct {
+  double Cv;                  /* volumetric heat capacity (constant)             */
+  double L;                   /* Lorentz number of Eq. wied_franz                */
+  double dt;                  /* time step                                      */
+  double theta;               /* Theta in [0, 1]; 1 is the paper's implicit Euler */
+  double T_amb;               /* Dirichlet temperature on Gamma5                  */
+  double tol;                 /* CG stopping test ||r|| <= tol ||b||              */
+  int64_t max_iter;
+} pic_heat_params;
+
+/* Copies the mesh to the device, builds the CSR pattern and the node-to-
+ * element lists on the host (setup), and the shape-function gradients and
+ * volumes on the device.  Lateral boundary faces not listed in faces carry
+ * no flux (Gamma4).  PIC_E_ARG for empty or out-of-range input or an
+ * element of zero volume. */
+PIC_API pic_status metal_create(const pic_metal_desc* desc, void* stream,
+                                pic_metal** out);
+PIC_API pic_status metal_destroy(pic_metal* metal);
+
+/* Eq. cont_mat: K(sigma) Phi = f with K_ab = sum_t sigma_t int grad N_a .
+ * grad N_b, f_a = sum over interface faces of flux_f A_f / 3 (flux_f =
+ * J_e . n, n the outward normal of the metal), Phi = 0 on Gamma5.  sigma:
+ * device [n_tets]; flux: device [n_faces]; Phi: device [n_nodes], in the
+ * initial guess, out the solution; P_J (optional, device [n_tets]): Eq.
+ * joule, sigma_t |grad Phi|^2.  The call waits for the solve (the host
+ * reads the convergence state every few iterations).  PIC_E_NOCONV when
+ * max_iter is reached (Phi holds the last iterate). */
+PIC_API pic_status continuity_solve(pic_metal* metal, const double* sigma,
+                                    const double* flux, double tol,
+                                    int64_t max_iter, double* Phi, double* P_J,
+                                    pic_metal_stats* stats, void* stream);
+
+/* Eq. heat_theta2 with kappa_t = L sigma_t Tbar_t (Eq. wied_franz, Tbar_t
+ * the mean of the element's four nodal temperatures at the start of the
+ * step: the conductivity lagged as App. D states), C = int C_v N_a N_b
+ * (consistent), f = int N_a P_J + int_Gamma3 N_a P_N (sources held over the
+ * step), T = T_amb on Gamma5.  sigma, P_J: device [n_tets]; P_N: device
+ * [n_faces]; T: device [n_nodes], in T^n, out T^{n+1}.  Waits like
+ * continuity_solve. */
+PIC_API pic_status heat_step(pic_metal* metal, const pic_heat_params* params,
+                             const double* sigma, const double* P_J,
+                             const double* P_N, double* T,
+                             pic_metal_stats* stats, void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* Batched stepping (an addition: many independent instances of the cycle   */

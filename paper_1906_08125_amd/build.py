@@ -16,7 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfemocs_pic.so")
 SOURCES = ["mesh.hip", "solver.hip", "amg.hip", "particles.hip", "sort.hip",
-           "adjoint.hip", "collide.hip", "charge.hip", "api.hip"]
+           "adjoint.hip", "collide.hip", "charge.hip", "metal.hip",
+           "api.hip"]
 ARCH = os.environ.get("FEMOCS_PIC_ARCH", "gfx950")
 
 

@@ -10,6 +10,7 @@
 #include "collide.h"
 #include "charge.h"
 #include "mesh.h"
+#include "metal.h"
 #include "particles.h"
 #include "solver.h"
 #include "sort.h"
@@ -706,6 +707,48 @@ pic_status collide(pic_mesh* h, const pic_particles* P,
     return hip_fail(e, "collide");
   prof_end(h, s);
   return PIC_OK;
+}
+
+pic_status metal_create(const pic_metal_desc* desc, void* stream, pic_metal** out) {
+  if (!desc || !out) return fail(PIC_E_ARG, "metal_create: null argument");
+  *out = nullptr;
+  std::string err;
+  const pic_status rc = fp::metal_build(desc, (hipStream_t)stream, out, &err);
+  return rc == PIC_OK ? rc : fail(rc, err);
+}
+
+pic_status metal_destroy(pic_metal* metal) {
+  fp::metal_free(metal);
+  return PIC_OK;
+}
+
+pic_status continuity_solve(pic_metal* metal, const double* sigma, const double* flux,
+                            double tol, int64_t max_iter, double* Phi, double* P_J,
+                            pic_metal_stats* stats, void* stream) {
+  if (!metal || !sigma || !Phi) return fail(PIC_E_ARG, "continuity_solve: null argument");
+  if (!flux && fp::metal_n_faces(metal) > 0)
+    return fail(PIC_E_ARG, "continuity_solve: null flux");
+  if (!finite_pos(tol) || max_iter < 0 || max_iter >= (1ll << 31))
+    return fail(PIC_E_ARG, "continuity_solve: tol must be > 0, max_iter in [0, 2^31)");
+  std::string err;
+  const pic_status rc = fp::metal_continuity(metal, sigma, flux, tol, max_iter, Phi, P_J,
+                                             stats, (hipStream_t)stream, &err);
+  return rc == PIC_OK ? rc : fail(rc, err);
+}
+
+pic_status heat_step(pic_metal* metal, const pic_heat_params* p, const double* sigma,
+                     const double* P_J, const double* P_N, double* T,
+                     pic_metal_stats* stats, void* stream) {
+  if (!metal || !p || !sigma || !T) return fail(PIC_E_ARG, "heat_step: null argument");
+  if (!P_N && fp::metal_n_faces(metal) > 0) return fail(PIC_E_ARG, "heat_step: null P_N");
+  if (!finite_pos(p->Cv) || !(std::isfinite(p->L) && p->L >= 0.0) || !finite_pos(p->dt) ||
+      !(p->theta >= 0.0 && p->theta <= 1.0) || !std::isfinite(p->T_amb) ||
+      !finite_pos(p->tol) || p->max_iter < 0 || p->max_iter >= (1ll << 31))
+    return fail(PIC_E_ARG, "heat_step: invalid parameters");
+  std::string err;
+  const pic_status rc = fp::metal_heat(metal, p, sigma, P_J, P_N, T, stats,
+                                       (hipStream_t)stream, &err);
+  return rc == PIC_OK ? rc : fail(rc, err);
 }
 
 pic_status surface_charge(pic_mesh* h, const pic_fields* F,

@@ -1,0 +1,671 @@
+// Metal-side solves (Sec. II D, weak forms of App. C and App. D): P1
+// assembly of the continuity and heat systems in CSR form on the device,
+// Joule heating, and a Jacobi-preconditioned CG in FP64.
+//
+// The metal mesh is small next to the vacuum mesh and its systems change
+// every call (sigma, kappa(T), dt), so the design favours a deterministic
+// one-pass assembly over reuse: one thread per matrix row walks the
+// elements incident to its node (ascending element id) and accumulates the
+// row in place, the right-hand side included, so no atomics and no
+// run-to-run rounding differences.  Every reduction of the CG is two-level
+// (workgroup tree, then every workgroup sums the partials in the same fixed
+// order), so every workgroup sees the same scalars.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "metal.h"
+
+namespace fp {
+namespace {
+
+constexpr int kMB = 256;       // threads per workgroup
+constexpr int kMaxG = 1024;    // workgroups of the CG kernels
+constexpr int kChunk = 24;     // CG iterations between host checks
+
+struct MetalCtrl {
+  double rz[2];      // z.r of the current and next iteration
+  double bb;         // ||b||^2 over the free rows
+  double rr;         // ||r||^2 at the last check
+  int64_t iters;
+  int32_t done;
+  int32_t pad;
+};
+
+// Element record: shape-function gradients g_a (a = 0..3) and the volume.
+struct alignas(128) MetalTet {
+  double g[12];
+  double vol;
+  double pad[3];
+};
+
+__device__ double block_sum(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < kMB / 64; ++k) s += sh[k];
+  return s;   // valid in thread 0
+}
+
+// Sum of the partials part[0 .. G) (stride `stride`), the same in every
+// workgroup: fixed per-thread order, then the fixed tree.
+__device__ double sum_partials(const double* part, int G, int stride,
+                               double* sh, double* bc) {
+  double v = 0.0;
+  for (int k = threadIdx.x; k < G; k += kMB) v += part[(size_t)k * stride];
+  const double s = block_sum(v, sh);
+  if (threadIdx.x == 0) *bc = s;
+  __syncthreads();
+  const double r = *bc;
+  __syncthreads();
+  return r;
+}
+
+__global__ void k_geom(const double* __restrict__ xyz,
+                       const int32_t* __restrict__ tet, int64_t nt,
+                       MetalTet* __restrict__ out, int32_t* __restrict__ bad) {
+  const int64_t t = (int64_t)blockIdx.x * kMB + threadIdx.x;
+  if (t >= nt) return;
+  double p[4][3];
+  for (int a = 0; a < 4; ++a)
+    for (int c = 0; c < 3; ++c) p[a][c] = xyz[3 * (int64_t)tet[4 * t + a] + c];
+  double e[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int c = 0; c < 3; ++c) e[a][c] = p[a + 1][c] - p[0][c];
+  // rows of the inverse of the edge matrix: g_a = (e_b x e_c) / det
+  auto cross = [](const double* u, const double* v, double* w) {
+    w[0] = u[1] * v[2] - u[2] * v[1];
+    w[1] = u[2] * v[0] - u[0] * v[2];
+    w[2] = u[0] * v[1] - u[1] * v[0];
+  };
+  double c1[3], c2[3], c3[3];
+  cross(e[1], e[2], c1);
+  cross(e[2], e[0], c2);
+  cross(e[0], e[1], c3);
+  const double det = e[0][0] * c1[0] + e[0][1] * c1[1] + e[0][2] * c1[2];
+  MetalTet r;
+  if (!(det != 0.0) || !std::isfinite(det)) {
+    atomicAdd(bad, 1);
+    for (int k = 0; k < 12; ++k) r.g[k] = 0.0;
+    r.vol = 0.0;
+  } else {
+    for (int c = 0; c < 3; ++c) {
+      r.g[3 + c] = c1[c] / det;
+      r.g[6 + c] = c2[c] / det;
+      r.g[9 + c] = c3[c] / det;
+      r.g[c] = -(r.g[3 + c] + r.g[6 + c] + r.g[9 + c]);
+    }
+    r.vol = fabs(det) / 6.0;
+  }
+  r.pad[0] = r.pad[1] = r.pad[2] = 0.0;
+  out[t] = r;
+}
+
+struct AsmArgs {
+  int64_t n;
+  const int32_t* row_ptr;
+  const int32_t* inc_ptr;
+  const int32_t* inc_tet;
+  const int8_t* inc_loc;
+  const int32_t* inc_pos;   // [4] CSR positions per incidence
+  const int32_t* fin_ptr;
+  const int32_t* fin_face;
+  const int32_t* tet;
+  const int32_t* face;
+  const double* xyz;
+  const MetalTet* geo;
+  const uint8_t* dir;
+  const double* sigma;
+  const double* flux;       // face flux (J_n or P_N)
+  const double* PJ;         // volume source or null
+  const double* T;          // heat: T^n; continuity: null
+  double L, Cv, dt, theta;
+  double* A;
+  double* b;
+  double* dinv;
+};
+
+__device__ double face_area(const double* xyz, const int32_t* f) {
+  double p[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int c = 0; c < 3; ++c) p[a][c] = xyz[3 * (int64_t)f[a] + c];
+  const double u0 = p[1][0] - p[0][0], u1 = p[1][1] - p[0][1], u2 = p[1][2] - p[0][2];
+  const double v0 = p[2][0] - p[0][0], v1 = p[2][1] - p[0][1], v2 = p[2][2] - p[0][2];
+  const double w0 = u1 * v2 - u2 * v1, w1 = u2 * v0 - u0 * v2, w2 = u0 * v1 - u1 * v0;
+  return 0.5 * sqrt(w0 * w0 + w1 * w1 + w2 * w2);
+}
+
+// One row per thread: the matrix row (continuity: K(sigma); heat:
+// C/dt + theta K(kappa)) and the right-hand side (face and volume loads,
+// and for the heat step (C/dt - (1 - theta) K) T^n).
+__global__ void k_assemble(AsmArgs a, double dir_value) {
+  const int64_t i = (int64_t)blockIdx.x * kMB + threadIdx.x;
+  if (i >= a.n) return;
+  const int32_t r0 = a.row_ptr[i], r1 = a.row_ptr[i + 1];
+  for (int32_t k = r0; k < r1; ++k) a.A[k] = 0.0;
+  const bool heat = a.T != nullptr;
+  double b = 0.0;
+  for (int32_t q = a.inc_ptr[i]; q < a.inc_ptr[i + 1]; ++q) {
+    const int32_t t = a.inc_tet[q];
+    const int loc = a.inc_loc[q];
+    const MetalTet& G = a.geo[t];
+    const double* gl = &G.g[3 * loc];
+    double kw;
+    int32_t nd[4];
+    for (int c = 0; c < 4; ++c) nd[c] = a.tet[4 * (int64_t)t + c];
+    if (heat) {
+      const double Tbar = (a.T[nd[0]] + a.T[nd[1]] + a.T[nd[2]] + a.T[nd[3]]) / 4.0;
+      kw = a.L * a.sigma[t] * Tbar * G.vol;
+      if (a.PJ) b += a.PJ[t] * G.vol / 4.0;
+    } else {
+      kw = a.sigma[t] * G.vol;
+    }
+    const double mw = heat ? a.Cv * G.vol / 20.0 / a.dt : 0.0;
+    for (int c = 0; c < 4; ++c) {
+      const double* gc = &G.g[3 * c];
+      const double kab = kw * (gl[0] * gc[0] + gl[1] * gc[1] + gl[2] * gc[2]);
+      const double mab = c == loc ? 2.0 * mw : mw;
+      const int32_t pos = a.inc_pos[4 * (int64_t)q + c];
+      if (heat) {
+        a.A[pos] += mab + a.theta * kab;
+        b += (mab - (1.0 - a.theta) * kab) * a.T[nd[c]];
+      } else {
+        a.A[pos] += kab;
+      }
+    }
+  }
+  for (int32_t q = a.fin_ptr[i]; q < a.fin_ptr[i + 1]; ++q) {
+    const int32_t f = a.fin_face[q];
+    b += a.flux[f] * face_area(a.xyz, &a.face[3 * (int64_t)f]) / 3.0;
+  }
+  a.b[i] = a.dir[i] ? dir_value : b;
+}
+
+// Second pass over the rows: Dirichlet rows become identity rows, the
+// Dirichlet columns of free rows move to the right-hand side, and the
+// inverse diagonal of the Jacobi preconditioner.
+__global__ void k_eliminate(int64_t n, const int32_t* __restrict__ row_ptr,
+                            const int32_t* __restrict__ col,
+                            const uint8_t* __restrict__ dir, double dir_value,
+                            double* __restrict__ A, double* __restrict__ b,
+                            double* __restrict__ dinv) {
+  const int64_t i = (int64_t)blockIdx.x * kMB + threadIdx.x;
+  if (i >= n) return;
+  const int32_t r0 = row_ptr[i], r1 = row_ptr[i + 1];
+  if (dir[i]) {
+    for (int32_t k = r0; k < r1; ++k) A[k] = col[k] == i ? 1.0 : 0.0;
+    dinv[i] = 1.0;
+    return;
+  }
+  double bi = b[i], d = 0.0;
+  for (int32_t k = r0; k < r1; ++k) {
+    const int32_t j = col[k];
+    if (dir[j]) {
+      bi -= A[k] * dir_value;
+      A[k] = 0.0;
+    } else if (j == i) {
+      d = A[k];
+    }
+  }
+  b[i] = bi;
+  dinv[i] = 1.0 / d;
+}
+
+struct CgArgsM {
+  int64_t n;
+  const int32_t* row_ptr;
+  const int32_t* col;
+  const double* A;
+  const double* b;
+  const double* dinv;
+  const uint8_t* dir;
+  double dir_value;
+  double tol2;
+  double *x, *r, *z, *p, *q;
+  double* part;      // [3][kMaxG]
+  MetalCtrl* ctrl;
+  int G;
+};
+
+__device__ double row_dot(const CgArgsM& a, int64_t i, const double* v) {
+  double s = 0.0;
+  for (int32_t k = a.row_ptr[i]; k < a.row_ptr[i + 1]; ++k) s += a.A[k] * v[a.col[k]];
+  return s;
+}
+
+__global__ void k_cg_dir(CgArgsM a) {
+  for (int64_t i = (int64_t)blockIdx.x * kMB + threadIdx.x; i < a.n;
+       i += (int64_t)a.G * kMB)
+    if (a.dir[i]) a.x[i] = a.dir_value;
+}
+
+// r = b - A x, z = D^-1 r; partials of r.z, r.r and b.b over free rows
+__global__ void k_cg_init(CgArgsM a) {
+  __shared__ double sh[kMB / 64];
+  double rz = 0.0, rr = 0.0, bb = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kMB + threadIdx.x; i < a.n;
+       i += (int64_t)a.G * kMB) {
+    double ri = 0.0, bi = 0.0;
+    if (!a.dir[i]) {
+      bi = a.b[i];
+      ri = bi - row_dot(a, i, a.x);
+    }
+    const double zi = ri * a.dinv[i];
+    a.r[i] = ri;
+    a.z[i] = zi;
+    rz += ri * zi;
+    rr += ri * ri;
+    bb += bi * bi;
+  }
+  const double s0 = block_sum(rz, sh);
+  const double s1 = block_sum(rr, sh);
+  const double s2 = block_sum(bb, sh);
+  if (threadIdx.x == 0) {
+    a.part[blockIdx.x] = s0;
+    a.part[kMaxG + blockIdx.x] = s1;
+    a.part[2 * kMaxG + blockIdx.x] = s2;
+  }
+}
+
+// p = z; the control word; a zero right-hand side has the zero solution
+__global__ void k_cg_start(CgArgsM a) {
+  __shared__ double sh[kMB / 64];
+  __shared__ double bc;
+  const double rz = sum_partials(a.part, a.G, 1, sh, &bc);
+  const double rr = sum_partials(a.part + kMaxG, a.G, 1, sh, &bc);
+  const double bb = sum_partials(a.part + 2 * kMaxG, a.G, 1, sh, &bc);
+  for (int64_t i = (int64_t)blockIdx.x * kMB + threadIdx.x; i < a.n;
+       i += (int64_t)a.G * kMB) {
+    if (bb == 0.0 && !a.dir[i]) a.x[i] = 0.0;
+    a.p[i] = a.z[i];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.ctrl->rz[0] = rz;
+    a.ctrl->rz[1] = 0.0;
+    a.ctrl->bb = bb;
+    a.ctrl->rr = bb == 0.0 ? 0.0 : rr;
+    a.ctrl->iters = 0;
+    a.ctrl->done = (bb == 0.0 || rr <= a.tol2 * bb) ? 1 : 0;
+  }
+}
+
+// q = A p; partial p.q
+// The control word's done flag as one value for the whole workgroup (block
+// 0 of k_cg_direction may set it while other workgroups start).
+__device__ bool block_done(const MetalCtrl* c) {
+  __shared__ int d;
+  if (threadIdx.x == 0) d = __atomic_load_n(&c->done, __ATOMIC_RELAXED);
+  __syncthreads();
+  const bool r = d != 0;
+  __syncthreads();
+  return r;
+}
+
+__global__ void k_cg_spmv(CgArgsM a) {
+  if (block_done(a.ctrl)) return;
+  __shared__ double sh[kMB / 64];
+  double pq = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kMB + threadIdx.x; i < a.n;
+       i += (int64_t)a.G * kMB) {
+    const double qi = row_dot(a, i, a.p);
+    a.q[i] = qi;
+    pq += a.p[i] * qi;
+  }
+  const double s = block_sum(pq, sh);
+  if (threadIdx.x == 0) a.part[blockIdx.x] = s;
+}
+
+// x += alpha p, r -= alpha q, z = D^-1 r; partials of r.z and r.r
+__global__ void k_cg_update(CgArgsM a, int it) {
+  if (block_done(a.ctrl)) return;
+  __shared__ double sh[kMB / 64];
+  __shared__ double bc;
+  const double pq = sum_partials(a.part, a.G, 1, sh, &bc);
+  const double alpha = a.ctrl->rz[it & 1] / pq;
+  double rz = 0.0, rr = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kMB + threadIdx.x; i < a.n;
+       i += (int64_t)a.G * kMB) {
+    a.x[i] += alpha * a.p[i];
+    const double ri = a.r[i] - alpha * a.q[i];
+    const double zi = ri * a.dinv[i];
+    a.r[i] = ri;
+    a.z[i] = zi;
+    rz += ri * zi;
+    rr += ri * ri;
+  }
+  const double s0 = block_sum(rz, sh);
+  const double s1 = block_sum(rr, sh);
+  if (threadIdx.x == 0) {
+    a.part[kMaxG + blockIdx.x] = s0;
+    a.part[2 * kMaxG + blockIdx.x] = s1;
+  }
+}
+
+// p = z + beta p; block 0 advances the control word
+__global__ void k_cg_direction(CgArgsM a, int it) {
+  if (block_done(a.ctrl)) return;
+  __shared__ double sh[kMB / 64];
+  __shared__ double bc;
+  const double rz = sum_partials(a.part + kMaxG, a.G, 1, sh, &bc);
+  const double rr = sum_partials(a.part + 2 * kMaxG, a.G, 1, sh, &bc);
+  const double beta = rz / a.ctrl->rz[it & 1];
+  const bool conv = rr <= a.tol2 * a.ctrl->bb;
+  if (!conv)
+    for (int64_t i = (int64_t)blockIdx.x * kMB + threadIdx.x; i < a.n;
+         i += (int64_t)a.G * kMB)
+      a.p[i] = a.z[i] + beta * a.p[i];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.ctrl->rz[(it + 1) & 1] = rz;
+    a.ctrl->rr = rr;
+    a.ctrl->iters = it + 1;
+    if (conv) a.ctrl->done = 1;
+  }
+}
+
+__global__ void k_joule(int64_t nt, const int32_t* __restrict__ tet,
+                        const MetalTet* __restrict__ geo,
+                        const double* __restrict__ sigma,
+                        const double* __restrict__ phi, double* __restrict__ pj) {
+  const int64_t t = (int64_t)blockIdx.x * kMB + threadIdx.x;
+  if (t >= nt) return;
+  const MetalTet& G = geo[t];
+  double g[3] = {0.0, 0.0, 0.0};
+  for (int a = 0; a < 4; ++a) {
+    const double v = phi[tet[4 * t + a]];
+    for (int c = 0; c < 3; ++c) g[c] += v * G.g[3 * a + c];
+  }
+  pj[t] = sigma[t] * (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+}
+
+unsigned blocks_for(int64_t n) { return (unsigned)((n + kMB - 1) / kMB); }
+
+}  // namespace
+
+struct MetalImpl {
+  int64_t n = 0, nt = 0, nf = 0, nnz = 0, ninc = 0, nfin = 0;
+  double *xyz = nullptr, *A = nullptr, *b = nullptr, *dinv = nullptr;
+  double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *part = nullptr;
+  int32_t *tet = nullptr, *face = nullptr, *row_ptr = nullptr, *col = nullptr;
+  int32_t *inc_ptr = nullptr, *inc_tet = nullptr, *inc_pos = nullptr;
+  int32_t *fin_ptr = nullptr, *fin_face = nullptr;
+  int8_t* inc_loc = nullptr;
+  uint8_t* dir = nullptr;
+  MetalTet* geo = nullptr;
+  MetalCtrl* ctrl = nullptr;
+  MetalCtrl* hctrl = nullptr;   // pinned host mirror
+  int G = 1;
+};
+
+}  // namespace fp
+
+struct pic_metal {
+  fp::MetalImpl m;
+  std::vector<void*> allocs;
+  int device = 0;
+};
+
+namespace fp {
+
+namespace {
+template <typename T>
+hipError_t dalloc(pic_metal* h, T** p, size_t n) {
+  hipError_t e = hipMalloc((void**)p, std::max<size_t>(n, 1) * sizeof(T));
+  if (e == hipSuccess) h->allocs.push_back((void*)*p);
+  return e;
+}
+
+}  // namespace
+
+pic_status metal_build(const pic_metal_desc* d, hipStream_t s, pic_metal** out,
+                       std::string* err) {
+  const int64_t n = d->n_nodes, nt = d->n_tets, nf = d->n_faces;
+  if (n < 4 || nt < 1 || nf < 0 || !d->xyz || !d->tets || !d->dirichlet ||
+      (nf > 0 && !d->faces)) {
+    *err = "metal_create: empty mesh or null array";
+    return PIC_E_ARG;
+  }
+  if (n >= (1LL << 31) || nt >= (1LL << 31) / 4 || nf >= (1LL << 31) / 3) {
+    *err = "metal_create: mesh too large";
+    return PIC_E_ARG;
+  }
+  for (int64_t k = 0; k < 4 * nt; ++k)
+    if (d->tets[k] < 0 || d->tets[k] >= n) {
+      *err = "metal_create: element node out of range";
+      return PIC_E_ARG;
+    }
+  for (int64_t k = 0; k < 3 * nf; ++k)
+    if (d->faces[k] < 0 || d->faces[k] >= n) {
+      *err = "metal_create: face node out of range";
+      return PIC_E_ARG;
+    }
+  for (int64_t k = 0; k < 3 * n; ++k)
+    if (!std::isfinite(d->xyz[k])) {
+      *err = "metal_create: non-finite coordinate";
+      return PIC_E_ARG;
+    }
+  // node -> element incidences (ascending element id)
+  std::vector<int32_t> inc_ptr(n + 1, 0), inc_tet(4 * nt);
+  std::vector<int8_t> inc_loc(4 * nt);
+  for (int64_t k = 0; k < 4 * nt; ++k) ++inc_ptr[d->tets[k] + 1];
+  for (int64_t i = 0; i < n; ++i) inc_ptr[i + 1] += inc_ptr[i];
+  {
+    std::vector<int32_t> fill(inc_ptr.begin(), inc_ptr.end() - 1);
+    for (int64_t t = 0; t < nt; ++t)
+      for (int a = 0; a < 4; ++a) {
+        const int32_t v = d->tets[4 * t + a];
+        inc_tet[fill[v]] = (int32_t)t;
+        inc_loc[fill[v]++] = (int8_t)a;
+      }
+  }
+  // CSR pattern: the nodes of the incident elements, sorted
+  std::vector<int32_t> row_ptr(n + 1, 0), col;
+  col.reserve(16 * n);
+  std::vector<int32_t> nb;
+  for (int64_t i = 0; i < n; ++i) {
+    nb.clear();
+    for (int32_t q = inc_ptr[i]; q < inc_ptr[i + 1]; ++q)
+      for (int a = 0; a < 4; ++a) nb.push_back(d->tets[4 * (int64_t)inc_tet[q] + a]);
+    if (nb.empty()) nb.push_back((int32_t)i);
+    std::sort(nb.begin(), nb.end());
+    nb.erase(std::unique(nb.begin(), nb.end()), nb.end());
+    col.insert(col.end(), nb.begin(), nb.end());
+    if (col.size() >= (size_t)1 << 31) {
+      *err = "metal_create: too many matrix entries";
+      return PIC_E_ARG;
+    }
+    row_ptr[i + 1] = (int32_t)col.size();
+  }
+  std::vector<int32_t> inc_pos(16 * (size_t)nt);
+  for (int64_t i = 0; i < n; ++i)
+    for (int32_t q = inc_ptr[i]; q < inc_ptr[i + 1]; ++q)
+      for (int a = 0; a < 4; ++a) {
+        const int32_t v = d->tets[4 * (int64_t)inc_tet[q] + a];
+        const int32_t* lo = col.data() + row_ptr[i];
+        const int32_t* hi = col.data() + row_ptr[i + 1];
+        inc_pos[4 * (size_t)q + a] = (int32_t)(std::lower_bound(lo, hi, v) - col.data());
+      }
+  // node -> interface faces
+  std::vector<int32_t> fin_ptr(n + 1, 0), fin_face(3 * nf);
+  for (int64_t k = 0; k < 3 * nf; ++k) ++fin_ptr[d->faces[k] + 1];
+  for (int64_t i = 0; i < n; ++i) fin_ptr[i + 1] += fin_ptr[i];
+  {
+    std::vector<int32_t> fill(fin_ptr.begin(), fin_ptr.end() - 1);
+    for (int64_t f = 0; f < nf; ++f)
+      for (int a = 0; a < 3; ++a) fin_face[fill[d->faces[3 * f + a]]++] = (int32_t)f;
+  }
+
+  pic_metal* h = new pic_metal();
+  (void)hipGetDevice(&h->device);
+  MetalImpl& M = h->m;
+  M.n = n; M.nt = nt; M.nf = nf; M.nnz = (int64_t)col.size(); M.ninc = 4 * nt;
+  M.nfin = 3 * nf;
+  hipError_t e = hipSuccess;
+  auto up = [&](auto** dst, const auto* src, size_t count) {
+    if (e != hipSuccess) return;
+    e = dalloc(h, dst, count);
+    if (e == hipSuccess && count)
+      e = hipMemcpyAsync(*dst, src, count * sizeof(**dst), hipMemcpyHostToDevice, s);
+  };
+  up(&M.xyz, d->xyz, 3 * n);
+  up(&M.tet, d->tets, 4 * nt);
+  up(&M.face, d->faces, 3 * nf);
+  up(&M.dir, d->dirichlet, n);
+  up(&M.row_ptr, row_ptr.data(), n + 1);
+  up(&M.col, col.data(), col.size());
+  up(&M.inc_ptr, inc_ptr.data(), n + 1);
+  up(&M.inc_tet, inc_tet.data(), inc_tet.size());
+  up(&M.inc_loc, inc_loc.data(), inc_loc.size());
+  up(&M.inc_pos, inc_pos.data(), inc_pos.size());
+  up(&M.fin_ptr, fin_ptr.data(), n + 1);
+  up(&M.fin_face, fin_face.data(), fin_face.size());
+  if (e == hipSuccess) e = dalloc(h, &M.geo, nt);
+  if (e == hipSuccess) e = dalloc(h, &M.A, col.size());
+  for (double** v : {&M.b, &M.dinv, &M.r, &M.z, &M.p, &M.q})
+    if (e == hipSuccess) e = dalloc(h, v, n);
+  if (e == hipSuccess) e = dalloc(h, &M.part, 3 * kMaxG);
+  if (e == hipSuccess) e = dalloc(h, &M.ctrl, 1);
+  int32_t* bad = nullptr;
+  if (e == hipSuccess) e = dalloc(h, &bad, 1);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&M.hctrl, sizeof(MetalCtrl), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipMemsetAsync(bad, 0, sizeof(int32_t), s);
+  if (e == hipSuccess)
+    hipLaunchKernelGGL(k_geom, dim3(blocks_for(nt)), dim3(kMB), 0, s, M.xyz, M.tet,
+                       nt, M.geo, bad);
+  if (e == hipSuccess) e = hipGetLastError();
+  int32_t nbad = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&nbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  M.G = (int)std::min<int64_t>(kMaxG, std::max<int64_t>(1, (n + kMB - 1) / kMB));
+  if (e != hipSuccess) {
+    *err = std::string("metal_create: ") + hipGetErrorString(e);
+    metal_free(h);
+    return PIC_E_DEVICE;
+  }
+  if (nbad) {
+    *err = "metal_create: element of zero volume";
+    metal_free(h);
+    return PIC_E_ARG;
+  }
+  *out = h;
+  return PIC_OK;
+}
+
+int64_t metal_n_faces(const pic_metal* h) { return h->m.nf; }
+
+void metal_free(pic_metal* h) {
+  if (!h) return;
+  for (void* p : h->allocs) (void)hipFree(p);
+  if (h->m.hctrl) (void)hipHostFree(h->m.hctrl);
+  delete h;
+}
+
+namespace {
+
+pic_status run_cg(pic_metal* h, double* x, double dir_value, double tol,
+                  int64_t max_iter, pic_metal_stats* st, hipStream_t s,
+                  std::string* err, const char* who) {
+  MetalImpl& M = h->m;
+  CgArgsM a{};
+  a.n = M.n; a.row_ptr = M.row_ptr; a.col = M.col; a.A = M.A; a.b = M.b;
+  a.dinv = M.dinv; a.dir = M.dir; a.dir_value = dir_value; a.tol2 = tol * tol;
+  a.x = x; a.r = M.r; a.z = M.z; a.p = M.p; a.q = M.q; a.part = M.part;
+  a.ctrl = M.ctrl; a.G = M.G;
+  const dim3 g(M.G), b(kMB);
+  hipLaunchKernelGGL(k_cg_dir, g, b, 0, s, a);
+  hipLaunchKernelGGL(k_cg_init, g, b, 0, s, a);
+  hipLaunchKernelGGL(k_cg_start, g, b, 0, s, a);
+  hipError_t e = hipGetLastError();
+  int64_t it = 0;
+  bool done = false;
+  while (e == hipSuccess) {
+    e = hipMemcpyAsync(M.hctrl, M.ctrl, sizeof(MetalCtrl), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) break;
+    done = M.hctrl->done != 0;
+    if (done || it >= max_iter) break;
+    const int64_t n = std::min<int64_t>(kChunk, max_iter - it);
+    for (int64_t k = 0; k < n && e == hipSuccess; ++k, ++it) {
+      hipLaunchKernelGGL(k_cg_spmv, g, b, 0, s, a);
+      hipLaunchKernelGGL(k_cg_update, g, b, 0, s, a, (int)it);
+      hipLaunchKernelGGL(k_cg_direction, g, b, 0, s, a, (int)it);
+      e = hipGetLastError();
+    }
+  }
+  if (e != hipSuccess) {
+    *err = std::string(who) + ": " + hipGetErrorString(e);
+    return PIC_E_DEVICE;
+  }
+  const MetalCtrl c = *M.hctrl;
+  if (st) {
+    st->iters = c.iters;
+    st->relres = c.bb > 0.0 ? std::sqrt(c.rr / c.bb) : 0.0;
+    st->converged = done ? 1 : 0;
+    st->pad = 0;
+  }
+  if (!done) {
+    *err = std::string(who) + ": no convergence within max_iter";
+    return PIC_E_NOCONV;
+  }
+  return PIC_OK;
+}
+
+AsmArgs asm_args(const MetalImpl& M) {
+  AsmArgs a{};
+  a.n = M.n; a.row_ptr = M.row_ptr; a.inc_ptr = M.inc_ptr; a.inc_tet = M.inc_tet;
+  a.inc_loc = M.inc_loc; a.inc_pos = M.inc_pos; a.fin_ptr = M.fin_ptr;
+  a.fin_face = M.fin_face; a.tet = M.tet; a.face = M.face; a.xyz = M.xyz;
+  a.geo = M.geo; a.dir = M.dir; a.A = M.A; a.b = M.b; a.dinv = M.dinv;
+  return a;
+}
+
+}  // namespace
+
+pic_status metal_continuity(pic_metal* h, const double* sigma, const double* flux,
+                            double tol, int64_t max_iter, double* phi, double* pj,
+                            pic_metal_stats* st, hipStream_t s, std::string* err) {
+  MetalImpl& M = h->m;
+  AsmArgs a = asm_args(M);
+  a.sigma = sigma;
+  a.flux = flux;
+  const unsigned g = blocks_for(M.n);
+  hipLaunchKernelGGL(k_assemble, dim3(g), dim3(kMB), 0, s, a, 0.0);
+  hipLaunchKernelGGL(k_eliminate, dim3(g), dim3(kMB), 0, s, M.n, M.row_ptr, M.col,
+                     M.dir, 0.0, M.A, M.b, M.dinv);
+  pic_status rc = run_cg(h, phi, 0.0, tol, max_iter, st, s, err, "continuity_solve");
+  if (rc != PIC_OK && rc != PIC_E_NOCONV) return rc;
+  if (pj) {
+    hipLaunchKernelGGL(k_joule, dim3(blocks_for(M.nt)), dim3(kMB), 0, s, M.nt, M.tet,
+                       M.geo, sigma, phi, pj);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+      *err = std::string("continuity_solve: ") + hipGetErrorString(e);
+      return PIC_E_DEVICE;
+    }
+  }
+  return rc;
+}
+
+pic_status metal_heat(pic_metal* h, const pic_heat_params* p, const double* sigma,
+                      const double* pj, const double* pn, double* T,
+                      pic_metal_stats* st, hipStream_t s, std::string* err) {
+  MetalImpl& M = h->m;
+  AsmArgs a = asm_args(M);
+  a.sigma = sigma;
+  a.flux = pn;
+  a.PJ = pj;
+  a.T = T;
+  a.L = p->L; a.Cv = p->Cv; a.dt = p->dt; a.theta = p->theta;
+  const unsigned g = blocks_for(M.n);
+  hipLaunchKernelGGL(k_assemble, dim3(g), dim3(kMB), 0, s, a, p->T_amb);
+  hipLaunchKernelGGL(k_eliminate, dim3(g), dim3(kMB), 0, s, M.n, M.row_ptr, M.col,
+                     M.dir, p->T_amb, M.A, M.b, M.dinv);
+  return run_cg(h, T, p->T_amb, p->tol, p->max_iter, st, s, err, "heat_step");
+}
+
+}  // namespace fp

@@ -81,6 +81,24 @@ class ChargeParams(C.Structure):
                 ("precision", C.c_int32)]
 
 
+class MetalDesc(C.Structure):
+    _fields_ = [("n_nodes", C.c_int64), ("xyz", C.c_void_p),
+                ("n_tets", C.c_int64), ("tets", C.c_void_p),
+                ("n_faces", C.c_int64), ("faces", C.c_void_p),
+                ("dirichlet", C.c_void_p)]
+
+
+class MetalStats(C.Structure):
+    _fields_ = [("iters", C.c_int64), ("relres", C.c_double),
+                ("converged", C.c_int32), ("pad", C.c_int32)]
+
+
+class HeatParams(C.Structure):
+    _fields_ = [("Cv", C.c_double), ("L", C.c_double), ("dt", C.c_double),
+                ("theta", C.c_double), ("T_amb", C.c_double),
+                ("tol", C.c_double), ("max_iter", C.c_int64)]
+
+
 class CollideParams(C.Structure):
     _fields_ = [("dt_coll", C.c_double), ("w_sp", C.c_double),
                 ("seed", C.c_uint64), ("step", C.c_int64),
@@ -117,7 +135,8 @@ EXPORTS = ("mesh_create", "mesh_destroy", "mesh_query", "mesh_emit_faces",
            "locate", "deposit", "poisson_solve", "pic_step", "emission_rate",
            "adjoint_step", "pic_batch_create", "pic_batch_destroy",
            "pic_batch_step", "pic_profile", "pic_profile_read",
-           "pic_last_error", "collide", "surface_charge")
+           "pic_last_error", "collide", "surface_charge", "metal_create",
+           "metal_destroy", "continuity_solve", "heat_step")
 KERNEL_CLASSES = ("push", "emit", "inject", "fallback", "solve", "sort",
                   "clear", "adjoint", "collide")
 
@@ -162,6 +181,12 @@ def load_library(path: str = LIB_PATH):
     L.surface_charge.argtypes = [vp, C.POINTER(Fields), C.POINTER(ChargeParams),
                                  vp, vp, vp]
     L.pic_profile_read.argtypes = [vp, C.POINTER(KernelTimes)]
+    L.metal_create.argtypes = [C.POINTER(MetalDesc), vp, C.POINTER(vp)]
+    L.metal_destroy.argtypes = [vp]
+    L.continuity_solve.argtypes = [vp, vp, vp, dbl, i64, vp, vp,
+                                   C.POINTER(MetalStats), vp]
+    L.heat_step.argtypes = [vp, C.POINTER(HeatParams), vp, vp, vp, vp,
+                            C.POINTER(MetalStats), vp]
     L.pic_last_error.restype = C.c_char_p
     for n in EXPORTS:
         if n != "pic_last_error":
@@ -740,3 +765,65 @@ class Batch:
             snap.restore(st)
         self.push_tile, self.cg_rows = best[0], best[1]
         return best
+
+
+class Metal:
+    """Device metal mesh (metal_create) for the solves of Sec. II D: the
+    continuity equation with Joule heating and the Theta-scheme heat step.
+    `mesh` is a workloads.MetalMesh (host arrays)."""
+
+    def __init__(self, mesh):
+        torch = _torch()
+        L = load_library()
+        self.n_nodes, self.n_tets = mesh.n_nodes, mesh.n_tets
+        self.n_faces = mesh.n_faces
+        self._keep = [np.ascontiguousarray(mesh.xyz, np.float64),
+                      np.ascontiguousarray(mesh.tet, np.int32),
+                      np.ascontiguousarray(mesh.faces, np.int32).reshape(-1, 3),
+                      np.ascontiguousarray(mesh.dirichlet, np.uint8)]
+        xyz, tet, fac, dr = self._keep
+        d = MetalDesc(self.n_nodes, xyz.ctypes.data, self.n_tets,
+                      tet.ctypes.data, self.n_faces,
+                      fac.ctypes.data if self.n_faces else None, dr.ctypes.data)
+        h = C.c_void_p()
+        _check(L.metal_create(C.byref(d), _stream(torch), C.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.metal_destroy(self._h)
+            self._h = None
+
+    def continuity_solve(self, sigma, flux, phi=None, tol=1e-12,
+                         max_iter=100_000, joule=True):
+        """Phi of Eq. cont_mat (device f64 tensors sigma [n_tets], flux
+        [n_faces]); returns (Phi, P_J or None, stats dict)."""
+        torch = _torch()
+        if phi is None:
+            phi = torch.zeros(self.n_nodes, dtype=torch.float64,
+                              device=sigma.device)
+        pj = torch.empty(self.n_tets, dtype=torch.float64,
+                         device=sigma.device) if joule else None
+        st = MetalStats()
+        _check(load_library().continuity_solve(
+            self._h, sigma.data_ptr(), _ptr(flux) if self.n_faces else None,
+            float(tol), int(max_iter), phi.data_ptr(),
+            pj.data_ptr() if joule else None, C.byref(st), _stream(torch)))
+        return phi, pj, dict(iters=st.iters, relres=st.relres,
+                             converged=bool(st.converged))
+
+    def heat_step(self, T, sigma, P_J, P_N, Cv, L, dt, theta=1.0,
+                  T_amb=300.0, tol=1e-12, max_iter=100_000):
+        """One step of Eq. heat_theta2 in place on T (device f64 [n_nodes]);
+        returns the solver stats."""
+        torch = _torch()
+        prm = HeatParams(float(Cv), float(L), float(dt), float(theta),
+                         float(T_amb), float(tol), int(max_iter))
+        st = MetalStats()
+        _check(load_library().heat_step(
+            self._h, C.byref(prm), sigma.data_ptr(),
+            None if P_J is None else P_J.data_ptr(),
+            _ptr(P_N) if self.n_faces else None, T.data_ptr(), C.byref(st),
+            _stream(torch)))
+        return dict(iters=st.iters, relres=st.relres,
+                    converged=bool(st.converged))

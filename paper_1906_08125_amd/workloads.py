@@ -291,6 +291,23 @@ def config_diode(E0: float, nx: int = 32, nz: int = 50, h: float = 0.364,
                      E0, 4.5, dt, n_steps, 1e-10, 0, 0.0, 5, 20, T)
 
 
+def metal_production() -> MetalMesh:
+    """The metal under the production tip (64 x 64 x 128 cubes of 0.5 nm,
+    R = 3, H = 30): the tip solid and a 10 nm substrate (20 layers)."""
+    return kuhn_metal_mesh(64, 64, 128, 0.5, 3.0, 30.0, 20)
+
+
+def metal_sources(m: MetalMesh, J0: float = 1.0, decay: float = 2.0):
+    """Synthetic interface fluxes for the metal solves: a current density
+    J0 exp((z_f - z_max) / decay) through every interface face (z_f its
+    centroid height), concentrated at the apex the way field emission is,
+    as J_n = -J (electrons leave, so the current enters the metal), and a
+    Nottingham flux of a tenth of it with the opposite sign."""
+    zc = m.xyz[m.faces][:, :, 2].mean(axis=1)
+    J = J0 * np.exp((zc - zc.max()) / decay)
+    return np.ascontiguousarray(-J), np.ascontiguousarray(0.1 * J)
+
+
 def philox_uniform_stream(seed: int, n: int) -> np.ndarray:
     """Plain seeded uniforms for *input* generation (instance draws, test
     points).  Not used by the method itself."""

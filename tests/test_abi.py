@@ -103,3 +103,29 @@ def test_binding_fails_loudly_without_the_library(tmp_path, monkeypatch):
     monkeypatch.setattr(pic, "_lib", None)
     with pytest.raises(ImportError):
         pic.load_library(str(tmp_path / "absent.so"))
+
+
+def test_metal_rejects_null():
+    from paper_1906_08125_amd import pic
+    if not os.path.exists(pic.LIB_PATH):
+        pytest.skip("library not built")
+    L = pic.load_library()
+    h = C.c_void_p()
+    assert L.metal_create(None, None, C.byref(h)) == pic.PIC_E_ARG
+    d = pic.MetalDesc(0, None, 0, None, 0, None, None)
+    assert L.metal_create(C.byref(d), None, C.byref(h)) == pic.PIC_E_ARG
+    assert b"empty" in L.pic_last_error()
+    # out-of-range node ids are caught on the host, before any device work
+    xyz = (C.c_double * 12)(0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0, 1)
+    tets = (C.c_int32 * 4)(0, 1, 2, 4)
+    dr = (C.c_uint8 * 4)(1, 0, 0, 0)
+    d = pic.MetalDesc(4, C.cast(xyz, C.c_void_p), 1, C.cast(tets, C.c_void_p),
+                      0, None, C.cast(dr, C.c_void_p))
+    assert L.metal_create(C.byref(d), None, C.byref(h)) == pic.PIC_E_ARG
+    assert b"range" in L.pic_last_error()
+    st = pic.MetalStats()
+    assert L.continuity_solve(None, None, None, 1e-10, 10, None, None,
+                              C.byref(st), None) == pic.PIC_E_ARG
+    hp = pic.HeatParams(1.0, 2e-8, 1.0, 1.0, 300.0, 1e-10, 10)
+    assert L.heat_step(None, C.byref(hp), None, None, None, None, None,
+                       None) == pic.PIC_E_ARG

@@ -16,8 +16,6 @@ what the equations and the mesh fix independently of the oracle's code:
 * the steady state of the heat equation with kappa = L sigma T
   (Eq. wied_franz) in a slab heated through its top face: T(z)^2 =
   T_amb^2 + 2 q (z - z_b) / (L sigma), to the discretisation error."""
-import math
-
 import numpy as np
 import pytest
 
