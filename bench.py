@@ -432,6 +432,8 @@ def run_metal_leg(args):
     Times per call are host wall times (each call waits for its solve)."""
     import torch
 
+    import numpy as np
+
     from paper_1906_08125_amd import pic, workloads as W
 
     t0 = time.time()
@@ -457,7 +459,17 @@ def run_metal_leg(args):
         iters.append(sh["iters"])
     torch.cuda.synchronize()
     heat_s = (time.perf_counter() - t2) / args.metal_calls
+    # algorithmic bytes of one CG iteration: the CSR product (8-byte values
+    # and 4-byte columns per entry, the row pointers, z, r and w once) and
+    # the step's vector updates (7 vectors read, 5 written)
+    e = np.sort(m.tet[:, [[0, 1], [0, 2], [0, 3], [1, 2], [1, 3], [2, 3]]]
+                .reshape(-1, 2), axis=1)
+    nnz = 2 * int(np.unique(e[:, 0].astype(np.int64) * m.n_nodes + e[:, 1]).size) \
+        + m.n_nodes
+    it_bytes = 12 * nnz + (4 + 32 + 96) * m.n_nodes
     out = dict(nodes=m.n_nodes, tets=m.n_tets, interface_faces=m.n_faces,
+               nnz=nnz, cg_bytes_per_iter=it_bytes,
+               cg_GBps_wall=round(it_bytes * st["iters"] / cont_s / 1e9, 1),
                setup_s=round(setup, 2),
                continuity_ms=round(1e3 * cont_s, 3),
                continuity_iters=int(st["iters"]),

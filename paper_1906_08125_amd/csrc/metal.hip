@@ -22,14 +22,22 @@ namespace fp {
 namespace {
 
 constexpr int kMB = 256;       // threads per workgroup
-constexpr int kMaxG = 1024;    // workgroups of the CG kernels
+constexpr int kMaxG = 1024;    // workgroups of the row-loop kernels
+constexpr int kMaxS = 65536;   // workgroups of the product (a row per thread)
 constexpr int kChunk = 24;     // CG iterations between host checks
 
 struct MetalCtrl {
-  double rz[2];      // z.r of the current and next iteration
+  double gam[2];     // r.z of the last two iterations (by parity)
+  double alpha[2];   // step lengths of the last two iterations (by parity)
   double bb;         // ||b||^2 over the free rows
-  double rr;         // ||r||^2 at the last check
+  double rr;         // ||r||^2 of the last iterate tested
+  double tol2;
+  double red[3];     // r.z, (A z).z and r.r of the last product
+  // iterations completed: written by k_cg_step and read by k_cg_reduce,
+  // which copies it to it_cur for k_cg_step, so that no kernel reads a
+  // counter that its own launch writes
   int64_t iters;
+  int64_t it_cur;
   int32_t done;
   int32_t pad;
 };
@@ -51,20 +59,6 @@ __device__ double block_sum(double v, double* sh) {
   if (threadIdx.x == 0)
     for (int k = 0; k < kMB / 64; ++k) s += sh[k];
   return s;   // valid in thread 0
-}
-
-// Sum of the partials part[0 .. G) (stride `stride`), the same in every
-// workgroup: fixed per-thread order, then the fixed tree.
-__device__ double sum_partials(const double* part, int G, int stride,
-                               double* sh, double* bc) {
-  double v = 0.0;
-  for (int k = threadIdx.x; k < G; k += kMB) v += part[(size_t)k * stride];
-  const double s = block_sum(v, sh);
-  if (threadIdx.x == 0) *bc = s;
-  __syncthreads();
-  const double r = *bc;
-  __syncthreads();
-  return r;
 }
 
 __global__ void k_geom(const double* __restrict__ xyz,
@@ -226,17 +220,27 @@ struct CgArgsM {
   const double* dinv;
   const uint8_t* dir;
   double dir_value;
-  double tol2;
-  double *x, *r, *z, *p, *q;
-  double* part;      // [3][kMaxG]
+  double tol2;       // read by k_cg_init only (the others read ctrl->tol2)
+  double *x, *r, *z, *p, *s, *w;
+  double* part;      // [3][kMaxS]
+  int Gs;            // workgroups of the product
   MetalCtrl* ctrl;
   int G;
 };
 
-__device__ double row_dot(const CgArgsM& a, int64_t i, const double* v) {
-  double s = 0.0;
-  for (int32_t k = a.row_ptr[i]; k < a.row_ptr[i + 1]; ++k) s += a.A[k] * v[a.col[k]];
-  return s;
+
+// Sums nv arrays of nparts partials (stride kMaxS) in index order in one
+// workgroup: every reduction of the solver has the same fixed order.
+__device__ double sum_fixed(const double* part, int nparts, double* sh, double* bc) {
+  double v = 0.0;
+#pragma unroll 8
+  for (int k = threadIdx.x; k < nparts; k += kMB) v += part[k];
+  const double s = block_sum(v, sh);
+  if (threadIdx.x == 0) *bc = s;
+  __syncthreads();
+  const double r = *bc;
+  __syncthreads();
+  return r;
 }
 
 __global__ void k_cg_dir(CgArgsM a) {
@@ -245,59 +249,46 @@ __global__ void k_cg_dir(CgArgsM a) {
     if (a.dir[i]) a.x[i] = a.dir_value;
 }
 
-// r = b - A x, z = D^-1 r; partials of r.z, r.r and b.b over free rows
+// r = b - A x, z = D^-1 r on free rows (zero on Dirichlet rows), partials
+// of b.b; resets the control word
 __global__ void k_cg_init(CgArgsM a) {
   __shared__ double sh[kMB / 64];
-  double rz = 0.0, rr = 0.0, bb = 0.0;
+  double bb = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * kMB + threadIdx.x; i < a.n;
        i += (int64_t)a.G * kMB) {
-    double ri = 0.0, bi = 0.0;
+    double ri = 0.0;
     if (!a.dir[i]) {
-      bi = a.b[i];
-      ri = bi - row_dot(a, i, a.x);
+      const double bi = a.b[i];
+      double ax = 0.0;
+      for (int32_t k = a.row_ptr[i]; k < a.row_ptr[i + 1]; ++k)
+        ax += a.A[k] * a.x[a.col[k]];
+      ri = bi - ax;
+      bb += bi * bi;
     }
-    const double zi = ri * a.dinv[i];
     a.r[i] = ri;
-    a.z[i] = zi;
-    rz += ri * zi;
-    rr += ri * ri;
-    bb += bi * bi;
+    a.z[i] = ri * a.dinv[i];
   }
-  const double s0 = block_sum(rz, sh);
-  const double s1 = block_sum(rr, sh);
-  const double s2 = block_sum(bb, sh);
-  if (threadIdx.x == 0) {
-    a.part[blockIdx.x] = s0;
-    a.part[kMaxG + blockIdx.x] = s1;
-    a.part[2 * kMaxG + blockIdx.x] = s2;
-  }
+  const double s = block_sum(bb, sh);
+  if (threadIdx.x == 0) a.part[blockIdx.x] = s;
 }
 
-// p = z; the control word; a zero right-hand side has the zero solution
+// One workgroup: ||b||^2 from the partials of k_cg_init, and the control
+// word reset for a new solve.
 __global__ void k_cg_start(CgArgsM a) {
   __shared__ double sh[kMB / 64];
   __shared__ double bc;
-  const double rz = sum_partials(a.part, a.G, 1, sh, &bc);
-  const double rr = sum_partials(a.part + kMaxG, a.G, 1, sh, &bc);
-  const double bb = sum_partials(a.part + 2 * kMaxG, a.G, 1, sh, &bc);
-  for (int64_t i = (int64_t)blockIdx.x * kMB + threadIdx.x; i < a.n;
-       i += (int64_t)a.G * kMB) {
-    if (bb == 0.0 && !a.dir[i]) a.x[i] = 0.0;
-    a.p[i] = a.z[i];
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    a.ctrl->rz[0] = rz;
-    a.ctrl->rz[1] = 0.0;
+  const double bb = sum_fixed(a.part, a.G, sh, &bc);
+  if (threadIdx.x == 0) {
     a.ctrl->bb = bb;
-    a.ctrl->rr = bb == 0.0 ? 0.0 : rr;
+    a.ctrl->tol2 = a.tol2;
     a.ctrl->iters = 0;
-    a.ctrl->done = (bb == 0.0 || rr <= a.tol2 * bb) ? 1 : 0;
+    a.ctrl->it_cur = 0;
+    a.ctrl->done = 0;
   }
 }
 
-// q = A p; partial p.q
 // The control word's done flag as one value for the whole workgroup (block
-// 0 of k_cg_direction may set it while other workgroups start).
+// 0 of k_cg_step may set it while other workgroups start).
 __device__ bool block_done(const MetalCtrl* c) {
   __shared__ int d;
   if (threadIdx.x == 0) d = __atomic_load_n(&c->done, __ATOMIC_RELAXED);
@@ -307,65 +298,113 @@ __device__ bool block_done(const MetalCtrl* c) {
   return r;
 }
 
+// w = A z (one row per thread; the row is read eight entries at a time so
+// that their loads are in flight together, and summed in entry order) and
+// the partials of r.z, w.z and r.r
 __global__ void k_cg_spmv(CgArgsM a) {
   if (block_done(a.ctrl)) return;
   __shared__ double sh[kMB / 64];
-  double pq = 0.0;
+  double gz = 0.0, wz = 0.0, rr = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * kMB + threadIdx.x; i < a.n;
-       i += (int64_t)a.G * kMB) {
-    const double qi = row_dot(a, i, a.p);
-    a.q[i] = qi;
-    pq += a.p[i] * qi;
-  }
-  const double s = block_sum(pq, sh);
-  if (threadIdx.x == 0) a.part[blockIdx.x] = s;
-}
-
-// x += alpha p, r -= alpha q, z = D^-1 r; partials of r.z and r.r
-__global__ void k_cg_update(CgArgsM a, int it) {
-  if (block_done(a.ctrl)) return;
-  __shared__ double sh[kMB / 64];
-  __shared__ double bc;
-  const double pq = sum_partials(a.part, a.G, 1, sh, &bc);
-  const double alpha = a.ctrl->rz[it & 1] / pq;
-  double rz = 0.0, rr = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * kMB + threadIdx.x; i < a.n;
-       i += (int64_t)a.G * kMB) {
-    a.x[i] += alpha * a.p[i];
-    const double ri = a.r[i] - alpha * a.q[i];
-    const double zi = ri * a.dinv[i];
-    a.r[i] = ri;
-    a.z[i] = zi;
-    rz += ri * zi;
+       i += (int64_t)gridDim.x * kMB) {
+    const int32_t r0 = a.row_ptr[i], r1 = a.row_ptr[i + 1];
+    double v = 0.0;
+    for (int32_t k0 = r0; k0 < r1; k0 += 8) {
+      int32_t c[8];
+      double av[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const bool ok = k0 + u < r1;
+        c[u] = ok ? a.col[k0 + u] : (int32_t)i;
+        av[u] = ok ? a.A[k0 + u] : 0.0;
+      }
+      double zv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) zv[u] = a.z[c[u]];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v += av[u] * zv[u];
+    }
+    const double ri = a.r[i], zi = a.z[i];
+    a.w[i] = v;
+    gz += ri * zi;
+    wz += v * zi;
     rr += ri * ri;
   }
-  const double s0 = block_sum(rz, sh);
-  const double s1 = block_sum(rr, sh);
+  const double s0 = block_sum(gz, sh);
+  const double s1 = block_sum(wz, sh);
+  const double s2 = block_sum(rr, sh);
   if (threadIdx.x == 0) {
-    a.part[kMaxG + blockIdx.x] = s0;
-    a.part[2 * kMaxG + blockIdx.x] = s1;
+    a.part[blockIdx.x] = s0;
+    a.part[kMaxS + blockIdx.x] = s1;
+    a.part[2 * kMaxS + blockIdx.x] = s2;
   }
 }
 
-// p = z + beta p; block 0 advances the control word
-__global__ void k_cg_direction(CgArgsM a, int it) {
+// One workgroup: the three sums of the product's partials into the control
+// word, and the iteration counter for k_cg_step.
+__global__ void k_cg_reduce(CgArgsM a) {
   if (block_done(a.ctrl)) return;
   __shared__ double sh[kMB / 64];
   __shared__ double bc;
-  const double rz = sum_partials(a.part + kMaxG, a.G, 1, sh, &bc);
-  const double rr = sum_partials(a.part + 2 * kMaxG, a.G, 1, sh, &bc);
-  const double beta = rz / a.ctrl->rz[it & 1];
-  const bool conv = rr <= a.tol2 * a.ctrl->bb;
-  if (!conv)
-    for (int64_t i = (int64_t)blockIdx.x * kMB + threadIdx.x; i < a.n;
-         i += (int64_t)a.G * kMB)
-      a.p[i] = a.z[i] + beta * a.p[i];
+  double r[3];
+  for (int k = 0; k < 3; ++k) r[k] = sum_fixed(a.part + (size_t)k * kMaxS, a.Gs, sh, &bc);
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < 3; ++k) a.ctrl->red[k] = r[k];
+    a.ctrl->it_cur = a.ctrl->iters;
+  }
+}
+
+// One iteration of the single-reduction (Chronopoulos-Gear) form of
+// Jacobi-preconditioned CG: from gamma = r.z, delta = (A z).z,
+//   beta = gamma / gamma_prev, alpha = gamma / (delta - beta gamma / alpha_prev)
+//   (beta = 0, alpha = gamma / delta at the first iteration),
+//   p = z + beta p, s = w + beta s, x += alpha p, r -= alpha s, z = D^-1 r.
+// The residual of the incoming iterate is tested first.
+__global__ void k_cg_step(CgArgsM a) {
+  if (block_done(a.ctrl)) return;
+  const int64_t it = a.ctrl->it_cur;
+  const double gam = a.ctrl->red[0], del = a.ctrl->red[1], rr = a.ctrl->red[2];
+  const double bb = a.ctrl->bb;
+  if (bb == 0.0 || rr <= a.ctrl->tol2 * bb) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      a.ctrl->rr = rr;
+      a.ctrl->iters = it;
+      a.ctrl->done = 1;
+    }
+    return;
+  }
+  double alpha, beta;
+  if (it == 0) {
+    beta = 0.0;
+    alpha = gam / del;
+  } else {
+    beta = gam / a.ctrl->gam[it & 1];
+    alpha = gam / (del - beta * gam / a.ctrl->alpha[it & 1]);
+  }
+  for (int64_t i = (int64_t)blockIdx.x * kMB + threadIdx.x; i < a.n;
+       i += (int64_t)a.G * kMB) {
+    const double pi = a.z[i] + beta * a.p[i];
+    const double si = a.w[i] + beta * a.s[i];
+    a.p[i] = pi;
+    a.s[i] = si;
+    a.x[i] += alpha * pi;
+    const double ri = a.r[i] - alpha * si;
+    a.r[i] = ri;
+    a.z[i] = ri * a.dinv[i];
+  }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    a.ctrl->rz[(it + 1) & 1] = rz;
+    a.ctrl->gam[(it + 1) & 1] = gam;
+    a.ctrl->alpha[(it + 1) & 1] = alpha;
     a.ctrl->rr = rr;
     a.ctrl->iters = it + 1;
-    if (conv) a.ctrl->done = 1;
   }
+}
+
+// A zero right-hand side has the zero solution on the free rows.
+__global__ void k_cg_zero(CgArgsM a) {
+  for (int64_t i = (int64_t)blockIdx.x * kMB + threadIdx.x; i < a.n;
+       i += (int64_t)a.G * kMB)
+    if (!a.dir[i]) a.x[i] = 0.0;
 }
 
 __global__ void k_joule(int64_t nt, const int32_t* __restrict__ tet,
@@ -390,16 +429,22 @@ unsigned blocks_for(int64_t n) { return (unsigned)((n + kMB - 1) / kMB); }
 struct MetalImpl {
   int64_t n = 0, nt = 0, nf = 0, nnz = 0, ninc = 0, nfin = 0;
   double *xyz = nullptr, *A = nullptr, *b = nullptr, *dinv = nullptr;
-  double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *part = nullptr;
+  double *r = nullptr, *z = nullptr, *p = nullptr, *sv = nullptr, *w = nullptr;
+  double* part = nullptr;
   int32_t *tet = nullptr, *face = nullptr, *row_ptr = nullptr, *col = nullptr;
   int32_t *inc_ptr = nullptr, *inc_tet = nullptr, *inc_pos = nullptr;
   int32_t *fin_ptr = nullptr, *fin_face = nullptr;
   int8_t* inc_loc = nullptr;
   uint8_t* dir = nullptr;
+  double* x = nullptr;           // the iterate (the caller's vector is copied)
   MetalTet* geo = nullptr;
   MetalCtrl* ctrl = nullptr;
   MetalCtrl* hctrl = nullptr;   // pinned host mirror
   int G = 1;
+  // kChunk CG iterations captured once per handle (their kernels read
+  // every per-solve value from the control word)
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t chunk = nullptr;
 };
 
 }  // namespace fp
@@ -526,10 +571,11 @@ pic_status metal_build(const pic_metal_desc* d, hipStream_t s, pic_metal** out,
   up(&M.fin_face, fin_face.data(), fin_face.size());
   if (e == hipSuccess) e = dalloc(h, &M.geo, nt);
   if (e == hipSuccess) e = dalloc(h, &M.A, col.size());
-  for (double** v : {&M.b, &M.dinv, &M.r, &M.z, &M.p, &M.q})
+  for (double** v : {&M.b, &M.dinv, &M.r, &M.z, &M.p, &M.sv, &M.w, &M.x})
     if (e == hipSuccess) e = dalloc(h, v, n);
-  if (e == hipSuccess) e = dalloc(h, &M.part, 3 * kMaxG);
+  if (e == hipSuccess) e = dalloc(h, &M.part, 3 * kMaxS);
   if (e == hipSuccess) e = dalloc(h, &M.ctrl, 1);
+  if (e == hipSuccess) e = hipMemsetAsync(M.ctrl, 0, sizeof(MetalCtrl), s);
   int32_t* bad = nullptr;
   if (e == hipSuccess) e = dalloc(h, &bad, 1);
   if (e == hipSuccess) e = hipHostMalloc((void**)&M.hctrl, sizeof(MetalCtrl), hipHostMallocDefault);
@@ -562,25 +608,69 @@ void metal_free(pic_metal* h) {
   if (!h) return;
   for (void* p : h->allocs) (void)hipFree(p);
   if (h->m.hctrl) (void)hipHostFree(h->m.hctrl);
+  if (h->m.chunk) (void)hipGraphExecDestroy(h->m.chunk);
+  if (h->m.graph) (void)hipGraphDestroy(h->m.graph);
   delete h;
 }
 
 namespace {
 
+CgArgsM cg_args(MetalImpl& M, double dir_value, double tol) {
+  CgArgsM a{};
+  a.n = M.n; a.row_ptr = M.row_ptr; a.col = M.col; a.A = M.A; a.b = M.b;
+  a.dinv = M.dinv; a.dir = M.dir; a.dir_value = dir_value; a.tol2 = tol * tol;
+  a.x = M.x; a.r = M.r; a.z = M.z; a.p = M.p; a.s = M.sv; a.w = M.w; a.part = M.part;
+  a.ctrl = M.ctrl; a.G = M.G;
+  a.Gs = (int)std::min<int64_t>(kMaxS, (M.n + kMB - 1) / kMB);
+  return a;
+}
+
+// One iteration: the step (which first tests the incoming iterate) and the
+// product for the next one.
+void launch_iter(const CgArgsM& a, hipStream_t s) {
+  const dim3 g(a.G), b(kMB);
+  hipLaunchKernelGGL(k_cg_step, g, b, 0, s, a);
+  hipLaunchKernelGGL(k_cg_spmv, dim3(a.Gs), b, 0, s, a);
+  hipLaunchKernelGGL(k_cg_reduce, dim3(1), b, 0, s, a);
+}
+
+// Capture kChunk iterations into a graph on a private stream (capture is
+// not possible on the legacy default stream the caller may use).
+hipError_t build_chunk(MetalImpl& M) {
+  hipStream_t cs = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e != hipSuccess) return e;
+  const CgArgsM a = cg_args(M, 0.0, 1.0);
+  e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    for (int k = 0; k < kChunk; ++k) launch_iter(a, cs);
+    hipError_t e2 = hipStreamEndCapture(cs, &M.graph);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = e2;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&M.chunk, M.graph, nullptr, nullptr, 0);
+  (void)hipStreamDestroy(cs);
+  return e;
+}
+
 pic_status run_cg(pic_metal* h, double* x, double dir_value, double tol,
                   int64_t max_iter, pic_metal_stats* st, hipStream_t s,
                   std::string* err, const char* who) {
   MetalImpl& M = h->m;
-  CgArgsM a{};
-  a.n = M.n; a.row_ptr = M.row_ptr; a.col = M.col; a.A = M.A; a.b = M.b;
-  a.dinv = M.dinv; a.dir = M.dir; a.dir_value = dir_value; a.tol2 = tol * tol;
-  a.x = x; a.r = M.r; a.z = M.z; a.p = M.p; a.q = M.q; a.part = M.part;
-  a.ctrl = M.ctrl; a.G = M.G;
+  hipError_t e = hipSuccess;
+  if (!M.chunk) e = build_chunk(M);
+  const CgArgsM a = cg_args(M, dir_value, tol);
   const dim3 g(M.G), b(kMB);
-  hipLaunchKernelGGL(k_cg_dir, g, b, 0, s, a);
-  hipLaunchKernelGGL(k_cg_init, g, b, 0, s, a);
-  hipLaunchKernelGGL(k_cg_start, g, b, 0, s, a);
-  hipError_t e = hipGetLastError();
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(M.x, x, sizeof(double) * M.n, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_cg_dir, g, b, 0, s, a);
+    hipLaunchKernelGGL(k_cg_init, g, b, 0, s, a);
+    hipLaunchKernelGGL(k_cg_start, dim3(1), b, 0, s, a);
+    hipLaunchKernelGGL(k_cg_spmv, dim3(a.Gs), b, 0, s, a);
+    hipLaunchKernelGGL(k_cg_reduce, dim3(1), b, 0, s, a);
+    e = hipGetLastError();
+  }
   int64_t it = 0;
   bool done = false;
   while (e == hipSuccess) {
@@ -589,14 +679,20 @@ pic_status run_cg(pic_metal* h, double* x, double dir_value, double tol,
     if (e != hipSuccess) break;
     done = M.hctrl->done != 0;
     if (done || it >= max_iter) break;
-    const int64_t n = std::min<int64_t>(kChunk, max_iter - it);
-    for (int64_t k = 0; k < n && e == hipSuccess; ++k, ++it) {
-      hipLaunchKernelGGL(k_cg_spmv, g, b, 0, s, a);
-      hipLaunchKernelGGL(k_cg_update, g, b, 0, s, a, (int)it);
-      hipLaunchKernelGGL(k_cg_direction, g, b, 0, s, a, (int)it);
+    if (max_iter - it >= kChunk) {
+      e = hipGraphLaunch(M.chunk, s);
+      it += kChunk;
+    } else {
+      for (; it < max_iter; ++it) launch_iter(a, s);
       e = hipGetLastError();
     }
   }
+  if (e == hipSuccess && done && M.hctrl->bb == 0.0) {
+    hipLaunchKernelGGL(k_cg_zero, g, b, 0, s, a);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(x, M.x, sizeof(double) * M.n, hipMemcpyDeviceToDevice, s);
   if (e != hipSuccess) {
     *err = std::string(who) + ": " + hipGetErrorString(e);
     return PIC_E_DEVICE;

@@ -297,7 +297,7 @@ def metal_production() -> MetalMesh:
     return kuhn_metal_mesh(64, 64, 128, 0.5, 3.0, 30.0, 20)
 
 
-def metal_sources(m: MetalMesh, J0: float = 1.0, decay: float = 2.0):
+def metal_sources(m: MetalMesh, J0: float = 0.02, decay: float = 2.0):
     """Synthetic interface fluxes for the metal solves: a current density
     J0 exp((z_f - z_max) / decay) through every interface face (z_f its
     centroid height), concentrated at the apex the way field emission is,
