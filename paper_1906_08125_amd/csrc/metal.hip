@@ -105,8 +105,6 @@ struct AsmArgs {
   int64_t n;
   const int32_t* row_ptr;
   const int32_t* inc_ptr;
-  const int32_t* inc_tet;
-  const int8_t* inc_loc;
   const int32_t* inc_pos;   // [4] CSR positions per incidence
   const int32_t* fin_ptr;
   const int32_t* fin_face;
@@ -120,9 +118,12 @@ struct AsmArgs {
   const double* PJ;         // volume source or null
   const double* T;          // heat: T^n; continuity: null
   double L, Cv, dt, theta;
+  const int32_t* elem_inc;  // [4 n_tets] incidence of each element's nodes
+  double* stage;            // [5 incidences] element contributions
   double* A;
   double* b;
   double* dinv;
+  int64_t nt;
 };
 
 __device__ double face_area(const double* xyz, const int32_t* f) {
@@ -135,44 +136,59 @@ __device__ double face_area(const double* xyz, const int32_t* f) {
   return 0.5 * sqrt(w0 * w0 + w1 * w1 + w2 * w2);
 }
 
-// One row per thread: the matrix row (continuity: K(sigma); heat:
-// C/dt + theta K(kappa)) and the right-hand side (face and volume loads,
-// and for the heat step (C/dt - (1 - theta) K) T^n).
+// One element per thread: its contributions to the rows of its four nodes
+// (continuity: K(sigma); heat: C/dt + theta K(kappa), and the right-hand
+// side (C/dt - (1 - theta) K) T^n + int N_a P_J), staged per incidence
+// (four matrix entries and one right-hand-side value).
+__global__ void k_element(AsmArgs a) {
+  const int64_t t = (int64_t)blockIdx.x * kMB + threadIdx.x;
+  if (t >= a.nt) return;
+  const MetalTet G = a.geo[t];
+  int32_t nd[4];
+  for (int c = 0; c < 4; ++c) nd[c] = a.tet[4 * t + c];
+  const bool heat = a.T != nullptr;
+  double Tn[4] = {0.0, 0.0, 0.0, 0.0};
+  double kw, mw = 0.0, pj = 0.0;
+  if (heat) {
+    for (int c = 0; c < 4; ++c) Tn[c] = a.T[nd[c]];
+    const double Tbar = (Tn[0] + Tn[1] + Tn[2] + Tn[3]) / 4.0;
+    kw = a.L * a.sigma[t] * Tbar * G.vol;
+    mw = a.Cv * G.vol / 20.0 / a.dt;
+    if (a.PJ) pj = a.PJ[t] * G.vol / 4.0;
+  } else {
+    kw = a.sigma[t] * G.vol;
+  }
+  for (int l = 0; l < 4; ++l) {
+    const double* gl = &G.g[3 * l];
+    double* out = a.stage + 5 * (int64_t)a.elem_inc[4 * t + l];
+    double b = pj;
+    for (int c = 0; c < 4; ++c) {
+      const double* gc = &G.g[3 * c];
+      const double kab = kw * (gl[0] * gc[0] + gl[1] * gc[1] + gl[2] * gc[2]);
+      if (heat) {
+        const double mab = c == l ? 2.0 * mw : mw;
+        out[c] = mab + a.theta * kab;
+        b += (mab - (1.0 - a.theta) * kab) * Tn[c];
+      } else {
+        out[c] = kab;
+      }
+    }
+    out[4] = b;
+  }
+}
+
+// One row per thread: the staged contributions of its node's elements,
+// added in ascending element order, and the face loads.
 __global__ void k_assemble(AsmArgs a, double dir_value) {
   const int64_t i = (int64_t)blockIdx.x * kMB + threadIdx.x;
   if (i >= a.n) return;
   const int32_t r0 = a.row_ptr[i], r1 = a.row_ptr[i + 1];
   for (int32_t k = r0; k < r1; ++k) a.A[k] = 0.0;
-  const bool heat = a.T != nullptr;
   double b = 0.0;
   for (int32_t q = a.inc_ptr[i]; q < a.inc_ptr[i + 1]; ++q) {
-    const int32_t t = a.inc_tet[q];
-    const int loc = a.inc_loc[q];
-    const MetalTet& G = a.geo[t];
-    const double* gl = &G.g[3 * loc];
-    double kw;
-    int32_t nd[4];
-    for (int c = 0; c < 4; ++c) nd[c] = a.tet[4 * (int64_t)t + c];
-    if (heat) {
-      const double Tbar = (a.T[nd[0]] + a.T[nd[1]] + a.T[nd[2]] + a.T[nd[3]]) / 4.0;
-      kw = a.L * a.sigma[t] * Tbar * G.vol;
-      if (a.PJ) b += a.PJ[t] * G.vol / 4.0;
-    } else {
-      kw = a.sigma[t] * G.vol;
-    }
-    const double mw = heat ? a.Cv * G.vol / 20.0 / a.dt : 0.0;
-    for (int c = 0; c < 4; ++c) {
-      const double* gc = &G.g[3 * c];
-      const double kab = kw * (gl[0] * gc[0] + gl[1] * gc[1] + gl[2] * gc[2]);
-      const double mab = c == loc ? 2.0 * mw : mw;
-      const int32_t pos = a.inc_pos[4 * (int64_t)q + c];
-      if (heat) {
-        a.A[pos] += mab + a.theta * kab;
-        b += (mab - (1.0 - a.theta) * kab) * a.T[nd[c]];
-      } else {
-        a.A[pos] += kab;
-      }
-    }
+    const double* st = a.stage + 5 * (int64_t)q;
+    for (int c = 0; c < 4; ++c) a.A[a.inc_pos[4 * (int64_t)q + c]] += st[c];
+    b += st[4];
   }
   for (int32_t q = a.fin_ptr[i]; q < a.fin_ptr[i + 1]; ++q) {
     const int32_t f = a.fin_face[q];
@@ -432,9 +448,10 @@ struct MetalImpl {
   double *r = nullptr, *z = nullptr, *p = nullptr, *sv = nullptr, *w = nullptr;
   double* part = nullptr;
   int32_t *tet = nullptr, *face = nullptr, *row_ptr = nullptr, *col = nullptr;
-  int32_t *inc_ptr = nullptr, *inc_tet = nullptr, *inc_pos = nullptr;
+  int32_t *inc_ptr = nullptr, *inc_pos = nullptr;
   int32_t *fin_ptr = nullptr, *fin_face = nullptr;
-  int8_t* inc_loc = nullptr;
+  int32_t* elem_inc = nullptr;
+  double* stage = nullptr;
   uint8_t* dir = nullptr;
   double* x = nullptr;           // the iterate (the caller's vector is copied)
   MetalTet* geo = nullptr;
@@ -497,6 +514,7 @@ pic_status metal_build(const pic_metal_desc* d, hipStream_t s, pic_metal** out,
   // node -> element incidences (ascending element id)
   std::vector<int32_t> inc_ptr(n + 1, 0), inc_tet(4 * nt);
   std::vector<int8_t> inc_loc(4 * nt);
+  std::vector<int32_t> elem_inc(4 * nt);
   for (int64_t k = 0; k < 4 * nt; ++k) ++inc_ptr[d->tets[k] + 1];
   for (int64_t i = 0; i < n; ++i) inc_ptr[i + 1] += inc_ptr[i];
   {
@@ -504,6 +522,7 @@ pic_status metal_build(const pic_metal_desc* d, hipStream_t s, pic_metal** out,
     for (int64_t t = 0; t < nt; ++t)
       for (int a = 0; a < 4; ++a) {
         const int32_t v = d->tets[4 * t + a];
+        elem_inc[4 * t + a] = fill[v];
         inc_tet[fill[v]] = (int32_t)t;
         inc_loc[fill[v]++] = (int8_t)a;
       }
@@ -564,9 +583,9 @@ pic_status metal_build(const pic_metal_desc* d, hipStream_t s, pic_metal** out,
   up(&M.row_ptr, row_ptr.data(), n + 1);
   up(&M.col, col.data(), col.size());
   up(&M.inc_ptr, inc_ptr.data(), n + 1);
-  up(&M.inc_tet, inc_tet.data(), inc_tet.size());
-  up(&M.inc_loc, inc_loc.data(), inc_loc.size());
   up(&M.inc_pos, inc_pos.data(), inc_pos.size());
+  up(&M.elem_inc, elem_inc.data(), elem_inc.size());
+  if (e == hipSuccess) e = dalloc(h, &M.stage, 5 * (size_t)M.ninc);
   up(&M.fin_ptr, fin_ptr.data(), n + 1);
   up(&M.fin_face, fin_face.data(), fin_face.size());
   if (e == hipSuccess) e = dalloc(h, &M.geo, nt);
@@ -713,10 +732,11 @@ pic_status run_cg(pic_metal* h, double* x, double dir_value, double tol,
 
 AsmArgs asm_args(const MetalImpl& M) {
   AsmArgs a{};
-  a.n = M.n; a.row_ptr = M.row_ptr; a.inc_ptr = M.inc_ptr; a.inc_tet = M.inc_tet;
-  a.inc_loc = M.inc_loc; a.inc_pos = M.inc_pos; a.fin_ptr = M.fin_ptr;
+  a.n = M.n; a.row_ptr = M.row_ptr; a.inc_ptr = M.inc_ptr;
+  a.inc_pos = M.inc_pos; a.fin_ptr = M.fin_ptr;
   a.fin_face = M.fin_face; a.tet = M.tet; a.face = M.face; a.xyz = M.xyz;
   a.geo = M.geo; a.dir = M.dir; a.A = M.A; a.b = M.b; a.dinv = M.dinv;
+  a.elem_inc = M.elem_inc; a.stage = M.stage; a.nt = M.nt;
   return a;
 }
 
@@ -730,6 +750,7 @@ pic_status metal_continuity(pic_metal* h, const double* sigma, const double* flu
   a.sigma = sigma;
   a.flux = flux;
   const unsigned g = blocks_for(M.n);
+  hipLaunchKernelGGL(k_element, dim3(blocks_for(M.nt)), dim3(kMB), 0, s, a);
   hipLaunchKernelGGL(k_assemble, dim3(g), dim3(kMB), 0, s, a, 0.0);
   hipLaunchKernelGGL(k_eliminate, dim3(g), dim3(kMB), 0, s, M.n, M.row_ptr, M.col,
                      M.dir, 0.0, M.A, M.b, M.dinv);
@@ -758,6 +779,7 @@ pic_status metal_heat(pic_metal* h, const pic_heat_params* p, const double* sigm
   a.T = T;
   a.L = p->L; a.Cv = p->Cv; a.dt = p->dt; a.theta = p->theta;
   const unsigned g = blocks_for(M.n);
+  hipLaunchKernelGGL(k_element, dim3(blocks_for(M.nt)), dim3(kMB), 0, s, a);
   hipLaunchKernelGGL(k_assemble, dim3(g), dim3(kMB), 0, s, a, p->T_amb);
   hipLaunchKernelGGL(k_eliminate, dim3(g), dim3(kMB), 0, s, M.n, M.row_ptr, M.col,
                      M.dir, p->T_amb, M.A, M.b, M.dinv);
