@@ -178,17 +178,34 @@ __global__ void k_element(AsmArgs a) {
 }
 
 // One row per thread: the staged contributions of its node's elements,
-// added in ascending element order, and the face loads.
-__global__ void k_assemble(AsmArgs a, double dir_value) {
+// added in ascending element order, and the face loads.  A row of up to
+// kRowLds entries (15 for an interior node of a Kuhn mesh) is accumulated
+// in the thread's LDS slot and written once; longer rows in place.
+constexpr int kRowLds = 16;
+
+__global__ void __launch_bounds__(kMB) k_assemble(AsmArgs a, double dir_value) {
+  __shared__ double acc[kMB][kRowLds + 1];
   const int64_t i = (int64_t)blockIdx.x * kMB + threadIdx.x;
   if (i >= a.n) return;
   const int32_t r0 = a.row_ptr[i], r1 = a.row_ptr[i + 1];
-  for (int32_t k = r0; k < r1; ++k) a.A[k] = 0.0;
   double b = 0.0;
-  for (int32_t q = a.inc_ptr[i]; q < a.inc_ptr[i + 1]; ++q) {
-    const double* st = a.stage + 5 * (int64_t)q;
-    for (int c = 0; c < 4; ++c) a.A[a.inc_pos[4 * (int64_t)q + c]] += st[c];
-    b += st[4];
+  if (r1 - r0 <= kRowLds) {
+    double* row = acc[threadIdx.x];
+    for (int k = 0; k < r1 - r0; ++k) row[k] = 0.0;
+    for (int32_t q = a.inc_ptr[i]; q < a.inc_ptr[i + 1]; ++q) {
+      const double* st = a.stage + 5 * (int64_t)q;
+      const int32_t* ps = a.inc_pos + 4 * (int64_t)q;
+      for (int c = 0; c < 4; ++c) row[ps[c] - r0] += st[c];
+      b += st[4];
+    }
+    for (int k = 0; k < r1 - r0; ++k) a.A[r0 + k] = row[k];
+  } else {
+    for (int32_t k = r0; k < r1; ++k) a.A[k] = 0.0;
+    for (int32_t q = a.inc_ptr[i]; q < a.inc_ptr[i + 1]; ++q) {
+      const double* st = a.stage + 5 * (int64_t)q;
+      for (int c = 0; c < 4; ++c) a.A[a.inc_pos[4 * (int64_t)q + c]] += st[c];
+      b += st[4];
+    }
   }
   for (int32_t q = a.fin_ptr[i]; q < a.fin_ptr[i + 1]; ++q) {
     const int32_t f = a.fin_face[q];
