@@ -416,8 +416,9 @@ __global__ void k_cg_step(CgArgsM a) {
   }
   for (int64_t i = (int64_t)blockIdx.x * kMB + threadIdx.x; i < a.n;
        i += (int64_t)a.G * kMB) {
-    const double pi = a.z[i] + beta * a.p[i];
-    const double si = a.w[i] + beta * a.s[i];
+    // p and s hold nothing yet at the first iteration (not even zeros)
+    const double pi = it == 0 ? a.z[i] : a.z[i] + beta * a.p[i];
+    const double si = it == 0 ? a.w[i] : a.w[i] + beta * a.s[i];
     a.p[i] = pi;
     a.s[i] = si;
     a.x[i] += alpha * pi;

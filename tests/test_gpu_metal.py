@@ -128,6 +128,29 @@ def test_metal_checks_arguments(pic, tiny):
         pic.Metal(bad)
 
 
+def test_metal_on_reused_memory(pic, tiny):
+    """A handle whose device buffers are memory that earlier work left full
+    of NaN: the first CG iteration must not read its search directions
+    (regression: it multiplied them by beta = 0)."""
+    junk = torch.full((1 << 27,), float("nan"), dtype=torch.float64,
+                      device="cuda")
+    torch.cuda.synchronize()
+    del junk
+    torch.cuda.empty_cache()
+    rng = np.random.default_rng(5)
+    sigma = 0.5 + rng.random(tiny.n_tets)
+    flux = rng.normal(0.0, 0.2, tiny.n_faces)
+    gm = pic.Metal(tiny)
+    phi, _, st = gm.continuity_solve(_dev(sigma), _dev(flux), tol=1e-13)
+    assert st["converged"]
+    assert _rel(phi.cpu().numpy(), OM.continuity_solve(tiny, sigma, flux)) < 1e-9
+    T = _dev(np.full(tiny.n_nodes, 300.0))
+    st = gm.heat_step(T, _dev(sigma), _dev(np.full(tiny.n_tets, 1e-3)),
+                      _dev(np.zeros(tiny.n_faces)), 3.45e-3, L_CU, 40.0,
+                      tol=1e-13)
+    assert st["converged"] and np.isfinite(T.cpu().numpy()).all()
+
+
 def _outward_nz(m):
     P = m.xyz[m.faces]
     n = np.cross(P[:, 1] - P[:, 0], P[:, 2] - P[:, 0])
