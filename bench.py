@@ -3,8 +3,10 @@
 Workload: the production-shaped tip (box 32 x 32 x 64 nm, 64 x 64 x 128
 Kuhn grid, 3,100,504 tets, tip R = 3 nm, H = 30 nm, E0 = 0.5 V/nm, apex
 faces emitting, w_sp set for ~1e6 live superparticles, dt = 0.5 fs,
-PCG tolerance 1e-10).  W warm-up steps bring the run to its steady state
-(~1e6 live), then K steps are timed between device synchronizations.
+PCG tolerance 1e-10).  An untimed fill runs from the empty gap until at
+least 95 % of the ~1e6 target population is live (the steady state,
+whatever W says), then W untimed warm-up steps, then K steps are timed
+between device synchronizations.
 
 Prints one JSON line.  Roofline byte model of the push: 112 B per live
 superparticle and step in FP64 (read x, y, z, vx, vy, vz, w and the tet
@@ -30,18 +32,23 @@ HBM_PEAK_GBS = 8000.0
 # production workload, from rocprofv3 FETCH_SIZE and WRITE_SIZE counter runs
 # scaled by a plain 1 GiB copy (profiles/pic_step_fp64_production_tip.md).
 # It is reported only while the kernel sources are the ones profiled.
-PUSH_TRAFFIC = dict(bytes=200.0e6, read=134.4e6, written=65.6e6,
+PUSH_TRAFFIC = dict(bytes=200.0e6, read=134.4e6, written=65.6e6, live=992_310,
                     sources=("paper_1906_08125_amd/csrc/particles.hip",
                              "paper_1906_08125_amd/csrc/common.h"),
                     sha256=("134e33f198c3176cfe6b232d6ed92ef5f7f5f3d69bea0fbcf81858bb7249254c", "7d8f3c2344d581d986633cc1e8597ea0062a3ad5736211095600e29a54930541"))
 
 
-def measured_traffic():
+def measured_traffic(live):
+    """The counters' bytes per launch, when they were taken on the kernel
+    as it is now and at the population `achieved` is measured at (within
+    5 %); else None."""
     import hashlib
     for path, digest in zip(PUSH_TRAFFIC["sources"], PUSH_TRAFFIC["sha256"]):
         with open(os.path.join(ROOT, path), "rb") as f:
             if hashlib.sha256(f.read()).hexdigest() != digest:
                 return None
+    if abs(live / PUSH_TRAFFIC["live"] - 1) > 0.05:
+        return None
     return PUSH_TRAFFIC["bytes"]
 
 
@@ -49,19 +56,30 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def solve_bytes(info, iters):
-    """Algorithmic HBM bytes of one step's solve: the fused residual + field
-    pass over phi (rows: node map, own phi, charge, Neumann load, x, r, u,
-    D^-1, E; entries: node column, K, R (3)), the convergence test, and per
-    CG iteration the update (7 vector reads, 5 writes) and the K u product
-    (column + value per entry, u and w per row).  A re-check after
-    iterations adds a scatter and another fused pass."""
+def solve_bytes(info, rows, first_full=True):
+    """Algorithmic HBM bytes of the solves of a run of consecutive steps of
+    one pic_step call (rows: their stats).  The first solve of a call starts
+    with the fused residual + field pass over phi (rows: node map, own phi,
+    charge, Neumann load, x, r, u, D^-1, E; entries: node column, K, R (3));
+    every later one with the incremental residual pass r = (b - b_prev) +
+    r_prev (node map, charge, Neumann load, b_prev and r read and written,
+    x written, phi, D^-1, u written: 84 B per free row), which needs no
+    product with K because phi and the field have not changed since the
+    previous solve ended.  Per CG iteration: the update (7 vector reads, 5
+    writes) and the K u product (column + value per entry, u and w per
+    row); a solve that iterated ends with phi = x (20 B per free row) and a
+    fused re-check pass."""
     n, nnz = info["n_free"], info["nnz"]
     N, nf = info["n_nodes"], info["nnz_field"]
     fused = 100 * n + 36 * nnz + 28 * (nf - nnz) + 40 * (N - n)
+    inc = 84 * n
     it = 96 * n + 12 * nnz + 16 * n
-    recheck = (20 * n + fused) if iters > 0 else 0
-    return fused + iters * it + recheck
+    total = 0
+    for k, r in enumerate(rows):
+        total += fused if (k == 0 and first_full) else inc
+        if r["cg_iters"] > 0:
+            total += r["cg_iters"] * it + 20 * n + fused
+    return total
 
 
 def push_bytes(n_live, real_bytes=8):
@@ -70,7 +88,7 @@ def push_bytes(n_live, real_bytes=8):
     return (12 * real_bytes + 16) * n_live
 
 
-def run_leg(gm, cfg, w_sp, precision, args):
+def run_leg(gm, cfg, w_sp, precision, args, fill_steps=None):
     """Warm-up then K timed steps of one run at the given precision."""
     import torch
 
@@ -87,13 +105,16 @@ def run_leg(gm, cfg, w_sp, precision, args):
     cold = dict(pic.Mesh.solve_stats(st0), ms=round(1e3 * (time.perf_counter() - t0), 3))
     kw = dict(dt=cfg.dt, E0=cfg.E0, w_sp=w_sp, phi_w=cfg.phi_w,
               seed=cfg.seed, tol=cfg.tol, resort_every=args.resort)
-    step = 0
+    step, fill = fill_to_steady_state(gm, gs, kw, cfg.n_target, args,
+                                      fill_steps)
+    log(f"fill ({precision}): {fill['steps']} steps to "
+        f"{fill['live']} live superparticles")
     if args.warmup:
         wstats = gs.step(step0=step, n_steps=args.warmup, **kw)
         torch.cuda.synchronize()
         log(f"after warmup ({precision}): "
             f"{pic.State.decode_stats(wstats)[-1]}")
-    step += args.warmup
+        step += args.warmup
     stats = torch.zeros(args.steps * pic.STEP_STATS_BYTES // 8,
                         dtype=torch.int64, device="cuda")
     # timed region: K steps, bracketed by synchronizations; HIP events
@@ -145,7 +166,51 @@ def run_leg(gm, cfg, w_sp, precision, args):
         if r["status"] != 0:
             raise RuntimeError(f"step status {r['status']}: {r}")
     return dict(elapsed=elapsed, kt=kt, kt_timed=kt_timed, rows=rows,
-                rows_b=rows_b, state=gs, cold=cold, kt_coll=kt_coll, snap=snap)
+                rows_b=rows_b, state=gs, cold=cold, kt_coll=kt_coll, snap=snap,
+                fill=fill)
+
+
+def fill_to_steady_state(gm, gs, kw, n_target, args, steps=None):
+    """Untimed steps from the empty gap until at least args.fill_frac of the
+    target population is live, one step per call with the push kernel timed
+    by HIP events: the pairs (superparticles pushed, push time) of the fill
+    separate the push's fixed cost per launch from its cost per particle
+    (least-squares line).  steps: run exactly this many instead (the
+    mixed-precision leg repeats the FP64 leg's fill, so that both are
+    compared after the same steps).  Returns the next step index and the
+    fill record."""
+    import numpy as np
+    import torch
+
+    from paper_1906_08125_amd import pic
+
+    pts = []
+    step, live = 0, 0
+    while (live < args.fill_frac * n_target if steps is None
+           else step < steps):
+        if step >= args.max_fill:
+            raise RuntimeError(f"fill: {live} live after {step} steps, "
+                               f"target {args.fill_frac} x {n_target}")
+        gm.profile(True, classes=("push",))
+        st = pic.State.decode_stats(gs.step(step0=step, n_steps=1, **kw))[0]
+        kt = gm.profile_read()
+        gm.profile(False)
+        if st["status"] != 0:
+            raise RuntimeError(f"fill step status {st['status']}: {st}")
+        pts.append((st["n_before"] + st["n_inj"], 1e3 * kt["push"]["ms"]))
+        live = st["n_after"]
+        step += 1
+    torch.cuda.synchronize()
+    n = np.array([p[0] for p in pts], float)
+    us = np.array([p[1] for p in pts])
+    # the first steps also load code objects and page the mesh in
+    use = slice(3, None) if len(pts) > 8 else slice(0, None)
+    b, a = np.polyfit(n[use], us[use], 1)
+    return step, dict(steps=step, live=int(live),
+                      push_fixed_us=round(float(a), 2),
+                      push_us_per_million=round(float(b) * 1e6, 2),
+                      samples=[(int(x), round(float(y), 2))
+                               for x, y in zip(n[::5], us[::5])])
 
 
 def precision_drift(a, b):
@@ -222,6 +287,7 @@ def run_gpu(args):
     elapsed, kt, rows = leg["elapsed"], leg["kt"], leg["rows"]
     kt_timed, rows_b = leg["kt_timed"], leg["rows_b"]
     snap64 = leg["snap"]
+    fill64 = leg["fill"]
     collisions = None
     if "collide" in leg["kt_coll"]:
         c = leg["kt_coll"]["collide"]
@@ -248,9 +314,9 @@ def run_gpu(args):
     dom, dom_bytes, dom_us = "push", pb, push_us
     if "solve" in kt and rows_b:
         solve_us = kt["solve"]["ms"] * 1e3 / kt["solve"]["launches"]
-        iters_b = sum(r["cg_iters"] for r in rows_b) / len(rows_b)
-        live_b = sum(r["n_before"] for r in rows_b) / len(rows_b)
-        sb = solve_bytes(gm.info, iters_b)
+        nb = args.breakdown_steps
+        live_b = sum(r["n_before"] for r in rows_b[:nb]) / nb
+        sb = solve_bytes(gm.info, rows_b[:nb]) / nb
         kernels["solve"]["algo_bytes"] = sb
         kernels["solve"]["GBps"] = round(sb / solve_us / 1e3, 1)
         pbb = push_bytes(live_b)
@@ -259,11 +325,19 @@ def run_gpu(args):
         if kt["solve"]["ms"] > kt["push"]["ms"]:
             dom, dom_bytes, dom_us = "solve", sb, solve_us
     achieved = dom_bytes / dom_us / 1e3  # GB/s
+    for name, v in kernels.items():
+        if v.get("GBps", 0.0) > HBM_PEAK_GBS:
+            # only a working set held in the 256 MB Infinity Cache could
+            # do this; the byte model of that kernel is to be checked
+            log(f"warning: {name} at {v['GBps']} GB/s of algorithmic bytes "
+                f"exceeds the HBM peak")
+            v["above_hbm_peak"] = True
 
     mixed = None
     if not args.no_mixed:
         torch.cuda.empty_cache()
-        ml = run_leg(gm, cfg, w_sp, pic.PIC_MIXED, args)
+        ml = run_leg(gm, cfg, w_sp, pic.PIC_MIXED, args,
+                     fill_steps=fill64["steps"])
         mr = ml["rows"]
         m_live = sum(r["n_before"] for r in mr) / len(mr)
         mk = ml["kt"]
@@ -279,6 +353,7 @@ def run_gpu(args):
             cg_iters_per_step=sum(r["cg_iters"] for r in mr) / len(mr),
             inner_tol=args.inner_tol,
             cold_solve=ml["cold"],
+            fill=ml["fill"],
             kernels={n: dict(ms_total=round(v["ms"], 4),
                              launches=v["launches"],
                              us_per_launch=round(1e3 * v["ms"] / v["launches"], 2))
@@ -322,6 +397,7 @@ def run_gpu(args):
                     resort_every=args.resort),
         pushes_per_s=round(pushes / elapsed, 1),
         cg_iters_per_step=sum(r["cg_iters"] for r in rows) / len(rows),
+        fill=fill64,
         cold_solve=dict(iters=cold["iters"], ms=round(cold_ms, 3),
                         iters_per_s=round(cold["iters"] / cold_ms * 1e3, 1),
                         relres=cold["relres"], precond="jacobi"),
@@ -340,8 +416,14 @@ def run_gpu(args):
         roofline=dict(kernel=dom, bound="hbm", achieved=round(achieved, 1),
                       peak=HBM_PEAK_GBS, unit="GB/s",
                       frac=round(achieved / HBM_PEAK_GBS, 4),
-                      traffic=(measured_traffic() if dom == "push" else None)),
+                      traffic=(measured_traffic(live_mean) if dom == "push"
+                               else None),
+                      live_particles=round(live_mean),
+                      limiter=("dependent gathers (tet record, nodal field, "
+                               "walk) at the occupancy the registers allow"
+                               if dom == "push" else "HBM")),
     )
+    gm.close()
     return out, dict(cfg=cfg, tip=tip, w_sp=w_sp)
 
 
@@ -421,7 +503,8 @@ def run_charge_leg(tip, args):
                                            / (ms * 1e-3), 1),
                total_charge_e=round(float(Q.sum().item()), 6),
                conservation=float(q.sum().item() / Q.sum().item()))
-    del gmc, gs
+    del gs
+    gmc.close()
     return out
 
 
@@ -478,6 +561,7 @@ def run_metal_leg(args):
                us_per_cg_iter=round(1e6 * cont_s / max(st["iters"], 1), 2),
                T_max=round(float(T.max().item()), 4))
     log(f"metal leg {out}")
+    gm.close()
     return out
 
 
@@ -602,6 +686,8 @@ def run_batch_leg(args):
         t_seq += time.perf_counter() - w0
     del sts
     torch.cuda.empty_cache()
+    for m in meshes:
+        m.close()
     n = len(cfgs)
     return dict(instances=n, tets=int(sum(m.n_tets for m in meshes)),
                 live_particles=int(sum(x["n_after"] for x in rows[-1])),
@@ -695,7 +781,12 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10,
+                    help="untimed steps after the fill, before the timed ones")
+    ap.add_argument("--fill-frac", type=float, default=0.95,
+                    help="the untimed fill runs until this fraction of the "
+                         "target population is live")
+    ap.add_argument("--max-fill", type=int, default=400)
     ap.add_argument("--capacity", type=float, default=2.5e6)
     ap.add_argument("--resort", type=int, default=10)
     ap.add_argument("--breakdown-steps", type=int, default=20,

@@ -6,8 +6,11 @@ missing or a GPU is not available -- there is no CPU fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import sys
+import weakref
 
 import numpy as np
 
@@ -131,6 +134,29 @@ class BatchSchedule(C.Structure):
                 ("fallback_blocks", C.c_int32), ("pad", C.c_int32)]
 
 _lib = None
+
+# Handles still open when the interpreter exits are closed by an atexit
+# hook (registered when the library loads, so it runs before torch's own
+# exit hooks and long before the HIP runtime's teardown at process exit):
+# batches first, then metal meshes, then vacuum meshes.  Finalizers do not
+# call into HIP while the interpreter is finalizing.
+_open_handles = weakref.WeakSet()
+
+
+def _close_all():
+    objs = list(_open_handles)
+    order = {"Batch": 0, "Metal": 1, "Mesh": 2}
+    for o in sorted(objs, key=lambda o: order.get(type(o).__name__, 3)):
+        try:
+            o.close()
+        except Exception:
+            pass
+
+
+def _finalizing() -> bool:
+    return sys.is_finalizing()
+
+
 EXPORTS = ("mesh_create", "mesh_destroy", "mesh_query", "mesh_emit_faces",
            "locate", "deposit", "poisson_solve", "pic_step", "emission_rate",
            "adjoint_step", "pic_batch_create", "pic_batch_destroy",
@@ -192,6 +218,7 @@ def load_library(path: str = LIB_PATH):
         if n != "pic_last_error":
             getattr(L, n).restype = C.c_int32
     _lib = L
+    atexit.register(_close_all)
     return L
 
 
@@ -209,6 +236,28 @@ def _torch():
 
 def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _dev_arrays(*specs):
+    """Checks, before anything reaches the library, that each (tensor,
+    dtype names, n, name) spec is a contiguous tensor of one of the dtypes
+    ("float64", "int32", ...) holding exactly n elements (the kernels index
+    it up to n), and then that every one of them is on the HIP device."""
+    for t, dtypes, n, name in specs:
+        if isinstance(dtypes, str):
+            dtypes = (dtypes,)
+        dt = str(getattr(t, "dtype", "")).replace("torch.", "")
+        if dt not in dtypes:
+            raise TypeError(f"{name}: dtype {dt or type(t).__name__}, "
+                            f"expected {' or '.join(dtypes)}")
+        if t.numel() != n:
+            raise ValueError(f"{name}: {t.numel()} elements, expected {n}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name}: not contiguous")
+    for t, _, _, name in specs:
+        if t.device.type != "cuda":
+            raise TypeError(f"{name}: on {t.device}, expected a HIP device "
+                            "tensor")
 
 
 def _stream(torch):
@@ -231,6 +280,7 @@ class Mesh:
         h = C.c_void_p()
         _check(L.mesh_create(C.byref(d), _stream(torch), C.byref(h)))
         self._h = h
+        _open_handles.add(self)
         info = MeshInfo()
         _check(L.mesh_query(h, C.byref(info)))
         self.info = {k: getattr(info, k) for k, _ in info._fields_}
@@ -246,11 +296,15 @@ class Mesh:
         return self._h
 
     def close(self):
+        """Frees the device mesh (mesh_destroy); later calls do nothing."""
         if getattr(self, "_h", None) is not None:
-            load_library().mesh_destroy(self._h)
-            self._h = None
+            h, self._h = self._h, None
+            _open_handles.discard(self)
+            load_library().mesh_destroy(h)
 
     def __del__(self):
+        if _finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -307,12 +361,21 @@ class Mesh:
 
     # ---- single calls ---------------------------------------------------
     def locate(self, x, y, z, tet_inout, where_out):
+        n = x.numel()
+        _dev_arrays((x, "float64", n, "x"), (y, "float64", n, "y"),
+                    (z, "float64", n, "z"), (tet_inout, "int32", n, "tet_inout"),
+                    (where_out, "uint8", n, "where_out"))
         torch = _torch()
         _check(load_library().locate(self._h, x.numel(), _ptr(x), _ptr(y),
                                      _ptr(z), _ptr(tet_inout), _ptr(where_out),
                                      _stream(torch)))
 
     def deposit(self, x, y, z, tet, w, charge):
+        n = x.numel()
+        _dev_arrays((x, "float64", n, "x"), (y, "float64", n, "y"),
+                    (z, "float64", n, "z"), (w, "float64", n, "w"),
+                    (tet, "int32", n, "tet"),
+                    (charge, "int64", self.n_nodes, "charge"))
         torch = _torch()
         _check(load_library().deposit(self._h, x.numel(), _ptr(x), _ptr(y),
                                       _ptr(z), _ptr(tet), _ptr(w),
@@ -321,6 +384,13 @@ class Mesh:
     def poisson_solve(self, charge, w_sp, E0, phi, E=None, tol=1e-12,
                       max_iter=20000, precision=PIC_FP64, inner_tol=1e-4,
                       precond=PIC_PRECOND_JACOBI):
+        specs = [(phi, "float64", self.n_nodes, "phi")]
+        if charge is not None:
+            specs.append((charge, "int64", self.n_nodes, "charge"))
+        if E is not None:
+            specs.append((E, "float64" if precision == PIC_FP64 else "float32",
+                          4 * self.n_nodes, "E"))
+        _dev_arrays(*specs)
         torch = _torch()
         st = torch.zeros(6, dtype=torch.float64, device=phi.device)
         prm = SolveParams(tol, inner_tol, max_iter, precision, precond)
@@ -340,9 +410,8 @@ class Mesh:
     def emission_rate(self, E, phi_w):
         """FN rate (e/fs) and |E| per emitting face for the FP64 nodal field
         E [4 n_nodes]."""
+        _dev_arrays((E, "float64", 4 * self.n_nodes, "E (FP64 nodal field)"))
         torch = _torch()
-        if E.dtype != torch.float64:
-            raise TypeError("emission_rate takes the FP64 nodal field")
         rate = torch.zeros(1, dtype=torch.float64, device=E.device)
         faceF = torch.zeros(max(self.n_emit, 1), dtype=torch.float64,
                             device=E.device)
@@ -666,6 +735,7 @@ class Batch:
         h = C.c_void_p()
         _check(L.pic_batch_create(arr, n, C.byref(h), lim))
         self._h = h
+        _open_handles.add(self)
         self.limits = np.array(list(lim), dtype=np.int64).reshape(n, 4)
         self.push_tile, self.cg_rows = 4096, 1024
         self.inject_blocks, self.clear_blocks, self.fallback_blocks = 16, 16, 8
@@ -674,10 +744,13 @@ class Batch:
 
     def close(self):
         if getattr(self, "_h", None) is not None:
-            load_library().pic_batch_destroy(self._h)
-            self._h = None
+            h, self._h = self._h, None
+            _open_handles.discard(self)
+            load_library().pic_batch_destroy(h)
 
     def __del__(self):
+        if _finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -788,16 +861,33 @@ class Metal:
         h = C.c_void_p()
         _check(L.metal_create(C.byref(d), _stream(torch), C.byref(h)))
         self._h = h
+        _open_handles.add(self)
+
+    def close(self):
+        """Frees the device metal mesh (metal_destroy)."""
+        if getattr(self, "_h", None) is not None:
+            h, self._h = self._h, None
+            _open_handles.discard(self)
+            load_library().metal_destroy(h)
 
     def __del__(self):
-        if getattr(self, "_h", None) and _lib is not None:
-            _lib.metal_destroy(self._h)
-            self._h = None
+        if _finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
 
     def continuity_solve(self, sigma, flux, phi=None, tol=1e-12,
                          max_iter=100_000, joule=True):
         """Phi of Eq. cont_mat (device f64 tensors sigma [n_tets], flux
         [n_faces]); returns (Phi, P_J or None, stats dict)."""
+        specs = [(sigma, "float64", self.n_tets, "sigma")]
+        if self.n_faces:
+            specs.append((flux, "float64", self.n_faces, "flux"))
+        if phi is not None:
+            specs.append((phi, "float64", self.n_nodes, "phi"))
+        _dev_arrays(*specs)
         torch = _torch()
         if phi is None:
             phi = torch.zeros(self.n_nodes, dtype=torch.float64,
@@ -816,6 +906,13 @@ class Metal:
                   T_amb=300.0, tol=1e-12, max_iter=100_000):
         """One step of Eq. heat_theta2 in place on T (device f64 [n_nodes]);
         returns the solver stats."""
+        specs = [(T, "float64", self.n_nodes, "T"),
+                 (sigma, "float64", self.n_tets, "sigma")]
+        if P_J is not None:
+            specs.append((P_J, "float64", self.n_tets, "P_J"))
+        if self.n_faces:
+            specs.append((P_N, "float64", self.n_faces, "P_N"))
+        _dev_arrays(*specs)
         torch = _torch()
         prm = HeatParams(float(Cv), float(L), float(dt), float(theta),
                          float(T_amb), float(tol), int(max_iter))

@@ -129,3 +129,44 @@ def test_metal_rejects_null():
     hp = pic.HeatParams(1.0, 2e-8, 1.0, 1.0, 300.0, 1e-10, 10)
     assert L.heat_step(None, C.byref(hp), None, None, None, None, None,
                        None) == pic.PIC_E_ARG
+
+
+def test_binding_rejects_bad_arrays_before_the_library():
+    """The binding checks dtype, length, contiguity and device of every
+    array it passes to the metal solves and the single calls before
+    anything is enqueued (a float32 temperature or a short conductivity
+    would otherwise be read and written out of bounds by the kernels).
+    Runs on the host: every case fails before the library is called."""
+    import torch
+    from paper_1906_08125_amd import pic
+
+    m = pic.Metal.__new__(pic.Metal)
+    m.n_nodes, m.n_tets, m.n_faces, m._h = 10, 20, 4, None
+    f64 = lambda n: torch.zeros(n, dtype=torch.float64)
+    with pytest.raises(TypeError, match="T: dtype float32"):
+        m.heat_step(torch.full((10,), 300.0), f64(20), None, f64(4),
+                    1.0, 1.0, 1.0)
+    with pytest.raises(ValueError, match="sigma: 19 elements"):
+        m.heat_step(f64(10), f64(19), None, f64(4), 1.0, 1.0, 1.0)
+    with pytest.raises(ValueError, match="P_N: 3 elements"):
+        m.heat_step(f64(10), f64(20), f64(20), f64(3), 1.0, 1.0, 1.0)
+    with pytest.raises(ValueError, match="not contiguous"):
+        m.heat_step(f64(20)[::2], f64(20), None, f64(4), 1.0, 1.0, 1.0)
+    with pytest.raises(TypeError, match="HIP device"):
+        m.heat_step(f64(10), f64(20), None, f64(4), 1.0, 1.0, 1.0)
+    with pytest.raises(TypeError, match="flux: dtype int64"):
+        m.continuity_solve(f64(20), torch.zeros(4, dtype=torch.int64))
+    with pytest.raises(ValueError, match="phi: 9 elements"):
+        m.continuity_solve(f64(20), f64(4), phi=f64(9))
+    g = pic.Mesh.__new__(pic.Mesh)
+    g.n_nodes, g._h = 7, None
+    with pytest.raises(TypeError, match="E .*dtype float32"):
+        g.emission_rate(torch.zeros(28, dtype=torch.float32), 4.5)
+    with pytest.raises(ValueError, match="phi: 6 elements"):
+        g.poisson_solve(None, 0.0, 0.5, f64(6))
+    with pytest.raises(TypeError, match="tet: dtype int64"):
+        g.deposit(f64(3), f64(3), f64(3), torch.zeros(3, dtype=torch.int64),
+                  f64(3), torch.zeros(7, dtype=torch.int64))
+    with pytest.raises(TypeError, match="where_out: dtype int32"):
+        g.locate(f64(3), f64(3), f64(3), torch.zeros(3, dtype=torch.int32),
+                 torch.zeros(3, dtype=torch.int32))

@@ -182,6 +182,77 @@ def test_cell_field_of_linear_potential(small_tip_mesh, tiny_mesh):
         assert np.abs(En[:, 2] + 2.0).max() <= 1e-12
 
 
+def _interior_patch_nodes(mesh, om):
+    """Nodes whose patch is the full 24-tet Kuhn star and does not cross the
+    lateral seam (every incident tet has its vertices at the nodes' own,
+    wrapped coordinates)."""
+    T = om.tets()
+    inner = np.all(T["vert"] == mesh.xyz[T["tet"]], axis=(1, 2))
+    count = np.bincount(T["tet"].reshape(-1), minlength=mesh.n_nodes)
+    bad = np.zeros(mesh.n_nodes, bool)
+    bad[T["tet"][~inner].reshape(-1)] = True
+    return np.nonzero((count == 24) & ~bad)[0]
+
+
+def test_nodal_field_of_quadratic_potential(tiny_mesh):
+    """Reading R2 (Sec. II B 2): the nodal field is the volume-weighted mean
+    of -grad phi over the tets holding the node.  For any quadratic q the
+    element gradient of its P1 interpolant is grad q at the tet centroid
+    plus a shape term that changes sign under the point reflection about a
+    vertex; the Kuhn star of an interior vertex is symmetric under that
+    reflection with equal volumes, so the recovered field there is exactly
+    -grad q(vertex).  A linear q (the older pin) cannot tell the nodes of a
+    tet apart; a quadratic one can."""
+    om = O.OracleMesh(tiny_mesh, 0.01)
+    nodes = _interior_patch_nodes(tiny_mesh, om)
+    assert nodes.size > 0.5 * tiny_mesh.n_nodes
+    x, y, z = tiny_mesh.xyz.T
+    # q = z^2 (the closed form of the plates' space-charge potential) and a
+    # full quadratic with mixed terms
+    cases = [(z * z, lambda p: np.stack([0 * p[:, 0], 0 * p[:, 0], 2 * p[:, 2]], 1)),
+             (0.3 * x * x - 0.2 * y * y + 0.7 * z * z + 0.5 * x * y
+              - 0.4 * y * z + 0.25 * x * z + 1.5 * x - 0.5 * z,
+              lambda p: np.stack([0.6 * p[:, 0] + 0.5 * p[:, 1] + 0.25 * p[:, 2] + 1.5,
+                                  -0.4 * p[:, 1] + 0.5 * p[:, 0] - 0.4 * p[:, 2],
+                                  1.4 * p[:, 2] - 0.4 * p[:, 1] + 0.25 * p[:, 0] - 0.5], 1))]
+    for q, grad in cases:
+        E = om.field(q)
+        want = -grad(tiny_mesh.xyz[nodes])
+        err = np.abs(E[nodes] - want).max()
+        assert err <= 1e-13 * max(1.0, np.abs(want).max()), err
+
+
+def test_nodal_field_graded_mesh_weights():
+    """Volume weights of the nodal field (reading R2) on a mesh whose layers
+    have unequal heights (so tets above and below a node differ in volume):
+    every tet of layer k (between z_k and z_k+1) interpolates phi = z^2 by
+    the linear function with slope z_k + z_k+1, and half of a Kuhn star lies
+    in each layer, so the volume-weighted mean at an interior node of level
+    k is -(z_k-1 + z_k+1) e_z, at the bottom and top levels -(z_0 + z_1) and
+    -(z_n-1 + z_n).  An unweighted mean would give -(z_k-1 + 2 z_k +
+    z_k+1)/2 instead."""
+    mesh = W.kuhn_tip_mesh(4, 4, 8, 0.5)
+    g = np.random.default_rng(5)
+    levels = np.concatenate([[0.0], np.cumsum(g.uniform(0.25, 0.9, mesh.nz))])
+    k = np.rint(mesh.xyz[:, 2] / mesh.h).astype(int)
+    xyz = mesh.xyz.copy()
+    xyz[:, 2] = levels[k]
+    import dataclasses
+    gm = dataclasses.replace(mesh, xyz=xyz, z_top=float(levels[-1]))
+    om = O.OracleMesh(gm, 0.01)
+    E = om.field(xyz[:, 2] ** 2)
+    zl = levels
+    want = np.where(k == 0, -(zl[0] + zl[1]),
+                    np.where(k == mesh.nz, -(zl[-2] + zl[-1]),
+                             -(zl[np.clip(k - 1, 0, None)] + zl[np.clip(k + 1, None, mesh.nz)])))
+    assert np.abs(E[:, :2]).max() <= 1e-13
+    assert np.abs(E[:, 2] - want).max() <= 1e-13 * np.abs(want).max()
+    inner = (k > 0) & (k < mesh.nz)
+    unweighted = -(zl[np.clip(k - 1, 0, None)] + 2 * zl[k]
+                   + zl[np.clip(k + 1, None, mesh.nz)]) / 2
+    assert np.abs(unweighted - want)[inner].min() > 1e-6
+
+
 def test_cell_mode_emission_uses_the_face_tet(small_tip_mesh):
     """Cell mode emission: every emitting face sees the field of its own
     vacuum tet.  With phi = -4 z^2 (a field growing with height, so that
@@ -379,6 +450,58 @@ def test_fn_current_limits():
     y = np.log([O.fn_current(x, phi)[0] / x**2 for x in F])
     slope = np.polyfit(1 / F, y, 1)[0]
     assert -1.0 < slope / (k["b_fn"] * phi**1.5) < -0.9
+
+
+def _sn_barrier_functions(f):
+    """Exact Schottky-Nordheim barrier functions (Forbes and Deane, Proc. R.
+    Soc. A 463 (2007) 2907): with l = sqrt(f) and elliptic parameter
+    m = (1 - l)/(1 + l), v(f) = sqrt(1 + l) (E(m) - l K(m)), and
+    t(f) = v - (4/3) f dv/df (Richardson-extrapolated central difference)."""
+    from scipy.special import ellipe, ellipk
+
+    def v(f):
+        l = np.sqrt(f)
+        m = (1 - l) / (1 + l)
+        return np.sqrt(1 + l) * (ellipe(m) - l * ellipk(m))
+    h = 1e-5
+    d1 = (v(f + h) - v(f - h)) / (2 * h)
+    d2 = (v(f + 2 * h) - v(f - 2 * h)) / (4 * h)
+    return v(f), v(f) - 4.0 / 3.0 * f * (4 * d1 - d2) / 3
+
+
+def _oracle_v_t(f):
+    """v(f) and t(f) as the oracle's FN current uses them, recovered from
+    two currents at the same scaled field f but different work functions:
+    ln(J phi / (a F^2)) = -2 ln t - v b phi^1.5 / F is linear in (ln t, v)."""
+    k = O.constants()
+    ys, cs = [], []
+    for phi in (4.5, 2.0):
+        F = f * phi * phi / k["c_s"]
+        j, clamped = O.fn_current(F, phi)
+        assert not clamped
+        ys.append(math.log(j * phi / (k["a_fn"] * (F * 1e9) ** 2)))
+        cs.append(k["b_fn"] * phi ** 1.5 / F)
+    v = -(ys[0] - ys[1]) / (cs[0] - cs[1])
+    return v, math.exp(-(ys[0] + v * cs[0]) / 2)
+
+
+def test_fn_barrier_functions_against_exact_sn():
+    """The Murphy-Good current (Sec. II B 3; GETELEC stands in the paper)
+    takes Forbes' approximations of the Schottky-Nordheim v(f) and t(f).
+    The oracle's v and t, read back from its currents, lie within the
+    approximations' own deviation from the exact elliptic-integral functions
+    over 0.05 <= f <= 0.95 (at most 0.33 % for v, 0.39 % for t); a dropped
+    log term or a swapped sign exceeds it many times over."""
+    fs = np.linspace(0.05, 0.95, 19)
+    v_ex, t_ex = _sn_barrier_functions(fs)
+    for f, ve, te in zip(fs, v_ex, t_ex):
+        vo, to = _oracle_v_t(float(f))
+        assert abs(vo / ve - 1) <= 0.0034, (f, vo, ve)
+        assert abs(to / te - 1) <= 0.0040, (f, to, te)
+    # the bounds are tight enough to reject the plausible slips
+    assert np.abs((1 - fs) / v_ex - 1).max() > 0.03          # no log term
+    assert np.abs((1 - fs - fs / 6 * np.log(fs)) / v_ex - 1).max() > 0.03
+    assert np.abs((1 + fs / 9 + fs / 18 * np.log(fs)) / t_ex - 1).max() > 0.01
 
 
 def _face_field_state(mesh, E0=5.0, emit_zmin=-1.0):
