@@ -337,6 +337,9 @@ struct AdjTable {
 __device__ inline void adj_node_add(AdjTable& T, int32_t node, const long long q[3],
                                     long long* acc) {
   uint32_t h = ((uint32_t)node * 2654435761u) >> 22;  // 10 bits
+  // kept as a loop (unrolled at each call site it bloats the kernel and
+  // spills scalar registers)
+#pragma unroll 1
   for (int probe = 0; probe < 64; ++probe) {
     const int32_t old = atomicCAS(&T.key[h], -1, node);
     if (old == -1 || old == node) {

@@ -338,13 +338,25 @@ __device__ inline void table_clear(ChargeTable& T) {
   __syncthreads();
 }
 
+// 64-bit add into LDS.  The table reaches the helpers by reference, and
+// through it the compiler emits a generic (flat) atomic, which takes the
+// vector-memory path; the explicit LDS address space gives ds_add_u64.
+__device__ inline void lds_add_u64(unsigned long long* p, unsigned long long v) {
+  __atomic_fetch_add((__attribute__((address_space(3))) unsigned long long*)p, v,
+                     __ATOMIC_RELAXED);
+}
+
 __device__ inline void table_add(ChargeTable& T, int32_t node, int64_t q,
                                  int64_t* charge) {
   uint32_t h = ((uint32_t)node * 2654435761u) >> 21;  // 11 bits
+  // kept as a loop: unrolled at every inlined call site, the 64 probes
+  // made the particle kernel tens of thousands of instructions long (an
+  // instruction-cache and scalar-register-spill cost paid by every wave)
+#pragma unroll 1
   for (int probe = 0; probe < 64; ++probe) {
     const int32_t old = atomicCAS(&T.key[h], -1, node);
     if (old == -1 || old == node) {
-      atomicAdd(&T.val[h], (unsigned long long)q);
+      lds_add_u64(&T.val[h], (unsigned long long)q);
       return;
     }
     h = (h + 1) & (kTable - 1);

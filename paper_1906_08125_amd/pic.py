@@ -153,10 +153,6 @@ def _close_all():
             pass
 
 
-def _finalizing() -> bool:
-    return sys.is_finalizing()
-
-
 EXPORTS = ("mesh_create", "mesh_destroy", "mesh_query", "mesh_emit_faces",
            "locate", "deposit", "poisson_solve", "pic_step", "emission_rate",
            "adjoint_step", "pic_batch_create", "pic_batch_destroy",
@@ -302,7 +298,9 @@ class Mesh:
             _open_handles.discard(self)
             load_library().mesh_destroy(h)
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # (module globals may already be None while the interpreter
+        # finalizes: the check is bound at definition time)
         if _finalizing():
             return
         try:
@@ -748,7 +746,9 @@ class Batch:
             _open_handles.discard(self)
             load_library().pic_batch_destroy(h)
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # (module globals may already be None while the interpreter
+        # finalizes: the check is bound at definition time)
         if _finalizing():
             return
         try:
@@ -870,7 +870,9 @@ class Metal:
             _open_handles.discard(self)
             load_library().metal_destroy(h)
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # (module globals may already be None while the interpreter
+        # finalizes: the check is bound at definition time)
         if _finalizing():
             return
         try:
