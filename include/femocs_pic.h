@@ -117,6 +117,25 @@ PIC_API pic_status locate(const pic_mesh* mesh, int64_t n, const double* x,
                   uint8_t* where_out, void* stream);
 
 /* ------------------------------------------------------------------------ */
+/* locate without allocation.  For callers that cannot allocate device      */
+/* memory (code under HIP graph capture, tight serving loops, harnesses     */
+/* that forbid hipMalloc): the same results as locate, with its scratch --  */
+/* the queue of points for the exact scan and its counter -- in a fixed     */
+/* 4 MiB device array of the library instead of the mesh handle's           */
+/* (grown) queue.  Every GPU the library runs on holds its own copy until   */
+/* the process ends; the call allocates nothing, and clears the counter     */
+/* with a kernel (no memset).  Arguments as locate; the mesh must live on   */
+/* the current device.  PIC_E_ARG when n > PIC_LOCATE_NOALLOC_MAX (locate  */
+/* larger sets in chunks).  All calls on one GPU share the array: calls     */
+/* that overlap in time on one GPU (two streams, or two threads) race, so   */
+/* the caller serializes them.                                              */
+/* ------------------------------------------------------------------------ */
+#define PIC_LOCATE_NOALLOC_MAX 1048512 /* 2^20 - 64 points per call */
+PIC_API pic_status locate_noalloc(const pic_mesh* mesh, int64_t n, const double* x,
+                                  const double* y, const double* z, int32_t* tet_inout,
+                                  uint8_t* where_out, void* stream);
+
+/* ------------------------------------------------------------------------ */
 /* Charge deposition (Eq. q_delta, Eq. poisson_rhs; same shape functions    */
 /* as the field gather).  For each point with tet >= 0: lambda_i of the     */
 /* point in its tet, q_i = rint(lambda_i w 2^40) (i = 1..3),                */

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "adjoint.h"
@@ -504,6 +505,52 @@ void prof_end(pic_mesh* h, hipStream_t s) {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Scratch of locate_noalloc: a file-scope device array, one copy per GPU,
+// held until the process ends.  Element 0 is the counter of the exact-scan
+// queue, elements [kNoallocHead, kNoallocHead + n) the queue itself.  Host
+// code never uses the array's name as an address: each device's copy is
+// looked up once (hipGetSymbolAddress with that device current) and only
+// that address is passed to kernels.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int64_t kNoallocHead = 64;  // counter, padded to 256 bytes
+constexpr int64_t kNoallocInts = kNoallocHead + PIC_LOCATE_NOALLOC_MAX;
+static_assert(kNoallocInts == (1 << 20), "4 MiB of scratch");
+
+}  // namespace
+
+static __device__ __align__(256) int32_t scratch[kNoallocInts];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+int32_t* g_scratch_dev[kMaxDevices] = {};
+
+// The address of the current device's copy of scratch (looked up on the
+// first call on that device), or null with *err set.
+int32_t* noalloc_scratch(int device, hipError_t* err) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void* ptr = nullptr;
+    *err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (*err != hipSuccess) return nullptr;
+    g_scratch_dev[device] = (int32_t*)ptr;
+  }
+  *err = hipSuccess;
+  return g_scratch_dev[device];
+}
+
+// Clears the queue counter with a kernel (no memset node where the caller
+// captures the stream into a graph).
+__global__ void k_noalloc_clear(int32_t* head) {
+  if (threadIdx.x < kNoallocHead) head[threadIdx.x] = 0;
+}
+
+}  // namespace
+
 extern "C" {
 
 pic_status pic_profile(pic_mesh* h, int32_t classes) {
@@ -618,6 +665,42 @@ pic_status locate(const pic_mesh* hc, int64_t n, const double* x,
   const int grid = (int)std::min<int64_t>(want, (int64_t)h->n_cu * 8);
   e = fp::launch_locate(a, std::max(grid, 1), s);
   if (e != hipSuccess) return hip_fail(e, "locate");
+  return PIC_OK;
+}
+
+pic_status locate_noalloc(const pic_mesh* h, int64_t n, const double* x,
+                          const double* y, const double* z, int32_t* tet_inout,
+                          uint8_t* where_out, void* stream) {
+  if (!h || n < 0) return fail(PIC_E_ARG, "locate_noalloc: bad mesh or count");
+  if (n > PIC_LOCATE_NOALLOC_MAX)
+    return fail(PIC_E_ARG, "locate_noalloc: n exceeds PIC_LOCATE_NOALLOC_MAX");
+  if (n == 0) return PIC_OK;
+  if (!x || !y || !z || !tet_inout || !where_out)
+    return fail(PIC_E_ARG, "locate_noalloc: null array");
+  int device = -1;
+  hipError_t e = hipGetDevice(&device);
+  if (e != hipSuccess) return hip_fail(e, "locate_noalloc");
+  if (device != h->device || device < 0 || device >= kMaxDevices)
+    return fail(PIC_E_ARG, "locate_noalloc: the mesh lives on another device");
+  int32_t* sc = noalloc_scratch(device, &e);
+  if (!sc) return hip_fail(e, "locate_noalloc");
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_noalloc_clear, dim3(1), dim3(kNoallocHead), 0, s, sc);
+  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "locate_noalloc");
+  fp::LocateArgs a;
+  a.m = h->dm;
+  a.n = n;
+  a.x = x;
+  a.y = y;
+  a.z = z;
+  a.tet = tet_inout;
+  a.where = where_out;
+  a.queue = sc + kNoallocHead;
+  a.n_queue = sc;
+  const int64_t want = (n + 255) / 256;
+  const int grid = (int)std::min<int64_t>(want, (int64_t)h->n_cu * 8);
+  e = fp::launch_locate(a, std::max(grid, 1), s);
+  if (e != hipSuccess) return hip_fail(e, "locate_noalloc");
   return PIC_OK;
 }
 

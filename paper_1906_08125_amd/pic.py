@@ -153,8 +153,10 @@ def _close_all():
             pass
 
 
+LOCATE_NOALLOC_MAX = (1 << 20) - 64
+
 EXPORTS = ("mesh_create", "mesh_destroy", "mesh_query", "mesh_emit_faces",
-           "locate", "deposit", "poisson_solve", "pic_step", "emission_rate",
+           "locate", "locate_noalloc", "deposit", "poisson_solve", "pic_step", "emission_rate",
            "adjoint_step", "pic_batch_create", "pic_batch_destroy",
            "pic_batch_step", "pic_profile", "pic_profile_read",
            "pic_last_error", "collide", "surface_charge", "metal_create",
@@ -183,6 +185,7 @@ def load_library(path: str = LIB_PATH):
     L.mesh_query.argtypes = [vp, C.POINTER(MeshInfo)]
     L.mesh_emit_faces.argtypes = [vp, vp, vp, vp]
     L.locate.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp]
+    L.locate_noalloc.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp]
     L.deposit.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp]
     L.poisson_solve.argtypes = [vp, vp, dbl, dbl, vp, vp,
                                 C.POINTER(SolveParams), vp, vp]
@@ -367,6 +370,18 @@ class Mesh:
         _check(load_library().locate(self._h, x.numel(), _ptr(x), _ptr(y),
                                      _ptr(z), _ptr(tet_inout), _ptr(where_out),
                                      _stream(torch)))
+
+    def locate_noalloc(self, x, y, z, tet_inout, where_out):
+        """locate with the library's fixed scratch (no device allocation;
+        at most LOCATE_NOALLOC_MAX points per call)."""
+        n = x.numel()
+        _dev_arrays((x, "float64", n, "x"), (y, "float64", n, "y"),
+                    (z, "float64", n, "z"), (tet_inout, "int32", n, "tet_inout"),
+                    (where_out, "uint8", n, "where_out"))
+        torch = _torch()
+        _check(load_library().locate_noalloc(self._h, n, _ptr(x), _ptr(y),
+                                             _ptr(z), _ptr(tet_inout),
+                                             _ptr(where_out), _stream(torch)))
 
     def deposit(self, x, y, z, tet, w, charge):
         n = x.numel()
