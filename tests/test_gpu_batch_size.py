@@ -1,0 +1,85 @@
+"""Parity at the batched workload's own size (the ensemble of seeded,
+independent tips the paper averages over, Sec. III B): four of the 32
+uneven instances of the batch workload -- the largest grid (62 x 62 x 124
+cubes, 2.8M tets, the largest among the 32 draws), the largest population
+(target 9.0e5 superparticles), the smallest grid and the smallest
+population -- advanced together by pic_batch_step in mixed precision with
+the default schedule, 41 steps from the empty gap (re-sorts included).
+After the last batched step each instance is checked against the oracle
+with the production-size checks: one step of 3,000 sampled superparticles
+replayed by the oracle (FP32 bound), the oracle's canonical location of
+the survivors (bit-exact), the oracle's deposition of every live
+superparticle (bit-exact), the true residual of the potential under the
+oracle's K, and the oracle's nodal field of the device potential."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1906_08125_amd import workloads as W
+from tests.production_checks import fields_and_charge, host, replay_sample
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def batch():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1906_08125_amd import pic
+    pic.load_library()
+    cfgs = W.batch_configs(32, seed=4)
+    nx = [c.nx * 100 + i for i, c in enumerate(cfgs)]
+    nt = [c.n_target for c in cfgs]
+    pick = []
+    for i in (int(np.argmax(nx)), int(np.argmax(nt)), int(np.argmin(nx)),
+              int(np.argmin(nt))):
+        if i not in pick:
+            pick.append(i)
+    inst = []
+    for i in pick:
+        c = cfgs[i]
+        tip = c.mesh()
+        gm = pic.Mesh(tip, c.emit_zmin)
+        phi = torch.zeros(gm.n_nodes, dtype=torch.float64, device="cuda")
+        E = torch.zeros(4 * gm.n_nodes, dtype=torch.float64, device="cuda")
+        gm.poisson_solve(None, 0.0, c.E0, phi, E, tol=c.tol)
+        rate, _ = gm.emission_rate(E, c.phi_w)
+        w_sp = rate.item() * c.dt * c.transit_steps / c.n_target
+        st = pic.State(gm, int(2.5 * c.n_target) + 50_000,
+                       precision=pic.PIC_MIXED)
+        st.init_field(c.E0, tol=c.tol)
+        kw = dict(dt=c.dt, E0=c.E0, w_sp=w_sp, phi_w=c.phi_w, seed=c.seed,
+                  instance=i, tol=c.tol, resort_every=10)
+        inst.append(dict(cfg=c, tip=tip, gm=gm, st=st, kw=kw))
+        del phi, E
+    b = pic.Batch([d["gm"] for d in inst], [d["st"] for d in inst],
+                  [d["kw"] for d in inst])
+    b.step(0, 40)
+    torch.cuda.synchronize()
+    A = [host(d["st"]) for d in inst]
+    rows = pic.Batch.decode(b.step(40, 1), len(inst))[0]
+    B = [host(d["st"]) for d in inst]
+    yield pic, inst, A, B, rows
+    b.close()
+    for d in inst:
+        d["gm"].close()
+
+
+def test_batch_instances_at_size(batch):
+    pic, inst, A, B, rows = batch
+    assert inst[0]["tip"].nx == max(c.nx for c in W.batch_configs(32, seed=4))
+    for d, a, b, r in zip(inst, A, B, rows):
+        c, tip = d["cfg"], d["tip"]
+        om = O.OracleMesh(tip, c.emit_zmin)
+        live = int((b["tet"] >= 0).sum())
+        print(f"{c.name}: {tip.nx}x{tip.ny}x{tip.nz}, {tip.n_tets} tets, "
+              f"{live} live (target {c.n_target}), status {r['status']}",
+              flush=True)
+        assert r["status"] == 0
+        assert live > 0.3 * c.n_target
+        fields_and_charge(om, c, d["kw"], b, 1e-6)
+        n, s = replay_sample(om, tip, c.dt, a, b, 1e-6)
+        print(f"  replayed {n}, survivors {s}", flush=True)
+        del om

@@ -99,3 +99,40 @@ def test_surface_charge_no_faces(setup):
     Q, q = g0.surface_charge(at, E=E)
     q_host = q.cpu().numpy()
     assert Q.numel() == 0 and q_host.size == len(atoms) and (q_host == 0).all()
+
+
+@pytest.mark.parametrize("cell", [False, True], ids=["nodal", "cell"])
+def test_surface_charge_production_size(cell):
+    """Every metal face of the production tip (13,124 faces) to its seeded
+    surface atoms (6,245): the full-size path (faces beyond one face per
+    workgroup, the atom pass split over many face ranges) against the
+    oracle on the same field, to 1e-12."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1906_08125_amd import pic
+    pic.load_library()
+    cfg = W.config_production()
+    tip = cfg.mesh()
+    om = O.OracleMesh(tip, -1.0)
+    gm = pic.Mesh(tip, -1.0)
+    assert gm.n_emit == om.n_emit == 13124
+    gs = pic.State(gm, 4)
+    gs.init_field(cfg.E0, tol=1e-12)
+    torch.cuda.synchronize()
+    E3 = gs.E.cpu().numpy().reshape(-1, 4)[:, :3].copy()
+    phi = gs.phi.cpu().numpy()
+    atoms = W.surface_atoms(tip, density=4.0)
+    assert len(atoms) == 6245
+    Qo, qo = om.surface_charge(E3, atoms, r_c=0.1, phi=phi if cell else None)
+    ad = torch.from_numpy(atoms).cuda()
+    if cell:
+        Qg, qg = gm.surface_charge(ad, r_c=0.1, phi=gs.phi)
+    else:
+        Qg, qg = gm.surface_charge(ad, r_c=0.1, E=gs.E)
+    Qg, qg = Qg.cpu().numpy(), qg.cpu().numpy()
+    print("faces rel", _rel(Qg, Qo), "atoms rel", _rel(qg, qo))
+    assert _rel(Qg, Qo) < 1e-12
+    assert _rel(qg, qo) < 1e-12
+    assert abs(qg.sum() / Qg.sum() - 1) < 1e-12
+    del gs
+    gm.close()

@@ -28,6 +28,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_1906_08125_amd import workloads as W
+from tests.production_checks import fields_and_charge, host, replay_sample
 
 pytestmark = pytest.mark.gpu
 
@@ -62,41 +63,13 @@ def setup(request, prod):
     return pic, cfg, om, gm, gs, kw, (1e-6 if request.param == "mixed" else 1e-12)
 
 
-def _host(gs):
-    n = int(gs.n_slots.item())
-    g = lambda t: t[:n].cpu().numpy().astype(np.float64)
-    i = lambda t: t[:n].cpu().numpy()
-    return dict(n=n, x=g(gs.x), y=g(gs.y), z=g(gs.z), vx=g(gs.vx), vy=g(gs.vy),
-                vz=g(gs.vz), w=g(gs.w), tet=i(gs.tet), id=i(gs.id),
-                phi=gs.phi.cpu().numpy(),
-                E=gs.E.cpu().numpy().astype(np.float64).reshape(-1, 4)[:, :3],
-                charge=gs.charge.cpu().numpy())
-
-
-def _fields_and_charge(om, cfg, kw, S, ftol):
-    live = S["tet"] >= 0
-    p = np.stack([S["x"], S["y"], S["z"]], 1)[live]
-    c = om.deposit(p, S["tet"][live], S["w"][live])
-    assert np.array_equal(c, S["charge"])
-    q = np.rint(S["w"][live] * 2.0**40).astype(np.int64)
-    assert int(S["charge"].sum()) == int(q.sum())
-    fid, _ = om.free()
-    free = np.flatnonzero(fid >= 0)
-    free = free[np.argsort(fid[free])]
-    b = om.rhs(S["charge"], kw["w_sp"], cfg.E0)
-    r = b - om.spmv(S["phi"][free])
-    assert np.linalg.norm(r) <= 1.5 * cfg.tol * np.linalg.norm(b)
-    E = om.field(S["phi"])
-    assert np.linalg.norm(E - S["E"]) <= ftol * np.linalg.norm(E)
-
-
 def test_production_step_sampled(setup):
     pic, cfg, om, gm, gs, kw, ftol = setup
     cell = kw["field_mode"] == pic.PIC_FIELD_CELL
-    A = _host(gs)
+    A = host(gs)
     srow = pic.State.decode_stats(gs.step(step0=50, n_steps=1, **kw))[0]
-    B = _host(gs)
-    _fields_and_charge(om, cfg, kw, B, ftol)
+    B = host(gs)
+    fields_and_charge(om, cfg, kw, B, ftol)
     # emission rate of the field the step started from
     if cell:
         r_or, _ = om.emission_rate(A["E"], cfg.phi_w, phi=A["phi"])
@@ -107,65 +80,7 @@ def test_production_step_sampled(setup):
             cfg.phi_w)
         r_or, _ = om.emission_rate(A["E"], cfg.phi_w)
         assert abs(r_dev.item() - r_or) <= ftol * r_or
-    Et = om.cell_field(A["phi"]) if cell else None
-    # one step of 3000 sampled pre-step superparticles
-    live = np.flatnonzero(A["tet"] >= 0)
-    rng = np.random.default_rng(11)
-    pick = rng.choice(live, size=min(3000, live.size), replace=False)
-    where_b = {int(i): k for k, i in enumerate(B["id"]) if B["tet"][k] >= 0}
-    k_ = O.constants()
-    Q = (k_["qm"] * cfg.dt) * 0.5
-    Lx, Ly, ztop = gm.tip.Lx, gm.tip.Ly, gm.tip.z_top
-    tets = om.tets()
-    nodes = tets["tet"]
-    survivors = []
-    # FP32 storage can put a particle on the other side of a decision
-    # boundary (anode plane, lateral wrap, metal surface) than the FP64
-    # replay when it lies within rounding of it: counted, none allowed
-    # in FP64, a few in mixed precision
-    mism = 0
-    for i in pick:
-        p = np.array([A["x"][i], A["y"][i], A["z"][i]])
-        v = np.array([A["vx"][i], A["vy"][i], A["vz"][i]])
-        t = int(A["tet"][i])
-        if cell:
-            E = Et[t]
-        else:
-            lam = om.lam(t, p)
-            e = A["E"][nodes[t]]
-            E = ((lam[0] * e[0] + lam[1] * e[1]) + lam[2] * e[2]) + lam[3] * e[3]
-        qE = Q * E
-        v = (v + qE) + qE
-        p = p + cfg.dt * v
-        if p[0] >= Lx:
-            p[0] -= Lx
-        elif p[0] < 0.0:
-            p[0] += Lx
-        if p[1] >= Ly:
-            p[1] -= Ly
-        elif p[1] < 0.0:
-            p[1] += Ly
-        k = where_b.get(int(A["id"][i]))
-        if p[2] >= ztop:  # anode-absorbed on the device too
-            mism += k is not None
-            continue
-        if k is None:  # absorbed by the cathode: outside every vacuum tet
-            tt, wh = om.locate(p[None, :])
-            mism += not (tt[0] < 0 and wh[0] == 2)
-            continue
-        q = np.array([B["x"][k], B["y"][k], B["z"][k]])
-        if np.abs(q - p).max() > ftol * max(1.0, np.abs(p).max()):
-            mism += 1  # (wrapped on the other side)
-            continue
-        assert np.abs(np.array([B["vx"][k], B["vy"][k], B["vz"][k]]) - v).max() \
-            <= ftol * max(1.0, np.abs(v).max())
-        survivors.append(k)
-    assert mism <= (0 if ftol < 1e-9 else 3), mism
-    assert len(survivors) > 0.9 * len(pick)
-    ks = np.array(survivors)
-    pts = np.stack([B["x"][ks], B["y"][ks], B["z"][ks]], 1)
-    tt, wh = om.locate(pts)
-    assert np.array_equal(tt, B["tet"][ks])
+    replay_sample(om, gm.tip, cfg.dt, A, B, ftol, cell=cell)
 
 
 def test_production_multi_step_call(setup):
@@ -173,10 +88,10 @@ def test_production_multi_step_call(setup):
     pic, cfg, om, gm, gs, kw, ftol = setup
     gs.step(step0=51, n_steps=9, **kw)   # steps 51..59: (59 + 1) % 10 == 0
     torch.cuda.synchronize()
-    C = _host(gs)
+    C = host(gs)
     assert (C["tet"] >= 0).all() and (np.diff(C["tet"]) >= 0).all()
     assert C["n"] > 500_000
-    _fields_and_charge(om, cfg, kw, C, ftol)
+    fields_and_charge(om, cfg, kw, C, ftol)
     # canonical location of a sample after the multi-step call
     rng = np.random.default_rng(12)
     ks = rng.choice(C["n"], size=3000, replace=False)
