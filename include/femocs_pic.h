@@ -11,8 +11,10 @@
  *  Memory: "host" pointers are read during the call only; "device" pointers
  *    are HIP device memory owned by the caller.  The library never frees
  *    caller memory.  mesh_create allocates the mesh's own device arrays
- *    (freed by mesh_destroy); pic_step grows a per-handle particle scratch
- *    on the first call with a larger capacity and allocates nothing after.
+ *    (freed by mesh_destroy), mesh_create_in places them in a caller
+ *    workspace sized by mesh_workspace_bytes; pic_step grows a per-handle
+ *    particle scratch on the first call with a larger capacity and
+ *    allocates nothing after.
  *  Streams: `stream` is a hipStream_t passed as void*; NULL is the null
  *    stream.  Every call only enqueues work on that stream (mesh_create and
  *    mesh_destroy synchronize it); results land in device memory.  One mesh
@@ -96,6 +98,20 @@ typedef struct {
  * everything to the current device.  PIC_E_MESH for out-of-range node ids,
  * zero-volume or non-manifold elements.  *out receives the handle. */
 PIC_API pic_status mesh_create(const pic_mesh_desc* desc, void* stream, pic_mesh** out);
+/* The same set-up with the mesh's persistent device arrays (the element     */
+/* records, K and the field operator, face and bucket data, the solver's    */
+/* vectors) placed in a caller-owned workspace: mesh_workspace_bytes runs   */
+/* the host part of the set-up (seconds at millions of tets) and returns    */
+/* the bytes needed; mesh_create_in takes a device workspace of at least    */
+/* that size, 256-byte aligned (hipMalloc's alignment), which must outlive  */
+/* the handle -- mesh_destroy does not free it.  PIC_E_ARG when it is too   */
+/* small or misaligned.  Not in the workspace: the per-call scratch that    */
+/* pic_step, collide, surface_charge and adjoint_step grow on the first     */
+/* call with a larger capacity, the AMG hierarchy (built on the first AMG   */
+/* solve), and the pinned host record of the solver's convergence report.   */
+PIC_API pic_status mesh_workspace_bytes(const pic_mesh_desc* desc, size_t* bytes);
+PIC_API pic_status mesh_create_in(const pic_mesh_desc* desc, void* workspace,
+                                  size_t ws_bytes, void* stream, pic_mesh** out);
 PIC_API pic_status mesh_destroy(pic_mesh* mesh);
 PIC_API pic_status mesh_query(const pic_mesh* mesh, pic_mesh_info* info);
 /* Host copies of the emitting faces: owner tet, node ids (3 per face),
@@ -348,6 +364,26 @@ PIC_API pic_status adjoint_step(pic_mesh* mesh, const pic_particles* pre,
                         const pic_fields* Fk1, const pic_step_params* params,
                         const pic_adjoint* adj, pic_solve_stats* stats,
                         void* stream);
+
+/* The forward side of the window objective above, so that a caller        */
+/* composes a window from library calls only:                               */
+/* window_objective adds one step's terms to J (device [3] f64): J[0] +=    */
+/* w_sp q_anode 2^-40 (stats->q_anode: the step's collected fixed-point    */
+/* charge), J[1] += (1/T) times the mean over the emitting faces of |E| at  */
+/* the face centroid, E_f = ((E_a + E_b) + E_c) / 3 of the post-solve nodal */
+/* field E (device [4*n_nodes], f64 for PIC_FP64, f32 for PIC_MIXED), and    */
+/* sets J[2] = wQ J[0] + wE J[1].  stats: device pic_step_stats of the step. */
+/* apply_face_weights sets, for every slot below *n_slots, w = w_base s_f   */
+/* with f the slot's birth face when the slot is live (tet >= 0), else      */
+/* w = w_base (w_base, s_face: device f64 [capacity], [n_emit]): the        */
+/* multiplier s_f acts on the in-flight superparticles born at f.           */
+/* ------------------------------------------------------------------------ */
+PIC_API pic_status window_objective(const pic_mesh* mesh, const void* E, int32_t precision,
+                                    const pic_step_stats* stats, double w_sp, int32_t T,
+                                    double wQ, double wE, double* J, void* stream);
+PIC_API pic_status apply_face_weights(const pic_mesh* mesh, const pic_particles* particles,
+                                      const double* w_base, const double* s_face,
+                                      void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* Binary Monte Carlo collisions (App. F, after Takizuka and Abe): the      */

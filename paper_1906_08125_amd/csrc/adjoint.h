@@ -53,5 +53,16 @@ struct AdjArgs {
 hipError_t adj_launch_pre_solve(const AdjArgs& a, hipStream_t s);
 // after the solve of K mu = rhs: the particle reverse and the scatters
 hipError_t adj_launch_post_solve(const AdjArgs& a, hipStream_t s);
+// J[0] += w_sp q_anode 2^-40, J[1] += (mean emitting-face |E|) / T,
+// J[2] = wQ J[0] + wE J[1] (one workgroup).
+hipError_t launch_window_objective(const DevMesh& m, const void* E, int f32,
+                                   const pic_step_stats* st, double w_sp,
+                                   int T, double wQ, double wE, double* J,
+                                   hipStream_t s);
+// w[i] = w_base[i] s_face[birth[i]] for live slots, w_base[i] otherwise.
+hipError_t launch_face_weights(int64_t cap, const int32_t* n_slots,
+                               const int32_t* tet, const int32_t* birth,
+                               const double* w_base, const double* s_face,
+                               double* w, int grid, hipStream_t s);
 
 }  // namespace fp

@@ -474,4 +474,77 @@ hipError_t adj_launch_post_solve(const AdjArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Window objective and face weights (the forward side of the adjoint's
+// objective, reading R15): one workgroup sums |E| at the emitting-face
+// centroids ((E_a + E_b) + E_c) / 3 in a fixed order.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kAdjBlock) k_window_objective(
+    DevMesh m, const void* E, int f32, const pic_step_stats* st, double w_sp,
+    double inv_T, double wQ, double wE, double* J) {
+  __shared__ double lds[kAdjBlock / 64];
+  double acc = 0.0;
+  for (int64_t f = threadIdx.x; f < m.n_emit; f += blockDim.x) {
+    const int32_t* nd = m.e_nodes + 3 * f;
+    double e[3][3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if (f32) {
+        const float4 v = reinterpret_cast<const float4*>(E)[nd[k]];
+        e[k][0] = v.x;
+        e[k][1] = v.y;
+        e[k][2] = v.z;
+      } else {
+        const double4 v = reinterpret_cast<const double4*>(E)[nd[k]];
+        e[k][0] = v.x;
+        e[k][1] = v.y;
+        e[k][2] = v.z;
+      }
+    }
+    double c[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) c[d] = ((e[0][d] + e[1][d]) + e[2][d]) / 3.0;
+    acc += sqrt((c[0] * c[0] + c[1] * c[1]) + c[2] * c[2]);
+  }
+  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sum = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) sum += lds[w];
+    const double mean = m.n_emit ? sum / (double)m.n_emit : 0.0;
+    J[0] += (double)st->q_anode * (w_sp * kFxInv);
+    J[1] += mean * inv_T;
+    J[2] = wQ * J[0] + wE * J[1];
+  }
+}
+
+__global__ void __launch_bounds__(kAdjBlock) k_face_weights(
+    int64_t cap, const int32_t* n_slots, const int32_t* tet,
+    const int32_t* birth, const double* w_base, const double* s_face,
+    double* w) {
+  const int64_t n = *n_slots < cap ? *n_slots : cap;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    w[i] = tet[i] >= 0 ? w_base[i] * s_face[birth[i]] : w_base[i];
+}
+
+hipError_t launch_window_objective(const DevMesh& m, const void* E, int f32,
+                                   const pic_step_stats* st, double w_sp,
+                                   int T, double wQ, double wE, double* J,
+                                   hipStream_t s) {
+  hipLaunchKernelGGL(k_window_objective, dim3(1), dim3(kAdjBlock), 0, s, m, E,
+                     f32, st, w_sp, 1.0 / (double)T, wQ, wE, J);
+  return hipGetLastError();
+}
+
+hipError_t launch_face_weights(int64_t cap, const int32_t* n_slots,
+                               const int32_t* tet, const int32_t* birth,
+                               const double* w_base, const double* s_face,
+                               double* w, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_face_weights, dim3(grid), dim3(kAdjBlock), 0, s, cap,
+                     n_slots, tet, birth, w_base, s_face, w);
+  return hipGetLastError();
+}
+
 }  // namespace fp

@@ -606,6 +606,50 @@ pic_status mesh_create(const pic_mesh_desc* desc, void* stream, pic_mesh** out) 
   return PIC_OK;
 }
 
+pic_status mesh_workspace_bytes(const pic_mesh_desc* desc, size_t* bytes) {
+  if (!desc || !bytes) return fail(PIC_E_ARG, "mesh_workspace_bytes: null argument");
+  *bytes = 0;
+  pic_mesh* h = new pic_mesh();
+  (void)hipGetDevice(&h->device);
+  h->ws_dry = true;
+  std::string msg;
+  const pic_status s = fp::build_mesh(desc, h, msg);
+  const size_t need = h->ws_used;
+  fp::free_mesh(h);
+  delete h;
+  if (s != PIC_OK) return fail(s, msg);
+  *bytes = need;
+  return PIC_OK;
+}
+
+pic_status mesh_create_in(const pic_mesh_desc* desc, void* workspace, size_t ws_bytes,
+                          void* stream, pic_mesh** out) {
+  if (!desc || !out || !workspace)
+    return fail(PIC_E_ARG, "mesh_create_in: null argument");
+  if (((uintptr_t)workspace & 255u) != 0)
+    return fail(PIC_E_ARG, "mesh_create_in: workspace not 256-byte aligned");
+  *out = nullptr;
+  pic_mesh* h = new pic_mesh();
+  (void)hipGetDevice(&h->device);
+  h->ws_base = (char*)workspace;
+  h->ws_size = ws_bytes;
+  std::string msg;
+  const pic_status s = fp::build_mesh(desc, h, msg);
+  if (s != PIC_OK) {
+    fp::free_mesh(h);
+    delete h;
+    return fail(s, msg);
+  }
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) {
+    fp::free_mesh(h);
+    delete h;
+    return hip_fail(e, "mesh_create_in");
+  }
+  *out = h;
+  return PIC_OK;
+}
+
 pic_status mesh_destroy(pic_mesh* h) {
   if (!h) return PIC_OK;
   (void)hipDeviceSynchronize();
@@ -1122,6 +1166,40 @@ pic_status adjoint_step(pic_mesh* h, const pic_particles* pre,
   if ((e = run_solve(h, ca, 0, s, &iters)) != hipSuccess) return hip_fail(e, "adjoint_step solve");
   if ((e = fp::adj_launch_post_solve(a, s)) != hipSuccess) return hip_fail(e, "adjoint_step");
   prof_end(h, s);
+  return PIC_OK;
+}
+
+pic_status window_objective(const pic_mesh* h, const void* E, int32_t precision,
+                            const pic_step_stats* stats, double w_sp, int32_t T,
+                            double wQ, double wE, double* J, void* stream) {
+  if (!h || !E || !stats || !J) return fail(PIC_E_ARG, "window_objective: null argument");
+  if (precision != PIC_FP64 && precision != PIC_MIXED)
+    return fail(PIC_E_ARG, "window_objective: unknown precision");
+  if (T <= 0 || !finite_pos(w_sp) || !std::isfinite(wQ) || !std::isfinite(wE))
+    return fail(PIC_E_ARG, "window_objective: T > 0, w_sp > 0 and finite weights required");
+  const hipError_t e = fp::launch_window_objective(h->dm, E, precision == PIC_MIXED ? 1 : 0,
+                                                   stats, w_sp, T, wQ, wE, J,
+                                                   (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "window_objective");
+  return PIC_OK;
+}
+
+pic_status apply_face_weights(const pic_mesh* h, const pic_particles* P,
+                              const double* w_base, const double* s_face,
+                              void* stream) {
+  if (!h || !P || !w_base || !s_face)
+    return fail(PIC_E_ARG, "apply_face_weights: null argument");
+  if (P->capacity <= 0 || P->capacity >= (1ll << 31))
+    return fail(PIC_E_ARG, "apply_face_weights: capacity must be in [1, 2^31)");
+  if (!P->w || !P->tet || !P->birth || !P->n_slots)
+    return fail(PIC_E_ARG, "apply_face_weights: null particle array");
+  if (h->dm.n_emit == 0) return fail(PIC_E_ARG, "apply_face_weights: no emitting faces");
+  const int64_t want = (P->capacity + 255) / 256;
+  const int grid = (int)std::min<int64_t>(want, (int64_t)h->n_cu * 8);
+  const hipError_t e = fp::launch_face_weights(P->capacity, P->n_slots, P->tet, P->birth,
+                                               w_base, s_face, P->w, std::max(grid, 1),
+                                               (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "apply_face_weights");
   return PIC_OK;
 }
 

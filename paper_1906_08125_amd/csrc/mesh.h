@@ -11,6 +11,12 @@ struct pic_mesh {
   fp::DevMesh dm{};
   pic_mesh_info info{};
   std::vector<void*> allocs;
+  // caller workspace of mesh_create_in: the persistent device arrays are
+  // carved from it (256-byte aligned) instead of allocated; ws_dry only
+  // adds up their sizes (mesh_workspace_bytes: no device memory touched)
+  char* ws_base = nullptr;
+  size_t ws_size = 0, ws_used = 0;
+  bool ws_dry = false;
   int device = 0;
   int n_cu = 0;
   // solver scratch: b, x, r, u, w, p, s (f64) and the partial sums

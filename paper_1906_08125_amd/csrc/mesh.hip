@@ -113,29 +113,43 @@ struct FaceKey {
   bool same(const FaceKey& o) const { return hi == o.hi && lo == o.lo; }
 };
 
-template <typename T>
-T* upload(pic_mesh* h, const std::vector<T>& v, hipError_t& err) {
+// Device memory for a persistent mesh array: from the caller's workspace
+// when the handle has one (nothing when only sizes are being added up),
+// else allocated and owned by the handle.
+void* mesh_mem(pic_mesh* h, size_t bytes, hipError_t& err) {
   if (err != hipSuccess) return nullptr;
+  bytes = std::max<size_t>(bytes, 16);
+  const size_t at = (h->ws_used + 255) & ~(size_t)255;
+  if (h->ws_dry || h->ws_base) {
+    h->ws_used = at + bytes;
+    h->info.device_bytes += (int64_t)bytes;
+    if (h->ws_dry) return nullptr;
+    if (h->ws_used > h->ws_size) {
+      err = hipErrorOutOfMemory;
+      return nullptr;
+    }
+    return h->ws_base + at;
+  }
   void* p = nullptr;
-  const size_t bytes = std::max<size_t>(v.size() * sizeof(T), 16);
   err = hipMalloc(&p, bytes);
   if (err != hipSuccess) return nullptr;
   h->allocs.push_back(p);
   h->info.device_bytes += (int64_t)bytes;
-  if (!v.empty()) err = hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+  return p;
+}
+
+template <typename T>
+T* upload(pic_mesh* h, const std::vector<T>& v, hipError_t& err) {
+  void* p = mesh_mem(h, v.size() * sizeof(T), err);
+  if (p && !v.empty())
+    err = hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
   return (T*)p;
 }
 
 }  // namespace
 
 void* dev_alloc(pic_mesh* h, size_t bytes, hipError_t& err) {
-  if (err != hipSuccess) return nullptr;
-  void* p = nullptr;
-  err = hipMalloc(&p, std::max<size_t>(bytes, 16));
-  if (err != hipSuccess) return nullptr;
-  h->allocs.push_back(p);
-  h->info.device_bytes += (int64_t)bytes;
-  return p;
+  return mesh_mem(h, bytes, err);
 }
 
 pic_status build_mesh(const pic_mesh_desc* d, pic_mesh* h, std::string& msg) {
@@ -699,14 +713,17 @@ pic_status build_mesh(const pic_mesh_desc* d, pic_mesh* h, std::string& msg) {
   }
   h->cg_part = (double*)dev_alloc(h, sizeof(double) * kCgSlots * (size_t)std::max(h->cg_grid, 1), err);
   h->cg_ctrl = (CgCtrl*)dev_alloc(h, sizeof(CgCtrl), err);
-  if (err == hipSuccess)
+  // the solver's convergence report: a pinned, device-mapped host record
+  // (host metadata of the handle, also with a caller workspace)
+  if (err == hipSuccess && !h->ws_dry)
     err = hipHostMalloc((void**)&h->cg_report_host, sizeof(CgReport),
                         hipHostMallocMapped | hipHostMallocCoherent);
-  if (err == hipSuccess) {
+  if (err == hipSuccess && !h->ws_dry) {
     std::memset(h->cg_report_host, 0, sizeof(CgReport));
     err = hipHostGetDevicePointer((void**)&h->cg_report_dev, h->cg_report_host, 0);
   }
-  if (err == hipSuccess) err = hipEventCreateWithFlags(&h->rb_event, hipEventDisableTiming);
+  if (err == hipSuccess && !h->ws_dry)
+    err = hipEventCreateWithFlags(&h->rb_event, hipEventDisableTiming);
   h->scratch = (StepScratch*)dev_alloc(h, sizeof(StepScratch), err);
   h->offsets = (int32_t*)dev_alloc(h, sizeof(int32_t) * (size_t)(M.n_emit + 1), err);
   h->counts = (int32_t*)dev_alloc(h, sizeof(int32_t) * (size_t)(M.n_emit + 1), err);
@@ -722,13 +739,18 @@ pic_status build_mesh(const pic_mesh_desc* d, pic_mesh* h, std::string& msg) {
   M.lam_c = (4.01 + 1.01 * kappa) * 1.1102230246251565e-16;
   M.fseed = (int32_t*)dev_alloc(
       h, sizeof(int32_t) * (size_t)M.fnb[0] * M.fnb[1] * M.fnb[2], err);
-  if (err == hipSuccess) err = launch_seed_build(M, std::max(8, h->n_cu * 8), nullptr);
-  if (err == hipSuccess) err = hipDeviceSynchronize();
+  if (err == hipSuccess && !h->ws_dry)
+    err = launch_seed_build(M, std::max(8, h->n_cu * 8), nullptr);
+  if (err == hipSuccess && !h->ws_dry) err = hipDeviceSynchronize();
   h->grid_push = std::max(8, h->n_cu * 8);
   h->grid_inj = std::max(8, h->n_cu * 2);
   h->grid_fb = 64;
   h->acc_rows = (int64_t*)dev_alloc(
       h, sizeof(int64_t) * 16 * (size_t)(h->grid_push + h->grid_inj + h->grid_fb), err);
+  if (err == hipErrorOutOfMemory && h->ws_base) {
+    msg = "mesh_create_in: the workspace is smaller than mesh_workspace_bytes";
+    return PIC_E_ARG;
+  }
   if (err != hipSuccess) {
     msg = std::string("mesh_create: ") + hipGetErrorString(err);
     return PIC_E_DEVICE;

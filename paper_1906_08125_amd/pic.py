@@ -155,11 +155,13 @@ def _close_all():
 
 LOCATE_NOALLOC_MAX = (1 << 20) - 64
 
-EXPORTS = ("mesh_create", "mesh_destroy", "mesh_query", "mesh_emit_faces",
+EXPORTS = ("mesh_create", "mesh_workspace_bytes", "mesh_create_in",
+           "mesh_destroy", "mesh_query", "mesh_emit_faces",
            "locate", "locate_noalloc", "deposit", "poisson_solve", "pic_step", "emission_rate",
            "adjoint_step", "pic_batch_create", "pic_batch_destroy",
            "pic_batch_step", "pic_profile", "pic_profile_read",
-           "pic_last_error", "collide", "surface_charge", "metal_create",
+           "pic_last_error", "collide", "surface_charge", "window_objective",
+           "apply_face_weights", "metal_create",
            "metal_destroy", "continuity_solve", "heat_step")
 KERNEL_CLASSES = ("push", "emit", "inject", "fallback", "solve", "sort",
                   "clear", "adjoint", "collide")
@@ -181,6 +183,9 @@ def load_library(path: str = LIB_PATH):
     L = C.CDLL(path)
     vp, i64, i32, dbl = C.c_void_p, C.c_int64, C.c_int32, C.c_double
     L.mesh_create.argtypes = [C.POINTER(MeshDesc), vp, C.POINTER(vp)]
+    L.mesh_workspace_bytes.argtypes = [C.POINTER(MeshDesc), C.POINTER(C.c_size_t)]
+    L.mesh_create_in.argtypes = [C.POINTER(MeshDesc), vp, C.c_size_t, vp,
+                                 C.POINTER(vp)]
     L.mesh_destroy.argtypes = [vp]
     L.mesh_query.argtypes = [vp, C.POINTER(MeshInfo)]
     L.mesh_emit_faces.argtypes = [vp, vp, vp, vp]
@@ -202,6 +207,8 @@ def load_library(path: str = LIB_PATH):
                                C.POINTER(StepParams), C.POINTER(AdjointArgs),
                                vp, vp]
     L.pic_profile.argtypes = [vp, i32]
+    L.window_objective.argtypes = [vp, vp, i32, vp, dbl, i32, dbl, dbl, vp, vp]
+    L.apply_face_weights.argtypes = [vp, C.POINTER(Particles), vp, vp, vp]
     L.collide.argtypes = [vp, C.POINTER(Particles), C.POINTER(CollideParams), vp]
     L.surface_charge.argtypes = [vp, C.POINTER(Fields), C.POINTER(ChargeParams),
                                  vp, vp, vp]
@@ -264,9 +271,10 @@ def _stream(torch):
 
 
 class Mesh:
-    """Device mesh handle (mesh_create)."""
+    """Device mesh handle (mesh_create; with workspace=True, mesh_create_in
+    into a torch-allocated workspace of mesh_workspace_bytes)."""
 
-    def __init__(self, tip_mesh, emit_zmin: float):
+    def __init__(self, tip_mesh, emit_zmin: float, workspace: bool = False):
         torch = _torch()
         L = load_library()
         self._keep = (np.ascontiguousarray(tip_mesh.xyz, np.float64),
@@ -277,7 +285,16 @@ class Mesh:
                      self._keep[2].ctypes.data, tip_mesh.Lx, tip_mesh.Ly,
                      tip_mesh.z_top, emit_zmin)
         h = C.c_void_p()
-        _check(L.mesh_create(C.byref(d), _stream(torch), C.byref(h)))
+        self.workspace = None
+        if workspace:
+            nb = C.c_size_t()
+            _check(L.mesh_workspace_bytes(C.byref(d), C.byref(nb)))
+            self.workspace = torch.empty(nb.value, dtype=torch.uint8,
+                                         device="cuda")
+            _check(L.mesh_create_in(C.byref(d), _ptr(self.workspace),
+                                    nb.value, _stream(torch), C.byref(h)))
+        else:
+            _check(L.mesh_create(C.byref(d), _stream(torch), C.byref(h)))
         self._h = h
         _open_handles.add(self)
         info = MeshInfo()
@@ -614,31 +631,26 @@ class Window:
                                 precision=st.precision,
                                 inner_tol=st.inner_tol)
 
-    def _face_mean(self, E):
-        torch = _torch()
-        _, F = self.mesh.emission_rate(E.to(torch.float64), self.kw["phi_w"])
-        return F.mean() if F.numel() else torch.zeros((), dtype=torch.float64,
-                                                      device=E.device)
-
-    def forward(self, E0: float, s, counts=None):
+    def forward(self, E0: float, s, counts=None, wQ=1.0, wE=1.0):
         """Runs the window from the base population; returns (J_Q, J_E) as
-        device scalars and keeps the checkpoints.  counts: None, or the
-        per-step emission counts to hold (a list of T device int32 [n_emit],
-        e.g. the `counts` of an earlier forward) -- finite differences of J
-        hold them, as the adjoint does.  The counts used are kept in
-        `counts` (and replayed by backward)."""
+        device scalars (and keeps J = wQ J_Q + wE J_E in self.J[2]) and the
+        checkpoints.  counts: None, or the per-step emission counts to hold
+        (a list of T device int32 [n_emit], e.g. the `counts` of an earlier
+        forward) -- finite differences of J hold them, as the adjoint does.
+        The counts used are kept in `counts` (and replayed by backward)."""
         torch = _torch()
         st, k = self.state, self.kw
+        L = load_library()
+        strm = _stream(torch)
+        _dev_arrays((s, "float64", max(self.mesh.n_emit, 1), "s"))
         self.base.restore(st)
-        live = st.tet >= 0
-        sb = s.to(torch.float64)[st.birth.long().clamp(min=0)]
-        st.w.copy_(torch.where(live, self.base.w * sb, self.base.w))
+        _check(L.apply_face_weights(self.mesh.handle, C.byref(st._p),
+                                    _ptr(self.base.w), _ptr(s), strm))
         self._initial_field(st, E0)
         self.cks = []
         used = [torch.zeros(max(self.mesh.n_emit, 1), dtype=torch.int32,
                             device=st.phi.device) for _ in range(self.T)]
-        JQ = torch.zeros((), dtype=torch.float64, device=st.phi.device)
-        JE = torch.zeros((), dtype=torch.float64, device=st.phi.device)
+        J = torch.zeros(3, dtype=torch.float64, device=st.phi.device)
         for j in range(self.T):
             self.cks.append(_Checkpoint(st))
             stats = st.step(dt=k["dt"], E0=E0, w_sp=k["w_sp"], phi_w=k["phi_w"],
@@ -648,12 +660,13 @@ class Window:
                             resort_every=0,
                             counts_in=None if counts is None else counts[j],
                             counts_out=used[j])
-            row = stats.view(-1)
-            JQ = JQ + row[STEP_STATS_FIELDS.index("q_anode")].to(torch.float64) * (
-                k["w_sp"] / CHARGE_SCALE)
-            JE = JE + self._face_mean(st.E) / self.T
+            _check(L.window_objective(self.mesh.handle, _ptr(st.E),
+                                      int(st.precision), _ptr(stats),
+                                      float(k["w_sp"]), self.T, float(wQ),
+                                      float(wE), _ptr(J), strm))
         self.counts = used
-        return JQ, JE
+        self.J = J
+        return J[0], J[1]
 
     def backward(self, E0: float, s, wQ=1.0, wE=1.0):
         """dJ/dE0 (device scalar) and dJ/ds (device [n_emit]) of the last
@@ -708,10 +721,10 @@ def _window_function():
         def forward(ctx, E0, s, window, wQ, wE):
             e0 = float(E0)
             s64 = s.detach().to(torch.float64).contiguous()
-            JQ, JE = window.forward(e0, s64)
+            window.forward(e0, s64, wQ=wQ, wE=wE)
             ctx.window, ctx.e0, ctx.w = window, e0, (wQ, wE)
             ctx.save_for_backward(s64)
-            return (wQ * JQ + wE * JE).to(E0.dtype)
+            return window.J[2].clone().to(E0.dtype)
 
         @staticmethod
         def backward(ctx, g):

@@ -630,3 +630,47 @@ def test_pic_step_held_counts(pic):
         assert (out.cpu().numpy() == held).all()
         assert so_all[-1]["n_inj"] == int(held.sum())
     _compare_runs(ost, gs, so_all, sg_all)
+
+
+def test_mesh_in_caller_workspace(pic):
+    """mesh_create_in: the mesh's persistent arrays in a caller workspace
+    of mesh_workspace_bytes give the same steps, bit for bit, as a handle
+    that allocates them; a workspace one byte short is rejected."""
+    import ctypes as C
+    cfg = W.config_tiny()
+    tip = cfg.mesh()
+    ga = pic.Mesh(tip, cfg.emit_zmin)
+    gb = pic.Mesh(tip, cfg.emit_zmin, workspace=True)
+    assert gb.workspace.numel() >= ga.info["device_bytes"]
+    assert gb.info["device_bytes"] == ga.info["device_bytes"]
+    out = []
+    for gm in (ga, gb):
+        gs = pic.State(gm, 30000)
+        gs.init_field(cfg.E0, tol=cfg.tol)
+        rate, _ = gm.emission_rate(gs.E, cfg.phi_w)
+        per_run = rate.item() * cfg.dt * cfg.transit_steps
+        st = gs.step(dt=cfg.dt, E0=cfg.E0, w_sp=0.5 / 2000, phi_w=cfg.phi_w,
+                     step0=0, seed=cfg.seed, j_scale=0.5 / per_run, tol=cfg.tol,
+                     resort_every=4, n_steps=9)
+        torch.cuda.synchronize()
+        out.append((gs.live(), gs.phi.cpu().numpy(), st.cpu().numpy()))
+    (Pa, phia, sa), (Pb, phib, sb) = out
+    assert Pa["id"].size > 0
+    for k in ("x", "y", "z", "vx", "vy", "vz", "tet", "id"):
+        assert np.array_equal(Pa[k], Pb[k]), k
+    assert np.array_equal(phia, phib) and np.array_equal(sa, sb)
+    L = pic.load_library()
+    keep = (np.ascontiguousarray(tip.xyz, np.float64),
+            np.ascontiguousarray(tip.tet, np.int32),
+            np.ascontiguousarray(tip.shift, np.int8))
+    d = pic.MeshDesc(tip.n_nodes, keep[0].ctypes.data, tip.n_tets,
+                     keep[1].ctypes.data, keep[2].ctypes.data, tip.Lx, tip.Ly,
+                     tip.z_top, cfg.emit_zmin)
+    nb = C.c_size_t()
+    assert L.mesh_workspace_bytes(C.byref(d), C.byref(nb)) == pic.PIC_OK
+    assert nb.value == gb.workspace.numel()
+    h = C.c_void_p()
+    assert L.mesh_create_in(C.byref(d), C.c_void_p(gb.workspace.data_ptr()),
+                            nb.value - 1, None, C.byref(h)) == pic.PIC_E_ARG
+    gb.close()
+    ga.close()
