@@ -371,7 +371,8 @@ def run_gpu(args):
         stress = [run_stress_leg(gm, cfg, rate, faceF, args, pc, pr)
                   for pc, pr in ((pic.PIC_PRECOND_JACOBI, pic.PIC_FP64),
                                  (pic.PIC_PRECOND_JACOBI, pic.PIC_MIXED),
-                                 (pic.PIC_PRECOND_AMG, pic.PIC_FP64))]
+                                 (pic.PIC_PRECOND_AMG, pic.PIC_FP64),
+                                 (pic.PIC_PRECOND_AMG, pic.PIC_MIXED))]
         log(f"stress leg {stress}")
     charge = None
     if args.charge_calls > 0:

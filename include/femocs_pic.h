@@ -185,7 +185,10 @@ PIC_API pic_status deposit(const pic_mesh* mesh, int64_t n, const double* x,
 /*   PIC_PRECOND_JACOBI  diagonal scaling (default);                        */
 /*   PIC_PRECOND_AMG     one V(1,1)-cycle of smoothed-aggregation algebraic */
 /*                       multigrid (Jacobi smoothing, dense coarsest solve) */
-/*                       per iteration; PIC_FP64 only.  The hierarchy is    */
+/*                       per iteration.  With PIC_MIXED the CG recursion    */
+/*                       stays FP64 and the V-cycle runs in FP32 (level     */
+/*                       matrices, diagonals and vectors rounded to FP32;   */
+/*                       no refinement restarts).  The hierarchy is         */
 /*                       built on the host from the mesh's K on the first   */
 /*                       solve that asks for it (seconds at 5e5 unknowns)   */
 /*                       and kept with the mesh.                            */

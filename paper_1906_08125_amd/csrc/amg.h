@@ -20,6 +20,7 @@ struct SellMat {
   const int32_t* sptr;     // SELL slice offsets, or CSR row offsets [nrows+1]
   const int32_t* col;
   const double* val;
+  const float* val32;      // the same values rounded to FP32
 };
 
 // One level of the hierarchy.  Level 0 is K on the free nodes; b of level 0
@@ -34,6 +35,9 @@ struct AmgLevel {
   double* x;      // pre-smoothed iterate, then corrected
   double* r;      // residual after pre-smoothing
   double* t;      // post-smoothed iterate (levels > 0)
+  // FP32 copies for the FP32 V-cycle (mixed precision)
+  const float* invdiag32;
+  float *b32, *x32, *r32, *t32;
 };
 
 struct AmgDev {
@@ -43,6 +47,9 @@ struct AmgDev {
   const double* coarse_inv;  // [n_coarse][n_coarse] inverse, row-major
   double* coarse_b;
   double* coarse_x;
+  const float* coarse_inv32;
+  float* coarse_b32;
+  float* coarse_x32;
   int64_t rows[kAmgMaxLevels + 1];  // rows per level (the coarsest last)
 };
 
@@ -58,6 +65,9 @@ hipError_t amg_build(const DevMesh& m, hipStream_t s,
 // Chronopoulos-Gear ordering [V-cycle, w = K u, update], numbered by the
 // device counters of the control word; no report.  The first V-cycle
 // kernel of every iteration after the first tests the recursive residual.
+// With a.amg32 the V-cycle runs in FP32 (level matrices, diagonals and
+// vectors; the CG recursion stays FP64).  Levels below the finest launch
+// grids sized to their rows.
 hipError_t amg_launch_iters(const CgArgs& a, const AmgDev& d, int n,
                             hipStream_t s);
 

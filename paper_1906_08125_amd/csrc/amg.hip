@@ -395,29 +395,40 @@ hipError_t amg_build(const DevMesh& m, hipStream_t s,
       out.sptr = (const int32_t*)up(S.sptr.data(), sizeof(int32_t) * S.sptr.size());
       out.col = (const int32_t*)up(S.col.data(), sizeof(int32_t) * std::max<size_t>(S.col.size(), 1));
       out.val = (const double*)up(S.val.data(), sizeof(double) * std::max<size_t>(S.val.size(), 1));
+      const std::vector<float> v32(S.val.begin(), S.val.end());
+      out.val32 = (const float*)up(v32.data(), sizeof(float) * std::max<size_t>(v32.size(), 1));
       // (synchronized before the host copies go out of scope)
-      return out.sptr && out.col && out.val && hipStreamSynchronize(s) == hipSuccess;
+      return out.sptr && out.col && out.val && out.val32 &&
+             hipStreamSynchronize(s) == hipSuccess;
     }
     std::vector<int32_t> rp(M.rp.begin(), M.rp.end());
     out.nslices = 0;
     out.sptr = (const int32_t*)up(rp.data(), sizeof(int32_t) * rp.size());
     out.col = (const int32_t*)up(M.ci.data(), sizeof(int32_t) * std::max<size_t>(M.ci.size(), 1));
     out.val = (const double*)up(M.v.data(), sizeof(double) * std::max<size_t>(M.v.size(), 1));
-    return out.sptr && out.col && out.val && hipStreamSynchronize(s) == hipSuccess;
+    const std::vector<float> v32(M.v.begin(), M.v.end());
+    out.val32 = (const float*)up(v32.data(), sizeof(float) * std::max<size_t>(v32.size(), 1));
+    return out.sptr && out.col && out.val && out.val32 &&
+           hipStreamSynchronize(s) == hipSuccess;
   };
   d.n_levels = L;
   for (int l = 0; l <= L; ++l) d.rows[l] = A[l].n;
   for (int l = 0; l < L; ++l) {
     AmgLevel& lv = d.lv[l];
     if (l == 0) {
-      lv.A = SellMat{m.n_free, m.k_nslices, 1, m.k_sptr, m.k_scol, m.k_sval};
+      lv.A = SellMat{m.n_free, m.k_nslices, 1, m.k_sptr, m.k_scol, m.k_sval,
+                     m.k_sval32};
       lv.invdiag = m.invdiag;
+      lv.invdiag32 = m.invdiag32;
     } else {
       if (!up_sell(A[l], lv.A)) return hipErrorOutOfMemory;
       std::vector<double> inv(A[l].n);
       for (int64_t i = 0; i < A[l].n; ++i) inv[i] = 1.0 / diag[l][i];
+      const std::vector<float> inv32(inv.begin(), inv.end());
       lv.invdiag = (const double*)up(inv.data(), sizeof(double) * inv.size());
-      if (!lv.invdiag || hipStreamSynchronize(s) != hipSuccess) return hipErrorOutOfMemory;
+      lv.invdiag32 = (const float*)up(inv32.data(), sizeof(float) * inv32.size());
+      if (!lv.invdiag || !lv.invdiag32 || hipStreamSynchronize(s) != hipSuccess)
+        return hipErrorOutOfMemory;
     }
     lv.omega = omega[l];
     if (!up_sell(P[l], lv.P) || !up_sell(R[l], lv.R)) return hipErrorOutOfMemory;
@@ -427,12 +438,23 @@ hipError_t amg_build(const DevMesh& m, hipStream_t s,
     lv.r = (double*)alloc(ctx, vb);
     lv.t = l > 0 ? (double*)alloc(ctx, vb) : nullptr;
     if (!lv.x || !lv.r || (l > 0 && (!lv.b || !lv.t))) return hipErrorOutOfMemory;
+    lv.b32 = l > 0 ? (float*)alloc(ctx, vb / 2) : nullptr;
+    lv.x32 = (float*)alloc(ctx, vb / 2);
+    lv.r32 = (float*)alloc(ctx, vb / 2);
+    lv.t32 = l > 0 ? (float*)alloc(ctx, vb / 2) : nullptr;
+    if (!lv.x32 || !lv.r32 || (l > 0 && (!lv.b32 || !lv.t32))) return hipErrorOutOfMemory;
   }
   d.n_coarse = Ac.n;
   d.coarse_inv = (const double*)up(dense.data(), sizeof(double) * dense.size());
+  const std::vector<float> dense32(dense.begin(), dense.end());
+  d.coarse_inv32 = (const float*)up(dense32.data(), sizeof(float) * dense32.size());
   d.coarse_b = (double*)alloc(ctx, sizeof(double) * Ac.n);
   d.coarse_x = (double*)alloc(ctx, sizeof(double) * Ac.n);
-  if (!d.coarse_inv || !d.coarse_b || !d.coarse_x) return hipErrorOutOfMemory;
+  d.coarse_b32 = (float*)alloc(ctx, sizeof(float) * Ac.n);
+  d.coarse_x32 = (float*)alloc(ctx, sizeof(float) * Ac.n);
+  if (!d.coarse_inv || !d.coarse_b || !d.coarse_x || !d.coarse_inv32 ||
+      !d.coarse_b32 || !d.coarse_x32)
+    return hipErrorOutOfMemory;
   return hipStreamSynchronize(s);
 }
 

@@ -350,8 +350,6 @@ pic_status check_solve(const pic_solve_params* p) {
     return fail(PIC_E_ARG, "solve params: inner_tol must be in [1e-7, 0.5]");
   if (p->precond != PIC_PRECOND_JACOBI && p->precond != PIC_PRECOND_AMG)
     return fail(PIC_E_ARG, "solve params: unknown preconditioner");
-  if (p->precond == PIC_PRECOND_AMG && p->precision != PIC_FP64)
-    return fail(PIC_E_ARG, "solve params: the AMG preconditioner is FP64 only");
   return PIC_OK;
 }
 
@@ -376,6 +374,10 @@ pic_status use_precond(pic_mesh* h, const pic_solve_params* p, fp::CgArgs& a,
     h->amg_ready = true;
   }
   a.amg = &h->amg;
+  // mixed precision with AMG: the CG recursion stays FP64, the V-cycle runs
+  // in FP32 (no refinement restarts)
+  a.amg32 = a.mixed;
+  a.mixed = 0;
   return PIC_OK;
 }
 

@@ -73,8 +73,10 @@ struct CgArgs {
   double* bprev;          // [n_free] right-hand side of the last pass
   CgCtrl* ctrl;
   // host address of the AMG hierarchy (AmgDev) when the solve is
-  // preconditioned by it, else null (Jacobi); FP64 only
+  // preconditioned by it, else null (Jacobi); the CG recursion is then FP64
+  // (mixed = 0), and amg32 runs the V-cycle in FP32
   const void* amg;
+  int amg32;
   CgReport* report;       // host-mapped report record (device address)
   const int32_t* dir_nodes;
   int64_t n_dir;

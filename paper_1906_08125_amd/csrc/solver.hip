@@ -32,6 +32,8 @@
 // (workgroup g runs on XCD g mod 8) sweeps one contiguous eighth of the
 // matrix, which keeps neighbour gathers in one L2.
 #include "amg.h"
+
+#include <type_traits>
 #include "common.h"
 #include "solver.h"
 
@@ -691,12 +693,20 @@ __global__ void k_cg_report_b(CgBatch b, int n, int64_t seq) {
 namespace {
 
 // emit(r, sum_j val_rj g(col_rj)) for every row r of M in this workgroup's
-// share.  SELL (lpr = 1): one lane per row, entries in order, four loads in
-// flight per trip.  CSR (lpr > 1): lpr lanes per row, each summing every
-// lpr-th entry, then a fixed shuffle tree; every group of a workgroup makes
-// the same number of trips, so the shuffles run on whole waves.
-template <typename Gf, typename Ef>
+// share, in the arithmetic of T (the values of M in T: val or val32).
+// SELL (lpr = 1): one lane per row, entries in order, four loads in flight
+// per trip.  CSR (lpr > 1): lpr lanes per row, each summing every lpr-th
+// entry, then a fixed shuffle tree; every group of a workgroup makes the
+// same number of trips, so the shuffles run on whole waves.
+template <typename T>
+__device__ inline const T* mat_val(const SellMat& M) {
+  if constexpr (std::is_same<T, float>::value) return M.val32;
+  else return M.val;
+}
+
+template <typename T, typename Gf, typename Ef>
 __device__ inline void amg_rows(const SellMat& M, VB vb, Gf&& g, Ef&& emit) {
+  const T* __restrict__ val = mat_val<T>(M);
   if (M.lpr == 1) {
     const Range sl = my_range(M.nslices, vb);
     const int lane = threadIdx.x & (kSell - 1);
@@ -704,21 +714,21 @@ __device__ inline void amg_rows(const SellMat& M, VB vb, Gf&& g, Ef&& emit) {
          s += blockDim.x / kSell) {
       const int32_t p1 = M.sptr[s + 1];
       int32_t p = M.sptr[s] + lane;
-      double acc = 0.0;
+      T acc = 0;
       for (; p + 3 * kSell < p1; p += 4 * kSell) {
         int32_t c[4];
-        double v[4], xv[4];
+        T v[4], xv[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           c[u] = M.col[p + u * kSell];
-          v[u] = M.val[p + u * kSell];
+          v[u] = val[p + u * kSell];
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) xv[u] = g(c[u]);
 #pragma unroll
         for (int u = 0; u < 4; ++u) acc += v[u] * xv[u];
       }
-      for (; p < p1; p += kSell) acc += M.val[p] * g(M.col[p]);
+      for (; p < p1; p += kSell) acc += val[p] * g(M.col[p]);
       const int64_t r = s * kSell + lane;
       if (r < M.nrows) emit(r, acc);
     }
@@ -730,10 +740,10 @@ __device__ inline void amg_rows(const SellMat& M, VB vb, Gf&& g, Ef&& emit) {
   const int grp = threadIdx.x / lpr, ngrp = blockDim.x / lpr;
   for (int64_t r0 = rows.lo; r0 < rows.hi; r0 += ngrp) {
     const int64_t r = r0 + grp;
-    double acc = 0.0;
+    T acc = 0;
     if (r < rows.hi)
       for (int32_t p = M.sptr[r] + sub; p < M.sptr[r + 1]; p += lpr)
-        acc += M.val[p] * g(M.col[p]);
+        acc += val[p] * g(M.col[p]);
     for (int off = lpr >> 1; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, lpr);
     if (r < rows.hi && sub == 0) emit(r, acc);
   }
@@ -761,47 +771,68 @@ __device__ inline bool amg_stop(const CgArgs& a, VB vb) {
   return false;
 }
 
+// Vectors and diagonal of a level in the arithmetic of T.
+template <typename T>
+struct LevelVecs {
+  const T* dinv;
+  T *b, *x, *r, *t;
+};
+template <typename T>
+__host__ __device__ inline LevelVecs<T> level_vecs(const AmgLevel& L) {
+  if constexpr (std::is_same<T, float>::value)
+    return LevelVecs<T>{L.invdiag32, L.b32, L.x32, L.r32, L.t32};
+  else
+    return LevelVecs<T>{L.invdiag, L.b, L.x, L.r, L.t};
+}
+
 }  // namespace
 
 // Pre-smoothing from zero and the residual: x = w D^-1 b,
-// r = b - A x = b - w sum_j a_ij d_j^-1 b_j.
+// r = b - A x = b - w sum_j a_ij d_j^-1 b_j.  On the finest level b is the
+// CG residual (FP64; rounded once to T).
+template <typename T>
 __global__ void __launch_bounds__(kCgBlock) k_amg_down(CgArgs a, AmgLevel L,
                                                        int level) {
   if (a.ctrl->state != CG_ITER) return;
   const VB vb{(int)blockIdx.x, (int)gridDim.x};
   if (level == 0 && amg_stop(a, vb)) return;
-  const double* __restrict__ b = level == 0 ? a.r : L.b;
-  const double* __restrict__ dinv = L.invdiag;
-  amg_rows(L.A, vb, [&](int32_t c) { return b[c] * dinv[c]; },
-           [&](int64_t r, double ax) {
-             const double br = b[r];
-             L.x[r] = L.omega * (dinv[r] * br);
-             L.r[r] = br - L.omega * ax;
-           });
+  const LevelVecs<T> V = level_vecs<T>(L);
+  const double* __restrict__ r64 = a.r;
+  const T* __restrict__ bl = V.b;
+  const T* __restrict__ dinv = V.dinv;
+  const T omega = (T)L.omega;
+  auto B = [&](int64_t c) -> T { return level == 0 ? (T)r64[c] : bl[c]; };
+  amg_rows<T>(L.A, vb, [&](int32_t c) { return B(c) * dinv[c]; },
+              [&](int64_t r, T ax) {
+                const T br = B(r);
+                V.x[r] = omega * (dinv[r] * br);
+                V.r[r] = br - omega * ax;
+              });
 }
 
 // y = M x for the rows of M (restriction and prolongation; add: y += M x).
+template <typename T>
 __global__ void __launch_bounds__(kCgBlock) k_amg_apply(CgArgs a, SellMat M,
-                                                        const double* x,
-                                                        double* y, int add) {
+                                                        const T* x, T* y,
+                                                        int add) {
   if (a.ctrl->state != CG_ITER) return;
   const VB vb{(int)blockIdx.x, (int)gridDim.x};
-  amg_rows(M, vb, [&](int32_t c) { return x[c]; },
-           [&](int64_t r, double v) { y[r] = add ? y[r] + v : v; });
+  amg_rows<T>(M, vb, [&](int32_t c) { return x[c]; },
+              [&](int64_t r, T v) { y[r] = add ? y[r] + v : v; });
 }
 
 // Coarsest level: x = A^-1 b with the dense inverse, one wave per row.
+template <typename T>
 __global__ void __launch_bounds__(kCgBlock) k_amg_coarse(CgArgs a, int64_t n,
-                                                         const double* inv,
-                                                         const double* b,
-                                                         double* x) {
+                                                         const T* inv,
+                                                         const T* b, T* x) {
   if (a.ctrl->state != CG_ITER) return;
   const VB vb{(int)blockIdx.x, (int)gridDim.x};
   const Range rows = my_range(n, vb);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int64_t i0 = rows.lo; i0 < rows.hi; i0 += blockDim.x >> 6) {
     const int64_t i = i0 + wave;
-    double s = 0.0;
+    T s = 0;
     if (i < rows.hi)
       for (int64_t j = lane; j < n; j += 64) s += inv[i * n + j] * b[j];
     for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
@@ -809,23 +840,29 @@ __global__ void __launch_bounds__(kCgBlock) k_amg_coarse(CgArgs a, int64_t n,
   }
 }
 
-// Post-smoothing: out = x + w D^-1 (b - A x); on level 0 out is u and the
-// workgroups write their share of (r,u).
+// Post-smoothing: out = x + w D^-1 (b - A x); on the finest level out is
+// the CG vector u (FP64) and the workgroups write their share of (r,u).
+template <typename T>
 __global__ void __launch_bounds__(kCgBlock) k_amg_post(CgArgs a, AmgLevel L,
                                                        int level) {
   if (a.ctrl->state != CG_ITER) return;
   const VB vb{(int)blockIdx.x, (int)gridDim.x};
-  const double* __restrict__ b = level == 0 ? a.r : L.b;
-  double* out = level == 0 ? a.u : L.t;
-  const double* __restrict__ x = L.x;
+  const LevelVecs<T> V = level_vecs<T>(L);
+  const double* __restrict__ r64 = a.r;
+  const T* __restrict__ x = V.x;
+  const T omega = (T)L.omega;
   double v[1] = {0.0};
-  amg_rows(L.A, vb, [&](int32_t c) { return x[c]; },
-           [&](int64_t r, double ax) {
-             const double br = b[r];
-             const double o = x[r] + L.omega * (L.invdiag[r] * (br - ax));
-             out[r] = o;
-             v[0] += br * o;
-           });
+  amg_rows<T>(L.A, vb, [&](int32_t c) { return x[c]; },
+              [&](int64_t r, T ax) {
+                const T br = level == 0 ? (T)r64[r] : V.b[r];
+                const T o = x[r] + omega * (V.dinv[r] * (br - ax));
+                if (level == 0) {
+                  a.u[r] = (double)o;
+                  v[0] += r64[r] * (double)o;
+                } else {
+                  V.t[r] = o;
+                }
+              });
   if (level == 0) write_partials<1>(slot(a, 5 + 2 * (a.ctrl->it_a & 1)), a.G, v, vb);
 }
 
@@ -886,31 +923,78 @@ __global__ void __launch_bounds__(kCgBlock) k_amg_upd(CgArgs a) {
   write_partials<1>(slot(a, 4 + 2 * pb), a.G, v, vb);
 }
 
-hipError_t amg_launch_iters(const CgArgs& a, const AmgDev& d, int n,
-                            hipStream_t s) {
-  const dim3 g(a.G), b(kCgBlock);
+namespace {
+
+// Workgroups for a level kernel over n rows: the full solver grid on the
+// finest level (its kernels also reduce over that grid), fewer below, so
+// that the small coarse passes do not launch and drain hundreds of idle
+// workgroups.
+template <typename T>
+struct CoarseVecs {
+  const T* inv;
+  T *b, *x;
+};
+template <typename T>
+CoarseVecs<T> coarse_host(const AmgDev& d) {
+  if constexpr (std::is_same<T, float>::value)
+    return CoarseVecs<T>{d.coarse_inv32, d.coarse_b32, d.coarse_x32};
+  else
+    return CoarseVecs<T>{d.coarse_inv, d.coarse_b, d.coarse_x};
+}
+
+// Workgroups for a level kernel over the rows of M: about two lanes of
+// work per thread (a row takes M.lpr lanes), at most the solver grid, so
+// that the small coarse passes do not launch and drain hundreds of idle
+// workgroups.  The finest level's smoothing kernels keep the solver grid
+// (they also reduce over it).
+int amg_grid(const CgArgs& a, const SellMat& M) {
+  const int64_t lanes = M.nrows * (int64_t)M.lpr;
+  const int64_t want = (lanes + 2 * kCgBlock - 1) / (2 * kCgBlock);
+  int g = (int)std::min<int64_t>(a.G, std::max<int64_t>(8, want));
+  return g >= 8 ? g - g % 8 : g;
+}
+
+template <typename T>
+hipError_t amg_iters_t(const CgArgs& a, const AmgDev& d, int n, hipStream_t s) {
+  const dim3 b(kCgBlock);
   const int L = d.n_levels;
+  auto vec = [](const AmgLevel& lv) { return level_vecs<T>(lv); };
+  const auto cv = coarse_host<T>(d);
+  // one wave per row of the dense coarsest inverse
+  const int gc = (int)std::min<int64_t>(
+      a.G, std::max<int64_t>(8, (d.n_coarse + kCgBlock / 64 - 1) / (kCgBlock / 64)));
   for (int k = 0; k < n; ++k) {
     for (int l = 0; l < L; ++l) {
       const AmgLevel& lv = d.lv[l];
-      hipLaunchKernelGGL(k_amg_down, g, b, 0, s, a, lv, l);
-      double* nb = l + 1 < L ? d.lv[l + 1].b : d.coarse_b;
-      hipLaunchKernelGGL(k_amg_apply, g, b, 0, s, a, lv.R, (const double*)lv.r, nb, 0);
+      hipLaunchKernelGGL(k_amg_down<T>, dim3(l == 0 ? a.G : amg_grid(a, lv.A)), b, 0,
+                         s, a, lv, l);
+      T* nb = l + 1 < L ? vec(d.lv[l + 1]).b : cv.b;
+      hipLaunchKernelGGL(k_amg_apply<T>, dim3(amg_grid(a, lv.R)), b, 0, s, a, lv.R,
+                         (const T*)vec(lv).r, nb, 0);
     }
-    hipLaunchKernelGGL(k_amg_coarse, g, b, 0, s, a, d.n_coarse, d.coarse_inv,
-                       (const double*)d.coarse_b, d.coarse_x);
+    hipLaunchKernelGGL(k_amg_coarse<T>, dim3(gc), b, 0, s, a, d.n_coarse, cv.inv,
+                       (const T*)cv.b, cv.x);
     for (int l = L - 1; l >= 0; --l) {
       const AmgLevel& lv = d.lv[l];
-      const double* y = l + 1 < L ? d.lv[l + 1].t : d.coarse_x;
-      hipLaunchKernelGGL(k_amg_apply, g, b, 0, s, a, lv.P, y, lv.x, 1);
-      hipLaunchKernelGGL(k_amg_post, g, b, 0, s, a, lv, l);
+      const T* y = l + 1 < L ? vec(d.lv[l + 1]).t : cv.x;
+      hipLaunchKernelGGL(k_amg_apply<T>, dim3(amg_grid(a, lv.P)), b, 0, s, a, lv.P, y,
+                         vec(lv).x, 1);
+      hipLaunchKernelGGL(k_amg_post<T>, dim3(l == 0 ? a.G : amg_grid(a, lv.A)), b, 0,
+                         s, a, lv, l);
     }
-    hipLaunchKernelGGL(k_amg_spmv, g, b, 0, s, a);
-    hipLaunchKernelGGL(k_amg_upd, g, b, 0, s, a);
+    hipLaunchKernelGGL(k_amg_spmv, dim3(a.G), b, 0, s, a);
+    hipLaunchKernelGGL(k_amg_upd, dim3(a.G), b, 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t amg_launch_iters(const CgArgs& a, const AmgDev& d, int n,
+                            hipStream_t s) {
+  return a.amg32 ? amg_iters_t<float>(a, d, n, s) : amg_iters_t<double>(a, d, n, s);
 }
 
 #define LAUNCH(kern, ...)                                                   \

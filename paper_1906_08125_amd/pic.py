@@ -459,7 +459,8 @@ class State:
                  inner_tol: float = 1e-4, precond: int = PIC_PRECOND_JACOBI):
         """precision: PIC_FP64, or PIC_MIXED for FP32 particles and field;
         solve_precision (default: precision) picks the Poisson solver;
-        precond its preconditioner (PIC_PRECOND_AMG: FP64 solves only)."""
+        precond its preconditioner (PIC_PRECOND_AMG with mixed solves: the
+        V-cycle in FP32 inside the FP64 CG)."""
         torch = _torch()
         self.mesh = mesh
         self.capacity = int(capacity)
@@ -494,7 +495,7 @@ class State:
         st = self.mesh.poisson_solve(
             None, 0.0, E0, self.phi, self.E, tol, max_iter,
             precision=self.precision, inner_tol=self.inner_tol,
-            precond=self.precond if self.precision == PIC_FP64 else PIC_PRECOND_JACOBI)
+            precond=self.precond)
         return st
 
     def step(self, *, dt, E0, w_sp, phi_w, step0, seed, n_steps=1, instance=0,

@@ -130,10 +130,19 @@ def test_poisson_amg_matches_oracle(pic, name):
     st2 = gm.poisson_solve(_dev(c), 1e-3, 0.4, phi, None, tol=1e-12,
                            precond=pic.PIC_PRECOND_AMG)
     assert gm.solve_stats(st2)["iters"] == 0
-    # the AMG preconditioner is FP64 only
-    with pytest.raises(pic.PicError):
-        gm.poisson_solve(_dev(c), 1e-3, 0.4, phi, None, tol=1e-12,
-                         precision=pic.PIC_MIXED, precond=pic.PIC_PRECOND_AMG)
+    # mixed precision: the V-cycle in FP32 inside the FP64 CG; the stopping
+    # test stays on the FP64 true residual, so the potential is the FP64 one
+    phi3 = torch.zeros(tip.n_nodes, dtype=torch.float64, device="cuda")
+    E3 = torch.zeros(4 * tip.n_nodes, dtype=torch.float32, device="cuda")
+    st3 = gm.poisson_solve(_dev(c), 1e-3, 0.4, phi3, E3, tol=1e-12,
+                           precision=pic.PIC_MIXED, precond=pic.PIC_PRECOND_AMG)
+    s3 = gm.solve_stats(st3)
+    print(name, "fp32 v-cycle", s3)
+    assert s3["status"] == 0 and s3["relres"] <= 1e-12
+    assert s3["restarts"] <= 2
+    assert s3["iters"] <= max(info["iters"] // 4, 10)
+    assert _rel(phi3.cpu().numpy(), phi_o) < 1e-9
+    assert _rel(E3.cpu().numpy().reshape(-1, 4)[:, :3], E_o) < 1e-6
 
 
 def _locate_case(pic, tip, pts, hint=None):
@@ -596,6 +605,22 @@ def test_pic_step_mixed_space_charge(pic):
                                         precision=pic.PIC_MIXED,
                                         phi_err=err)
     assert all(s["cg_iters"] > 0 for s in sg[1:])
+    _compare_mixed(ost, gs, so, sg, err)
+
+
+def test_pic_step_mixed_amg(pic):
+    """Mixed precision with the FP32 V-cycle preconditioning the FP64 CG
+    (space charge, re-sorting, 24 steps): the mixed-precision bounds
+    against the oracle, fewer iterations than the oracle's Jacobi PCG."""
+    cfg = W.config_tiny()
+    err = []
+    om, ost, gm, gs, so, sg = _run_pair(pic, cfg, 24, 0.01, 3000, 60_000,
+                                        resort_every=5,
+                                        precision=pic.PIC_MIXED,
+                                        precond=pic.PIC_PRECOND_AMG,
+                                        phi_err=err)
+    assert all(s["cg_iters"] > 0 for s in sg[1:])
+    assert sum(s["cg_iters"] for s in sg) < sum(s["cg_iters"] for s in so)
     _compare_mixed(ost, gs, so, sg, err)
 
 
