@@ -32,10 +32,11 @@ HBM_PEAK_GBS = 8000.0
 # production workload, from rocprofv3 FETCH_SIZE and WRITE_SIZE counter runs
 # scaled by a plain 1 GiB copy (profiles/pic_step_fp64_production_tip.md).
 # It is reported only while the kernel sources are the ones profiled.
-PUSH_TRAFFIC = dict(bytes=200.0e6, read=134.4e6, written=65.6e6, live=992_310,
+PUSH_TRAFFIC = dict(bytes=199.2e6, read=133.8e6, written=65.4e6, live=992_300,
                     sources=("paper_1906_08125_amd/csrc/particles.hip",
                              "paper_1906_08125_amd/csrc/common.h"),
-                    sha256=("134e33f198c3176cfe6b232d6ed92ef5f7f5f3d69bea0fbcf81858bb7249254c", "7d8f3c2344d581d986633cc1e8597ea0062a3ad5736211095600e29a54930541"))
+                    sha256=("26260919966f515d918ad42efa8987d440e317a7c0e7c338905a0283449d9717",
+                            "7d8f3c2344d581d986633cc1e8597ea0062a3ad5736211095600e29a54930541"))
 
 
 def measured_traffic(live):
