@@ -217,6 +217,13 @@ hipError_t iterate_graphs(pic_mesh* h, const fp::CgArgs& a0, int n, hipStream_t 
   fp::CgArgs a = a0;
   a.stats = nullptr;
   a.step_stats = nullptr;
+  a.acc_rows = nullptr;
+  a.acc_n = 0;
+  a.next_stats = nullptr;
+  a.next_scratch = nullptr;
+  a.n_slots = nullptr;
+  a.clear_charge = nullptr;
+  a.n_clear = 0;
   a.report = nullptr;
   a.charge = nullptr;
   a.rhs = nullptr;
@@ -968,18 +975,20 @@ pic_status pic_step(pic_mesh* h, const pic_particles* P, const pic_fields* F,
     ek.defer = 1;  // the emission runs inside the particle kernel
     *prof0 = h->ev_class.size();
     hipError_t e;
-    prof_begin(h, PIC_K_EMIT, s);
-    if ((e = fp::launch_begin(ek, h->n_cu * 2, s)) != hipSuccess) return e;
-    prof_end(h, s);
+    // the first step of a call clears the charges and counters itself;
+    // later steps find them cleared by the solve before them
+    if (k == 0) {
+      prof_begin(h, PIC_K_EMIT, s);
+      if ((e = fp::launch_begin(ek, h->n_cu * 2, s)) != hipSuccess) return e;
+      prof_end(h, s);
+    }
     prof_begin(h, PIC_K_PUSH, s);
     if ((e = fp::launch_particles(ak, &ek, grid_push, grid_inj, s)) != hipSuccess) return e;
     prof_end(h, s);
     prof_begin(h, PIC_K_FALLBACK, s);
     if ((e = fp::launch_fallback(ak, grid_fb, s)) != hipSuccess) return e;
-    if ((e = fp::launch_stats(h->acc_rows, grid_push + grid_inj + grid_fb,
-                              stats + k, gate, s)) != hipSuccess)
-      return e;
     prof_end(h, s);
+    // (the step's counter rows are summed by the first pass of its solve)
     return hipSuccess;
   };
   // The host learns the outcome of a solve from its report.  Rather than
@@ -1016,6 +1025,14 @@ pic_status pic_step(pic_mesh* h, const pic_particles* P, const pic_fields* F,
       }
     }
     ca.step_stats = st;
+    ca.acc_rows = h->acc_rows;
+    ca.acc_n = grid_push + grid_inj + grid_fb;
+    const bool next = k + 1 < n_steps;
+    ca.next_stats = next ? stats + k + 1 : nullptr;
+    ca.next_scratch = h->scratch;
+    ca.n_slots = P->n_slots;
+    ca.clear_charge = F->charge;
+    ca.n_clear = h->dm.n_nodes;
     // after the first step of this call, E = R phi still holds from the
     // previous solve (every solve ends with a field pass over its final phi)
     ca.keep_field = k > 0 ? 1 : 0;

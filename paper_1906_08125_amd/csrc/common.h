@@ -394,6 +394,38 @@ __host__ __device__ inline int bucket_axis(double x, double x0, double inv,
   return (int)f;
 }
 
+// Sum of the per-workgroup counter rows of one step into its stats record
+// (rows: [12][n_rows], field-major; counter k = 11 is a maximum, the
+// others are sums -- integers, so the order does not matter): one
+// workgroup per counter, any block size up to 1024.
+constexpr int kStepCounters = 12;
+__device__ inline void step_counter_sum(const int64_t* rows, int n_rows,
+                                        pic_step_stats* st, int k) {
+  __shared__ long long part[16];
+  const bool is_max = k == kStepCounters - 1;
+  long long s = 0;
+  for (int r = threadIdx.x; r < n_rows; r += blockDim.x) {
+    const long long v = rows[(int64_t)k * n_rows + r];
+    s = is_max ? (v > s ? v : s) : s + v;
+  }
+  for (int off = 32; off >= 1; off >>= 1) {
+    const long long o = __shfl_xor(s, off, 64);
+    s = is_max ? (o > s ? o : s) : s + o;
+  }
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long t = 0;
+    for (int w = 0; w < (int)((blockDim.x + 63) >> 6); ++w)
+      t = is_max ? (part[w] > t ? part[w] : t) : t + part[w];
+    int64_t* dst[kStepCounters] = {&st->n_before, &st->q_before, &st->n_anode,
+                                   &st->q_anode,  &st->n_after,  &st->q_after,
+                                   &st->n_cathode, &st->q_cathode, &st->n_inj,
+                                   &st->q_inj,    &st->walk_steps, &st->walk_max};
+    *dst[k] = t;
+  }
+}
+
 // Internal per-handle device scratch layout (counters and scalars).
 struct StepScratch {
   // counters used by the particle kernels of one step

@@ -4,7 +4,7 @@
 
 namespace fp {
 
-constexpr int kAccFields = 12;  // counters per block row (see acc_flush)
+constexpr int kAccFields = kStepCounters;  // counters per block row (see acc_flush)
 
 struct EmitConsts {
   double a_fn, b_fn, c_s, j_unit;

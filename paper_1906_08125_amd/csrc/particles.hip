@@ -1002,39 +1002,12 @@ __global__ void __launch_bounds__(kBlock) k_fallback_b(const StepArgs* A,
   fallback_body(a, vb);
 }
 
-// Sum of the counter rows of one step into its stats: one workgroup per
-// counter, a fixed-order tree inside the workgroup.
-__device__ inline void stats_body(const int64_t* rows, int n_rows,
-                                  pic_step_stats* st, int k) {
-  __shared__ long long lds[kBlock / 64];
-  const bool is_max = k == kAccFields - 1;
-  long long s = 0;
-  for (int r = threadIdx.x; r < n_rows; r += blockDim.x) {
-    const long long v = rows[(int64_t)k * n_rows + r];
-    s = is_max ? (v > s ? v : s) : s + v;
-  }
-  s = is_max ? (long long)wave_max((int)s) : wave_sum(s);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 0) lds[wave] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    long long t = 0;
-    for (int w = 0; w < kBlock / 64; ++w)
-      t = is_max ? (lds[w] > t ? lds[w] : t) : t + lds[w];
-    int64_t* dst[kAccFields] = {&st->n_before, &st->q_before, &st->n_anode,
-                                &st->q_anode,  &st->n_after,  &st->q_after,
-                                &st->n_cathode, &st->q_cathode, &st->n_inj,
-                                &st->q_inj,    &st->walk_steps, &st->walk_max};
-    *dst[k] = t;
-  }
-}
-
 __global__ void __launch_bounds__(kBlock) k_stats(const int64_t* rows,
                                                   int n_rows,
                                                   pic_step_stats* st,
                                                   const int32_t* gate) {
   if (gate_closed(gate)) return;
-  stats_body(rows, n_rows, st, (int)blockIdx.x);
+  step_counter_sum(rows, n_rows, st, (int)blockIdx.x);
 }
 
 // Batched: kAccFields workgroups per instance (schedule of 16 per instance).
@@ -1044,7 +1017,7 @@ __global__ void __launch_bounds__(kBlock) k_stats_b(const StepArgs* A,
   const VB vb = batch_block(map, i);
   if (vb.id >= kAccFields) return;
   const StepArgs& a = A[i];
-  stats_body(a.acc_rows, a.acc_stride, a.stats, vb.id);
+  step_counter_sum(a.acc_rows, a.acc_stride, a.stats, vb.id);
 }
 
 // ---------------------------------------------------------------------------

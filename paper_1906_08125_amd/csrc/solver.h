@@ -82,6 +82,21 @@ struct CgArgs {
   int64_t n_dir;
   pic_solve_stats* stats;      // or null
   pic_step_stats* step_stats;  // or null
+  // the particle kernels' per-workgroup counter rows of the step (or null):
+  // the first pass of the solve sums them into step_stats (workgroups
+  // 0 .. kStepCounters - 1), in place of a launch of its own
+  const int64_t* acc_rows;
+  int acc_n;
+  // the start of the next step of a pic_step call, done by the kernel that
+  // ends this solve instead of a launch of its own: the node charges
+  // cleared, the next step's stats record and the particle counters reset,
+  // inj_base taken from *n_slots.  next_stats null: no next step (the
+  // charges of the last step stay for the caller).
+  pic_step_stats* next_stats;
+  StepScratch* next_scratch;
+  const int32_t* n_slots;
+  int64_t* clear_charge;
+  int64_t n_clear;
 };
 
 // seq != 0: the last kernel of the launch writes the state with this

@@ -186,6 +186,8 @@ __device__ inline void report(const CgCtrl* c, CgReport* r, int64_t seq,
 __device__ inline void k_cg_resfield_body(const CgArgs& a, int reset, VB vb) {
   const DevMesh& m = a.m;
   if (reset && vb.id == 0 && threadIdx.x == 0) ctrl_reset(a.ctrl);
+  if (reset && a.acc_rows && vb.id < kStepCounters)
+    step_counter_sum(a.acc_rows, a.acc_n, a.step_stats, vb.id);
   const int lane = threadIdx.x & (kSell - 1);
   const int sub = threadIdx.x / kSell;
   const int nsub = blockDim.x / kSell;
@@ -367,6 +369,8 @@ __device__ inline void k_cg_resfield_body(const CgArgs& a, int reset, VB vb) {
 __device__ inline void k_cg_resinc_body(const CgArgs& a, VB vb) {
   const DevMesh& m = a.m;
   if (vb.id == 0 && threadIdx.x == 0) ctrl_reset(a.ctrl);
+  if (a.acc_rows && vb.id < kStepCounters)
+    step_counter_sum(a.acc_rows, a.acc_n, a.step_stats, vb.id);
   const Range rows = my_range(m.n_free, vb);
   double v[2] = {0.0, 0.0};
   for (int64_t i = rows.lo + threadIdx.x; i < rows.hi; i += blockDim.x) {
@@ -458,6 +462,22 @@ __device__ inline void k_cg_start_body(const CgArgs& a, int64_t seq, VB vb) {
       else if (a.E)
         reinterpret_cast<double4*>(a.E)[i] = make_double4(0.0, 0.0, 0.0, 0.0);
     }
+  }
+  if ((done || noconv) && a.next_stats) {
+    // the start of the next step (as k_begin does it)
+    if (vb.id == 0) {
+      int64_t* s64 = reinterpret_cast<int64_t*>(a.next_stats);
+      const int ns = (int)(sizeof(pic_step_stats) / sizeof(int64_t));
+      if (threadIdx.x < ns) s64[threadIdx.x] = 0;
+      int32_t* c32 = reinterpret_cast<int32_t*>(a.next_scratch);
+      const int nc = (int)(sizeof(StepScratch) / sizeof(int32_t));
+      if (threadIdx.x < nc) c32[threadIdx.x] = 0;
+      __syncthreads();
+      if (threadIdx.x == 0) a.next_scratch->inj_base = *a.n_slots;
+    }
+    const Range cr = my_range(a.n_clear, vb);
+    for (int64_t i = cr.lo + threadIdx.x; i < cr.hi; i += blockDim.x)
+      a.clear_charge[i] = 0;
   }
   if (done || noconv) return;
   if (a.amg) return;  // its iterations start with the V-cycle
