@@ -649,16 +649,18 @@ def run_batch_leg(args):
         f"setup {time.time() - t0:.1f}s")
     warm, K = args.batch_warmup, args.batch_steps
 
-    def states(precision):
+    def states(precision, precond=pic.PIC_PRECOND_JACOBI):
         out = []
         for c, m, kw in zip(cfgs, meshes, kws):
-            st = pic.State(m, int(2.5 * c.n_target) + 50_000, precision=precision)
+            st = pic.State(m, int(2.5 * c.n_target) + 50_000, precision=precision,
+                           precond=precond)
             st.init_field(c.E0, tol=c.tol)
             out.append(st)
         return out
 
-    # batched, mixed precision, autotuned
-    sts = states(pic.PIC_MIXED)
+    # batched, mixed precision (the FP32 V-cycle preconditioning the FP64 CG
+    # of every instance), autotuned
+    sts = states(pic.PIC_MIXED, pic.PIC_PRECOND_AMG)
     batch = pic.Batch(meshes, sts, kws)
     batch.step(0, warm)
     best = batch.autotune(warm)
@@ -676,18 +678,23 @@ def run_batch_leg(args):
     batch.close()
     del sts
     torch.cuda.empty_cache()
-    # plain FP64, one instance after another
-    sts = states(pic.PIC_FP64)
-    t_seq = 0.0
-    for st, kw in zip(sts, kws):
-        st.step(step0=0, n_steps=warm, **kw)
-        torch.cuda.synchronize()
-        w0 = time.perf_counter()
-        st.step(step0=warm, n_steps=K, **kw)
-        torch.cuda.synchronize()
-        t_seq += time.perf_counter() - w0
-    del sts
-    torch.cuda.empty_cache()
+    # plain FP64, one instance after another: with the default (Jacobi)
+    # preconditioner, and with the FP64 AMG one
+    def sequential(precond):
+        sts = states(pic.PIC_FP64, precond)
+        t = 0.0
+        for st, kw in zip(sts, kws):
+            st.step(step0=0, n_steps=warm, **kw)
+            torch.cuda.synchronize()
+            w0 = time.perf_counter()
+            st.step(step0=warm, n_steps=K, **kw)
+            torch.cuda.synchronize()
+            t += time.perf_counter() - w0
+        del sts
+        torch.cuda.empty_cache()
+        return t
+    t_seq = sequential(pic.PIC_PRECOND_JACOBI)
+    t_seq_amg = sequential(pic.PIC_PRECOND_AMG)
     for m in meshes:
         m.close()
     n = len(cfgs)
@@ -699,6 +706,9 @@ def run_batch_leg(args):
                 ms_per_batch_step=round(1e3 * t_batch / K, 4),
                 fp64_sequential_ms_per_step=round(1e3 * t_seq / K, 4),
                 speedup_vs_fp64_sequential=round(t_seq / t_batch, 4),
+                fp64_amg_sequential_ms_per_step=round(1e3 * t_seq_amg / K, 4),
+                speedup_vs_fp64_amg_sequential=round(t_seq_amg / t_batch, 4),
+                precond="amg (FP32 V-cycle in the FP64 CG)",
                 schedule=dict(push_tile=best[0], cg_rows=best[1]),
                 autotune=[dict(push_tile=a, cg_rows=b, ms=round(c, 4))
                           for a, b, c in batch.tuning])

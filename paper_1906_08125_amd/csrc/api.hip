@@ -1329,8 +1329,6 @@ pic_status pic_batch_step(pic_batch* b, const pic_particles* P,
     if (ps != PIC_OK) return ps;
     if ((P[i].precision == PIC_MIXED) != f32)
       return fail(PIC_E_ARG, "pic_batch_step: instances differ in precision");
-    if (prm[i].solve.precond != PIC_PRECOND_JACOBI)
-      return fail(PIC_E_ARG, "pic_batch_step: batched solves use the Jacobi preconditioner");
     c_push[i] = round8(std::max(sc->push_blocks[i], 8));
     c_inj[i] = round8(std::max(sc->inject_blocks[i], 8));
     c_cg[i] = round8(std::max(sc->cg_blocks[i], 8));
@@ -1365,6 +1363,8 @@ pic_status pic_batch_step(pic_batch* b, const pic_particles* P,
   char* hb = (char*)b->h_args;
   for (int i = 0; i < n; ++i) {
     StepSet ss = step_set(b->h[i], &P[i], &F[i], &prm[i], c_push[i], c_inj[i], fb);
+    pic_status ps = use_precond(b->h[i], &prm[i].solve, ss.ca, s, "pic_batch_step");
+    if (ps != PIC_OK) return ps;
     ss.ca.G = c_cg[i];
     ss.ca.report = b->h[i]->cg_report_dev;
     for (int32_t k = 0; k < n_steps; ++k) {
@@ -1443,32 +1443,65 @@ pic_status pic_batch_step(pic_batch* b, const pic_particles* P,
       return *(const fp::CgArgs*)(hb + per * k + (sa + se) * n + sg * i);
     };
     // counts: per instance (speculation) or one for all (count >= 0)
+    // Instances preconditioned by AMG -- and every instance when at most
+    // two Jacobi ones are left -- iterate in their own launches (replayed
+    // graphs; an AMG round is capped at 16 iterations, each some fifteen
+    // launches); the other Jacobi instances share batched launches.
     auto iterate = [&](const std::vector<char>& act, uint64_t mask, int count,
                        const std::vector<int>* counts) {
-      int cnt = 0;
-      for (int i = 0; i < n; ++i) cnt += act[i] ? 1 : 0;
-      if (cnt == 0) return hipSuccess;
-      hipError_t r;
-      if (cnt <= 2) {  // few instances: their own launches, full grids
-        for (int i = 0; i < n; ++i) {
-          if (!act[i]) continue;
-          const fp::CgArgs& ai = host_cg(i);
-          if ((mask >> i) & 1ull)
-            if ((r = fp::cg_launch_recheck(ai, 0, s)) != hipSuccess) return r;
-          const int c = counts ? (*counts)[i] : count;
-          if ((r = iterate_graphs(b->h[i], ai, c, s)) != hipSuccess) return r;
+      std::vector<char> own(n, 0), shared(n, 0);
+      int n_shared = 0;
+      for (int i = 0; i < n; ++i) {
+        if (!act[i]) continue;
+        if (host_cg(i).amg) {
+          own[i] = 1;
+        } else {
+          shared[i] = 1;
+          ++n_shared;
         }
-        return hipSuccess;
       }
-      if (counts)
+      if (n_shared <= 2) {
         for (int i = 0; i < n; ++i)
-          if (act[i]) count = std::max(count, (*counts)[i]);
+          if (shared[i]) own[i] = 1, shared[i] = 0;
+        n_shared = 0;
+      }
+      // an instance whose recursion has stopped gets its true-residual
+      // re-check alone this round (iterations launched behind it would
+      // mostly find the solve ended)
+      hipError_t r;
+      for (int i = 0; i < n; ++i) {
+        if (!own[i]) continue;
+        const fp::CgArgs& ai = host_cg(i);
+        if ((mask >> i) & 1ull) {
+          if ((r = fp::cg_launch_recheck(ai, 0, s)) != hipSuccess) return r;
+          continue;
+        }
+        int c = counts ? (*counts)[i] : count;
+        if (ai.amg) c = std::min(c, 16);
+        if ((r = iterate_graphs(b->h[i], ai, c, s)) != hipSuccess) return r;
+      }
+      if (n_shared == 0) return hipSuccess;
+      uint64_t smask = 0;
+      std::vector<char> iter_on(n, 0);
+      int n_iter = 0;
+      for (int i = 0; i < n; ++i) {
+        if (!shared[i]) continue;
+        smask |= 1ull << i;
+        if ((mask >> i) & 1ull) continue;
+        iter_on[i] = 1;
+        ++n_iter;
+        if (counts) count = std::max(count, (*counts)[i]);
+      }
       fp::CgBatch ca = cb;
-      ca.map = batch_map(c_cg, act);
-      ca.mask = mask;
-      const int grid = ca.map.off[ca.map.n_seg];
-      if (mask && (r = fp::cg_batch_recheck(ca, grid, s)) != hipSuccess) return r;
-      return fp::cg_batch_iters(ca, grid, count, s);
+      ca.map = batch_map(c_cg, shared);
+      ca.mask = mask & smask;
+      if (ca.mask &&
+          (r = fp::cg_batch_recheck(ca, ca.map.off[ca.map.n_seg], s)) != hipSuccess)
+        return r;
+      if (n_iter == 0) return hipSuccess;
+      ca.map = batch_map(c_cg, iter_on);
+      ca.mask = 0;
+      return fp::cg_batch_iters(ca, ca.map.off[ca.map.n_seg], count, s);
     };
     if ((e = fp::cg_batch_begin(cb, m_cg.off[m_cg.n_seg], k > 0 ? 1 : 0, s)) != hipSuccess ||
         (spec > 0 && (e = iterate(spec_on, 0, 0, &spec_n)) != hipSuccess) ||

@@ -823,7 +823,8 @@ class Batch:
                 None if kw.get("counts_in") is None else kw["counts_in"].data_ptr(),
                 None if kw.get("counts_out") is None else kw["counts_out"].data_ptr(),
                 SolveParams(kw.get("tol", 1e-10), st.inner_tol,
-                            kw.get("max_iter", 20000), st.solve_precision)))
+                            kw.get("max_iter", 20000), st.solve_precision,
+                            kw.get("precond", st.precond))))
         S = (StepParams * n)(*prms)
         sc = sched if sched is not None else self.schedule()
         _check(load_library().pic_batch_step(self._h, P, F, S, C.byref(sc),

@@ -170,3 +170,51 @@ def test_batch_held_counts(pic):
     for i in range(len(cases)):
         assert rows[i]["n_inj"] == int(held[i].sum())
         assert (outs[i].cpu().numpy() == held[i]).all()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_with_amg_instances(pic, precision):
+    """Instances preconditioned by AMG next to Jacobi ones in one batch (the
+    AMG ones iterate in their own launches; in mixed precision their V-cycle
+    runs in FP32 inside the FP64 CG): every instance against the oracle,
+    with the FP64 bounds (counts, ids, tets exact; positions and phi 1e-9)
+    or the mixed-precision ones, and fewer iterations for the AMG ones."""
+    cap, steps = 40_000, 12
+    cases = [_setup(pic, c, 0.01, 3000, cap) for c in _cases()]
+    mixed = precision == "mixed"
+    pre = [pic.PIC_PRECOND_AMG, pic.PIC_PRECOND_JACOBI, pic.PIC_PRECOND_AMG]
+    states, params = [], []
+    for (tip, om, ost, gm, kw), pc in zip(cases, pre):
+        gs = pic.State(gm, cap, precision=pic.PIC_MIXED if mixed else pic.PIC_FP64,
+                       precond=pc)
+        gs.init_field(kw["E0"], tol=kw["tol"])
+        states.append(gs)
+        params.append(dict(kw, resort_every=5))
+    batch = pic.Batch([c[3] for c in cases], states, params)
+    so_all = [[] for _ in cases]
+    sg_all = [[] for _ in cases]
+    for k in range(steps):
+        for i, (tip, om, ost, gm, kw) in enumerate(cases):
+            so_all[i].append(ost.step(step=k, **kw))
+        rows = pic.Batch.decode(batch.step(k, 1), len(cases))[0]
+        for i in range(len(cases)):
+            sg_all[i].append(rows[i])
+    torch.cuda.synchronize()
+    for i, (tip, om, ost, gm, kw) in enumerate(cases):
+        it_g = sum(s["cg_iters"] for s in sg_all[i])
+        it_o = sum(s["cg_iters"] for s in so_all[i])
+        print(i, "precond", pre[i], "iterations", it_g, "oracle", it_o)
+        assert it_o > 0
+        if pre[i] == pic.PIC_PRECOND_AMG:
+            assert it_g < it_o
+        if mixed:
+            assert _rel(states[i].phi.cpu().numpy(), ost.phi) < 1e-6
+            P, Q = states[i].live(), ost.particles()
+            common, ia, ib = np.intersect1d(P["id"], Q["id"], return_indices=True)
+            assert common.size >= 0.999 * max(P["id"].size, Q["id"].size)
+            pg = np.stack([P["x"][ia], P["y"][ia], P["z"][ia]], 1)
+            po = np.stack([Q["x"][ib], Q["y"][ib], Q["z"][ib]], 1)
+            assert _rel(pg, po) < 1e-6
+        else:
+            _compare_runs(ost, states[i], so_all[i], sg_all[i],
+                          same_solver=pre[i] == pic.PIC_PRECOND_JACOBI)
