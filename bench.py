@@ -28,29 +28,46 @@ METRIC = ("PIC steps/s & pushes/s at 3M tets/1M e-; mixed vs FP64 speedup; "
           "adjoint/fwd")
 HBM_PEAK_GBS = 8000.0
 
-# HBM traffic of the dominant kernel (FP64 push) per launch at the
-# production workload, from rocprofv3 FETCH_SIZE and WRITE_SIZE counter runs
-# scaled by a plain 1 GiB copy (profiles/pic_step_fp64_production_tip.md).
-# It is reported only while the kernel sources are the ones profiled.
+# HBM traffic from rocprofv3 FETCH_SIZE and WRITE_SIZE counter runs, scaled
+# by what the counters read for a plain 1 GiB device copy (fetch 1.9999,
+# write 1.0000).  A figure is reported only while the sources it was taken
+# on are unchanged and the run's load matches the one profiled.
+# The dominant kernel (FP64 push) per launch at the production workload
+# (profiles/pic_step_fp64_production_tip.md):
 PUSH_TRAFFIC = dict(bytes=199.2e6, read=133.8e6, written=65.4e6, live=992_300,
                     sources=("paper_1906_08125_amd/csrc/particles.hip",
                              "paper_1906_08125_amd/csrc/common.h"),
                     sha256=("26260919966f515d918ad42efa8987d440e317a7c0e7c338905a0283449d9717",
                             "7d8f3c2344d581d986633cc1e8597ea0062a3ad5736211095600e29a54930541"))
+# One step of the 32-instance batch (every dispatch between consecutive
+# batched particle launches, averaged over the timed steps;
+# profiles/pic_batch_step_32_instances.md):
+BATCH_TRAFFIC = dict(bytes=3374.5e6, read=2745.2e6, written=629.3e6,
+                     live=3_371_102,
+                     sources=("paper_1906_08125_amd/csrc/particles.hip",
+                              "paper_1906_08125_amd/csrc/solver.hip",
+                              "paper_1906_08125_amd/csrc/amg.hip",
+                              "paper_1906_08125_amd/csrc/api.hip",
+                              "paper_1906_08125_amd/csrc/common.h"),
+                     sha256=("b7adb28bfcfd54e1d6acca604cd791d13c3d2da1bed4ba2e3107d21ee005f510",
+                             "8a9839c4a8aceb567764914275820070b7a86cce52d0ace807647f0212b5d207",
+                             "0d5ab663968bfe79d3f6c96c20b601c5b1dface104743cd0f1f52a43419f9e24",
+                             "cd2c5ff7f2bd3346e05bd83f0750ce64453cf0b9e218740a4634d4c90316ec01",
+                             "df664d921b2048d0e38d5de9ccce0edb99bc52cb2a034c6b94b3b69f07cb3843"))
 
 
-def measured_traffic(live):
-    """The counters' bytes per launch, when they were taken on the kernel
-    as it is now and at the population `achieved` is measured at (within
-    5 %); else None."""
+def measured_traffic(rec, live):
+    """The counters' bytes of record `rec`, when they were taken on the
+    sources as they are now and at the population the figure it goes with
+    is measured at (within 5 %); else None."""
     import hashlib
-    for path, digest in zip(PUSH_TRAFFIC["sources"], PUSH_TRAFFIC["sha256"]):
+    for path, digest in zip(rec["sources"], rec["sha256"]):
         with open(os.path.join(ROOT, path), "rb") as f:
             if hashlib.sha256(f.read()).hexdigest() != digest:
                 return None
-    if abs(live / PUSH_TRAFFIC["live"] - 1) > 0.05:
+    if abs(live / rec["live"] - 1) > 0.05:
         return None
-    return PUSH_TRAFFIC["bytes"]
+    return rec["bytes"]
 
 
 def log(*a):
@@ -418,7 +435,7 @@ def run_gpu(args):
         roofline=dict(kernel=dom, bound="hbm", achieved=round(achieved, 1),
                       peak=HBM_PEAK_GBS, unit="GB/s",
                       frac=round(achieved / HBM_PEAK_GBS, 4),
-                      traffic=(measured_traffic(live_mean) if dom == "push"
+                      traffic=(measured_traffic(PUSH_TRAFFIC, live_mean) if dom == "push"
                                else None),
                       live_particles=round(live_mean),
                       limiter=("dependent gathers (tet record, nodal field, "
@@ -675,6 +692,24 @@ def run_batch_leg(args):
             if x["status"] != 0:
                 raise RuntimeError(f"batch step status {x['status']}")
     pushes = sum(x["n_before"] + x["n_inj"] for r in rows for x in r)
+    # algorithmic bytes of the timed batch steps: the particle streams (64 B
+    # per superparticle in mixed precision) and, per instance, the solver
+    # passes that ran (the fused residual + field pass of the call's first
+    # step, the incremental residual pass after it, a re-check pass after
+    # iterations); the V-cycle iterations themselves (a few per step over
+    # all instances) are not counted, so the figure is a lower bound
+    algo = 0.0
+    for i, m in enumerate(meshes):
+        ri = [r[i] for r in rows]
+        algo += sum(push_bytes(x["n_before"] + x["n_inj"], 4) for x in ri)
+        inf = m.info
+        n, nnz, N, nf = inf["n_free"], inf["nnz"], inf["n_nodes"], inf["nnz_field"]
+        fused = 100 * n + 36 * nnz + 28 * (nf - nnz) + 40 * (N - n)
+        algo += fused + 84 * n * (len(ri) - 1)
+        algo += sum(20 * n + fused for x in ri if x["cg_iters"] > 0)
+    batch_gbps = algo / t_batch / 1e9
+    csr_bytes = sum(12 * m.info["nnz"] + 36 * (m.info["nnz_field"]) for m in meshes)
+    live_b = sum(x["n_after"] for x in rows[-1])
     batch.close()
     del sts
     torch.cuda.empty_cache()
@@ -699,7 +734,7 @@ def run_batch_leg(args):
         m.close()
     n = len(cfgs)
     return dict(instances=n, tets=int(sum(m.n_tets for m in meshes)),
-                live_particles=int(sum(x["n_after"] for x in rows[-1])),
+                live_particles=int(live_b),
                 warmup=warm, steps=K, precision="mixed",
                 instance_steps_per_s=round(n * K / t_batch, 1),
                 pushes_per_s=round(pushes / t_batch, 1),
@@ -709,6 +744,17 @@ def run_batch_leg(args):
                 fp64_amg_sequential_ms_per_step=round(1e3 * t_seq_amg / K, 4),
                 speedup_vs_fp64_amg_sequential=round(t_seq_amg / t_batch, 4),
                 precond="amg (FP32 V-cycle in the FP64 CG)",
+                roofline=dict(bound="hbm", achieved=round(batch_gbps, 1),
+                              peak=HBM_PEAK_GBS, unit="GB/s",
+                              frac=round(batch_gbps / HBM_PEAK_GBS, 4),
+                              algo_bytes_per_step=round(algo / K),
+                              traffic=measured_traffic(BATCH_TRAFFIC, live_b),
+                              note="particle streams and solver passes over "
+                                   "the wall time of the batch steps; V-cycle "
+                                   "iterations not counted (the traffic "
+                                   "figure counts them)"),
+                operators_bytes=csr_bytes,
+                mall_resident=bool(csr_bytes < 256e6),
                 schedule=dict(push_tile=best[0], cg_rows=best[1]),
                 autotune=[dict(push_tile=a, cg_rows=b, ms=round(c, 4))
                           for a, b, c in batch.tuning])
