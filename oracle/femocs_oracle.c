@@ -11,6 +11,11 @@
  * specified operation by operation and must not be re-associated.
  *
  * Parity unpinned: om_fn_current (see the header).
+ *
+ * Built twice: the plain build (the checker of the tests) and, with
+ * -fopenmp, the timing build of the benchmark's CPU baseline.  The OpenMP
+ * pragmas sit only on loops whose iterations are independent or add
+ * integers (deposition), so both builds give bit-identical results.
  */
 #include "femocs_oracle.h"
 
@@ -18,6 +23,18 @@
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* threads of the parallel loops: 1 in the plain build */
+int om_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------------ */
 /* Physical constants, derived from CODATA 2018 base values.                 */
@@ -797,6 +814,7 @@ static int32_t locate_one(const omesh* m, const double* p, int32_t hint) {
 void om_locate(const omesh* m, int64_t n, const double* x, const double* y,
                const double* z, const int32_t* hint, int32_t* tet_out,
                uint8_t* where_out) {
+#pragma omp parallel for schedule(dynamic, 4096)
   for (int64_t i = 0; i < n; ++i) {
     double p[3] = {x[i], y[i], z[i]};
     if (p[2] >= m->z_top) {
@@ -839,6 +857,7 @@ static void particle_charge(const double* lam, double w, int64_t* q) {
 void om_deposit(const omesh* m, int64_t n, const double* x, const double* y,
                 const double* z, const int32_t* tet, const double* w,
                 int64_t* c) {
+#pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
     int32_t t = tet[i];
     if (t < 0) continue;
@@ -846,7 +865,10 @@ void om_deposit(const omesh* m, int64_t n, const double* x, const double* y,
     om_lambda(m, t, p, lam);
     int64_t q[4];
     particle_charge(lam, w[i], q);
-    for (int a = 0; a < 4; ++a) c[m->tet[4 * (int64_t)t + a]] += q[a];
+    for (int a = 0; a < 4; ++a) {
+#pragma omp atomic
+      c[m->tet[4 * (int64_t)t + a]] += q[a];
+    }
   }
 }
 
@@ -869,6 +891,7 @@ void om_rhs(const omesh* m, const int64_t* c, double w_sp, double E0,
 }
 
 void om_spmv(const omesh* m, const double* x, double* y) {
+#pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < m->n_free; ++i) {
     double s = 0.0;
     for (int64_t q = m->rowptr[i]; q < m->rowptr[i + 1]; ++q)
@@ -1347,6 +1370,7 @@ int om_pic_step(const omesh* m, oparticles* P, double* phi, double* E3,
   pr.phi = phi;
   prm = &pr;
   const double* phi_cell = prm->field_mode == 1 ? phi : NULL;
+#pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n0; ++i) {
     double p[3] = {P->x[i], P->y[i], P->z[i]}, Ep[3];
     gather(m, P->tet[i], p, E3, phi_cell, Ep);
@@ -1360,8 +1384,11 @@ int om_pic_step(const omesh* m, oparticles* P, double* phi, double* E3,
   om_inject(m, P, E3, prm, st, NULL, NULL);
   int64_t n = P->n;
 
-  /* 3. drift (Eq. leapfrog2), 4. lateral wrap, absorption, location */
-  int64_t out = 0;
+  /* 3. drift (Eq. leapfrog2), 4. lateral wrap, absorption, location: each
+   *    particle on its own (fate -2: anode, -1: cathode, else its tet),
+   *    then the survivors compacted in order */
+  int32_t* fate = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+#pragma omp parallel for schedule(dynamic, 4096)
   for (int64_t i = 0; i < n; ++i) {
     double x = P->x[i] + dt * P->vx[i];
     double y = P->y[i] + dt * P->vy[i];
@@ -1370,35 +1397,44 @@ int om_pic_step(const omesh* m, oparticles* P, double* phi, double* E3,
     else if (x < 0.0) x = x + m->Lx;
     if (y >= m->Ly) y = y - m->Ly;
     else if (y < 0.0) y = y + m->Ly;
-    int64_t q = charge_of(P->w[i]);
-    if (prm->fate_out) prm->fate_out[i] = 0;
+    P->x[i] = x;
+    P->y[i] = y;
+    P->z[i] = z;
     if (z >= m->z_top) {
-      st->n_anode++;
-      st->q_anode += q;
-      if (prm->fate_out) prm->fate_out[i] = 1;
+      fate[i] = -2;
       continue;
     }
     double p[3] = {x, y, z};
     int32_t t = locate_one(m, p, P->tet[i]);
-    if (t < 0) {
-      st->n_cathode++;
-      st->q_cathode += q;
-      if (prm->fate_out) prm->fate_out[i] = 2;
+    fate[i] = t < 0 ? -1 : t;
+  }
+  int64_t out = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t q = charge_of(P->w[i]);
+    if (prm->fate_out) prm->fate_out[i] = fate[i] == -2 ? 1 : fate[i] == -1 ? 2 : 0;
+    if (fate[i] == -2) {
+      st->n_anode++;
+      st->q_anode += q;
       continue;
     }
-    /* stable compaction */
-    P->x[out] = x;
-    P->y[out] = y;
-    P->z[out] = z;
+    if (fate[i] == -1) {
+      st->n_cathode++;
+      st->q_cathode += q;
+      continue;
+    }
+    P->x[out] = P->x[i];
+    P->y[out] = P->y[i];
+    P->z[out] = P->z[i];
     P->vx[out] = P->vx[i];
     P->vy[out] = P->vy[i];
     P->vz[out] = P->vz[i];
     P->w[out] = P->w[i];
-    P->tet[out] = t;
+    P->tet[out] = fate[i];
     P->birth[out] = P->birth[i];
     P->id[out] = P->id[i];
     ++out;
   }
+  free(fate);
   P->n = out;
   st->n_after = out;
   for (int64_t i = 0; i < out; ++i) st->q_after += charge_of(P->w[i]);

@@ -95,6 +95,10 @@ void om_constants(double* out8);
 void om_philox4x64(uint64_t k0, uint64_t k1, const uint64_t* ctr,
                    uint64_t* out4);
 
+/* Threads of the parallel loops: 1 in the plain build; in the -fopenmp
+ * timing build, OpenMP's thread count. */
+int om_threads(void);
+
 typedef struct {
   int64_t cap, n;
   double *x, *y, *z, *vx, *vy, *vz, *w;

@@ -16,6 +16,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "femocs_oracle.c")
 _LIB = os.path.join(_HERE, "libfemocs_oracle.so")
+_LIB_OMP = os.path.join(_HERE, "libfemocs_oracle_omp.so")
+_openmp = False
 
 _dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
 _i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
@@ -26,11 +28,30 @@ _u64p = np.ctypeslib.ndpointer(dtype=np.uint64, flags="C_CONTIGUOUS")
 
 
 def build(openmp: bool = False) -> str:
-    """Compile the oracle with gcc (-O2, no FMA contraction, no fast-math)."""
+    """Compile the oracle with gcc (-O2, no FMA contraction, no fast-math);
+    openmp: the timing build of the CPU baseline (-fopenmp; its parallel
+    loops give the plain build's results bit for bit)."""
+    out = _LIB_OMP if openmp else _LIB
     cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-           "-shared", "-std=c11", "-Wall", "-o", _LIB, _SRC, "-lm"]
+           "-shared", "-std=c11", "-Wall", "-Wno-unknown-pragmas"]
+    cmd += ["-fopenmp"] if openmp else []
+    cmd += ["-o", out, _SRC, "-lm"]
     subprocess.run(cmd, check=True)
-    return _LIB
+    return out
+
+
+def use_openmp() -> None:
+    """Load the -fopenmp timing build instead of the plain one (before the
+    first use of the oracle in this process)."""
+    global _openmp
+    if _lib is not None and not _openmp:
+        raise RuntimeError("the plain oracle build is already loaded")
+    _openmp = True
+
+
+def threads() -> int:
+    """Threads of the loaded build's parallel loops (1: plain build)."""
+    return int(lib().om_threads())
 
 
 _lib = None
@@ -40,12 +61,15 @@ def lib():
     global _lib
     if _lib is not None:
         return _lib
-    if (not os.path.exists(_LIB)
-            or os.path.getmtime(_LIB) < os.path.getmtime(_SRC)
-            or os.path.getmtime(_LIB) < os.path.getmtime(
+    path = _LIB_OMP if _openmp else _LIB
+    if (not os.path.exists(path)
+            or os.path.getmtime(path) < os.path.getmtime(_SRC)
+            or os.path.getmtime(path) < os.path.getmtime(
                 os.path.join(_HERE, "femocs_oracle.h"))):
-        build()
-    L = C.CDLL(_LIB)
+        build(_openmp)
+    L = C.CDLL(path)
+    L.om_threads.restype = C.c_int
+    L.om_threads.argtypes = []
     L.om_create.restype = C.c_void_p
     L.om_create.argtypes = [C.c_int64, _dp, C.c_int64, _i32p, _i8p,
                             C.c_double, C.c_double, C.c_double, C.c_double,
