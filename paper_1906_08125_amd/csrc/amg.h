@@ -1,6 +1,8 @@
 // Smoothed-aggregation algebraic multigrid as a CG preconditioner for the
 // FP64 solve (an alternative to Jacobi; the paper names no preconditioner).
 #pragma once
+#include <vector>
+
 #include "common.h"
 #include "solver.h"
 
@@ -51,6 +53,10 @@ struct AmgDev {
   float* coarse_b32;
   float* coarse_x32;
   int64_t rows[kAmgMaxLevels + 1];  // rows per level (the coarsest last)
+  // device copy of this descriptor (written last by amg_build), read by
+  // the batched launches, which find each instance's hierarchy through
+  // CgArgs::amg_dev
+  const AmgDev* dev;
 };
 
 // Builds the hierarchy of the FP64 stiffness of m on the host (strength of
@@ -70,5 +76,14 @@ hipError_t amg_build(const DevMesh& m, hipStream_t s,
 // grids sized to their rows.
 hipError_t amg_launch_iters(const CgArgs& a, const AmgDev& d, int n,
                             hipStream_t s);
+
+// n such iterations of several instances at once: every V-cycle stage (a
+// level's smoothing, restriction, prolongation; the coarse solve; the
+// product; the update) is one launch over all instances i with on[i], each
+// getting the workgroups its own launch would have.  dargs: the instances'
+// solver arguments in device memory (index i), hargs: the same on the host
+// (their amg set, all alike in amg32).
+hipError_t amg_batch_iters(const CgArgs* dargs, const std::vector<const CgArgs*>& hargs,
+                           const std::vector<char>& on, int n, hipStream_t s);
 
 }  // namespace fp

@@ -455,6 +455,11 @@ hipError_t amg_build(const DevMesh& m, hipStream_t s,
   if (!d.coarse_inv || !d.coarse_b || !d.coarse_x || !d.coarse_inv32 ||
       !d.coarse_b32 || !d.coarse_x32)
     return hipErrorOutOfMemory;
+  AmgDev* dd = (AmgDev*)alloc(ctx, sizeof(AmgDev));
+  if (!dd) return hipErrorOutOfMemory;
+  d.dev = dd;
+  if ((e = hipMemcpyAsync(dd, &d, sizeof d, hipMemcpyHostToDevice, s)) != hipSuccess)
+    return e;
   return hipStreamSynchronize(s);
 }
 

@@ -291,6 +291,7 @@ hipError_t solve_start(pic_mesh* h, fp::CgArgs& a, int spec, hipStream_t s,
   if (e != hipSuccess) return e;
   if (spec > 0) {
     if ((e = iterate_graphs(h, a, spec, s)) != hipSuccess ||
+        (e = fp::cg_launch_recheck_if(a, s)) != hipSuccess ||
         (e = fp::cg_launch_report(a, seq, s)) != hipSuccess)
       return e;
   }
@@ -314,7 +315,7 @@ hipError_t solve_finish(pic_mesh* h, const fp::CgArgs& a, int spec,
   hipError_t e = cg_wait(h, seq, r);
   if (e != hipSuccess) return e;
   if (first_state) *first_state = r.state;
-  int batch = spec;
+  int batch = spec, rounds = 0;
   for (int guard = 0; guard < (1 << 20); ++guard) {
     if (r.state == fp::CG_DONE || r.state == fp::CG_NOCONV) break;
     seq = ++h->cg_seq;
@@ -323,9 +324,18 @@ hipError_t solve_finish(pic_mesh* h, const fp::CgArgs& a, int spec,
       if ((e = fp::cg_launch_recheck(a, seq, s)) != hipSuccess) return e;
       batch = 16;
     } else {
-      // (an AMG iteration is some fifteen launches and needs few rounds)
-      batch = batch < 8 ? 8 : std::min(2 * batch, a.amg ? 32 : 256);
+      // Every round ends with the conditional re-check, so a recursion that
+      // stops inside it comes back tested.  An AMG iteration is some fifteen
+      // dependent launches and a solve needs few: after a speculated round
+      // the next ones run 1, 2, 4, ... iterations (launches past the stop
+      // cost as much as working ones); Jacobi rounds start at 8.
+      if (a.amg)
+        batch = rounds == 0 ? (spec > 0 ? 1 : 4) : std::min(2 * batch, 32);
+      else
+        batch = batch < 8 ? 8 : std::min(2 * batch, 256);
+      ++rounds;
       if ((e = iterate_graphs(h, a, batch, s)) != hipSuccess ||
+          (e = fp::cg_launch_recheck_if(a, s)) != hipSuccess ||
           (e = fp::cg_launch_report(a, seq, s)) != hipSuccess)
         return e;
     }
@@ -371,6 +381,7 @@ void* amg_alloc(void* ctx, size_t bytes) {
 pic_status use_precond(pic_mesh* h, const pic_solve_params* p, fp::CgArgs& a,
                        hipStream_t s, const char* who) {
   a.amg = nullptr;
+  a.amg_dev = nullptr;
   if (p->precond != PIC_PRECOND_AMG) return PIC_OK;
   if (!h->amg_ready) {
     std::string msg;
@@ -381,6 +392,7 @@ pic_status use_precond(pic_mesh* h, const pic_solve_params* p, fp::CgArgs& a,
     h->amg_ready = true;
   }
   a.amg = &h->amg;
+  a.amg_dev = h->amg.dev;
   // mixed precision with AMG: the CG recursion stays FP64, the V-cycle runs
   // in FP32 (no refinement restarts)
   a.amg32 = a.mixed;
@@ -1442,74 +1454,93 @@ pic_status pic_batch_step(pic_batch* b, const pic_particles* P,
     auto host_cg = [&](int i) -> const fp::CgArgs& {
       return *(const fp::CgArgs*)(hb + per * k + (sa + se) * n + sg * i);
     };
-    // counts: per instance (speculation) or one for all (count >= 0)
-    // Instances preconditioned by AMG -- and every instance when at most
-    // two Jacobi ones are left -- iterate in their own launches (replayed
-    // graphs; an AMG round is capped at 16 iterations, each some fifteen
-    // launches); the other Jacobi instances share batched launches.
+    // One round of iterations over the instances act[i].  counts: per
+    // instance (speculation), else count for the Jacobi instances and
+    // amg_count for the AMG ones.  Instances in mask have a stopped
+    // recursion and get their re-check alone this round.  Two or more AMG
+    // instances iterating share the V-cycle launches (as many iterations as
+    // the most any of them asks for, at most 16); a single one replays its
+    // own graphs.  More than two Jacobi instances share batched launches,
+    // fewer replay their own graphs.  The round ends with the conditional
+    // re-check of every instance that iterated, so one whose recursion
+    // stopped inside the round comes back tested.
     auto iterate = [&](const std::vector<char>& act, uint64_t mask, int count,
-                       const std::vector<int>* counts) {
-      std::vector<char> own(n, 0), shared(n, 0);
-      int n_shared = 0;
+                       int amg_count, const std::vector<int>* counts) {
+      auto want = [&](int i) {
+        return counts ? (*counts)[i] : host_cg(i).amg ? amg_count : count;
+      };
+      std::vector<char> amg_on(n, 0), jac_on(n, 0), iterated(n, 0);
+      int n_amg = 0, n_jac = 0, c_amg = 0, c_jac = 0;
       for (int i = 0; i < n; ++i) {
-        if (!act[i]) continue;
+        if (!act[i] || ((mask >> i) & 1ull)) continue;
         if (host_cg(i).amg) {
-          own[i] = 1;
+          amg_on[i] = 1;
+          ++n_amg;
+          c_amg = std::max(c_amg, std::min(want(i), 16));
         } else {
-          shared[i] = 1;
-          ++n_shared;
+          jac_on[i] = 1;
+          ++n_jac;
+          c_jac = std::max(c_jac, want(i));
         }
       }
-      if (n_shared <= 2) {
-        for (int i = 0; i < n; ++i)
-          if (shared[i]) own[i] = 1, shared[i] = 0;
-        n_shared = 0;
-      }
-      // an instance whose recursion has stopped gets its true-residual
-      // re-check alone this round (iterations launched behind it would
-      // mostly find the solve ended)
+      const bool amg_shared = n_amg >= 2, jac_shared = n_jac > 2;
       hipError_t r;
-      for (int i = 0; i < n; ++i) {
-        if (!own[i]) continue;
-        const fp::CgArgs& ai = host_cg(i);
-        if ((mask >> i) & 1ull) {
-          if ((r = fp::cg_launch_recheck(ai, 0, s)) != hipSuccess) return r;
-          continue;
-        }
-        int c = counts ? (*counts)[i] : count;
-        if (ai.amg) c = std::min(c, 16);
-        if ((r = iterate_graphs(b->h[i], ai, c, s)) != hipSuccess) return r;
+      // re-checks of stopped recursions
+      std::vector<char> rc_on(n, 0);
+      bool any_rc = false;
+      for (int i = 0; i < n; ++i)
+        if (act[i] && ((mask >> i) & 1ull)) rc_on[i] = any_rc = true;
+      if (any_rc) {
+        fp::CgBatch ca = cb;
+        ca.map = batch_map(c_cg, rc_on);
+        ca.mask = mask;
+        if ((r = fp::cg_batch_recheck(ca, ca.map.off[ca.map.n_seg], s)) != hipSuccess)
+          return r;
       }
-      if (n_shared == 0) return hipSuccess;
-      uint64_t smask = 0;
-      std::vector<char> iter_on(n, 0);
-      int n_iter = 0;
+      // iterations
       for (int i = 0; i < n; ++i) {
-        if (!shared[i]) continue;
-        smask |= 1ull << i;
-        if ((mask >> i) & 1ull) continue;
-        iter_on[i] = 1;
-        ++n_iter;
-        if (counts) count = std::max(count, (*counts)[i]);
+        const bool mine = (amg_on[i] && !amg_shared) || (jac_on[i] && !jac_shared);
+        if (!mine) continue;
+        const int c = host_cg(i).amg ? std::min(want(i), 16) : want(i);
+        if (c <= 0) continue;
+        if ((r = iterate_graphs(b->h[i], host_cg(i), c, s)) != hipSuccess) return r;
+        iterated[i] = 1;
       }
+      if (amg_shared && c_amg > 0) {
+        std::vector<const fp::CgArgs*> hargs(n);
+        for (int i = 0; i < n; ++i) hargs[i] = &host_cg(i);
+        if ((r = fp::amg_batch_iters(cb.args, hargs, amg_on, c_amg, s)) != hipSuccess)
+          return r;
+        for (int i = 0; i < n; ++i)
+          if (amg_on[i]) iterated[i] = 1;
+      }
+      if (jac_shared && c_jac > 0) {
+        fp::CgBatch ca = cb;
+        ca.map = batch_map(c_cg, jac_on);
+        ca.mask = 0;
+        if ((r = fp::cg_batch_iters(ca, ca.map.off[ca.map.n_seg], c_jac, s)) != hipSuccess)
+          return r;
+        for (int i = 0; i < n; ++i)
+          if (jac_on[i]) iterated[i] = 1;
+      }
+      bool any_it = false;
+      for (int i = 0; i < n; ++i) any_it = any_it || iterated[i];
+      if (!any_it) return hipSuccess;
       fp::CgBatch ca = cb;
-      ca.map = batch_map(c_cg, shared);
-      ca.mask = mask & smask;
-      if (ca.mask &&
-          (r = fp::cg_batch_recheck(ca, ca.map.off[ca.map.n_seg], s)) != hipSuccess)
-        return r;
-      if (n_iter == 0) return hipSuccess;
-      ca.map = batch_map(c_cg, iter_on);
+      ca.map = batch_map(c_cg, iterated);
       ca.mask = 0;
-      return fp::cg_batch_iters(ca, ca.map.off[ca.map.n_seg], count, s);
+      return fp::cg_batch_recheck_if(ca, ca.map.off[ca.map.n_seg], s);
     };
     if ((e = fp::cg_batch_begin(cb, m_cg.off[m_cg.n_seg], k > 0 ? 1 : 0, s)) != hipSuccess ||
-        (spec > 0 && (e = iterate(spec_on, 0, 0, &spec_n)) != hipSuccess) ||
+        (spec > 0 && (e = iterate(spec_on, 0, 0, 0, &spec_n)) != hipSuccess) ||
         (e = fp::cg_batch_report(cb, n, seq, s)) != hipSuccess ||
         (e = hipEventRecord(b->reported, s)) != hipSuccess ||
         (e = batch_wait(b, seq)) != hipSuccess)
       return hip_fail(e, "pic_batch_step solve");
-    int batch = spec;
+    // later rounds: Jacobi 8, 16, 32, ... iterations; AMG (some fifteen
+    // dependent launches per iteration, launches past the stop costing as
+    // much as working ones) 1, 2, 4, ... after a speculated round, else from 4
+    int batch = spec, amg_batch = 0;
     for (int guard = 0; guard < (1 << 20); ++guard) {
       uint64_t mask = 0;
       std::vector<char> active(n, 0);
@@ -1523,7 +1554,8 @@ pic_status pic_batch_step(pic_batch* b, const pic_particles* P,
       seq = batch_next_seq(b);
       batch = batch < 8 ? 8 : std::min(2 * batch, 256);
       if (mask) batch = std::min(batch, 16);
-      if ((e = iterate(active, mask, batch, nullptr)) != hipSuccess ||
+      amg_batch = guard == 0 ? (spec > 0 ? 1 : 4) : std::min(2 * amg_batch, 16);
+      if ((e = iterate(active, mask, batch, amg_batch, nullptr)) != hipSuccess ||
           (e = fp::cg_batch_report(cb, n, seq, s)) != hipSuccess ||
           (e = hipEventRecord(b->reported, s)) != hipSuccess ||
           (e = batch_wait(b, seq)) != hipSuccess)

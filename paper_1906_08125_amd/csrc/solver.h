@@ -21,6 +21,9 @@ struct CgCtrl {
   // instance): it_a is read by upd and written by spmv, it_b the reverse,
   // so no kernel reads a counter that the same launch writes
   int32_t it_a, it_b;
+  // set by the resfield pass of a conditional re-check (1: the recursion
+  // had stopped, the re-check runs) and read by the start pass after it
+  int32_t rc_gate, pad;
 };
 
 // Host-visible report of the control word (pinned, device-mapped memory).
@@ -77,6 +80,7 @@ struct CgArgs {
   // (mixed = 0), and amg32 runs the V-cycle in FP32
   const void* amg;
   int amg32;
+  const void* amg_dev;    // device copy of that AmgDev (batched launches)
   CgReport* report;       // host-mapped report record (device address)
   const int32_t* dir_nodes;
   int64_t n_dir;
@@ -105,6 +109,11 @@ hipError_t cg_launch_begin(const CgArgs& a, int64_t seq, hipStream_t s);
 hipError_t cg_launch_iters(const CgArgs& a, int it0, int n, int64_t seq,
                            hipStream_t s);
 hipError_t cg_launch_recheck(const CgArgs& a, int64_t seq, hipStream_t s);
+// the same re-check, done only if the recursion has stopped (state
+// CG_RECHECK; decided on the device, no report): ends a round of
+// iterations so that a solve whose recursion stopped in it comes out of the
+// round with its true-residual test done
+hipError_t cg_launch_recheck_if(const CgArgs& a, hipStream_t s);
 // n iterations numbered by the device counters (no report)
 hipError_t cg_launch_iters_dev(const CgArgs& a, int n, hipStream_t s);
 // the control state with sequence number seq into a.report
@@ -124,6 +133,8 @@ hipError_t cg_batch_begin(const CgBatch& b, int grid, int incremental,
                           hipStream_t s);
 hipError_t cg_batch_iters(const CgBatch& b, int grid, int n, hipStream_t s);
 hipError_t cg_batch_recheck(const CgBatch& b, int grid, hipStream_t s);
+// cg_launch_recheck_if for every instance of the map
+hipError_t cg_batch_recheck_if(const CgBatch& b, int grid, hipStream_t s);
 // reports instances 0 .. n - 1 (all of the batch, whatever the map)
 hipError_t cg_batch_report(const CgBatch& b, int n, int64_t seq, hipStream_t s);
 

@@ -33,6 +33,8 @@
 // matrix, which keeps neighbour gathers in one L2.
 #include "amg.h"
 
+#include <algorithm>
+#include <cstring>
 #include <type_traits>
 #include "common.h"
 #include "solver.h"
@@ -163,6 +165,7 @@ __device__ inline void ctrl_reset(CgCtrl* c) {
   z.alpha[0] = z.alpha[1] = 0.0;
   z.gamma[0] = z.gamma[1] = 0.0;
   z.it_a = z.it_b = 0;
+  z.rc_gate = z.pad = 0;
   *c = z;
 }
 
@@ -183,7 +186,15 @@ __device__ inline void report(const CgCtrl* c, CgReport* r, int64_t seq,
 // with R in FP32: the differences are of the size of E h, so rounding R
 // costs a relative error of about 2^-24 in E, while R_ij phi_j alone would
 // lose the ratio |phi| / (|E| h) to cancellation.
-__device__ inline void k_cg_resfield_body(const CgArgs& a, int reset, VB vb) {
+// dev_gate (re-check passes only): run only if the recursion has stopped;
+// workgroup 0 records the decision for the start pass that follows.
+__device__ inline void k_cg_resfield_body(const CgArgs& a, int reset, VB vb,
+                                          int dev_gate = 0) {
+  if (dev_gate) {
+    const bool on = a.ctrl->state == CG_RECHECK;
+    if (vb.id == 0 && threadIdx.x == 0) a.ctrl->rc_gate = on ? 1 : 0;
+    if (!on) return;
+  }
   const DevMesh& m = a.m;
   if (reset && vb.id == 0 && threadIdx.x == 0) ctrl_reset(a.ctrl);
   if (reset && a.acc_rows && vb.id < kStepCounters)
@@ -393,8 +404,10 @@ __device__ inline void k_cg_resinc_body(const CgArgs& a, VB vb) {
   write_partials<2>(slot(a, 0), a.G, v, vb);
 }
 
-// phi = x on the free nodes (before a re-check pass).
-__device__ inline void k_cg_scatter_body(const CgArgs& a, VB vb) {
+// phi = x on the free nodes (before a re-check pass; dev_gate: only if the
+// recursion has stopped).
+__device__ inline void k_cg_scatter_body(const CgArgs& a, VB vb, int dev_gate = 0) {
+  if (dev_gate && a.ctrl->state != CG_RECHECK) return;
   const DevMesh& m = a.m;
   const Range rows = my_range(m.n_free, vb);
   for (int64_t i = rows.lo + threadIdx.x; i < rows.hi; i += blockDim.x)
@@ -407,8 +420,12 @@ __device__ inline void k_cg_scatter_body(const CgArgs& a, VB vb) {
 // bb, relres, rstart, restarts) are never read by other workgroups of this
 // launch; they read iters_final, which is stable here.  A zero right-hand
 // side gives phi = 0 and E = 0, written by every workgroup.
-__device__ inline void k_cg_start_body(const CgArgs& a, int64_t seq, VB vb) {
+// dev_gate: only where the resfield pass before it ran (rc_gate; the state
+// itself is rewritten by workgroup 0 here).
+__device__ inline void k_cg_start_body(const CgArgs& a, int64_t seq, VB vb,
+                                       int dev_gate = 0) {
   CgCtrl* c = a.ctrl;
+  if (dev_gate && !c->rc_gate) return;
   double t[2];
   totals<2>(slot(a, 0), a.G, a.G, t);
   const double bn = sqrt(t[0]);
@@ -621,17 +638,19 @@ __device__ inline void k_cg_spmv_body(const CgArgs& a, int it,
 }
 
 // Single-instance kernels.
-__global__ void __launch_bounds__(kCgBlock) k_cg_resfield(CgArgs a, int reset) {
-  k_cg_resfield_body(a, reset, VB{(int)blockIdx.x, (int)gridDim.x});
+__global__ void __launch_bounds__(kCgBlock) k_cg_resfield(CgArgs a, int reset,
+                                                         int dev_gate) {
+  k_cg_resfield_body(a, reset, VB{(int)blockIdx.x, (int)gridDim.x}, dev_gate);
 }
-__global__ void __launch_bounds__(kCgBlock) k_cg_scatter(CgArgs a) {
-  k_cg_scatter_body(a, VB{(int)blockIdx.x, (int)gridDim.x});
+__global__ void __launch_bounds__(kCgBlock) k_cg_scatter(CgArgs a, int dev_gate) {
+  k_cg_scatter_body(a, VB{(int)blockIdx.x, (int)gridDim.x}, dev_gate);
 }
 __global__ void __launch_bounds__(kCgBlock) k_cg_resinc(CgArgs a) {
   k_cg_resinc_body(a, VB{(int)blockIdx.x, (int)gridDim.x});
 }
-__global__ void __launch_bounds__(kCgBlock) k_cg_start(CgArgs a, int64_t seq) {
-  k_cg_start_body(a, seq, VB{(int)blockIdx.x, (int)gridDim.x});
+__global__ void __launch_bounds__(kCgBlock) k_cg_start(CgArgs a, int64_t seq,
+                                                      int dev_gate) {
+  k_cg_start_body(a, seq, VB{(int)blockIdx.x, (int)gridDim.x}, dev_gate);
 }
 __global__ void __launch_bounds__(kCgBlock) k_cg_upd(CgArgs a, int it) {
   k_cg_upd_body(a, it, VB{(int)blockIdx.x, (int)gridDim.x});
@@ -648,14 +667,15 @@ __global__ void k_cg_report(CgArgs a, int64_t seq) {
 }
 
 // Batched kernels: block -> (instance, virtual block) by the schedule.
-// gated: skip the instances outside the mask (re-check launches).
+// gated (re-check launches): 1 skips the instances outside the mask, 2
+// leaves the decision to each instance's state (conditional re-check).
 __global__ void __launch_bounds__(kCgBlock) k_cg_resfield_b(CgBatch b, int reset,
                                                            int gated) {
   int i;
   const VB vb = batch_block(b.map, i);
-  if (gated && !((b.mask >> i) & 1ull)) return;
+  if (gated == 1 && !((b.mask >> i) & 1ull)) return;
   const CgArgs a = b.args[i];  // a private copy: no aliasing with the stores
-  k_cg_resfield_body(a, reset, vb);
+  k_cg_resfield_body(a, reset, vb, gated == 2);
 }
 __global__ void __launch_bounds__(kCgBlock) k_cg_resinc_b(CgBatch b) {
   int i;
@@ -663,19 +683,19 @@ __global__ void __launch_bounds__(kCgBlock) k_cg_resinc_b(CgBatch b) {
   const CgArgs a = b.args[i];
   k_cg_resinc_body(a, vb);
 }
-__global__ void __launch_bounds__(kCgBlock) k_cg_scatter_b(CgBatch b) {
+__global__ void __launch_bounds__(kCgBlock) k_cg_scatter_b(CgBatch b, int gated) {
   int i;
   const VB vb = batch_block(b.map, i);
-  if (!((b.mask >> i) & 1ull)) return;
+  if (gated == 1 && !((b.mask >> i) & 1ull)) return;
   const CgArgs a = b.args[i];
-  k_cg_scatter_body(a, vb);
+  k_cg_scatter_body(a, vb, gated == 2);
 }
 __global__ void __launch_bounds__(kCgBlock) k_cg_start_b(CgBatch b, int gated) {
   int i;
   const VB vb = batch_block(b.map, i);
-  if (gated && !((b.mask >> i) & 1ull)) return;
+  if (gated == 1 && !((b.mask >> i) & 1ull)) return;
   const CgArgs a = b.args[i];
-  k_cg_start_body(a, 0, vb);
+  k_cg_start_body(a, 0, vb, gated == 2);
 }
 __global__ void __launch_bounds__(kCgBlock) k_cg_upd_b(CgBatch b) {
   int i;
@@ -811,10 +831,9 @@ __host__ __device__ inline LevelVecs<T> level_vecs(const AmgLevel& L) {
 // r = b - A x = b - w sum_j a_ij d_j^-1 b_j.  On the finest level b is the
 // CG residual (FP64; rounded once to T).
 template <typename T>
-__global__ void __launch_bounds__(kCgBlock) k_amg_down(CgArgs a, AmgLevel L,
-                                                       int level) {
+__device__ inline void amg_down_body(const CgArgs& a, const AmgLevel& L,
+                                     int level, VB vb) {
   if (a.ctrl->state != CG_ITER) return;
-  const VB vb{(int)blockIdx.x, (int)gridDim.x};
   if (level == 0 && amg_stop(a, vb)) return;
   const LevelVecs<T> V = level_vecs<T>(L);
   const double* __restrict__ r64 = a.r;
@@ -832,22 +851,18 @@ __global__ void __launch_bounds__(kCgBlock) k_amg_down(CgArgs a, AmgLevel L,
 
 // y = M x for the rows of M (restriction and prolongation; add: y += M x).
 template <typename T>
-__global__ void __launch_bounds__(kCgBlock) k_amg_apply(CgArgs a, SellMat M,
-                                                        const T* x, T* y,
-                                                        int add) {
+__device__ inline void amg_apply_body(const CgArgs& a, const SellMat& M,
+                                      const T* x, T* y, int add, VB vb) {
   if (a.ctrl->state != CG_ITER) return;
-  const VB vb{(int)blockIdx.x, (int)gridDim.x};
   amg_rows<T>(M, vb, [&](int32_t c) { return x[c]; },
               [&](int64_t r, T v) { y[r] = add ? y[r] + v : v; });
 }
 
 // Coarsest level: x = A^-1 b with the dense inverse, one wave per row.
 template <typename T>
-__global__ void __launch_bounds__(kCgBlock) k_amg_coarse(CgArgs a, int64_t n,
-                                                         const T* inv,
-                                                         const T* b, T* x) {
+__device__ inline void amg_coarse_body(const CgArgs& a, int64_t n, const T* inv,
+                                       const T* b, T* x, VB vb) {
   if (a.ctrl->state != CG_ITER) return;
-  const VB vb{(int)blockIdx.x, (int)gridDim.x};
   const Range rows = my_range(n, vb);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int64_t i0 = rows.lo; i0 < rows.hi; i0 += blockDim.x >> 6) {
@@ -863,10 +878,9 @@ __global__ void __launch_bounds__(kCgBlock) k_amg_coarse(CgArgs a, int64_t n,
 // Post-smoothing: out = x + w D^-1 (b - A x); on the finest level out is
 // the CG vector u (FP64) and the workgroups write their share of (r,u).
 template <typename T>
-__global__ void __launch_bounds__(kCgBlock) k_amg_post(CgArgs a, AmgLevel L,
-                                                       int level) {
+__device__ inline void amg_post_body(const CgArgs& a, const AmgLevel& L,
+                                     int level, VB vb) {
   if (a.ctrl->state != CG_ITER) return;
-  const VB vb{(int)blockIdx.x, (int)gridDim.x};
   const LevelVecs<T> V = level_vecs<T>(L);
   const double* __restrict__ r64 = a.r;
   const T* __restrict__ x = V.x;
@@ -887,10 +901,9 @@ __global__ void __launch_bounds__(kCgBlock) k_amg_post(CgArgs a, AmgLevel L,
 }
 
 // w = K u and (w,u); it_b = it_a.
-__global__ void __launch_bounds__(kCgBlock) k_amg_spmv(CgArgs a) {
+__device__ inline void amg_spmv_body(const CgArgs& a, VB vb) {
   CgCtrl* c = a.ctrl;
   if (c->state != CG_ITER) return;
-  const VB vb{(int)blockIdx.x, (int)gridDim.x};
   const int it = c->it_a;
   if (vb.id == 0 && threadIdx.x == 0) c->it_b = it;
   const DevMesh& m = a.m;
@@ -905,10 +918,9 @@ __global__ void __launch_bounds__(kCgBlock) k_amg_spmv(CgArgs a) {
 
 // Scalars of iteration it from (r,u) and (w,u), then p, s, x, r and (r,r);
 // it_a = it + 1.
-__global__ void __launch_bounds__(kCgBlock) k_amg_upd(CgArgs a) {
+__device__ inline void amg_upd_body(const CgArgs& a, VB vb) {
   CgCtrl* c = a.ctrl;
   if (c->state != CG_ITER) return;
-  const VB vb{(int)blockIdx.x, (int)gridDim.x};
   const int it = c->it_b;
   const int pb = it & 1;
   double t1[1], t2[1];
@@ -941,6 +953,116 @@ __global__ void __launch_bounds__(kCgBlock) k_amg_upd(CgArgs a) {
     v[0] += ri * ri;
   }
   write_partials<1>(slot(a, 4 + 2 * pb), a.G, v, vb);
+}
+
+// One instance: the level, matrix and vectors come as kernel arguments.
+template <typename T>
+__global__ void __launch_bounds__(kCgBlock) k_amg_down(CgArgs a, AmgLevel L,
+                                                       int level) {
+  amg_down_body<T>(a, L, level, VB{(int)blockIdx.x, (int)gridDim.x});
+}
+template <typename T>
+__global__ void __launch_bounds__(kCgBlock) k_amg_apply(CgArgs a, SellMat M,
+                                                        const T* x, T* y,
+                                                        int add) {
+  amg_apply_body<T>(a, M, x, y, add, VB{(int)blockIdx.x, (int)gridDim.x});
+}
+template <typename T>
+__global__ void __launch_bounds__(kCgBlock) k_amg_coarse(CgArgs a, int64_t n,
+                                                         const T* inv,
+                                                         const T* b, T* x) {
+  amg_coarse_body<T>(a, n, inv, b, x, VB{(int)blockIdx.x, (int)gridDim.x});
+}
+template <typename T>
+__global__ void __launch_bounds__(kCgBlock) k_amg_post(CgArgs a, AmgLevel L,
+                                                       int level) {
+  amg_post_body<T>(a, L, level, VB{(int)blockIdx.x, (int)gridDim.x});
+}
+__global__ void __launch_bounds__(kCgBlock) k_amg_spmv(CgArgs a) {
+  amg_spmv_body(a, VB{(int)blockIdx.x, (int)gridDim.x});
+}
+__global__ void __launch_bounds__(kCgBlock) k_amg_upd(CgArgs a) {
+  amg_upd_body(a, VB{(int)blockIdx.x, (int)gridDim.x});
+}
+
+// Several instances: block -> (instance, virtual block) by the schedule;
+// each instance's hierarchy is read from the device copy of its AmgDev.
+struct AmgBatch {
+  const CgArgs* args;
+  BatchMap map;
+};
+
+template <typename T>
+__device__ inline T* coarse_vec(const AmgDev& D, int which) {
+  if constexpr (std::is_same<T, float>::value)
+    return which ? D.coarse_x32 : D.coarse_b32;
+  else
+    return which ? D.coarse_x : D.coarse_b;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kCgBlock) k_amg_down_b(AmgBatch b, int level) {
+  int i;
+  const VB vb = batch_block(b.map, i);
+  const CgArgs a = b.args[i];
+  const AmgLevel L = ((const AmgDev*)a.amg_dev)->lv[level];
+  amg_down_body<T>(a, L, level, vb);
+}
+// restriction of level l's residual into the next level's right-hand side
+template <typename T>
+__global__ void __launch_bounds__(kCgBlock) k_amg_restrict_b(AmgBatch b, int level) {
+  int i;
+  const VB vb = batch_block(b.map, i);
+  const CgArgs a = b.args[i];
+  const AmgDev* D = (const AmgDev*)a.amg_dev;
+  const AmgLevel& L = D->lv[level];
+  T* nb = level + 1 < D->n_levels ? level_vecs<T>(D->lv[level + 1]).b
+                                  : coarse_vec<T>(*D, 0);
+  amg_apply_body<T>(a, L.R, (const T*)level_vecs<T>(L).r, nb, 0, vb);
+}
+// the coarse correction of level l added to its pre-smoothed iterate
+template <typename T>
+__global__ void __launch_bounds__(kCgBlock) k_amg_prolong_b(AmgBatch b, int level) {
+  int i;
+  const VB vb = batch_block(b.map, i);
+  const CgArgs a = b.args[i];
+  const AmgDev* D = (const AmgDev*)a.amg_dev;
+  const AmgLevel& L = D->lv[level];
+  const T* y = level + 1 < D->n_levels ? level_vecs<T>(D->lv[level + 1]).t
+                                       : coarse_vec<T>(*D, 1);
+  amg_apply_body<T>(a, L.P, y, level_vecs<T>(L).x, 1, vb);
+}
+template <typename T>
+__global__ void __launch_bounds__(kCgBlock) k_amg_coarse_b(AmgBatch b) {
+  int i;
+  const VB vb = batch_block(b.map, i);
+  const CgArgs a = b.args[i];
+  const AmgDev* D = (const AmgDev*)a.amg_dev;
+  const T* inv;
+  if constexpr (std::is_same<T, float>::value) inv = D->coarse_inv32;
+  else inv = D->coarse_inv;
+  amg_coarse_body<T>(a, D->n_coarse, inv, coarse_vec<T>(*D, 0),
+                     coarse_vec<T>(*D, 1), vb);
+}
+template <typename T>
+__global__ void __launch_bounds__(kCgBlock) k_amg_post_b(AmgBatch b, int level) {
+  int i;
+  const VB vb = batch_block(b.map, i);
+  const CgArgs a = b.args[i];
+  const AmgLevel L = ((const AmgDev*)a.amg_dev)->lv[level];
+  amg_post_body<T>(a, L, level, vb);
+}
+__global__ void __launch_bounds__(kCgBlock) k_amg_spmv_b(AmgBatch b) {
+  int i;
+  const VB vb = batch_block(b.map, i);
+  const CgArgs a = b.args[i];
+  amg_spmv_body(a, vb);
+}
+__global__ void __launch_bounds__(kCgBlock) k_amg_upd_b(AmgBatch b) {
+  int i;
+  const VB vb = batch_block(b.map, i);
+  const CgArgs a = b.args[i];
+  amg_upd_body(a, vb);
 }
 
 namespace {
@@ -1017,6 +1139,95 @@ hipError_t amg_launch_iters(const CgArgs& a, const AmgDev& d, int n,
   return a.amg32 ? amg_iters_t<float>(a, d, n, s) : amg_iters_t<double>(a, d, n, s);
 }
 
+namespace {
+
+// Workgroups of one dense coarse solve: one wave per row.
+int coarse_grid(const CgArgs& a, int64_t n_coarse) {
+  return (int)std::min<int64_t>(
+      a.G, std::max<int64_t>(8, (n_coarse + kCgBlock / 64 - 1) / (kCgBlock / 64)));
+}
+
+// Schedule over the instances with on[i] and count(i) > 0 workgroups.
+template <typename F>
+BatchMap sched(const std::vector<char>& on, F&& count) {
+  BatchMap m;
+  std::memset(&m, 0, sizeof m);
+  int j = 0;
+  for (size_t i = 0; i < on.size(); ++i) {
+    if (!on[i]) continue;
+    const int c = count((int)i);
+    if (c <= 0) continue;
+    m.inst[j] = (int8_t)i;
+    m.off[j + 1] = m.off[j] + c;
+    ++j;
+  }
+  m.n_seg = j;
+  return m;
+}
+
+template <typename T>
+hipError_t amg_batch_t(const CgArgs* dargs, const std::vector<const CgArgs*>& hargs,
+                       const std::vector<char>& on, int n, hipStream_t s) {
+  const dim3 blk(kCgBlock);
+  auto hier = [&](int i) -> const AmgDev& { return *(const AmgDev*)hargs[i]->amg; };
+  int L = 0;
+  for (size_t i = 0; i < on.size(); ++i)
+    if (on[i]) L = std::max(L, hier((int)i).n_levels);
+  BatchMap mA[kAmgMaxLevels], mR[kAmgMaxLevels], mP[kAmgMaxLevels];
+  for (int l = 0; l < L; ++l) {
+    mA[l] = sched(on, [&](int i) {
+      const AmgDev& d = hier(i);
+      return l >= d.n_levels ? 0 : l == 0 ? hargs[i]->G : amg_grid(*hargs[i], d.lv[l].A);
+    });
+    mR[l] = sched(on, [&](int i) {
+      const AmgDev& d = hier(i);
+      return l >= d.n_levels ? 0 : amg_grid(*hargs[i], d.lv[l].R);
+    });
+    mP[l] = sched(on, [&](int i) {
+      const AmgDev& d = hier(i);
+      return l >= d.n_levels ? 0 : amg_grid(*hargs[i], d.lv[l].P);
+    });
+  }
+  const BatchMap mC = sched(on, [&](int i) { return coarse_grid(*hargs[i], hier(i).n_coarse); });
+  const BatchMap mG = sched(on, [&](int i) { return hargs[i]->G; });
+  auto grid = [](const BatchMap& m) { return m.off[m.n_seg]; };
+  auto B = [&](const BatchMap& m) { return AmgBatch{dargs, m}; };
+  for (int k = 0; k < n; ++k) {
+    for (int l = 0; l < L; ++l) {
+      if (grid(mA[l])) hipLaunchKernelGGL(k_amg_down_b<T>, dim3(grid(mA[l])), blk, 0, s, B(mA[l]), l);
+      if (grid(mR[l])) hipLaunchKernelGGL(k_amg_restrict_b<T>, dim3(grid(mR[l])), blk, 0, s, B(mR[l]), l);
+    }
+    if (grid(mC)) hipLaunchKernelGGL(k_amg_coarse_b<T>, dim3(grid(mC)), blk, 0, s, B(mC));
+    for (int l = L - 1; l >= 0; --l) {
+      if (grid(mP[l])) hipLaunchKernelGGL(k_amg_prolong_b<T>, dim3(grid(mP[l])), blk, 0, s, B(mP[l]), l);
+      if (grid(mA[l])) hipLaunchKernelGGL(k_amg_post_b<T>, dim3(grid(mA[l])), blk, 0, s, B(mA[l]), l);
+    }
+    if (grid(mG)) {
+      hipLaunchKernelGGL(k_amg_spmv_b, dim3(grid(mG)), blk, 0, s, B(mG));
+      hipLaunchKernelGGL(k_amg_upd_b, dim3(grid(mG)), blk, 0, s, B(mG));
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t amg_batch_iters(const CgArgs* dargs, const std::vector<const CgArgs*>& hargs,
+                           const std::vector<char>& on, int n, hipStream_t s) {
+  int f32 = -1;
+  for (size_t i = 0; i < on.size(); ++i) {
+    if (!on[i]) continue;
+    if (!hargs[i]->amg || !hargs[i]->amg_dev) return hipErrorInvalidValue;
+    if (f32 >= 0 && f32 != hargs[i]->amg32) return hipErrorInvalidValue;
+    f32 = hargs[i]->amg32;
+  }
+  if (f32 < 0 || n <= 0) return hipSuccess;
+  return f32 ? amg_batch_t<float>(dargs, hargs, on, n, s)
+             : amg_batch_t<double>(dargs, hargs, on, n, s);
+}
+
 #define LAUNCH(kern, ...)                                                   \
   do {                                                                      \
     hipLaunchKernelGGL(kern, dim3(a.G), dim3(kCgBlock), 0, s, __VA_ARGS__); \
@@ -1028,8 +1239,8 @@ hipError_t cg_launch_begin(const CgArgs& a, int64_t seq, hipStream_t s) {
   if (a.incremental && !a.rhs && a.bprev)
     LAUNCH(k_cg_resinc, a);
   else
-    LAUNCH(k_cg_resfield, a, 1);
-  LAUNCH(k_cg_start, a, seq);
+    LAUNCH(k_cg_resfield, a, 1, 0);
+  LAUNCH(k_cg_start, a, seq, 0);
   return hipSuccess;
 }
 
@@ -1056,9 +1267,16 @@ hipError_t cg_launch_iters_dev(const CgArgs& a, int n, hipStream_t s) {
 }
 
 hipError_t cg_launch_recheck(const CgArgs& a, int64_t seq, hipStream_t s) {
-  LAUNCH(k_cg_scatter, a);
-  LAUNCH(k_cg_resfield, a, 0);
-  LAUNCH(k_cg_start, a, seq);
+  LAUNCH(k_cg_scatter, a, 0);
+  LAUNCH(k_cg_resfield, a, 0, 0);
+  LAUNCH(k_cg_start, a, seq, 0);
+  return hipSuccess;
+}
+
+hipError_t cg_launch_recheck_if(const CgArgs& a, hipStream_t s) {
+  LAUNCH(k_cg_scatter, a, 1);
+  LAUNCH(k_cg_resfield, a, 0, 1);
+  LAUNCH(k_cg_start, a, (int64_t)0, 1);
   return hipSuccess;
 }
 
@@ -1088,9 +1306,16 @@ hipError_t cg_batch_iters(const CgBatch& b, int grid, int n, hipStream_t s) {
 }
 
 hipError_t cg_batch_recheck(const CgBatch& b, int grid, hipStream_t s) {
-  BLAUNCH(k_cg_scatter_b, b);
+  BLAUNCH(k_cg_scatter_b, b, 1);
   BLAUNCH(k_cg_resfield_b, b, 0, 1);
   BLAUNCH(k_cg_start_b, b, 1);
+  return hipSuccess;
+}
+
+hipError_t cg_batch_recheck_if(const CgBatch& b, int grid, hipStream_t s) {
+  BLAUNCH(k_cg_scatter_b, b, 2);
+  BLAUNCH(k_cg_resfield_b, b, 0, 2);
+  BLAUNCH(k_cg_start_b, b, 2);
   return hipSuccess;
 }
 

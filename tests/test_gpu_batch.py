@@ -172,17 +172,21 @@ def test_batch_held_counts(pic):
         assert (outs[i].cpu().numpy() == held[i]).all()
 
 
+@pytest.mark.parametrize("layout", ["amg_jacobi_amg", "all_amg"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_batch_with_amg_instances(pic, precision):
-    """Instances preconditioned by AMG next to Jacobi ones in one batch (the
-    AMG ones iterate in their own launches; in mixed precision their V-cycle
-    runs in FP32 inside the FP64 CG): every instance against the oracle,
-    with the FP64 bounds (counts, ids, tets exact; positions and phi 1e-9)
-    or the mixed-precision ones, and fewer iterations for the AMG ones."""
+def test_batch_with_amg_instances(pic, precision, layout):
+    """Instances preconditioned by AMG, next to a Jacobi one or all of them,
+    in one batch (AMG instances iterating in the same round share the
+    V-cycle launches, each stage one launch over their hierarchies of
+    different depths; in mixed precision the V-cycle runs in FP32 inside the
+    FP64 CG): every instance against the oracle, with the FP64 bounds
+    (counts, ids, tets exact; positions and phi 1e-9) or the mixed-precision
+    ones, and fewer iterations for the AMG ones."""
     cap, steps = 40_000, 12
     cases = [_setup(pic, c, 0.01, 3000, cap) for c in _cases()]
     mixed = precision == "mixed"
-    pre = [pic.PIC_PRECOND_AMG, pic.PIC_PRECOND_JACOBI, pic.PIC_PRECOND_AMG]
+    A, J = pic.PIC_PRECOND_AMG, pic.PIC_PRECOND_JACOBI
+    pre = [A, J, A] if layout == "amg_jacobi_amg" else [A, A, A]
     states, params = [], []
     for (tip, om, ost, gm, kw), pc in zip(cases, pre):
         gs = pic.State(gm, cap, precision=pic.PIC_MIXED if mixed else pic.PIC_FP64,

@@ -23,8 +23,8 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-@pytest.fixture(scope="module")
-def batch():
+@pytest.fixture(scope="module", params=["jacobi", "amg"])
+def batch(request):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_1906_08125_amd import pic
@@ -48,7 +48,9 @@ def batch():
         rate, _ = gm.emission_rate(E, c.phi_w)
         w_sp = rate.item() * c.dt * c.transit_steps / c.n_target
         st = pic.State(gm, int(2.5 * c.n_target) + 50_000,
-                       precision=pic.PIC_MIXED)
+                       precision=pic.PIC_MIXED,
+                       precond=pic.PIC_PRECOND_AMG if request.param == "amg"
+                       else pic.PIC_PRECOND_JACOBI)
         st.init_field(c.E0, tol=c.tol)
         kw = dict(dt=c.dt, E0=c.E0, w_sp=w_sp, phi_w=c.phi_w, seed=c.seed,
                   instance=i, tol=c.tol, resort_every=10)
