@@ -431,12 +431,20 @@ PIC_API pic_status collide(pic_mesh* mesh, const pic_particles* particles,
 /* sum_f Q_f (the printed normalisation condition, a sum over faces, would  */
 /* not conserve charge); d_fj from the face centroid, minimum image in x    */
 /* and y.  Charges in e.                                                    */
+/* Cutoff: when the periodic box holds a sphere of 40 r_c plus a cell of    */
+/* 10 r_c (the production tip at r_c = 0.1 nm), pairs with                  */
+/* d_fj - min_j' d_fj' > 40 r_c are left out of both sums (found through    */
+/* a cell grid of the atoms and face centroids); each face then loses less  */
+/* than n_atoms e^-40 (4.2e-18 n_atoms) of its charge, and sum_j q_j =      */
+/* sum_f Q_f still holds to rounding.  Otherwise every pair is summed.      */
 /* fields: phi (cell mode) or E (nodal mode; FP64, or FP32 when precision   */
 /* is PIC_MIXED).  face_Q: device [n_emit] out; atom_q: device [n_atoms]    */
 /* out (may be NULL when n_atoms is 0).  Uses a per-handle scratch, grown   */
-/* on demand (two doubles per face plus one per atom and face range, at    */
-/* most 1024 ranges).  PIC_E_ARG for null pointers,                         */
-/* n_atoms outside [0, 2^31), r_c <= 0 or an unknown mode or precision.     */
+/* on demand (all pairs: two doubles per face plus one per atom and face    */
+/* range, at most 1024 ranges; cutoff: in addition the cell grid, 6 doubles */
+/* and 4 ints per face, 3 doubles and 4 ints per atom).  PIC_E_ARG for null */
+/* pointers, n_atoms outside [0, 2^31), r_c <= 0 or an unknown mode or     */
+/* precision.                                                               */
 /* ------------------------------------------------------------------------ */
 typedef struct {
   int64_t n_atoms;

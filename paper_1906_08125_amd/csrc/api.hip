@@ -918,7 +918,17 @@ pic_status surface_charge(pic_mesh* h, const pic_fields* F,
     return fail(PIC_E_ARG, "surface_charge: null field array");
   hipStream_t s = (hipStream_t)stream;
   const int n_split = fp::charge_splits(h->dm.n_emit, prm->n_atoms, h->n_cu);
-  const size_t need = 2 * (size_t)h->dm.n_emit + (size_t)n_split * (size_t)prm->n_atoms;
+  fp::ChargeArgs a;
+  std::memset(&a, 0, sizeof a);
+  // the cutoff path when there are atoms and faces and the box holds the
+  // cutoff sphere (else every pair)
+  if (prm->n_atoms > 0 && h->dm.n_emit > 0) (void)fp::charge_cut_plan(h->dm, prm->r_c, a);
+  const size_t n_dbl = 2 * (size_t)h->dm.n_emit + (size_t)n_split * (size_t)prm->n_atoms;
+  // (cutoff path: sorted atom coordinates, face centroids and three face
+  // results by position)
+  const size_t n_cen = a.cut ? 3 * (size_t)prm->n_atoms + 6 * (size_t)h->dm.n_emit : 0;
+  const size_t n_int = a.cut ? fp::charge_cut_ints(a, prm->n_atoms, h->dm.n_emit) : 0;
+  const size_t need = n_dbl + n_cen + (n_int + 1) / 2;
   if (need > h->charge_cap) {
     if (h->charge_mem) {
       hipError_t e = hipFree(h->charge_mem);
@@ -930,8 +940,6 @@ pic_status surface_charge(pic_mesh* h, const pic_fields* F,
     if (e != hipSuccess) return hip_fail(e, "surface_charge");
     h->charge_cap = need;
   }
-  fp::ChargeArgs a;
-  std::memset(&a, 0, sizeof a);
   a.m = h->dm;
   a.E = F->E;
   a.f32 = prm->precision == PIC_MIXED;
@@ -947,6 +955,43 @@ pic_status surface_charge(pic_mesh* h, const pic_fields* F,
   a.f_sum = h->charge_mem ? h->charge_mem + h->dm.n_emit : nullptr;
   a.part = h->charge_mem ? h->charge_mem + 2 * h->dm.n_emit : nullptr;
   a.n_split = n_split;
+  if (a.cut) {
+    const int64_t n_cells = (int64_t)a.nx * a.ny * a.nz;
+    const int64_t na = prm->n_atoms, nf = h->dm.n_emit;
+    double* dp = h->charge_mem + n_dbl;
+    a.a_xyz = dp;
+    dp += 3 * na;
+    a.f_cen = dp;
+    dp += 3 * nf;
+    a.f_Q_s = dp;
+    dp += nf;
+    a.f_min_s = dp;
+    dp += nf;
+    a.f_sum_s = dp;
+    int32_t* ip = reinterpret_cast<int32_t*>(h->charge_mem + n_dbl + n_cen);
+    const int64_t tiles = (n_cells + 1023) / 1024;
+    a.a_cnt = ip;
+    ip += n_cells + 1 + tiles;
+    a.f_cnt = ip;
+    ip += n_cells + 1 + tiles;
+    a.a_idx = ip;
+    ip += na;
+    a.a_tmp = ip;
+    ip += na;
+    a.a_cell = ip;
+    ip += na;
+    a.a_rank = ip;
+    ip += na;
+    a.f_idx = ip;
+    ip += nf;
+    a.f_tmp = ip;
+    ip += nf;
+    a.f_cell = ip;
+    ip += nf;
+    a.f_rank = ip;
+    ip += nf;
+    a.n_far = ip;
+  }
   const hipError_t e = fp::surface_charge_launch(a, h->n_cu, s);
   if (e != hipSuccess) return hip_fail(e, "surface_charge");
   return PIC_OK;

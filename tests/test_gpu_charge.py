@@ -2,7 +2,12 @@
 Eq. charge_weight) against the oracle: the face charges of every metal face
 of the tiny tip and their distribution to seeded surface atoms, from the
 same field (1e-12), in the cell mode, from an FP32 field (1e-6), and from
-each side's own solve (1e-9); total charge conserved on the device."""
+each side's own solve (1e-9); total charge conserved on the device.  The
+oracle sums every face-atom pair; the library leaves out the pairs beyond
+d_min + 40 r_c when the box holds that sphere (less than n_atoms e^-40 of a
+face's charge): r_c = 0.05 nm on the tiny tip and the production cases take
+that path (with every face near an atom, and with faces far from all
+atoms), r_c = 0.1 and 0.6 nm on the tiny tip take every pair."""
 import numpy as np
 import pytest
 
@@ -41,7 +46,7 @@ def _E4(E3, dtype):
     return torch.from_numpy(E4.reshape(-1)).to(dtype).cuda()
 
 
-@pytest.mark.parametrize("r_c", [0.1, 0.6])
+@pytest.mark.parametrize("r_c", [0.1, 0.6, 0.05])
 def test_surface_charge_matches_oracle(setup, r_c):
     pic, cfg, om, gm, ost, atoms = setup
     Qo, qo = om.surface_charge(ost.E, atoms, r_c=r_c)
@@ -51,6 +56,23 @@ def test_surface_charge_matches_oracle(setup, r_c):
     assert _rel(Qg, Qo) < 1e-12
     assert _rel(qg, qo) < 1e-12
     assert abs(qg.sum() / Qg.sum() - 1) < 1e-12
+
+
+def test_surface_charge_cutoff_with_far_faces(setup):
+    """Atoms on the tip's upper part only: the faces of the flat cathode
+    have no atom within the cell size and scan every atom, and the atom pass
+    then takes every face (with the same pair test)."""
+    pic, cfg, om, gm, ost, atoms = setup
+    top = atoms[atoms[:, 2] > cfg.tip_H - 1.5]
+    assert 20 < len(top) < len(atoms) // 2
+    for r_c in (0.05, 0.04):
+        Qo, qo = om.surface_charge(ost.E, top, r_c=r_c)
+        Qg, qg = gm.surface_charge(torch.from_numpy(top).cuda(), r_c=r_c,
+                                   E=_E4(ost.E, torch.float64))
+        Qg, qg = Qg.cpu().numpy(), qg.cpu().numpy()
+        assert _rel(Qg, Qo) < 1e-12
+        assert _rel(qg, qo) < 1e-12
+        assert abs(qg.sum() / Qg.sum() - 1) < 1e-12
 
 
 def test_surface_charge_cell_mode(setup):
@@ -104,9 +126,9 @@ def test_surface_charge_no_faces(setup):
 @pytest.mark.parametrize("cell", [False, True], ids=["nodal", "cell"])
 def test_surface_charge_production_size(cell):
     """Every metal face of the production tip (13,124 faces) to its seeded
-    surface atoms (6,245): the full-size path (faces beyond one face per
-    workgroup, the atom pass split over many face ranges) against the
-    oracle on the same field, to 1e-12."""
+    surface atoms (6,245) at r_c = 0.1 nm: the library's cutoff path (cells
+    of 1 nm, pairs within d_min + 4 nm) against the oracle's sum over every
+    pair on the same field, to 1e-12."""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_1906_08125_amd import pic
