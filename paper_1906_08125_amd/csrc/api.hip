@@ -1011,13 +1011,13 @@ pic_status pic_step(pic_mesh* h, const pic_particles* P, const pic_fields* F,
   hipError_t e = ensure_capacity(h, P->capacity, prm->resort_every > 0, f32 ? 4 : 8);
   if (e != hipSuccess) return hip_fail(e, "pic_step");
 
-  StepSet ss = step_set(h, P, F, prm, h->grid_push, h->grid_inj, h->grid_fb);
+  StepSet ss = step_set(h, P, F, prm, h->step_push[f32 ? 1 : 0], h->step_inj, h->grid_fb);
   if ((ps = use_precond(h, &prm->solve, ss.ca, s, "pic_step")) != PIC_OK) return ps;
   const fp::StepArgs& a = ss.a;
   const fp::EmitArgs& ea = ss.ea;
   fp::CgArgs& ca = ss.ca;
-  const int grid_push = h->grid_push;
-  const int grid_inj = h->grid_inj;
+  const int grid_push = h->step_push[f32 ? 1 : 0];
+  const int grid_inj = h->step_inj;
   const int grid_fb = h->grid_fb;
   // The kernels of step k before its solve: clears + emission counts, the
   // live and new particles in one launch, the exact fallback, the counters.

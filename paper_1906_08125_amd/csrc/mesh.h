@@ -39,8 +39,13 @@ struct pic_mesh {
   int32_t* counts = nullptr;
   pic_solve_stats* solve_stats = nullptr;
   int32_t* locate_count = nullptr;
-  // particle kernel grids and their per-block counter rows
+  // particle kernel grids and their per-block counter rows: grid_push and
+  // grid_inj are the most any launch may use (the counter rows are sized
+  // for them; a batch schedule may ask up to them); pic_step launches
+  // step_push[f32] push workgroups (as many as are resident at once) and
+  // step_inj injecting ones
   int grid_push = 0, grid_inj = 0, grid_fb = 0;
+  int step_push[2] = {0, 0}, step_inj = 0;
   int64_t* acc_rows = nullptr;
   // particle-capacity scratch (grown on demand)
   int64_t pcap = 0;

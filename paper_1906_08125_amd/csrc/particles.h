@@ -90,6 +90,9 @@ struct DepositArgs {
 };
 
 hipError_t launch_begin(const EmitArgs& a, int grid, hipStream_t s);
+// Workgroups of the particle kernel (FP64 or FP32 storage) resident on one
+// compute unit at once, by the runtime's occupancy calculator (0 on error).
+int particle_blocks_per_cu(int f32);
 // e: the step's emission, computed by workgroup 0 while the others push
 // (e.defer set; the injecting workgroups wait for it), or null
 hipError_t launch_particles(const StepArgs& a, const EmitArgs* e, int g_push,

@@ -1125,6 +1125,14 @@ hipError_t launch_stats_b(const StepArgs* A, const BatchMap& map, int grid,
   hipLaunchKernelGGL(k_stats_b, dim3(grid), dim3(kBlock), 0, s, A, map);
   return hipGetLastError();
 }
+int particle_blocks_per_cu(int f32) {
+  int n = 0;
+  const hipError_t e =
+      f32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_particles<true>, kBlock, 0)
+          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_particles<false>, kBlock, 0);
+  return e == hipSuccess ? n : 0;
+}
+
 hipError_t launch_particles(const StepArgs& a, const EmitArgs* e, int g_push,
                             int g_inj, hipStream_t s) {
   StepArgs b = a;
