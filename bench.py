@@ -34,11 +34,12 @@ HBM_PEAK_GBS = 8000.0
 # on are unchanged and the run's load matches the one profiled.
 # The dominant kernel (FP64 push) per launch at the production workload
 # (profiles/pic_step_fp64_production_tip.md):
-PUSH_TRAFFIC = dict(bytes=199.2e6, read=133.8e6, written=65.4e6, live=992_300,
+PUSH_TRAFFIC = dict(bytes=241.9e6, read=173.3e6, written=68.6e6, live=992_300,
                     sources=("paper_1906_08125_amd/csrc/particles.hip",
                              "paper_1906_08125_amd/csrc/common.h"),
-                    sha256=("26260919966f515d918ad42efa8987d440e317a7c0e7c338905a0283449d9717",
-                            "7d8f3c2344d581d986633cc1e8597ea0062a3ad5736211095600e29a54930541"))
+                    sha256=("548a76aa7f11c630e0e9f0b1454b3d1b1d2132acf7fc1ff159d970de5db64e66",
+                            "df664d921b2048d0e38d5de9ccce0edb99bc52cb2a034c6b94b3b69f07cb3843"))
+
 # One step of the 32-instance batch (every dispatch between consecutive
 # batched particle launches, averaged over the timed steps;
 # profiles/pic_batch_step_32_instances.md):
