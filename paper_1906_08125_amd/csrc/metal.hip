@@ -24,7 +24,8 @@ namespace {
 constexpr int kMB = 256;       // threads per workgroup
 constexpr int kMaxG = 1024;    // workgroups of the row-loop kernels
 constexpr int kMaxS = 65536;   // workgroups of the product (a row per thread)
-constexpr int kChunk = 24;     // CG iterations between host checks
+constexpr int kChunk = 24;     // CG iterations before the first host check
+constexpr int kChunkBig = 96;  // and between the later ones
 
 struct MetalCtrl {
   double gam[2];     // r.z of the last two iterations (by parity)
@@ -32,10 +33,9 @@ struct MetalCtrl {
   double bb;         // ||b||^2 over the free rows
   double rr;         // ||r||^2 of the last iterate tested
   double tol2;
-  double red[3];     // r.z, (A z).z and r.r of the last product
-  // iterations completed: written by k_cg_step and read by k_cg_reduce,
-  // which copies it to it_cur for k_cg_step, so that no kernel reads a
-  // counter that its own launch writes
+  // iterations completed: written by k_cg_step and read by k_cg_spmv,
+  // whose workgroup 0 copies it to it_cur for the next k_cg_step, so that
+  // no kernel reads a counter that its own launch writes
   int64_t iters;
   int64_t it_cur;
   int32_t done;
@@ -249,6 +249,12 @@ struct CgArgsM {
   const int32_t* row_ptr;
   const int32_t* col;
   const double* A;
+  // the same matrix in sliced ELLPACK for the product: slices of 64 rows,
+  // column-major inside a slice (entry k of row 64 s + l at
+  // sptr[s] + 64 k + l), rows padded with zero entries
+  const int32_t* sptr;
+  const int32_t* scol;
+  const double* sval;
   const double* b;
   const double* dinv;
   const uint8_t* dir;
@@ -274,6 +280,31 @@ __device__ double sum_fixed(const double* part, int nparts, double* sh, double* 
   const double r = *bc;
   __syncthreads();
   return r;
+}
+
+// The three sums of nparts partials each (arrays at stride kMaxS), in the
+// same fixed order as sum_fixed, in one pass: every workgroup gets the
+// same values.
+__device__ void sum3_fixed(const double* part, int nparts, double out[3]) {
+  __shared__ double sh[3][kMB / 64];
+  double v[3] = {0.0, 0.0, 0.0};
+  for (int k = threadIdx.x; k < nparts; k += kMB) {
+    v[0] += part[k];
+    v[1] += part[kMaxS + k];
+    v[2] += part[2 * kMaxS + k];
+  }
+  for (int o = 32; o > 0; o >>= 1)
+    for (int j = 0; j < 3; ++j) v[j] += __shfl_down(v[j], o, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0)
+    for (int j = 0; j < 3; ++j) sh[j][w] = v[j];
+  __syncthreads();
+  for (int j = 0; j < 3; ++j) {
+    double t = 0.0;
+    for (int k = 0; k < kMB / 64; ++k) t += sh[j][k];
+    out[j] = t;
+  }
+  __syncthreads();
 }
 
 __global__ void k_cg_dir(CgArgsM a) {
@@ -331,37 +362,44 @@ __device__ bool block_done(const MetalCtrl* c) {
   return r;
 }
 
-// w = A z (one row per thread; the row is read eight entries at a time so
-// that their loads are in flight together, and summed in entry order) and
-// the partials of r.z, w.z and r.r
+// w = A z (one row per lane, 64-row slices of the sliced-ELLPACK copy, so
+// that every load of a wave is contiguous; entries summed in row order,
+// the padding adding zeros) and the partials of r.z, w.z and r.r; the
+// iteration counter for k_cg_step
 __global__ void k_cg_spmv(CgArgsM a) {
   if (block_done(a.ctrl)) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.ctrl->it_cur = a.ctrl->iters;
   __shared__ double sh[kMB / 64];
   double gz = 0.0, wz = 0.0, rr = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * kMB + threadIdx.x; i < a.n;
-       i += (int64_t)gridDim.x * kMB) {
-    const int32_t r0 = a.row_ptr[i], r1 = a.row_ptr[i + 1];
+  const int lane = threadIdx.x & 63;
+  const int64_t ns = (a.n + 63) / 64;
+  for (int64_t sl = (int64_t)blockIdx.x * (kMB / 64) + (threadIdx.x >> 6); sl < ns;
+       sl += (int64_t)gridDim.x * (kMB / 64)) {
+    const int32_t p0 = a.sptr[sl], p1 = a.sptr[sl + 1];
     double v = 0.0;
-    for (int32_t k0 = r0; k0 < r1; k0 += 8) {
-      int32_t c[8];
-      double av[8];
+    int32_t q = p0 + lane;
+    for (; q + 3 * 64 < p1; q += 4 * 64) {
+      int32_t c[4];
+      double av[4], zv[4];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const bool ok = k0 + u < r1;
-        c[u] = ok ? a.col[k0 + u] : (int32_t)i;
-        av[u] = ok ? a.A[k0 + u] : 0.0;
+      for (int u = 0; u < 4; ++u) {
+        c[u] = a.scol[q + 64 * u];
+        av[u] = a.sval[q + 64 * u];
       }
-      double zv[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) zv[u] = a.z[c[u]];
+      for (int u = 0; u < 4; ++u) zv[u] = a.z[c[u]];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v += av[u] * zv[u];
+      for (int u = 0; u < 4; ++u) v += av[u] * zv[u];
     }
-    const double ri = a.r[i], zi = a.z[i];
-    a.w[i] = v;
-    gz += ri * zi;
-    wz += v * zi;
-    rr += ri * ri;
+    for (; q < p1; q += 64) v += a.sval[q] * a.z[a.scol[q]];
+    const int64_t i = sl * 64 + lane;
+    if (i < a.n) {
+      const double ri = a.r[i], zi = a.z[i];
+      a.w[i] = v;
+      gz += ri * zi;
+      wz += v * zi;
+      rr += ri * ri;
+    }
   }
   const double s0 = block_sum(gz, sh);
   const double s1 = block_sum(wz, sh);
@@ -373,18 +411,12 @@ __global__ void k_cg_spmv(CgArgsM a) {
   }
 }
 
-// One workgroup: the three sums of the product's partials into the control
-// word, and the iteration counter for k_cg_step.
-__global__ void k_cg_reduce(CgArgsM a) {
-  if (block_done(a.ctrl)) return;
-  __shared__ double sh[kMB / 64];
-  __shared__ double bc;
-  double r[3];
-  for (int k = 0; k < 3; ++k) r[k] = sum_fixed(a.part + (size_t)k * kMaxS, a.Gs, sh, &bc);
-  if (threadIdx.x == 0) {
-    for (int k = 0; k < 3; ++k) a.ctrl->red[k] = r[k];
-    a.ctrl->it_cur = a.ctrl->iters;
-  }
+// The assembled (and eliminated) values into the sliced-ELLPACK copy.
+__global__ void k_to_sell(int64_t nnz, const int32_t* __restrict__ c2s,
+                          const double* __restrict__ A, double* __restrict__ sval) {
+  for (int64_t k = (int64_t)blockIdx.x * kMB + threadIdx.x; k < nnz;
+       k += (int64_t)gridDim.x * kMB)
+    sval[c2s[k]] = A[k];
 }
 
 // One iteration of the single-reduction (Chronopoulos-Gear) form of
@@ -392,11 +424,15 @@ __global__ void k_cg_reduce(CgArgsM a) {
 //   beta = gamma / gamma_prev, alpha = gamma / (delta - beta gamma / alpha_prev)
 //   (beta = 0, alpha = gamma / delta at the first iteration),
 //   p = z + beta p, s = w + beta s, x += alpha p, r -= alpha s, z = D^-1 r.
-// The residual of the incoming iterate is tested first.
+// The residual of the incoming iterate is tested first.  Every workgroup
+// sums the product's partials itself, in the same fixed order (no
+// reduction launch between the product and the step).
 __global__ void k_cg_step(CgArgsM a) {
   if (block_done(a.ctrl)) return;
   const int64_t it = a.ctrl->it_cur;
-  const double gam = a.ctrl->red[0], del = a.ctrl->red[1], rr = a.ctrl->red[2];
+  double red[3];
+  sum3_fixed(a.part, a.Gs, red);
+  const double gam = red[0], del = red[1], rr = red[2];
   const double bb = a.ctrl->bb;
   if (bb == 0.0 || rr <= a.ctrl->tol2 * bb) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -466,6 +502,9 @@ struct MetalImpl {
   double *r = nullptr, *z = nullptr, *p = nullptr, *sv = nullptr, *w = nullptr;
   double* part = nullptr;
   int32_t *tet = nullptr, *face = nullptr, *row_ptr = nullptr, *col = nullptr;
+  int32_t *sptr = nullptr, *scol = nullptr, *c2s = nullptr;  // sliced ELLPACK
+  double* sval = nullptr;
+  int64_t nsell = 0;
   int32_t *inc_ptr = nullptr, *inc_pos = nullptr;
   int32_t *fin_ptr = nullptr, *fin_face = nullptr;
   int32_t* elem_inc = nullptr;
@@ -476,10 +515,10 @@ struct MetalImpl {
   MetalCtrl* ctrl = nullptr;
   MetalCtrl* hctrl = nullptr;   // pinned host mirror
   int G = 1;
-  // kChunk CG iterations captured once per handle (their kernels read
-  // every per-solve value from the control word)
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t chunk = nullptr;
+  // kChunk and kChunkBig CG iterations captured once per handle (their
+  // kernels read every per-solve value from the control word)
+  hipGraph_t graph = nullptr, graph_big = nullptr;
+  hipGraphExec_t chunk = nullptr, chunk_big = nullptr;
 };
 
 }  // namespace fp
@@ -572,6 +611,35 @@ pic_status metal_build(const pic_metal_desc* d, hipStream_t s, pic_metal** out,
         const int32_t* hi = col.data() + row_ptr[i + 1];
         inc_pos[4 * (size_t)q + a] = (int32_t)(std::lower_bound(lo, hi, v) - col.data());
       }
+  // the sliced-ELLPACK copy of the pattern (64-row slices, column-major,
+  // rows padded with their own column and a zero value)
+  const int64_t n_sl = (n + 63) / 64;
+  std::vector<int32_t> sptr(n_sl + 1, 0);
+  for (int64_t sl = 0; sl < n_sl; ++sl) {
+    int32_t wmax = 0;
+    for (int64_t r = 64 * sl; r < std::min<int64_t>(n, 64 * sl + 64); ++r)
+      wmax = std::max(wmax, row_ptr[r + 1] - row_ptr[r]);
+    if ((int64_t)sptr[sl] + 64 * (int64_t)wmax >= ((int64_t)1 << 31)) {
+      *err = "metal_create: too many matrix entries";
+      return PIC_E_ARG;
+    }
+    sptr[sl + 1] = sptr[sl] + 64 * wmax;
+  }
+  std::vector<int32_t> scol(std::max<int32_t>(sptr[n_sl], 1), 0), c2s(col.size());
+  for (int64_t r = 0; r < 64 * n_sl; ++r) {
+    const int64_t sl = r / 64, l = r % 64;
+    const int32_t w = (sptr[sl + 1] - sptr[sl]) / 64;
+    const int32_t len = r < n ? row_ptr[r + 1] - row_ptr[r] : 0;
+    for (int32_t k = 0; k < w; ++k) {
+      const int32_t q = sptr[sl] + 64 * k + (int32_t)l;
+      if (k < len) {
+        scol[q] = col[row_ptr[r] + k];
+        c2s[row_ptr[r] + k] = q;
+      } else {
+        scol[q] = r < n ? (int32_t)r : 0;
+      }
+    }
+  }
   // node -> interface faces
   std::vector<int32_t> fin_ptr(n + 1, 0), fin_face(3 * nf);
   for (int64_t k = 0; k < 3 * nf; ++k) ++fin_ptr[d->faces[k] + 1];
@@ -600,6 +668,13 @@ pic_status metal_build(const pic_metal_desc* d, hipStream_t s, pic_metal** out,
   up(&M.dir, d->dirichlet, n);
   up(&M.row_ptr, row_ptr.data(), n + 1);
   up(&M.col, col.data(), col.size());
+  up(&M.sptr, sptr.data(), sptr.size());
+  up(&M.scol, scol.data(), scol.size());
+  up(&M.c2s, c2s.data(), c2s.size());
+  M.nsell = (int64_t)scol.size();
+  if (e == hipSuccess) e = dalloc(h, &M.sval, (size_t)M.nsell);
+  // the padding entries stay zero (only real entries are written per call)
+  if (e == hipSuccess) e = hipMemsetAsync(M.sval, 0, sizeof(double) * (size_t)M.nsell, s);
   up(&M.inc_ptr, inc_ptr.data(), n + 1);
   up(&M.inc_pos, inc_pos.data(), inc_pos.size());
   up(&M.elem_inc, elem_inc.data(), elem_inc.size());
@@ -647,6 +722,8 @@ void metal_free(pic_metal* h) {
   if (h->m.hctrl) (void)hipHostFree(h->m.hctrl);
   if (h->m.chunk) (void)hipGraphExecDestroy(h->m.chunk);
   if (h->m.graph) (void)hipGraphDestroy(h->m.graph);
+  if (h->m.chunk_big) (void)hipGraphExecDestroy(h->m.chunk_big);
+  if (h->m.graph_big) (void)hipGraphDestroy(h->m.graph_big);
   delete h;
 }
 
@@ -655,10 +732,11 @@ namespace {
 CgArgsM cg_args(MetalImpl& M, double dir_value, double tol) {
   CgArgsM a{};
   a.n = M.n; a.row_ptr = M.row_ptr; a.col = M.col; a.A = M.A; a.b = M.b;
+  a.sptr = M.sptr; a.scol = M.scol; a.sval = M.sval;
   a.dinv = M.dinv; a.dir = M.dir; a.dir_value = dir_value; a.tol2 = tol * tol;
   a.x = M.x; a.r = M.r; a.z = M.z; a.p = M.p; a.s = M.sv; a.w = M.w; a.part = M.part;
   a.ctrl = M.ctrl; a.G = M.G;
-  a.Gs = (int)std::min<int64_t>(kMaxS, (M.n + kMB - 1) / kMB);
+  a.Gs = (int)std::min<int64_t>(kMaxS, (M.n + kMB - 1) / kMB);  // 4 slices each
   return a;
 }
 
@@ -668,25 +746,30 @@ void launch_iter(const CgArgsM& a, hipStream_t s) {
   const dim3 g(a.G), b(kMB);
   hipLaunchKernelGGL(k_cg_step, g, b, 0, s, a);
   hipLaunchKernelGGL(k_cg_spmv, dim3(a.Gs), b, 0, s, a);
-  hipLaunchKernelGGL(k_cg_reduce, dim3(1), b, 0, s, a);
 }
 
-// Capture kChunk iterations into a graph on a private stream (capture is
+// Capture count iterations into a graph on a private stream (capture is
 // not possible on the legacy default stream the caller may use).
-hipError_t build_chunk(MetalImpl& M) {
+hipError_t capture_iters(MetalImpl& M, int count, hipGraph_t* graph, hipGraphExec_t* exec) {
   hipStream_t cs = nullptr;
   hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
   if (e != hipSuccess) return e;
   const CgArgsM a = cg_args(M, 0.0, 1.0);
   e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    for (int k = 0; k < kChunk; ++k) launch_iter(a, cs);
-    hipError_t e2 = hipStreamEndCapture(cs, &M.graph);
+    for (int k = 0; k < count; ++k) launch_iter(a, cs);
+    hipError_t e2 = hipStreamEndCapture(cs, graph);
     e = hipGetLastError();
     if (e == hipSuccess) e = e2;
   }
-  if (e == hipSuccess) e = hipGraphInstantiate(&M.chunk, M.graph, nullptr, nullptr, 0);
+  if (e == hipSuccess) e = hipGraphInstantiate(exec, *graph, nullptr, nullptr, 0);
   (void)hipStreamDestroy(cs);
+  return e;
+}
+
+hipError_t build_chunk(MetalImpl& M) {
+  hipError_t e = capture_iters(M, kChunk, &M.graph, &M.chunk);
+  if (e == hipSuccess) e = capture_iters(M, kChunkBig, &M.graph_big, &M.chunk_big);
   return e;
 }
 
@@ -695,7 +778,7 @@ pic_status run_cg(pic_metal* h, double* x, double dir_value, double tol,
                   std::string* err, const char* who) {
   MetalImpl& M = h->m;
   hipError_t e = hipSuccess;
-  if (!M.chunk) e = build_chunk(M);
+  if (!M.chunk_big) e = build_chunk(M);
   const CgArgsM a = cg_args(M, dir_value, tol);
   const dim3 g(M.G), b(kMB);
   if (e == hipSuccess)
@@ -705,9 +788,11 @@ pic_status run_cg(pic_metal* h, double* x, double dir_value, double tol,
     hipLaunchKernelGGL(k_cg_init, g, b, 0, s, a);
     hipLaunchKernelGGL(k_cg_start, dim3(1), b, 0, s, a);
     hipLaunchKernelGGL(k_cg_spmv, dim3(a.Gs), b, 0, s, a);
-    hipLaunchKernelGGL(k_cg_reduce, dim3(1), b, 0, s, a);
     e = hipGetLastError();
   }
+  // a first chunk of kChunk iterations (short solves, such as a heat step,
+  // end in it), then chunks of kChunkBig between host checks; iterations
+  // past convergence return at once
   int64_t it = 0;
   bool done = false;
   while (e == hipSuccess) {
@@ -716,7 +801,10 @@ pic_status run_cg(pic_metal* h, double* x, double dir_value, double tol,
     if (e != hipSuccess) break;
     done = M.hctrl->done != 0;
     if (done || it >= max_iter) break;
-    if (max_iter - it >= kChunk) {
+    if (it > 0 && max_iter - it >= kChunkBig) {
+      e = hipGraphLaunch(M.chunk_big, s);
+      it += kChunkBig;
+    } else if (max_iter - it >= kChunk) {
       e = hipGraphLaunch(M.chunk, s);
       it += kChunk;
     } else {
@@ -772,6 +860,8 @@ pic_status metal_continuity(pic_metal* h, const double* sigma, const double* flu
   hipLaunchKernelGGL(k_assemble, dim3(g), dim3(kMB), 0, s, a, 0.0);
   hipLaunchKernelGGL(k_eliminate, dim3(g), dim3(kMB), 0, s, M.n, M.row_ptr, M.col,
                      M.dir, 0.0, M.A, M.b, M.dinv);
+  hipLaunchKernelGGL(k_to_sell, dim3(blocks_for(M.nnz)), dim3(kMB), 0, s, M.nnz, M.c2s,
+                     M.A, M.sval);
   pic_status rc = run_cg(h, phi, 0.0, tol, max_iter, st, s, err, "continuity_solve");
   if (rc != PIC_OK && rc != PIC_E_NOCONV) return rc;
   if (pj) {
@@ -801,6 +891,8 @@ pic_status metal_heat(pic_metal* h, const pic_heat_params* p, const double* sigm
   hipLaunchKernelGGL(k_assemble, dim3(g), dim3(kMB), 0, s, a, p->T_amb);
   hipLaunchKernelGGL(k_eliminate, dim3(g), dim3(kMB), 0, s, M.n, M.row_ptr, M.col,
                      M.dir, p->T_amb, M.A, M.b, M.dinv);
+  hipLaunchKernelGGL(k_to_sell, dim3(blocks_for(M.nnz)), dim3(kMB), 0, s, M.nnz, M.c2s,
+                     M.A, M.sval);
   return run_cg(h, T, p->T_amb, p->tol, p->max_iter, st, s, err, "heat_step");
 }
 
