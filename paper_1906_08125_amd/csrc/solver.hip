@@ -781,9 +781,26 @@ __device__ inline void amg_rows(const SellMat& M, VB vb, Gf&& g, Ef&& emit) {
   for (int64_t r0 = rows.lo; r0 < rows.hi; r0 += ngrp) {
     const int64_t r = r0 + grp;
     T acc = 0;
-    if (r < rows.hi)
-      for (int32_t p = M.sptr[r] + sub; p < M.sptr[r + 1]; p += lpr)
-        acc += val[p] * g(M.col[p]);
+    if (r < rows.hi) {
+      // four entries per trip with their loads in flight together, summed
+      // in the lane's entry order
+      const int32_t p1 = M.sptr[r + 1];
+      int32_t p = M.sptr[r] + sub;
+      for (; p + 3 * lpr < p1; p += 4 * lpr) {
+        int32_t c[4];
+        T v[4], xv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          c[u] = M.col[p + u * lpr];
+          v[u] = val[p + u * lpr];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) xv[u] = g(c[u]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc += v[u] * xv[u];
+      }
+      for (; p < p1; p += lpr) acc += val[p] * g(M.col[p]);
+    }
     for (int off = lpr >> 1; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, lpr);
     if (r < rows.hi && sub == 0) emit(r, acc);
   }
@@ -1084,14 +1101,15 @@ CoarseVecs<T> coarse_host(const AmgDev& d) {
     return CoarseVecs<T>{d.coarse_inv, d.coarse_b, d.coarse_x};
 }
 
-// Workgroups for a level kernel over the rows of M: about two lanes of
-// work per thread (a row takes M.lpr lanes), at most the solver grid, so
-// that the small coarse passes do not launch and drain hundreds of idle
-// workgroups.  The finest level's smoothing kernels keep the solver grid
-// (they also reduce over it).
+// Workgroups for a level kernel over the rows of M: one lane of work per
+// thread (a row takes M.lpr lanes; the rows of a SELL slice share a lane
+// column), at most the solver grid, so that the small coarse passes neither
+// loop over row groups in one workgroup nor launch and drain hundreds of
+// idle workgroups.  The finest level's smoothing kernels keep the solver
+// grid (they also reduce over it).
 int amg_grid(const CgArgs& a, const SellMat& M) {
   const int64_t lanes = M.nrows * (int64_t)M.lpr;
-  const int64_t want = (lanes + 2 * kCgBlock - 1) / (2 * kCgBlock);
+  const int64_t want = (lanes + kCgBlock - 1) / kCgBlock;
   int g = (int)std::min<int64_t>(a.G, std::max<int64_t>(8, want));
   return g >= 8 ? g - g % 8 : g;
 }
