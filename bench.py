@@ -43,17 +43,17 @@ PUSH_TRAFFIC = dict(bytes=241.9e6, read=173.3e6, written=68.6e6, live=992_300,
 # One step of the 32-instance batch (every dispatch between consecutive
 # batched particle launches, averaged over the timed steps;
 # profiles/pic_batch_step_32_instances.md):
-BATCH_TRAFFIC = dict(bytes=3374.5e6, read=2745.2e6, written=629.3e6,
+BATCH_TRAFFIC = dict(bytes=3375.9e6, read=2747.1e6, written=628.8e6,
                      live=3_371_102,
                      sources=("paper_1906_08125_amd/csrc/particles.hip",
                               "paper_1906_08125_amd/csrc/solver.hip",
                               "paper_1906_08125_amd/csrc/amg.hip",
                               "paper_1906_08125_amd/csrc/api.hip",
                               "paper_1906_08125_amd/csrc/common.h"),
-                     sha256=("b7adb28bfcfd54e1d6acca604cd791d13c3d2da1bed4ba2e3107d21ee005f510",
-                             "8a9839c4a8aceb567764914275820070b7a86cce52d0ace807647f0212b5d207",
-                             "0d5ab663968bfe79d3f6c96c20b601c5b1dface104743cd0f1f52a43419f9e24",
-                             "cd2c5ff7f2bd3346e05bd83f0750ce64453cf0b9e218740a4634d4c90316ec01",
+                     sha256=("548a76aa7f11c630e0e9f0b1454b3d1b1d2132acf7fc1ff159d970de5db64e66",
+                             "a3e3309ac02012ac544dbc79abf2b8f40514441d20b240a38abdac84bb637f1c",
+                             "b7134060afc401da45819d5e18d224beee6fb57e6660ef3331fb9b6bb80d9af9",
+                             "773ef6ecc3c24cc032465d9a5bca0a5cd15452b5a50f1523abdbb9442c9608c5",
                              "df664d921b2048d0e38d5de9ccce0edb99bc52cb2a034c6b94b3b69f07cb3843"))
 
 
