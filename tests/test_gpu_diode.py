@@ -118,10 +118,12 @@ def _run_diode(pic, E0, n_steps=1600, per_step=200, chunk=50, cfg=None):
 
 
 def test_diode_current_field_curve(pic):
-    """Anode fields 5 .. 16 V/nm at A = 135.7 nm^2, d = 18.2 nm, 0.02 fs
-    steps, 1600 steps each (the second half averaged)."""
+    """Anode fields 5 .. 40 V/nm at A = 135.7 nm^2, d = 18.2 nm, 0.02 fs
+    steps, 1600 steps each (the second half averaged): from emission-limited
+    (J close to the FN current of the anode field) into the space-charge-
+    limited regime (J above 0.8 of the Child-Langmuir current)."""
     out = []
-    for E0 in (5.0, 8.0, 10.0, 12.0, 14.0, 16.0):
+    for E0 in (5.0, 8.0, 10.0, 12.0, 14.0, 16.0, 20.0, 25.0, 30.0, 40.0):
         r = _run_diode(pic, E0)
         out.append(r)
         print("diode E_a %5.1f  J %.4e  J/J_semi %.4f  J/J_FN(E_a) %.4f  "
@@ -142,7 +144,9 @@ def test_diode_current_field_curve(pic):
     assert abs(out[0]["J"] / out[0]["J_semi"] - 1) < 0.03
     assert np.abs(rel).max() < 0.12
     assert out[-1]["J"] < 0.3 * out[-1]["J_fn"]       # space charge limits
+    assert out[-1]["J"] > 0.8 * out[-1]["J_cl"]       # close to Child-Langmuir
     assert all(b["J"] > a["J"] for a, b in zip(out, out[1:]))
+    assert all(b["J"] / b["J_cl"] > a["J"] / a["J_cl"] for a, b in zip(out, out[1:]))
 
 
 def test_diode_surface_field_convergence(pic):
