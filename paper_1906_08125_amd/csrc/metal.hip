@@ -685,6 +685,11 @@ pic_status metal_build(const pic_metal_desc* d, hipStream_t s, pic_metal** out,
   if (e == hipSuccess) e = dalloc(h, &M.A, col.size());
   for (double** v : {&M.b, &M.dinv, &M.r, &M.z, &M.p, &M.sv, &M.w, &M.x})
     if (e == hipSuccess) e = dalloc(h, v, n);
+  // the search directions start as NaN (all bits set): the first CG
+  // iteration must set them outright, and a read before that write would
+  // spoil every solve, not only those on reused memory
+  if (e == hipSuccess) e = hipMemsetAsync(M.p, 0xFF, sizeof(double) * (size_t)n, s);
+  if (e == hipSuccess) e = hipMemsetAsync(M.sv, 0xFF, sizeof(double) * (size_t)n, s);
   if (e == hipSuccess) e = dalloc(h, &M.part, 3 * kMaxS);
   if (e == hipSuccess) e = dalloc(h, &M.ctrl, 1);
   if (e == hipSuccess) e = hipMemsetAsync(M.ctrl, 0, sizeof(MetalCtrl), s);

@@ -131,7 +131,10 @@ def test_metal_checks_arguments(pic, tiny):
 def test_metal_on_reused_memory(pic, tiny):
     """A handle whose device buffers are memory that earlier work left full
     of NaN: the first CG iteration must not read its search directions
-    (regression: it multiplied them by beta = 0)."""
+    (regression: it multiplied them by beta = 0).  The library itself
+    fills the search directions with NaN when a handle is created, so this
+    and every other metal solve here would fail deterministically if the
+    first iteration read them."""
     junk = torch.full((1 << 27,), float("nan"), dtype=torch.float64,
                       device="cuda")
     torch.cuda.synchronize()
