@@ -189,13 +189,23 @@ __global__ void __launch_bounds__(kThreads) k_sort_scatter(SortArgs a, int src,
 }
 
 // Gather every particle array into scratch in sorted order; the last live
-// position sets the new slot count.
+// position sets the new slot count.  The sorted order is close to the
+// previous one, so the sources of a run of outputs lie in a narrow window:
+// each XCD (block index mod 8) takes one contiguous eighth of the outputs,
+// so that a source line is fetched into one XCD's L2 rather than into
+// every XCD whose blocks interleave over it.
 __global__ void __launch_bounds__(kThreads) k_sort_gather(SortArgs a, int src) {
   const int64_t n = *a.n_slots;
   const uint32_t* key = a.key[src];
   const uint32_t* val = a.val[src];
-  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
-       j += (int64_t)gridDim.x * blockDim.x) {
+  const int parts = gridDim.x % 8 == 0 ? 8 : 1;
+  const int part = (int)blockIdx.x % parts;
+  const int64_t per_part = (n + parts - 1) / parts;
+  const int64_t lo = part * per_part;
+  const int64_t hi = lo + per_part < n ? lo + per_part : n;
+  const int64_t stride = (int64_t)(gridDim.x / parts) * blockDim.x;
+  for (int64_t j = lo + (int64_t)(blockIdx.x / parts) * blockDim.x + threadIdx.x;
+       j < hi; j += stride) {
     const bool live = key[j] < (uint32_t)a.n_tets;
     const bool last = live && (j + 1 == n || key[j + 1] >= (uint32_t)a.n_tets);
     if (last) *a.n_live = (int32_t)(j + 1);
