@@ -533,6 +533,39 @@ def test_resort_three_digit_passes(pic):
         assert (A[key][a] == B[key][b]).all(), key
 
 
+@pytest.mark.parametrize("n_inj", [1, 3, 9, 17, 4101])
+def test_resort_small_and_ragged_populations(pic, n_inj):
+    """Populations smaller than the sort's eight per-XCD parts of the gather,
+    not a multiple of eight, and one tile plus a ragged tail: the step that
+    injects exactly n_inj particles (held counts) and re-sorts after itself
+    leaves the same particles as the same step without re-sort, compacted
+    and ordered by tet (ties in injection = id order)."""
+    cfg = W.config_tiny()
+    gm = pic.Mesh(cfg.mesh(), cfg.emit_zmin)
+    held = np.zeros(gm.n_emit, np.int32)
+    np.add.at(held, np.random.default_rng(n_inj).integers(0, gm.n_emit, n_inj), 1)
+    out = []
+    for every in (0, 1):
+        gs = pic.State(gm, 20_000)
+        gs.init_field(cfg.E0, tol=cfg.tol)
+        st = pic.State.decode_stats(gs.step(
+            step0=0, n_steps=1, dt=cfg.dt, E0=cfg.E0, w_sp=1e-6,
+            phi_w=cfg.phi_w, seed=cfg.seed, tol=cfg.tol, resort_every=every,
+            counts_in=torch.from_numpy(held).cuda()))
+        assert st[0]["n_inj"] == n_inj
+        out.append((gs, st))
+    (ga, sa), (gb, sb) = out
+    A, B = ga.live(), gb.live()
+    n_live = sb[-1]["n_after"]
+    assert B["id"].size == n_live == int(gb.n_slots.item()) == A["id"].size
+    assert (gb.tet[:n_live].cpu().numpy() >= 0).all()
+    assert (np.diff(B["tet"]) >= 0).all()
+    assert (np.diff(B["id"])[np.diff(B["tet"]) == 0] > 0).all()
+    a, b = np.argsort(A["id"]), np.argsort(B["id"])
+    for key in ("id", "x", "y", "z", "vx", "vy", "vz", "w", "tet", "birth"):
+        assert (A[key][a] == B[key][b]).all(), key
+
+
 # ---------------------------------------------------------------------------
 # Mixed precision: FP32 particles, field and CG recursion against the FP64
 # oracle.  Bound: relative L2 <= 1e-6 for the potential (every step) and the
