@@ -173,6 +173,36 @@ def test_locate_bit_exact(pic, name):
     _locate_case(pic, tip, pts, hint)
 
 
+@pytest.mark.parametrize("name", ["small_tip", "tiny_tip"])
+def test_locate_on_face_interiors(pic, name):
+    """Points exactly on the relative interior of random faces (dyadic
+    weights of the face's three vertices, exact in FP64; the case a
+    position stored in FP32 meets most often): the oracle's canonical tet
+    (the lower index of the two holding the point, or the one tet on a
+    boundary or periodic face; both occur), from hints on either side of
+    the face and far away."""
+    tip = MESHES[name]()
+    rng = np.random.default_rng(11)
+    n = 6000
+    t = rng.integers(0, tip.n_tets, n)
+    k = rng.integers(0, 4, n)                   # the face opposite vertex k
+    wts = np.array([[0.25, 0.25, 0.5], [0.125, 0.375, 0.5],
+                    [0.375, 0.375, 0.25]])[rng.integers(0, 3, n)]
+    V = tip.xyz[tip.tet[t]].copy()              # [n, 4, 3]
+    V[:, :, 0] += tip.shift[t, :, 0] * tip.Lx
+    V[:, :, 1] += tip.shift[t, :, 1] * tip.Ly
+    others = np.array([[1, 2, 3], [0, 2, 3], [0, 1, 3], [0, 1, 2]])[k]
+    F = np.take_along_axis(V, others[:, :, None], axis=1)   # [n, 3, 3]
+    pts = np.einsum("nj,njc->nc", wts, F)
+    keep = (pts[:, 0] < tip.Lx) & (pts[:, 1] < tip.Ly) & (pts[:, 2] < tip.z_top)
+    pts, t = pts[keep], t[keep]
+    t_o = _locate_case(pic, tip, pts, t.astype(np.int32))
+    assert (t_o >= 0).mean() > 0.9
+    _locate_case(pic, tip, pts, t_o.astype(np.int32))
+    far = rng.integers(0, tip.n_tets, len(pts)).astype(np.int32)
+    _locate_case(pic, tip, pts, far)
+
+
 def test_locate_empty(pic):
     tip = MESHES["small_tip"]()
     gm = pic.Mesh(tip, 0.01)
