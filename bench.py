@@ -34,23 +34,23 @@ HBM_PEAK_GBS = 8000.0
 # on are unchanged and the run's load matches the one profiled.
 # The dominant kernel (FP64 push) per launch at the production workload
 # (profiles/pic_step_fp64_production_tip.md):
-PUSH_TRAFFIC = dict(bytes=241.9e6, read=173.3e6, written=68.6e6, live=992_300,
+PUSH_TRAFFIC = dict(bytes=220.5e6, read=155.9e6, written=64.6e6, live=992_300,
                     sources=("paper_1906_08125_amd/csrc/particles.hip",
                              "paper_1906_08125_amd/csrc/common.h"),
-                    sha256=("548a76aa7f11c630e0e9f0b1454b3d1b1d2132acf7fc1ff159d970de5db64e66",
+                    sha256=("5770ae084b9f9585a4b0d54bd5d8e7f9e881e1d3cf0fe7c783617cdb6aa6d220",
                             "df664d921b2048d0e38d5de9ccce0edb99bc52cb2a034c6b94b3b69f07cb3843"))
 
 # One step of the 32-instance batch (every dispatch between consecutive
 # batched particle launches, averaged over the timed steps;
 # profiles/pic_batch_step_32_instances.md):
-BATCH_TRAFFIC = dict(bytes=3375.9e6, read=2747.1e6, written=628.8e6,
+BATCH_TRAFFIC = dict(bytes=3355.9e6, read=2727.9e6, written=628.0e6,
                      live=3_371_102,
                      sources=("paper_1906_08125_amd/csrc/particles.hip",
                               "paper_1906_08125_amd/csrc/solver.hip",
                               "paper_1906_08125_amd/csrc/amg.hip",
                               "paper_1906_08125_amd/csrc/api.hip",
                               "paper_1906_08125_amd/csrc/common.h"),
-                     sha256=("548a76aa7f11c630e0e9f0b1454b3d1b1d2132acf7fc1ff159d970de5db64e66",
+                     sha256=("5770ae084b9f9585a4b0d54bd5d8e7f9e881e1d3cf0fe7c783617cdb6aa6d220",
                              "a3e3309ac02012ac544dbc79abf2b8f40514441d20b240a38abdac84bb637f1c",
                              "b7134060afc401da45819d5e18d224beee6fb57e6660ef3331fb9b6bb80d9af9",
                              "773ef6ecc3c24cc032465d9a5bca0a5cd15452b5a50f1523abdbb9442c9608c5",
