@@ -27,6 +27,8 @@ sys.path.insert(0, ROOT)
 METRIC = ("PIC steps/s & pushes/s at 3M tets/1M e-; mixed vs FP64 speedup; "
           "adjoint/fwd")
 HBM_PEAK_GBS = 8000.0
+# the timed steps bracket the push with HIP events in every this many steps
+PUSH_TIMING_EVERY = 5
 
 # HBM traffic from rocprofv3 FETCH_SIZE and WRITE_SIZE counter runs, scaled
 # by what the counters read for a plain 1 GiB device copy (fetch 1.9999,
@@ -43,7 +45,7 @@ PUSH_TRAFFIC = dict(bytes=220.5e6, read=155.9e6, written=64.6e6, live=992_300,
 # One step of the 32-instance batch (every dispatch between consecutive
 # batched particle launches, averaged over the timed steps;
 # profiles/pic_batch_step_32_instances.md):
-BATCH_TRAFFIC = dict(bytes=3355.9e6, read=2727.9e6, written=628.0e6,
+BATCH_TRAFFIC = dict(bytes=3357.0e6, read=2718.6e6, written=638.4e6,
                      live=3_371_102,
                      sources=("paper_1906_08125_amd/csrc/particles.hip",
                               "paper_1906_08125_amd/csrc/solver.hip",
@@ -53,7 +55,7 @@ BATCH_TRAFFIC = dict(bytes=3355.9e6, read=2727.9e6, written=628.0e6,
                      sha256=("5770ae084b9f9585a4b0d54bd5d8e7f9e881e1d3cf0fe7c783617cdb6aa6d220",
                              "a3e3309ac02012ac544dbc79abf2b8f40514441d20b240a38abdac84bb637f1c",
                              "b7134060afc401da45819d5e18d224beee6fb57e6660ef3331fb9b6bb80d9af9",
-                             "773ef6ecc3c24cc032465d9a5bca0a5cd15452b5a50f1523abdbb9442c9608c5",
+                             "ae55d3e89b0b5ecf7b0315f55806ab3698847e53dfe1d3abbf7d275bd5bdc4af",
                              "df664d921b2048d0e38d5de9ccce0edb99bc52cb2a034c6b94b3b69f07cb3843"))
 
 
@@ -137,9 +139,10 @@ def run_leg(gm, cfg, w_sp, precision, args, fill_steps=None):
     stats = torch.zeros(args.steps * pic.STEP_STATS_BYTES // 8,
                         dtype=torch.int64, device="cuda")
     # timed region: K steps, bracketed by synchronizations; HIP events
-    # bracket the push kernel (the dominant one) only: every event is a
-    # packet of its own in the stream and costs GPU time
-    gm.profile(True, classes=("push",))
+    # bracket the push kernel (the dominant one) only, and only in every
+    # fifth step: every event is a packet of its own in the stream, and the
+    # GPU idles some 5 us at each (two per timed push)
+    gm.profile(True, classes=("push",), every=PUSH_TIMING_EVERY)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     gs.step(step0=step, n_steps=args.steps, stats=stats, **kw)

@@ -604,6 +604,11 @@ typedef struct {
 /* to stop.                                                                 */
 #define PIC_PROFILE_ALL 0x1FF
 PIC_API pic_status pic_profile(pic_mesh* mesh, int32_t classes);
+/* Sampling of the timing in pic_step: only its steps k = 0, every,        */
+/* 2 every, ... of each call are bracketed (every >= 1; 1, the default,     */
+/* times every step; PIC_E_ARG below 1).  Other entry points time every     */
+/* call.  Fewer events leave the untimed steps as they run without timing.  */
+PIC_API pic_status pic_profile_every(pic_mesh* mesh, int32_t every);
 PIC_API pic_status pic_profile_read(pic_mesh* mesh, pic_kernel_times* out);
 
 PIC_API const char* pic_last_error(void);

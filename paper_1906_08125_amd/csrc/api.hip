@@ -2,6 +2,7 @@
 // the per-step kernel sequence.  Every entry point only enqueues work on the
 // caller's stream.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -181,14 +182,27 @@ fp::CgArgs cg_args(const pic_mesh* h, const int64_t* charge, double w_sp,
   return a;
 }
 
-// Wait (spinning on the host) for the solver report with sequence number seq;
-// the event recorded after the reporting kernel guards against a report that
-// never arrives.
-hipError_t cg_wait(pic_mesh* h, int64_t seq, fp::CgReport& out) {
+// Wait (spinning on the host) for the solver report with sequence number seq,
+// written by a kernel already enqueued on s.  Liveness: a report still
+// missing after 2 ms gets an event recorded behind everything enqueued so
+// far; once that event has completed, the report must be visible or never
+// comes.  (An event per solve instead would cost every step: each event is
+// a packet of its own, and the GPU idles ~5 us at it.)
+hipError_t cg_wait(pic_mesh* h, int64_t seq, hipStream_t s, fp::CgReport& out) {
+  const auto t0 = std::chrono::steady_clock::now();
+  bool armed = false;
   for (long spin = 0;; ++spin) {
     if (__atomic_load_n(&h->cg_report_host->seq, __ATOMIC_ACQUIRE) == seq) break;
     if ((spin & 1023) == 1023) {
-      // liveness: once the report kernel has finished its record is visible
+      if (!armed) {
+        if (std::chrono::steady_clock::now() - t0 < std::chrono::milliseconds(2))
+          continue;
+        const hipError_t r = hipEventRecord(h->rb_event, s);
+        if (r != hipSuccess) return r;
+        armed = true;
+        continue;
+      }
+      // once the event has completed, the report kernel before it has too
       const hipError_t q = hipEventQuery(h->rb_event);
       if (q == hipSuccess) {
         if (__atomic_load_n(&h->cg_report_host->seq, __ATOMIC_ACQUIRE) == seq) break;
@@ -295,7 +309,6 @@ hipError_t solve_start(pic_mesh* h, fp::CgArgs& a, int spec, hipStream_t s,
         (e = fp::cg_launch_report(a, seq, s)) != hipSuccess)
       return e;
   }
-  if ((e = hipEventRecord(h->rb_event, s)) != hipSuccess) return e;
   *seq_out = seq;
   return hipSuccess;
 }
@@ -312,7 +325,7 @@ hipError_t solve_finish(pic_mesh* h, const fp::CgArgs& a, int spec,
                         int64_t seq, hipStream_t s, int64_t* iters_out,
                         int32_t* first_state) {
   fp::CgReport r;
-  hipError_t e = cg_wait(h, seq, r);
+  hipError_t e = cg_wait(h, seq, s, r);
   if (e != hipSuccess) return e;
   if (first_state) *first_state = r.state;
   int batch = spec, rounds = 0;
@@ -340,8 +353,7 @@ hipError_t solve_finish(pic_mesh* h, const fp::CgArgs& a, int spec,
         return e;
     }
     prof_end(h, s);
-    if ((e = hipEventRecord(h->rb_event, s)) != hipSuccess) return e;
-    if ((e = cg_wait(h, seq, r)) != hipSuccess) return e;
+    if ((e = cg_wait(h, seq, s, r)) != hipSuccess) return e;
   }
   if (iters_out) *iters_out = r.iters;
   return hipSuccess;
@@ -511,9 +523,22 @@ void prof_mark(pic_mesh* h, hipStream_t s) {
   (void)hipEventRecord(h->ev_pool[h->ev_used++], s);
 }
 
+// The first event after kernels stalls the stream while the caches are
+// written back for the host (~5 us after a kernel that wrote much); an
+// untimed event just before the bracket takes that stall, so that the
+// bracket times the kernels inside it.
 void prof_begin(pic_mesh* h, int cls, hipStream_t s) {
-  h->prof_open = h->profiling && ((h->prof_mask >> (cls & 0xff)) & 1u);
+  const bool sampled = h->prof_every <= 1 || h->prof_step < 0 ||
+                       h->prof_step % h->prof_every == 0;
+  h->prof_open = h->profiling && sampled && ((h->prof_mask >> (cls & 0xff)) & 1u);
   if (!h->prof_open) return;
+  if (!h->prof_settle &&
+      hipEventCreateWithFlags(&h->prof_settle, hipEventDisableTiming) != hipSuccess) {
+    h->prof_settle = nullptr;
+    h->profiling = h->prof_open = false;
+    return;
+  }
+  (void)hipEventRecord(h->prof_settle, s);
   h->ev_class.push_back(cls);
   prof_mark(h, s);
 }
@@ -581,6 +606,13 @@ pic_status pic_profile(pic_mesh* h, int32_t classes) {
   h->prof_open = false;
   h->ev_used = 0;
   h->ev_class.clear();
+  return PIC_OK;
+}
+
+pic_status pic_profile_every(pic_mesh* h, int32_t every) {
+  if (!h) return fail(PIC_E_ARG, "pic_profile_every: null mesh");
+  if (every < 1) return fail(PIC_E_ARG, "pic_profile_every: every must be >= 1");
+  h->prof_every = every;
   return PIC_OK;
 }
 
@@ -682,6 +714,7 @@ pic_status mesh_destroy(pic_mesh* h) {
   drop_graphs(h);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   for (hipEvent_t ev : h->ev_pool) (void)hipEventDestroy(ev);
+  if (h->prof_settle) (void)hipEventDestroy(h->prof_settle);
   delete h;
   return PIC_OK;
 }
@@ -1023,7 +1056,14 @@ pic_status pic_step(pic_mesh* h, const pic_particles* P, const pic_fields* F,
   // live and new particles in one launch, the exact fallback, the counters.
   // gate: null, or the control state of the previous solve (see below).
   // *prof0 receives the first profile slot of these launches.
+  // (the step whose kernels are being enqueued, for the timing sample; reset
+  // on every return)
+  struct ProfStep {
+    pic_mesh* h;
+    ~ProfStep() { h->prof_step = -1; }
+  } prof_step_guard{h};
   auto pre_solve = [&](int32_t k, const int32_t* gate, size_t* prof0) -> hipError_t {
+    h->prof_step = k;
     fp::StepArgs ak = a;
     fp::EmitArgs ek = ea;
     ak.step = ek.step = prm->step0 + k;
@@ -1061,6 +1101,7 @@ pic_status pic_step(pic_mesh* h, const pic_particles* P, const pic_fields* F,
     size_t p0 = 0;
     if (!pre_done && (e = pre_solve(k, nullptr, &p0)) != hipSuccess)
       return hip_fail(e, "pic_step particles");
+    h->prof_step = k;
     // the re-sort touches only particles and the solve only the charge:
     // the sort goes first so that the next step's kernels can follow the
     // solve directly
@@ -1106,6 +1147,7 @@ pic_status pic_step(pic_mesh* h, const pic_particles* P, const pic_fields* F,
     size_t p1 = 0;
     if (ahead && (e = pre_solve(k + 1, &ca.ctrl->state, &p1)) != hipSuccess)
       return hip_fail(e, "pic_step particles");
+    h->prof_step = k;  // (further rounds of this step's solve)
     const size_t p1e = h->ev_class.size();
     int64_t iters = 0;
     int32_t first = fp::CG_ITER;
@@ -1340,12 +1382,23 @@ fp::BatchMap batch_map(const std::vector<int>& counts,
   return m;
 }
 
-// Wait until every instance's report carries seq.
-hipError_t batch_wait(pic_batch* b, int64_t seq) {
+// Wait until every instance's report carries seq (the liveness check of
+// cg_wait: an event recorded on s once the reports are 2 ms late).
+hipError_t batch_wait(pic_batch* b, int64_t seq, hipStream_t s) {
+  const auto t0 = std::chrono::steady_clock::now();
+  bool armed = false;
   for (pic_mesh* h : b->h) {
     for (long spin = 0;; ++spin) {
       if (__atomic_load_n(&h->cg_report_host->seq, __ATOMIC_ACQUIRE) == seq) break;
       if ((spin & 1023) == 1023) {
+        if (!armed) {
+          if (std::chrono::steady_clock::now() - t0 < std::chrono::milliseconds(2))
+            continue;
+          const hipError_t r = hipEventRecord(b->reported, s);
+          if (r != hipSuccess) return r;
+          armed = true;
+          continue;
+        }
         const hipError_t q = hipEventQuery(b->reported);
         if (q == hipSuccess) {
           if (__atomic_load_n(&h->cg_report_host->seq, __ATOMIC_ACQUIRE) == seq) break;
@@ -1579,8 +1632,7 @@ pic_status pic_batch_step(pic_batch* b, const pic_particles* P,
     if ((e = fp::cg_batch_begin(cb, m_cg.off[m_cg.n_seg], k > 0 ? 1 : 0, s)) != hipSuccess ||
         (spec > 0 && (e = iterate(spec_on, 0, 0, 0, &spec_n)) != hipSuccess) ||
         (e = fp::cg_batch_report(cb, n, seq, s)) != hipSuccess ||
-        (e = hipEventRecord(b->reported, s)) != hipSuccess ||
-        (e = batch_wait(b, seq)) != hipSuccess)
+        (e = batch_wait(b, seq, s)) != hipSuccess)
       return hip_fail(e, "pic_batch_step solve");
     // later rounds: Jacobi 8, 16, 32, ... iterations; AMG (some fifteen
     // dependent launches per iteration, launches past the stop costing as
@@ -1602,8 +1654,7 @@ pic_status pic_batch_step(pic_batch* b, const pic_particles* P,
       amg_batch = guard == 0 ? (spec > 0 ? 1 : 4) : std::min(2 * amg_batch, 16);
       if ((e = iterate(active, mask, batch, amg_batch, nullptr)) != hipSuccess ||
           (e = fp::cg_batch_report(cb, n, seq, s)) != hipSuccess ||
-          (e = hipEventRecord(b->reported, s)) != hipSuccess ||
-          (e = batch_wait(b, seq)) != hipSuccess)
+          (e = batch_wait(b, seq, s)) != hipSuccess)
         return hip_fail(e, "pic_batch_step solve");
     }
     for (int i = 0; i < n; ++i)

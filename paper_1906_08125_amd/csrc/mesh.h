@@ -77,6 +77,9 @@ struct pic_mesh {
   std::vector<int> ev_class;
   uint32_t prof_mask = 0;   // classes timed (1 << PIC_K_*)
   bool prof_open = false;   // the last prof_begin recorded an event
+  int32_t prof_every = 1;   // pic_step times its steps k = 0, every, 2 every, ...
+  hipEvent_t prof_settle = nullptr;  // untimed event before each bracket
+  int64_t prof_step = -1;   // the step k of the call pic_step is enqueuing (-1: none)
 };
 
 namespace fp {

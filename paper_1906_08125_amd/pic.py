@@ -159,7 +159,7 @@ EXPORTS = ("mesh_create", "mesh_workspace_bytes", "mesh_create_in",
            "mesh_destroy", "mesh_query", "mesh_emit_faces",
            "locate", "locate_noalloc", "deposit", "poisson_solve", "pic_step", "emission_rate",
            "adjoint_step", "pic_batch_create", "pic_batch_destroy",
-           "pic_batch_step", "pic_profile", "pic_profile_read",
+           "pic_batch_step", "pic_profile", "pic_profile_every", "pic_profile_read",
            "pic_last_error", "collide", "surface_charge", "window_objective",
            "apply_face_weights", "metal_create",
            "metal_destroy", "continuity_solve", "heat_step")
@@ -207,6 +207,7 @@ def load_library(path: str = LIB_PATH):
                                C.POINTER(StepParams), C.POINTER(AdjointArgs),
                                vp, vp]
     L.pic_profile.argtypes = [vp, i32]
+    L.pic_profile_every.argtypes = [vp, i32]
     L.window_objective.argtypes = [vp, vp, i32, vp, dbl, i32, dbl, dbl, vp, vp]
     L.apply_face_weights.argtypes = [vp, C.POINTER(Particles), vp, vp, vp]
     L.collide.argtypes = [vp, C.POINTER(Particles), C.POINTER(CollideParams), vp]
@@ -328,15 +329,18 @@ class Mesh:
         except Exception:
             pass
 
-    def profile(self, enable: bool = True, classes=None):
+    def profile(self, enable: bool = True, classes=None, every: int = 1):
         """Time the kernels of the named classes (KERNEL_CLASSES; all when
         None) with HIP events on the stream; enable=False stops.  Each
-        event costs GPU time, so time only what is read."""
+        event costs GPU time, so time only what is read: every > 1 times
+        only the steps of pic_step whose index is a multiple of it."""
         mask = 0
         if enable:
             mask = 0x1FF if classes is None else sum(
                 1 << KERNEL_CLASSES.index(c) for c in classes)
-        _check(load_library().pic_profile(self._h, mask))
+        L = load_library()
+        _check(L.pic_profile_every(self._h, int(every) if enable else 1))
+        _check(L.pic_profile(self._h, mask))
 
     def surface_charge(self, atoms, r_c=0.1, E=None, phi=None):
         """Face charges of the emitting faces and charges of the atoms
