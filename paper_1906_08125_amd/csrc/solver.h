@@ -101,11 +101,25 @@ struct CgArgs {
   const int32_t* n_slots;
   int64_t* clear_charge;
   int64_t n_clear;
+  // lean: the incremental first pass of a step whose warm start is expected
+  // to meet the tolerance (no iterations in the step before).  It leaves x
+  // and u (r32 and u32 in mixed precision) to k_cg_prep, launched only if
+  // the test asks for iterations, and clears the node charges as it reads
+  // them (the next step's clear); the later passes of the solve take b
+  // from bprev (b_saved).  The test then runs in one workgroup and does
+  // not start the product, which k_cg_start with dev_gate 2 does after
+  // k_cg_prep.  Requires a next step (next_stats) and clear_charge ==
+  // charge.
+  int lean;
+  int b_saved;
 };
 
 // seq != 0: the last kernel of the launch writes the state with this
 // sequence number into args.report (host-mapped).
 hipError_t cg_launch_begin(const CgArgs& a, int64_t seq, hipStream_t s);
+// after a lean first pass whose test asks for iterations: x and u, then the
+// start pass's product (none for AMG)
+hipError_t cg_launch_lean_iter(const CgArgs& a, hipStream_t s);
 hipError_t cg_launch_iters(const CgArgs& a, int it0, int n, int64_t seq,
                            hipStream_t s);
 hipError_t cg_launch_recheck(const CgArgs& a, int64_t seq, hipStream_t s);

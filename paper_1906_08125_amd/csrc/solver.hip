@@ -302,6 +302,8 @@ __device__ inline void k_cg_resfield_body(const CgArgs& a, int reset, VB vb,
       double bi;
       if (a.rhs) {
         bi = a.rhs[r];
+      } else if (a.b_saved) {
+        bi = a.bprev[r];  // the same value, formed by the solve's first pass
       } else {
         const double c = a.charge ? (double)a.charge[nd] : 0.0;
         bi = a.coef * c + a.E0 * m.g_unit[r];
@@ -372,6 +374,19 @@ __device__ inline void k_cg_resfield_body(const CgArgs& a, int reset, VB vb,
   write_partials<2>(slot(a, 0), a.G, v, vb);
 }
 
+// x = phi and u = D^-1 r of free row i (node nd) with residual ri: FP32
+// copies of r and u for the mixed-precision recursion.
+__device__ inline void cg_prep_row(const CgArgs& a, int64_t i, int32_t nd,
+                                   double ri) {
+  a.x[i] = a.phi[nd];
+  if (a.mixed) {
+    a.r32[i] = (float)ri;
+    a.u32[i] = (float)(ri * a.m.invdiag[i]);
+  } else {
+    a.u[i] = ri * a.m.invdiag[i];
+  }
+}
+
 // First pass of a solve whose previous solve (same system, phi unchanged
 // since) ended with the true residual r and right-hand side b_prev: r =
 // (b - b_prev) + r, the same quantity as b - K phi without the product with
@@ -391,17 +406,30 @@ __device__ inline void k_cg_resinc_body(const CgArgs& a, VB vb) {
     const double ri = (bi - a.bprev[i]) + a.r[i];
     a.r[i] = ri;
     a.bprev[i] = bi;
-    a.x[i] = a.phi[nd];
-    if (a.mixed) {
-      a.r32[i] = (float)ri;
-      a.u32[i] = (float)(ri * m.invdiag[i]);
+    if (a.lean) {
+      a.clear_charge[nd] = 0;  // (read above; b stays in bprev)
     } else {
-      a.u[i] = ri * m.invdiag[i];
+      cg_prep_row(a, i, nd, ri);
     }
     v[0] += bi * bi;
     v[1] += ri * ri;
   }
+  if (a.lean) {
+    // the Dirichlet nodes' charges (never part of b) cleared as well
+    const Range dr = my_range(a.n_dir, vb);
+    for (int64_t i = dr.lo + threadIdx.x; i < dr.hi; i += blockDim.x)
+      a.clear_charge[a.dir_nodes[i]] = 0;
+  }
   write_partials<2>(slot(a, 0), a.G, v, vb);
+}
+
+// x and u of a lean first pass whose test asked for iterations (the same
+// values as the full first pass writes).
+__device__ inline void k_cg_prep_body(const CgArgs& a, VB vb) {
+  const DevMesh& m = a.m;
+  const Range rows = my_range(m.n_free, vb);
+  for (int64_t i = rows.lo + threadIdx.x; i < rows.hi; i += blockDim.x)
+    cg_prep_row(a, i, m.free2node[i], a.r[i]);
 }
 
 // phi = x on the free nodes (before a re-check pass; dev_gate: only if the
@@ -414,18 +442,48 @@ __device__ inline void k_cg_scatter_body(const CgArgs& a, VB vb, int dev_gate = 
     a.phi[m.free2node[i]] = a.x[i];
 }
 
+// The first product w = K u of a (re)started CG and its two sums.
+__device__ inline void start_product(const CgArgs& a, VB vb) {
+  const DevMesh& m = a.m;
+  double v[2] = {0.0, 0.0};
+  if (a.mixed) {
+    spmv_sell(m.k_sptr, m.k_scol, m.k_sval32, a.u32, m.k_nslices, m.n_free, vb,
+              [&](int64_t i, float s) {
+                a.w32[i] = s;
+                const double ui = a.u32[i];
+                v[0] += (double)a.r32[i] * ui;
+                v[1] += (double)s * ui;
+              });
+  } else {
+    spmv_sell(m.k_sptr, m.k_scol, m.k_sval, a.u, m.k_nslices, m.n_free, vb,
+              [&](int64_t i, double s) {
+                a.w[i] = s;
+                const double ui = a.u[i];
+                v[0] += a.r[i] * ui;
+                v[1] += s * ui;
+              });
+  }
+  write_partials<2>(slot(a, 2), a.G, v, vb);
+}
+
 // Convergence test on the true residual of the last resfield pass; when the
 // solve ends, its statistics; when not converged, the first product w = K u
 // of a (re)started CG.  Fields written here by workgroup 0 (state, iters,
 // bb, relres, rstart, restarts) are never read by other workgroups of this
 // launch; they read iters_final, which is stable here.  A zero right-hand
 // side gives phi = 0 and E = 0, written by every workgroup.
-// dev_gate: only where the resfield pass before it ran (rc_gate; the state
-// itself is rewritten by workgroup 0 here).
+// dev_gate 1: only where the resfield pass before it ran (rc_gate; the
+// state itself is rewritten by workgroup 0 here); 2: the product only,
+// after a lean first pass's test (state CG_ITER) and k_cg_prep; 3: the test
+// of a lean first pass only (one workgroup).
 __device__ inline void k_cg_start_body(const CgArgs& a, int64_t seq, VB vb,
                                        int dev_gate = 0) {
   CgCtrl* c = a.ctrl;
-  if (dev_gate && !c->rc_gate) return;
+  if (dev_gate == 1 && !c->rc_gate) return;
+  if (dev_gate == 2) {
+    if (c->state == CG_ITER && !a.amg) start_product(a, vb);
+    return;
+  }
   double t[2];
   totals<2>(slot(a, 0), a.G, a.G, t);
   const double bn = sqrt(t[0]);
@@ -492,32 +550,16 @@ __device__ inline void k_cg_start_body(const CgArgs& a, int64_t seq, VB vb,
       __syncthreads();
       if (threadIdx.x == 0) a.next_scratch->inj_base = *a.n_slots;
     }
-    const Range cr = my_range(a.n_clear, vb);
-    for (int64_t i = cr.lo + threadIdx.x; i < cr.hi; i += blockDim.x)
-      a.clear_charge[i] = 0;
+    if (!a.b_saved) {  // (else the lean first pass cleared them)
+      const Range cr = my_range(a.n_clear, vb);
+      for (int64_t i = cr.lo + threadIdx.x; i < cr.hi; i += blockDim.x)
+        a.clear_charge[i] = 0;
+    }
   }
   if (done || noconv) return;
+  if (dev_gate == 3) return;  // the test of a lean first pass only
   if (a.amg) return;  // its iterations start with the V-cycle
-  const DevMesh& m = a.m;
-  double v[2] = {0.0, 0.0};
-  if (a.mixed) {
-    spmv_sell(m.k_sptr, m.k_scol, m.k_sval32, a.u32, m.k_nslices, m.n_free, vb,
-              [&](int64_t i, float s) {
-                a.w32[i] = s;
-                const double ui = a.u32[i];
-                v[0] += (double)a.r32[i] * ui;
-                v[1] += (double)s * ui;
-              });
-  } else {
-    spmv_sell(m.k_sptr, m.k_scol, m.k_sval, a.u, m.k_nslices, m.n_free, vb,
-              [&](int64_t i, double s) {
-                a.w[i] = s;
-                const double ui = a.u[i];
-                v[0] += a.r[i] * ui;
-                v[1] += s * ui;
-              });
-  }
-  write_partials<2>(slot(a, 2), a.G, v, vb);
+  start_product(a, vb);
 }
 
 // Iteration it (0-based since the last (re)start): scalars from the
@@ -647,6 +689,9 @@ __global__ void __launch_bounds__(kCgBlock) k_cg_scatter(CgArgs a, int dev_gate)
 }
 __global__ void __launch_bounds__(kCgBlock) k_cg_resinc(CgArgs a) {
   k_cg_resinc_body(a, VB{(int)blockIdx.x, (int)gridDim.x});
+}
+__global__ void __launch_bounds__(kCgBlock) k_cg_prep(CgArgs a) {
+  k_cg_prep_body(a, VB{(int)blockIdx.x, (int)gridDim.x});
 }
 __global__ void __launch_bounds__(kCgBlock) k_cg_start(CgArgs a, int64_t seq,
                                                       int dev_gate) {
@@ -1254,11 +1299,28 @@ hipError_t amg_batch_iters(const CgArgs* dargs, const std::vector<const CgArgs*>
   } while (0)
 
 hipError_t cg_launch_begin(const CgArgs& a, int64_t seq, hipStream_t s) {
-  if (a.incremental && !a.rhs && a.bprev)
+  const bool inc = a.incremental && !a.rhs && a.bprev;
+  if (a.lean) {
+    if (!inc || !a.next_stats || !a.charge ||
+        (const int64_t*)a.clear_charge != a.charge)
+      return hipErrorInvalidValue;
+    LAUNCH(k_cg_resinc, a);
+    // the test in one workgroup (no product to start)
+    hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(kCgBlock), 0, s, a, seq, 3);
+    return hipGetLastError();
+  }
+  if (inc)
     LAUNCH(k_cg_resinc, a);
   else
     LAUNCH(k_cg_resfield, a, 1, 0);
   LAUNCH(k_cg_start, a, seq, 0);
+  return hipSuccess;
+}
+
+hipError_t cg_launch_lean_iter(const CgArgs& a, hipStream_t s) {
+  if (!a.lean) return hipErrorInvalidValue;
+  LAUNCH(k_cg_prep, a);
+  if (!a.amg) LAUNCH(k_cg_start, a, (int64_t)0, 2);
   return hipSuccess;
 }
 
