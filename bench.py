@@ -45,7 +45,7 @@ PUSH_TRAFFIC = dict(bytes=220.5e6, read=155.9e6, written=64.6e6, live=992_300,
 # One step of the 32-instance batch (every dispatch between consecutive
 # batched particle launches, averaged over the timed steps;
 # profiles/pic_batch_step_32_instances.md):
-BATCH_TRAFFIC = dict(bytes=3357.0e6, read=2718.6e6, written=638.4e6,
+BATCH_TRAFFIC = dict(bytes=3349.7e6, read=2720.9e6, written=628.8e6,
                      live=3_371_102,
                      sources=("paper_1906_08125_amd/csrc/particles.hip",
                               "paper_1906_08125_amd/csrc/solver.hip",
@@ -53,9 +53,9 @@ BATCH_TRAFFIC = dict(bytes=3357.0e6, read=2718.6e6, written=638.4e6,
                               "paper_1906_08125_amd/csrc/api.hip",
                               "paper_1906_08125_amd/csrc/common.h"),
                      sha256=("5770ae084b9f9585a4b0d54bd5d8e7f9e881e1d3cf0fe7c783617cdb6aa6d220",
-                             "a3e3309ac02012ac544dbc79abf2b8f40514441d20b240a38abdac84bb637f1c",
+                             "48dc7dedd15d958bcf9d263391b89c760b31dc43d7838b22276f98ba3273aebf",
                              "b7134060afc401da45819d5e18d224beee6fb57e6660ef3331fb9b6bb80d9af9",
-                             "ae55d3e89b0b5ecf7b0315f55806ab3698847e53dfe1d3abbf7d275bd5bdc4af",
+                             "55de045281fd8ddcc4c247b6f87dc28116b66f926498b98042be0c3fe648bd06",
                              "df664d921b2048d0e38d5de9ccce0edb99bc52cb2a034c6b94b3b69f07cb3843"))
 
 
@@ -83,21 +83,32 @@ def solve_bytes(info, rows, first_full=True):
     with the fused residual + field pass over phi (rows: node map, own phi,
     charge, Neumann load, x, r, u, D^-1, E; entries: node column, K, R (3));
     every later one with the incremental residual pass r = (b - b_prev) +
-    r_prev (node map, charge, Neumann load, b_prev and r read and written,
-    x written, phi, D^-1, u written: 84 B per free row), which needs no
-    product with K because phi and the field have not changed since the
-    previous solve ended.  Per CG iteration: the update (7 vector reads, 5
-    writes) and the K u product (column + value per entry, u and w per
-    row); a solve that iterated ends with phi = x (20 B per free row) and a
-    fused re-check pass."""
+    r_prev, which needs no product with K because phi and the field have
+    not changed since the previous solve ended: node map, charge, Neumann
+    load, b_prev and r read and written, x written, phi, D^-1, u written
+    (84 B per free row).  Where the step before needed no iteration and a
+    step follows (the lean pass), it leaves x and u to a launch made only
+    if the test asks for iterations (node map, phi, r, D^-1 read, x and u
+    written: 44 B per free row) and clears the charges it reads (60 B per
+    free row, 12 B per Dirichlet node).  Per CG iteration: the update (7
+    vector reads, 5 writes) and the K u product (column + value per entry,
+    u and w per row); a solve that iterated ends with phi = x (20 B per
+    free row) and a fused re-check pass."""
     n, nnz = info["n_free"], info["nnz"]
     N, nf = info["n_nodes"], info["nnz_field"]
     fused = 100 * n + 36 * nnz + 28 * (nf - nnz) + 40 * (N - n)
     inc = 84 * n
+    lean = 60 * n + 12 * (N - n)
+    prep = 44 * n
     it = 96 * n + 12 * nnz + 16 * n
     total = 0
     for k, r in enumerate(rows):
-        total += fused if (k == 0 and first_full) else inc
+        if k == 0 and first_full:
+            total += fused
+        elif k > 0 and k + 1 < len(rows) and rows[k - 1]["cg_iters"] == 0:
+            total += lean + (prep if r["cg_iters"] > 0 else 0)
+        else:
+            total += inc
         if r["cg_iters"] > 0:
             total += r["cg_iters"] * it + 20 * n + fused
     return total
