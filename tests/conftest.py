@@ -32,3 +32,18 @@ def small_tip_mesh():
     """3 x 3 x 4 cubes (216 tets before removal) with a one-cell tip."""
     from paper_1906_08125_amd import workloads as w
     return w.kuhn_tip_mesh(3, 3, 4, 0.5, 0.5, 1.0)
+
+
+def golden(name):
+    """The named fixture of tests/golden/: {key: [fields]} from its
+    whitespace-separated lines ('#' starts a comment)."""
+    import os
+    out = {}
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
+    with open(path) as f:
+        for line in f:
+            line = line.split("#", 1)[0].strip()
+            if line:
+                k, *v = line.split()
+                out[k] = v
+    return out

@@ -16,6 +16,19 @@ from oracle import oracle as O
 from paper_1906_08125_amd import workloads as W
 
 
+def test_diode_workload_is_the_papers_geometry():
+    """The diode workload's default mesh is the paper's validation geometry
+    (Sec. III A; tests/golden/diode_validation.txt): the gap exactly, the
+    electrode area to the lattice (32 x 32 cubes of 0.364 nm: 135.7 nm^2)."""
+    from conftest import golden
+    g = golden("diode_validation.txt")
+    cfg = W.config_diode(14.0)
+    assert abs(cfg.nz * cfg.h - float(g["gap_nm"][0])) < 1e-12
+    area = (cfg.nx * cfg.h) * (cfg.ny * cfg.h)
+    assert abs(area / float(g["area_nm2"][0]) - 1) < 0.006
+    assert 0.0 < float(g["rms_vs_semianalytic"][0]) < 0.05
+
+
 def test_gap_reduces_to_child_langmuir():
     """E_c = 0: the closed-form gap of the Child-Langmuir density is d."""
     for Ea in (2.0, 7.5, 14.0, 30.0):

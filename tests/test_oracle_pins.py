@@ -425,14 +425,15 @@ def test_deposit_conservation_and_permutation(tiny_mesh):
 # ---------------------------------------------------------------------------
 
 def test_fn_constants_published_values():
+    """The oracle's constants against their published values (the first
+    and second FN constants and the Schottky constant of Forbes & Deane,
+    e/m_e and e/eps0 from CODATA; tests/golden/fn_constants.txt)."""
+    from conftest import golden
     k = O.constants()
-    # first and second FN constants and the Schottky constant (Forbes &
-    # Deane, Proc. R. Soc. A 463 (2007) 2907)
-    assert abs(k["a_fn"] / 1.541434e-6 - 1) < 2e-6
-    assert abs(k["b_fn"] / 6.830890 - 1) < 2e-6
-    assert abs(k["c_s"] / 1.439965 - 1) < 2e-6
-    assert abs(k["qm"] / -0.1758820 - 1) < 1e-6
-    assert abs(k["e_eps"] / 18.0951 - 1) < 1e-5
+    ref = golden("fn_constants.txt")
+    assert set(ref) == {"a_fn", "b_fn", "c_s", "qm", "e_eps"}
+    for name, (value, rtol, *unit) in ref.items():
+        assert abs(k[name] / float(value) - 1) < float(rtol), name
 
 
 def test_fn_current_limits():
