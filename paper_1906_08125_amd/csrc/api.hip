@@ -1078,9 +1078,44 @@ pic_status pic_step(pic_mesh* h, const pic_particles* P, const pic_fields* F,
     pic_mesh* h;
     ~ProfStep() { h->prof_step = -1; }
   } prof_step_guard{h};
+  // The particle arrays alternate between the caller's and the re-sort's
+  // scratch: a re-sort within the call gathers into the other set and the
+  // kernels after it take that one (no copy back per re-sort); a call that
+  // ends on the scratch set copies it back once.  Not with collisions,
+  // which use the sort scratch themselves.
+  const bool alternate = prm->resort_every > 0 && !prm->collide;
+  const fp::SortArgs base_sort =
+      prm->resort_every > 0 ? sort_args(h, P, f32 ? 4 : 8) : fp::SortArgs{};
+  int on_scratch = 0;
+  auto use_set = [&](fp::StepArgs& x) {
+    if (!on_scratch) return;
+    x.x = base_sort.s_real[0];
+    x.y = base_sort.s_real[1];
+    x.z = base_sort.s_real[2];
+    x.vx = base_sort.s_real[3];
+    x.vy = base_sort.s_real[4];
+    x.vz = base_sort.s_real[5];
+    x.w = base_sort.s_w;
+    x.tet = base_sort.s_tet;
+    x.birth = base_sort.s_birth;
+    x.id = base_sort.s_id;
+  };
+  // the re-sort (or final copy) from the current set into the other one
+  auto sort_from_current = [&]() {
+    fp::SortArgs sa = base_sort;
+    if (on_scratch) {
+      for (int f = 0; f < 6; ++f) std::swap(sa.real[f], sa.s_real[f]);
+      std::swap(sa.w, sa.s_w);
+      std::swap(sa.tet, sa.s_tet);
+      std::swap(sa.birth, sa.s_birth);
+      std::swap(sa.id, sa.s_id);
+    }
+    return sa;
+  };
   auto pre_solve = [&](int32_t k, const int32_t* gate, size_t* prof0) -> hipError_t {
     h->prof_step = k;
     fp::StepArgs ak = a;
+    use_set(ak);
     fp::EmitArgs ek = ea;
     ak.step = ek.step = prm->step0 + k;
     ak.stats = ek.stats = stats + k;
@@ -1123,10 +1158,11 @@ pic_status pic_step(pic_mesh* h, const pic_particles* P, const pic_fields* F,
     // solve directly
     if (prm->resort_every > 0 && (step + 1) % prm->resort_every == 0) {
       prof_begin(h, PIC_K_SORT, s);
-      fp::SortArgs sa = sort_args(h, P, f32 ? 4 : 8);
+      fp::SortArgs sa = alternate ? sort_from_current() : base_sort;
       sa.stats = st;
-      if ((e = fp::sort_particles(sa, P->capacity, h->n_cu, s)) != hipSuccess)
+      if ((e = fp::sort_particles(sa, P->capacity, h->n_cu, s, !alternate)) != hipSuccess)
         return hip_fail(e, "pic_step sort");
+      if (alternate) on_scratch ^= 1;
       prof_end(h, s);
       if (prm->collide) {
         prof_begin(h, PIC_K_COLLIDE, s);
@@ -1174,6 +1210,10 @@ pic_status pic_step(pic_mesh* h, const pic_particles* P, const pic_fields* F,
       for (size_t i = p1; i < p1e; ++i) h->ev_class[i] = -1;
     // speculate this many iterations in the next step's first round
     h->step_spec = (int)std::min<int64_t>(iters, 256);
+  }
+  if (on_scratch) {  // the caller's arrays hold the state again
+    if ((e = fp::copy_particles(base_sort, h->n_cu, s)) != hipSuccess)
+      return hip_fail(e, "pic_step copy");
   }
   return PIC_OK;
 }

@@ -31,8 +31,14 @@ struct SortArgs {
   int64_t* s_id;
 };
 
+// copyback: the sorted particles are copied back into the arrays they came
+// from (real, w, ...); else they stay in the scratch arrays (s_real, s_w,
+// ...), which the caller then uses as the particle arrays, and only the
+// slot count is set.
 hipError_t sort_particles(const SortArgs& a, int64_t capacity, int n_cu,
-                          hipStream_t s);
+                          hipStream_t s, bool copyback = true);
+// the s_* arrays copied into real, w, ... for the *n_slots slots in use
+hipError_t copy_particles(const SortArgs& a, int n_cu, hipStream_t s);
 size_t sort_scratch_bytes(int64_t capacity, int real_bytes);
 int sort_tiles(int64_t capacity);
 

@@ -248,12 +248,38 @@ __global__ void __launch_bounds__(kThreads) k_sort_copyback(SortArgs a) {
   }
 }
 
+// The slot count of a re-sort whose output stays in the scratch arrays.
+__global__ void k_sort_count(SortArgs a) {
+  if (threadIdx.x != 0) return;
+  const int32_t n = *a.n_live;
+  *a.n_slots = n;
+  if (a.stats) a.stats->n_slots = n;
+}
+
+__global__ void __launch_bounds__(kThreads) k_particles_copy(SortArgs a) {
+  const int64_t n = *a.n_slots;
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    if (a.real_bytes == 8) {
+      for (int f = 0; f < 6; ++f)
+        reinterpret_cast<double*>(a.real[f])[j] = reinterpret_cast<const double*>(a.s_real[f])[j];
+    } else {
+      for (int f = 0; f < 6; ++f)
+        reinterpret_cast<float*>(a.real[f])[j] = reinterpret_cast<const float*>(a.s_real[f])[j];
+    }
+    a.w[j] = a.s_w[j];
+    a.tet[j] = a.s_tet[j];
+    a.birth[j] = a.s_birth[j];
+    a.id[j] = a.s_id[j];
+  }
+}
+
 int sort_tiles(int64_t capacity) {
   return (int)((capacity + kSortTile - 1) / kSortTile);
 }
 
 hipError_t sort_particles(const SortArgs& a, int64_t capacity, int n_cu,
-                          hipStream_t s) {
+                          hipStream_t s, bool copyback) {
   const int ntiles = sort_tiles(capacity);
   const int grid = n_cu * 4;
   hipLaunchKernelGGL(k_sort_keys, dim3(grid), dim3(kThreads), 0, s, a);
@@ -267,7 +293,15 @@ hipError_t sort_particles(const SortArgs& a, int64_t capacity, int n_cu,
     src ^= 1;
   }
   hipLaunchKernelGGL(k_sort_gather, dim3(grid), dim3(kThreads), 0, s, a, src);
-  hipLaunchKernelGGL(k_sort_copyback, dim3(grid), dim3(kThreads), 0, s, a);
+  if (copyback)
+    hipLaunchKernelGGL(k_sort_copyback, dim3(grid), dim3(kThreads), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_sort_count, dim3(1), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t copy_particles(const SortArgs& a, int n_cu, hipStream_t s) {
+  hipLaunchKernelGGL(k_particles_copy, dim3(n_cu * 4), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 
