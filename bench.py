@@ -36,7 +36,7 @@ PUSH_TIMING_EVERY = 5
 # on are unchanged and the run's load matches the one profiled.
 # The dominant kernel (FP64 push) per launch at the production workload
 # (profiles/pic_step_fp64_production_tip.md):
-PUSH_TRAFFIC = dict(bytes=220.5e6, read=155.9e6, written=64.6e6, live=992_300,
+PUSH_TRAFFIC = dict(bytes=220.4e6, read=155.9e6, written=64.6e6, live=992_300,
                     sources=("paper_1906_08125_amd/csrc/particles.hip",
                              "paper_1906_08125_amd/csrc/common.h"),
                     sha256=("5770ae084b9f9585a4b0d54bd5d8e7f9e881e1d3cf0fe7c783617cdb6aa6d220",
@@ -45,7 +45,7 @@ PUSH_TRAFFIC = dict(bytes=220.5e6, read=155.9e6, written=64.6e6, live=992_300,
 # One step of the 32-instance batch (every dispatch between consecutive
 # batched particle launches, averaged over the timed steps;
 # profiles/pic_batch_step_32_instances.md):
-BATCH_TRAFFIC = dict(bytes=3349.7e6, read=2720.9e6, written=628.8e6,
+BATCH_TRAFFIC = dict(bytes=3345.7e6, read=2717.9e6, written=627.8e6,
                      live=3_371_102,
                      sources=("paper_1906_08125_amd/csrc/particles.hip",
                               "paper_1906_08125_amd/csrc/solver.hip",
@@ -55,7 +55,7 @@ BATCH_TRAFFIC = dict(bytes=3349.7e6, read=2720.9e6, written=628.8e6,
                      sha256=("5770ae084b9f9585a4b0d54bd5d8e7f9e881e1d3cf0fe7c783617cdb6aa6d220",
                              "48dc7dedd15d958bcf9d263391b89c760b31dc43d7838b22276f98ba3273aebf",
                              "b7134060afc401da45819d5e18d224beee6fb57e6660ef3331fb9b6bb80d9af9",
-                             "55de045281fd8ddcc4c247b6f87dc28116b66f926498b98042be0c3fe648bd06",
+                             "e86b16e48b77a312e297ff1664407f4a6d70ef7381df77a5ce39d568443292e9",
                              "df664d921b2048d0e38d5de9ccce0edb99bc52cb2a034c6b94b3b69f07cb3843"))
 
 
