@@ -305,7 +305,10 @@ typedef struct {
  * so one call of n steps and n calls of one step agree to the solver
  * tolerance, bit for bit when no solve iterates.  The host waits for each
  * solve's convergence report; the next step's kernels are already queued
- * behind it and do nothing if the solve needs more rounds.
+ * behind it and do nothing if the solve needs more rounds.  With re-sorts
+ * and no collisions, the particles may sit in the handle's re-sort scratch
+ * between re-sorts of a call; the caller's arrays hold the state again once
+ * the call's work on the stream has completed.
  * stats: device [n_steps] pic_step_stats (overwritten). */
 PIC_API pic_status pic_step(pic_mesh* mesh, const pic_particles* particles,
                     const pic_fields* fields, const pic_step_params* params,
